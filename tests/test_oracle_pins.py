@@ -1,0 +1,335 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test ties the oracle to something other than itself: a library routine
+the special case reduces to, an exactly low rank construction, the backward
+error identity of the left-looking method, hand-computed fixtures or
+published known-answer vectors.  All run on the CPU.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bookkeeping as bk
+from oracle import dense
+from oracle import philox
+from oracle import tlr
+from paper_2108_11932_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _cov(n, m, seed=5, ell=0.1, dim=2, kernel=dense.KERNEL_EXP, nugget=1e-4):
+    if n & (n - 1) == 0:
+        pts = wl.jittered_grid(n, dim, seed)
+    else:
+        pts = wl.uniform_points(n, dim, seed)
+    pts = pts[wl.morton_order(pts)]
+    return pts, dense.covariance_matrix(pts, kernel, ell, nugget)
+
+
+# ---------------------------------------------------------------- generators
+
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox_kat.txt")) if not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        w = [int(x, 16) for x in r]
+        assert philox.philox4x32_10(tuple(w[0:4]), tuple(w[4:6])) == tuple(w[6:10])
+
+
+def test_box_muller_moments():
+    z = philox.test_matrix(seed=12345, k=3, t=1, s=0, rows=4096, cols=4).ravel()
+    assert abs(z.mean()) < 0.03
+    assert abs(z.var() - 1.0) < 0.05
+    # Kolmogorov-Smirnov distance to the normal CDF
+    zs = np.sort(z)
+    cdf = 0.5 * (1 + np.vectorize(math.erf)(zs / math.sqrt(2)))
+    ks = np.max(np.abs(cdf - np.arange(1, len(zs) + 1) / len(zs)))
+    assert ks < 1.63 / math.sqrt(len(zs))   # 1% critical value
+
+
+def test_kernel_closed_forms():
+    ell = 0.25
+    r = np.array([0.0, ell, ell / math.sqrt(3.0)])
+    e = dense.kernel_values(r, dense.KERNEL_EXP, ell)
+    assert e[0] == 1.0 and abs(e[1] - math.exp(-1)) < 1e-15
+    mt = dense.kernel_values(r, dense.KERNEL_MATERN15, ell)
+    assert mt[0] == 1.0 and abs(mt[2] - 2.0 / math.e) < 1e-15
+
+
+def test_grid_one_point_per_cell_and_shapes():
+    assert wl.grid_shape(4096, 2) == (64, 64)
+    assert wl.grid_shape(32768, 2) == (256, 128)
+    assert wl.grid_shape(131072, 2) == (512, 256)
+    assert wl.grid_shape(131072, 3) == (64, 64, 32)
+    pts = wl.jittered_grid(1 << 10, 2, 3)
+    shape = np.array(wl.grid_shape(1 << 10, 2))
+    cells = np.floor(pts * shape).astype(int)
+    keys = cells[:, 0] * shape[1] + cells[:, 1]
+    assert sorted(keys.tolist()) == list(range(1 << 10))
+
+
+def test_morton_order_hand_computed():
+    # 4x4 grid, cell (a, b) has key a1 b1 a0 b0 (first coordinate first).
+    pts = wl.jittered_grid(16, 2, 0)
+    order = wl.morton_order(pts)
+    assert order.tolist() == [0, 1, 4, 5, 2, 3, 6, 7, 8, 9, 12, 13, 10, 11, 14, 15]
+
+
+# ---------------------------------------------------------------- dense oracle
+
+def test_ldlt_hand_computed():
+    vals = [l.split() for l in open(os.path.join(GOLDEN, "ldlt_3x3.txt")) if not l.startswith("#")]
+    a = np.array(vals[0:3], dtype=float)
+    lref = np.array(vals[3:6], dtype=float)
+    dref = np.array(vals[6], dtype=float)
+    l, d = dense.ldlt_unpivoted(a)
+    assert np.array_equal(l, lref) and np.array_equal(d, dref)
+
+
+def test_ldlt_reduces_to_cholesky_on_spd():
+    _, a = _cov(256, 256)
+    l, d = dense.ldlt_unpivoted(a)
+    assert np.all(d > 0)
+    c = np.linalg.cholesky(a)
+    np.testing.assert_allclose(l * np.sqrt(d)[None, :], c, rtol=0, atol=1e-10)
+
+
+def test_ldlt_inertia_sylvester():
+    rng = np.random.default_rng(0)
+    n = 60
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.concatenate([-rng.uniform(1, 3, 17), rng.uniform(1, 3, n - 17)])
+    a = (q * lam) @ q.T
+    l, d = dense.ldlt_unpivoted(a)
+    assert int(np.sum(d < 0)) == 17
+    np.testing.assert_allclose(l @ np.diag(d) @ l.T, a, atol=1e-9)
+
+
+def test_ldlt_zero_pivot_detected():
+    a = np.array([[1.0, 1.0], [1.0, 1.0]])
+    with pytest.raises(dense.ZeroPivot):
+        dense.ldlt_unpivoted(a)
+
+
+def test_power_iteration_norm():
+    _, a = _cov(300, 300)
+    est = dense.norm2_power(lambda x: a @ x, 300, iters=200, rtol=0)
+    assert abs(est - np.linalg.norm(a, 2)) < 1e-8 * est
+
+
+# ---------------------------------------------------------------- TLR compression
+
+def test_compress_truncation_is_optimal():
+    _, a = _cov(512, 128)
+    tau = 1e-6
+    t = tlr.compress_dense(a, 128, tau)
+    for (i, j), u in t.u.items():
+        blk = a[i * 128:(i + 1) * 128, j * 128:(j + 1) * 128]
+        s = np.linalg.svd(blk, compute_uv=False)
+        assert u.shape[1] == int(np.sum(s > tau))
+        err = np.linalg.norm(blk - u @ t.v[i, j].T, 2)
+        tail = s[u.shape[1]] if u.shape[1] < len(s) else 0.0
+        assert abs(err - tail) <= 1e-12 * s[0] + 1e-15
+        np.testing.assert_allclose(u.T @ u, np.eye(u.shape[1]), atol=1e-12)
+
+
+def test_compress_kernel_matches_dense_and_pads():
+    pts, a = _cov(300, 128)
+    t1 = tlr.compress_dense(a, 128, 1e-8)
+    t2 = tlr.compress_kernel(pts, 128, dense.KERNEL_EXP, 0.1, 1e-4, 1e-8)
+    assert t1.nb == t2.nb == 3
+    assert np.array_equal(t1.ranks(), t2.ranks())
+    np.testing.assert_allclose(t1.dense_symmetric(), t2.dense_symmetric(), atol=1e-12)
+    # padding: identity on the padded diagonal, zero rows in U and V
+    last = t2.diag[2]
+    assert np.array_equal(last[44:, 44:], np.eye(84)) and not last[44:, :44].any()
+    for j in range(2):
+        assert not t2.u[2, j][44:].any()
+
+
+def test_matvec_matches_dense():
+    _, a = _cov(320, 64)
+    t = tlr.compress_dense(a, 64, 1e-9)
+    x = np.random.default_rng(1).standard_normal((320, 3))
+    np.testing.assert_allclose(tlr.matvec(t, x), t.dense_symmetric()[:320, :320] @ x, atol=1e-10)
+
+
+# ---------------------------------------------------------------- TLR Cholesky
+
+def test_single_tile_is_dense_cholesky():
+    _, a = _cov(128, 128)
+    t = tlr.compress_dense(a, 128, 1e-6)
+    l = tlr.tlr_cholesky(t, 1e-6)
+    np.testing.assert_array_equal(l.diag[0], np.linalg.cholesky(a))
+
+
+def test_tiny_threshold_reproduces_lapack():
+    _, a = _cov(512, 64)
+    tau = 1e-14 * np.linalg.norm(a, 2)
+    l = tlr.tlr_cholesky(tlr.compress_dense(a, 64, tau), tau)
+    ref = np.linalg.cholesky(a)
+    err = np.max(np.abs(l.dense_lower() - ref))
+    assert err < 1e-9 * np.max(np.abs(ref))
+
+
+def _low_rank_plus_blockdiag(n, m, r, indefinite=False, seed=3):
+    rng = np.random.default_rng(seed)
+    nb = n // m
+    a = np.zeros((n, n))
+    for k in range(nb):
+        if indefinite:
+            sgn = np.where(rng.random(m) < 0.3, -1.0, 1.0)
+            b = np.diag(sgn * rng.uniform(5, 6, m)) + 0.05 * rng.standard_normal((m, m))
+            b = 0.5 * (b + b.T)
+        else:
+            g = rng.standard_normal((m, m))
+            b = g @ g.T / m + np.eye(m)
+        a[k * m:(k + 1) * m, k * m:(k + 1) * m] = b
+    w = rng.standard_normal((n, r))
+    return a + w @ w.T
+
+
+@pytest.mark.parametrize("indefinite", [False, True])
+def test_exactly_low_rank_ranks_recovered(indefinite):
+    # Off-diagonal tiles of blockdiag(B) + W W^T are W_i W_j^T, and every
+    # Schur-updated tile stays W_i C_k W_k^T (Woodbury), so rank is exactly r.
+    n, m, r = 384, 64, 3
+    a = _low_rank_plus_blockdiag(n, m, r, indefinite)
+    tau = 1e-8
+    t = tlr.compress_dense(a, m, tau)
+    assert set(t.ranks()[np.tril_indices(n // m, -1)].tolist()) == {r}
+    if indefinite:
+        l, d = tlr.tlr_ldlt(t, tau)
+        dd = np.concatenate(d)
+        rec = l.dense_lower() @ np.diag(dd) @ l.dense_lower().T
+        assert int(np.sum(dd < 0)) == int(np.sum(np.linalg.eigvalsh(a) < 0))
+    else:
+        l = tlr.tlr_cholesky(t, tau)
+        rec = l.dense_lower() @ l.dense_lower().T
+    assert set(l.ranks()[np.tril_indices(n // m, -1)].tolist()) == {r}
+    assert np.max(np.abs(rec - a)) < 1e-10 * np.max(np.abs(a))
+
+
+@pytest.mark.parametrize("factor", ["chol", "ldlt"])
+def test_backward_error_identity(factor):
+    # Left-looking: (A - L L^T)_ik equals the compression error of tile (i, k)
+    # for i > k, and vanishes on the diagonal tiles.
+    pts, a = _cov(448, 64, seed=9)
+    tau = 1e-5
+    t = tlr.compress_dense(a, 64, tau)
+    rec = {}
+    if factor == "chol":
+        l = tlr.tlr_cholesky(t, tau, record=rec)
+        r = t.dense_symmetric() - l.dense_lower() @ l.dense_lower().T
+    else:
+        l, d = tlr.tlr_ldlt(t, tau, record=rec)
+        ld = l.dense_lower()
+        r = t.dense_symmetric() - ld @ np.diag(np.concatenate(d)) @ ld.T
+    scale = np.linalg.norm(a, 2)
+    for k in range(t.nb):
+        blk = r[t.blk(k), t.blk(k)]
+        assert np.linalg.norm(blk, 2) < 1e-12 * scale
+        for i in range(k + 1, t.nb):
+            e = np.linalg.norm(r[t.blk(i), t.blk(k)], 2)
+            assert abs(e - rec[i, k]) < 1e-11 * scale
+            assert rec[i, k] <= tau
+    # the global error is bounded by the per-tile errors
+    est = tlr.factor_error_norm(t, l, None if factor == "chol" else d, iters=60)
+    assert abs(est - np.linalg.norm(r, 2)) < 1e-2 * np.linalg.norm(r, 2)
+    assert est <= (t.nb - 1) * tau
+
+
+def test_error_within_sqrt_nb_tau():
+    pts, a = _cov(1024, 128, seed=1)
+    for tau in (1e-6, 1e-3):
+        t = tlr.compress_dense(a, 128, tau)
+        l = tlr.tlr_cholesky(t, tau)
+        est = tlr.factor_error_norm(t, l)
+        assert est <= math.sqrt(t.nb) * tau
+
+
+def test_shift_keeps_error_with_unshifted_matrix():
+    pts, a = _cov(512, 64, seed=4)
+    tau = 1e-3
+    t = tlr.compress_dense(a, 64, tau)
+    l = tlr.tlr_cholesky(t, tau, shift=tau)
+    est = tlr.factor_error_norm(t, l)
+    assert est <= math.sqrt(t.nb) * tau + tau
+
+
+def test_not_spd_reported_at_first_failing_tile():
+    pts, a = _cov(256, 64, seed=2)
+    a2 = a.copy()
+    a2[130, 130] = -5.0
+    with pytest.raises(tlr.NotSPDTile) as exc:
+        tlr.tlr_cholesky(tlr.compress_dense(a2, 64, 1e-8), 1e-8)
+    assert exc.value.k == 2
+
+
+def test_ldlt_matches_cholesky_on_spd():
+    _, a = _cov(384, 64, seed=6)
+    tau = 1e-13 * np.linalg.norm(a, 2)
+    t = tlr.compress_dense(a, 64, tau)
+    l, d = tlr.tlr_ldlt(t, tau)
+    c = tlr.tlr_cholesky(t, tau)
+    dd = np.concatenate(d)
+    assert np.all(dd > 0)
+    np.testing.assert_allclose(l.dense_lower() * np.sqrt(dd)[None, :], c.dense_lower(), atol=1e-9)
+
+
+# ---------------------------------------------------------------- TLR solve
+
+@pytest.mark.parametrize("factor", ["chol", "ldlt"])
+def test_solve_matches_dense_triangular_solves(factor):
+    _, a = _cov(400, 64, seed=8)
+    tau = 1e-7
+    t = tlr.compress_dense(a, 64, tau)
+    b = np.random.default_rng(2).standard_normal((400, 2))
+    if factor == "chol":
+        l = tlr.tlr_cholesky(t, tau)
+        ld = l.dense_lower()
+        y = dense.solve_lower(ld, tlr.pad_vec(t, b))
+        x_ref = dense.solve_lower(ld, y, trans=True)[:400]
+        x = tlr.solve(l, b)
+    else:
+        l, d = tlr.tlr_ldlt(t, tau)
+        ld = l.dense_lower()
+        y = dense.solve_lower(ld, tlr.pad_vec(t, b), unit=True) / np.concatenate(d)[:, None]
+        x_ref = dense.solve_lower(ld, y, unit=True, trans=True)[:400]
+        x = tlr.solve(l, b, d)
+    np.testing.assert_allclose(x, x_ref, rtol=1e-9, atol=1e-9 * np.max(np.abs(x_ref)))
+    # and it solves the original system to the factorization accuracy
+    res = np.linalg.norm(a @ x - b) / (np.linalg.norm(a, 2) * np.linalg.norm(x))
+    assert res < 1e-6
+
+
+# ---------------------------------------------------------------- bookkeeping
+
+def test_offsets_hand_computed():
+    r = np.zeros((4, 4), dtype=int)
+    r[1, 0], r[2, 0], r[2, 1], r[3, 0], r[3, 1], r[3, 2] = 5, 2, 7, 1, 0, 4
+    off, total = bk.lower_offsets(r)
+    assert total == 19
+    assert [off[1, 0], off[2, 0], off[2, 1], off[3, 0], off[3, 1], off[3, 2]] == [0, 5, 7, 14, 15, 15]
+    po = bk.row_panel_offsets(r)
+    assert [po[3, 0], po[3, 1], po[3, 2], po[2, 1]] == [0, 1, 1, 2]
+    assert bk.row_widths(r, 2).tolist() == [0, 5, 9, 1]
+    assert bk.tile_rows(300, 128).tolist() == [128, 128, 44]
+
+
+def test_sort_ranks_ties_ascending_row():
+    a = np.zeros((6, 6), dtype=int)
+    a[2:, 1] = [4, 9, 4, 7]           # rows 2..5 of column 1
+    assert bk.sort_ranks(a, 1) == [3, 5, 2, 4]
+
+
+def test_active_set_evolution_hand_computed():
+    order = [7, 3, 9, 1, 4, 8]
+    sets = bk.active_sets(order, 4, [[False, True, True, False], [True, False, False, False],
+                                     [True, True, False], [True]])
+    assert sets == [[7, 3, 9, 1], [7, 1, 4, 8], [1, 4, 8], [8], []]
+    # without a cap the subset only shrinks
+    assert bk.active_sets([2, 5], 99, [[True, False], [True]]) == [[2, 5], [5], []]
