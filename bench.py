@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Benchmark of the TLR Cholesky hot path on one MI355X.
+
+One step is one complete left-looking TLR Cholesky (tlr_potrf: every column's
+dense diagonal update and POTRF, batched ARA of the Schur-complement tiles
+with dynamic batching, projection, triangular solve and panel append) of a
+covariance matrix that is already resident in HBM in TLR form.  The input is
+built on the GPU (tlr_compress_kernel) before the timed region.
+
+Prints one JSON line: time-to-solution (ms_per_step) and the executed TFLOP/s
+(value), the roofline of the dominant kernel (the Schur-complement sampling
+product, timed live with HIP events), and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload cov2d_131k] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "TLR Cholesky time-to-solution + TFLOP/s, N=131072 eps=1e-6; FP64 vs mixed"
+
+
+def _describe(w) -> str:
+    kern = {0: "exponential", 1: "Matern-1.5"}[w.kernel]
+    return ("%dD %s covariance (ell %g, diagonal %+g), N=%d jittered-grid points in Morton order, "
+            "tile %d, eps %g %s, ARA block %d" % (w.dim, kern, w.ell, w.diag_add, w.n, w.m, w.eps,
+                                                  "absolute" if w.eps_mode == 0 else "relative",
+                                                  w.bs))
+
+
+def cpu_baseline(w, n_sample: int, tlr, torch):
+    """Time the FP64 oracle (left-looking TLR Cholesky with exact SVD
+    recompression) on the leading n_sample x n_sample principal block of the
+    same covariance matrix, and express it in the metric's unit: the
+    executed-flop count of the GPU algorithm on that same block divided by the
+    oracle's time."""
+    from oracle import dense as odense
+    from oracle import tlr as otlr
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max((d.get("num_threads", 1) for d in threadpool_info()), default=os.cpu_count())
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    pts = np.ascontiguousarray(w.points[:n_sample])
+    a_s = otlr.compress_kernel(pts, w.m, w.kernel, w.ell, w.diag_add, w.eps)
+    t0 = time.perf_counter()
+    otlr.tlr_cholesky(a_s, w.eps)
+    t_cpu = time.perf_counter() - t0
+    g = tlr.TLRMatrix.from_tlr(a_s.n, a_s.m, a_s.diag, a_s.u, a_s.v)
+    o = tlr.opts(bs=w.bs, eps_mode=0)
+    g.potrf(w.eps, o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = g.potrf(w.eps, o)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    g.close()
+    return {"value": st["flops"] / t_cpu / 1e12, "unit": "TFLOP/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": "leading %dx%d principal block (%d tiles of %d) of the same matrix; oracle = "
+                      "left-looking TLR Cholesky with truncated-SVD recompression (numpy/LAPACK "
+                      "FP64); work = the GPU algorithm's executed flops on that block (%.3g)"
+                      % (n_sample, n_sample, a_s.nb, w.m, st["flops"]),
+            "oracle_seconds": t_cpu, "gpu_seconds_same_sample": t_gpu}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cov2d_131k")
+    ap.add_argument("--cpu-sample", type=int, default=8192,
+                    help="points of the leading block the CPU oracle factors (0 = skip)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: the factorization is a single-GPU code path "
+              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2108_11932_amd import tlr
+    from paper_2108_11932_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    w = wl.standard(a.workload)
+    print("[bench] building %s on the GPU" % w.name, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    mat = tlr.TLRMatrix.compress_kernel(w.points, w.kernel, w.ell, w.diag_add, w.m, w.eps,
+                                        tlr.opts(bs=w.bs))
+    t_build = time.perf_counter() - t0
+    ra = mat.ranks(tlr.INPUT)[np.tril_indices(mat.nb, -1)]
+    print("[bench] input built in %.1fs, ranks %d..%d mean %.1f" % (t_build, ra.min(), ra.max(),
+                                                                     ra.mean()), file=sys.stderr,
+          flush=True)
+    o = tlr.opts(bs=w.bs, eps_mode=w.eps_mode, flags=tlr.FLAG_KERNEL_TIMING)
+    for i in range(a.warmup):
+        mat.potrf(w.eps, o)
+        print("[bench] warmup %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(a.steps):
+        stats.append(mat.potrf(w.eps, o))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    print("[bench] %d timed steps, %.1f ms each" % (a.steps, dt * 1e3), file=sys.stderr, flush=True)
+    flops = float(np.mean([s["flops"] for s in stats]))
+    flops_paper = float(np.mean([s["flops_paper"] for s in stats]))
+    smp_bytes = sum(s["sample_bytes"] for s in stats)
+    smp_ms = sum(s["sample_ms"] for s in stats)
+    smp_n = sum(s["sample_launches"] for s in stats)
+    achieved = smp_bytes / (smp_ms * 1e-3) / 1e9 if smp_ms > 0 else 0.0
+    rl = mat.ranks(tlr.FACTOR)[np.tril_indices(mat.nb, -1)]
+    line = {
+        "metric": METRIC,
+        "value": flops / dt / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": _describe(w), "name": w.name, "N": w.n, "tile": w.m, "eps": w.eps,
+                   "eps_mode": "absolute" if w.eps_mode == 0 else "relative", "bs": w.bs,
+                   "precision": "fp64"},
+        "time_to_solution_s": dt,
+        "tflops_paper_count": flops_paper / dt / 1e12,
+        "ranks_factor": {"min": int(rl.min()), "mean": float(rl.mean()), "max": int(rl.max())},
+        "ara_iterations": int(stats[-1]["ara_iters"]),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "Schur-complement sampling product Y_i -= U_i* Z_i",
+                     "launches": int(smp_n / max(1, a.steps)),
+                     "bytes_per_launch": smp_bytes / max(1, smp_n),
+                     "avg_launch_us": smp_ms * 1e3 / max(1, smp_n)},
+    }
+    mat.close()
+    if a.cpu_sample > 0:
+        print("[bench] CPU oracle on a %d-point sample" % a.cpu_sample, file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w, min(a.cpu_sample, w.n), tlr, torch)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/* tlr.h -- tile low rank (TLR) Cholesky and LDL^T on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library.  It implements the left-looking TLR factorizations of
+ * Boukaram, Zampini, Turkiyyah and Keyes, "H2OPUS-TLR: High Performance Tile
+ * Low Rank Symmetric Factorizations using Adaptive Randomized Approximation"
+ * (arXiv:2108.11932):
+ *
+ *   tlr_potrf  -- Algorithm "Left Looking TLR Cholesky" (Section 4.3)
+ *   tlr_ldlt   -- Algorithm "Left Looking TLR LDL^T" (Section 5.3)
+ *   tlr_solve  -- Algorithm "TLR Triangular Solve" (Section 4.4), forward and
+ *                 transposed sweeps
+ *   tlr_matvec -- the TLR matrix-vector product (Section 4.4)
+ *   tlr_compress, tlr_compress_kernel -- the TLR representation of Section 1
+ *                 (dense diagonal tiles, off-diagonal tiles U V^T with adaptive
+ *                 ranks), built by adaptive randomized approximation (Section 3.1)
+ *
+ * Matrix format (Section 1, Figure 1).  An N x N symmetric matrix is cut into
+ * nb = ceil(N / m) block rows and columns of size m.  When m does not divide N
+ * the last block row and column are padded to m (Section 6): the padded part
+ * of the last diagonal tile is the identity and the padded rows of U and V are
+ * zero; solves and products ignore the padding.  Diagonal tiles are dense
+ * m x m.  Strictly lower tiles (i > j) are U_ij V_ij^T with U_ij, V_ij of size
+ * m x r_ij, r_ij >= 0; the upper tiles are implied by symmetry.  All matrices
+ * are column-major FP64.
+ *
+ * Threshold.  The compression threshold eps is an absolute per-tile 2-norm
+ * threshold (TLR_EPS_ABS, as in the paper's experiments: every compressed tile
+ * satisfies ||S - Q Q^T S||_2 <= tau with tau = eps, with high probability), or
+ * relative (TLR_EPS_REL: tau = eps * ||A||_2, the norm estimated by power
+ * iteration on the TLR input).
+ *
+ * Memory.  A handle owns all of its device memory.  It is allocated through
+ * the optional allocator callbacks (so a host framework can supply its caching
+ * allocator), else with hipMalloc.  Inputs are copied, never retained.  The
+ * factorization keeps the input tiles and writes the factor into separate
+ * storage of the same handle, so a handle can be refactored (for example with
+ * another threshold or shift) and the input stays available to products.
+ *
+ * Streams.  Every call enqueues its work on `stream` (a hipStream_t; NULL is
+ * the default stream) and returns after a final synchronisation of that
+ * stream, so results and status are valid on return.
+ *
+ * Errors.  Negative codes are caller or system errors, positive codes are
+ * numerical breakdowns.  tlr_last_error() returns a thread-local message for
+ * the last failing call.  On TLR_ERR_ARG nothing is modified.  On a
+ * breakdown, stats->info holds the 1-based global row of the failing pivot
+ * (LAPACK convention) and the factor is marked invalid.
+ */
+#ifndef TLR_H
+#define TLR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tlr_matrix_s* tlr_matrix_t;
+
+typedef enum {
+  TLR_OK = 0,
+  TLR_ERR_ARG = -1,        /* invalid argument */
+  TLR_ERR_OOM = -2,        /* device or pinned host allocation failed */
+  TLR_ERR_DEVICE = -3,     /* HIP runtime error */
+  TLR_ERR_STATE = -4,      /* handle not in the state the call needs */
+  TLR_ERR_NOT_SPD = 1,     /* a diagonal tile lost definiteness (Section 5.1) */
+  TLR_ERR_ZERO_PIVOT = 2   /* unpivoted LDL^T met a zero pivot */
+} tlr_status;
+
+enum { TLR_EPS_ABS = 0, TLR_EPS_REL = 1 };
+enum { TLR_FP64 = 0 };
+enum { TLR_KERNEL_EXP = 0, TLR_KERNEL_MATERN15 = 1 };
+enum { TLR_INPUT = 0, TLR_FACTOR = 1 };
+
+/* Device memory callbacks.  alloc returns NULL on failure; free receives
+ * pointers returned by alloc.  `stream` is the stream the memory is used on. */
+typedef struct {
+  void* ctx;
+  void* (*alloc)(void* ctx, size_t bytes, void* stream);
+  void (*free)(void* ctx, void* p, void* stream);
+} tlr_allocator;
+
+/* Options of compression and factorization. */
+typedef struct {
+  int bs;                  /* ARA block size: samples per iteration (1..32); the
+                              paper uses 16 in 2D and 32 in 3D (Section 6) */
+  int eps_mode;            /* TLR_EPS_ABS (default) or TLR_EPS_REL */
+  int precision;           /* TLR_FP64 */
+  double shift;            /* factor A + shift * I (diagonal shift, Section 5.1);
+                              a negative value means shift = tau */
+  int max_active;          /* size of the active subset of tiles per column
+                              (Algorithm "Left Looking Cholesky TLR ARA Update",
+                              "subset"); <= 0 means all tiles of the column */
+  int r_min;               /* a tile has converged once at least r_min samples of
+                              a block stay below tau after orthogonalisation (>= 1) */
+  unsigned long long seed; /* seed of the Philox4x32-10 test-matrix stream */
+  int flags;               /* TLR_FLAG_* bits */
+} tlr_opts;
+
+/* opts.flags: record HIP events around every launch of the Schur-complement
+ * sampling product (the dominant kernel) and report its time and
+ * algorithmic bytes in tlr_stats.sample_*. */
+enum { TLR_FLAG_KERNEL_TIMING = 1 };
+
+/* Results of a factorization. */
+typedef struct {
+  int info;                /* 1-based global row of a failed pivot, 0 = success */
+  double tau;              /* absolute per-tile threshold used */
+  double norm_a;           /* ||A||_2 estimate (TLR_EPS_REL only, else 0) */
+  double flops;            /* floating point operations executed on the GPU */
+  double flops_paper;      /* operation count of the paper's formulation */
+  double bytes_alg;        /* algorithmic HBM bytes of the sampling kernels */
+  long long ara_iters;     /* sum over columns of ARA iterations (launch batches) */
+  long long tile_iters;    /* sum over tiles of ARA iterations */
+  long long full_rank_tiles; /* tiles whose rank reached m */
+  int max_rank;            /* largest rank of the factor */
+  double mean_rank;        /* mean rank of the strictly lower tiles of the factor */
+  double factor_bytes;     /* device bytes held by the factor */
+  long long sample_launches; /* TLR_FLAG_KERNEL_TIMING: launches of the sampling product */
+  double sample_ms;        /* their summed duration (HIP events), milliseconds */
+  double sample_bytes;     /* their algorithmic HBM bytes: U panels, Z, Y read and write */
+  double sample_flops;     /* their flops */
+} tlr_stats;
+
+/* Fill *opts with the defaults: bs 16, absolute eps, FP64, shift 0, all tiles
+ * active, r_min 1, seed 0x5eed. */
+void tlr_opts_default(tlr_opts* opts);
+
+/* Create an N x N matrix with tile size m and the given ranks of the strictly
+ * lower tiles (ranks[i * nb + j] for i > j, other entries ignored; host
+ * memory; NULL means all zero).  Diagonal tiles start as the identity, factors
+ * as zero; fill them with tlr_set_diag / tlr_set_tile.  allocator may be NULL.
+ * Errors: TLR_ERR_ARG for N <= 0, m <= 0, m > N rounded up, a negative rank or
+ * a rank above m; TLR_ERR_OOM. */
+tlr_status tlr_create(long long N, int m, const int* ranks, const tlr_allocator* allocator,
+                      void* stream, tlr_matrix_t* out);
+
+/* Copy the m x m diagonal tile k (leading dimension ld) from host
+ * (on_device = 0) or device memory.  For the last, padded tile only the real
+ * rows and columns are read. */
+tlr_status tlr_set_diag(tlr_matrix_t A, int k, const double* D, int ld, int on_device);
+
+/* Copy U_ij and V_ij (m x r_ij each, leading dimension ld >= m) of the strictly
+ * lower tile (i, j), i > j.  Padded rows are set to zero. */
+tlr_status tlr_set_tile(tlr_matrix_t A, int i, int j, const double* U, const double* V, int ld,
+                        int on_device);
+
+/* Build the TLR form of the dense symmetric N x N matrix A (device memory,
+ * leading dimension lda >= N; only the lower triangle is read) with tile size
+ * m: diagonal tiles are copied and every strictly lower tile is compressed by
+ * adaptive randomized approximation at threshold eps (opts->eps_mode is
+ * ignored: eps is absolute).  opts may be NULL. */
+tlr_status tlr_compress(const double* A, long long lda, long long N, int m, double eps,
+                        const tlr_opts* opts, const tlr_allocator* allocator, void* stream,
+                        tlr_matrix_t* out);
+
+/* Build the TLR form of the covariance matrix K(x_a, x_b) + diag_add * I of N
+ * points (device memory, row-major N x dim, dim 1..3) without forming it:
+ * tiles are generated on the device and compressed as in tlr_compress.
+ * kernel: TLR_KERNEL_EXP, exp(-r / ell), or TLR_KERNEL_MATERN15,
+ * (1 + sqrt(3) r / ell) exp(-sqrt(3) r / ell); r is the Euclidean distance. */
+tlr_status tlr_compress_kernel(const double* points, int dim, long long N, int kernel, double ell,
+                               double diag_add, int m, double eps, const tlr_opts* opts,
+                               const tlr_allocator* allocator, void* stream, tlr_matrix_t* out);
+
+/* Left-looking TLR Cholesky A + shift I = L L^T (Algorithm "Left Looking TLR
+ * Cholesky").  Column k: dense update of the diagonal tile with the low rank
+ * products of row k, dense Cholesky, batched ARA of the Schur-complement
+ * tiles of column k sampled through Eq. (1)-(2) with dynamic batching, batched
+ * triangular solve with L_kk.  Every off-diagonal tile of L is compressed
+ * once, at threshold tau.  stats may be NULL.  Returns TLR_ERR_NOT_SPD when a
+ * diagonal tile is not positive definite after its update. */
+tlr_status tlr_potrf(tlr_matrix_t A, double eps, const tlr_opts* opts, tlr_stats* stats,
+                     void* stream);
+
+/* Left-looking TLR LDL^T A = L D L^T, L unit lower triangular, D diagonal
+ * (Algorithm "Left Looking TLR LDL^T", Eq. (3)); the diagonal tiles use an
+ * unpivoted LDL^T with scalar pivots.  D (device, N entries, may be NULL)
+ * receives the pivots.  Returns TLR_ERR_ZERO_PIVOT when a pivot satisfies
+ * |d| <= 64 u ||A_kk||_F. */
+tlr_status tlr_ldlt(tlr_matrix_t A, double eps, const tlr_opts* opts, double* D, tlr_stats* stats,
+                    void* stream);
+
+/* B <- (L L^T)^{-1} B or (L D L^T)^{-1} B with the factor held by the handle
+ * (Algorithm "TLR Triangular Solve" and its transpose).  B is N x nrhs,
+ * device memory, leading dimension ldb >= N.  TLR_ERR_STATE if the handle
+ * holds no factor. */
+tlr_status tlr_solve(tlr_matrix_t A, int nrhs, double* B, long long ldb, void* stream);
+
+/* Y <- A X for the TLR input matrix (which = TLR_INPUT), X and Y N x nrhs in
+ * device memory. */
+tlr_status tlr_matvec(tlr_matrix_t A, int nrhs, const double* X, long long ldx, double* Y,
+                      long long ldy, void* stream);
+
+/* Sizes and bookkeeping.  which = TLR_INPUT or TLR_FACTOR. */
+tlr_status tlr_get_info(tlr_matrix_t A, long long* N, int* m, int* nb, int* factored);
+/* ranks: host array of nb * nb ints, row-major, strictly lower part filled. */
+tlr_status tlr_get_ranks(tlr_matrix_t A, int which, int* ranks);
+/* offsets: host array of nb * nb long longs: column of tile (i, j) in the
+ * arena that holds all U (or V) factors side by side (input: row-major lower
+ * order), or inside block row i's panel (factor); -1 off the strict lower
+ * part. */
+tlr_status tlr_get_offsets(tlr_matrix_t A, int which, long long* offsets);
+/* Copy tile factors / diagonal tiles to host memory (ld >= m). */
+tlr_status tlr_get_tile(tlr_matrix_t A, int which, int i, int j, double* U, double* V, int ld);
+tlr_status tlr_get_diag(tlr_matrix_t A, int which, int k, double* D, int ld);
+/* LDL^T pivots (nb * m entries including the padding) to host memory. */
+tlr_status tlr_get_pivots(tlr_matrix_t A, double* d);
+
+tlr_status tlr_destroy(tlr_matrix_t A);
+const char* tlr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TLR_H */

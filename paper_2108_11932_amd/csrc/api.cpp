@@ -1,0 +1,375 @@
+// C ABI of the TLR library (include/tlr.h): argument validation, handle life
+// cycle, data transfer in and out of the handle.
+#include <algorithm>
+#include <cmath>
+
+#include "host.h"
+
+using namespace tlr;
+
+namespace tlr {
+const char* last_error();
+}
+
+#define TLR_ARG(cond, ...)          \
+  do {                              \
+    if (!(cond)) {                  \
+      ::tlr::set_error(__VA_ARGS__); \
+      return TLR_ERR_ARG;           \
+    }                               \
+  } while (0)
+
+static constexpr int M_MAX = 8192;
+
+extern "C" {
+
+void tlr_opts_default(tlr_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->bs = 16;
+  o->eps_mode = TLR_EPS_ABS;
+  o->precision = TLR_FP64;
+  o->shift = 0.0;
+  o->max_active = 0;
+  o->r_min = 1;
+  o->seed = 0x5eedULL;
+  o->flags = 0;
+}
+
+const char* tlr_last_error(void) { return tlr::last_error(); }
+
+}  // extern "C"
+
+static tlr_status check_opts(const tlr_opts* in, tlr_opts* out) {
+  if (in)
+    *out = *in;
+  else
+    tlr_opts_default(out);
+  TLR_ARG(out->bs >= 1 && out->bs <= 32, "opts.bs must be in 1..32, got %d", out->bs);
+  TLR_ARG(out->eps_mode == TLR_EPS_ABS || out->eps_mode == TLR_EPS_REL, "opts.eps_mode invalid");
+  TLR_ARG(out->precision == TLR_FP64, "opts.precision: only TLR_FP64 is supported");
+  TLR_ARG(out->r_min >= 1 && out->r_min <= out->bs, "opts.r_min must be in 1..bs");
+  TLR_ARG(std::isfinite(out->shift), "opts.shift must be finite");
+  return TLR_OK;
+}
+
+static tlr_status new_handle(long long N, int m, const tlr_allocator* alloc, void* stream,
+                             Handle** out) {
+  TLR_ARG(out != nullptr, "output handle pointer is NULL");
+  *out = nullptr;
+  TLR_ARG(N > 0, "N must be positive, got %lld", N);
+  TLR_ARG(m > 0 && m <= M_MAX, "tile size m must be in 1..%d, got %d", M_MAX, m);
+  TLR_ARG(N <= (1LL << 31) - 1, "N too large");
+  TLR_ARG(alloc == nullptr || (alloc->alloc && alloc->free), "allocator callbacks missing");
+  Handle* h = new Handle();
+  h->N = N;
+  h->m = m;
+  h->nb = (int)((N + m - 1) / m);
+  h->stream = (hipStream_t)stream;
+  h->mem.stream = h->stream;
+  if (alloc) {
+    h->mem.alloc = *alloc;
+    h->mem.custom = true;
+  }
+  if (hipGetDevice(&h->dev) != hipSuccess) {
+    (void)hipGetLastError();
+    delete h;
+    set_error("no HIP device available");
+    return TLR_ERR_DEVICE;
+  }
+  tlr_status st = h->stage.init(h->mem, (size_t)16 << 20);
+  if (st == TLR_OK) st = h->mem.get((void**)&h->d_info, 256);
+  if (st == TLR_OK && hipMemsetAsync(h->d_info, 0, 256, h->stream) != hipSuccess) {
+    set_error("hipMemsetAsync of the status word failed");
+    st = TLR_ERR_DEVICE;
+  }
+  if (st == TLR_OK) st = h->mem.get((void**)&h->Ad, sizeof(double) * (size_t)h->nb * m * m);
+  if (st != TLR_OK) {
+    tlr_destroy(h);
+    return st;
+  }
+  h->a_rank.assign((size_t)h->nb * h->nb, 0);
+  h->a_off.assign((size_t)h->nb * h->nb, -1);
+  free_factor(h);
+  *out = h;
+  return TLR_OK;
+}
+
+namespace tlr {
+tlr_status alloc_input(Handle* h, const int* ranks) {
+  const int nb = h->nb, m = h->m;
+  long long cols = 0;
+  for (int i = 0; i < nb; ++i)
+    for (int j = 0; j < i; ++j) {
+      const int r = ranks ? ranks[(size_t)i * nb + j] : 0;
+      h->a_rank[(size_t)i * nb + j] = r;
+      h->a_off[(size_t)i * nb + j] = cols;
+      cols += r;
+    }
+  h->a_cols = cols;
+  TLR_TRY(h->mem.get((void**)&h->UA, sizeof(double) * (size_t)std::max(cols, 1LL) * m));
+  TLR_TRY(h->mem.get((void**)&h->VA, sizeof(double) * (size_t)std::max(cols, 1LL) * m));
+  TLR_HIP(hipMemsetAsync(h->UA, 0, sizeof(double) * (size_t)std::max(cols, 1LL) * m, h->stream));
+  TLR_HIP(hipMemsetAsync(h->VA, 0, sizeof(double) * (size_t)std::max(cols, 1LL) * m, h->stream));
+  // identity diagonal tiles
+  TLR_HIP(hipMemsetAsync(h->Ad, 0, sizeof(double) * (size_t)nb * m * m, h->stream));
+  for (int k = 0; k < nb; ++k)
+    TLR_HIP(launch_copy_shift(h->diagA(k), h->diagA(k), m, m, 1.0, h->stream));
+  return h->sync();
+}
+}  // namespace tlr
+
+extern "C" {
+
+tlr_status tlr_create(long long N, int m, const int* ranks, const tlr_allocator* allocator,
+                      void* stream, tlr_matrix_t* out) {
+  Handle* h = nullptr;
+  TLR_TRY(new_handle(N, m, allocator, stream, &h));
+  if (ranks) {
+    for (int i = 0; i < h->nb; ++i)
+      for (int j = 0; j < i; ++j) {
+        const int r = ranks[(size_t)i * h->nb + j];
+        if (r < 0 || r > m) {
+          tlr_destroy(h);
+          set_error("rank of tile (%d, %d) is %d, must be in 0..m", i, j, r);
+          return TLR_ERR_ARG;
+        }
+      }
+  }
+  tlr_status st = alloc_input(h, ranks);
+  if (st != TLR_OK) {
+    tlr_destroy(h);
+    return st;
+  }
+  *out = h;
+  return TLR_OK;
+}
+
+static hipMemcpyKind kind_in(int on_device) {
+  return on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+}
+
+tlr_status tlr_set_diag(tlr_matrix_t A, int k, const double* D, int ld, int on_device) {
+  TLR_ARG(A && D, "NULL argument");
+  TLR_ARG(k >= 0 && k < A->nb, "tile index %d out of range", k);
+  const int nr = A->nreal(k);
+  TLR_ARG(ld >= nr, "leading dimension too small");
+  TLR_HIP(hipMemcpy2DAsync(A->diagA(k), sizeof(double) * A->m, D, sizeof(double) * ld,
+                           sizeof(double) * nr, nr, kind_in(on_device), A->stream));
+  A->norm_a = 0.0;
+  return A->sync();
+}
+
+tlr_status tlr_set_tile(tlr_matrix_t A, int i, int j, const double* U, const double* V, int ld,
+                        int on_device) {
+  TLR_ARG(A, "NULL handle");
+  TLR_ARG(i >= 0 && i < A->nb && j >= 0 && j < i, "tile (%d, %d) is not strictly lower", i, j);
+  const int r = A->ar(i, j);
+  if (r == 0) return TLR_OK;
+  TLR_ARG(U && V, "NULL factor");
+  const int m = A->m;
+  TLR_ARG(ld >= A->nreal(i) && ld >= A->nreal(j), "leading dimension too small");
+  TLR_HIP(hipMemsetAsync(A->ua(i, j), 0, sizeof(double) * (size_t)m * r, A->stream));
+  TLR_HIP(hipMemsetAsync(A->va(i, j), 0, sizeof(double) * (size_t)m * r, A->stream));
+  TLR_HIP(hipMemcpy2DAsync(A->ua(i, j), sizeof(double) * m, U, sizeof(double) * ld,
+                           sizeof(double) * A->nreal(i), r, kind_in(on_device), A->stream));
+  TLR_HIP(hipMemcpy2DAsync(A->va(i, j), sizeof(double) * m, V, sizeof(double) * ld,
+                           sizeof(double) * A->nreal(j), r, kind_in(on_device), A->stream));
+  A->norm_a = 0.0;
+  return A->sync();
+}
+
+tlr_status tlr_compress(const double* Adense, long long lda, long long N, int m, double eps,
+                        const tlr_opts* opts, const tlr_allocator* allocator, void* stream,
+                        tlr_matrix_t* out) {
+  TLR_ARG(Adense, "NULL matrix");
+  TLR_ARG(lda >= N, "lda < N");
+  TLR_ARG(eps > 0.0 && std::isfinite(eps), "eps must be positive");
+  tlr_opts o;
+  TLR_TRY(check_opts(opts, &o));
+  Handle* h = nullptr;
+  TLR_TRY(new_handle(N, m, allocator, stream, &h));
+  tlr_status st = compress(h, Adense, lda, nullptr, 0, -1, 1.0, 0.0, eps, o);
+  if (st != TLR_OK) {
+    tlr_destroy(h);
+    return st;
+  }
+  *out = h;
+  return TLR_OK;
+}
+
+tlr_status tlr_compress_kernel(const double* points, int dim, long long N, int kernel, double ell,
+                               double diag_add, int m, double eps, const tlr_opts* opts,
+                               const tlr_allocator* allocator, void* stream, tlr_matrix_t* out) {
+  TLR_ARG(points, "NULL points");
+  TLR_ARG(dim >= 1 && dim <= 3, "dim must be 1..3");
+  TLR_ARG(kernel == TLR_KERNEL_EXP || kernel == TLR_KERNEL_MATERN15, "unknown kernel");
+  TLR_ARG(ell > 0.0 && std::isfinite(ell), "ell must be positive");
+  TLR_ARG(std::isfinite(diag_add), "diag_add must be finite");
+  TLR_ARG(eps > 0.0 && std::isfinite(eps), "eps must be positive");
+  tlr_opts o;
+  TLR_TRY(check_opts(opts, &o));
+  Handle* h = nullptr;
+  TLR_TRY(new_handle(N, m, allocator, stream, &h));
+  tlr_status st = compress(h, nullptr, 0, points, dim, kernel, ell, diag_add, eps, o);
+  if (st != TLR_OK) {
+    tlr_destroy(h);
+    return st;
+  }
+  *out = h;
+  return TLR_OK;
+}
+
+static tlr_status factor_entry(tlr_matrix_t A, double eps, const tlr_opts* opts, tlr_stats* stats,
+                               bool ldl, double* D) {
+  TLR_ARG(A, "NULL handle");
+  TLR_ARG(eps > 0.0 && std::isfinite(eps), "eps must be positive");
+  tlr_opts o;
+  TLR_TRY(check_opts(opts, &o));
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  tlr_status st = factorize(A, eps, o, stats, ldl);
+  if (st == TLR_OK && ldl && D) {
+    TLR_HIP(hipMemcpyAsync(D, A->Dv, sizeof(double) * A->N, hipMemcpyDeviceToDevice, A->stream));
+    st = A->sync();
+  }
+  if (st < 0 && st != TLR_ERR_ARG) A->factored = 0;
+  return st;
+}
+
+tlr_status tlr_potrf(tlr_matrix_t A, double eps, const tlr_opts* opts, tlr_stats* stats,
+                     void* stream) {
+  if (A) A->stream = A->mem.stream = (hipStream_t)stream;
+  return factor_entry(A, eps, opts, stats, false, nullptr);
+}
+
+tlr_status tlr_ldlt(tlr_matrix_t A, double eps, const tlr_opts* opts, double* D, tlr_stats* stats,
+                    void* stream) {
+  if (A) A->stream = A->mem.stream = (hipStream_t)stream;
+  return factor_entry(A, eps, opts, stats, true, D);
+}
+
+tlr_status tlr_solve(tlr_matrix_t A, int nrhs, double* B, long long ldb, void* stream) {
+  TLR_ARG(A && B, "NULL argument");
+  TLR_ARG(nrhs >= 0, "nrhs must be non-negative");
+  TLR_ARG(ldb >= A->N, "ldb < N");
+  if (!A->factored) {
+    set_error("the handle holds no factor");
+    return TLR_ERR_STATE;
+  }
+  if (nrhs == 0) return TLR_OK;
+  A->stream = A->mem.stream = (hipStream_t)stream;
+  return solve(A, nrhs, B, ldb);
+}
+
+tlr_status tlr_matvec(tlr_matrix_t A, int nrhs, const double* X, long long ldx, double* Y,
+                      long long ldy, void* stream) {
+  TLR_ARG(A && X && Y, "NULL argument");
+  TLR_ARG(nrhs >= 0, "nrhs must be non-negative");
+  TLR_ARG(ldx >= A->N && ldy >= A->N, "leading dimension < N");
+  if (nrhs == 0) return TLR_OK;
+  A->stream = A->mem.stream = (hipStream_t)stream;
+  TLR_TRY(matvec(A, nrhs, X, ldx, Y, ldy));
+  return A->sync();
+}
+
+tlr_status tlr_get_info(tlr_matrix_t A, long long* N, int* m, int* nb, int* factored) {
+  TLR_ARG(A, "NULL handle");
+  if (N) *N = A->N;
+  if (m) *m = A->m;
+  if (nb) *nb = A->nb;
+  if (factored) *factored = A->factored;
+  return TLR_OK;
+}
+
+tlr_status tlr_get_ranks(tlr_matrix_t A, int which, int* ranks) {
+  TLR_ARG(A && ranks, "NULL argument");
+  TLR_ARG(which == TLR_INPUT || which == TLR_FACTOR, "which must be TLR_INPUT or TLR_FACTOR");
+  if (which == TLR_FACTOR && !A->factored) {
+    set_error("the handle holds no factor");
+    return TLR_ERR_STATE;
+  }
+  const auto& src = which == TLR_INPUT ? A->a_rank : A->l_rank;
+  std::copy(src.begin(), src.end(), ranks);
+  return TLR_OK;
+}
+
+tlr_status tlr_get_offsets(tlr_matrix_t A, int which, long long* offsets) {
+  TLR_ARG(A && offsets, "NULL argument");
+  TLR_ARG(which == TLR_INPUT || which == TLR_FACTOR, "which must be TLR_INPUT or TLR_FACTOR");
+  if (which == TLR_FACTOR && !A->factored) {
+    set_error("the handle holds no factor");
+    return TLR_ERR_STATE;
+  }
+  const auto& src = which == TLR_INPUT ? A->a_off : A->l_off;
+  for (int i = 0; i < A->nb; ++i)
+    for (int j = 0; j < A->nb; ++j) offsets[(size_t)i * A->nb + j] = j < i ? src[(size_t)i * A->nb + j] : -1;
+  return TLR_OK;
+}
+
+tlr_status tlr_get_tile(tlr_matrix_t A, int which, int i, int j, double* U, double* V, int ld) {
+  TLR_ARG(A, "NULL handle");
+  TLR_ARG(which == TLR_INPUT || which == TLR_FACTOR, "which must be TLR_INPUT or TLR_FACTOR");
+  TLR_ARG(i >= 0 && i < A->nb && j >= 0 && j < i, "tile (%d, %d) is not strictly lower", i, j);
+  TLR_ARG(ld >= A->m, "ld < m");
+  if (which == TLR_FACTOR && !A->factored) {
+    set_error("the handle holds no factor");
+    return TLR_ERR_STATE;
+  }
+  const int r = which == TLR_INPUT ? A->ar(i, j) : A->lr(i, j);
+  if (r == 0) return TLR_OK;
+  TLR_ARG(U && V, "NULL output");
+  const double* su = which == TLR_INPUT ? A->ua(i, j) : A->ul(i, j);
+  const double* sv = which == TLR_INPUT ? A->va(i, j) : A->vl(i, j);
+  TLR_HIP(hipMemcpy2D(U, sizeof(double) * ld, su, sizeof(double) * A->m, sizeof(double) * A->m, r,
+                      hipMemcpyDeviceToHost));
+  TLR_HIP(hipMemcpy2D(V, sizeof(double) * ld, sv, sizeof(double) * A->m, sizeof(double) * A->m, r,
+                      hipMemcpyDeviceToHost));
+  return TLR_OK;
+}
+
+tlr_status tlr_get_diag(tlr_matrix_t A, int which, int k, double* D, int ld) {
+  TLR_ARG(A && D, "NULL argument");
+  TLR_ARG(which == TLR_INPUT || which == TLR_FACTOR, "which must be TLR_INPUT or TLR_FACTOR");
+  TLR_ARG(k >= 0 && k < A->nb, "tile index out of range");
+  TLR_ARG(ld >= A->m, "ld < m");
+  if (which == TLR_FACTOR && !A->factored) {
+    set_error("the handle holds no factor");
+    return TLR_ERR_STATE;
+  }
+  const double* src = which == TLR_INPUT ? A->diagA(k) : A->diagL(k);
+  TLR_HIP(hipMemcpy2D(D, sizeof(double) * ld, src, sizeof(double) * A->m, sizeof(double) * A->m,
+                      A->m, hipMemcpyDeviceToHost));
+  return TLR_OK;
+}
+
+tlr_status tlr_get_pivots(tlr_matrix_t A, double* d) {
+  TLR_ARG(A && d, "NULL argument");
+  if (A->factored != 2) {
+    set_error("the handle holds no LDL^T factor");
+    return TLR_ERR_STATE;
+  }
+  TLR_HIP(hipMemcpy(d, A->Dv, sizeof(double) * (size_t)A->nb * A->m, hipMemcpyDeviceToHost));
+  return TLR_OK;
+}
+
+tlr_status tlr_destroy(tlr_matrix_t A) {
+  if (!A) return TLR_OK;
+  (void)hipStreamSynchronize(A->stream);
+  free_factor(A);
+  Mem& mem = A->mem;
+  mem.put(A->Ad);
+  mem.put(A->Ld);
+  mem.put(A->Dv);
+  mem.put(A->UA);
+  mem.put(A->VA);
+  mem.put(A->d_info);
+  Work& w = A->ws;
+  DevBuf* bufs[] = {&w.G, &w.W, &w.omega, &w.P, &w.Z, &w.T, &w.Ta, &w.H, &w.Ball, &w.C, &w.Wa,
+                    &w.Y, &w.Q, &w.part, &w.rfac, &w.ints, &w.orth, &w.dscale, &w.tol, &w.compact};
+  for (DevBuf* b : bufs) b->release(mem);
+  A->stage.release(mem);
+  delete A;
+  return TLR_OK;
+}
+
+}  // extern "C"

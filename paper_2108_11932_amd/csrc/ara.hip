@@ -1,0 +1,483 @@
+// Kernels of the batched adaptive randomized approximation (Section 3.1 and
+// Algorithm "Left Looking Cholesky TLR ARA Update", Section 4.2):
+//
+//  * batchRandn      -- Philox4x32-10 + Box-Muller Gaussian test matrices
+//  * batchOrthog     -- block Gram-Schmidt, the QR of each block done by a
+//                       Cholesky QR whose Gram matrix and Cholesky factor are
+//                       carried in double-double (the paper's mixed-precision
+//                       Cholesky QR), with diagonal pivoting and a threshold
+//                       so that the rank is found column by column
+//  * getConvergedTiles / updateSubset -- convergence flags and the stable
+//                       compaction + refill of the active subset
+//  * sortRanks       -- order of the tiles of a column by input rank
+#include "tlr_internal.h"
+
+// The double-double arithmetic below relies on error-free transformations
+// that must see every product and sum rounded separately: no contraction of
+// a*b + c into fused multiply-adds in this file (explicit fma() calls stay).
+#pragma clang fp contract(off)
+
+namespace tlr {
+
+namespace {
+
+// ------------------------------------------------------------------ Philox
+constexpr unsigned PH_M0 = 0xD2511F53u, PH_M1 = 0xCD9E8D57u;
+constexpr unsigned PH_W0 = 0x9E3779B9u, PH_W1 = 0xBB67AE85u;
+
+__device__ inline uint4 philox10(uint4 c, unsigned k0, unsigned k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += PH_W0; k1 += PH_W1; }
+    const unsigned hi0 = __umulhi(PH_M0, c.x), lo0 = PH_M0 * c.x;
+    const unsigned hi1 = __umulhi(PH_M1, c.z), lo1 = PH_M1 * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+__device__ inline double u53(unsigned hi, unsigned lo) {
+  return ((double)(hi >> 5) * 67108864.0 + (double)(lo >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+__global__ void k_randn(double* out, int rows, int cols, int ld, unsigned k0, unsigned k1,
+                        unsigned k, unsigned t, unsigned strm) {
+  const long long n = (long long)rows * cols;
+  const long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (2 * c >= n) return;
+  const uint4 w = philox10(make_uint4((unsigned)c, t, k, strm), k0, k1);
+  const double u1 = 1.0 - u53(w.x, w.y);
+  const double u2 = u53(w.z, w.w);
+  const double rad = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincos(6.283185307179586476925286766559 * u2, &sn, &cs);
+  long long e = 2 * c;
+  out[(e % rows) + (e / rows) * (long long)ld] = rad * cs;
+  if (e + 1 < n) {
+    e += 1;
+    out[(e % rows) + (e / rows) * (long long)ld] = rad * sn;
+  }
+}
+
+__global__ void k_philox_raw(unsigned* out, int n, unsigned k0, unsigned k1, unsigned c1,
+                             unsigned c2, unsigned c3) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const uint4 w = philox10(make_uint4((unsigned)c, c1, c2, c3), k0, k1);
+  out[4 * c + 0] = w.x;
+  out[4 * c + 1] = w.y;
+  out[4 * c + 2] = w.z;
+  out[4 * c + 3] = w.w;
+}
+
+// ------------------------------------------------------------ double-double
+// Error-free transformations (Knuth TwoSum, FMA-based TwoProduct) and the
+// double-double operations built on them (Dekker; Bailey's QD library).
+struct dd {
+  double hi, lo;
+};
+__device__ inline dd two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ inline dd fast_two_sum(double a, double b) {
+  const double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ inline dd two_prod(double a, double b) {
+  const double p = a * b;
+  return {p, fma(a, b, -p)};
+}
+__device__ inline dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  const dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+__device__ inline dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+__device__ inline dd dd_sub(dd a, dd b) { return dd_add(a, dd_neg(b)); }
+__device__ inline dd dd_mul(dd a, dd b) {
+  dd p = two_prod(a.hi, b.hi);
+  p.lo += a.hi * b.lo + a.lo * b.hi;
+  return fast_two_sum(p.hi, p.lo);
+}
+__device__ inline dd dd_div(dd a, dd b) {
+  const double q1 = a.hi / b.hi;
+  dd r = dd_sub(a, dd_mul(b, dd{q1, 0.0}));
+  const double q2 = r.hi / b.hi;
+  r = dd_sub(r, dd_mul(b, dd{q2, 0.0}));
+  const double q3 = r.hi / b.hi;
+  const dd q = fast_two_sum(q1, q2);
+  return dd_add(q, dd{q3, 0.0});
+}
+__device__ inline dd dd_sqrt(dd a) {
+  if (!(a.hi > 0.0)) return {0.0, 0.0};
+  const double x = 1.0 / sqrt(a.hi);
+  const double ax = a.hi * x;
+  const dd diff = dd_sub(a, two_prod(ax, ax));
+  return fast_two_sum(ax, diff.hi * (x * 0.5));
+}
+
+// ------------------------------------------------------------ Gram matrices
+// Partial Gram sums X^T X over a block of rows, accumulated with the
+// compensated dot product of Ogita, Rump and Oishi (Dot2) and stored as
+// unevaluated (hi, lo) pairs.  X is the first `nc` columns of the block;
+// nc comes from the tile's pivot record when ncols_from_piv is set.
+constexpr int GRAM_ROWS = 128;
+constexpr int BS_MAX = 32;
+
+__global__ __launch_bounds__(256) void k_gram_dd(const OrthDesc* __restrict__ descs, int m, int bs,
+                                                 int pass, int nrb) {
+  __shared__ double X[BS_MAX][GRAM_ROWS + 1];
+  const OrthDesc d = descs[blockIdx.y];
+  const int rb = blockIdx.x;
+  const int r0 = rb * GRAM_ROWS;
+  const int rows = min(GRAM_ROWS, m - r0);
+  const double* src;
+  int nc;
+  if (pass == 1) {
+    src = d.Y;
+    nc = bs;
+  } else {
+    nc = d.piv[bs];
+    src = d.Q + (size_t)d.qold * m;
+  }
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nc * GRAM_ROWS; e += blockDim.x) {
+    const int r = e % GRAM_ROWS, c = e / GRAM_ROWS;
+    X[c][r] = (r < rows) ? src[(r0 + r) + (size_t)c * m] : 0.0;
+  }
+  __syncthreads();
+  const int npairs = nc * (nc + 1) / 2;
+  double* out = d.part + (size_t)rb * bs * bs * 2;
+  for (int pr = tid; pr < npairs; pr += blockDim.x) {
+    // pair index -> (a, b), a <= b, column-by-column upper triangle
+    int b = (int)((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
+    while (b * (b + 1) / 2 > pr) --b;
+    while ((b + 1) * (b + 2) / 2 <= pr) ++b;
+    const int a = pr - b * (b + 1) / 2;
+    double s = 0.0, c = 0.0;
+    for (int r = 0; r < rows; ++r) {
+      const double x = X[a][r], y = X[b][r];
+      const double p = x * y;
+      const double e = fma(x, y, -p);
+      const double t = s + p;
+      const double z = t - s;
+      const double q = (s - (t - z)) + (p - z);
+      s = t;
+      c += q + e;
+    }
+    const dd v = fast_two_sum(s, c);
+    out[(a + b * bs) * 2 + 0] = v.hi;
+    out[(a + b * bs) * 2 + 1] = v.lo;
+  }
+}
+
+// Sum of the partial Gram matrices into G (dd, full symmetric, LDS).
+__device__ void gram_sum(const OrthDesc& d, int bs, int nc, int nrb, dd (*G)[BS_MAX + 1]) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nc * nc; e += blockDim.x) {
+    const int a = e % nc, b = e / nc;
+    if (a > b) continue;
+    dd acc{0.0, 0.0};
+    for (int rb = 0; rb < nrb; ++rb) {
+      const double* p = d.part + (size_t)rb * bs * bs * 2 + (a + b * bs) * 2;
+      acc = dd_add(acc, dd{p[0], p[1]});
+    }
+    G[a][b] = acc;
+    G[b][a] = acc;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------- pivoted Cholesky (pass 1)
+// Diagonally pivoted Cholesky of the dd Gram matrix G = Y^T Y with the
+// threshold tau^2 on the Schur-complement diagonal: column j is accepted
+// while the largest remaining diagonal (the squared norm of a sample
+// column after removing the accepted directions) exceeds tau^2.  p accepted
+// pivots give Y_P = Q_new R with R p x p upper triangular.  The tile has
+// converged when at least r_min samples were left below tau, or the basis
+// has reached its capacity.  Writes the pivots, p, the inverse factor R^{-1}
+// (rounded to double), the new basis width and the convergence flag.
+__global__ __launch_bounds__(64) void k_pivchol(const OrthDesc* __restrict__ descs, int bs, int nrb,
+                                                double tau2, int r_min, int qcap) {
+  __shared__ dd G[BS_MAX][BS_MAX + 1];
+  __shared__ dd R[BS_MAX][BS_MAX + 1];   // R[row][col], upper
+  __shared__ dd Ri[BS_MAX][BS_MAX + 1];  // inverse, upper
+  __shared__ int perm[BS_MAX];
+  __shared__ int s_p, s_piv;
+  const OrthDesc d = descs[blockIdx.x];
+  const int tid = threadIdx.x;
+  gram_sum(d, bs, bs, nrb, G);
+  if (tid < bs) perm[tid] = tid;
+  for (int e = tid; e < BS_MAX * BS_MAX; e += blockDim.x) {
+    R[e % BS_MAX][e / BS_MAX] = dd{0.0, 0.0};
+    Ri[e % BS_MAX][e / BS_MAX] = dd{0.0, 0.0};
+  }
+  if (tid == 0) s_p = 0;
+  __syncthreads();
+  const int qold = d.qold;
+  const int room = max(0, qcap - qold);
+  for (int j = 0; j < bs; ++j) {
+    if (tid == 0) {
+      int best = j;
+      double bv = G[j][j].hi;
+      for (int c = j + 1; c < bs; ++c)
+        if (G[c][c].hi > bv) { bv = G[c][c].hi; best = c; }
+      s_piv = (bv > tau2 && j < room) ? best : -1;
+    }
+    __syncthreads();
+    const int pv = s_piv;
+    if (pv < 0) break;
+    // symmetric swap of j and pv in G (rows and columns), and in R's
+    // already computed rows
+    if (pv != j) {
+      for (int c = tid; c < bs; c += blockDim.x) {
+        const dd t = G[j][c]; G[j][c] = G[pv][c]; G[pv][c] = t;
+      }
+      __syncthreads();
+      for (int c = tid; c < bs; c += blockDim.x) {
+        const dd t = G[c][j]; G[c][j] = G[c][pv]; G[c][pv] = t;
+      }
+      for (int r = tid; r < j; r += blockDim.x) {
+        const dd t = R[r][j]; R[r][j] = R[r][pv]; R[r][pv] = t;
+      }
+      if (tid == 0) { const int t = perm[j]; perm[j] = perm[pv]; perm[pv] = t; }
+      __syncthreads();
+    }
+    if (tid == 0) R[j][j] = dd_sqrt(G[j][j]);
+    __syncthreads();
+    for (int c = j + 1 + tid; c < bs; c += blockDim.x) R[j][c] = dd_div(G[j][c], R[j][j]);
+    __syncthreads();
+    for (int e = tid; e < bs * bs; e += blockDim.x) {
+      const int a = e % bs, b = e / bs;
+      if (a > j && b > j) G[a][b] = dd_sub(G[a][b], dd_mul(R[j][a], R[j][b]));
+    }
+    if (tid == 0) s_p = j + 1;
+    __syncthreads();
+  }
+  const int p = s_p;
+  // R^{-1} (upper): column c solves R x = e_c by back substitution
+  for (int c = tid; c < p; c += blockDim.x) {
+    for (int r = c; r >= 0; --r) {
+      dd v = (r == c) ? dd{1.0, 0.0} : dd{0.0, 0.0};
+      for (int t = r + 1; t <= c; ++t) v = dd_sub(v, dd_mul(R[r][t], Ri[t][c]));
+      Ri[r][c] = dd_div(v, R[r][r]);
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < bs * bs; e += blockDim.x) {
+    const int r = e % bs, c = e / bs;
+    d.rfac[r + c * bs] = (r < p && c < p) ? Ri[r][c].hi + Ri[r][c].lo : 0.0;
+  }
+  if (tid < bs) d.piv[tid] = perm[tid];
+  if (tid == 0) {
+    d.piv[bs] = p;
+    *d.q = qold + p;
+    const bool conv = (p <= bs - r_min) || (qold + p >= qcap);
+    *d.flag = conv ? 1 : 0;
+  }
+}
+
+// Unpivoted Cholesky of the Gram matrix of the new columns (pass 2); the
+// columns are already orthonormal to about u * cond, so the Gram is close to
+// the identity.  Writes R^{-1} to rfac.
+__global__ __launch_bounds__(64) void k_chol_small(const OrthDesc* __restrict__ descs, int bs,
+                                                   int nrb) {
+  __shared__ dd G[BS_MAX][BS_MAX + 1];
+  __shared__ dd Ri[BS_MAX][BS_MAX + 1];
+  const OrthDesc d = descs[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int p = d.piv[bs];
+  gram_sum(d, bs, p, nrb, G);
+  // in-place right-looking Cholesky: upper factor R in G's upper triangle
+  for (int j = 0; j < p; ++j) {
+    if (tid == 0) {
+      G[j][j] = dd_sqrt(G[j][j]);
+      if (G[j][j].hi == 0.0) G[j][j] = dd{1.0, 0.0};
+    }
+    __syncthreads();
+    for (int c = j + 1 + tid; c < p; c += blockDim.x) G[j][c] = dd_div(G[j][c], G[j][j]);
+    __syncthreads();
+    for (int e = tid; e < p * p; e += blockDim.x) {
+      const int a = e % p, b = e / p;
+      if (a > j && b >= a) G[a][b] = dd_sub(G[a][b], dd_mul(G[j][a], G[j][b]));
+    }
+    __syncthreads();
+  }
+  for (int c = tid; c < p; c += blockDim.x) {
+    for (int r = c; r >= 0; --r) {
+      dd v = (r == c) ? dd{1.0, 0.0} : dd{0.0, 0.0};
+      for (int t = r + 1; t <= c; ++t) v = dd_sub(v, dd_mul(G[r][t], Ri[t][c]));
+      Ri[r][c] = dd_div(v, G[r][r]);
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < bs * bs; e += blockDim.x) {
+    const int r = e % bs, c = e / bs;
+    d.rfac[r + c * bs] = (r < p && c < p && r <= c) ? Ri[r][c].hi + Ri[r][c].lo : 0.0;
+  }
+}
+
+// New basis columns = (selected sample columns) * R^{-1}.
+// pass 1: source Y with the pivot permutation, destination Q[:, qold:qold+p]
+// pass 2: in place on Q[:, qold:qold+p]
+constexpr int APPLY_ROWS = 256;
+
+__global__ __launch_bounds__(APPLY_ROWS) void k_apply_rinv(const OrthDesc* __restrict__ descs,
+                                                           int m, int bs, int pass) {
+  const OrthDesc d = descs[blockIdx.y];
+  const int r = blockIdx.x * APPLY_ROWS + threadIdx.x;
+  const int p = d.piv[bs];
+  if (r >= m || p == 0) return;
+  double* dst = d.Q + (size_t)d.qold * m;
+  double x[BS_MAX];
+#pragma unroll
+  for (int a = 0; a < BS_MAX; ++a) {
+    if (a < p) {
+      x[a] = (pass == 1) ? d.Y[r + (size_t)d.piv[a] * m] : dst[r + (size_t)a * m];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < BS_MAX; ++c) {
+    if (c < p) {
+      double v = 0.0;
+#pragma unroll
+      for (int a = 0; a < BS_MAX; ++a)
+        if (a <= c) v += x[a] * d.rfac[a + c * bs];
+      dst[r + (size_t)c * m] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------- dynamic batching
+// Stable compaction of the active list (slots whose flag is set leave) and
+// refill from the waiting list, keeping at most s_max tiles.  One workgroup.
+__global__ __launch_bounds__(256) void k_compact(int* act, int* counts, const int* flag,
+                                                 const int* waiting, int nwaiting, int s_max) {
+  __shared__ int keep_total;
+  __shared__ int scan[256];
+  const int tid = threadIdx.x;
+  const int n = counts[0];
+  if (tid == 0) keep_total = 0;
+  __syncthreads();
+  // in-place stable compaction, processed in chunks of 256 entries; writes
+  // never overtake reads because pos <= index
+  for (int base = 0; base < n; base += 256) {
+    const int i = base + tid;
+    int slot = -1, keep = 0;
+    if (i < n) {
+      slot = act[i];
+      keep = flag[slot] ? 0 : 1;
+    }
+    scan[tid] = keep;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int v = (tid >= off) ? scan[tid - off] : 0;
+      __syncthreads();
+      scan[tid] += v;
+      __syncthreads();
+    }
+    const int pos = keep_total + scan[tid] - keep;
+    const int chunk_keep = scan[255];
+    __syncthreads();
+    if (keep) act[pos] = slot;
+    __syncthreads();
+    if (tid == 0) keep_total += chunk_keep;
+    __syncthreads();
+  }
+  const int kept = keep_total;
+  const int cursor = counts[1];
+  const int take = max(0, min(min(n - kept, s_max - kept), nwaiting - cursor));
+  for (int j = tid; j < take; j += blockDim.x) act[kept + j] = waiting[cursor + j];
+  __syncthreads();
+  if (tid == 0) {
+    counts[0] = kept + take;
+    counts[1] = cursor + take;
+  }
+}
+
+// order[p] = rows sorted by (rank descending, row ascending): the position of
+// element i is the number of elements that precede it.
+__global__ void k_sort_ranks(const int* ranks, const int* rows, int n, int* order) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int ri = ranks[i], wi = rows[i];
+  int pos = 0;
+  for (int j = 0; j < n; ++j) {
+    const int rj = ranks[j], wj = rows[j];
+    pos += (rj > ri || (rj == ri && wj < wi)) ? 1 : 0;
+  }
+  order[pos] = wi;
+}
+
+}  // namespace
+
+hipError_t launch_randn(double* out, int rows, int cols, int ld, unsigned long long seed, unsigned k,
+                        unsigned t, unsigned stream, hipStream_t s) {
+  const long long pairs = ((long long)rows * cols + 1) / 2;
+  if (pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_randn, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, out, rows,
+                     cols, ld, (unsigned)(seed & 0xffffffffu), (unsigned)(seed >> 32), k, t,
+                     stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox_raw(unsigned* out, int n, unsigned long long seed, unsigned c1,
+                             unsigned c2, unsigned c3, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_philox_raw, dim3((n + 255) / 256), dim3(256), 0, s, out, n,
+                     (unsigned)(seed & 0xffffffffu), (unsigned)(seed >> 32), c1, c2, c3);
+  return hipGetLastError();
+}
+
+int gram_row_blocks(int m) { return (m + GRAM_ROWS - 1) / GRAM_ROWS; }
+
+hipError_t launch_gram_dd(const OrthDesc* d, int ntiles, int m, int bs, int pass, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (bs > BS_MAX) return hipErrorInvalidValue;
+  const int nrb = gram_row_blocks(m);
+  hipLaunchKernelGGL(k_gram_dd, dim3(nrb, ntiles), dim3(256), 0, s, d, m, bs, pass, nrb);
+  return hipGetLastError();
+}
+
+hipError_t launch_pivchol(const OrthDesc* d, int ntiles, int m, int bs, double tau2, int r_min,
+                          int qcap, hipStream_t s) {
+  if (bs > BS_MAX) return hipErrorInvalidValue;
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pivchol, dim3(ntiles), dim3(64), 0, s, d, bs, gram_row_blocks(m), tau2,
+                     r_min, qcap);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_small(const OrthDesc* d, int ntiles, int m, int bs, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_chol_small, dim3(ntiles), dim3(64), 0, s, d, bs, gram_row_blocks(m));
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_rinv(const OrthDesc* d, int ntiles, int m, int bs, int pass,
+                             hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_apply_rinv, dim3((m + APPLY_ROWS - 1) / APPLY_ROWS, ntiles),
+                     dim3(APPLY_ROWS), 0, s, d, m, bs, pass);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(int* act, int* counts, const int* flag, const int* waiting, int nwaiting,
+                          int s_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(256), 0, s, act, counts, flag, waiting, nwaiting,
+                     s_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_ranks(const int* ranks, const int* rows, int n, int* order, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sort_ranks, dim3((n + 255) / 256), dim3(256), 0, s, ranks, rows, n, order);
+  return hipGetLastError();
+}
+
+}  // namespace tlr

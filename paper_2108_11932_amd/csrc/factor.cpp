@@ -1,0 +1,411 @@
+// Left-looking TLR Cholesky and LDL^T (Algorithms "Left Looking TLR
+// Cholesky" and "Left Looking TLR LDL^T" of the paper).
+//
+// Storage of the factor: block row i of L keeps its low rank factors as two
+// m x R_i column-major panels [U_i0 | U_i1 | ...] and [V_i0 | V_i1 | ...]
+// that grow by one column block per factorization step (the row-panel
+// storage the paper proposes in its conclusions).  With it, the sum over
+// j < k of Eq. (1) becomes one long contraction per tile instead of k small
+// products and a reduction over parallel buffers.
+//
+// Sampling of the Schur-complement tile S_ik = A_ik - sum_j L_ij L_kj^T
+// (Eq. (2), reassociated, exact algebra):
+//   G_ij  = V_ij^T V_kj                      once per column (Eq. (3): V_ij^T D_j V_kj)
+//   P     = U_k*^T Omega                     once per ARA iteration (Omega shared)
+//   Y_i   = U^A_ik (V^A_ik^T Omega) - U_i* [G_ij P_j]_j
+// Projection B_i = S_ik^T Q_i:
+//   B_i   = V^A_ik (U^A_ik^T Q_i) - U_k* [G_ij^T (U_ij^T Q_i)]_j
+// where the last product is a single m x R_k x (sum_i q_i) GEMM for the whole
+// column.
+#include <algorithm>
+#include <cmath>
+
+#include "ara_engine.h"
+
+namespace tlr {
+
+void free_factor(Handle* h) {
+  for (double* p : h->UL) h->mem.put(p);
+  for (double* p : h->VL) h->mem.put(p);
+  h->UL.assign(h->nb, nullptr);
+  h->VL.assign(h->nb, nullptr);
+  h->R.assign(h->nb, 0);
+  h->cap.assign(h->nb, 0);
+  h->l_rank.assign((size_t)h->nb * h->nb, 0);
+  h->l_off.assign((size_t)h->nb * h->nb, -1);
+  h->factored = 0;
+}
+
+// Make room for `extra` more columns in block row i's panels.
+static tlr_status grow_row(Handle* h, int i, int extra) {
+  const int need = h->R[i] + extra;
+  if (need <= h->cap[i]) return TLR_OK;
+  int nc = std::max(need, h->cap[i] + h->cap[i] / 2 + 16);
+  nc = (nc + 15) & ~15;
+  void* u = nullptr;
+  void* v = nullptr;
+  TLR_TRY(h->mem.get(&u, sizeof(double) * (size_t)h->m * nc));
+  tlr_status st = h->mem.get(&v, sizeof(double) * (size_t)h->m * nc);
+  if (st != TLR_OK) {
+    h->mem.put(u);
+    return st;
+  }
+  if (h->R[i] > 0) {
+    const size_t bytes = sizeof(double) * (size_t)h->m * h->R[i];
+    TLR_HIP(hipMemcpyAsync(u, h->UL[i], bytes, hipMemcpyDeviceToDevice, h->stream));
+    TLR_HIP(hipMemcpyAsync(v, h->VL[i], bytes, hipMemcpyDeviceToDevice, h->stream));
+  }
+  TLR_TRY(h->sync());
+  h->mem.put(h->UL[i]);
+  h->mem.put(h->VL[i]);
+  h->UL[i] = (double*)u;
+  h->VL[i] = (double*)v;
+  h->cap[i] = nc;
+  return TLR_OK;
+}
+
+tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bool ldl) {
+  const int m = h->m, nb = h->nb, bs = o.bs;
+  free_factor(h);
+  if (!h->Ld) {
+    void* p = nullptr;
+    TLR_TRY(h->mem.get(&p, sizeof(double) * (size_t)nb * m * m));
+    h->Ld = (double*)p;
+  }
+  if (ldl && !h->Dv) {
+    void* p = nullptr;
+    TLR_TRY(h->mem.get(&p, sizeof(double) * (size_t)nb * m));
+    h->Dv = (double*)p;
+  }
+  double tau = eps;
+  if (o.eps_mode == TLR_EPS_REL) {
+    if (h->norm_a <= 0.0) TLR_TRY(estimate_norm(h, &h->norm_a));
+    tau = eps * h->norm_a;
+  }
+  const double shift = o.shift < 0.0 ? tau : o.shift;
+  TLR_HIP(hipMemsetAsync(h->d_info, 0, sizeof(int), h->stream));
+
+  // initial panel capacities from the input ranks (a large rank in A tends to
+  // stay large in L, Section 4.2)
+  for (int i = 1; i < nb; ++i) {
+    long long s = 0;
+    for (int j = 0; j < i; ++j) s += h->ar(i, j);
+    long long c = (long long)(1.25 * s) + 32;
+    c = std::min(c, (long long)i * m);
+    TLR_TRY(grow_row(h, i, (int)c));
+  }
+
+  Work& w = h->ws;
+  double flops = 0.0, flops_paper = 0.0, bytes_alg = 0.0;
+  long long ara_iters = 0, tile_iters = 0;
+  AraConfig cfg;
+  cfg.m = m;
+  cfg.bs = bs;
+  cfg.qcap = m;
+  cfg.tau = tau;
+  cfg.r_min = o.r_min;
+  cfg.s_max = o.max_active;
+  cfg.seed = o.seed;
+  AraSlots slots;
+  TLR_TRY(ara_slots(h, cfg, std::max(1, nb - 1), &slots));
+
+  const bool timing = (o.flags & TLR_FLAG_KERNEL_TIMING) != 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  double samp_bytes = 0.0, samp_flops = 0.0;
+  std::vector<long long> goff((size_t)nb * nb, -1);
+  for (int k = 0; k < nb; ++k) {
+    const int Rk = h->R[k];
+    // ---------------------------------------------- G_ij = V_ij^T (D_j) V_kj
+    const double* Vk = h->VL[k];
+    if (ldl && Rk > 0) {
+      TLR_TRY(w.W.ensure(h->mem, sizeof(double) * (size_t)m * Rk));
+      for (int j = 0; j < k; ++j) {
+        const int r = h->lr(k, j);
+        if (r == 0) continue;
+        TLR_HIP(launch_scale_rows(h->vl(k, j), m, w.W.as<double>() + h->lo(k, j) * m, m,
+                                  h->Dv + (size_t)j * m, m, r, false, h->stream));
+      }
+      Vk = w.W.as<double>();
+    }
+    long long gtot = 0;
+    for (int i = k; i < nb; ++i)
+      for (int j = 0; j < k; ++j) {
+        const int a = h->lr(i, j), b = h->lr(k, j);
+        goff[(size_t)i * nb + j] = (a > 0 && b > 0) ? gtot : -1;
+        if (a > 0 && b > 0) gtot += (long long)a * b;
+      }
+    TLR_TRY(w.G.ensure(h->mem, sizeof(double) * (size_t)std::max(gtot, 1LL)));
+    double* G = w.G.as<double>();
+    {
+      GemmBatch g(true, false);
+      for (int i = k; i < nb; ++i)
+        for (int j = 0; j < k; ++j) {
+          const long long go = goff[(size_t)i * nb + j];
+          if (go < 0) continue;
+          const int a = h->lr(i, j), b = h->lr(k, j);
+          g.add(a, b, m, h->vl(i, j), m, Vk + h->lo(k, j) * m, m, G + go, a, 1.0, 0.0);
+        }
+      TLR_TRY(g.run(h));
+      flops += g.flops;
+    }
+    auto gptr = [&](int i, int j) -> const double* {
+      const long long go = goff[(size_t)i * nb + j];
+      return go >= 0 ? G + go : G;
+    };
+
+    // ---------------------------------------------- updateDense + chol / ldl
+    double* Lkk = h->diagL(k);
+    TLR_HIP(launch_copy_shift(h->diagA(k), Lkk, m, h->nreal(k), shift, h->stream));
+    if (Rk > 0) {
+      TLR_TRY(w.H.ensure(h->mem, sizeof(double) * (size_t)m * Rk));
+      double* Wd = w.H.as<double>();
+      GemmBatch wb(false, false);
+      for (int j = 0; j < k; ++j) {
+        const int r = h->lr(k, j);
+        if (r == 0) continue;
+        wb.add(m, r, r, h->ul(k, j), m, gptr(k, j), r, Wd + h->lo(k, j) * m, m, 1.0, 0.0);
+      }
+      TLR_TRY(wb.run(h));
+      GemmBatch up(false, true);
+      up.add(m, m, Rk, Wd, m, h->UL[k], m, Lkk, m, -1.0, 1.0);
+      TLR_TRY(up.run(h));
+      flops += wb.flops + up.flops;
+    }
+    flops_paper += 2.0 * m * (double)m * Rk + (double)m * m * m / 3.0;
+    if (ldl) {
+      TLR_TRY(dense_ldlt(h, Lkk, m, m, h->Dv + (size_t)k * m, k * m));
+    } else {
+      TLR_TRY(dense_potrf(h, Lkk, m, m, k * m));
+    }
+    flops += (double)m * m * m / 3.0;
+
+    const int nrow = nb - k - 1;
+    if (nrow == 0) break;
+
+    // ---------------------------------------------- sortRanks (device)
+    std::vector<int> order(nrow);
+    {
+      std::vector<int> rk(nrow), rows(nrow);
+      for (int s = 0; s < nrow; ++s) {
+        rk[s] = h->ar(k + 1 + s, k);
+        rows[s] = s;
+      }
+      void* dr = nullptr;
+      void* dw = nullptr;
+      TLR_TRY(h->stage.upload(h, rk.data(), sizeof(int) * nrow, &dr));
+      TLR_TRY(h->stage.upload(h, rows.data(), sizeof(int) * nrow, &dw));
+      TLR_HIP(launch_sort_ranks((const int*)dr, (const int*)dw, nrow, slots.waiting, h->stream));
+      TLR_HIP(hipMemcpyAsync(order.data(), slots.waiting, sizeof(int) * nrow, hipMemcpyDeviceToHost,
+                             h->stream));
+      TLR_TRY(h->sync());
+    }
+
+    // ---------------------------------------------- cholARAUpdate
+    TLR_TRY(w.P.ensure(h->mem, sizeof(double) * (size_t)std::max(Rk, 1) * bs));
+    TLR_TRY(w.Wa.ensure(h->mem, sizeof(double) * (size_t)nrow * m * bs));
+    {
+      long long zt = 0;
+      for (int s = 0; s < nrow; ++s) zt += h->R[k + 1 + s];
+      TLR_TRY(w.Z.ensure(h->mem, sizeof(double) * (size_t)std::max(zt, 1LL) * bs));
+    }
+    double* P = w.P.as<double>();
+    double* Wa = w.Wa.as<double>();
+    double* Z = w.Z.as<double>();
+    SampleFn sample = [&](const std::vector<int>& act, const double* omega, double* f) -> tlr_status {
+      if (Rk > 0) {
+        GemmBatch pb(true, false);
+        pb.add(Rk, bs, m, h->UL[k], m, omega, m, P, Rk, 1.0, 0.0);
+        TLR_TRY(pb.run(h));
+        *f += pb.flops;
+      }
+      GemmBatch wa(true, false), zb(false, false), y1(false, false), y2(false, false);
+      long long zo = 0;
+      for (int sl : act) {
+        const int i = k + 1 + sl;
+        const int a = h->ar(i, k);
+        double* wa_s = Wa + (size_t)sl * m * bs;
+        if (a > 0) wa.add(a, bs, m, h->va(i, k), m, omega, m, wa_s, m, 1.0, 0.0);
+        y1.add(m, bs, a, h->ua(i, k), m, wa_s, m, slots.y(sl), m, 1.0, 0.0);
+        const int Ri = h->R[i];
+        if (Rk > 0 && Ri > 0) {
+          for (int j = 0; j < k; ++j) {
+            const int rij = h->lr(i, j);
+            if (rij == 0) continue;
+            zb.add(rij, bs, h->lr(k, j), gptr(i, j), rij, P + h->lo(k, j), Rk, Z + zo + h->lo(i, j),
+                   Ri, 1.0, 0.0);
+          }
+          y2.add(m, bs, Ri, h->UL[i], m, Z + zo, Ri, slots.y(sl), m, -1.0, 1.0);
+          zo += (long long)Ri * bs;
+        }
+      }
+      TLR_TRY(wa.run(h));
+      TLR_TRY(zb.run(h));
+      TLR_TRY(y1.run(h));
+      if (timing && !y2.d.empty()) {
+        hipEvent_t e0, e1;
+        TLR_HIP(hipEventCreate(&e0));
+        TLR_HIP(hipEventCreate(&e1));
+        TLR_HIP(hipEventRecord(e0, h->stream));
+        TLR_TRY(y2.run(h));
+        TLR_HIP(hipEventRecord(e1, h->stream));
+        events.push_back({e0, e1});
+        double b = 0.0;
+        for (const auto& g : y2.d)
+          b += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + 2.0 * g.M * g.N);
+        samp_bytes += b;
+        samp_flops += y2.flops;
+      } else {
+        TLR_TRY(y2.run(h));
+      }
+      *f += wa.flops + zb.flops + y1.flops + y2.flops;
+      return TLR_OK;
+    };
+    // slots hold rows k+1.. in natural order; `order` is the sorted order
+    AraResult res;
+    cfg.stream_id = (unsigned)k;
+    bool abort = false;
+    TLR_TRY(ara_run(h, cfg, slots, order, sample, &res, &abort));
+    if (abort) break;
+    flops += res.flops;
+    ara_iters += res.launches;
+
+    // ---------------------------------------------- projection  B_i = S_ik^T Q_i
+    const std::vector<int>& q = res.q;
+    std::vector<long long> boff(nrow), toff(nrow), taoff(nrow);
+    long long sq = 0, st_ = 0, sta = 0;
+    for (int s = 0; s < nrow; ++s) {
+      const int i = k + 1 + s;
+      boff[s] = sq;
+      toff[s] = st_;
+      taoff[s] = sta;
+      sq += q[s];
+      st_ += (long long)h->R[i] * q[s];
+      sta += (long long)h->ar(i, k) * q[s];
+    }
+    TLR_TRY(w.T.ensure(h->mem, sizeof(double) * (size_t)std::max(st_, 1LL)));
+    TLR_TRY(w.Ta.ensure(h->mem, sizeof(double) * (size_t)std::max(sta, 1LL)));
+    TLR_TRY(w.H.ensure(h->mem, sizeof(double) * (size_t)std::max((long long)Rk * sq, 1LL)));
+    TLR_TRY(w.Ball.ensure(h->mem, sizeof(double) * (size_t)std::max((long long)m * sq, 1LL)));
+    double* T = w.T.as<double>();
+    double* Ta = w.Ta.as<double>();
+    double* H = w.H.as<double>();
+    double* Ball = w.Ball.as<double>();
+    {
+      GemmBatch t1(true, false), t2(true, false), hb(true, false), b1(false, false), b2(false, false);
+      for (int s = 0; s < nrow; ++s) {
+        const int i = k + 1 + s, qs = q[s];
+        if (qs == 0) continue;
+        const int a = h->ar(i, k), Ri = h->R[i];
+        const double* Qs = slots.q(s);
+        if (Ri > 0) t1.add(Ri, qs, m, h->UL[i], m, Qs, m, T + toff[s], Ri, 1.0, 0.0);
+        if (a > 0) t2.add(a, qs, m, h->ua(i, k), m, Qs, m, Ta + taoff[s], a, 1.0, 0.0);
+        if (Rk > 0) {
+          for (int j = 0; j < k; ++j) {
+            const int rkj = h->lr(k, j);
+            if (rkj == 0) continue;
+            const int rij = h->lr(i, j);
+            hb.add(rkj, qs, rij, gptr(i, j), rij, T + toff[s] + (rij > 0 ? h->lo(i, j) : 0),
+                   std::max(Ri, 1), H + boff[s] * Rk + h->lo(k, j), Rk, 1.0, 0.0);
+          }
+        }
+        b1.add(m, qs, a, h->va(i, k), m, Ta + taoff[s], std::max(a, 1), Ball + boff[s] * m, m, 1.0,
+               0.0);
+      }
+      if (Rk > 0 && sq > 0) b2.add(m, (int)sq, Rk, h->UL[k], m, H, Rk, Ball, m, -1.0, 1.0);
+      TLR_TRY(t1.run(h));
+      TLR_TRY(t2.run(h));
+      TLR_TRY(hb.run(h));
+      TLR_TRY(b1.run(h));
+      TLR_TRY(b2.run(h));
+      flops += t1.flops + t2.flops + hb.flops + b1.flops + b2.flops;
+    }
+    // ---------------------------------------------- batchTrsm (+ batchIDMult)
+    TLR_TRY(dense_trsm(h, Lkk, m, Ball, m, m, (int)sq, ldl, false));
+    flops += (double)m * m * sq;
+    if (ldl && sq > 0)
+      TLR_HIP(launch_scale_rows(Ball, m, Ball, m, h->Dv + (size_t)k * m, m, (int)sq, true, h->stream));
+
+    // ---------------------------------------------- updateTiles
+    for (int s = 0; s < nrow; ++s)
+      if (q[s] > 0) TLR_TRY(grow_row(h, k + 1 + s, q[s]));
+    {
+      std::vector<CopyDesc> cd;
+      int maxc = 0;
+      for (int s = 0; s < nrow; ++s) {
+        const int i = k + 1 + s, qs = q[s];
+        if (qs == 0) continue;
+        cd.push_back(CopyDesc{slots.q(s), h->UL[i] + (size_t)h->R[i] * m, m, qs, m, m});
+        cd.push_back(CopyDesc{Ball + boff[s] * m, h->VL[i] + (size_t)h->R[i] * m, m, qs, m, m});
+        maxc = std::max(maxc, qs);
+      }
+      if (!cd.empty()) {
+        void* dcd = nullptr;
+        TLR_TRY(h->stage.upload(h, cd.data(), sizeof(CopyDesc) * cd.size(), &dcd));
+        TLR_HIP(launch_copy_batched((const CopyDesc*)dcd, (int)cd.size(), maxc, h->stream));
+      }
+    }
+    for (int s = 0; s < nrow; ++s) {
+      const int i = k + 1 + s;
+      h->l_rank[(size_t)i * nb + k] = q[s];
+      h->l_off[(size_t)i * nb + k] = h->R[i];
+      h->R[i] += q[s];
+      // operation count of the paper's formulation (four-product sampling of
+      // Eq. (2) per iteration, the same for the projection, orthogonalisation,
+      // triangular solve)
+      const double ext = (double)h->R[i] - q[s] + Rk + h->ar(i, k);
+      flops_paper += res.iters[s] * 4.0 * m * bs * ext + 4.0 * m * q[s] * ext +
+                     res.flops_paper_orth[s] + (double)m * m * q[s];
+      bytes_alg += res.iters[s] * 8.0 * m * ((double)h->R[i] - q[s] + h->ar(i, k));
+      tile_iters += res.iters[s];
+    }
+  }
+  TLR_TRY(h->sync());
+  double samp_ms = 0.0;
+  for (auto& ev : events) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) samp_ms += ms;
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  int info = 0;
+  TLR_HIP(hipMemcpy(&info, h->d_info, sizeof(int), hipMemcpyDeviceToHost));
+  if (st) {
+    std::memset(st, 0, sizeof *st);
+    st->info = info;
+    st->tau = tau;
+    st->norm_a = o.eps_mode == TLR_EPS_REL ? h->norm_a : 0.0;
+    st->flops = flops;
+    st->flops_paper = flops_paper;
+    st->bytes_alg = bytes_alg;
+    st->ara_iters = ara_iters;
+    st->tile_iters = tile_iters;
+    long long cnt = 0, tot = 0, full = 0;
+    int mx = 0;
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < i; ++j) {
+        const int r = h->lr(i, j);
+        tot += r;
+        ++cnt;
+        mx = std::max(mx, r);
+        if (r >= m) ++full;
+      }
+    st->max_rank = mx;
+    st->mean_rank = cnt ? (double)tot / cnt : 0.0;
+    st->full_rank_tiles = full;
+    st->factor_bytes = 8.0 * ((double)nb * m * m + 2.0 * m * (double)tot);
+    st->sample_launches = (long long)events.size();
+    st->sample_ms = samp_ms;
+    st->sample_bytes = samp_bytes;
+    st->sample_flops = samp_flops;
+  }
+  if (info != 0) {
+    h->factored = 0;
+    set_error("diagonal tile %d lost %s at global row %d", (info - 1) / m,
+              ldl ? "a nonzero pivot" : "positive definiteness", info);
+    return ldl ? TLR_ERR_ZERO_PIVOT : TLR_ERR_NOT_SPD;
+  }
+  h->factored = ldl ? 2 : 1;
+  return TLR_OK;
+}
+
+}  // namespace tlr

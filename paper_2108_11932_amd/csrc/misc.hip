@@ -1,0 +1,154 @@
+// Data-movement and elementwise kernels of the TLR library: batched panel
+// copies ("updateTiles": appending the new column of low rank factors to the
+// block-row panels), the diagonal tile set-up with the optional shift
+// (Section 5.1), row scaling by a diagonal (the D factors of LDL^T,
+// Section 5.3), zeroing of a strict triangle, and the covariance tile
+// generator of the Section 6 test matrices.
+#include "tlr_internal.h"
+
+namespace tlr {
+
+namespace {
+
+// One workgroup per (descriptor, 8-column slab); each thread copies rows.
+__global__ __launch_bounds__(256) void k_copy_batched(const CopyDesc* __restrict__ descs) {
+  const CopyDesc d = descs[blockIdx.y];
+  const int c0 = blockIdx.x * 8;
+  if (c0 >= d.cols) return;
+  const int c1 = min(d.cols, c0 + 8);
+  for (int c = c0; c < c1; ++c)
+    for (int r = threadIdx.x; r < d.rows; r += blockDim.x)
+      d.dst[r + (size_t)c * d.ldd] = d.src[r + (size_t)c * d.lds];
+}
+
+__global__ void k_copy_shift(const double* src, double* dst, int m, int nreal, double shift) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= (long long)m * m) return;
+  const int r = (int)(e % m), c = (int)(e / m);
+  double v = src[e];
+  if (r == c && r < nreal) v += shift;
+  dst[e] = v;
+}
+
+__global__ void k_scale_rows(const double* in, int ldi, double* out, int ldo, const double* dg,
+                             int rows, int cols, int inverse) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= (long long)rows * cols) return;
+  const int r = (int)(e % rows), c = (int)(e / rows);
+  const double v = in[r + (size_t)c * ldi];
+  out[r + (size_t)c * ldo] = inverse ? v / dg[r] : v * dg[r];
+}
+
+__global__ void k_zero_upper(double* A, int lda, int m) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= (long long)m * m) return;
+  const int r = (int)(e % m), c = (int)(e / m);
+  if (c > r) A[r + (size_t)c * lda] = 0.0;
+}
+
+// 64 * u * ||A||_F (the LDL^T zero-pivot tolerance) for an m x m tile.
+__global__ __launch_bounds__(256) void k_pivot_tol(const double* A, int lda, int m, double* tol) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (long long e = threadIdx.x; e < (long long)m * m; e += blockDim.x) {
+    const double v = A[(e % m) + (e / m) * (size_t)lda];
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *tol = 64.0 * 1.1102230246251565e-16 * sqrt(red[0]);
+}
+
+// Covariance tiles: out(r, c) = k(|x_{r0+r} - x_{c0+c}|) (+ diag_add on the
+// global diagonal); identity where the row or column lies in the padding.
+__global__ __launch_bounds__(256) void k_gen_tiles(const GenDesc* __restrict__ descs,
+                                                   const double* __restrict__ pts, int dim,
+                                                   long long n, int m, int kernel, double ell,
+                                                   double diag_add, const double* __restrict__ src,
+                                                   long long lds) {
+  const GenDesc d = descs[blockIdx.y];
+  const int c = blockIdx.x;          // one column per workgroup x
+  const long long gc = d.c0 + c;
+  double xc[3] = {0.0, 0.0, 0.0};
+  if (gc < n && kernel >= 0)
+    for (int t = 0; t < dim; ++t) xc[t] = pts[gc * dim + t];
+  const double inv_ell = 1.0 / ell;
+  const double s3 = 1.7320508075688772935274463415059;
+  for (int r = threadIdx.x; r < m; r += blockDim.x) {
+    const long long gr = d.r0 + r;
+    double v;
+    if (gr >= n || gc >= n) {
+      v = (gr == gc) ? 1.0 : 0.0;
+    } else if (kernel < 0) {
+      // lower triangle of the dense input, mirrored above the diagonal
+      v = (gr >= gc) ? src[gr + gc * lds] : src[gc + gr * lds];
+    } else {
+      double s = 0.0;
+      for (int t = 0; t < dim; ++t) {
+        const double df = pts[gr * dim + t] - xc[t];
+        s += df * df;
+      }
+      const double dist = sqrt(s);
+      if (kernel == 0) {
+        v = exp(-dist * inv_ell);
+      } else {
+        const double q = s3 * dist * inv_ell;
+        v = (1.0 + q) * exp(-q);
+      }
+      if (gr == gc) v += diag_add;
+    }
+    d.out[r + (size_t)c * d.ld] = v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_copy_batched(const CopyDesc* d, int n, int max_cols, hipStream_t s) {
+  if (n <= 0 || max_cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_batched, dim3((max_cols + 7) / 8, n), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_shift(const double* src, double* dst, int m, int nreal, double shift,
+                             hipStream_t s) {
+  const long long n = (long long)m * m;
+  hipLaunchKernelGGL(k_copy_shift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, m,
+                     nreal, shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_rows(const double* in, int ldi, double* out, int ldo, const double* dg,
+                             int rows, int cols, bool inverse, hipStream_t s) {
+  const long long n = (long long)rows * cols;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, ldi, out,
+                     ldo, dg, rows, cols, inverse ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_upper(double* A, int lda, int m, hipStream_t s) {
+  const long long n = (long long)m * m;
+  hipLaunchKernelGGL(k_zero_upper, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, lda, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_pivot_tol(const double* A, int lda, int m, double* tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_pivot_tol, dim3(1), dim3(256), 0, s, A, lda, m, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_gen_tiles(const GenDesc* d, int ntiles, const double* pts, int dim, long long n,
+                            int m, int kernel, double ell, double diag_add, const double* src,
+                            long long lds, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (kernel >= 0 && (dim < 1 || dim > 3)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gen_tiles, dim3(m, ntiles), dim3(256), 0, s, d, pts, dim, n, m, kernel, ell,
+                     diag_add, src, lds);
+  return hipGetLastError();
+}
+
+}  // namespace tlr

@@ -1,0 +1,199 @@
+// Products and solves with TLR matrices (Section 4.4): the TLR matrix-vector
+// product of the input matrix, the 2-norm estimate it serves, and the
+// triangular solves with the factor (Algorithm "TLR Triangular Solve" and
+// its transpose).
+#include <algorithm>
+#include <cmath>
+
+#include "host.h"
+
+namespace tlr {
+
+// Copy N x nrhs (ld) into the padded nb*m x nrhs work vector (zero padding),
+// or back.
+static tlr_status pad_in(Handle* h, const double* X, long long ldx, int nrhs, double* Xp) {
+  const long long np = (long long)h->nb * h->m;
+  TLR_HIP(hipMemsetAsync(Xp, 0, sizeof(double) * np * nrhs, h->stream));
+  CopyDesc cd{X, Xp, (int)h->N, nrhs, (int)ldx, (int)np};
+  void* d = nullptr;
+  TLR_TRY(h->stage.upload(h, &cd, sizeof cd, &d));
+  TLR_HIP(launch_copy_batched((const CopyDesc*)d, 1, nrhs, h->stream));
+  return TLR_OK;
+}
+
+static tlr_status pad_out(Handle* h, const double* Xp, int nrhs, double* Y, long long ldy) {
+  const long long np = (long long)h->nb * h->m;
+  CopyDesc cd{Xp, Y, (int)h->N, nrhs, (int)np, (int)ldy};
+  void* d = nullptr;
+  TLR_TRY(h->stage.upload(h, &cd, sizeof cd, &d));
+  TLR_HIP(launch_copy_batched((const CopyDesc*)d, 1, nrhs, h->stream));
+  return TLR_OK;
+}
+
+tlr_status matvec(Handle* h, int nrhs, const double* X, long long ldx, double* Y, long long ldy) {
+  const int m = h->m, nb = h->nb;
+  const long long np = (long long)nb * m;
+  Work& w = h->ws;
+  TLR_TRY(w.omega.ensure(h->mem, sizeof(double) * np * nrhs * 2));
+  TLR_TRY(w.T.ensure(h->mem, sizeof(double) * (size_t)std::max(h->a_cols, 1LL) * nrhs * 2));
+  double* Xp = w.omega.as<double>();
+  double* Yp = Xp + np * nrhs;
+  double* Tl = w.T.as<double>();
+  double* Tu = Tl + (size_t)std::max(h->a_cols, 1LL) * nrhs;
+  const int ldt = (int)std::max(h->a_cols, 1LL);
+  TLR_TRY(pad_in(h, X, ldx, nrhs, Xp));
+  {
+    GemmBatch dg(false, false);
+    for (int i = 0; i < nb; ++i)
+      dg.add(m, nrhs, m, h->diagA(i), m, Xp + (size_t)i * m, (int)np, Yp + (size_t)i * m, (int)np,
+             1.0, 0.0);
+    TLR_TRY(dg.run(h));
+  }
+  if (h->a_cols > 0) {
+    GemmBatch tl(true, false), tu(true, false);
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < i; ++j) {
+        const int a = h->ar(i, j);
+        if (a == 0) continue;
+        const long long off = h->a_off[(size_t)i * nb + j];
+        tl.add(a, nrhs, m, h->va(i, j), m, Xp + (size_t)j * m, (int)np, Tl + off, ldt, 1.0, 0.0);
+        tu.add(a, nrhs, m, h->ua(i, j), m, Xp + (size_t)i * m, (int)np, Tu + off, ldt, 1.0, 0.0);
+      }
+    TLR_TRY(tl.run(h));
+    TLR_TRY(tu.run(h));
+    // lower part: row i's tiles are adjacent in the arena -> one product per row
+    GemmBatch lo(false, false);
+    for (int i = 1; i < nb; ++i) {
+      long long K = 0;
+      for (int j = 0; j < i; ++j) K += h->ar(i, j);
+      if (K == 0) continue;
+      const long long off = h->a_off[(size_t)i * nb + 0];
+      lo.add(m, nrhs, (int)K, h->UA + (size_t)off * m, m, Tl + off, ldt, Yp + (size_t)i * m, (int)np,
+             1.0, 1.0);
+    }
+    TLR_TRY(lo.run(h));
+    // upper part: tiles (j + d, j) of one sub-diagonal d update distinct rows
+    for (int d = 1; d < nb; ++d) {
+      GemmBatch up(false, false);
+      for (int j = 0; j + d < nb; ++j) {
+        const int i = j + d, a = h->ar(i, j);
+        if (a == 0) continue;
+        const long long off = h->a_off[(size_t)i * nb + j];
+        up.add(m, nrhs, a, h->va(i, j), m, Tu + off, ldt, Yp + (size_t)j * m, (int)np, 1.0, 1.0);
+      }
+      TLR_TRY(up.run(h));
+    }
+  }
+  TLR_TRY(pad_out(h, Yp, nrhs, Y, ldy));
+  return TLR_OK;
+}
+
+tlr_status estimate_norm(Handle* h, double* out) {
+  const long long n = h->N;
+  void* xv = nullptr;
+  TLR_TRY(h->mem.get(&xv, sizeof(double) * n * 2));
+  double* x = (double*)xv;
+  double* y = x + n;
+  std::vector<double> hv(n);
+  tlr_status st = TLR_OK;
+  double lam = 0.0;
+  if (launch_randn(x, (int)n, 1, (int)n, 0x4e6f726dULL, 0, 0, 0, h->stream) != hipSuccess) {
+    set_error("norm estimate: randn launch failed");
+    st = TLR_ERR_DEVICE;
+  }
+  for (int it = 0; it < 20 && st == TLR_OK; ++it) {
+    st = matvec(h, 1, x, n, y, n);
+    if (st != TLR_OK) break;
+    if (hipMemcpyAsync(hv.data(), y, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream) !=
+        hipSuccess) {
+      st = TLR_ERR_DEVICE;
+      break;
+    }
+    st = h->sync();
+    if (st != TLR_OK) break;
+    double s = 0.0;
+    for (double v : hv) s += v * v;
+    s = std::sqrt(s);
+    if (it == 0) {
+      // first pass normalises the random start vector's image
+      double xs = 0.0;
+      std::vector<double> hx(n);
+      (void)hipMemcpy(hx.data(), x, sizeof(double) * n, hipMemcpyDeviceToHost);
+      for (double v : hx) xs += v * v;
+      lam = s / std::sqrt(xs);
+    } else {
+      lam = s;
+    }
+    if (s == 0.0) break;
+    for (double& v : hv) v /= s;
+    if (hipMemcpyAsync(x, hv.data(), sizeof(double) * n, hipMemcpyHostToDevice, h->stream) !=
+        hipSuccess) {
+      st = TLR_ERR_DEVICE;
+      break;
+    }
+    st = h->sync();
+  }
+  h->mem.put(xv);
+  *out = lam;
+  return st;
+}
+
+tlr_status solve(Handle* h, int nrhs, double* B, long long ldb) {
+  const int m = h->m, nb = h->nb;
+  const long long np = (long long)nb * m;
+  const bool ldl = h->factored == 2;
+  Work& w = h->ws;
+  long long rmax = 0;
+  for (int k = 0; k < nb; ++k) rmax = std::max<long long>(rmax, h->R[k]);
+  long long tcap = 0;
+  for (int k = 0; k < nb; ++k) {
+    long long s = 0;
+    for (int i = k + 1; i < nb; ++i) s += h->lr(i, k);
+    tcap = std::max(tcap, s);
+  }
+  tcap = std::max(tcap, rmax);
+  TLR_TRY(w.omega.ensure(h->mem, sizeof(double) * np * nrhs));
+  TLR_TRY(w.T.ensure(h->mem, sizeof(double) * (size_t)std::max(tcap, 1LL) * nrhs));
+  double* Xp = w.omega.as<double>();
+  double* T = w.T.as<double>();
+  const int ldx = (int)np;
+  TLR_TRY(pad_in(h, B, ldb, nrhs, Xp));
+  // forward sweep: x_k = L_kk^{-1} x_k, then x_i -= U_ik (V_ik^T x_k) for i > k
+  for (int k = 0; k < nb; ++k) {
+    double* xk = Xp + (size_t)k * m;
+    TLR_TRY(dense_trsm(h, h->diagL(k), m, xk, ldx, m, nrhs, ldl, false));
+    GemmBatch t(true, false), u(false, false);
+    long long off = 0;
+    for (int i = k + 1; i < nb; ++i) {
+      const int r = h->lr(i, k);
+      if (r == 0) continue;
+      t.add(r, nrhs, m, h->vl(i, k), m, xk, ldx, T + off, (int)tcap, 1.0, 0.0);
+      u.add(m, nrhs, r, h->ul(i, k), m, T + off, (int)tcap, Xp + (size_t)i * m, ldx, -1.0, 1.0);
+      off += r;
+    }
+    TLR_TRY(t.run(h));
+    TLR_TRY(u.run(h));
+  }
+  if (ldl) TLR_HIP(launch_scale_rows(Xp, ldx, Xp, ldx, h->Dv, (int)np, nrhs, true, h->stream));
+  // backward sweep with L^T: x_k = L_kk^{-T} x_k, then x_j -= V_kj (U_kj^T x_k)
+  for (int k = nb - 1; k >= 0; --k) {
+    double* xk = Xp + (size_t)k * m;
+    TLR_TRY(dense_trsm(h, h->diagL(k), m, xk, ldx, m, nrhs, ldl, true));
+    const int Rk = h->R[k];
+    if (Rk == 0) continue;
+    GemmBatch t(true, false), v(false, false);
+    t.add(Rk, nrhs, m, h->UL[k], m, xk, ldx, T, (int)tcap, 1.0, 0.0);
+    for (int j = 0; j < k; ++j) {
+      const int r = h->lr(k, j);
+      if (r == 0) continue;
+      v.add(m, nrhs, r, h->vl(k, j), m, T + h->lo(k, j), (int)tcap, Xp + (size_t)j * m, ldx, -1.0,
+            1.0);
+    }
+    TLR_TRY(t.run(h));
+    TLR_TRY(v.run(h));
+  }
+  TLR_TRY(pad_out(h, Xp, nrhs, B, ldb));
+  return h->sync();
+}
+
+}  // namespace tlr

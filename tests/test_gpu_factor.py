@@ -1,0 +1,232 @@
+"""End-to-end parity of the GPU TLR factorizations, solve and product with the
+FP64 oracle, through the C ABI.
+
+The ARA compression is randomized, so the factor is not unique: the tests
+compare what is unique (L L^T against A, the first diagonal tile, solves and
+products given a factor) and check the rest against the invariants the
+method fixes: per-tile backward error equal to the compression error
+(left-looking identity), the global error bound, Eckart-Young lower bounds
+and exact ranks on exactly low rank inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dense
+from oracle import tlr as otlr
+from paper_2108_11932_amd import tlr
+from paper_2108_11932_amd import workloads as wl
+
+from gpu_util import dev, host, oracle_tlr
+
+pytestmark = pytest.mark.gpu
+
+
+def _cov(n, seed, ell=0.1, nugget=1e-4, dim=2, kernel=dense.KERNEL_EXP):
+    if n & (n - 1) == 0:
+        pts = wl.jittered_grid(n, dim, seed)
+    else:
+        pts = wl.uniform_points(n, dim, seed)
+    pts = np.ascontiguousarray(pts[wl.morton_order(pts)])
+    return pts, dense.covariance_matrix(pts, kernel, ell, nugget)
+
+
+def _upload(t):
+    return tlr.TLRMatrix.from_tlr(t.n, t.m, t.diag, t.u, t.v)
+
+
+def _residual_tiles(a_tlr, l_tlr, d=None):
+    ad = a_tlr.dense_symmetric()
+    ld = l_tlr.dense_lower()
+    rec = ld @ (np.diag(np.concatenate(d)) if d is not None else np.eye(ld.shape[0])) @ ld.T
+    return ad - rec
+
+
+def test_single_tile_is_dense_cholesky():
+    _, a = _cov(200, 1)
+    t = otlr.compress_dense(a, 200, 1e-6)
+    mat = _upload(t)
+    mat.potrf(1e-6)
+    L = mat.diag(tlr.FACTOR, 0)
+    ref = np.linalg.cholesky(a)
+    np.testing.assert_allclose(L, ref, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,m,r", [(768, 128, 3), (1000, 128, 5)])
+def test_exactly_low_rank_recovered(n, m, r):
+    rng = np.random.default_rng(n + r)
+    a = np.zeros((n, n))
+    for k in range(0, n, m):
+        e = min(n, k + m)
+        g = rng.standard_normal((e - k, e - k))
+        a[k:e, k:e] = g @ g.T / (e - k) + np.eye(e - k)
+    w = rng.standard_normal((n, r))
+    a += w @ w.T
+    tau = 1e-8
+    t = otlr.compress_dense(a, m, tau)
+    mat = _upload(t)
+    st = mat.potrf(tau)
+    ranks = mat.ranks(tlr.FACTOR)
+    lower = ranks[np.tril_indices(t.nb, -1)]
+    assert set(lower.tolist()) == {r}
+    l = oracle_tlr(mat, tlr.FACTOR)
+    res = _residual_tiles(t, l)
+    assert np.abs(res).max() < 1e-10 * np.abs(a).max()
+    assert st["max_rank"] == r
+
+
+@pytest.mark.parametrize("n,m,eps", [(2048, 256, 1e-6), (1000, 128, 1e-6), (2048, 256, 1e-3)])
+def test_cholesky_matches_oracle_invariants(n, m, eps):
+    pts, a = _cov(n, 3)
+    t = otlr.compress_dense(a, m, eps)
+    mat = _upload(t)
+    st = mat.potrf(eps)
+    assert st["info"] == 0 and abs(st["tau"] - eps) == 0
+    l = oracle_tlr(mat, tlr.FACTOR)
+    ref = otlr.tlr_cholesky(t, eps)
+    # the first diagonal tile sees no update: LAPACK's factor
+    np.testing.assert_allclose(l.diag[0], ref.diag[0], rtol=0, atol=1e-12 * np.abs(ref.diag[0]).max())
+    # left-looking identity: every residual tile is a compression error
+    res = _residual_tiles(t, l)
+    scale = np.linalg.norm(a, 2)
+    for k in range(t.nb):
+        assert np.linalg.norm(res[t.blk(k), t.blk(k)], 2) < 1e-11 * scale
+        for i in range(k + 1, t.nb):
+            e = np.linalg.norm(res[t.blk(i), t.blk(k)], 2)
+            assert e <= 4 * eps, (i, k, e)
+    err = np.linalg.norm(res, 2)
+    assert err <= 2 * math.sqrt(t.nb) * eps
+    # ranks: never below the optimal rank at the achieved tile error, and
+    # within 10% (plus one block) of the oracle's optimal ranks in total
+    rg = mat.ranks(tlr.FACTOR)
+    ro = ref.ranks()
+    assert rg.sum() <= 1.10 * ro.sum() + t.nb
+    for k in range(t.nb):
+        for i in range(k + 1, t.nb):
+            s_ik = otlr.schur_tile(t, l, i, k)
+            sv = np.linalg.svd(s_ik, compute_uv=False)
+            e = np.linalg.norm(res[t.blk(i), t.blk(k)], 2)
+            assert rg[i, k] >= int(np.sum(sv > e * (1 + 1e-8) + 1e-14 * scale))
+
+
+def test_dynamic_batching_subset_gives_same_quality():
+    pts, a = _cov(2048, 5)
+    eps = 1e-6
+    t = otlr.compress_dense(a, 256, eps)
+    mat = _upload(t)
+    st = mat.potrf(eps, tlr.opts(max_active=2))
+    l = oracle_tlr(mat, tlr.FACTOR)
+    err = np.linalg.norm(_residual_tiles(t, l), 2)
+    assert err <= 2 * math.sqrt(t.nb) * eps
+    assert st["ara_iters"] >= t.nb - 1
+
+
+def test_solve_matches_oracle_on_gpu_factor():
+    pts, a = _cov(1000, 7)
+    eps = 1e-7
+    t = otlr.compress_dense(a, 128, eps)
+    mat = _upload(t)
+    mat.potrf(eps)
+    l = oracle_tlr(mat, tlr.FACTOR)
+    b = np.random.default_rng(4).standard_normal((1000, 3))
+    ref = otlr.solve(l, b)
+    import torch
+    got = mat.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+    res = np.linalg.norm(a @ got - b) / (np.linalg.norm(a, 2) * np.linalg.norm(got))
+    assert res < 1e-6
+
+
+def test_matvec_matches_oracle():
+    pts, a = _cov(1000, 8)
+    t = otlr.compress_dense(a, 128, 1e-8)
+    mat = _upload(t)
+    x = np.random.default_rng(2).standard_normal((1000, 2))
+    import torch
+    got = mat.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = otlr.matvec(t, x)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_ldlt_indefinite_inertia_and_residual():
+    n, m, r = 768, 128, 4
+    rng = np.random.default_rng(9)
+    a = np.zeros((n, n))
+    for k in range(0, n, m):
+        sgn = np.where(rng.random(m) < 0.3, -1.0, 1.0)
+        b = np.diag(sgn * rng.uniform(5, 6, m)) + 0.05 * rng.standard_normal((m, m))
+        a[k:k + m, k:k + m] = 0.5 * (b + b.T)
+    w = rng.standard_normal((n, r))
+    a += w @ w.T
+    tau = 1e-9
+    t = otlr.compress_dense(a, m, tau)
+    mat = _upload(t)
+    st, d = mat.ldlt(tau)
+    dd = d.cpu().numpy()
+    assert int(np.sum(dd < 0)) == int(np.sum(np.linalg.eigvalsh(a) < 0))
+    l = oracle_tlr(mat, tlr.FACTOR)
+    piv = mat.pivots()
+    res = _residual_tiles(t, l, [piv[k * m:(k + 1) * m] for k in range(t.nb)])
+    assert np.abs(res).max() < 1e-9 * np.abs(a).max()
+    # and the solve with L D L^T
+    import torch
+    bvec = rng.standard_normal(n)
+    x = mat.solve(torch.from_numpy(bvec).cuda()).cpu().numpy()
+    assert np.linalg.norm(a @ x - bvec) / np.linalg.norm(bvec) < 1e-7
+
+
+def test_ldlt_matches_cholesky_on_spd():
+    pts, a = _cov(1024, 11)
+    eps = 1e-6
+    t = otlr.compress_dense(a, 128, eps)
+    mat = _upload(t)
+    st, d = mat.ldlt(eps)
+    assert np.all(d.cpu().numpy() > 0)
+    l = oracle_tlr(mat, tlr.FACTOR)
+    piv = mat.pivots()
+    res = _residual_tiles(t, l, [piv[k * 128:(k + 1) * 128] for k in range(t.nb)])
+    assert np.linalg.norm(res, 2) <= 2 * math.sqrt(t.nb) * eps
+
+
+def test_not_spd_reports_row():
+    pts, a = _cov(512, 2)
+    a[300, 300] = -4.0
+    t = otlr.compress_dense(a, 128, 1e-8)
+    mat = _upload(t)
+    status, st = mat.potrf_status(1e-8)
+    assert status == tlr.TLR_ERR_NOT_SPD
+    assert (st["info"] - 1) // 128 == 2
+
+
+def test_compress_kernel_matches_oracle_tiles():
+    n, m, eps = 1500, 256, 1e-6
+    pts = wl.uniform_points(n, 2, 12)
+    pts = np.ascontiguousarray(pts[wl.morton_order(pts)])
+    mat = tlr.TLRMatrix.compress_kernel(pts, tlr.KERNEL_EXP, 0.1, 1e-4, m, eps)
+    ref = otlr.compress_kernel(pts, m, dense.KERNEL_EXP, 0.1, 1e-4, eps)
+    got = oracle_tlr(mat, tlr.INPUT)
+    for k in range(ref.nb):
+        np.testing.assert_allclose(got.diag[k], ref.diag[k], rtol=0, atol=1e-14)
+    rg, ro = mat.ranks(tlr.INPUT), ref.ranks()
+    for i in range(ref.nb):
+        for j in range(i):
+            exact = otlr.kernel_tile(pts, m, i, j, dense.KERNEL_EXP, 0.1, 1e-4)
+            e = np.linalg.norm(exact - got.u[i, j] @ got.v[i, j].T, 2)
+            assert e <= 4 * eps
+            assert rg[i, j] >= ro[i, j] - 2 and rg[i, j] <= ro[i, j] + 16
+            assert not got.u[i, j][mat.n - i * m:].any() if (i + 1) * m > n else True
+
+
+def test_relative_threshold_uses_norm_estimate():
+    pts, a = _cov(1024, 13)
+    t = otlr.compress_dense(a, 128, 1e-9)
+    mat = _upload(t)
+    st = mat.potrf(1e-6, tlr.opts(eps_mode=tlr.EPS_REL))
+    norm = np.linalg.norm(t.dense_symmetric()[:1024, :1024], 2)
+    # 20 power iterations: a lower bound of ||A||_2 within a fraction of a percent
+    assert 0.995 * norm <= st["norm_a"] <= norm * (1 + 1e-12)
+    assert abs(st["tau"] - 1e-6 * st["norm_a"]) < 1e-12 * norm
+    l = oracle_tlr(mat, tlr.FACTOR)
+    err = np.linalg.norm(_residual_tiles(t, l), 2)
+    assert err <= 2 * math.sqrt(t.nb) * st["tau"]
