@@ -359,15 +359,18 @@ tlr_status tlr_destroy(tlr_matrix_t A) {
   Mem& mem = A->mem;
   mem.put(A->Ad);
   mem.put(A->Ld);
+  mem.put(A->Li);
   mem.put(A->Dv);
   mem.put(A->UA);
   mem.put(A->VA);
   mem.put(A->d_info);
-  Work& w = A->ws;
-  DevBuf* bufs[] = {&w.G, &w.W, &w.omega, &w.P, &w.Z, &w.T, &w.Ta, &w.H, &w.Ball, &w.C, &w.Wa,
-                    &w.Y, &w.Q, &w.part, &w.rfac, &w.ints, &w.orth, &w.dscale, &w.tol, &w.compact};
-  for (DevBuf* b : bufs) b->release(mem);
+  if (A->side) (void)hipStreamSynchronize(A->side);
+  A->ws.release_all(mem);
   A->stage.release(mem);
+  if (A->pin_back) (void)hipHostFree(A->pin_back);
+  if (A->ev_fork) (void)hipEventDestroy(A->ev_fork);
+  if (A->ev_join) (void)hipEventDestroy(A->ev_join);
+  if (A->side) (void)hipStreamDestroy(A->side);
   delete A;
   return TLR_OK;
 }

@@ -357,7 +357,8 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_apply_rinv(const OrthDesc* __res
 // Stable compaction of the active list (slots whose flag is set leave) and
 // refill from the waiting list, keeping at most s_max tiles.  One workgroup.
 __global__ __launch_bounds__(256) void k_compact(int* act, int* counts, const int* flag,
-                                                 const int* waiting, int nwaiting, int s_max) {
+                                                 const int* waiting, int nwaiting, int s_max,
+                                                 const int* info) {
   __shared__ int keep_total;
   __shared__ int scan[256];
   const int tid = threadIdx.x;
@@ -397,6 +398,7 @@ __global__ __launch_bounds__(256) void k_compact(int* act, int* counts, const in
   if (tid == 0) {
     counts[0] = kept + take;
     counts[1] = cursor + take;
+    if (info) counts[2] = *info;
   }
 }
 
@@ -468,9 +470,9 @@ hipError_t launch_apply_rinv(const OrthDesc* d, int ntiles, int m, int bs, int p
 }
 
 hipError_t launch_compact(int* act, int* counts, const int* flag, const int* waiting, int nwaiting,
-                          int s_max, hipStream_t s) {
+                          int s_max, const int* info, hipStream_t s) {
   hipLaunchKernelGGL(k_compact, dim3(1), dim3(256), 0, s, act, counts, flag, waiting, nwaiting,
-                     s_max);
+                     s_max, info);
   return hipGetLastError();
 }
 

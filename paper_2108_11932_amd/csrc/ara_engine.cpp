@@ -21,7 +21,7 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   if (fresh_q) TLR_HIP(hipMemsetAsync(w.Q.p, 0, w.Q.cap, h->stream));
   TLR_TRY(w.part.ensure(h->mem, sizeof(double) * nn * nrb * bs * bs * 2));
   TLR_TRY(w.rfac.ensure(h->mem, sizeof(double) * nn * bs * bs));
-  const size_t nint = al(nn) * 2 + al(nn * (bs + 1)) + al(nn) * 2 + 64;
+  const size_t nint = 4 + 2 * nn + al(nn) + al(nn * (bs + 1)) + al(nn) + 64;
   TLR_TRY(w.ints.ensure(h->mem, sizeof(int) * nint));
   s->Y = w.Y.as<double>();
   s->C = w.C.as<double>();
@@ -29,17 +29,17 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   s->part = w.part.as<double>();
   s->rfac = w.rfac.as<double>();
   int* ip = w.ints.as<int>();
+  s->counts = ip;
+  ip += 4;
+  s->act = ip;
+  ip += nn;
   s->qv = ip;
-  ip += al(nn);
+  ip += nn;
   s->flag = ip;
   ip += al(nn);
   s->piv = ip;
   ip += al(nn * (bs + 1));
-  s->act = ip;
-  ip += al(nn);
   s->waiting = ip;
-  ip += al(nn);
-  s->counts = ip;
   return TLR_OK;
 }
 
@@ -80,35 +80,36 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   }
   std::vector<int>& q = res->q;
 
-  // read-back area: counts[2], info, act[n], q[n]
-  std::vector<int> back(3 + 2 * (size_t)n);
+  // read-back block: counts[2], status word, pad, act[ns], q[ns], laid out for
+  // the slot capacity ns >= n
+  const int ns = s.n;
+  if (n > ns) {
+    set_error("ARA batch of %d tiles exceeds the %d workspace slots", n, ns);
+    return TLR_ERR_STATE;
+  }
   int* pinned = nullptr;
-  TLR_HIP(hipHostMalloc((void**)&pinned, sizeof(int) * back.size(), hipHostMallocDefault));
-  struct PinGuard {
-    int* p;
-    ~PinGuard() { (void)hipHostFree(p); }
-  } guard{pinned};
+  TLR_TRY(h->pinned_ints(4 + 2 * (size_t)ns, &pinned));
 
   unsigned t = 0;
   bool first = true;
   while (!act.empty()) {
     const int na = (int)act.size();
-    TLR_HIP(launch_randn(omega, m, bs, m, c.seed, c.stream_id, t, 0, h->stream));
-    double f = 0.0;
-    TLR_TRY(sample(act, omega, &f));
-    res->flops += f;
+    Plan plan(h);
+    const unsigned tt = t;
+    plan.launch([=]() { return launch_randn(omega, m, bs, m, c.seed, c.stream_id, tt, 0, h->stream); });
+    TLR_TRY(sample(act, omega, plan));
 
     // block Gram-Schmidt, pass 1: Y -= Q (Q^T Y)
     {
-      GemmBatch c1(true, false), c2(false, false);
+      GemmBatch c1(true, false);
+      SegBatch c2;
       for (int sl : act)
         if (q[sl] > 0) {
-          c1.add(q[sl], bs, m, s.q(sl), m, s.y(sl), m, s.c(sl), m, 1.0, 0.0);
-          c2.add(m, bs, q[sl], s.q(sl), m, s.c(sl), m, s.y(sl), m, -1.0, 1.0);
+          c1.add(q[sl], bs, m, s.q(sl), m, s.y(sl), m, s.c(sl), m, -1.0, 0.0);
+          c2.add(m, bs, s.q(sl), m, s.c(sl), m, q[sl], nullptr, 1, nullptr, 1, 0, s.y(sl), m, 1.0);
         }
-      TLR_TRY(c1.run(h));
-      TLR_TRY(c2.run(h));
-      res->flops += c1.flops + c2.flops;
+      plan.gemm(c1);
+      plan.seg(c2);
     }
     std::vector<OrthDesc> od(na);
     for (int a = 0; a < na; ++a) {
@@ -117,28 +118,37 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
                        s.part + (size_t)sl * nrb * bs * bs * 2, s.rfac + (size_t)sl * bs * bs,
                        s.piv + (size_t)sl * (bs + 1)};
     }
-    void* dod = nullptr;
-    TLR_TRY(h->stage.upload(h, od.data(), sizeof(OrthDesc) * na, &dod));
-    const OrthDesc* D = (const OrthDesc*)dod;
-    TLR_HIP(launch_gram_dd(D, na, m, bs, 1, h->stream));
-    TLR_HIP(launch_pivchol(D, na, m, bs, c.tau * c.tau, c.r_min, c.qcap, h->stream));
-    TLR_HIP(launch_apply_rinv(D, na, m, bs, 1, h->stream));
+    const size_t ood = plan.stage(od.data(), sizeof(OrthDesc) * na);
+    hipStream_t st = h->stream;
+    const double tau2 = c.tau * c.tau;
+    const int r_min = c.r_min, qcap = c.qcap;
+    plan.launch(ood, [=](const char* p) { return launch_gram_dd((const OrthDesc*)p, na, m, bs, 1, st); });
+    plan.launch(ood, [=](const char* p) {
+      return launch_pivchol((const OrthDesc*)p, na, m, bs, tau2, r_min, qcap, st);
+    });
+    plan.launch(ood, [=](const char* p) { return launch_apply_rinv((const OrthDesc*)p, na, m, bs, 1, st); });
     // pass 2 on the new columns X = Q[:, qold : qold + bs]
     {
-      GemmBatch c1(true, false), c2(false, false);
+      GemmBatch c1(true, false);
+      SegBatch c2;
       for (int sl : act)
         if (q[sl] > 0) {
           double* X = s.q(sl) + (size_t)q[sl] * m;
-          c1.add(q[sl], bs, m, s.q(sl), m, X, m, s.c(sl), m, 1.0, 0.0);
-          c2.add(m, bs, q[sl], s.q(sl), m, s.c(sl), m, X, m, -1.0, 1.0);
+          c1.add(q[sl], bs, m, s.q(sl), m, X, m, s.c(sl), m, -1.0, 0.0);
+          c2.add(m, bs, s.q(sl), m, s.c(sl), m, q[sl], nullptr, 1, nullptr, 1, 0, X, m, 1.0);
         }
-      TLR_TRY(c1.run(h));
-      TLR_TRY(c2.run(h));
-      res->flops += c1.flops + c2.flops;
+      plan.gemm(c1);
+      plan.seg(c2);
     }
-    TLR_HIP(launch_gram_dd(D, na, m, bs, 2, h->stream));
-    TLR_HIP(launch_chol_small(D, na, m, bs, h->stream));
-    TLR_HIP(launch_apply_rinv(D, na, m, bs, 2, h->stream));
+    plan.launch(ood, [=](const char* p) { return launch_gram_dd((const OrthDesc*)p, na, m, bs, 2, st); });
+    plan.launch(ood, [=](const char* p) { return launch_chol_small((const OrthDesc*)p, na, m, bs, st); });
+    plan.launch(ood, [=](const char* p) { return launch_apply_rinv((const OrthDesc*)p, na, m, bs, 2, st); });
+    // convergence flags -> compaction and refill on the device
+    const int nwait = (int)waiting.size(), smax = s_max;
+    int* info = h->d_info;
+    plan.launch([=]() { return launch_compact(s.act, s.counts, s.flag, s.waiting, nwait, smax, info, st); });
+    TLR_TRY(plan.run());
+    res->flops += plan.flops;
     for (int sl : act) {
       // two Gram matrices, pivoted factor, two projections and the R^{-1} products
       const double qq = q[sl];
@@ -147,14 +157,9 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       res->flops += orth;
       res->iters[sl] += 1;
     }
-
-    // convergence flags -> compaction and refill on the device
-    TLR_HIP(launch_compact(s.act, s.counts, s.flag, s.waiting, (int)waiting.size(), s_max, h->stream));
-    TLR_HIP(hipMemcpyAsync(pinned, s.counts, sizeof(int) * 2, hipMemcpyDeviceToHost, h->stream));
-    TLR_HIP(hipMemcpyAsync(pinned + 2, h->d_info, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    TLR_HIP(hipMemcpyAsync(pinned + 3, s.act, sizeof(int) * n, hipMemcpyDeviceToHost, h->stream));
-    TLR_HIP(hipMemcpyAsync(pinned + 3 + n, s.qv, sizeof(int) * n, hipMemcpyDeviceToHost, h->stream));
-    TLR_TRY(h->sync());
+    TLR_HIP(hipMemcpyAsync(pinned, s.counts, sizeof(int) * (4 + 2 * (size_t)ns),
+                           hipMemcpyDeviceToHost, h->stream));
+    TLR_TRY(h->sync_main());
     const int cnt = pinned[0];
     if (cnt < 0 || cnt > n) {
       set_error("ARA compaction returned an invalid active count %d", cnt);
@@ -165,8 +170,8 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       return TLR_OK;
     }
     first = false;
-    act.assign(pinned + 3, pinned + 3 + cnt);
-    for (int i = 0; i < n; ++i) q[i] = pinned[3 + n + i];
+    act.assign(pinned + 4, pinned + 4 + cnt);
+    for (int i = 0; i < n; ++i) q[i] = pinned[4 + ns + i];
     ++t;
     res->launches += 1;
     if ((long long)t > (long long)n * (c.qcap + 1) + 1) {

@@ -37,11 +37,12 @@ struct AraSlots {
   double* C = nullptr;   // n x (m x bs)
   double* part = nullptr;
   double* rfac = nullptr;
+  // contiguous read-back block: counts[2], status word copy, pad, act[n], qv[n]
+  int* counts = nullptr; // 2 (+ 2)
+  int* act = nullptr;    // n
   int* qv = nullptr;     // n
   int* flag = nullptr;   // n
   int* piv = nullptr;    // n x (bs + 1)
-  int* act = nullptr;    // n
-  int* counts = nullptr; // 2
   int* waiting = nullptr;// n
   size_t qstride = 0;    // doubles per slot in Q
   double* y(int s) const { return Y + (size_t)s * m * bs; }
@@ -60,9 +61,10 @@ struct AraResult {
 // Allocate the slot buffers for n slots.
 tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s);
 
-// Sample callback: fill Y(s) = S_s * omega for every slot in `act`.
+// Sample callback: add to `plan` the launches that fill Y(s) = S_s * omega
+// for every slot in `act`.
 using SampleFn = std::function<tlr_status(const std::vector<int>& act, const double* omega,
-                                          double* flops)>;
+                                          Plan& plan)>;
 
 // Run the ARA loop.  `order` lists the slots in processing order (the
 // sortRanks order); the first s_max start active.  `info_abort` is checked

@@ -94,11 +94,12 @@ tlr_status compress(Handle* h, const double* A, long long lda, const double* pts
     TLR_TRY(h->stage.upload(h, gd.data(), sizeof(GenDesc) * nt, &dg));
     TLR_HIP(launch_gen_tiles((const GenDesc*)dg, nt, pts, dim, h->N, m, kern, ell, diag_add, A, lda,
                              h->stream));
-    SampleFn sample = [&](const std::vector<int>& act, const double* omega, double* f) -> tlr_status {
-      GemmBatch y(false, false);
-      for (int sl : act) y.add(m, bs, m, Tt + (size_t)sl * m * m, m, omega, m, slots.y(sl), m, 1.0, 0.0);
-      TLR_TRY(y.run(h));
-      *f += y.flops;
+    SampleFn sample = [&](const std::vector<int>& act, const double* omega, Plan& plan) -> tlr_status {
+      SegBatch y;
+      for (int sl : act)
+        y.add(m, bs, Tt + (size_t)sl * m * m, m, omega, m, m, nullptr, 1, nullptr, 1, 0, slots.y(sl), m,
+              0.0);
+      plan.seg(y);
       return TLR_OK;
     };
     std::vector<int> order(nt);

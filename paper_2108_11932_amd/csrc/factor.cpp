@@ -72,6 +72,12 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
     TLR_TRY(h->mem.get(&p, sizeof(double) * (size_t)nb * m * m));
     h->Ld = (double*)p;
   }
+  if (!h->Li) {
+    void* p = nullptr;
+    TLR_TRY(h->mem.get(&p, sizeof(double) * (size_t)nb * m * m));
+    h->Li = (double*)p;
+  }
+  TLR_TRY(h->init_streams());
   if (ldl && !h->Dv) {
     void* p = nullptr;
     TLR_TRY(h->mem.get(&p, sizeof(double) * (size_t)nb * m));
@@ -154,30 +160,39 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
     };
 
     // ---------------------------------------------- updateDense + chol / ldl
+    // on the diagonal-tile stream: they need only the G blocks and row k's
+    // panels, and the column's ARA needs L_kk only at the triangular solve
     double* Lkk = h->diagL(k);
-    TLR_HIP(launch_copy_shift(h->diagA(k), Lkk, m, h->nreal(k), shift, h->stream));
+    hipStream_t ds = h->side;
+    TLR_HIP(hipEventRecord(h->ev_fork, h->stream));
+    TLR_HIP(hipStreamWaitEvent(ds, h->ev_fork, 0));
+    TLR_HIP(launch_copy_shift(h->diagA(k), Lkk, m, h->nreal(k), shift, ds));
     if (Rk > 0) {
-      TLR_TRY(w.H.ensure(h->mem, sizeof(double) * (size_t)m * Rk));
-      double* Wd = w.H.as<double>();
+      if (w.Wd.cap < sizeof(double) * (size_t)m * Rk) {
+        TLR_HIP(hipStreamSynchronize(ds));
+        TLR_TRY(w.Wd.ensure(h->mem, sizeof(double) * (size_t)m * Rk));
+      }
+      double* Wd = w.Wd.as<double>();
       GemmBatch wb(false, false);
       for (int j = 0; j < k; ++j) {
         const int r = h->lr(k, j);
         if (r == 0) continue;
         wb.add(m, r, r, h->ul(k, j), m, gptr(k, j), r, Wd + h->lo(k, j) * m, m, 1.0, 0.0);
       }
-      TLR_TRY(wb.run(h));
+      TLR_TRY(wb.run(h, ds));
       GemmBatch up(false, true);
-      up.add(m, m, Rk, Wd, m, h->UL[k], m, Lkk, m, -1.0, 1.0);
-      TLR_TRY(up.run(h));
-      flops += wb.flops + up.flops;
+      up.add(m, m, Rk, Wd, m, h->UL[k], m, Lkk, m, -1.0, 1.0, GEMM_LOWER_C);
+      TLR_TRY(up.run(h, ds));
+      flops += wb.flops + up.flops / 2;
     }
     flops_paper += 2.0 * m * (double)m * Rk + (double)m * m * m / 3.0;
     if (ldl) {
-      TLR_TRY(dense_ldlt(h, Lkk, m, m, h->Dv + (size_t)k * m, k * m));
+      TLR_TRY(dense_ldlt(h, Lkk, m, m, h->Dv + (size_t)k * m, k * m, h->invL(k), ds));
     } else {
-      TLR_TRY(dense_potrf(h, Lkk, m, m, k * m));
+      TLR_TRY(dense_potrf(h, Lkk, m, m, k * m, h->invL(k), ds));
     }
-    flops += (double)m * m * m / 3.0;
+    TLR_HIP(hipEventRecord(h->ev_join, ds));
+    flops += (double)m * m * m / 3.0 + (double)m * m * m / 3.0;
 
     const int nrow = nb - k - 1;
     if (nrow == 0) break;
@@ -195,9 +210,12 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
       TLR_TRY(h->stage.upload(h, rk.data(), sizeof(int) * nrow, &dr));
       TLR_TRY(h->stage.upload(h, rows.data(), sizeof(int) * nrow, &dw));
       TLR_HIP(launch_sort_ranks((const int*)dr, (const int*)dw, nrow, slots.waiting, h->stream));
-      TLR_HIP(hipMemcpyAsync(order.data(), slots.waiting, sizeof(int) * nrow, hipMemcpyDeviceToHost,
+      int* pin = nullptr;
+      TLR_TRY(h->pinned_ints(nrow, &pin));
+      TLR_HIP(hipMemcpyAsync(pin, slots.waiting, sizeof(int) * nrow, hipMemcpyDeviceToHost,
                              h->stream));
-      TLR_TRY(h->sync());
+      TLR_TRY(h->sync_main());
+      order.assign(pin, pin + nrow);
     }
 
     // ---------------------------------------------- cholARAUpdate
@@ -211,53 +229,54 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
     double* P = w.P.as<double>();
     double* Wa = w.Wa.as<double>();
     double* Z = w.Z.as<double>();
-    SampleFn sample = [&](const std::vector<int>& act, const double* omega, double* f) -> tlr_status {
+    SampleFn sample = [&](const std::vector<int>& act, const double* omega, Plan& plan) -> tlr_status {
       if (Rk > 0) {
         GemmBatch pb(true, false);
         pb.add(Rk, bs, m, h->UL[k], m, omega, m, P, Rk, 1.0, 0.0);
-        TLR_TRY(pb.run(h));
-        *f += pb.flops;
+        plan.gemm(pb);
       }
-      GemmBatch wa(true, false), zb(false, false), y1(false, false), y2(false, false);
+      GemmBatch wa(true, false), zb(false, false);
+      SegBatch y;
       long long zo = 0;
       for (int sl : act) {
         const int i = k + 1 + sl;
         const int a = h->ar(i, k);
         double* wa_s = Wa + (size_t)sl * m * bs;
         if (a > 0) wa.add(a, bs, m, h->va(i, k), m, omega, m, wa_s, m, 1.0, 0.0);
-        y1.add(m, bs, a, h->ua(i, k), m, wa_s, m, slots.y(sl), m, 1.0, 0.0);
         const int Ri = h->R[i];
+        int k1 = 0;
+        const double* zs = nullptr;
         if (Rk > 0 && Ri > 0) {
+          // Z' = -[G_ij P_j]_j, so that Y = U^A Wa + U_i* Z'
           for (int j = 0; j < k; ++j) {
             const int rij = h->lr(i, j);
             if (rij == 0) continue;
             zb.add(rij, bs, h->lr(k, j), gptr(i, j), rij, P + h->lo(k, j), Rk, Z + zo + h->lo(i, j),
-                   Ri, 1.0, 0.0);
+                   Ri, -1.0, 0.0);
           }
-          y2.add(m, bs, Ri, h->UL[i], m, Z + zo, Ri, slots.y(sl), m, -1.0, 1.0);
+          zs = Z + zo;
+          k1 = Ri;
           zo += (long long)Ri * bs;
         }
+        y.add(m, bs, h->ua(i, k), m, wa_s, m, a, h->UL[i], m, zs, std::max(Ri, 1), k1,
+              slots.y(sl), m, 0.0);
       }
-      TLR_TRY(wa.run(h));
-      TLR_TRY(zb.run(h));
-      TLR_TRY(y1.run(h));
-      if (timing && !y2.d.empty()) {
+      plan.gemm(wa);
+      plan.gemm(zb);
+      if (timing && !y.d.empty()) {
         hipEvent_t e0, e1;
         TLR_HIP(hipEventCreate(&e0));
         TLR_HIP(hipEventCreate(&e1));
-        TLR_HIP(hipEventRecord(e0, h->stream));
-        TLR_TRY(y2.run(h));
-        TLR_HIP(hipEventRecord(e1, h->stream));
         events.push_back({e0, e1});
-        double b = 0.0;
-        for (const auto& g : y2.d)
-          b += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + 2.0 * g.M * g.N);
-        samp_bytes += b;
-        samp_flops += y2.flops;
+        hipStream_t st = h->stream;
+        plan.launch([=]() { return hipEventRecord(e0, st); });
+        plan.seg(y);
+        plan.launch([=]() { return hipEventRecord(e1, st); });
+        samp_bytes += y.bytes;
+        samp_flops += y.flops;
       } else {
-        TLR_TRY(y2.run(h));
+        plan.seg(y);
       }
-      *f += wa.flops + zb.flops + y1.flops + y2.flops;
       return TLR_OK;
     };
     // slots hold rows k+1.. in natural order; `order` is the sorted order
@@ -290,6 +309,11 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
     double* Ta = w.Ta.as<double>();
     double* H = w.H.as<double>();
     double* Ball = w.Ball.as<double>();
+    TLR_TRY(w.Bt.ensure(h->mem, sizeof(double) * (size_t)std::max((long long)m * sq, 1LL)));
+    double* Bt = w.Bt.as<double>();
+    for (int s = 0; s < nrow; ++s)
+      if (q[s] > 0) TLR_TRY(grow_row(h, k + 1 + s, q[s]));
+    Plan plan(h);
     {
       GemmBatch t1(true, false), t2(true, false), hb(true, false), b1(false, false), b2(false, false);
       for (int s = 0; s < nrow; ++s) {
@@ -312,22 +336,29 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
                0.0);
       }
       if (Rk > 0 && sq > 0) b2.add(m, (int)sq, Rk, h->UL[k], m, H, Rk, Ball, m, -1.0, 1.0);
-      TLR_TRY(t1.run(h));
-      TLR_TRY(t2.run(h));
-      TLR_TRY(hb.run(h));
-      TLR_TRY(b1.run(h));
-      TLR_TRY(b2.run(h));
-      flops += t1.flops + t2.flops + hb.flops + b1.flops + b2.flops;
+      plan.gemm(t1);
+      plan.gemm(t2);
+      plan.gemm(hb);
+      plan.gemm(b1);
+      plan.gemm(b2);
     }
     // ---------------------------------------------- batchTrsm (+ batchIDMult)
-    TLR_TRY(dense_trsm(h, Lkk, m, Ball, m, m, (int)sq, ldl, false));
+    // V = L_kk^{-1} B for every tile of the column: one triangular product
+    {
+      hipStream_t st = h->stream;
+      hipEvent_t ej = h->ev_join;
+      plan.launch([=]() { return hipStreamWaitEvent(st, ej, 0); });
+      GemmBatch tb(false, false);
+      tb.add(m, (int)sq, m, h->invL(k), m, Ball, m, Bt, m, 1.0, 0.0, GEMM_TRIL_A);
+      plan.gemm(tb);
+      if (ldl && sq > 0) {
+        const double* dk = h->Dv + (size_t)k * m;
+        const int n = (int)sq;
+        plan.launch([=]() { return launch_scale_rows(Bt, m, Bt, m, dk, m, n, true, st); });
+      }
+    }
     flops += (double)m * m * sq;
-    if (ldl && sq > 0)
-      TLR_HIP(launch_scale_rows(Ball, m, Ball, m, h->Dv + (size_t)k * m, m, (int)sq, true, h->stream));
-
     // ---------------------------------------------- updateTiles
-    for (int s = 0; s < nrow; ++s)
-      if (q[s] > 0) TLR_TRY(grow_row(h, k + 1 + s, q[s]));
     {
       std::vector<CopyDesc> cd;
       int maxc = 0;
@@ -335,15 +366,20 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
         const int i = k + 1 + s, qs = q[s];
         if (qs == 0) continue;
         cd.push_back(CopyDesc{slots.q(s), h->UL[i] + (size_t)h->R[i] * m, m, qs, m, m});
-        cd.push_back(CopyDesc{Ball + boff[s] * m, h->VL[i] + (size_t)h->R[i] * m, m, qs, m, m});
+        cd.push_back(CopyDesc{Bt + boff[s] * m, h->VL[i] + (size_t)h->R[i] * m, m, qs, m, m});
         maxc = std::max(maxc, qs);
       }
       if (!cd.empty()) {
-        void* dcd = nullptr;
-        TLR_TRY(h->stage.upload(h, cd.data(), sizeof(CopyDesc) * cd.size(), &dcd));
-        TLR_HIP(launch_copy_batched((const CopyDesc*)dcd, (int)cd.size(), maxc, h->stream));
+        const size_t off = plan.stage(cd.data(), sizeof(CopyDesc) * cd.size());
+        const int n = (int)cd.size();
+        hipStream_t st = h->stream;
+        plan.launch(off, [=](const char* p) {
+          return launch_copy_batched((const CopyDesc*)p, n, maxc, st);
+        });
       }
     }
+    TLR_TRY(plan.run());
+    flops += plan.flops;
     for (int s = 0; s < nrow; ++s) {
       const int i = k + 1 + s;
       h->l_rank[(size_t)i * nb + k] = q[s];
@@ -359,6 +395,8 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
       tile_iters += res.iters[s];
     }
   }
+  TLR_HIP(hipEventRecord(h->ev_join, h->side));
+  TLR_HIP(hipStreamWaitEvent(h->stream, h->ev_join, 0));
   TLR_TRY(h->sync());
   double samp_ms = 0.0;
   for (auto& ev : events) {

@@ -46,6 +46,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   const int tiles_m = (d.M + BM - 1) / BM;
   const int row0 = (bm.tile % tiles_m) * BM;
   const int col0 = (bm.tile / tiles_m) * BN;
+  if ((d.flags & GEMM_LOWER_C) && col0 >= row0 + BM) return;
+  int kbeg = 0, kend = d.K;
+  if (d.flags & GEMM_TRIL_A) kend = min(kend, row0 + BM);
+  if (d.flags & GEMM_TRIU_A) kbeg = (row0 / BK) * BK;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -61,7 +65,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < d.K; k0 += BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     // ---- stage op(A)(row0 + r, k0 + kk), 64 x 16
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -122,6 +126,104 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
     }
 }
 
+// C = alpha A^T B + beta C with A stored K x M and B stored K x N (both
+// column-major, the contraction runs down their columns): the projections
+// U^T Omega, Q^T Y, V^T V, U^T Q of the method, where K is the tile height.
+// A workgroup owns a (16 FM) x (16 FN) tile of C; its four waves take
+// interleaved 16-row slices of K.  Within a slice lane (i, g) reads rows
+// 4g..4g+3 of column i of A and of B, so both operands are read in 32-byte
+// runs down their columns, and MFMA t of the slice consumes row 4g + t: the
+// same permutation of k on both operands, so the sum is unchanged.  The four
+// partial tiles are added in LDS in a fixed order.
+template <int FM, int FN>
+__global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ descs,
+                                                 const BlockMap* __restrict__ map) {
+  constexpr int TM = 16 * FM, TN = 16 * FN;
+  __shared__ double red[4][FM * FN * 4][64];
+  const BlockMap bm = map[blockIdx.x];
+  const GemmDesc d = descs[bm.desc];
+  const int tiles_m = (d.M + TM - 1) / TM;
+  const int row0 = (bm.tile % tiles_m) * TM;
+  const int col0 = (bm.tile / tiles_m) * TN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  int kbeg = 0, kend = d.K;
+  if (d.flags & GEMM_TRIU_A) kbeg = (row0 / 16) * 16;
+
+  d4 acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const double* acol[FM];
+  const double* bcol[FN];
+  bool aok[FM], bok[FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a) {
+    const int i = row0 + a * 16 + li;
+    aok[a] = i < d.M;
+    acol[a] = d.A + (size_t)(aok[a] ? i : 0) * d.lda;
+  }
+#pragma unroll
+  for (int b = 0; b < FN; ++b) {
+    const int j = col0 + b * 16 + li;
+    bok[b] = j < d.N;
+    bcol[b] = d.B + (size_t)(bok[b] ? j : 0) * d.ldb;
+  }
+  for (int k0 = kbeg + wave * 16; k0 < kend; k0 += 64) {
+    const int kr = k0 + 4 * g;
+    double av[FM][4], bv[FN][4];
+    if (kr + 3 < kend) {
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) av[a][t] = aok[a] ? acol[a][kr + t] : 0.0;
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bv[b][t] = bok[b] ? bcol[b][kr + t] : 0.0;
+    } else {
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) av[a][t] = (aok[a] && kr + t < kend) ? acol[a][kr + t] : 0.0;
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bv[b][t] = (bok[b] && kr + t < kend) ? bcol[b][kr + t] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a][t], bv[b][t], acc[a][b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wave][(a * FN + b) * 4 + r][lane] = acc[a][b][r];
+  __syncthreads();
+  // each thread finishes FM*FN*4*64/256 outputs
+  for (int e = threadIdx.x; e < FM * FN * 4 * 64; e += 256) {
+    const int slot = e / 64, l = e % 64;
+    const int ab = slot / 4, r = slot % 4;
+    const int a = ab / FN, b = ab % FN;
+    const int gr = row0 + a * 16 + (l >> 4) + 4 * r;
+    const int gc = col0 + b * 16 + (l & 15);
+    if (gr >= d.M || gc >= d.N) continue;
+    const double v = ((red[0][slot][l] + red[1][slot][l]) + red[2][slot][l]) + red[3][slot][l];
+    double* cp = d.C + gr + (size_t)gc * d.ldc;
+    double out = d.alpha * v;
+    if (d.beta != 0.0) out += d.beta * *cp;
+    *cp = out;
+  }
+}
+
 template <bool TA, bool TB>
 hipError_t launch_tt(const GemmDesc* d, const BlockMap* map, int nblocks, int bn, hipStream_t s) {
   if (bn == 64)
@@ -135,11 +237,27 @@ hipError_t launch_tt(const GemmDesc* d, const BlockMap* map, int nblocks, int bn
 
 int gemm_tile_n(int N) { return N <= 16 ? 16 : 64; }
 
+void gemm_tile_shape(bool trans_a, bool trans_b, int maxn, int* tm, int* tn) {
+  if (trans_a && !trans_b) {
+    *tm = 32;
+    *tn = maxn <= 16 ? 16 : 32;
+  } else {
+    *tm = 64;
+    *tn = gemm_tile_n(maxn);
+  }
+}
+
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, int nblocks,
                                bool trans_a, bool trans_b, int bn, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
   if (!trans_a && !trans_b) return launch_tt<false, false>(d_descs, d_map, nblocks, bn, s);
-  if (trans_a && !trans_b) return launch_tt<true, false>(d_descs, d_map, nblocks, bn, s);
+  if (trans_a && !trans_b) {
+    if (bn <= 16)
+      hipLaunchKernelGGL((k_gemm_tn<2, 1>), dim3(nblocks), dim3(256), 0, s, d_descs, d_map);
+    else
+      hipLaunchKernelGGL((k_gemm_tn<2, 2>), dim3(nblocks), dim3(256), 0, s, d_descs, d_map);
+    return hipGetLastError();
+  }
   if (!trans_a && trans_b) return launch_tt<false, true>(d_descs, d_map, nblocks, bn, s);
   return launch_tt<true, true>(d_descs, d_map, nblocks, bn, s);
 }

@@ -6,6 +6,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -66,8 +67,10 @@ struct Staging {
   size_t cap = 0, used = 0;
   tlr_status init(Mem& mem, size_t bytes);
   void release(Mem& mem);
-  // Copy `bytes` of host data to device memory; returns the device address.
-  tlr_status upload(Handle* h, const void* data, size_t bytes, void** dptr);
+  // Copy `bytes` of host data to device memory on stream s (default: the
+  // handle's main stream); returns the device address.
+  tlr_status upload(Handle* h, const void* data, size_t bytes, void** dptr,
+                    hipStream_t s = nullptr);
 };
 
 // One batch of GEMMs with uniform transposition.
@@ -77,19 +80,72 @@ struct GemmBatch {
   double flops = 0.0;
   GemmBatch(bool ta_, bool tb_) : ta(ta_), tb(tb_) {}
   void add(int M, int N, int K, const double* A, int lda, const double* B, int ldb, double* C,
-           int ldc, double alpha, double beta) {
+           int ldc, double alpha, double beta, int flags = 0) {
     if (M <= 0 || N <= 0) return;
-    d.push_back(GemmDesc{A, B, C, M, N, K, lda > 0 ? lda : 1, ldb > 0 ? ldb : 1, ldc, alpha, beta});
+    d.push_back(GemmDesc{A, B, C, M, N, K, lda > 0 ? lda : 1, ldb > 0 ? ldb : 1, ldc, flags, alpha,
+                         beta});
     flops += 2.0 * M * N * (double)K;
   }
-  tlr_status run(Handle* h);
+  // Stage descriptors and block map in one copy, then launch on stream s
+  // (default: the handle's main stream).
+  tlr_status run(Handle* h, hipStream_t s = nullptr);
+};
+
+// One launch of the narrow two-segment product (sampling, Gram-Schmidt).
+struct SegBatch {
+  std::vector<SegDesc> d;
+  double flops = 0.0, bytes = 0.0;
+  void add(int M, int N, const double* A0, int lda0, const double* B0, int ldb0, int K0,
+           const double* A1, int lda1, const double* B1, int ldb1, int K1, double* C, int ldc,
+           double beta) {
+    if (M <= 0 || N <= 0) return;
+    SegDesc s{};
+    s.A[0] = A0; s.B[0] = B0; s.lda[0] = lda0 > 0 ? lda0 : 1; s.ldb[0] = ldb0 > 0 ? ldb0 : 1;
+    s.K[0] = K0 > 0 ? K0 : 0;
+    s.A[1] = A1; s.B[1] = B1; s.lda[1] = lda1 > 0 ? lda1 : 1; s.ldb[1] = ldb1 > 0 ? ldb1 : 1;
+    s.K[1] = K1 > 0 ? K1 : 0;
+    s.C = C; s.ldc = ldc; s.M = M; s.N = N; s.beta = beta;
+    d.push_back(s);
+    const double K = (double)s.K[0] + s.K[1];
+    flops += 2.0 * M * N * K;
+    bytes += 8.0 * ((double)M * K + K * N + (beta != 0.0 ? 2.0 : 1.0) * M * N);
+  }
+  tlr_status run(Handle* h, hipStream_t s = nullptr);
+};
+
+// A sequence of launches whose descriptors are staged with a single copy:
+// add() batches in launch order, then run() uploads everything once and
+// issues the launches on the plan's stream.
+struct Plan {
+  Handle* h;
+  hipStream_t s;
+  std::vector<char> blob;
+  std::vector<std::function<hipError_t(const char*)>> steps;
+  double flops = 0.0;
+  Plan(Handle* h_, hipStream_t s_ = nullptr);
+  // stage raw bytes; returns the offset of the copy inside the device blob
+  size_t stage(const void* p, size_t n);
+  void gemm(const GemmBatch& b);
+  void seg(const SegBatch& b);
+  // a launch that reads staged bytes at `off` (device address passed in)
+  void launch(size_t off, std::function<hipError_t(const char*)> f);
+  // a launch that needs no staged data
+  void launch(std::function<hipError_t()> f);
+  tlr_status run();
 };
 
 // Per-column workspace of the factorization.
 struct Work {
   DevBuf G, W, omega, P, Z, T, Ta, H, Ball, C, Wa, Y, Q, part, rfac, ints, orth, dscale, tol,
-      compact;
+      compact, Bt;
+  // buffers of the diagonal-tile stream (never touched by the main stream)
+  DevBuf Wd, dW, dtol;
   int slots = 0;   // slot capacity of the per-tile buffers
+  void release_all(Mem& mem) {
+    DevBuf* bufs[] = {&G, &W, &omega, &P, &Z, &T, &Ta, &H, &Ball, &C, &Wa, &Y, &Q, &part, &rfac,
+                      &ints, &orth, &dscale, &tol, &compact, &Bt, &Wd, &dW, &dtol};
+    for (DevBuf* b : bufs) b->release(mem);
+  }
 };
 
 }  // namespace tlr
@@ -102,8 +158,12 @@ struct tlr_matrix_s {
   long long N = 0;
   int m = 0, nb = 0, dev = 0;
   Mem mem;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // caller's stream: everything is ordered on it
+  hipStream_t side = nullptr;     // library stream for the diagonal tiles (default priority)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   Staging stage;
+  int* pin_back = nullptr;        // pinned read-back area
+  size_t pin_back_n = 0;
 
   // input matrix
   double* Ad = nullptr;           // nb diagonal tiles, m x m each
@@ -117,6 +177,7 @@ struct tlr_matrix_s {
   // factor
   int factored = 0;               // 0 none, 1 Cholesky, 2 LDL^T
   double* Ld = nullptr;
+  double* Li = nullptr;           // nb tiles L_kk^{-1}, m x m each
   double* Dv = nullptr;           // nb * m LDL^T pivots
   std::vector<int> l_rank;
   std::vector<long long> l_off;   // column of tile (i, j) inside row i's panel
@@ -132,6 +193,7 @@ struct tlr_matrix_s {
   }
   double* diagA(int k) const { return Ad + (size_t)k * m * m; }
   double* diagL(int k) const { return Ld + (size_t)k * m * m; }
+  double* invL(int k) const { return Li + (size_t)k * m * m; }
   double* ua(int i, int j) const { return UA + (size_t)a_off[(size_t)i * nb + j] * m; }
   double* va(int i, int j) const { return VA + (size_t)a_off[(size_t)i * nb + j] * m; }
   int ar(int i, int j) const { return a_rank[(size_t)i * nb + j]; }
@@ -140,14 +202,22 @@ struct tlr_matrix_s {
   double* vl(int i, int j) const { return VL[i] + (size_t)l_off[(size_t)i * nb + j] * m; }
   long long lo(int i, int j) const { return l_off[(size_t)i * nb + j]; }
 
-  tlr_status sync();
+  tlr_status sync();          // both streams; recycles the staging area
+  tlr_status sync_main();     // the caller's stream only
+  tlr_status init_streams();
+  tlr_status pinned_ints(size_t n, int** p);
 };
 
 namespace tlr {
 
-// Dense tile operations built from the panel kernels and the batched GEMM.
-tlr_status dense_potrf(Handle* h, double* A, int lda, int m, int row_base);
-tlr_status dense_ldlt(Handle* h, double* A, int lda, int m, double* d, int row_base);
+// Dense tile operations built from the diagonal-block kernel and the batched
+// GEMM, on stream s.  The factor overwrites A (lower, upper part zeroed);
+// Linv (ld m) receives the inverse of the lower factor.  For LDL^T the
+// factor is unit lower and d the pivots.
+tlr_status dense_potrf(Handle* h, double* A, int lda, int m, int row_base, double* Linv,
+                       hipStream_t s);
+tlr_status dense_ldlt(Handle* h, double* A, int lda, int m, double* d, int row_base, double* Linv,
+                      hipStream_t s);
 tlr_status dense_trsm(Handle* h, const double* L, int ldl, double* B, int ldb, int m, int n,
                       bool unit, bool trans);
 

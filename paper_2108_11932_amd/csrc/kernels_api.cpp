@@ -25,12 +25,10 @@ struct Ctx {
   }
   ~Ctx() {
     (void)hipStreamSynchronize(h.stream);
-    Work& w = h.ws;
-    DevBuf* bufs[] = {&w.G, &w.W, &w.omega, &w.P, &w.Z, &w.T, &w.Ta, &w.H, &w.Ball, &w.C, &w.Wa,
-                      &w.Y, &w.Q, &w.part, &w.rfac, &w.ints, &w.orth, &w.dscale, &w.tol, &w.compact};
-    for (DevBuf* b : bufs) b->release(h.mem);
+    h.ws.release_all(h.mem);
     h.mem.put(h.d_info);
     h.stage.release(h.mem);
+    if (h.pin_back) (void)hipHostFree(h.pin_back);
   }
   tlr_status info(int* out) {
     TLR_TRY(h.sync());
@@ -75,16 +73,24 @@ tlr_status tlrk_potrf(int m, double* A, int lda, int* info, void* stream) {
   KARG(m > 0 && A && lda >= m && info, "invalid argument");
   Ctx c;
   TLR_TRY(c.init(stream, m));
-  TLR_TRY(dense_potrf(&c.h, A, lda, m, 0));
-  return c.info(info);
+  void* inv = nullptr;
+  TLR_TRY(c.h.mem.get(&inv, sizeof(double) * (size_t)m * m));
+  tlr_status st = dense_potrf(&c.h, A, lda, m, 0, (double*)inv, c.h.stream);
+  if (st == TLR_OK) st = c.info(info);
+  c.h.mem.put(inv);
+  return st;
 }
 
 tlr_status tlrk_ldlt(int m, double* A, int lda, double* d, int* info, void* stream) {
   KARG(m > 0 && A && d && lda >= m && info, "invalid argument");
   Ctx c;
   TLR_TRY(c.init(stream, m));
-  TLR_TRY(dense_ldlt(&c.h, A, lda, m, d, 0));
-  return c.info(info);
+  void* inv = nullptr;
+  TLR_TRY(c.h.mem.get(&inv, sizeof(double) * (size_t)m * m));
+  tlr_status st = dense_ldlt(&c.h, A, lda, m, d, 0, (double*)inv, c.h.stream);
+  if (st == TLR_OK) st = c.info(info);
+  c.h.mem.put(inv);
+  return st;
 }
 
 tlr_status tlrk_trsm(int m, int n, const double* L, int ldl, double* B, int ldb, int unit, int trans,
@@ -130,12 +136,12 @@ tlr_status tlrk_ara(int m, int count, const double* tiles, double tau, int bs, i
   cfg.stream_id = 0;
   AraSlots slots;
   TLR_TRY(ara_slots(&c.h, cfg, count, &slots));
-  SampleFn sample = [&](const std::vector<int>& act, const double* omega, double* f) -> tlr_status {
-    GemmBatch y(false, false);
+  SampleFn sample = [&](const std::vector<int>& act, const double* omega, Plan& plan) -> tlr_status {
+    SegBatch y;
     for (int sl : act)
-      y.add(m, bs, m, tiles + (size_t)sl * m * m, m, omega, m, slots.y(sl), m, 1.0, 0.0);
-    TLR_TRY(y.run(&c.h));
-    *f += y.flops;
+      y.add(m, bs, tiles + (size_t)sl * m * m, m, omega, m, m, nullptr, 1, nullptr, 1, 0, slots.y(sl),
+            m, 0.0);
+    plan.seg(y);
     return TLR_OK;
   };
   std::vector<int> order(count);
@@ -203,7 +209,7 @@ tlr_status tlrk_compact(int nslots, int* act, int* count, const int* flags, cons
   TLR_TRY(c.h.stage.upload(&c.h, flags, sizeof(int) * std::max(nslots, 1), &dflags));
   if (nwaiting > 0) TLR_TRY(c.h.stage.upload(&c.h, waiting, sizeof(int) * nwaiting, &dwait));
   TLR_HIP(launch_compact(dact, dcounts, (const int*)dflags, (const int*)dwait, nwaiting, s_max,
-                         c.h.stream));
+                         nullptr, c.h.stream));
   TLR_TRY(c.h.sync());
   int back[2];
   TLR_HIP(hipMemcpy(back, dcounts, sizeof back, hipMemcpyDeviceToHost));

@@ -50,9 +50,12 @@ __global__ void k_zero_upper(double* A, int lda, int m) {
 __global__ __launch_bounds__(256) void k_pivot_tol(const double* A, int lda, int m, double* tol) {
   __shared__ double red[256];
   double s = 0.0;
+  // the lower triangle holds the tile (the strict upper part may be stale)
   for (long long e = threadIdx.x; e < (long long)m * m; e += blockDim.x) {
-    const double v = A[(e % m) + (e / m) * (size_t)lda];
-    s += v * v;
+    const int r = (int)(e % m), c = (int)(e / m);
+    if (r < c) continue;
+    const double v = A[r + (size_t)c * lda];
+    s += (r == c ? 1.0 : 2.0) * v * v;
   }
   red[threadIdx.x] = s;
   __syncthreads();

@@ -152,16 +152,28 @@ tlr_status solve(Handle* h, int nrhs, double* B, long long ldb) {
     tcap = std::max(tcap, s);
   }
   tcap = std::max(tcap, rmax);
-  TLR_TRY(w.omega.ensure(h->mem, sizeof(double) * np * nrhs));
+  TLR_TRY(w.omega.ensure(h->mem, sizeof(double) * (np + m) * nrhs));
   TLR_TRY(w.T.ensure(h->mem, sizeof(double) * (size_t)std::max(tcap, 1LL) * nrhs));
   double* Xp = w.omega.as<double>();
+  double* tk = Xp + np * nrhs;   // m x nrhs
   double* T = w.T.as<double>();
   const int ldx = (int)np;
   TLR_TRY(pad_in(h, B, ldb, nrhs, Xp));
+  auto apply_inv = [&](int k, bool trans) -> tlr_status {
+    double* xk = Xp + (size_t)k * m;
+    GemmBatch g(trans, false);
+    g.add(m, nrhs, m, h->invL(k), m, xk, ldx, tk, m, 1.0, 0.0, trans ? GEMM_TRIU_A : GEMM_TRIL_A);
+    TLR_TRY(g.run(h));
+    CopyDesc cd{tk, xk, m, nrhs, m, ldx};
+    void* d = nullptr;
+    TLR_TRY(h->stage.upload(h, &cd, sizeof cd, &d));
+    TLR_HIP(launch_copy_batched((const CopyDesc*)d, 1, nrhs, h->stream));
+    return TLR_OK;
+  };
   // forward sweep: x_k = L_kk^{-1} x_k, then x_i -= U_ik (V_ik^T x_k) for i > k
   for (int k = 0; k < nb; ++k) {
     double* xk = Xp + (size_t)k * m;
-    TLR_TRY(dense_trsm(h, h->diagL(k), m, xk, ldx, m, nrhs, ldl, false));
+    TLR_TRY(apply_inv(k, false));
     GemmBatch t(true, false), u(false, false);
     long long off = 0;
     for (int i = k + 1; i < nb; ++i) {
@@ -178,7 +190,7 @@ tlr_status solve(Handle* h, int nrhs, double* B, long long ldb) {
   // backward sweep with L^T: x_k = L_kk^{-T} x_k, then x_j -= V_kj (U_kj^T x_k)
   for (int k = nb - 1; k >= 0; --k) {
     double* xk = Xp + (size_t)k * m;
-    TLR_TRY(dense_trsm(h, h->diagL(k), m, xk, ldx, m, nrhs, ldl, true));
+    TLR_TRY(apply_inv(k, true));
     const int Rk = h->R[k];
     if (Rk == 0) continue;
     GemmBatch t(true, false), v(false, false);

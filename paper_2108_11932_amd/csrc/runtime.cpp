@@ -1,5 +1,6 @@
 // Runtime pieces of the TLR library: error text, device memory, descriptor
 // staging, batched GEMM launches and the dense tile operations.
+#include <algorithm>
 #include <cstdarg>
 
 #include "host.h"
@@ -90,7 +91,8 @@ void Staging::release(Mem& mem) {
   cap = used = 0;
 }
 
-tlr_status Staging::upload(Handle* h, const void* data, size_t bytes, void** dptr) {
+tlr_status Staging::upload(Handle* h, const void* data, size_t bytes, void** dptr,
+                           hipStream_t s) {
   const size_t need = (bytes + 255) & ~(size_t)255;
   if (used + need > cap) {
     TLR_TRY(h->sync());
@@ -101,7 +103,8 @@ tlr_status Staging::upload(Handle* h, const void* data, size_t bytes, void** dpt
     }
   }
   std::memcpy(host + used, data, bytes);
-  TLR_HIP(hipMemcpyAsync(dev + used, host + used, bytes, hipMemcpyHostToDevice, h->stream));
+  TLR_HIP(hipMemcpyAsync(dev + used, host + used, bytes, hipMemcpyHostToDevice,
+                         s ? s : h->stream));
   *dptr = dev + used;
   used += need;
   return TLR_OK;
@@ -111,74 +114,244 @@ tlr_status Staging::upload(Handle* h, const void* data, size_t bytes, void** dpt
 
 tlr_status tlr_matrix_s::sync() {
   TLR_HIP(hipStreamSynchronize(stream));
+  if (side) TLR_HIP(hipStreamSynchronize(side));
   stage.used = 0;
+  return TLR_OK;
+}
+
+tlr_status tlr_matrix_s::sync_main() {
+  TLR_HIP(hipStreamSynchronize(stream));
+  return TLR_OK;
+}
+
+tlr_status tlr_matrix_s::init_streams() {
+  if (!side) {
+    TLR_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    TLR_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    TLR_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  }
+  return TLR_OK;
+}
+
+tlr_status tlr_matrix_s::pinned_ints(size_t n, int** p) {
+  if (n > pin_back_n) {
+    if (pin_back) (void)hipHostFree(pin_back);
+    pin_back = nullptr;
+    pin_back_n = 0;
+    if (hipHostMalloc((void**)&pin_back, sizeof(int) * n, hipHostMallocDefault) != hipSuccess) {
+      pin_back = nullptr;
+      tlr::set_error("pinned host allocation failed");
+      return TLR_ERR_OOM;
+    }
+    pin_back_n = n;
+  }
+  *p = pin_back;
   return TLR_OK;
 }
 
 namespace tlr {
 
 // ---------------------------------------------------------------- GEMM batch
-tlr_status GemmBatch::run(Handle* h) {
-  if (d.empty()) return TLR_OK;
+tlr_status GemmBatch::run(Handle* h, hipStream_t s) {
+  Plan p(h, s);
+  p.gemm(*this);
+  return p.run();
+}
+
+tlr_status SegBatch::run(Handle* h, hipStream_t s) {
+  Plan p(h, s);
+  p.seg(*this);
+  return p.run();
+}
+
+// ---------------------------------------------------------------- plans
+Plan::Plan(Handle* h_, hipStream_t s_) : h(h_), s(s_ ? s_ : h_->stream) {}
+
+size_t Plan::stage(const void* p, size_t n) {
+  const size_t off = blob.size();
+  const size_t pad = (n + 255) & ~(size_t)255;
+  blob.resize(off + pad);
+  if (n) std::memcpy(blob.data() + off, p, n);
+  return off;
+}
+
+void Plan::launch(size_t off, std::function<hipError_t(const char*)> f) {
+  steps.push_back([off, f](const char* base) { return f(base + off); });
+}
+
+void Plan::launch(std::function<hipError_t()> f) {
+  steps.push_back([f](const char*) { return f(); });
+}
+
+static void build_map(const GemmBatch& b, std::vector<BlockMap>* map, int* bn) {
   int maxn = 0;
-  for (const auto& g : d) maxn = g.N > maxn ? g.N : maxn;
-  const int bn = gemm_tile_n(maxn);
-  std::vector<BlockMap> map;
-  map.reserve(d.size() * 4);
-  for (size_t i = 0; i < d.size(); ++i) {
-    const int tiles = ((d[i].M + 63) / 64) * ((d[i].N + bn - 1) / bn);
-    for (int t = 0; t < tiles; ++t) map.push_back(BlockMap{(int)i, t});
+  for (const auto& g : b.d) maxn = g.N > maxn ? g.N : maxn;
+  int TM = 64;
+  gemm_tile_shape(b.ta, b.tb, maxn, &TM, bn);
+  for (size_t i = 0; i < b.d.size(); ++i) {
+    const int tm = (b.d[i].M + TM - 1) / TM, tn = (b.d[i].N + *bn - 1) / *bn;
+    for (int t = 0; t < tm * tn; ++t) {
+      if ((b.d[i].flags & GEMM_LOWER_C) && (t / tm) * *bn >= (t % tm) * TM + TM) continue;
+      map->push_back(BlockMap{(int)i, t});
+    }
   }
-  void* dd = nullptr;
-  void* dm = nullptr;
-  TLR_TRY(h->stage.upload(h, d.data(), d.size() * sizeof(GemmDesc), &dd));
-  TLR_TRY(h->stage.upload(h, map.data(), map.size() * sizeof(BlockMap), &dm));
-  TLR_HIP(launch_gemm_batched((const GemmDesc*)dd, (const BlockMap*)dm, (int)map.size(), ta, tb,
-                              bn, h->stream));
+}
+
+void Plan::gemm(const GemmBatch& b) {
+  if (b.d.empty()) return;
+  std::vector<BlockMap> map;
+  int bn = 16;
+  build_map(b, &map, &bn);
+  const size_t od = stage(b.d.data(), b.d.size() * sizeof(GemmDesc));
+  const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
+  const int nblk = (int)map.size();
+  const bool ta = b.ta, tb = b.tb;
+  hipStream_t st = s;
+  steps.push_back([=](const char* base) {
+    return launch_gemm_batched((const GemmDesc*)(base + od), (const BlockMap*)(base + om), nblk, ta,
+                               tb, bn, st);
+  });
+  flops += b.flops;
+}
+
+void Plan::seg(const SegBatch& b) {
+  if (b.d.empty()) return;
+  int maxn = 0;
+  std::vector<BlockMap> map;
+  for (size_t i = 0; i < b.d.size(); ++i) {
+    maxn = b.d[i].N > maxn ? b.d[i].N : maxn;
+    for (int t = 0; t < (b.d[i].M + 63) / 64; ++t) map.push_back(BlockMap{(int)i, t});
+  }
+  const size_t od = stage(b.d.data(), b.d.size() * sizeof(SegDesc));
+  const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
+  const int nblk = (int)map.size();
+  hipStream_t st = s;
+  steps.push_back([=](const char* base) {
+    return launch_sample_nn((const SegDesc*)(base + od), (const BlockMap*)(base + om), nblk, maxn, st);
+  });
+  flops += b.flops;
+}
+
+tlr_status Plan::run() {
+  const char* base = nullptr;
+  if (!blob.empty()) {
+    void* dp = nullptr;
+    TLR_TRY(h->stage.upload(h, blob.data(), blob.size(), &dp, s));
+    base = (const char*)dp;
+  }
+  for (auto& f : steps) TLR_HIP(f(base));
+  steps.clear();
+  blob.clear();
   return TLR_OK;
 }
 
 // ---------------------------------------------------------------- dense tiles
 static constexpr int NBP = 64;
 
-tlr_status dense_potrf(Handle* h, double* A, int lda, int m, int row_base) {
-  for (int p0 = 0; p0 < m; p0 += NBP) {
-    const int w = m - p0 < NBP ? m - p0 : NBP;
-    TLR_HIP(launch_potrf_panel(A, lda, m, p0, w, h->d_info, row_base, h->stream));
-    const int rem = m - p0 - w;
-    if (rem > 0) {
-      GemmBatch g(false, true);
-      const double* l21 = A + (p0 + w) + (size_t)p0 * lda;
-      g.add(rem, rem, w, l21, lda, l21, lda, A + (p0 + w) + (size_t)(p0 + w) * lda, lda, -1.0, 1.0);
-      TLR_TRY(g.run(h));
-    }
+// Off-diagonal blocks of the inverse of a lower triangular m x m matrix L
+// whose 64 x 64 diagonal blocks are already inverted in Linv:
+// [A 0; B C]^{-1} = [A^{-1} 0; -C^{-1} B A^{-1}  C^{-1}], applied bottom-up
+// over a binary split of the block rows; nodes of one level are batched.
+static tlr_status inverse_assemble(Handle* h, const double* L, int ldl, int m, double* Linv,
+                                   hipStream_t s) {
+  struct Node {
+    int lo, mid, hi;
+  };
+  std::vector<std::vector<Node>> levels;
+  std::vector<std::pair<std::pair<int, int>, int>> stack = {{{0, m}, 0}};
+  while (!stack.empty()) {
+    auto it = stack.back();
+    stack.pop_back();
+    const int lo = it.first.first, hi = it.first.second, dep = it.second;
+    if (hi - lo <= NBP) continue;
+    const int nblk = (hi - lo + NBP - 1) / NBP;
+    const int mid = lo + ((nblk + 1) / 2) * NBP;
+    if ((int)levels.size() <= dep) levels.resize(dep + 1);
+    levels[dep].push_back(Node{lo, mid, hi});
+    stack.push_back({{lo, mid}, dep + 1});
+    stack.push_back({{mid, hi}, dep + 1});
   }
-  TLR_HIP(launch_zero_upper(A, lda, m, h->stream));
+  if (levels.empty()) return TLR_OK;
+  Work& w = h->ws;
+  if (w.dW.cap < sizeof(double) * (size_t)m * m) {
+    TLR_HIP(hipStreamSynchronize(s));
+    TLR_TRY(w.dW.ensure(h->mem, sizeof(double) * (size_t)m * m));
+  }
+  double* W = w.dW.as<double>();
+  for (int dep = (int)levels.size() - 1; dep >= 0; --dep) {
+    GemmBatch g1(false, false), g2(false, false);
+    for (const Node& n : levels[dep]) {
+      const int a = n.mid - n.lo, c = n.hi - n.mid;
+      // W = B A^{-1}
+      g1.add(c, a, a, L + n.mid + (size_t)n.lo * ldl, ldl, Linv + n.lo + (size_t)n.lo * m, m,
+             W + n.mid + (size_t)n.lo * m, m, 1.0, 0.0);
+      // X21 = -C^{-1} W
+      g2.add(c, a, c, Linv + n.mid + (size_t)n.mid * m, m, W + n.mid + (size_t)n.lo * m, m,
+             Linv + n.mid + (size_t)n.lo * m, m, -1.0, 0.0, GEMM_TRIL_A);
+    }
+    TLR_TRY(g1.run(h, s));
+    TLR_TRY(g2.run(h, s));
+  }
   return TLR_OK;
 }
 
-tlr_status dense_ldlt(Handle* h, double* A, int lda, int m, double* d, int row_base) {
+static tlr_status dense_factor(Handle* h, bool chol, double* A, int lda, int m, double* d,
+                               int row_base, double* Linv, hipStream_t s) {
   Work& w = h->ws;
-  TLR_TRY(w.tol.ensure(h->mem, sizeof(double)));
-  TLR_TRY(w.dscale.ensure(h->mem, sizeof(double) * (size_t)m * NBP));
-  TLR_HIP(launch_pivot_tol(A, lda, m, w.tol.as<double>(), h->stream));
-  double* W = w.dscale.as<double>();
+  const size_t need = sizeof(double) * (size_t)m * NBP;
+  if (w.dW.cap < need || w.dtol.cap < 256) {
+    TLR_HIP(hipStreamSynchronize(s));
+    TLR_TRY(w.dW.ensure(h->mem, std::max(need, sizeof(double) * (size_t)m * m)));
+    TLR_TRY(w.dtol.ensure(h->mem, 256));
+  }
+  TLR_HIP(hipMemsetAsync(Linv, 0, sizeof(double) * (size_t)m * m, s));
+  if (!chol) TLR_HIP(launch_pivot_tol(A, lda, m, w.dtol.as<double>(), s));
+  double* W = w.dW.as<double>();
   for (int p0 = 0; p0 < m; p0 += NBP) {
     const int wd = m - p0 < NBP ? m - p0 : NBP;
-    TLR_HIP(launch_ldlt_panel(A, lda, m, p0, wd, d, W, m, h->d_info, row_base, w.tol.as<double>(),
-                              h->stream));
+    double* inv = Linv + p0 + (size_t)p0 * m;
+    TLR_HIP(launch_diag_block(chol, A, lda, p0, wd, inv, m, d, h->d_info, row_base,
+                              w.dtol.as<double>(), s));
     const int rem = m - p0 - wd;
-    if (rem > 0) {
-      GemmBatch g(false, true);
-      const double* l21 = A + (p0 + wd) + (size_t)p0 * lda;
-      g.add(rem, rem, wd, W, m, l21, lda, A + (p0 + wd) + (size_t)(p0 + wd) * lda, lda, -1.0, 1.0);
-      TLR_TRY(g.run(h));
+    if (rem <= 0) continue;
+    double* a21 = A + (p0 + wd) + (size_t)p0 * lda;
+    double* a22 = A + (p0 + wd) + (size_t)(p0 + wd) * lda;
+    if (chol) {
+      // L21 = A21 L11^{-T}, in place: one column tile (wd <= 64), every
+      // workgroup reads its own rows before writing them
+      GemmBatch p(false, true);
+      p.add(rem, wd, wd, a21, lda, inv, m, a21, lda, 1.0, 0.0);
+      TLR_TRY(p.run(h, s));
+      GemmBatch t(false, true);
+      t.add(rem, rem, wd, a21, lda, a21, lda, a22, lda, -1.0, 1.0, GEMM_LOWER_C);
+      TLR_TRY(t.run(h, s));
+    } else {
+      // W21 = A21 L11^{-T} = L21 D, L21 = W21 D^{-1}, A22 -= W21 L21^T
+      GemmBatch p(false, true);
+      p.add(rem, wd, wd, a21, lda, inv, m, W, m, 1.0, 0.0);
+      TLR_TRY(p.run(h, s));
+      TLR_HIP(launch_scale_cols(W, m, a21, lda, d + p0, rem, wd, true, s));
+      GemmBatch t(false, true);
+      t.add(rem, rem, wd, W, m, a21, lda, a22, lda, -1.0, 1.0, GEMM_LOWER_C);
+      TLR_TRY(t.run(h, s));
     }
   }
-  TLR_HIP(launch_zero_upper(A, lda, m, h->stream));
-  return TLR_OK;
+  TLR_HIP(launch_zero_upper(A, lda, m, s));
+  return inverse_assemble(h, A, lda, m, Linv, s);
 }
 
+tlr_status dense_potrf(Handle* h, double* A, int lda, int m, int row_base, double* Linv,
+                       hipStream_t s) {
+  return dense_factor(h, true, A, lda, m, nullptr, row_base, Linv, s);
+}
+
+tlr_status dense_ldlt(Handle* h, double* A, int lda, int m, double* d, int row_base, double* Linv,
+                      hipStream_t s) {
+  return dense_factor(h, false, A, lda, m, d, row_base, Linv, s);
+}
+
+// Blocked triangular solve with the diagonal-block kernel (used by the
+// kernel-level entry point).
 tlr_status dense_trsm(Handle* h, const double* L, int ldl, double* B, int ldb, int m, int n,
                       bool unit, bool trans) {
   if (n <= 0) return TLR_OK;

@@ -1,0 +1,117 @@
+// Streaming product of the Schur-complement sampling (Eq. (2), Section 4.1):
+//
+//   C = beta C + A0 B0 + A1 B1,   A_s m x K_s column-major, B_s K_s x N,
+//
+// with N = the ARA block size (16 or 32).  For one tile of column k the two
+// segments are (U^A_ik, V^A_ik^T Omega) and (U_i*, -[G_ij P_j]_j), i.e. the
+// sampled input tile and the row panel of the factor against the reduced
+// test matrix; the same kernel performs the Gram-Schmidt update Y - Q C.
+// Every element of A is used once, so the kernel is bound by HBM: a
+// workgroup owns 64 rows of one problem, each wave 16 rows and the whole K of
+// both segments.  Lane (i, g) reads row i of A for the four columns
+// k0 + 4 g + t (128-byte runs per column over the 16 lanes of a group) and
+// rows k0 + 4 g + t of column i of B (32-byte runs); MFMA t consumes k0 +
+// 4 g + t on both operands.
+#include "tlr_internal.h"
+
+namespace tlr {
+
+typedef double d4s __attribute__((ext_vector_type(4)));
+
+namespace {
+
+template <int NF>
+__global__ __launch_bounds__(256) void k_sample_nn(const SegDesc* __restrict__ descs,
+                                                   const BlockMap* __restrict__ map) {
+  const BlockMap bm = map[blockIdx.x];
+  const SegDesc d = descs[bm.desc];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int r0 = bm.tile * 64 + wave * 16;
+  if (r0 >= d.M) return;
+  const int row = r0 + li;
+  const bool rok = row < d.M;
+
+  d4s acc[NF];
+#pragma unroll
+  for (int b = 0; b < NF; ++b) acc[b] = d4s{0.0, 0.0, 0.0, 0.0};
+
+#pragma unroll
+  for (int sg = 0; sg < 2; ++sg) {
+    const int K = d.K[sg];
+    if (K <= 0) continue;
+    const double* __restrict__ A = d.A[sg] + (rok ? row : 0);
+    const double* __restrict__ B = d.B[sg];
+    const size_t lda = d.lda[sg], ldb = d.ldb[sg];
+    const double* bcol[NF];
+    bool bok[NF];
+#pragma unroll
+    for (int b = 0; b < NF; ++b) {
+      const int c = b * 16 + li;
+      bok[b] = c < d.N;
+      bcol[b] = B + (size_t)(bok[b] ? c : 0) * ldb;
+    }
+    int k0 = 0;
+    // full 16-wide k steps
+    for (; k0 + 16 <= K; k0 += 16) {
+      const int kr = k0 + 4 * g;
+      double av[4], bv[NF][4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) av[t] = rok ? A[(size_t)(kr + t) * lda] : 0.0;
+#pragma unroll
+      for (int b = 0; b < NF; ++b)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bv[b][t] = bok[b] ? bcol[b][kr + t] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int b = 0; b < NF; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[b][t], acc[b], 0, 0, 0);
+    }
+    if (k0 < K) {
+      const int kr = k0 + 4 * g;
+      double av[4], bv[NF][4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) av[t] = (rok && kr + t < K) ? A[(size_t)(kr + t) * lda] : 0.0;
+#pragma unroll
+      for (int b = 0; b < NF; ++b)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bv[b][t] = (bok[b] && kr + t < K) ? bcol[b][kr + t] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int b = 0; b < NF; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[b][t], acc[b], 0, 0, 0);
+    }
+  }
+  // accumulator register r of lane (li, g) holds row r0 + g + 4 r, column li
+#pragma unroll
+  for (int b = 0; b < NF; ++b) {
+    const int c = b * 16 + li;
+    if (c >= d.N) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = r0 + g + 4 * r;
+      if (rr >= d.M) continue;
+      double* cp = d.C + rr + (size_t)c * d.ldc;
+      double v = acc[b][r];
+      if (d.beta != 0.0) v += d.beta * *cp;
+      *cp = v;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_sample_nn(const SegDesc* d, const BlockMap* map, int nblocks, int maxn,
+                            hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (maxn > 32) return hipErrorInvalidValue;
+  if (maxn <= 16)
+    hipLaunchKernelGGL((k_sample_nn<1>), dim3(nblocks), dim3(256), 0, s, d, map);
+  else
+    hipLaunchKernelGGL((k_sample_nn<2>), dim3(nblocks), dim3(256), 0, s, d, map);
+  return hipGetLastError();
+}
+
+}  // namespace tlr

@@ -22,8 +22,17 @@ struct GemmDesc {
   double* C;
   int M, N, K;
   int lda, ldb, ldc;
+  int flags;   // GEMM_* bits
   double alpha, beta;
 };
+// Only output tiles that reach the lower triangle (row >= col) are computed.
+constexpr int GEMM_LOWER_C = 1;
+// op(A) is lower triangular (k <= row): the K loop of a row tile stops at
+// its last row.
+constexpr int GEMM_TRIL_A = 2;
+// op(A) is upper triangular (k >= row): the K loop starts at the tile's
+// first row.
+constexpr int GEMM_TRIU_A = 4;
 
 // One entry per launched workgroup: x = descriptor index, y = output tile
 // index inside that descriptor (row tiles vary fastest).
@@ -35,21 +44,39 @@ struct BlockMap {
 // Host-side staging of a batched GEMM; builds the block map and launches.
 // trans_a / trans_b are uniform over the batch.
 int gemm_tile_n(int N);                     // BN chosen for a problem (16 or 64)
+// Output tile (rows x cols) of the kernel that runs a batch with these
+// transpositions and largest N; the block map enumerates tiles of this shape.
+void gemm_tile_shape(bool trans_a, bool trans_b, int maxn, int* tm, int* tn);
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, int nblocks,
                                bool trans_a, bool trans_b, int bn, hipStream_t s);
+
+// Two-segment product with a narrow right-hand side (N <= 32):
+// C = beta C + A[0] B[0] + A[1] B[1]; a segment with K = 0 is skipped.
+// The block map enumerates 64-row blocks of C (tile = row block).
+struct SegDesc {
+  const double* A[2];
+  const double* B[2];
+  int lda[2], ldb[2], K[2];
+  double* C;
+  int ldc, M, N;
+  double beta;
+};
+hipError_t launch_sample_nn(const SegDesc* d, const BlockMap* map, int nblocks, int maxn,
+                            hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Dense tile kernels (one m x m tile, m <= 4096)
 // ---------------------------------------------------------------------------
-// Panel step of the blocked right-looking Cholesky: factor the nbp x nbp
-// diagonal block at (p, p) and solve the rows below it.  info (device int)
-// receives the 1-based row of the first non-positive pivot (0 = none).
-hipError_t launch_potrf_panel(double* A, int lda, int m, int p, int nbp, int* info, int row_base,
-                              hipStream_t s);
-// Same for the unpivoted LDL^T: the unit lower factor overwrites A, the
-// pivots go to d, and W receives L21 * D (needed by the trailing update).
-hipError_t launch_ldlt_panel(double* A, int lda, int m, int p, int nbp, double* d, double* W,
-                             int ldw, int* info, int row_base, const double* tolp, hipStream_t s);
+// Factor the w x w (w <= 64) diagonal block at (p0, p0) of A in place
+// (Cholesky, or unit LDL^T with pivots into dvec[p0..]) and write the inverse
+// of its lower factor to Inv (ld ldi).  info (device int) receives the
+// 1-based row (row_base + p0 + j + 1) of the first failing pivot.
+hipError_t launch_diag_block(bool chol, double* A, int lda, int p0, int w, double* Inv, int ldi,
+                             double* dvec, int* info, int row_base, const double* tolp,
+                             hipStream_t s);
+// out(r, c) = in(r, c) * s[c] (or / s[c]).
+hipError_t launch_scale_cols(const double* in, int ldi, double* out, int ldo, const double* sc,
+                             int rows, int cols, bool inverse, hipStream_t s);
 // Diagonal-block step of the blocked triangular solve: X_p = L_pp^{-1} B_p
 // (or L_pp^{-T}), for all n columns of B.
 hipError_t launch_trsm_diag(const double* L, int ldl, double* B, int ldb, int p, int nbp, int n,
@@ -88,8 +115,10 @@ hipError_t launch_apply_rinv(const OrthDesc* d, int ntiles, int m, int bs, int p
 // Dynamic batching: stable compaction of the active list by the convergence
 // flags (flag[slot] != 0 removes the slot), then refill from the waiting
 // list.  counts[0] = active count in/out, counts[1] = waiting cursor.
+// When info is not NULL, counts[2] receives a copy of *info (status word
+// read back together with the active list).
 hipError_t launch_compact(int* act, int* counts, const int* flag, const int* waiting, int nwaiting,
-                          int s_max, hipStream_t s);
+                          int s_max, const int* info, hipStream_t s);
 // Rank sort of a column: order rows by rank descending, ties ascending row.
 hipError_t launch_sort_ranks(const int* ranks, const int* rows, int n, int* order, hipStream_t s);
 
