@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cov2d_131k")
+    ap.add_argument("--bs", type=int, default=0, help="ARA block size (0 = the workload's)")
     ap.add_argument("--cpu-sample", type=int, default=8192,
                     help="points of the leading block the CPU oracle factors (0 = skip)")
     a = ap.parse_args()
@@ -92,6 +93,8 @@ def main():
 
     torch.cuda.set_device(0)
     w = wl.standard(a.workload)
+    if a.bs:
+        w.bs = a.bs
     print("[bench] building %s on the GPU" % w.name, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     mat = tlr.TLRMatrix.compress_kernel(w.points, w.kernel, w.ell, w.diag_add, w.m, w.eps,

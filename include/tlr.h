@@ -82,8 +82,9 @@ typedef struct {
 
 /* Options of compression and factorization. */
 typedef struct {
-  int bs;                  /* ARA block size: samples per iteration (1..32); the
-                              paper uses 16 in 2D and 32 in 3D (Section 6) */
+  int bs;                  /* ARA block size: samples per iteration, one of
+                              1, 2, 4, 8, 16, 24, 32; the paper uses 16 in 2D
+                              and 32 in 3D (Section 6) */
   int eps_mode;            /* TLR_EPS_ABS (default) or TLR_EPS_REL */
   int precision;           /* TLR_FP64 */
   double shift;            /* factor A + shift * I (diagonal shift, Section 5.1);

@@ -63,7 +63,8 @@ tlr_status tlrk_randn(int rows, int cols, unsigned long long seed, unsigned k, u
  * (device, tile b at tiles + b m^2), Algorithm "Adaptive Randomized
  * Approximation": on return Q (device, count x m x m) holds orthonormal
  * bases and B (device, count x m x m) the projections B = A^T Q, so
- * A_b ~ Q_b B_b^T with ranks[b] columns; iters[b] = ARA iterations. */
+ * A_b ~ Q_b B_b^T with ranks[b] columns; iters[b] = ARA iterations.  bs is
+ * one of 1, 2, 4, 8, 16, 24, 32. */
 tlr_status tlrk_ara(int m, int count, const double* tiles, double tau, int bs, int r_min,
                     unsigned long long seed, double* Q, double* B, int* ranks, int* iters,
                     void* stream);

@@ -45,7 +45,8 @@ static tlr_status check_opts(const tlr_opts* in, tlr_opts* out) {
     *out = *in;
   else
     tlr_opts_default(out);
-  TLR_ARG(out->bs >= 1 && out->bs <= 32, "opts.bs must be in 1..32, got %d", out->bs);
+  TLR_ARG(orth_block_supported(out->bs), "opts.bs must be one of 1, 2, 4, 8, 16, 24, 32, got %d",
+          out->bs);
   TLR_ARG(out->eps_mode == TLR_EPS_ABS || out->eps_mode == TLR_EPS_REL, "opts.eps_mode invalid");
   TLR_ARG(out->precision == TLR_FP64, "opts.precision: only TLR_FP64 is supported");
   TLR_ARG(out->r_min >= 1 && out->r_min <= out->bs, "opts.r_min must be in 1..bs");

@@ -176,19 +176,34 @@ __global__ __launch_bounds__(256) void k_gram_dd(const OrthDesc* __restrict__ de
   }
 }
 
-// Sum of the partial Gram matrices into G (dd, full symmetric, LDS).
-__device__ void gram_sum(const OrthDesc& d, int bs, int nc, int nrb, dd (*G)[BS_MAX + 1]) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nc * nc; e += blockDim.x) {
-    const int a = e % nc, b = e / nc;
-    if (a > b) continue;
+// Sum of the partial Gram matrices into G (dd, full symmetric, LDS), one
+// entry of the upper triangle per lane and step.
+template <int BS>
+__device__ void gram_sum(const OrthDesc& d, int nc, int nrb, dd (*G)[BS_MAX + 1]) {
+  for (int e = threadIdx.x; e < BS * BS; e += 64) {
+    const int a = e % BS, b = e / BS;
+    if (a > b || b >= nc) continue;
     dd acc{0.0, 0.0};
     for (int rb = 0; rb < nrb; ++rb) {
-      const double* p = d.part + (size_t)rb * bs * bs * 2 + (a + b * bs) * 2;
+      const double* p = d.part + (size_t)rb * BS * BS * 2 + (a + b * BS) * 2;
       acc = dd_add(acc, dd{p[0], p[1]});
     }
     G[a][b] = acc;
     G[b][a] = acc;
+  }
+  __syncthreads();
+}
+
+// Inverse of the p x p upper triangular R (double) by columns: thread c
+// solves R x = e_c.  Ri must be zero-initialised.
+__device__ void upper_inverse(const double (*R)[BS_MAX + 1], double (*Ri)[BS_MAX + 1], int p) {
+  const int c = threadIdx.x;
+  if (c < p) {
+    for (int r = c; r >= 0; --r) {
+      double v = (r == c) ? 1.0 : 0.0;
+      for (int t = r + 1; t <= c; ++t) v -= R[r][t] * Ri[t][c];
+      Ri[r][c] = v / R[r][r];
+    }
   }
   __syncthreads();
 }
@@ -200,125 +215,150 @@ __device__ void gram_sum(const OrthDesc& d, int bs, int nc, int nrb, dd (*G)[BS_
 // column after removing the accepted directions) exceeds tau^2.  p accepted
 // pivots give Y_P = Q_new R with R p x p upper triangular.  The tile has
 // converged when at least r_min samples were left below tau, or the basis
-// has reached its capacity.  Writes the pivots, p, the inverse factor R^{-1}
-// (rounded to double), the new basis width and the convergence flag.
-__global__ __launch_bounds__(64) void k_pivchol(const OrthDesc* __restrict__ descs, int bs, int nrb,
+// has reached its capacity.  Writes the pivots, p, R^{-1}, the new basis
+// width and the convergence flag.
+//
+// One wave per tile.  Columns are never moved: step j picks the pivot by a
+// wave max-reduction over the remaining diagonal, every lane forms the
+// multipliers l_x = G[pv][x] / sqrt(G[pv][pv]) of its columns, and the Schur
+// update G[a][b] -= l_a l_b is spread over all lanes.  R in pivot order is
+// read off the stored multipliers at the end.
+template <int BS>
+__global__ __launch_bounds__(64) void k_pivchol(const OrthDesc* __restrict__ descs, int nrb,
                                                 double tau2, int r_min, int qcap) {
   __shared__ dd G[BS_MAX][BS_MAX + 1];
-  __shared__ dd R[BS_MAX][BS_MAX + 1];   // R[row][col], upper
-  __shared__ dd Ri[BS_MAX][BS_MAX + 1];  // inverse, upper
+  __shared__ double Lm[BS_MAX][BS_MAX + 1];  // Lm[j][x]: multiplier of column x at step j
+  __shared__ double R[BS_MAX][BS_MAX + 1];
+  __shared__ double Ri[BS_MAX][BS_MAX + 1];
+  __shared__ dd lrow[BS_MAX];
   __shared__ int perm[BS_MAX];
-  __shared__ int s_p, s_piv;
+  __shared__ int taken[BS_MAX];
   const OrthDesc d = descs[blockIdx.x];
-  const int tid = threadIdx.x;
-  gram_sum(d, bs, bs, nrb, G);
-  if (tid < bs) perm[tid] = tid;
-  for (int e = tid; e < BS_MAX * BS_MAX; e += blockDim.x) {
-    R[e % BS_MAX][e / BS_MAX] = dd{0.0, 0.0};
-    Ri[e % BS_MAX][e / BS_MAX] = dd{0.0, 0.0};
+  const int t = threadIdx.x;
+  gram_sum<BS>(d, BS, nrb, G);
+  if (t < BS) {
+    taken[t] = 0;
+    perm[t] = t;
   }
-  if (tid == 0) s_p = 0;
+  for (int e = t; e < BS_MAX * (BS_MAX + 1); e += 64) {
+    (&R[0][0])[e] = 0.0;
+    (&Ri[0][0])[e] = 0.0;
+    (&Lm[0][0])[e] = 0.0;
+  }
   __syncthreads();
   const int qold = d.qold;
   const int room = max(0, qcap - qold);
-  for (int j = 0; j < bs; ++j) {
-    if (tid == 0) {
-      int best = j;
-      double bv = G[j][j].hi;
-      for (int c = j + 1; c < bs; ++c)
-        if (G[c][c].hi > bv) { bv = G[c][c].hi; best = c; }
-      s_piv = (bv > tau2 && j < room) ? best : -1;
+  int p = 0;
+  for (int j = 0; j < BS && j < room; ++j) {
+    // pivot: largest remaining diagonal (ties: lowest column)
+    double v = -1.0;
+    int idx = BS;
+    if (t < BS && !taken[t]) {
+      v = G[t][t].hi;
+      idx = t;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off);
+      const int oi = __shfl_xor(idx, off);
+      if (ov > v || (ov == v && oi < idx)) {
+        v = ov;
+        idx = oi;
+      }
+    }
+    if (!(v > tau2)) break;
+    const int pv = idx;
+    const dd rinv = dd_div(dd{1.0, 0.0}, dd_sqrt(G[pv][pv]));
+    __syncthreads();
+    if (t < BS) {
+      dd l{0.0, 0.0};
+      if (!taken[t]) l = dd_mul(G[pv][t], rinv);
+      lrow[t] = l;
+      Lm[j][t] = l.hi + l.lo;
     }
     __syncthreads();
-    const int pv = s_piv;
-    if (pv < 0) break;
-    // symmetric swap of j and pv in G (rows and columns), and in R's
-    // already computed rows
-    if (pv != j) {
-      for (int c = tid; c < bs; c += blockDim.x) {
-        const dd t = G[j][c]; G[j][c] = G[pv][c]; G[pv][c] = t;
-      }
-      __syncthreads();
-      for (int c = tid; c < bs; c += blockDim.x) {
-        const dd t = G[c][j]; G[c][j] = G[c][pv]; G[c][pv] = t;
-      }
-      for (int r = tid; r < j; r += blockDim.x) {
-        const dd t = R[r][j]; R[r][j] = R[r][pv]; R[r][pv] = t;
-      }
-      if (tid == 0) { const int t = perm[j]; perm[j] = perm[pv]; perm[pv] = t; }
-      __syncthreads();
+    if (t == 0) {
+      taken[pv] = 1;
+      perm[j] = pv;
     }
-    if (tid == 0) R[j][j] = dd_sqrt(G[j][j]);
-    __syncthreads();
-    for (int c = j + 1 + tid; c < bs; c += blockDim.x) R[j][c] = dd_div(G[j][c], R[j][j]);
-    __syncthreads();
-    for (int e = tid; e < bs * bs; e += blockDim.x) {
-      const int a = e % bs, b = e / bs;
-      if (a > j && b > j) G[a][b] = dd_sub(G[a][b], dd_mul(R[j][a], R[j][b]));
+    // Schur complement of the remaining columns
+    for (int e = t; e < BS * BS; e += 64) {
+      const int a = e % BS, b = e / BS;
+      if (a <= b) {
+        const dd nv = dd_sub(G[a][b], dd_mul(lrow[a], lrow[b]));
+        G[a][b] = nv;
+        G[b][a] = nv;
+      }
     }
-    if (tid == 0) s_p = j + 1;
     __syncthreads();
+    p = j + 1;
   }
-  const int p = s_p;
-  // R^{-1} (upper): column c solves R x = e_c by back substitution
-  for (int c = tid; c < p; c += blockDim.x) {
-    for (int r = c; r >= 0; --r) {
-      dd v = (r == c) ? dd{1.0, 0.0} : dd{0.0, 0.0};
-      for (int t = r + 1; t <= c; ++t) v = dd_sub(v, dd_mul(R[r][t], Ri[t][c]));
-      Ri[r][c] = dd_div(v, R[r][r]);
-    }
+  // complete the permutation with the columns that were not accepted
+  if (t == 0) {
+    int nxt = p;
+    for (int c = 0; c < BS; ++c)
+      if (!taken[c]) perm[nxt++] = c;
   }
   __syncthreads();
-  for (int e = tid; e < bs * bs; e += blockDim.x) {
-    const int r = e % bs, c = e / bs;
-    d.rfac[r + c * bs] = (r < p && c < p) ? Ri[r][c].hi + Ri[r][c].lo : 0.0;
+  // R in pivot order: R[j][i] = Lm[j][perm[i]] for i >= j
+  for (int e = t; e < BS * BS; e += 64) {
+    const int jj = e % BS, i = e / BS;
+    if (jj < p && i < p && i >= jj) R[jj][i] = Lm[jj][perm[i]];
   }
-  if (tid < bs) d.piv[tid] = perm[tid];
-  if (tid == 0) {
-    d.piv[bs] = p;
+  __syncthreads();
+  upper_inverse(R, Ri, p);
+  for (int e = t; e < BS * BS; e += 64) {
+    const int r = e % BS, c = e / BS;
+    d.rfac[r + c * BS] = (r < p && c < p) ? Ri[r][c] : 0.0;
+  }
+  if (t < BS) d.piv[t] = perm[t];
+  if (t == 0) {
+    d.piv[BS] = p;
     *d.q = qold + p;
-    const bool conv = (p <= bs - r_min) || (qold + p >= qcap);
+    const bool conv = (p <= BS - r_min) || (qold + p >= qcap);
     *d.flag = conv ? 1 : 0;
   }
 }
 
 // Unpivoted Cholesky of the Gram matrix of the new columns (pass 2); the
 // columns are already orthonormal to about u * cond, so the Gram is close to
-// the identity.  Writes R^{-1} to rfac.
-__global__ __launch_bounds__(64) void k_chol_small(const OrthDesc* __restrict__ descs, int bs,
-                                                   int nrb) {
+// the identity.  Writes R^{-1} to rfac.  One wave per tile.
+template <int BS>
+__global__ __launch_bounds__(64) void k_chol_small(const OrthDesc* __restrict__ descs, int nrb) {
   __shared__ dd G[BS_MAX][BS_MAX + 1];
-  __shared__ dd Ri[BS_MAX][BS_MAX + 1];
+  __shared__ double R[BS_MAX][BS_MAX + 1];
+  __shared__ double Ri[BS_MAX][BS_MAX + 1];
+  __shared__ dd lrow[BS_MAX];
   const OrthDesc d = descs[blockIdx.x];
-  const int tid = threadIdx.x;
-  const int p = d.piv[bs];
-  gram_sum(d, bs, p, nrb, G);
-  // in-place right-looking Cholesky: upper factor R in G's upper triangle
-  for (int j = 0; j < p; ++j) {
-    if (tid == 0) {
-      G[j][j] = dd_sqrt(G[j][j]);
-      if (G[j][j].hi == 0.0) G[j][j] = dd{1.0, 0.0};
-    }
-    __syncthreads();
-    for (int c = j + 1 + tid; c < p; c += blockDim.x) G[j][c] = dd_div(G[j][c], G[j][j]);
-    __syncthreads();
-    for (int e = tid; e < p * p; e += blockDim.x) {
-      const int a = e % p, b = e / p;
-      if (a > j && b >= a) G[a][b] = dd_sub(G[a][b], dd_mul(G[j][a], G[j][b]));
-    }
-    __syncthreads();
-  }
-  for (int c = tid; c < p; c += blockDim.x) {
-    for (int r = c; r >= 0; --r) {
-      dd v = (r == c) ? dd{1.0, 0.0} : dd{0.0, 0.0};
-      for (int t = r + 1; t <= c; ++t) v = dd_sub(v, dd_mul(G[r][t], Ri[t][c]));
-      Ri[r][c] = dd_div(v, G[r][r]);
-    }
+  const int t = threadIdx.x;
+  const int p = d.piv[BS];
+  gram_sum<BS>(d, p, nrb, G);
+  for (int e = t; e < BS_MAX * (BS_MAX + 1); e += 64) {
+    (&R[0][0])[e] = 0.0;
+    (&Ri[0][0])[e] = 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < bs * bs; e += blockDim.x) {
-    const int r = e % bs, c = e / bs;
-    d.rfac[r + c * bs] = (r < p && c < p && r <= c) ? Ri[r][c].hi + Ri[r][c].lo : 0.0;
+  for (int j = 0; j < p; ++j) {
+    dd gj = dd_sqrt(G[j][j]);
+    if (gj.hi == 0.0) gj = dd{1.0, 0.0};
+    const dd rinv = dd_div(dd{1.0, 0.0}, gj);
+    __syncthreads();
+    if (t >= j && t < p) {
+      const dd l = (t == j) ? gj : dd_mul(G[j][t], rinv);
+      lrow[t] = l;
+      R[j][t] = l.hi + l.lo;
+    }
+    __syncthreads();
+    for (int e = t; e < BS * BS; e += 64) {
+      const int a = e % BS, b = e / BS;
+      if (a > j && a <= b && b < p) G[a][b] = dd_sub(G[a][b], dd_mul(lrow[a], lrow[b]));
+    }
+    __syncthreads();
+  }
+  upper_inverse(R, Ri, p);
+  for (int e = t; e < BS * BS; e += 64) {
+    const int r = e % BS, c = e / BS;
+    d.rfac[r + c * BS] = (r < p && c < p && r <= c) ? Ri[r][c] : 0.0;
   }
 }
 
@@ -446,18 +486,34 @@ hipError_t launch_gram_dd(const OrthDesc* d, int ntiles, int m, int bs, int pass
   return hipGetLastError();
 }
 
+#define TLR_BS_DISPATCH(bs, KERNEL, ...)                                          \
+  switch (bs) {                                                                   \
+    case 16: hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__); break;                  \
+    case 32: hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__); break;                  \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__); break;                    \
+    case 24: hipLaunchKernelGGL(KERNEL<24>, __VA_ARGS__); break;                  \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                     \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                     \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                     \
+    default: return hipErrorInvalidValue;                                         \
+  }
+
+bool orth_block_supported(int bs) {
+  return bs == 1 || bs == 2 || bs == 4 || bs == 8 || bs == 16 || bs == 24 || bs == 32;
+}
+
 hipError_t launch_pivchol(const OrthDesc* d, int ntiles, int m, int bs, double tau2, int r_min,
                           int qcap, hipStream_t s) {
-  if (bs > BS_MAX) return hipErrorInvalidValue;
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pivchol, dim3(ntiles), dim3(64), 0, s, d, bs, gram_row_blocks(m), tau2,
-                     r_min, qcap);
+  const int nrb = gram_row_blocks(m);
+  TLR_BS_DISPATCH(bs, k_pivchol, dim3(ntiles), dim3(64), 0, s, d, nrb, tau2, r_min, qcap);
   return hipGetLastError();
 }
 
 hipError_t launch_chol_small(const OrthDesc* d, int ntiles, int m, int bs, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_chol_small, dim3(ntiles), dim3(64), 0, s, d, bs, gram_row_blocks(m));
+  const int nrb = gram_row_blocks(m);
+  TLR_BS_DISPATCH(bs, k_chol_small, dim3(ntiles), dim3(64), 0, s, d, nrb);
   return hipGetLastError();
 }
 

@@ -4,8 +4,8 @@
 //
 // The diagonal tile factorization is the "chol" (Algorithm "Left Looking TLR
 // Cholesky") and "ldl" (Algorithm "Left Looking TLR LDL^T", unpivoted with
-// scalar pivots) step of the paper.  The tile is factored by blocks of 64
-// columns: one workgroup factors the 64 x 64 diagonal block in LDS and also
+// scalar pivots) step of the paper.  The tile is factored by blocks of 32
+// columns: one wave factors the 32 x 32 diagonal block in registers and also
 // writes its inverse; the panel below (L21 = A21 L11^{-T}) and the trailing
 // update then run as MFMA GEMMs.  The block inverses are reused to assemble
 // L_kk^{-1}, so the batched triangular solve of a column ("batchTrsm", one
@@ -16,89 +16,101 @@ namespace tlr {
 
 namespace {
 
-constexpr int NB = 64;   // block size of the blocked factorizations
+constexpr int NB = 64;   // block size of the blocked triangular solve
+constexpr int ND = 32;   // diagonal block of the blocked factorizations
 
-// Factor the w x w lower block S (LDS, S[c][r] = block(r, c)) in LDL^T form
-// with unscaled columns: after step j, S[j][r] (r > j) holds l_rj * d_j and
-// d[j] the pivot.  One barrier per step.  Pivots failing `bad` are reported
-// and replaced by 1 so no NaN spreads.
+// Factor the diagonal block (p0, p0) of A (w <= 32) in place: Cholesky, or
+// unit LDL^T with the pivots in dvec[p0..]; write the inverse of the lower
+// factor into Inv (ld ldi).
+//
+// One wave; lanes 0..31 work.  Lane r holds row r of the block in registers
+// (rows and columns beyond w are the identity, which leaves the real part
+// unchanged).  Step j of the factorization needs column j, i.e. register j
+// of every lane: each lane picks it out with a select chain (constant
+// register indices), writes it to LDS, and reads the column back as uniform
+// broadcasts.  Rows are kept in unscaled LDL^T form (row[p] = l_rp d_p).
+// The inverse X = L^{-1} is a column-oriented forward substitution on the
+// identity, row i of X on lane i, with row p of X broadcast through LDS.
 template <bool CHOL>
-__device__ void block_factor(double (*S)[NB + 1], double* d, int w, int* info, int row_base,
-                             double tol, bool report) {
-  const int tid = threadIdx.x;
-  for (int j = 0; j < w; ++j) {
-    __syncthreads();
-    double dj = S[j][j];
-    const bool bad = CHOL ? !(dj > 0.0) : !(fabs(dj) > tol);
-    if (bad) {
-      if (report && tid == 0) atomicCAS(info, 0, row_base + j + 1);
-      dj = 1.0;
-    }
-    if (tid == 0) d[j] = dj;
-    const double inv = 1.0 / dj;
-    const int nt = w - j - 1;
-    for (int e = tid; e < nt * nt; e += blockDim.x) {
-      const int r = j + 1 + e % nt, c = j + 1 + e / nt;
-      if (c <= r) S[c][r] -= S[j][r] * S[j][c] * inv;
-    }
-  }
-  __syncthreads();
-}
-
-// X = L^{-1} for the w x w lower triangle L held as S (unscaled LDL^T form
-// with pivots d; CHOL: L = unit(S) * sqrt(D), else L = unit(S)).
-// Column-oriented forward substitution on the identity, two barriers per step.
-template <bool CHOL>
-__device__ void block_inverse(double (*S)[NB + 1], const double* d, double (*X)[NB + 1], int w) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < w * w; e += blockDim.x) X[e / w][e % w] = (e % w == e / w) ? 1.0 : 0.0;
-  for (int j = 0; j < w; ++j) {
-    __syncthreads();
-    // row j of X: divide by the diagonal of L
-    const double djj = CHOL ? sqrt(d[j]) : 1.0;
-    if (CHOL)
-      for (int c = tid; c <= j; c += blockDim.x) X[c][j] /= djj;
-    __syncthreads();
-    // rows i > j: X[i, c] -= L[i][j] X[j, c], c <= j
-    const int nr = w - j - 1;
-    for (int e = tid; e < nr * (j + 1); e += blockDim.x) {
-      const int i = j + 1 + e % nr, c = e / nr;
-      const double lij = CHOL ? S[j][i] / sqrt(d[j]) : S[j][i] / d[j];
-      X[c][i] -= lij * X[c][j];
-    }
-  }
-  __syncthreads();
-}
-
-// Factor the diagonal block (p0, p0) of A (w <= 64) and write L11 back into
-// A, its inverse into Inv (ld ldi), and for LDL^T the pivots into dvec.
-template <bool CHOL>
-__global__ __launch_bounds__(256) void k_diag_block(double* A, int lda, int p0, int w,
-                                                    double* Inv, int ldi, double* dvec, int* info,
-                                                    int row_base, const double* tolp) {
-  __shared__ double S[NB][NB + 1];
-  __shared__ double X[NB][NB + 1];
-  __shared__ double d[NB];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < w * w; e += blockDim.x) {
-    const int r = e % w, c = e / w;
-    S[c][r] = (c <= r) ? A[(p0 + r) + (size_t)(p0 + c) * lda] : 0.0;
+__global__ __launch_bounds__(64) void k_diag_block(double* A, int lda, int p0, int w, double* Inv,
+                                                   int ldi, double* dvec, int* info, int row_base,
+                                                   const double* tolp) {
+  __shared__ double col[ND];
+  __shared__ double dsh[ND];
+  __shared__ double Ls[ND][ND + 1];   // Ls[p][i] = L(i, p)
+  const int r = threadIdx.x & (ND - 1);
+  const bool act = threadIdx.x < ND;
+  double row[ND];
+#pragma unroll
+  for (int c = 0; c < ND; ++c) {
+    double v = (r == c) ? 1.0 : 0.0;
+    if (act && r < w && c < w && c <= r) v = A[(p0 + r) + (size_t)(p0 + c) * lda];
+    row[c] = v;
   }
   const double tol = CHOL ? 0.0 : *tolp;
-  block_factor<CHOL>(S, d, w, info, row_base + p0, tol, true);
-  block_inverse<CHOL>(S, d, X, w);
-  for (int e = tid; e < w * w; e += blockDim.x) {
-    const int r = e % w, c = e / w;
-    double l;
-    if (CHOL)
-      l = (r == c) ? sqrt(d[c]) : (r > c ? S[c][r] / sqrt(d[c]) : 0.0);
-    else
-      l = (r == c) ? 1.0 : (r > c ? S[c][r] / d[c] : 0.0);
-    A[(p0 + r) + (size_t)(p0 + c) * lda] = l;
-    Inv[r + (size_t)c * ldi] = (r >= c) ? X[c][r] : 0.0;
+  int bad_row = 0;
+#pragma nounroll
+  for (int j = 0; j < ND; ++j) {
+    double rj = 0.0;
+#pragma unroll
+    for (int c = 0; c < ND; ++c) rj = (c == j) ? row[c] : rj;
+    if (act) col[r] = rj;
+    __syncthreads();
+    double dj = col[j];
+    const bool bad = CHOL ? !(dj > 0.0) : !(fabs(dj) > tol);
+    if (bad) {
+      if (j < w && bad_row == 0) bad_row = row_base + p0 + j + 1;
+      dj = 1.0;
+    }
+    if (threadIdx.x == 0) dsh[j] = dj;
+    const double mr = rj / dj;   // l_rj
+#pragma unroll
+    for (int c = 0; c < ND; ++c) {
+      const double v = row[c] - mr * col[c];
+      row[c] = (c > j) ? v : row[c];
+    }
+    __syncthreads();
   }
-  if (!CHOL)
-    for (int j = tid; j < w; j += blockDim.x) dvec[p0 + j] = d[j];
+  if (bad_row && threadIdx.x == 0) atomicCAS(info, 0, bad_row);
+  // L(r, p) to LDS and to A
+#pragma unroll
+  for (int p = 0; p < ND; ++p) {
+    double l;
+    if (CHOL) {
+      const double sq = sqrt(dsh[p]);
+      l = (r == p) ? sq : (r > p ? row[p] / sq : 0.0);
+    } else {
+      l = (r == p) ? 1.0 : (r > p ? row[p] / dsh[p] : 0.0);
+    }
+    if (act) Ls[p][r] = l;
+    if (act && r < w && p < w) A[(p0 + r) + (size_t)(p0 + p) * lda] = l;
+  }
+  if (!CHOL && act && r < w) dvec[p0 + r] = dsh[r];
+  __syncthreads();
+  // X = L^{-1}: lane p finishes row p (divides by L(p, p)) and broadcasts
+  // it; rows i > p lose L(i, p) X(p, :)  (X(p, c) = 0 for c > p)
+  double x[ND];
+#pragma unroll
+  for (int c = 0; c < ND; ++c) x[c] = (r == c) ? 1.0 : 0.0;
+#pragma nounroll
+  for (int p = 0; p < ND; ++p) {
+    if (act && r == p) {
+      const double inv = 1.0 / Ls[p][p];
+#pragma unroll
+      for (int c = 0; c < ND; ++c) {
+        x[c] *= inv;
+        col[c] = x[c];
+      }
+    }
+    __syncthreads();
+    const double lip = (act && r > p) ? Ls[p][r] : 0.0;
+#pragma unroll
+    for (int c = 0; c < ND; ++c) x[c] -= lip * col[c];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < ND; ++c)
+    if (act && r < w && c < w) Inv[r + (size_t)c * ldi] = (r >= c) ? x[c] : 0.0;
 }
 
 // out(r, c) = in(r, c) * s[c] or / s[c] (column scaling, LDL^T panels).
@@ -154,15 +166,17 @@ __global__ __launch_bounds__(64) void k_trsm_diag(const double* L, int ldl, doub
 
 }  // namespace
 
+int diag_block_size() { return ND; }
+
 hipError_t launch_diag_block(bool chol, double* A, int lda, int p0, int w, double* Inv, int ldi,
                              double* dvec, int* info, int row_base, const double* tolp,
                              hipStream_t s) {
-  if (w <= 0 || w > NB) return hipErrorInvalidValue;
+  if (w <= 0 || w > ND) return hipErrorInvalidValue;
   if (chol)
-    hipLaunchKernelGGL(k_diag_block<true>, dim3(1), dim3(256), 0, s, A, lda, p0, w, Inv, ldi, dvec,
+    hipLaunchKernelGGL(k_diag_block<true>, dim3(1), dim3(64), 0, s, A, lda, p0, w, Inv, ldi, dvec,
                        info, row_base, tolp);
   else
-    hipLaunchKernelGGL(k_diag_block<false>, dim3(1), dim3(256), 0, s, A, lda, p0, w, Inv, ldi,
+    hipLaunchKernelGGL(k_diag_block<false>, dim3(1), dim3(64), 0, s, A, lda, p0, w, Inv, ldi,
                        dvec, info, row_base, tolp);
   return hipGetLastError();
 }

@@ -166,31 +166,34 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
     hipStream_t ds = h->side;
     TLR_HIP(hipEventRecord(h->ev_fork, h->stream));
     TLR_HIP(hipStreamWaitEvent(ds, h->ev_fork, 0));
-    TLR_HIP(launch_copy_shift(h->diagA(k), Lkk, m, h->nreal(k), shift, ds));
-    if (Rk > 0) {
-      if (w.Wd.cap < sizeof(double) * (size_t)m * Rk) {
-        TLR_HIP(hipStreamSynchronize(ds));
-        TLR_TRY(w.Wd.ensure(h->mem, sizeof(double) * (size_t)m * Rk));
+    if (Rk > 0 && w.Wd.cap < sizeof(double) * (size_t)m * Rk) {
+      TLR_HIP(hipStreamSynchronize(ds));
+      TLR_TRY(w.Wd.ensure(h->mem, sizeof(double) * (size_t)m * Rk));
+    }
+    {
+      Plan dplan(h, ds);
+      const double* Akk = h->diagA(k);
+      const int nr = h->nreal(k);
+      dplan.launch([=]() { return launch_copy_shift(Akk, Lkk, m, nr, shift, ds); });
+      if (Rk > 0) {
+        double* Wd = w.Wd.as<double>();
+        GemmBatch wb(false, false);
+        for (int j = 0; j < k; ++j) {
+          const int r = h->lr(k, j);
+          if (r == 0) continue;
+          wb.add(m, r, r, h->ul(k, j), m, gptr(k, j), r, Wd + h->lo(k, j) * m, m, 1.0, 0.0);
+        }
+        dplan.gemm(wb);
+        GemmBatch up(false, true);
+        up.add(m, m, Rk, Wd, m, h->UL[k], m, Lkk, m, -1.0, 1.0, GEMM_LOWER_C);
+        dplan.gemm(up);
+        flops += wb.flops + up.flops / 2;
       }
-      double* Wd = w.Wd.as<double>();
-      GemmBatch wb(false, false);
-      for (int j = 0; j < k; ++j) {
-        const int r = h->lr(k, j);
-        if (r == 0) continue;
-        wb.add(m, r, r, h->ul(k, j), m, gptr(k, j), r, Wd + h->lo(k, j) * m, m, 1.0, 0.0);
-      }
-      TLR_TRY(wb.run(h, ds));
-      GemmBatch up(false, true);
-      up.add(m, m, Rk, Wd, m, h->UL[k], m, Lkk, m, -1.0, 1.0, GEMM_LOWER_C);
-      TLR_TRY(up.run(h, ds));
-      flops += wb.flops + up.flops / 2;
+      TLR_TRY(dense_factor(h, dplan, !ldl, Lkk, m, m, ldl ? h->Dv + (size_t)k * m : nullptr, k * m,
+                           h->invL(k)));
+      TLR_TRY(dplan.run());
     }
     flops_paper += 2.0 * m * (double)m * Rk + (double)m * m * m / 3.0;
-    if (ldl) {
-      TLR_TRY(dense_ldlt(h, Lkk, m, m, h->Dv + (size_t)k * m, k * m, h->invL(k), ds));
-    } else {
-      TLR_TRY(dense_potrf(h, Lkk, m, m, k * m, h->invL(k), ds));
-    }
     TLR_HIP(hipEventRecord(h->ev_join, ds));
     flops += (double)m * m * m / 3.0 + (double)m * m * m / 3.0;
 

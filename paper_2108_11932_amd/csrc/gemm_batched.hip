@@ -129,17 +129,17 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
 // C = alpha A^T B + beta C with A stored K x M and B stored K x N (both
 // column-major, the contraction runs down their columns): the projections
 // U^T Omega, Q^T Y, V^T V, U^T Q of the method, where K is the tile height.
-// A workgroup owns a (16 FM) x (16 FN) tile of C; its four waves take
+// A workgroup owns a (16 FM) x (16 FN) tile of C; its eight waves take
 // interleaved 16-row slices of K.  Within a slice lane (i, g) reads rows
 // 4g..4g+3 of column i of A and of B, so both operands are read in 32-byte
 // runs down their columns, and MFMA t of the slice consumes row 4g + t: the
-// same permutation of k on both operands, so the sum is unchanged.  The four
+// same permutation of k on both operands, so the sum is unchanged.  The eight
 // partial tiles are added in LDS in a fixed order.
 template <int FM, int FN>
-__global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ descs,
+__global__ __launch_bounds__(512) void k_gemm_tn(const GemmDesc* __restrict__ descs,
                                                  const BlockMap* __restrict__ map) {
-  constexpr int TM = 16 * FM, TN = 16 * FN;
-  __shared__ double red[4][FM * FN * 4][64];
+  constexpr int TM = 16 * FM, TN = 16 * FN, NW = 8;
+  __shared__ double red[NW][FM * FN * 4][64];
   const BlockMap bm = map[blockIdx.x];
   const GemmDesc d = descs[bm.desc];
   const int tiles_m = (d.M + TM - 1) / TM;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
     bok[b] = j < d.N;
     bcol[b] = d.B + (size_t)(bok[b] ? j : 0) * d.ldb;
   }
-  for (int k0 = kbeg + wave * 16; k0 < kend; k0 += 64) {
+  for (int k0 = kbeg + wave * 16; k0 < kend; k0 += 16 * NW) {
     const int kr = k0 + 4 * g;
     double av[FM][4], bv[FN][4];
     if (kr + 3 < kend) {
@@ -208,15 +208,16 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
 #pragma unroll
       for (int r = 0; r < 4; ++r) red[wave][(a * FN + b) * 4 + r][lane] = acc[a][b][r];
   __syncthreads();
-  // each thread finishes FM*FN*4*64/256 outputs
-  for (int e = threadIdx.x; e < FM * FN * 4 * 64; e += 256) {
-    const int slot = e / 64, l = e % 64;
-    const int ab = slot / 4, r = slot % 4;
+  for (int e = threadIdx.x; e < FM * FN * 4 * 64; e += 64 * NW) {
+    const int slot = e >> 6, l = e & 63;
+    const int ab = slot >> 2, r = slot & 3;
     const int a = ab / FN, b = ab % FN;
     const int gr = row0 + a * 16 + (l >> 4) + 4 * r;
     const int gc = col0 + b * 16 + (l & 15);
     if (gr >= d.M || gc >= d.N) continue;
-    const double v = ((red[0][slot][l] + red[1][slot][l]) + red[2][slot][l]) + red[3][slot][l];
+    double v = red[0][slot][l];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += red[w][slot][l];
     double* cp = d.C + gr + (size_t)gc * d.ldc;
     double out = d.alpha * v;
     if (d.beta != 0.0) out += d.beta * *cp;
@@ -253,9 +254,9 @@ hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, i
   if (!trans_a && !trans_b) return launch_tt<false, false>(d_descs, d_map, nblocks, bn, s);
   if (trans_a && !trans_b) {
     if (bn <= 16)
-      hipLaunchKernelGGL((k_gemm_tn<2, 1>), dim3(nblocks), dim3(256), 0, s, d_descs, d_map);
+      hipLaunchKernelGGL((k_gemm_tn<2, 1>), dim3(nblocks), dim3(512), 0, s, d_descs, d_map);
     else
-      hipLaunchKernelGGL((k_gemm_tn<2, 2>), dim3(nblocks), dim3(256), 0, s, d_descs, d_map);
+      hipLaunchKernelGGL((k_gemm_tn<2, 2>), dim3(nblocks), dim3(512), 0, s, d_descs, d_map);
     return hipGetLastError();
   }
   if (!trans_a && trans_b) return launch_tt<false, true>(d_descs, d_map, nblocks, bn, s);

@@ -220,6 +220,10 @@ tlr_status dense_ldlt(Handle* h, double* A, int lda, int m, double* d, int row_b
                       hipStream_t s);
 tlr_status dense_trsm(Handle* h, const double* L, int ldl, double* B, int ldb, int m, int n,
                       bool unit, bool trans);
+// Append the blocked factorization of A and the assembly of Linv to a plan
+// (on the plan's stream); d is the pivot vector for LDL^T (chol = false).
+tlr_status dense_factor(Handle* h, struct Plan& plan, bool chol, double* A, int lda, int m,
+                        double* d, int row_base, double* Linv);
 
 // Kernel wrappers not declared in tlr_internal.h.
 hipError_t launch_zero_upper(double* A, int lda, int m, hipStream_t s);

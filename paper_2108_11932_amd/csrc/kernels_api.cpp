@@ -122,7 +122,7 @@ tlr_status tlrk_ara(int m, int count, const double* tiles, double tau, int bs, i
                     unsigned long long seed, double* Q, double* B, int* ranks, int* iters,
                     void* stream) {
   KARG(m > 0 && count >= 0 && tiles && Q && B && ranks && iters, "invalid argument");
-  KARG(bs >= 1 && bs <= 32 && r_min >= 1 && r_min <= bs && tau > 0.0, "invalid ARA parameters");
+  KARG(orth_block_supported(bs) && r_min >= 1 && r_min <= bs && tau > 0.0, "invalid ARA parameters");
   if (count == 0) return TLR_OK;
   Ctx c;
   TLR_TRY(c.init(stream, m));

@@ -220,7 +220,7 @@ void Plan::seg(const SegBatch& b) {
   std::vector<BlockMap> map;
   for (size_t i = 0; i < b.d.size(); ++i) {
     maxn = b.d[i].N > maxn ? b.d[i].N : maxn;
-    for (int t = 0; t < (b.d[i].M + 63) / 64; ++t) map.push_back(BlockMap{(int)i, t});
+    for (int t = 0; t < (b.d[i].M + 15) / 16; ++t) map.push_back(BlockMap{(int)i, t});
   }
   const size_t od = stage(b.d.data(), b.d.size() * sizeof(SegDesc));
   const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
@@ -249,11 +249,11 @@ tlr_status Plan::run() {
 static constexpr int NBP = 64;
 
 // Off-diagonal blocks of the inverse of a lower triangular m x m matrix L
-// whose 64 x 64 diagonal blocks are already inverted in Linv:
+// whose diagonal blocks (diag_block_size() wide) are already inverted in Linv:
 // [A 0; B C]^{-1} = [A^{-1} 0; -C^{-1} B A^{-1}  C^{-1}], applied bottom-up
 // over a binary split of the block rows; nodes of one level are batched.
-static tlr_status inverse_assemble(Handle* h, const double* L, int ldl, int m, double* Linv,
-                                   hipStream_t s) {
+// W is an m x m workspace.
+static void inverse_assemble(Plan& plan, const double* L, int ldl, int m, double* Linv, double* W) {
   struct Node {
     int lo, mid, hi;
   };
@@ -263,21 +263,15 @@ static tlr_status inverse_assemble(Handle* h, const double* L, int ldl, int m, d
     auto it = stack.back();
     stack.pop_back();
     const int lo = it.first.first, hi = it.first.second, dep = it.second;
-    if (hi - lo <= NBP) continue;
-    const int nblk = (hi - lo + NBP - 1) / NBP;
-    const int mid = lo + ((nblk + 1) / 2) * NBP;
+    const int nd = diag_block_size();
+    if (hi - lo <= nd) continue;
+    const int nblk = (hi - lo + nd - 1) / nd;
+    const int mid = lo + ((nblk + 1) / 2) * nd;
     if ((int)levels.size() <= dep) levels.resize(dep + 1);
     levels[dep].push_back(Node{lo, mid, hi});
     stack.push_back({{lo, mid}, dep + 1});
     stack.push_back({{mid, hi}, dep + 1});
   }
-  if (levels.empty()) return TLR_OK;
-  Work& w = h->ws;
-  if (w.dW.cap < sizeof(double) * (size_t)m * m) {
-    TLR_HIP(hipStreamSynchronize(s));
-    TLR_TRY(w.dW.ensure(h->mem, sizeof(double) * (size_t)m * m));
-  }
-  double* W = w.dW.as<double>();
   for (int dep = (int)levels.size() - 1; dep >= 0; --dep) {
     GemmBatch g1(false, false), g2(false, false);
     for (const Node& n : levels[dep]) {
@@ -289,65 +283,75 @@ static tlr_status inverse_assemble(Handle* h, const double* L, int ldl, int m, d
       g2.add(c, a, c, Linv + n.mid + (size_t)n.mid * m, m, W + n.mid + (size_t)n.lo * m, m,
              Linv + n.mid + (size_t)n.lo * m, m, -1.0, 0.0, GEMM_TRIL_A);
     }
-    TLR_TRY(g1.run(h, s));
-    TLR_TRY(g2.run(h, s));
+    plan.gemm(g1);
+    plan.gemm(g2);
   }
-  return TLR_OK;
 }
 
-static tlr_status dense_factor(Handle* h, bool chol, double* A, int lda, int m, double* d,
-                               int row_base, double* Linv, hipStream_t s) {
+tlr_status dense_factor(Handle* h, Plan& plan, bool chol, double* A, int lda, int m, double* d,
+                        int row_base, double* Linv) {
   Work& w = h->ws;
-  const size_t need = sizeof(double) * (size_t)m * NBP;
+  hipStream_t s = plan.s;
+  const size_t need = sizeof(double) * (size_t)m * m;
   if (w.dW.cap < need || w.dtol.cap < 256) {
     TLR_HIP(hipStreamSynchronize(s));
-    TLR_TRY(w.dW.ensure(h->mem, std::max(need, sizeof(double) * (size_t)m * m)));
+    TLR_TRY(w.dW.ensure(h->mem, need));
     TLR_TRY(w.dtol.ensure(h->mem, 256));
   }
-  TLR_HIP(hipMemsetAsync(Linv, 0, sizeof(double) * (size_t)m * m, s));
-  if (!chol) TLR_HIP(launch_pivot_tol(A, lda, m, w.dtol.as<double>(), s));
   double* W = w.dW.as<double>();
-  for (int p0 = 0; p0 < m; p0 += NBP) {
-    const int wd = m - p0 < NBP ? m - p0 : NBP;
+  double* tol = w.dtol.as<double>();
+  int* info = h->d_info;
+  plan.launch([=]() { return hipMemsetAsync(Linv, 0, sizeof(double) * (size_t)m * m, s); });
+  if (!chol) plan.launch([=]() { return launch_pivot_tol(A, lda, m, tol, s); });
+  const int nd = diag_block_size();
+  for (int p0 = 0; p0 < m; p0 += nd) {
+    const int wd = m - p0 < nd ? m - p0 : nd;
     double* inv = Linv + p0 + (size_t)p0 * m;
-    TLR_HIP(launch_diag_block(chol, A, lda, p0, wd, inv, m, d, h->d_info, row_base,
-                              w.dtol.as<double>(), s));
+    plan.launch([=]() {
+      return launch_diag_block(chol, A, lda, p0, wd, inv, m, d, info, row_base, tol, s);
+    });
     const int rem = m - p0 - wd;
     if (rem <= 0) continue;
     double* a21 = A + (p0 + wd) + (size_t)p0 * lda;
     double* a22 = A + (p0 + wd) + (size_t)(p0 + wd) * lda;
     if (chol) {
-      // L21 = A21 L11^{-T}, in place: one column tile (wd <= 64), every
+      // L21 = A21 L11^{-T}, in place: one column tile (wd <= 32 < 64), every
       // workgroup reads its own rows before writing them
       GemmBatch p(false, true);
       p.add(rem, wd, wd, a21, lda, inv, m, a21, lda, 1.0, 0.0);
-      TLR_TRY(p.run(h, s));
+      plan.gemm(p);
       GemmBatch t(false, true);
       t.add(rem, rem, wd, a21, lda, a21, lda, a22, lda, -1.0, 1.0, GEMM_LOWER_C);
-      TLR_TRY(t.run(h, s));
+      plan.gemm(t);
     } else {
       // W21 = A21 L11^{-T} = L21 D, L21 = W21 D^{-1}, A22 -= W21 L21^T
       GemmBatch p(false, true);
       p.add(rem, wd, wd, a21, lda, inv, m, W, m, 1.0, 0.0);
-      TLR_TRY(p.run(h, s));
-      TLR_HIP(launch_scale_cols(W, m, a21, lda, d + p0, rem, wd, true, s));
+      plan.gemm(p);
+      const double* dp = d + p0;
+      plan.launch([=]() { return launch_scale_cols(W, m, a21, lda, dp, rem, wd, true, s); });
       GemmBatch t(false, true);
       t.add(rem, rem, wd, W, m, a21, lda, a22, lda, -1.0, 1.0, GEMM_LOWER_C);
-      TLR_TRY(t.run(h, s));
+      plan.gemm(t);
     }
   }
-  TLR_HIP(launch_zero_upper(A, lda, m, s));
-  return inverse_assemble(h, A, lda, m, Linv, s);
+  plan.launch([=]() { return launch_zero_upper(A, lda, m, s); });
+  inverse_assemble(plan, A, lda, m, Linv, W);
+  return TLR_OK;
 }
 
 tlr_status dense_potrf(Handle* h, double* A, int lda, int m, int row_base, double* Linv,
                        hipStream_t s) {
-  return dense_factor(h, true, A, lda, m, nullptr, row_base, Linv, s);
+  Plan plan(h, s);
+  TLR_TRY(dense_factor(h, plan, true, A, lda, m, nullptr, row_base, Linv));
+  return plan.run();
 }
 
 tlr_status dense_ldlt(Handle* h, double* A, int lda, int m, double* d, int row_base, double* Linv,
                       hipStream_t s) {
-  return dense_factor(h, false, A, lda, m, d, row_base, Linv, s);
+  Plan plan(h, s);
+  TLR_TRY(dense_factor(h, plan, false, A, lda, m, d, row_base, Linv));
+  return plan.run();
 }
 
 // Blocked triangular solve with the diagonal-block kernel (used by the

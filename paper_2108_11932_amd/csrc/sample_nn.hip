@@ -7,8 +7,9 @@
 // sampled input tile and the row panel of the factor against the reduced
 // test matrix; the same kernel performs the Gram-Schmidt update Y - Q C.
 // Every element of A is used once, so the kernel is bound by HBM: a
-// workgroup owns 64 rows of one problem, each wave 16 rows and the whole K of
-// both segments.  Lane (i, g) reads row i of A for the four columns
+// workgroup owns 16 rows of one problem and its four waves take interleaved
+// 16-wide slices of the K range of both segments (many loads in flight even
+// when few tiles are active), reduced through LDS in a fixed order.  Lane (i, g) reads row i of A for the four columns
 // k0 + 4 g + t (128-byte runs per column over the 16 lanes of a group) and
 // rows k0 + 4 g + t of column i of B (32-byte runs); MFMA t consumes k0 +
 // 4 g + t on both operands.
@@ -23,12 +24,12 @@ namespace {
 template <int NF>
 __global__ __launch_bounds__(256) void k_sample_nn(const SegDesc* __restrict__ descs,
                                                    const BlockMap* __restrict__ map) {
+  __shared__ double red[4][NF * 4][64];
   const BlockMap bm = map[blockIdx.x];
   const SegDesc d = descs[bm.desc];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
-  const int r0 = bm.tile * 64 + wave * 16;
-  if (r0 >= d.M) return;
+  const int r0 = bm.tile * 16;
   const int row = r0 + li;
   const bool rok = row < d.M;
 
@@ -51,32 +52,25 @@ __global__ __launch_bounds__(256) void k_sample_nn(const SegDesc* __restrict__ d
       bok[b] = c < d.N;
       bcol[b] = B + (size_t)(bok[b] ? c : 0) * ldb;
     }
-    int k0 = 0;
-    // full 16-wide k steps
-    for (; k0 + 16 <= K; k0 += 16) {
+    // wave w takes the 16-wide k steps w, w + 4, w + 8, ...
+    for (int k0 = wave * 16; k0 < K; k0 += 64) {
       const int kr = k0 + 4 * g;
       double av[4], bv[NF][4];
+      if (k0 + 16 <= K) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) av[t] = rok ? A[(size_t)(kr + t) * lda] : 0.0;
-#pragma unroll
-      for (int b = 0; b < NF; ++b)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) bv[b][t] = bok[b] ? bcol[b][kr + t] : 0.0;
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 4; ++t) av[t] = rok ? A[(size_t)(kr + t) * lda] : 0.0;
 #pragma unroll
         for (int b = 0; b < NF; ++b)
-          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[b][t], acc[b], 0, 0, 0);
-    }
-    if (k0 < K) {
-      const int kr = k0 + 4 * g;
-      double av[4], bv[NF][4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) av[t] = (rok && kr + t < K) ? A[(size_t)(kr + t) * lda] : 0.0;
+          for (int t = 0; t < 4; ++t) bv[b][t] = bok[b] ? bcol[b][kr + t] : 0.0;
+      } else {
 #pragma unroll
-      for (int b = 0; b < NF; ++b)
+        for (int t = 0; t < 4; ++t) av[t] = (rok && kr + t < K) ? A[(size_t)(kr + t) * lda] : 0.0;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) bv[b][t] = (bok[b] && kr + t < K) ? bcol[b][kr + t] : 0.0;
+        for (int b = 0; b < NF; ++b)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) bv[b][t] = (bok[b] && kr + t < K) ? bcol[b][kr + t] : 0.0;
+      }
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -84,20 +78,22 @@ __global__ __launch_bounds__(256) void k_sample_nn(const SegDesc* __restrict__ d
           acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[b][t], acc[b], 0, 0, 0);
     }
   }
-  // accumulator register r of lane (li, g) holds row r0 + g + 4 r, column li
 #pragma unroll
-  for (int b = 0; b < NF; ++b) {
-    const int c = b * 16 + li;
-    if (c >= d.N) continue;
+  for (int b = 0; b < NF; ++b)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int rr = r0 + g + 4 * r;
-      if (rr >= d.M) continue;
-      double* cp = d.C + rr + (size_t)c * d.ldc;
-      double v = acc[b][r];
-      if (d.beta != 0.0) v += d.beta * *cp;
-      *cp = v;
-    }
+    for (int r = 0; r < 4; ++r) red[wave][b * 4 + r][lane] = acc[b][r];
+  __syncthreads();
+  // accumulator register r of lane l holds row r0 + l/16 + 4 r, column l%16
+  for (int e = threadIdx.x; e < NF * 4 * 64; e += 256) {
+    const int slot = e >> 6, l = e & 63;
+    const int b = slot >> 2, r = slot & 3;
+    const int rr = r0 + (l >> 4) + 4 * r;
+    const int c = b * 16 + (l & 15);
+    if (rr >= d.M || c >= d.N) continue;
+    double v = ((red[0][slot][l] + red[1][slot][l]) + red[2][slot][l]) + red[3][slot][l];
+    double* cp = d.C + rr + (size_t)c * d.ldc;
+    if (d.beta != 0.0) v += d.beta * *cp;
+    *cp = v;
   }
 }
 

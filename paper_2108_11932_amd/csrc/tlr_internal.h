@@ -52,7 +52,7 @@ hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, i
 
 // Two-segment product with a narrow right-hand side (N <= 32):
 // C = beta C + A[0] B[0] + A[1] B[1]; a segment with K = 0 is skipped.
-// The block map enumerates 64-row blocks of C (tile = row block).
+// The block map enumerates 16-row blocks of C (tile = row block).
 struct SegDesc {
   const double* A[2];
   const double* B[2];
@@ -67,7 +67,9 @@ hipError_t launch_sample_nn(const SegDesc* d, const BlockMap* map, int nblocks, 
 // ---------------------------------------------------------------------------
 // Dense tile kernels (one m x m tile, m <= 4096)
 // ---------------------------------------------------------------------------
-// Factor the w x w (w <= 64) diagonal block at (p0, p0) of A in place
+// Width of the diagonal blocks the factorization kernel handles (32).
+int diag_block_size();
+// Factor the w x w (w <= diag_block_size()) diagonal block at (p0, p0) of A in place
 // (Cholesky, or unit LDL^T with pivots into dvec[p0..]) and write the inverse
 // of its lower factor to Inv (ld ldi).  info (device int) receives the
 // 1-based row (row_base + p0 + j + 1) of the first failing pivot.
@@ -104,6 +106,9 @@ struct OrthDesc {
   double* rfac;    // bs x bs inverse triangular factor
   int* piv;        // bs pivots, then the accepted count at [bs]
 };
+// Block sizes the orthogonalisation kernels are built for (1, 2, 4, 8, 16,
+// 24, 32).
+bool orth_block_supported(int bs);
 // pass 1: Gram of the bs sample columns; pass 2: of the p new basis columns.
 hipError_t launch_gram_dd(const OrthDesc* d, int ntiles, int m, int bs, int pass, hipStream_t s);
 hipError_t launch_pivchol(const OrthDesc* d, int ntiles, int m, int bs, double tau2, int r_min,
