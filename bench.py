@@ -73,6 +73,30 @@ def cpu_baseline(w, n_sample: int, tlr, torch):
             "oracle_seconds": t_cpu, "gpu_seconds_same_sample": t_gpu}
 
 
+def residual(mat, torch, nvec: int = 4, seed: int = 7) -> float:
+    """Random-vector residual of the factor against the FP64 TLR input:
+    max over Gaussian b of ||A x - b|| / ||x|| with x = (L L^T)^{-1} b, i.e.
+    ||(A - L L^T) x|| / ||x||; A is applied by tlr_matvec (FP64), x by
+    tlr_solve with the factor."""
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    b = torch.randn(mat.n, nvec, generator=g, dtype=torch.float64).cuda()
+    x = mat.solve(b)
+    r = mat.matvec(x) - b
+    return float((r.norm(dim=0) / x.norm(dim=0)).max())
+
+
+def time_form(mat, w, eps_mode, precision, tlr, torch, steps, warmup):
+    """Warm up, then time `steps` factorizations of one form."""
+    o = tlr.opts(bs=w.bs, eps_mode=eps_mode, precision=precision, flags=tlr.FLAG_KERNEL_TIMING)
+    for _ in range(warmup):
+        mat.potrf(w.eps, o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [mat.potrf(w.eps, o) for _ in range(steps)]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, stats
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +106,11 @@ def main():
     ap.add_argument("--bs", type=int, default=0, help="ARA block size (0 = the workload's)")
     ap.add_argument("--cpu-sample", type=int, default=8192,
                     help="points of the leading block the CPU oracle factors (0 = skip)")
+    ap.add_argument("--no-forms", dest="forms", action="store_false",
+                    help="skip the relative-threshold FP64 / mixed-precision comparison")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (calibrates HBM "
+                         "byte counters against a kernel of known traffic)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: the factorization is a single-GPU code path "
@@ -92,6 +121,16 @@ def main():
     from paper_2108_11932_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if a.copy_probe_mb > 0:
+        n = a.copy_probe_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] copy probe: %d MiB read, %d MiB written" % (a.copy_probe_mb, a.copy_probe_mb),
+              file=sys.stderr, flush=True)
+        del src, dst
     w = wl.standard(a.workload)
     if a.bs:
         w.bs = a.bs
@@ -104,18 +143,9 @@ def main():
     print("[bench] input built in %.1fs, ranks %d..%d mean %.1f" % (t_build, ra.min(), ra.max(),
                                                                      ra.mean()), file=sys.stderr,
           flush=True)
-    o = tlr.opts(bs=w.bs, eps_mode=w.eps_mode, flags=tlr.FLAG_KERNEL_TIMING)
-    for i in range(a.warmup):
-        mat.potrf(w.eps, o)
-        print("[bench] warmup %d done" % i, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for i in range(a.steps):
-        stats.append(mat.potrf(w.eps, o))
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / a.steps
+    dt, stats = time_form(mat, w, w.eps_mode, tlr.FP64, tlr, torch, a.steps, a.warmup)
     print("[bench] %d timed steps, %.1f ms each" % (a.steps, dt * 1e3), file=sys.stderr, flush=True)
+    err_primary = residual(mat, torch)
     flops = float(np.mean([s["flops"] for s in stats]))
     flops_paper = float(np.mean([s["flops_paper"] for s in stats]))
     smp_bytes = sum(s["sample_bytes"] for s in stats)
@@ -123,6 +153,25 @@ def main():
     smp_n = sum(s["sample_launches"] for s in stats)
     achieved = smp_bytes / (smp_ms * 1e-3) / 1e9 if smp_ms > 0 else 0.0
     rl = mat.ranks(tlr.FACTOR)[np.tril_indices(mat.nb, -1)]
+    # FP64 against mixed precision at the relative threshold, where the FP32
+    # rounding guard admits the tiles (at an absolute 1e-6 it admits almost
+    # none, and the mixed form is the FP64 one)
+    forms = {}
+    if a.forms:
+        for name, mode, prec in (("fp64_rel", 1, tlr.FP64), ("mixed_fp32_rel", 1, tlr.MIXED_FP32),
+                                 ("mixed_fp32_abs", 0, tlr.MIXED_FP32)):
+            fdt, fst = time_form(mat, w, mode, prec, tlr, torch, a.steps, a.warmup)
+            s0 = fst[-1]
+            forms[name] = {"ms_per_step": fdt * 1e3,
+                           "tflops": float(np.mean([x["flops"] for x in fst])) / fdt / 1e12,
+                           "eps_mode": "relative" if mode else "absolute", "tau": s0["tau"],
+                           "residual": residual(mat, torch),
+                           "fp32_share": s0["fp32_tile_iters"] / max(1, s0["tile_iters"]),
+                           "ara_iterations": int(s0["ara_iters"]),
+                           "mean_rank": s0["mean_rank"], "max_rank": int(s0["max_rank"])}
+            print("[bench] form %s: %.1f ms, residual %.3g" % (name, fdt * 1e3,
+                                                               forms[name]["residual"]),
+                  file=sys.stderr, flush=True)
     line = {
         "metric": METRIC,
         "value": flops / dt / 1e12,
@@ -143,6 +192,9 @@ def main():
         "tflops_paper_count": flops_paper / dt / 1e12,
         "ranks_factor": {"min": int(rl.min()), "mean": float(rl.mean()), "max": int(rl.max())},
         "ara_iterations": int(stats[-1]["ara_iters"]),
+        "tau": stats[-1]["tau"],
+        "residual": err_primary,
+        "forms": forms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "Schur-complement sampling product Y_i -= U_i* Z_i",

@@ -68,7 +68,14 @@ typedef enum {
 } tlr_status;
 
 enum { TLR_EPS_ABS = 0, TLR_EPS_REL = 1 };
-enum { TLR_FP64 = 0 };
+/* Precision of the factorization.  TLR_MIXED_FP32 keeps an FP32 copy of the
+ * factor's block-row U panels and streams it in the Schur-complement
+ * sampling of Eq. (2) (products still accumulated in FP64) for every tile
+ * whose FP32 rounding cannot reach the threshold:
+ *   u_32 * nu_ik <= tau / 16,  nu_ik = ||A_ik||_F + sum_j ||L_ij||_F ||L_kj||_F.
+ * Other tiles, the dense diagonal work, the orthogonalisation, the final
+ * projection and the triangular solve stay FP64. */
+enum { TLR_FP64 = 0, TLR_MIXED_FP32 = 1 };
 enum { TLR_KERNEL_EXP = 0, TLR_KERNEL_MATERN15 = 1 };
 enum { TLR_INPUT = 0, TLR_FACTOR = 1 };
 
@@ -86,7 +93,7 @@ typedef struct {
                               1, 2, 4, 8, 16, 24, 32; the paper uses 16 in 2D
                               and 32 in 3D (Section 6) */
   int eps_mode;            /* TLR_EPS_ABS (default) or TLR_EPS_REL */
-  int precision;           /* TLR_FP64 */
+  int precision;           /* TLR_FP64 (default) or TLR_MIXED_FP32 */
   double shift;            /* factor A + shift * I (diagonal shift, Section 5.1);
                               a negative value means shift = tau */
   int max_active;          /* size of the active subset of tiles per column
@@ -121,6 +128,7 @@ typedef struct {
   double sample_ms;        /* their summed duration (HIP events), milliseconds */
   double sample_bytes;     /* their algorithmic HBM bytes: U panels, Z, Y read and write */
   double sample_flops;     /* their flops */
+  long long fp32_tile_iters; /* TLR_MIXED_FP32: tile iterations sampled from FP32 panels */
 } tlr_stats;
 
 /* Fill *opts with the defaults: bs 16, absolute eps, FP64, shift 0, all tiles

@@ -48,7 +48,8 @@ static tlr_status check_opts(const tlr_opts* in, tlr_opts* out) {
   TLR_ARG(orth_block_supported(out->bs), "opts.bs must be one of 1, 2, 4, 8, 16, 24, 32, got %d",
           out->bs);
   TLR_ARG(out->eps_mode == TLR_EPS_ABS || out->eps_mode == TLR_EPS_REL, "opts.eps_mode invalid");
-  TLR_ARG(out->precision == TLR_FP64, "opts.precision: only TLR_FP64 is supported");
+  TLR_ARG(out->precision == TLR_FP64 || out->precision == TLR_MIXED_FP32,
+          "opts.precision must be TLR_FP64 or TLR_MIXED_FP32");
   TLR_ARG(out->r_min >= 1 && out->r_min <= out->bs, "opts.r_min must be in 1..bs");
   TLR_ARG(std::isfinite(out->shift), "opts.shift must be finite");
   return TLR_OK;
@@ -158,6 +159,7 @@ tlr_status tlr_set_diag(tlr_matrix_t A, int k, const double* D, int ld, int on_d
   TLR_HIP(hipMemcpy2DAsync(A->diagA(k), sizeof(double) * A->m, D, sizeof(double) * ld,
                            sizeof(double) * nr, nr, kind_in(on_device), A->stream));
   A->norm_a = 0.0;
+  A->a_fro.clear();
   return A->sync();
 }
 
@@ -177,6 +179,8 @@ tlr_status tlr_set_tile(tlr_matrix_t A, int i, int j, const double* U, const dou
   TLR_HIP(hipMemcpy2DAsync(A->va(i, j), sizeof(double) * m, V, sizeof(double) * ld,
                            sizeof(double) * A->nreal(j), r, kind_in(on_device), A->stream));
   A->norm_a = 0.0;
+  A->a_fro.clear();
+  A->a_orth = false;
   return A->sync();
 }
 
@@ -369,6 +373,7 @@ tlr_status tlr_destroy(tlr_matrix_t A) {
   A->ws.release_all(mem);
   A->stage.release(mem);
   if (A->pin_back) (void)hipHostFree(A->pin_back);
+  if (A->pin_norm) (void)hipHostFree(A->pin_norm);
   if (A->ev_fork) (void)hipEventDestroy(A->ev_fork);
   if (A->ev_join) (void)hipEventDestroy(A->ev_join);
   if (A->side) (void)hipStreamDestroy(A->side);

@@ -126,7 +126,7 @@ __device__ inline dd dd_sqrt(dd a) {
 // compensated dot product of Ogita, Rump and Oishi (Dot2) and stored as
 // unevaluated (hi, lo) pairs.  X is the first `nc` columns of the block;
 // nc comes from the tile's pivot record when ncols_from_piv is set.
-constexpr int GRAM_ROWS = 128;
+constexpr int GRAM_ROWS = 64;
 constexpr int BS_MAX = 32;
 
 __global__ __launch_bounds__(256) void k_gram_dd(const OrthDesc* __restrict__ descs, int m, int bs,
@@ -176,218 +176,172 @@ __global__ __launch_bounds__(256) void k_gram_dd(const OrthDesc* __restrict__ de
   }
 }
 
-// Sum of the partial Gram matrices into G (dd, full symmetric, LDS), one
-// entry of the upper triangle per lane and step.
-template <int BS>
-__device__ void gram_sum(const OrthDesc& d, int nc, int nrb, dd (*G)[BS_MAX + 1]) {
-  for (int e = threadIdx.x; e < BS * BS; e += 64) {
-    const int a = e % BS, b = e / BS;
-    if (a > b || b >= nc) continue;
-    dd acc{0.0, 0.0};
-    for (int rb = 0; rb < nrb; ++rb) {
-      const double* p = d.part + (size_t)rb * BS * BS * 2 + (a + b * BS) * 2;
-      acc = dd_add(acc, dd{p[0], p[1]});
-    }
-    G[a][b] = acc;
-    G[b][a] = acc;
-  }
-  __syncthreads();
-}
-
-// Inverse of the p x p upper triangular R (double) by columns: thread c
-// solves R x = e_c.  Ri must be zero-initialised.
-__device__ void upper_inverse(const double (*R)[BS_MAX + 1], double (*Ri)[BS_MAX + 1], int p) {
-  const int c = threadIdx.x;
-  if (c < p) {
-    for (int r = c; r >= 0; --r) {
-      double v = (r == c) ? 1.0 : 0.0;
-      for (int t = r + 1; t <= c; ++t) v -= R[r][t] * Ri[t][c];
-      Ri[r][c] = v / R[r][r];
-    }
-  }
-  __syncthreads();
-}
-
-// ------------------------------------------------- pivoted Cholesky (pass 1)
-// Diagonally pivoted Cholesky of the dd Gram matrix G = Y^T Y with the
-// threshold tau^2 on the Schur-complement diagonal: column j is accepted
-// while the largest remaining diagonal (the squared norm of a sample
-// column after removing the accepted directions) exceeds tau^2.  p accepted
-// pivots give Y_P = Q_new R with R p x p upper triangular.  The tile has
-// converged when at least r_min samples were left below tau, or the basis
-// has reached its capacity.  Writes the pivots, p, R^{-1}, the new basis
-// width and the convergence flag.
+// ------------------------------------- Cholesky QR step: factor + apply
+// One kernel per pass.  Every workgroup of a tile sums the partial Gram
+// matrices, factors the BS x BS Gram, then turns its own block of APPLY_ROWS
+// rows into new basis rows by a triangular solve with R.  The factorization
+// is repeated by the workgroups of a tile (it is tiny and deterministic, so
+// all of them reach the same R); only the first writes the pivot record.
 //
-// One wave per tile.  Columns are never moved: step j picks the pivot by a
-// wave max-reduction over the remaining diagonal, every lane forms the
-// multipliers l_x = G[pv][x] / sqrt(G[pv][pv]) of its columns, and the Schur
-// update G[a][b] -= l_a l_b is spread over all lanes.  R in pivot order is
-// read off the stored multipliers at the end.
-template <int BS>
-__global__ __launch_bounds__(64) void k_pivchol(const OrthDesc* __restrict__ descs, int nrb,
-                                                double tau2, int r_min, int qcap) {
-  __shared__ dd G[BS_MAX][BS_MAX + 1];
-  __shared__ double Lm[BS_MAX][BS_MAX + 1];  // Lm[j][x]: multiplier of column x at step j
-  __shared__ double R[BS_MAX][BS_MAX + 1];
-  __shared__ double Ri[BS_MAX][BS_MAX + 1];
-  __shared__ dd lrow[BS_MAX];
-  __shared__ int perm[BS_MAX];
-  __shared__ int taken[BS_MAX];
-  const OrthDesc d = descs[blockIdx.x];
-  const int t = threadIdx.x;
-  gram_sum<BS>(d, BS, nrb, G);
-  if (t < BS) {
-    taken[t] = 0;
-    perm[t] = t;
-  }
-  for (int e = t; e < BS_MAX * (BS_MAX + 1); e += 64) {
-    (&R[0][0])[e] = 0.0;
-    (&Ri[0][0])[e] = 0.0;
-    (&Lm[0][0])[e] = 0.0;
-  }
-  __syncthreads();
-  const int qold = d.qold;
-  const int room = max(0, qcap - qold);
-  int p = 0;
-  for (int j = 0; j < BS && j < room; ++j) {
-    // pivot: largest remaining diagonal (ties: lowest column)
-    double v = -1.0;
-    int idx = BS;
-    if (t < BS && !taken[t]) {
-      v = G[t][t].hi;
-      idx = t;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(v, off);
-      const int oi = __shfl_xor(idx, off);
-      if (ov > v || (ov == v && oi < idx)) {
-        v = ov;
-        idx = oi;
-      }
-    }
-    if (!(v > tau2)) break;
-    const int pv = idx;
-    const dd rinv = dd_div(dd{1.0, 0.0}, dd_sqrt(G[pv][pv]));
-    __syncthreads();
-    if (t < BS) {
-      dd l{0.0, 0.0};
-      if (!taken[t]) l = dd_mul(G[pv][t], rinv);
-      lrow[t] = l;
-      Lm[j][t] = l.hi + l.lo;
-    }
-    __syncthreads();
-    if (t == 0) {
-      taken[pv] = 1;
-      perm[j] = pv;
-    }
-    // Schur complement of the remaining columns
-    for (int e = t; e < BS * BS; e += 64) {
-      const int a = e % BS, b = e / BS;
-      if (a <= b) {
-        const dd nv = dd_sub(G[a][b], dd_mul(lrow[a], lrow[b]));
-        G[a][b] = nv;
-        G[b][a] = nv;
-      }
-    }
-    __syncthreads();
-    p = j + 1;
-  }
-  // complete the permutation with the columns that were not accepted
-  if (t == 0) {
-    int nxt = p;
-    for (int c = 0; c < BS; ++c)
-      if (!taken[c]) perm[nxt++] = c;
-  }
-  __syncthreads();
-  // R in pivot order: R[j][i] = Lm[j][perm[i]] for i >= j
-  for (int e = t; e < BS * BS; e += 64) {
-    const int jj = e % BS, i = e / BS;
-    if (jj < p && i < p && i >= jj) R[jj][i] = Lm[jj][perm[i]];
-  }
-  __syncthreads();
-  upper_inverse(R, Ri, p);
-  for (int e = t; e < BS * BS; e += 64) {
-    const int r = e % BS, c = e / BS;
-    d.rfac[r + c * BS] = (r < p && c < p) ? Ri[r][c] : 0.0;
-  }
-  if (t < BS) d.piv[t] = perm[t];
-  if (t == 0) {
-    d.piv[BS] = p;
-    *d.q = qold + p;
-    const bool conv = (p <= BS - r_min) || (qold + p >= qcap);
-    *d.flag = conv ? 1 : 0;
-  }
-}
-
-// Unpivoted Cholesky of the Gram matrix of the new columns (pass 2); the
-// columns are already orthonormal to about u * cond, so the Gram is close to
-// the identity.  Writes R^{-1} to rfac.  One wave per tile.
-template <int BS>
-__global__ __launch_bounds__(64) void k_chol_small(const OrthDesc* __restrict__ descs, int nrb) {
-  __shared__ dd G[BS_MAX][BS_MAX + 1];
-  __shared__ double R[BS_MAX][BS_MAX + 1];
-  __shared__ double Ri[BS_MAX][BS_MAX + 1];
-  __shared__ dd lrow[BS_MAX];
-  const OrthDesc d = descs[blockIdx.x];
-  const int t = threadIdx.x;
-  const int p = d.piv[BS];
-  gram_sum<BS>(d, p, nrb, G);
-  for (int e = t; e < BS_MAX * (BS_MAX + 1); e += 64) {
-    (&R[0][0])[e] = 0.0;
-    (&Ri[0][0])[e] = 0.0;
-  }
-  __syncthreads();
-  for (int j = 0; j < p; ++j) {
-    dd gj = dd_sqrt(G[j][j]);
-    if (gj.hi == 0.0) gj = dd{1.0, 0.0};
-    const dd rinv = dd_div(dd{1.0, 0.0}, gj);
-    __syncthreads();
-    if (t >= j && t < p) {
-      const dd l = (t == j) ? gj : dd_mul(G[j][t], rinv);
-      lrow[t] = l;
-      R[j][t] = l.hi + l.lo;
-    }
-    __syncthreads();
-    for (int e = t; e < BS * BS; e += 64) {
-      const int a = e % BS, b = e / BS;
-      if (a > j && a <= b && b < p) G[a][b] = dd_sub(G[a][b], dd_mul(lrow[a], lrow[b]));
-    }
-    __syncthreads();
-  }
-  upper_inverse(R, Ri, p);
-  for (int e = t; e < BS * BS; e += 64) {
-    const int r = e % BS, c = e / BS;
-    d.rfac[r + c * BS] = (r < p && c < p && r <= c) ? Ri[r][c] : 0.0;
-  }
-}
-
-// New basis columns = (selected sample columns) * R^{-1}.
-// pass 1: source Y with the pivot permutation, destination Q[:, qold:qold+p]
-// pass 2: in place on Q[:, qold:qold+p]
+// Pass 1 (PIV): diagonally pivoted Cholesky with the threshold tau^2 on the
+// Schur-complement diagonal.  Column j is accepted while the largest
+// remaining diagonal (the squared norm of a sample column after removing
+// the accepted directions) exceeds tau^2; p accepted pivots give
+// Y_P = Q_new R, R p x p upper triangular in pivot order.  The tile has
+// converged when at least r_min samples were left below tau, or the basis
+// has reached its capacity.
+// Pass 2: unpivoted Cholesky of the Gram of the p new columns (already
+// orthogonal to about u * cond, so the Gram is close to the identity);
+// the columns are replaced in place.
+//
+// The dd Gram is spread over the workgroup: thread t = x + BS g holds row x,
+// columns g CPG .. g CPG + CPG - 1, in registers, and mirrors them to LDS,
+// from which every thread reads the pivot column at each step (one LDS
+// exchange and two barriers per step; symmetry is exact because the
+// partial sums are shared and the dd product is commutative).
 constexpr int APPLY_ROWS = 256;
 
-__global__ __launch_bounds__(APPLY_ROWS) void k_apply_rinv(const OrthDesc* __restrict__ descs,
-                                                           int m, int bs, int pass) {
+template <int BS, bool PIV>
+__global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(const OrthDesc* __restrict__ descs, int m,
+                                                          int nrb, double tau2, int r_min,
+                                                          int qcap) {
+  constexpr int NG = APPLY_ROWS / BS;
+  constexpr int CPG = (BS + NG - 1) / NG;
+  __shared__ dd Gs[BS][BS + 1];
+  __shared__ double Lm[BS][BS + 1];   // Lm[j][b]: multiplier of column b at step j
+  __shared__ double Rs[BS][BS + 1];   // R(a, c), a <= c
+  __shared__ int perm[BS];
   const OrthDesc d = descs[blockIdx.y];
-  const int r = blockIdx.x * APPLY_ROWS + threadIdx.x;
-  const int p = d.piv[bs];
-  if (r >= m || p == 0) return;
-  double* dst = d.Q + (size_t)d.qold * m;
-  double x[BS_MAX];
+  const int t = threadIdx.x;
+  const int x = t % BS, g = t / BS;
+  const int nc = PIV ? BS : d.piv[BS];
+  if (nc == 0) return;
+  // ---- sum of the partial Gram matrices (stored for a <= b)
+  dd gv[CPG];
 #pragma unroll
-  for (int a = 0; a < BS_MAX; ++a) {
-    if (a < p) {
-      x[a] = (pass == 1) ? d.Y[r + (size_t)d.piv[a] * m] : dst[r + (size_t)a * m];
+  for (int i = 0; i < CPG; ++i) {
+    const int b = g * CPG + i;
+    dd acc{0.0, 0.0};
+    if (g < NG && b < nc && x < nc) {
+      const int lo = min(x, b), hi = max(x, b);
+      const double* pp = d.part + (size_t)(lo + hi * BS) * 2;
+      for (int rb = 0; rb < nrb; ++rb) {
+        const double* q2 = pp + (size_t)rb * BS * BS * 2;
+        acc = dd_add(acc, dd{q2[0], q2[1]});
+      }
+    }
+    gv[i] = acc;
+    if (g < NG && b < BS) Gs[x][b] = acc;
+  }
+  for (int e = t; e < BS * (BS + 1); e += APPLY_ROWS) {
+    (&Lm[0][0])[e] = 0.0;
+    (&Rs[0][0])[e] = 0.0;
+  }
+  __syncthreads();
+  int np = 0;
+  if (PIV) {
+    const int room = max(0, qcap - d.qold);
+    unsigned taken = 0u;
+    for (int j = 0; j < BS && j < room; ++j) {
+      // pivot: largest remaining diagonal, ties to the lowest column
+      double vmax = -1.0;
+      int pv = BS;
+      for (int c = 0; c < BS; ++c) {
+        const double v = Gs[c][c].hi;
+        if (!((taken >> c) & 1u) && v > vmax) {
+          vmax = v;
+          pv = c;
+        }
+      }
+      if (!(vmax > tau2)) break;
+      const dd rinv = dd_div(dd{1.0, 0.0}, dd_sqrt(Gs[pv][pv]));
+      const dd lx = ((taken >> x) & 1u) ? dd{0.0, 0.0} : dd_mul(Gs[x][pv], rinv);
+      dd lb[CPG];
+#pragma unroll
+      for (int i = 0; i < CPG; ++i) {
+        const int b = g * CPG + i;
+        lb[i] = (b < BS && !((taken >> b) & 1u)) ? dd_mul(Gs[pv][b], rinv) : dd{0.0, 0.0};
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < CPG; ++i) {
+        const int b = g * CPG + i;
+        if (g < NG && b < BS) {
+          gv[i] = dd_sub(gv[i], dd_mul(lx, lb[i]));
+          Gs[x][b] = gv[i];
+          if (x == 0) Lm[j][b] = lb[i].hi + lb[i].lo;
+        }
+      }
+      if (t == 0) perm[j] = pv;
+      taken |= 1u << pv;
+      np = j + 1;
+      __syncthreads();
+    }
+    if (t == 0) {
+      int nxt = np;
+      for (int c = 0; c < BS; ++c)
+        if (!((taken >> c) & 1u)) perm[nxt++] = c;
+    }
+    __syncthreads();
+    // R in pivot order: R(jj, i) = Lm[jj][perm[i]] for i >= jj
+    for (int e = t; e < BS * BS; e += APPLY_ROWS) {
+      const int jj = e % BS, i = e / BS;
+      if (jj < np && i < np && i >= jj) Rs[jj][i] = Lm[jj][perm[i]];
+    }
+    if (blockIdx.x == 0) {
+      if (t < BS) d.piv[t] = perm[t];
+      if (t == 0) {
+        d.piv[BS] = np;
+        *d.q = d.qold + np;
+        *d.flag = ((np <= BS - r_min) || (d.qold + np >= qcap)) ? 1 : 0;
+      }
+    }
+  } else {
+    np = nc;
+    for (int j = 0; j < nc; ++j) {
+      dd gj = dd_sqrt(Gs[j][j]);
+      if (gj.hi == 0.0) gj = dd{1.0, 0.0};
+      const dd rinv = dd_div(dd{1.0, 0.0}, gj);
+      const dd lx = (x > j && x < nc) ? dd_mul(Gs[x][j], rinv) : dd{0.0, 0.0};
+      dd lb[CPG];
+#pragma unroll
+      for (int i = 0; i < CPG; ++i) {
+        const int b = g * CPG + i;
+        lb[i] = (b > j && b < nc) ? dd_mul(Gs[j][b], rinv) : (b == j ? gj : dd{0.0, 0.0});
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < CPG; ++i) {
+        const int b = g * CPG + i;
+        if (g < NG && b < BS) {
+          if (x > j && b > j) {
+            gv[i] = dd_sub(gv[i], dd_mul(lx, lb[i]));
+            Gs[x][b] = gv[i];
+          }
+          if (x == 0 && b >= j) Rs[j][b] = lb[i].hi + lb[i].lo;
+        }
+      }
+      __syncthreads();
     }
   }
+  __syncthreads();
+  // ---- apply: rows of Q_new from Y_P = Q_new R (pass 1) or X = Q_new R
+  // (pass 2, in place), by forward substitution along the row
+  const int r = blockIdx.x * APPLY_ROWS + t;
+  if (r >= m || np == 0) return;
+  double* dst = d.Q + (size_t)d.qold * m;
+  double xv[BS];
 #pragma unroll
-  for (int c = 0; c < BS_MAX; ++c) {
-    if (c < p) {
-      double v = 0.0;
+  for (int a = 0; a < BS; ++a)
+    if (a < np) xv[a] = PIV ? d.Y[r + (size_t)perm[a] * m] : dst[r + (size_t)a * m];
 #pragma unroll
-      for (int a = 0; a < BS_MAX; ++a)
-        if (a <= c) v += x[a] * d.rfac[a + c * bs];
+  for (int c = 0; c < BS; ++c) {
+    if (c < np) {
+      double v = xv[c];
+#pragma unroll
+      for (int a = 0; a < c; ++a) v = fma(-xv[a], Rs[a][c], v);
+      v = v / Rs[c][c];
+      xv[c] = v;
       dst[r + (size_t)c * m] = v;
     }
   }
@@ -486,42 +440,41 @@ hipError_t launch_gram_dd(const OrthDesc* d, int ntiles, int m, int bs, int pass
   return hipGetLastError();
 }
 
-#define TLR_BS_DISPATCH(bs, KERNEL, ...)                                          \
-  switch (bs) {                                                                   \
-    case 16: hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__); break;                  \
-    case 32: hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__); break;                  \
-    case 8: hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__); break;                    \
-    case 24: hipLaunchKernelGGL(KERNEL<24>, __VA_ARGS__); break;                  \
-    case 4: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                     \
-    case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                     \
-    case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                     \
-    default: return hipErrorInvalidValue;                                         \
+// KERNEL is a template-id whose block-size argument is spelled BS_ARG.
+#define TLR_BS_CASE(v, KERNEL, ...)                    \
+  case v: {                                            \
+    constexpr int BS_ARG = v;                          \
+    hipLaunchKernelGGL(KERNEL, __VA_ARGS__);           \
+    break;                                             \
+  }
+#define TLR_BS_DISPATCH(bs, KERNEL, ...)               \
+  switch (bs) {                                        \
+    TLR_BS_CASE(16, KERNEL, __VA_ARGS__)               \
+    TLR_BS_CASE(32, KERNEL, __VA_ARGS__)               \
+    TLR_BS_CASE(8, KERNEL, __VA_ARGS__)                \
+    TLR_BS_CASE(24, KERNEL, __VA_ARGS__)               \
+    TLR_BS_CASE(4, KERNEL, __VA_ARGS__)                \
+    TLR_BS_CASE(2, KERNEL, __VA_ARGS__)                \
+    TLR_BS_CASE(1, KERNEL, __VA_ARGS__)                \
+    default: return hipErrorInvalidValue;              \
   }
 
 bool orth_block_supported(int bs) {
   return bs == 1 || bs == 2 || bs == 4 || bs == 8 || bs == 16 || bs == 24 || bs == 32;
 }
 
-hipError_t launch_pivchol(const OrthDesc* d, int ntiles, int m, int bs, double tau2, int r_min,
-                          int qcap, hipStream_t s) {
+hipError_t launch_orth_step(const OrthDesc* d, int ntiles, int m, int bs, int pass, double tau2,
+                            int r_min, int qcap, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   const int nrb = gram_row_blocks(m);
-  TLR_BS_DISPATCH(bs, k_pivchol, dim3(ntiles), dim3(64), 0, s, d, nrb, tau2, r_min, qcap);
-  return hipGetLastError();
-}
-
-hipError_t launch_chol_small(const OrthDesc* d, int ntiles, int m, int bs, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  const int nrb = gram_row_blocks(m);
-  TLR_BS_DISPATCH(bs, k_chol_small, dim3(ntiles), dim3(64), 0, s, d, nrb);
-  return hipGetLastError();
-}
-
-hipError_t launch_apply_rinv(const OrthDesc* d, int ntiles, int m, int bs, int pass,
-                             hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_apply_rinv, dim3((m + APPLY_ROWS - 1) / APPLY_ROWS, ntiles),
-                     dim3(APPLY_ROWS), 0, s, d, m, bs, pass);
+  const dim3 grid((m + APPLY_ROWS - 1) / APPLY_ROWS, ntiles);
+  if (pass == 1) {
+    TLR_BS_DISPATCH(bs, (k_orth_step<BS_ARG, true>), grid, dim3(APPLY_ROWS), 0, s, d, m, nrb, tau2,
+                    r_min, qcap);
+  } else {
+    TLR_BS_DISPATCH(bs, (k_orth_step<BS_ARG, false>), grid, dim3(APPLY_ROWS), 0, s, d, m, nrb, tau2,
+                    r_min, qcap);
+  }
   return hipGetLastError();
 }
 

@@ -20,14 +20,12 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   TLR_TRY(w.Q.ensure(h->mem, sizeof(double) * nn * s->qstride));
   if (fresh_q) TLR_HIP(hipMemsetAsync(w.Q.p, 0, w.Q.cap, h->stream));
   TLR_TRY(w.part.ensure(h->mem, sizeof(double) * nn * nrb * bs * bs * 2));
-  TLR_TRY(w.rfac.ensure(h->mem, sizeof(double) * nn * bs * bs));
   const size_t nint = 4 + 2 * nn + al(nn) + al(nn * (bs + 1)) + al(nn) + 64;
   TLR_TRY(w.ints.ensure(h->mem, sizeof(int) * nint));
   s->Y = w.Y.as<double>();
   s->C = w.C.as<double>();
   s->Q = w.Q.as<double>();
   s->part = w.part.as<double>();
-  s->rfac = w.rfac.as<double>();
   int* ip = w.ints.as<int>();
   s->counts = ip;
   ip += 4;
@@ -115,8 +113,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     for (int a = 0; a < na; ++a) {
       const int sl = act[a];
       od[a] = OrthDesc{s.y(sl), s.q(sl), q[sl], s.qv + sl, s.flag + sl,
-                       s.part + (size_t)sl * nrb * bs * bs * 2, s.rfac + (size_t)sl * bs * bs,
-                       s.piv + (size_t)sl * (bs + 1)};
+                       s.part + (size_t)sl * nrb * bs * bs * 2, s.piv + (size_t)sl * (bs + 1)};
     }
     const size_t ood = plan.stage(od.data(), sizeof(OrthDesc) * na);
     hipStream_t st = h->stream;
@@ -124,9 +121,8 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     const int r_min = c.r_min, qcap = c.qcap;
     plan.launch(ood, [=](const char* p) { return launch_gram_dd((const OrthDesc*)p, na, m, bs, 1, st); });
     plan.launch(ood, [=](const char* p) {
-      return launch_pivchol((const OrthDesc*)p, na, m, bs, tau2, r_min, qcap, st);
+      return launch_orth_step((const OrthDesc*)p, na, m, bs, 1, tau2, r_min, qcap, st);
     });
-    plan.launch(ood, [=](const char* p) { return launch_apply_rinv((const OrthDesc*)p, na, m, bs, 1, st); });
     // pass 2 on the new columns X = Q[:, qold : qold + bs]
     {
       GemmBatch c1(true, false);
@@ -141,8 +137,9 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       plan.seg(c2);
     }
     plan.launch(ood, [=](const char* p) { return launch_gram_dd((const OrthDesc*)p, na, m, bs, 2, st); });
-    plan.launch(ood, [=](const char* p) { return launch_chol_small((const OrthDesc*)p, na, m, bs, st); });
-    plan.launch(ood, [=](const char* p) { return launch_apply_rinv((const OrthDesc*)p, na, m, bs, 2, st); });
+    plan.launch(ood, [=](const char* p) {
+      return launch_orth_step((const OrthDesc*)p, na, m, bs, 2, tau2, r_min, qcap, st);
+    });
     // convergence flags -> compaction and refill on the device
     const int nwait = (int)waiting.size(), smax = s_max;
     int* info = h->d_info;

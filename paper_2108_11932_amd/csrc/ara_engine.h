@@ -36,7 +36,6 @@ struct AraSlots {
   double* Q = nullptr;   // n x (m x (qcap + bs))
   double* C = nullptr;   // n x (m x bs)
   double* part = nullptr;
-  double* rfac = nullptr;
   // contiguous read-back block: counts[2], status word copy, pad, act[n], qv[n]
   int* counts = nullptr; // 2 (+ 2)
   int* act = nullptr;    // n

@@ -53,6 +53,8 @@ tlr_status compress(Handle* h, const double* A, long long lda, const double* pts
   h->a_rank.assign((size_t)nb * nb, 0);
   h->a_off.assign((size_t)nb * nb, -1);
   h->a_cols = 0;
+  h->a_orth = true;   // every tile becomes Q B^T with orthonormal Q
+  h->a_fro.clear();
   h->mem.put(h->UA);
   h->mem.put(h->VA);
   h->UA = h->VA = nullptr;

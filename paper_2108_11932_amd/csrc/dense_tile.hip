@@ -19,94 +19,87 @@ namespace {
 constexpr int NB = 64;   // block size of the blocked triangular solve
 constexpr int ND = 32;   // diagonal block of the blocked factorizations
 
+// Broadcast lane `lane` (a compile-time constant) of a double to the wave.
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Factor the diagonal block (p0, p0) of A (w <= 32) in place: Cholesky, or
 // unit LDL^T with the pivots in dvec[p0..]; write the inverse of the lower
 // factor into Inv (ld ldi).
 //
-// One wave; lanes 0..31 work.  Lane r holds row r of the block in registers
-// (rows and columns beyond w are the identity, which leaves the real part
-// unchanged).  Step j of the factorization needs column j, i.e. register j
-// of every lane: each lane picks it out with a select chain (constant
-// register indices), writes it to LDS, and reads the column back as uniform
-// broadcasts.  Rows are kept in unscaled LDL^T form (row[p] = l_rp d_p).
-// The inverse X = L^{-1} is a column-oriented forward substitution on the
-// identity, row i of X on lane i, with row p of X broadcast through LDS.
+// One wave; lane r holds row r of the block in registers (rows and columns
+// beyond w are the identity, which leaves the real part unchanged; lanes
+// 32..63 carry copies and store nothing).  Both loops are unrolled, so every
+// register index is a constant and every cross-lane value is a readlane into
+// scalar registers: no LDS round trip sits on the dependency chain.
+// Right-looking: step j takes d = a_jj from lane j, each lane its own a_rj,
+// and subtracts (a_rj / d) a_cj from a_rc, a_cj read from lane c.  The
+// inverse X = L^{-1} is a forward substitution with row i of X on lane i:
+// lane p finishes row p, whose entries are then read from lane p.
 template <bool CHOL>
 __global__ __launch_bounds__(64) void k_diag_block(double* A, int lda, int p0, int w, double* Inv,
                                                    int ldi, double* dvec, int* info, int row_base,
                                                    const double* tolp) {
-  __shared__ double col[ND];
-  __shared__ double dsh[ND];
-  __shared__ double Ls[ND][ND + 1];   // Ls[p][i] = L(i, p)
   const int r = threadIdx.x & (ND - 1);
   const bool act = threadIdx.x < ND;
   double row[ND];
 #pragma unroll
   for (int c = 0; c < ND; ++c) {
     double v = (r == c) ? 1.0 : 0.0;
-    if (act && r < w && c < w && c <= r) v = A[(p0 + r) + (size_t)(p0 + c) * lda];
+    if (r < w && c < w && c <= r) v = A[(p0 + r) + (size_t)(p0 + c) * lda];
     row[c] = v;
   }
   const double tol = CHOL ? 0.0 : *tolp;
   int bad_row = 0;
-#pragma nounroll
-  for (int j = 0; j < ND; ++j) {
-    double rj = 0.0;
+  double dpiv = 1.0;   // this lane's pivot d_r
 #pragma unroll
-    for (int c = 0; c < ND; ++c) rj = (c == j) ? row[c] : rj;
-    if (act) col[r] = rj;
-    __syncthreads();
-    double dj = col[j];
-    const bool bad = CHOL ? !(dj > 0.0) : !(fabs(dj) > tol);
+  for (int j = 0; j < ND; ++j) {
+    double d = lane_bcast(row[j], j);
+    const bool bad = CHOL ? !(d > 0.0) : !(fabs(d) > tol);
     if (bad) {
       if (j < w && bad_row == 0) bad_row = row_base + p0 + j + 1;
-      dj = 1.0;
+      d = 1.0;
     }
-    if (threadIdx.x == 0) dsh[j] = dj;
-    const double mr = rj / dj;   // l_rj
+    const double a = row[j];     // a_rj (unscaled)
+    const double mr = a / d;     // l_rj of the unit factor
 #pragma unroll
-    for (int c = 0; c < ND; ++c) {
-      const double v = row[c] - mr * col[c];
-      row[c] = (c > j) ? v : row[c];
+    for (int c = j + 1; c < ND; ++c) row[c] -= mr * lane_bcast(a, c);
+    if (r == j) dpiv = d;
+    if (CHOL) {
+      const double sq = sqrt(d);
+      row[j] = (r == j) ? sq : (r > j ? a / sq : 0.0);
+    } else {
+      row[j] = (r == j) ? 1.0 : (r > j ? mr : 0.0);
     }
-    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);   // keep the scalar broadcasts of a step together
   }
   if (bad_row && threadIdx.x == 0) atomicCAS(info, 0, bad_row);
-  // L(r, p) to LDS and to A
 #pragma unroll
-  for (int p = 0; p < ND; ++p) {
-    double l;
-    if (CHOL) {
-      const double sq = sqrt(dsh[p]);
-      l = (r == p) ? sq : (r > p ? row[p] / sq : 0.0);
-    } else {
-      l = (r == p) ? 1.0 : (r > p ? row[p] / dsh[p] : 0.0);
-    }
-    if (act) Ls[p][r] = l;
-    if (act && r < w && p < w) A[(p0 + r) + (size_t)(p0 + p) * lda] = l;
-  }
-  if (!CHOL && act && r < w) dvec[p0 + r] = dsh[r];
-  __syncthreads();
-  // X = L^{-1}: lane p finishes row p (divides by L(p, p)) and broadcasts
-  // it; rows i > p lose L(i, p) X(p, :)  (X(p, c) = 0 for c > p)
+  for (int p = 0; p < ND; ++p)
+    if (act && r < w && p < w) A[(p0 + r) + (size_t)(p0 + p) * lda] = (p <= r) ? row[p] : 0.0;
+  if (!CHOL && act && r < w) dvec[p0 + r] = dpiv;
+  // X = L^{-1}: at step p lane p scales its row by 1 / L(p, p); rows i > p
+  // then lose L(i, p) X(p, :) (X(p, c) = 0 for c > p).
   double x[ND];
 #pragma unroll
   for (int c = 0; c < ND; ++c) x[c] = (r == c) ? 1.0 : 0.0;
-#pragma nounroll
-  for (int p = 0; p < ND; ++p) {
-    if (act && r == p) {
-      const double inv = 1.0 / Ls[p][p];
 #pragma unroll
-      for (int c = 0; c < ND; ++c) {
-        x[c] *= inv;
-        col[c] = x[c];
+  for (int p = 0; p < ND; ++p) {
+    if (CHOL) {
+      const double inv = 1.0 / row[p];
+      if (r == p) {
+#pragma unroll
+        for (int c = 0; c <= p; ++c) x[c] *= inv;
       }
     }
-    __syncthreads();
-    const double lip = (act && r > p) ? Ls[p][r] : 0.0;
+    const double lip = (r > p) ? row[p] : 0.0;
 #pragma unroll
-    for (int c = 0; c < ND; ++c) x[c] -= lip * col[c];
-    __syncthreads();
+    for (int c = 0; c <= p; ++c) x[c] -= lip * lane_bcast(x[c], p);
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int c = 0; c < ND; ++c)

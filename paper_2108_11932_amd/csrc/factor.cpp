@@ -27,8 +27,10 @@ namespace tlr {
 void free_factor(Handle* h) {
   for (double* p : h->UL) h->mem.put(p);
   for (double* p : h->VL) h->mem.put(p);
+  for (float* p : h->UL32) h->mem.put(p);
   h->UL.assign(h->nb, nullptr);
   h->VL.assign(h->nb, nullptr);
+  h->UL32.assign(h->nb, nullptr);
   h->R.assign(h->nb, 0);
   h->cap.assign(h->nb, 0);
   h->l_rank.assign((size_t)h->nb * h->nb, 0);
@@ -50,17 +52,60 @@ static tlr_status grow_row(Handle* h, int i, int extra) {
     h->mem.put(u);
     return st;
   }
+  void* u32 = nullptr;
+  if (h->mixed) {
+    st = h->mem.get(&u32, sizeof(float) * (size_t)h->m * nc);
+    if (st != TLR_OK) {
+      h->mem.put(u);
+      h->mem.put(v);
+      return st;
+    }
+  }
   if (h->R[i] > 0) {
     const size_t bytes = sizeof(double) * (size_t)h->m * h->R[i];
     TLR_HIP(hipMemcpyAsync(u, h->UL[i], bytes, hipMemcpyDeviceToDevice, h->stream));
     TLR_HIP(hipMemcpyAsync(v, h->VL[i], bytes, hipMemcpyDeviceToDevice, h->stream));
+    if (h->mixed)
+      TLR_HIP(hipMemcpyAsync(u32, h->UL32[i], bytes / 2, hipMemcpyDeviceToDevice, h->stream));
   }
   TLR_TRY(h->sync());
   h->mem.put(h->UL[i]);
   h->mem.put(h->VL[i]);
+  h->mem.put(h->UL32[i]);
   h->UL[i] = (double*)u;
   h->VL[i] = (double*)v;
+  h->UL32[i] = (float*)u32;
   h->cap[i] = nc;
+  return TLR_OK;
+}
+
+// ||A_ij||_F of every input tile for the mixed-precision guard: ||V||_F when
+// U has orthonormal columns, else the bound ||U||_F ||V||_F.
+static tlr_status input_norms(Handle* h) {
+  const int nb = h->nb, m = h->m;
+  std::vector<NormDesc> nd;
+  std::vector<size_t> tile;
+  h->a_fro.assign((size_t)nb * nb, 0.0);
+  for (int i = 0; i < nb; ++i)
+    for (int j = 0; j < i; ++j)
+      if (h->ar(i, j) > 0) tile.push_back((size_t)i * nb + j);
+  if (tile.empty()) return TLR_OK;
+  const size_t n = tile.size();
+  TLR_TRY(h->ws.fro.ensure(h->mem, sizeof(double) * 2 * n));
+  double* out = h->ws.fro.as<double>();
+  for (size_t t = 0; t < n; ++t) {
+    const int i = (int)(tile[t] / nb), j = (int)(tile[t] % nb), r = h->ar(i, j);
+    nd.push_back(NormDesc{h->va(i, j), m, r, m, out + 2 * t});
+    nd.push_back(NormDesc{h->ua(i, j), m, r, m, out + 2 * t + 1});
+  }
+  void* dd = nullptr;
+  TLR_TRY(h->stage.upload(h, nd.data(), sizeof(NormDesc) * nd.size(), &dd));
+  TLR_HIP(launch_fro_norms((const NormDesc*)dd, (int)nd.size(), h->stream));
+  std::vector<double> host(2 * n);
+  TLR_TRY(h->sync());
+  TLR_HIP(hipMemcpy(host.data(), out, sizeof(double) * 2 * n, hipMemcpyDeviceToHost));
+  for (size_t t = 0; t < n; ++t)
+    h->a_fro[tile[t]] = h->a_orth ? host[2 * t] : host[2 * t] * host[2 * t + 1];
   return TLR_OK;
 }
 
@@ -90,6 +135,15 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
   }
   const double shift = o.shift < 0.0 ? tau : o.shift;
   TLR_HIP(hipMemsetAsync(h->d_info, 0, sizeof(int), h->stream));
+  // mixed precision: FP32 panels for the tiles whose FP32 rounding stays
+  // below tau / 16 (the LDL^T variant samples in FP64 throughout)
+  h->mixed = o.precision == TLR_MIXED_FP32 && !ldl;
+  const double u32 = 5.9604644775390625e-08;   // 2^-24
+  if (h->mixed && h->a_fro.empty()) TLR_TRY(input_norms(h));
+  h->l_fro.assign((size_t)nb * nb, 0.0);
+  double* pin_norm = nullptr;
+  if (h->mixed) TLR_TRY(h->pinned_norms((size_t)std::max(nb, 1), &pin_norm));
+  long long fp32_tile_iters = 0;
 
   // initial panel capacities from the input ranks (a large rank in A tends to
   // stay large in L, Section 4.2)
@@ -220,6 +274,17 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
       TLR_TRY(h->sync_main());
       order.assign(pin, pin + nrow);
     }
+    // the V norms of column k - 1 arrived with that sync
+    if (h->mixed && k > 0)
+      for (int s = 0; s < nrow + 1; ++s) h->l_fro[(size_t)(k + s) * nb + (k - 1)] = pin_norm[s];
+    std::vector<char> use32(nrow, 0);
+    if (h->mixed)
+      for (int s = 0; s < nrow; ++s) {
+        const int i = k + 1 + s;
+        double nu = h->a_fro[(size_t)i * nb + k];
+        for (int j = 0; j < k; ++j) nu += h->l_fro[(size_t)i * nb + j] * h->l_fro[(size_t)k * nb + j];
+        use32[s] = (u32 * nu <= tau / 16.0) ? 1 : 0;
+      }
 
     // ---------------------------------------------- cholARAUpdate
     TLR_TRY(w.P.ensure(h->mem, sizeof(double) * (size_t)std::max(Rk, 1) * bs));
@@ -239,7 +304,7 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
         plan.gemm(pb);
       }
       GemmBatch wa(true, false), zb(false, false);
-      SegBatch y;
+      SegBatch y, y32;
       long long zo = 0;
       for (int sl : act) {
         const int i = k + 1 + sl;
@@ -261,12 +326,18 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
           k1 = Ri;
           zo += (long long)Ri * bs;
         }
-        y.add(m, bs, h->ua(i, k), m, wa_s, m, a, h->UL[i], m, zs, std::max(Ri, 1), k1,
-              slots.y(sl), m, 0.0);
+        if (use32[sl]) {
+          y32.add_f32(m, bs, h->ua(i, k), m, wa_s, m, a, h->UL32[i], m, zs, std::max(Ri, 1), k1,
+                      slots.y(sl), m, 0.0);
+          ++fp32_tile_iters;
+        } else {
+          y.add(m, bs, h->ua(i, k), m, wa_s, m, a, h->UL[i], m, zs, std::max(Ri, 1), k1,
+                slots.y(sl), m, 0.0);
+        }
       }
       plan.gemm(wa);
       plan.gemm(zb);
-      if (timing && !y.d.empty()) {
+      if (timing && !(y.d.empty() && y32.d.empty())) {
         hipEvent_t e0, e1;
         TLR_HIP(hipEventCreate(&e0));
         TLR_HIP(hipEventCreate(&e1));
@@ -274,11 +345,13 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
         hipStream_t st = h->stream;
         plan.launch([=]() { return hipEventRecord(e0, st); });
         plan.seg(y);
+        plan.seg(y32);
         plan.launch([=]() { return hipEventRecord(e1, st); });
-        samp_bytes += y.bytes;
-        samp_flops += y.flops;
+        samp_bytes += y.bytes + y32.bytes;
+        samp_flops += y.flops + y32.flops;
       } else {
         plan.seg(y);
+        plan.seg(y32);
       }
       return TLR_OK;
     };
@@ -368,7 +441,12 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
       for (int s = 0; s < nrow; ++s) {
         const int i = k + 1 + s, qs = q[s];
         if (qs == 0) continue;
-        cd.push_back(CopyDesc{slots.q(s), h->UL[i] + (size_t)h->R[i] * m, m, qs, m, m});
+        CopyDesc c{slots.q(s), h->UL[i] + (size_t)h->R[i] * m, m, qs, m, m};
+        if (h->mixed) {
+          c.dst32 = h->UL32[i] + (size_t)h->R[i] * m;
+          c.ldd32 = m;
+        }
+        cd.push_back(c);
         cd.push_back(CopyDesc{Bt + boff[s] * m, h->VL[i] + (size_t)h->R[i] * m, m, qs, m, m});
         maxc = std::max(maxc, qs);
       }
@@ -380,6 +458,23 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
           return launch_copy_batched((const CopyDesc*)p, n, maxc, st);
         });
       }
+    }
+    if (h->mixed) {
+      // ||L_ik||_F = ||V_ik||_F (U_ik orthonormal), read back with the next
+      // column's first synchronisation
+      TLR_TRY(w.fro.ensure(h->mem, sizeof(double) * (size_t)std::max(nrow, 1)));
+      double* fro = w.fro.as<double>();
+      std::vector<NormDesc> nd;
+      for (int s = 0; s < nrow; ++s)
+        nd.push_back(NormDesc{Bt + boff[s] * m, m, q[s], m, fro + s});
+      const size_t off = plan.stage(nd.data(), sizeof(NormDesc) * nd.size());
+      const int n = nrow;
+      hipStream_t st = h->stream;
+      double* pn = pin_norm;
+      plan.launch(off, [=](const char* p) { return launch_fro_norms((const NormDesc*)p, n, st); });
+      plan.launch([=]() {
+        return hipMemcpyAsync(pn, fro, sizeof(double) * n, hipMemcpyDeviceToHost, st);
+      });
     }
     TLR_TRY(plan.run());
     flops += plan.flops;
@@ -420,6 +515,7 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
     st->bytes_alg = bytes_alg;
     st->ara_iters = ara_iters;
     st->tile_iters = tile_iters;
+    st->fp32_tile_iters = fp32_tile_iters;
     long long cnt = 0, tot = 0, full = 0;
     int mx = 0;
     for (int i = 0; i < nb; ++i)

@@ -65,32 +65,50 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // ---- stage op(A)(row0 + r, k0 + kk), 64 x 16
+  // Software pipeline: the global loads of slice k0 + BK are issued into
+  // registers before the MFMAs of slice k0 run from LDS, so one memory
+  // latency per slice is hidden behind the compute and the barriers.
+  // op(A)(row0 + r, k0 + kk) is staged as 64 x 16, op(B)(k0 + kk, col0 + c)
+  // as 16 x BN; every thread owns fixed (r, kk) / (kk, c) positions.
+  constexpr int NBL = BN / 16;
+  int ar[4], ak[4], bc[NBL], bk[NBL];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (!TA) { ar[j] = tid & 63; ak[j] = (tid >> 6) + 4 * j; }
+    else     { ak[j] = tid & 15; ar[j] = (tid >> 4) + 16 * j; }
+  }
+#pragma unroll
+  for (int j = 0; j < NBL; ++j) {
+    if (!TB) { bk[j] = tid & 15; bc[j] = (tid >> 4) + 16 * j; }
+    else     { bc[j] = tid % BN; bk[j] = tid / BN + (256 / BN) * j; }
+  }
+  double ra[4], rb[NBL];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      int r, kk;
-      if (!TA) { r = tid & 63; kk = (tid >> 6) + 4 * j; }
-      else     { kk = tid & 15; r = (tid >> 4) + 16 * j; }
-      const int gr = row0 + r, gk = k0 + kk;
+      const int gr = row0 + ar[j], gk = k0 + ak[j];
       double v = 0.0;
       if (gr < d.M && gk < d.K)
         v = TA ? d.A[gk + (size_t)gr * d.lda] : d.A[gr + (size_t)gk * d.lda];
-      sA[kk][r] = v;
+      ra[j] = v;
     }
-    // ---- stage op(B)(k0 + kk, col0 + c), 16 x BN
 #pragma unroll
-    for (int j = 0; j < BN / 16; ++j) {
-      int c, kk;
-      if (!TB) { kk = tid & 15; c = (tid >> 4) + 16 * j; }
-      else     { c = tid % BN; kk = tid / BN + (256 / BN) * j; }
-      const int gc = col0 + c, gk = k0 + kk;
+    for (int j = 0; j < NBL; ++j) {
+      const int gc = col0 + bc[j], gk = k0 + bk[j];
       double v = 0.0;
       if (gc < d.N && gk < d.K)
         v = TB ? d.B[gc + (size_t)gk * d.ldb] : d.B[gk + (size_t)gc * d.ldb];
-      sB[kk][c] = v;
+      rb[j] = v;
     }
+  };
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sA[ak[j]][ar[j]] = ra[j];
+#pragma unroll
+    for (int j = 0; j < NBL; ++j) sB[bk[j]][bc[j]] = rb[j];
     __syncthreads();
+    if (k0 + BK < kend) load(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       double av[FM], bv[FN];
@@ -171,35 +189,42 @@ __global__ __launch_bounds__(512) void k_gemm_tn(const GemmDesc* __restrict__ de
     bok[b] = j < d.N;
     bcol[b] = d.B + (size_t)(bok[b] ? j : 0) * d.ldb;
   }
-  for (int k0 = kbeg + wave * 16; k0 < kend; k0 += 16 * NW) {
-    const int kr = k0 + 4 * g;
-    double av[FM][4], bv[FN][4];
-    if (kr + 3 < kend) {
+  // U slices per pass: all their loads are issued before the first MFMA, so
+  // a pass costs one memory latency instead of U (K is ~1000 and the grids
+  // of these products are small, so latency, not bandwidth, is the limit).
+  // Loads past the end of K read a clamped in-range address and are zeroed.
+  constexpr int U = 4;
+  for (int k0 = kbeg + wave * 16; k0 < kend; k0 += 16 * NW * U) {
+    double av[U][FM][4], bv[U][FN][4];
 #pragma unroll
-      for (int a = 0; a < FM; ++a)
+    for (int u = 0; u < U; ++u) {
+      const int kr = k0 + u * 16 * NW + 4 * g;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) av[a][t] = aok[a] ? acol[a][kr + t] : 0.0;
+      for (int t = 0; t < 4; ++t) {
+        const bool kin = kr + t < kend;
+        const int kk = kin ? kr + t : kend - 1;
 #pragma unroll
-      for (int b = 0; b < FN; ++b)
+        for (int a = 0; a < FM; ++a) {
+          const double v = acol[a][kk];
+          av[u][a][t] = (aok[a] && kin) ? v : 0.0;
+        }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) bv[b][t] = bok[b] ? bcol[b][kr + t] : 0.0;
-    } else {
-#pragma unroll
-      for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) av[a][t] = (aok[a] && kr + t < kend) ? acol[a][kr + t] : 0.0;
-#pragma unroll
-      for (int b = 0; b < FN; ++b)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) bv[b][t] = (bok[b] && kr + t < kend) ? bcol[b][kr + t] : 0.0;
+        for (int b = 0; b < FN; ++b) {
+          const double v = bcol[b][kk];
+          bv[u][b][t] = (bok[b] && kin) ? v : 0.0;
+        }
+      }
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int a = 0; a < FM; ++a)
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int b = 0; b < FN; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a][t], bv[b][t], acc[a][b], 0, 0, 0);
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b)
+            acc[a][b] =
+                __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][a][t], bv[u][b][t], acc[a][b], 0, 0, 0);
   }
 #pragma unroll
   for (int a = 0; a < FM; ++a)

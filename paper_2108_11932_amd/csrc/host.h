@@ -95,9 +95,21 @@ struct GemmBatch {
 struct SegBatch {
   std::vector<SegDesc> d;
   double flops = 0.0, bytes = 0.0;
+  bool a1_f32 = false;   // segment 1's A is float in every problem of the batch
   void add(int M, int N, const double* A0, int lda0, const double* B0, int ldb0, int K0,
            const double* A1, int lda1, const double* B1, int ldb1, int K1, double* C, int ldc,
            double beta) {
+    add_any(M, N, A0, lda0, B0, ldb0, K0, A1, lda1, B1, ldb1, K1, C, ldc, beta, 8.0);
+  }
+  void add_f32(int M, int N, const double* A0, int lda0, const double* B0, int ldb0, int K0,
+               const float* A1, int lda1, const double* B1, int ldb1, int K1, double* C, int ldc,
+               double beta) {
+    a1_f32 = true;
+    add_any(M, N, A0, lda0, B0, ldb0, K0, A1, lda1, B1, ldb1, K1, C, ldc, beta, 4.0);
+  }
+  void add_any(int M, int N, const double* A0, int lda0, const double* B0, int ldb0, int K0,
+               const void* A1, int lda1, const double* B1, int ldb1, int K1, double* C, int ldc,
+               double beta, double a1_bytes) {
     if (M <= 0 || N <= 0) return;
     SegDesc s{};
     s.A[0] = A0; s.B[0] = B0; s.lda[0] = lda0 > 0 ? lda0 : 1; s.ldb[0] = ldb0 > 0 ? ldb0 : 1;
@@ -108,7 +120,8 @@ struct SegBatch {
     d.push_back(s);
     const double K = (double)s.K[0] + s.K[1];
     flops += 2.0 * M * N * K;
-    bytes += 8.0 * ((double)M * K + K * N + (beta != 0.0 ? 2.0 : 1.0) * M * N);
+    bytes += 8.0 * ((double)M * s.K[0] + K * N + (beta != 0.0 ? 2.0 : 1.0) * M * N) +
+             a1_bytes * M * s.K[1];
   }
   tlr_status run(Handle* h, hipStream_t s = nullptr);
 };
@@ -136,14 +149,14 @@ struct Plan {
 
 // Per-column workspace of the factorization.
 struct Work {
-  DevBuf G, W, omega, P, Z, T, Ta, H, Ball, C, Wa, Y, Q, part, rfac, ints, orth, dscale, tol,
-      compact, Bt;
+  DevBuf G, W, omega, P, Z, T, Ta, H, Ball, C, Wa, Y, Q, part, ints, orth, dscale, tol,
+      compact, Bt, fro;
   // buffers of the diagonal-tile stream (never touched by the main stream)
   DevBuf Wd, dW, dtol;
   int slots = 0;   // slot capacity of the per-tile buffers
   void release_all(Mem& mem) {
-    DevBuf* bufs[] = {&G, &W, &omega, &P, &Z, &T, &Ta, &H, &Ball, &C, &Wa, &Y, &Q, &part, &rfac,
-                      &ints, &orth, &dscale, &tol, &compact, &Bt, &Wd, &dW, &dtol};
+    DevBuf* bufs[] = {&G, &W, &omega, &P, &Z, &T, &Ta, &H, &Ball, &C, &Wa, &Y, &Q, &part,
+                      &ints, &orth, &dscale, &tol, &compact, &Bt, &fro, &Wd, &dW, &dtol};
     for (DevBuf* b : bufs) b->release(mem);
   }
 };
@@ -173,6 +186,8 @@ struct tlr_matrix_s {
   double* UA = nullptr;
   double* VA = nullptr;
   double norm_a = 0.0;            // ||A||_2 estimate, 0 = not computed
+  bool a_orth = false;            // every input U has orthonormal columns (compressed input)
+  std::vector<double> a_fro;      // ||A_ij||_F bound per tile (mixed precision), empty = stale
 
   // factor
   int factored = 0;               // 0 none, 1 Cholesky, 2 LDL^T
@@ -183,6 +198,11 @@ struct tlr_matrix_s {
   std::vector<long long> l_off;   // column of tile (i, j) inside row i's panel
   std::vector<int> R, cap;        // panel width and capacity per block row
   std::vector<double*> UL, VL;
+  std::vector<float*> UL32;       // FP32 copies of the U panels (mixed precision)
+  bool mixed = false;             // the current factorization keeps UL32
+  std::vector<double> l_fro;      // ||L_ij||_F per tile (U orthonormal: ||V_ij||_F)
+  double* pin_norm = nullptr;     // pinned read-back of a column's V norms
+  size_t pin_norm_n = 0;
 
   Work ws;
   int* d_info = nullptr;          // device status word
@@ -206,6 +226,7 @@ struct tlr_matrix_s {
   tlr_status sync_main();     // the caller's stream only
   tlr_status init_streams();
   tlr_status pinned_ints(size_t n, int** p);
+  tlr_status pinned_norms(size_t n, double** p);
 };
 
 namespace tlr {

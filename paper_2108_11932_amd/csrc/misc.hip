@@ -17,8 +17,31 @@ __global__ __launch_bounds__(256) void k_copy_batched(const CopyDesc* __restrict
   if (c0 >= d.cols) return;
   const int c1 = min(d.cols, c0 + 8);
   for (int c = c0; c < c1; ++c)
-    for (int r = threadIdx.x; r < d.rows; r += blockDim.x)
-      d.dst[r + (size_t)c * d.ldd] = d.src[r + (size_t)c * d.lds];
+    for (int r = threadIdx.x; r < d.rows; r += blockDim.x) {
+      const double v = d.src[r + (size_t)c * d.lds];
+      d.dst[r + (size_t)c * d.ldd] = v;
+      if (d.dst32) d.dst32[r + (size_t)c * d.ldd32] = (float)v;
+    }
+}
+
+// Frobenius norms: one workgroup per block, a fixed-order tree reduction.
+__global__ __launch_bounds__(256) void k_fro_norms(const NormDesc* __restrict__ descs) {
+  __shared__ double red[256];
+  const NormDesc d = descs[blockIdx.x];
+  double s = 0.0;
+  const long long n = (long long)d.rows * d.cols;
+  for (long long e = threadIdx.x; e < n; e += 256) {
+    const int r = (int)(e % d.rows), c = (int)(e / d.rows);
+    const double v = d.p[r + (size_t)c * d.ld];
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *d.out = sqrt(red[0]);
 }
 
 __global__ void k_copy_shift(const double* src, double* dst, int m, int nreal, double shift) {
@@ -113,6 +136,12 @@ __global__ __launch_bounds__(256) void k_gen_tiles(const GenDesc* __restrict__ d
 hipError_t launch_copy_batched(const CopyDesc* d, int n, int max_cols, hipStream_t s) {
   if (n <= 0 || max_cols <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_batched, dim3((max_cols + 7) / 8, n), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_fro_norms(const NormDesc* d, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fro_norms, dim3(n), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 

@@ -133,6 +133,22 @@ tlr_status tlr_matrix_s::init_streams() {
   return TLR_OK;
 }
 
+tlr_status tlr_matrix_s::pinned_norms(size_t n, double** p) {
+  if (n > pin_norm_n) {
+    if (pin_norm) (void)hipHostFree(pin_norm);
+    pin_norm = nullptr;
+    pin_norm_n = 0;
+    if (hipHostMalloc((void**)&pin_norm, sizeof(double) * n, hipHostMallocDefault) != hipSuccess) {
+      pin_norm = nullptr;
+      tlr::set_error("pinned host allocation failed");
+      return TLR_ERR_OOM;
+    }
+    pin_norm_n = n;
+  }
+  *p = pin_norm;
+  return TLR_OK;
+}
+
 tlr_status tlr_matrix_s::pinned_ints(size_t n, int** p) {
   if (n > pin_back_n) {
     if (pin_back) (void)hipHostFree(pin_back);
@@ -225,9 +241,11 @@ void Plan::seg(const SegBatch& b) {
   const size_t od = stage(b.d.data(), b.d.size() * sizeof(SegDesc));
   const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
   const int nblk = (int)map.size();
+  const bool f32 = b.a1_f32;
   hipStream_t st = s;
   steps.push_back([=](const char* base) {
-    return launch_sample_nn((const SegDesc*)(base + od), (const BlockMap*)(base + om), nblk, maxn, st);
+    return launch_sample_nn((const SegDesc*)(base + od), (const BlockMap*)(base + om), nblk, maxn,
+                            f32, st);
   });
   flops += b.flops;
 }

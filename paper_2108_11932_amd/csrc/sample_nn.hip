@@ -21,7 +21,10 @@ typedef double d4s __attribute__((ext_vector_type(4)));
 
 namespace {
 
-template <int NF>
+// Segment 1's A is read as float when A1F32 is set (the FP32 copy of the
+// factor's row panels used by the mixed-precision sampling); the products
+// are still formed and accumulated in FP64.
+template <int NF, bool A1F32>
 __global__ __launch_bounds__(256) void k_sample_nn(const SegDesc* __restrict__ descs,
                                                    const BlockMap* __restrict__ map) {
   __shared__ double red[4][NF * 4][64];
@@ -37,11 +40,16 @@ __global__ __launch_bounds__(256) void k_sample_nn(const SegDesc* __restrict__ d
 #pragma unroll
   for (int b = 0; b < NF; ++b) acc[b] = d4s{0.0, 0.0, 0.0, 0.0};
 
+  // U 16-wide k steps per pass, all loads of a pass in flight together;
+  // loads past K read a clamped in-range address and are zeroed
+  constexpr int U = 4;
 #pragma unroll
   for (int sg = 0; sg < 2; ++sg) {
     const int K = d.K[sg];
     if (K <= 0) continue;
-    const double* __restrict__ A = d.A[sg] + (rok ? row : 0);
+    const bool f32 = A1F32 && sg == 1;
+    const double* __restrict__ A = (const double*)d.A[sg] + (rok ? row : 0);
+    const float* __restrict__ Af = (const float*)d.A[sg] + (rok ? row : 0);
     const double* __restrict__ B = d.B[sg];
     const size_t lda = d.lda[sg], ldb = d.ldb[sg];
     const double* bcol[NF];
@@ -53,29 +61,31 @@ __global__ __launch_bounds__(256) void k_sample_nn(const SegDesc* __restrict__ d
       bcol[b] = B + (size_t)(bok[b] ? c : 0) * ldb;
     }
     // wave w takes the 16-wide k steps w, w + 4, w + 8, ...
-    for (int k0 = wave * 16; k0 < K; k0 += 64) {
-      const int kr = k0 + 4 * g;
-      double av[4], bv[NF][4];
-      if (k0 + 16 <= K) {
+    for (int k0 = wave * 16; k0 < K; k0 += 64 * U) {
+      double av[U][4], bv[U][NF][4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) av[t] = rok ? A[(size_t)(kr + t) * lda] : 0.0;
+      for (int u = 0; u < U; ++u) {
+        const int kr = k0 + 64 * u + 4 * g;
 #pragma unroll
-        for (int b = 0; b < NF; ++b)
+        for (int t = 0; t < 4; ++t) {
+          const bool kin = kr + t < K;
+          const int kk = kin ? kr + t : K - 1;
+          const double a = f32 ? (double)Af[(size_t)kk * lda] : A[(size_t)kk * lda];
+          av[u][t] = (rok && kin) ? a : 0.0;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) bv[b][t] = bok[b] ? bcol[b][kr + t] : 0.0;
-      } else {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) av[t] = (rok && kr + t < K) ? A[(size_t)(kr + t) * lda] : 0.0;
-#pragma unroll
-        for (int b = 0; b < NF; ++b)
-#pragma unroll
-          for (int t = 0; t < 4; ++t) bv[b][t] = (bok[b] && kr + t < K) ? bcol[b][kr + t] : 0.0;
+          for (int b = 0; b < NF; ++b) {
+            const double v = bcol[b][kk];
+            bv[u][b][t] = (bok[b] && kin) ? v : 0.0;
+          }
+        }
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int b = 0; b < NF; ++b)
-          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[b][t], acc[b], 0, 0, 0);
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int b = 0; b < NF; ++b)
+            acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][t], bv[u][b][t], acc[b], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -100,13 +110,20 @@ __global__ __launch_bounds__(256) void k_sample_nn(const SegDesc* __restrict__ d
 }  // namespace
 
 hipError_t launch_sample_nn(const SegDesc* d, const BlockMap* map, int nblocks, int maxn,
-                            hipStream_t s) {
+                            bool a1_f32, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
   if (maxn > 32) return hipErrorInvalidValue;
-  if (maxn <= 16)
-    hipLaunchKernelGGL((k_sample_nn<1>), dim3(nblocks), dim3(256), 0, s, d, map);
-  else
-    hipLaunchKernelGGL((k_sample_nn<2>), dim3(nblocks), dim3(256), 0, s, d, map);
+  if (maxn <= 16) {
+    if (a1_f32)
+      hipLaunchKernelGGL((k_sample_nn<1, true>), dim3(nblocks), dim3(256), 0, s, d, map);
+    else
+      hipLaunchKernelGGL((k_sample_nn<1, false>), dim3(nblocks), dim3(256), 0, s, d, map);
+  } else {
+    if (a1_f32)
+      hipLaunchKernelGGL((k_sample_nn<2, true>), dim3(nblocks), dim3(256), 0, s, d, map);
+    else
+      hipLaunchKernelGGL((k_sample_nn<2, false>), dim3(nblocks), dim3(256), 0, s, d, map);
+  }
   return hipGetLastError();
 }
 

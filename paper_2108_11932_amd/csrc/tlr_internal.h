@@ -54,7 +54,7 @@ hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, i
 // C = beta C + A[0] B[0] + A[1] B[1]; a segment with K = 0 is skipped.
 // The block map enumerates 16-row blocks of C (tile = row block).
 struct SegDesc {
-  const double* A[2];
+  const void* A[2];   // double, or float for segment 1 of an FP32-panel batch
   const double* B[2];
   int lda[2], ldb[2], K[2];
   double* C;
@@ -62,7 +62,7 @@ struct SegDesc {
   double beta;
 };
 hipError_t launch_sample_nn(const SegDesc* d, const BlockMap* map, int nblocks, int maxn,
-                            hipStream_t s);
+                            bool a1_f32, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Dense tile kernels (one m x m tile, m <= 4096)
@@ -103,7 +103,6 @@ struct OrthDesc {
   int* q;          // device basis width (updated by the pivoted Cholesky)
   int* flag;       // set to 1 when the tile has converged
   double* part;    // partial Gram sums: nrb x bs x bs x 2 (hi, lo)
-  double* rfac;    // bs x bs inverse triangular factor
   int* piv;        // bs pivots, then the accepted count at [bs]
 };
 // Block sizes the orthogonalisation kernels are built for (1, 2, 4, 8, 16,
@@ -111,11 +110,11 @@ struct OrthDesc {
 bool orth_block_supported(int bs);
 // pass 1: Gram of the bs sample columns; pass 2: of the p new basis columns.
 hipError_t launch_gram_dd(const OrthDesc* d, int ntiles, int m, int bs, int pass, hipStream_t s);
-hipError_t launch_pivchol(const OrthDesc* d, int ntiles, int m, int bs, double tau2, int r_min,
-                          int qcap, hipStream_t s);
-hipError_t launch_chol_small(const OrthDesc* d, int ntiles, int m, int bs, hipStream_t s);
-hipError_t launch_apply_rinv(const OrthDesc* d, int ntiles, int m, int bs, int pass,
-                             hipStream_t s);
+// Cholesky QR step of pass 1 (pivoted, thresholded: appends the accepted
+// directions of Y to Q and sets q, flag and the pivot record) or pass 2
+// (re-orthonormalises the new columns in place), from the partial Grams.
+hipError_t launch_orth_step(const OrthDesc* d, int ntiles, int m, int bs, int pass, double tau2,
+                            int r_min, int qcap, hipStream_t s);
 
 // Dynamic batching: stable compaction of the active list by the convergence
 // flags (flag[slot] != 0 removes the slot), then refill from the waiting
@@ -134,7 +133,16 @@ struct CopyDesc {
   const double* src;
   double* dst;
   int rows, cols, lds, ldd;
+  float* dst32 = nullptr;   // optional FP32 copy of the destination
+  int ldd32 = 0;
 };
+// Frobenius norm of a rows x cols block (ld) into *out.
+struct NormDesc {
+  const double* p;
+  int rows, cols, ld;
+  double* out;
+};
+hipError_t launch_fro_norms(const NormDesc* d, int n, hipStream_t s);
 hipError_t launch_copy_batched(const CopyDesc* d, int n, int max_cols, hipStream_t s);
 // dst = src (m x m) + shift on the first nreal diagonal entries.
 hipError_t launch_copy_shift(const double* src, double* dst, int m, int nreal, double shift,

@@ -24,6 +24,7 @@ TLR_ERR_STATE = -4
 TLR_ERR_NOT_SPD = 1
 TLR_ERR_ZERO_PIVOT = 2
 EPS_ABS, EPS_REL = 0, 1
+FP64, MIXED_FP32 = 0, 1
 FLAG_KERNEL_TIMING = 1
 KERNEL_EXP, KERNEL_MATERN15 = 0, 1
 INPUT, FACTOR = 0, 1
@@ -52,7 +53,7 @@ class Stats(ctypes.Structure):
                 ("max_rank", ctypes.c_int), ("mean_rank", ctypes.c_double),
                 ("factor_bytes", ctypes.c_double), ("sample_launches", ctypes.c_longlong),
                 ("sample_ms", ctypes.c_double), ("sample_bytes", ctypes.c_double),
-                ("sample_flops", ctypes.c_double)]
+                ("sample_flops", ctypes.c_double), ("fp32_tile_iters", ctypes.c_longlong)]
 
     def as_dict(self) -> Dict[str, float]:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -230,3 +230,46 @@ def test_relative_threshold_uses_norm_estimate():
     l = oracle_tlr(mat, tlr.FACTOR)
     err = np.linalg.norm(_residual_tiles(t, l), 2)
     assert err <= 2 * math.sqrt(t.nb) * st["tau"]
+
+
+def test_mixed_fp32_sampling_equal_accuracy():
+    # FP32 panels in the sampling (TLR_MIXED_FP32): at a relative threshold
+    # every tile passes the rounding guard; the factor must reach the same
+    # accuracy bound as the FP64 form, and about the same error
+    n, m, eps = 2048, 128, 1e-5
+    pts = wl.jittered_grid(n, 2, 21)
+    pts = np.ascontiguousarray(pts[wl.morton_order(pts)])
+    errs, stats = {}, {}
+    for prec in (tlr.FP64, tlr.MIXED_FP32):
+        mat = tlr.TLRMatrix.compress_kernel(pts, tlr.KERNEL_EXP, 0.1, 1e-4, m, eps)
+        a_t = oracle_tlr(mat, tlr.INPUT)
+        st = mat.potrf(eps, tlr.opts(eps_mode=tlr.EPS_REL, precision=prec))
+        l = oracle_tlr(mat, tlr.FACTOR)
+        errs[prec] = np.linalg.norm(_residual_tiles(a_t, l), 2)
+        stats[prec] = st
+    tau = stats[tlr.MIXED_FP32]["tau"]
+    assert stats[tlr.FP64]["fp32_tile_iters"] == 0
+    assert stats[tlr.MIXED_FP32]["fp32_tile_iters"] >= 0.9 * stats[tlr.MIXED_FP32]["tile_iters"]
+    nb = n // m
+    assert errs[tlr.MIXED_FP32] <= 2 * math.sqrt(nb) * tau
+    assert errs[tlr.MIXED_FP32] <= 2 * errs[tlr.FP64] + tau
+
+
+def test_mixed_guard_keeps_fp64_below_fp32_rounding():
+    # at a threshold far below FP32 rounding no tile may use the FP32 panels,
+    # and the mixed form then runs the FP64 kernels: identical factor
+    pts, a = _cov(1024, 17)
+    eps = 1e-10
+    t = otlr.compress_dense(a, 128, eps)
+    out = []
+    for prec in (tlr.FP64, tlr.MIXED_FP32):
+        mat = _upload(t)
+        st = mat.potrf(eps, tlr.opts(precision=prec))
+        out.append((st, mat.ranks(tlr.FACTOR), oracle_tlr(mat, tlr.FACTOR)))
+    assert out[1][0]["fp32_tile_iters"] == 0
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    for k in range(t.nb):
+        np.testing.assert_array_equal(out[0][2].diag[k], out[1][2].diag[k])
+        for i in range(k + 1, t.nb):
+            np.testing.assert_array_equal(out[0][2].u[i, k], out[1][2].u[i, k])
+            np.testing.assert_array_equal(out[0][2].v[i, k], out[1][2].v[i, k])
