@@ -372,8 +372,7 @@ tlr_status tlr_destroy(tlr_matrix_t A) {
   if (A->side) (void)hipStreamSynchronize(A->side);
   A->ws.release_all(mem);
   A->stage.release(mem);
-  if (A->pin_back) (void)hipHostFree(A->pin_back);
-  if (A->pin_norm) (void)hipHostFree(A->pin_norm);
+  A->release_host();
   if (A->ev_fork) (void)hipEventDestroy(A->ev_fork);
   if (A->ev_join) (void)hipEventDestroy(A->ev_join);
   if (A->side) (void)hipStreamDestroy(A->side);

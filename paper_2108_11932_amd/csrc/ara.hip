@@ -10,6 +10,7 @@
 //  * getConvergedTiles / updateSubset -- convergence flags and the stable
 //                       compaction + refill of the active subset
 //  * sortRanks       -- order of the tiles of a column by input rank
+#include "dd.h"
 #include "tlr_internal.h"
 
 // The double-double arithmetic below relies on error-free transformations
@@ -70,109 +71,25 @@ __global__ void k_philox_raw(unsigned* out, int n, unsigned k0, unsigned k1, uns
   out[4 * c + 3] = w.w;
 }
 
-// ------------------------------------------------------------ double-double
-// Error-free transformations (Knuth TwoSum, FMA-based TwoProduct) and the
-// double-double operations built on them (Dekker; Bailey's QD library).
-struct dd {
-  double hi, lo;
-};
-__device__ inline dd two_sum(double a, double b) {
-  const double s = a + b;
-  const double bb = s - a;
-  return {s, (a - (s - bb)) + (b - bb)};
-}
-__device__ inline dd fast_two_sum(double a, double b) {
-  const double s = a + b;
-  return {s, b - (s - a)};
-}
-__device__ inline dd two_prod(double a, double b) {
-  const double p = a * b;
-  return {p, fma(a, b, -p)};
-}
-__device__ inline dd dd_add(dd a, dd b) {
-  dd s = two_sum(a.hi, b.hi);
-  const dd t = two_sum(a.lo, b.lo);
-  s.lo += t.hi;
-  s = fast_two_sum(s.hi, s.lo);
-  s.lo += t.lo;
-  return fast_two_sum(s.hi, s.lo);
-}
-__device__ inline dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
-__device__ inline dd dd_sub(dd a, dd b) { return dd_add(a, dd_neg(b)); }
-__device__ inline dd dd_mul(dd a, dd b) {
-  dd p = two_prod(a.hi, b.hi);
-  p.lo += a.hi * b.lo + a.lo * b.hi;
-  return fast_two_sum(p.hi, p.lo);
-}
-__device__ inline dd dd_div(dd a, dd b) {
-  const double q1 = a.hi / b.hi;
-  dd r = dd_sub(a, dd_mul(b, dd{q1, 0.0}));
-  const double q2 = r.hi / b.hi;
-  r = dd_sub(r, dd_mul(b, dd{q2, 0.0}));
-  const double q3 = r.hi / b.hi;
-  const dd q = fast_two_sum(q1, q2);
-  return dd_add(q, dd{q3, 0.0});
-}
-__device__ inline dd dd_sqrt(dd a) {
-  if (!(a.hi > 0.0)) return {0.0, 0.0};
-  const double x = 1.0 / sqrt(a.hi);
-  const double ax = a.hi * x;
-  const dd diff = dd_sub(a, two_prod(ax, ax));
-  return fast_two_sum(ax, diff.hi * (x * 0.5));
-}
-
-// ------------------------------------------------------------ Gram matrices
-// Partial Gram sums X^T X over a block of rows, accumulated with the
-// compensated dot product of Ogita, Rump and Oishi (Dot2) and stored as
-// unevaluated (hi, lo) pairs.  X is the first `nc` columns of the block;
-// nc comes from the tile's pivot record when ncols_from_piv is set.
-constexpr int GRAM_ROWS = 64;
-constexpr int BS_MAX = 32;
-
-__global__ __launch_bounds__(256) void k_gram_dd(const OrthDesc* __restrict__ descs, int m, int bs,
-                                                 int pass, int nrb) {
-  __shared__ double X[BS_MAX][GRAM_ROWS + 1];
-  const OrthDesc d = descs[blockIdx.y];
-  const int rb = blockIdx.x;
-  const int r0 = rb * GRAM_ROWS;
-  const int rows = min(GRAM_ROWS, m - r0);
-  const double* src;
-  int nc;
-  if (pass == 1) {
-    src = d.Y;
-    nc = bs;
-  } else {
-    nc = d.piv[bs];
-    src = d.Q + (size_t)d.qold * m;
-  }
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nc * GRAM_ROWS; e += blockDim.x) {
-    const int r = e % GRAM_ROWS, c = e / GRAM_ROWS;
-    X[c][r] = (r < rows) ? src[(r0 + r) + (size_t)c * m] : 0.0;
-  }
-  __syncthreads();
+// Gram partials of a block of rows, one 16-row strip at a time: X (ld ldx)
+// holds rows [0, 16 nstrips) of the block in LDS, part receives, for strip
+// s, the Dot2 sums of X(16 s : 16 s + 16, a) . X(.., b) for a <= b < nc as
+// (hi, lo) at part + s * bs * bs * 2 + (a + b * bs) * 2.
+__device__ inline void strip_grams(const double* X, int ldx, int nstrips, int nc, int bs,
+                                   double* part) {
   const int npairs = nc * (nc + 1) / 2;
-  double* out = d.part + (size_t)rb * bs * bs * 2;
-  for (int pr = tid; pr < npairs; pr += blockDim.x) {
-    // pair index -> (a, b), a <= b, column-by-column upper triangle
+  for (int e = threadIdx.x; e < nstrips * npairs; e += blockDim.x) {
+    const int st = e / npairs, pr = e % npairs;
     int b = (int)((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
     while (b * (b + 1) / 2 > pr) --b;
     while ((b + 1) * (b + 2) / 2 <= pr) ++b;
     const int a = pr - b * (b + 1) / 2;
-    double s = 0.0, c = 0.0;
-    for (int r = 0; r < rows; ++r) {
-      const double x = X[a][r], y = X[b][r];
-      const double p = x * y;
-      const double e = fma(x, y, -p);
-      const double t = s + p;
-      const double z = t - s;
-      const double q = (s - (t - z)) + (p - z);
-      s = t;
-      c += q + e;
-    }
-    const dd v = fast_two_sum(s, c);
-    out[(a + b * bs) * 2 + 0] = v.hi;
-    out[(a + b * bs) * 2 + 1] = v.lo;
+    double sh = 0.0, sl = 0.0;
+    for (int r = 0; r < 16; ++r) dot2_step(X[16 * st + r + a * ldx], X[16 * st + r + b * ldx], sh, sl);
+    const dd v = fast_two_sum(sh, sl);
+    double* o = part + (size_t)st * bs * bs * 2 + (a + b * bs) * 2;
+    o[0] = v.hi;
+    o[1] = v.lo;
   }
 }
 
@@ -202,21 +119,28 @@ __global__ __launch_bounds__(256) void k_gram_dd(const OrthDesc* __restrict__ de
 constexpr int APPLY_ROWS = 256;
 
 template <int BS, bool PIV>
-__global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(const OrthDesc* __restrict__ descs, int m,
-                                                          int nrb, double tau2, int r_min,
-                                                          int qcap) {
+__global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2, int r_min) {
   constexpr int NG = APPLY_ROWS / BS;
   constexpr int CPG = (BS + NG - 1) / NG;
+  constexpr int XR = 64;   // rows of X staged at a time for the pass-1 strip Grams
   __shared__ dd Gs[BS][BS + 1];
   __shared__ double Lm[BS][BS + 1];   // Lm[j][b]: multiplier of column b at step j
   __shared__ double Rs[BS][BS + 1];   // R(a, c), a <= c
+  __shared__ double Xs[BS][XR + 1];
   __shared__ int perm[BS];
-  const OrthDesc d = descs[blockIdx.y];
+  if ((int)blockIdx.y >= D.counts[0]) return;
+  const int slot = D.act[blockIdx.y];
+  const AraSlotDesc& d = D.slots[slot];
+  const int m = D.m, qcap = D.qcap, nrb = D.nstrip;
+  const int qold = D.q[slot];
+  const double* part = PIV ? d.part1 : d.part2;
   const int t = threadIdx.x;
   const int x = t % BS, g = t / BS;
   const int nc = PIV ? BS : d.piv[BS];
   if (nc == 0) return;
   // ---- sum of the partial Gram matrices (stored for a <= b)
+  // (loads in chunks of PCH partials, all in flight before the sums)
+  constexpr int PCH = 16;
   dd gv[CPG];
 #pragma unroll
   for (int i = 0; i < CPG; ++i) {
@@ -224,10 +148,19 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(const OrthDesc* __rest
     dd acc{0.0, 0.0};
     if (g < NG && b < nc && x < nc) {
       const int lo = min(x, b), hi = max(x, b);
-      const double* pp = d.part + (size_t)(lo + hi * BS) * 2;
-      for (int rb = 0; rb < nrb; ++rb) {
-        const double* q2 = pp + (size_t)rb * BS * BS * 2;
-        acc = dd_add(acc, dd{q2[0], q2[1]});
+      const double* pp = part + (size_t)(lo + hi * BS) * 2;
+      for (int rb0 = 0; rb0 < nrb; rb0 += PCH) {
+        double ph[PCH], pl[PCH];
+#pragma unroll
+        for (int u = 0; u < PCH; ++u) {
+          const double* q2 = pp + (size_t)min(rb0 + u, nrb - 1) * BS * BS * 2;
+          ph[u] = q2[0];
+          pl[u] = q2[1];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < PCH; ++u)
+          if (rb0 + u < nrb) acc = dd_add(acc, dd{ph[u], pl[u]});
       }
     }
     gv[i] = acc;
@@ -240,7 +173,7 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(const OrthDesc* __rest
   __syncthreads();
   int np = 0;
   if (PIV) {
-    const int room = max(0, qcap - d.qold);
+    const int room = max(0, qcap - qold);
     unsigned taken = 0u;
     for (int j = 0; j < BS && j < room; ++j) {
       // pivot: largest remaining diagonal, ties to the lowest column
@@ -292,8 +225,10 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(const OrthDesc* __rest
       if (t < BS) d.piv[t] = perm[t];
       if (t == 0) {
         d.piv[BS] = np;
-        *d.q = d.qold + np;
-        *d.flag = ((np <= BS - r_min) || (d.qold + np >= qcap)) ? 1 : 0;
+        D.qnew[slot] = qold + np;
+        D.flag[slot] = ((np <= BS - r_min) || (qold + np >= qcap)) ? 1 : 0;
+        D.iters[slot] += 1;
+        D.qsum[slot] += qold;
       }
     }
   } else {
@@ -328,36 +263,54 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(const OrthDesc* __rest
   // ---- apply: rows of Q_new from Y_P = Q_new R (pass 1) or X = Q_new R
   // (pass 2, in place), by forward substitution along the row
   const int r = blockIdx.x * APPLY_ROWS + t;
-  if (r >= m || np == 0) return;
-  double* dst = d.Q + (size_t)d.qold * m;
+  if (np == 0) return;
+  double* dst = d.q + (size_t)qold * m;
   double xv[BS];
 #pragma unroll
-  for (int a = 0; a < BS; ++a)
-    if (a < np) xv[a] = PIV ? d.Y[r + (size_t)perm[a] * m] : dst[r + (size_t)a * m];
+  for (int a = 0; a < BS; ++a) xv[a] = 0.0;
+  if (r < m) {
 #pragma unroll
-  for (int c = 0; c < BS; ++c) {
-    if (c < np) {
-      double v = xv[c];
+    for (int a = 0; a < BS; ++a)
+      if (a < np) xv[a] = PIV ? d.y[r + (size_t)perm[a] * m] : dst[r + (size_t)a * m];
 #pragma unroll
-      for (int a = 0; a < c; ++a) v = fma(-xv[a], Rs[a][c], v);
-      v = v / Rs[c][c];
-      xv[c] = v;
-      dst[r + (size_t)c * m] = v;
+    for (int c = 0; c < BS; ++c) {
+      if (c < np) {
+        double v = xv[c];
+#pragma unroll
+        for (int a = 0; a < c; ++a) v = fma(-xv[a], Rs[a][c], v);
+        v = v / Rs[c][c];
+        xv[c] = v;
+        dst[r + (size_t)c * m] = v;
+      }
+    }
+  }
+  // pass 1 on an empty basis: no block Gram-Schmidt step follows, so the
+  // Gram partials of the new columns for pass 2 are formed here
+  if (PIV && qold == 0) {
+    for (int h = 0; h < APPLY_ROWS / XR; ++h) {
+      if (t / XR == h) {
+#pragma unroll
+        for (int a = 0; a < BS; ++a) Xs[a][t % XR] = xv[a];
+      }
+      __syncthreads();
+      const int strip0 = (blockIdx.x * APPLY_ROWS + h * XR) / 16;
+      const int ns = min(XR / 16, nrb - strip0);
+      if (ns > 0)
+        strip_grams(&Xs[0][0], XR + 1, ns, np, BS, d.part2 + (size_t)strip0 * BS * BS * 2);
+      __syncthreads();
     }
   }
 }
 
 // ------------------------------------------------------- dynamic batching
 // Stable compaction of the active list (slots whose flag is set leave) and
-// refill from the waiting list, keeping at most s_max tiles.  One workgroup.
-__global__ __launch_bounds__(256) void k_compact(int* act, int* counts, const int* flag,
-                                                 const int* waiting, int nwaiting, int s_max,
-                                                 const int* info) {
-  __shared__ int keep_total;
-  __shared__ int scan[256];
+// refill from the waiting list, keeping at most s_max tiles.  Run by one
+// whole workgroup of 256 threads.
+__device__ inline void compact_active(int* act, int* counts, const int* flag, const int* waiting,
+                                      int nwaiting, int s_max, int* keep_total, int* scan) {
   const int tid = threadIdx.x;
   const int n = counts[0];
-  if (tid == 0) keep_total = 0;
+  if (tid == 0) *keep_total = 0;
   __syncthreads();
   // in-place stable compaction, processed in chunks of 256 entries; writes
   // never overtake reads because pos <= index
@@ -376,15 +329,15 @@ __global__ __launch_bounds__(256) void k_compact(int* act, int* counts, const in
       scan[tid] += v;
       __syncthreads();
     }
-    const int pos = keep_total + scan[tid] - keep;
+    const int pos = *keep_total + scan[tid] - keep;
     const int chunk_keep = scan[255];
     __syncthreads();
     if (keep) act[pos] = slot;
     __syncthreads();
-    if (tid == 0) keep_total += chunk_keep;
+    if (tid == 0) *keep_total += chunk_keep;
     __syncthreads();
   }
-  const int kept = keep_total;
+  const int kept = *keep_total;
   const int cursor = counts[1];
   const int take = max(0, min(min(n - kept, s_max - kept), nwaiting - cursor));
   for (int j = tid; j < take; j += blockDim.x) act[kept + j] = waiting[cursor + j];
@@ -392,7 +345,46 @@ __global__ __launch_bounds__(256) void k_compact(int* act, int* counts, const in
   if (tid == 0) {
     counts[0] = kept + take;
     counts[1] = cursor + take;
-    if (info) counts[2] = *info;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_compact(int* act, int* counts, const int* flag,
+                                                 const int* waiting, int nwaiting, int s_max,
+                                                 const int* info) {
+  __shared__ int keep_total;
+  __shared__ int scan[256];
+  compact_active(act, counts, flag, waiting, nwaiting, s_max, &keep_total, scan);
+  if (threadIdx.x == 0 && info) counts[2] = *info;
+}
+
+// End of an ARA iteration: commit the basis widths of the slots that ran,
+// compact and refill, then record the status word and the largest basis
+// width among the active slots (the host's bound for the next products).
+__global__ __launch_bounds__(256) void k_ara_compact(AraDev D, const int* waiting, int nwaiting,
+                                                     int s_max, const int* info) {
+  __shared__ int keep_total;
+  __shared__ int scan[256];
+  const int tid = threadIdx.x;
+  const int n = D.counts[0];
+  for (int i = tid; i < n; i += 256) {
+    const int slot = D.act[i];
+    D.q[slot] = D.qnew[slot];
+  }
+  __syncthreads();
+  compact_active(D.act, D.counts, D.flag, waiting, nwaiting, s_max, &keep_total, scan);
+  const int na = D.counts[0];
+  int qm = 0;
+  for (int i = tid; i < na; i += 256) qm = max(qm, D.q[D.act[i]]);
+  scan[tid] = qm;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) scan[tid] = max(scan[tid], scan[tid + w]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    D.counts[3] = scan[0];
+    D.counts[2] = info ? *info : 0;
   }
 }
 
@@ -430,16 +422,6 @@ hipError_t launch_philox_raw(unsigned* out, int n, unsigned long long seed, unsi
   return hipGetLastError();
 }
 
-int gram_row_blocks(int m) { return (m + GRAM_ROWS - 1) / GRAM_ROWS; }
-
-hipError_t launch_gram_dd(const OrthDesc* d, int ntiles, int m, int bs, int pass, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  if (bs > BS_MAX) return hipErrorInvalidValue;
-  const int nrb = gram_row_blocks(m);
-  hipLaunchKernelGGL(k_gram_dd, dim3(nrb, ntiles), dim3(256), 0, s, d, m, bs, pass, nrb);
-  return hipGetLastError();
-}
-
 // KERNEL is a template-id whose block-size argument is spelled BS_ARG.
 #define TLR_BS_CASE(v, KERNEL, ...)                    \
   case v: {                                            \
@@ -463,18 +445,22 @@ bool orth_block_supported(int bs) {
   return bs == 1 || bs == 2 || bs == 4 || bs == 8 || bs == 16 || bs == 24 || bs == 32;
 }
 
-hipError_t launch_orth_step(const OrthDesc* d, int ntiles, int m, int bs, int pass, double tau2,
-                            int r_min, int qcap, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  const int nrb = gram_row_blocks(m);
-  const dim3 grid((m + APPLY_ROWS - 1) / APPLY_ROWS, ntiles);
+hipError_t launch_orth_step(const AraDev& D, int pass, double tau2, int r_min, int count_bound,
+                            hipStream_t s) {
+  if (count_bound <= 0) return hipSuccess;
+  const dim3 grid((D.m + APPLY_ROWS - 1) / APPLY_ROWS, count_bound);
   if (pass == 1) {
-    TLR_BS_DISPATCH(bs, (k_orth_step<BS_ARG, true>), grid, dim3(APPLY_ROWS), 0, s, d, m, nrb, tau2,
-                    r_min, qcap);
+    TLR_BS_DISPATCH(D.bs, (k_orth_step<BS_ARG, true>), grid, dim3(APPLY_ROWS), 0, s, D, tau2, r_min);
   } else {
-    TLR_BS_DISPATCH(bs, (k_orth_step<BS_ARG, false>), grid, dim3(APPLY_ROWS), 0, s, d, m, nrb, tau2,
-                    r_min, qcap);
+    TLR_BS_DISPATCH(D.bs, (k_orth_step<BS_ARG, false>), grid, dim3(APPLY_ROWS), 0, s, D, tau2,
+                    r_min);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_ara_compact(const AraDev& D, const int* waiting, int nwaiting, int s_max,
+                              const int* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_ara_compact, dim3(1), dim3(256), 0, s, D, waiting, nwaiting, s_max, info);
   return hipGetLastError();
 }
 

@@ -1,5 +1,7 @@
-// Batched ARA loop with device-side dynamic batching (see ara_engine.h).
+// Device-driven batched ARA loop with dynamic batching (see ara_engine.h).
 #include "ara_engine.h"
+
+#include <algorithm>
 
 namespace tlr {
 
@@ -8,10 +10,11 @@ static size_t al(size_t n) { return (n + 63) & ~(size_t)63; }
 tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   Work& w = h->ws;
   const int m = c.m, bs = c.bs;
-  const int nrb = gram_row_blocks(m);
+  const int nstrip = (m + 15) / 16;
   s->n = n;
   s->m = m;
   s->bs = bs;
+  s->nstrip = nstrip;
   s->qstride = (size_t)m * (c.qcap + bs);
   const size_t nn = n > 0 ? (size_t)n : 1;
   TLR_TRY(w.Y.ensure(h->mem, sizeof(double) * nn * m * bs));
@@ -19,21 +22,29 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   const bool fresh_q = w.Q.cap < sizeof(double) * nn * s->qstride;
   TLR_TRY(w.Q.ensure(h->mem, sizeof(double) * nn * s->qstride));
   if (fresh_q) TLR_HIP(hipMemsetAsync(w.Q.p, 0, w.Q.cap, h->stream));
-  TLR_TRY(w.part.ensure(h->mem, sizeof(double) * nn * nrb * bs * bs * 2));
-  const size_t nint = 4 + 2 * nn + al(nn) + al(nn * (bs + 1)) + al(nn) + 64;
+  const size_t pn = nn * nstrip * bs * bs * 2;
+  TLR_TRY(w.part.ensure(h->mem, sizeof(double) * 2 * pn));
+  const size_t nint = 8 + 6 * al(nn) + al(nn * (bs + 1)) + al(nn) + 64;
   TLR_TRY(w.ints.ensure(h->mem, sizeof(int) * nint));
   s->Y = w.Y.as<double>();
   s->C = w.C.as<double>();
   s->Q = w.Q.as<double>();
-  s->part = w.part.as<double>();
+  s->part1 = w.part.as<double>();
+  s->part2 = s->part1 + pn;
   int* ip = w.ints.as<int>();
   s->counts = ip;
-  ip += 4;
+  ip += 8;
   s->act = ip;
-  ip += nn;
-  s->qv = ip;
-  ip += nn;
+  ip += al(nn);
+  s->q = ip;   // q, qnew, flag, iters, qsum are contiguous (cleared together)
+  ip += al(nn);
+  s->qnew = ip;
+  ip += al(nn);
   s->flag = ip;
+  ip += al(nn);
+  s->iters = ip;
+  ip += al(nn);
+  s->qsum = ip;
   ip += al(nn);
   s->piv = ip;
   ip += al(nn * (bs + 1));
@@ -41,140 +52,228 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   return TLR_OK;
 }
 
+tlr_status ara_omega(Handle* h, const AraConfig& c, double** omega) {
+  TLR_TRY(h->ws.omega.ensure(h->mem, sizeof(double) * (size_t)c.m * c.bs));
+  *omega = h->ws.omega.as<double>();
+  return TLR_OK;
+}
+
+tlr_status ara_explicit_spec(Handle* h, const AraConfig& c, int n, const double* tiles, int ld,
+                             AraSpec* spec) {
+  double* omega = nullptr;
+  TLR_TRY(ara_omega(h, c, &omega));
+  const int m = c.m, bs = c.bs;
+  spec->slots.assign(n, AraSlotDesc{});
+  spec->samp_flops.assign(n, 2.0 * m * (double)m * bs);
+  spec->samp_bytes.assign(n, 8.0 * ((double)m * m + 2.0 * m * bs));
+  for (int t = 0; t < n; ++t) {
+    AraSlotDesc& d = spec->slots[t];
+    d.a0 = tiles + (size_t)t * ld * m;
+    d.lda0 = ld;
+    d.k0 = m;
+    d.b0 = omega;
+    d.ldb0 = m;
+    d.lda1 = 1;
+    d.ldb1 = 1;
+  }
+  return TLR_OK;
+}
+
+namespace {
+
+// Host-side knowledge of the device state after some iteration.
+struct Known {
+  int iter = -1;    // the iteration whose end state this is (-1: the start)
+  int count = 0;    // active slots
+  int cursor = 0;   // waiting-list cursor
+  int info = 0;     // status word
+  int qmax = 0;     // largest basis width among the active slots
+};
+
+}  // namespace
+
 tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::vector<int>& order,
-                   const SampleFn& sample, AraResult* res, bool* info_abort) {
+                   AraSpec& spec, AraResult* res, bool* info_abort,
+                   const std::function<tlr_status()>& idle) {
   const int n = (int)order.size();
   const int m = c.m, bs = c.bs;
-  const int nrb = gram_row_blocks(m);
-  const int s_max = c.s_max > 0 ? (c.s_max < n ? c.s_max : n) : n;
+  const int s_max = c.s_max > 0 ? std::min(c.s_max, n) : n;
   res->q.assign(n, 0);
   res->iters.assign(n, 0);
   res->flops_paper_orth.assign(n, 0.0);
   if (info_abort) *info_abort = false;
   if (n == 0) return TLR_OK;
-
-  Work& w = h->ws;
-  TLR_TRY(w.omega.ensure(h->mem, sizeof(double) * (size_t)m * bs));
-  double* omega = w.omega.as<double>();
-
-  // initial active list and waiting list (slots in sorted order)
-  std::vector<int> act(order.begin(), order.begin() + s_max);
-  std::vector<int> waiting(order.begin() + s_max, order.end());
-  {
-    // q = 0 and flag = 0 for all slots
-    TLR_HIP(hipMemsetAsync(s.qv, 0, sizeof(int) * n, h->stream));
-    TLR_HIP(hipMemsetAsync(s.flag, 0, sizeof(int) * n, h->stream));
-    int hdr[2] = {s_max, 0};
-    void* tmp = nullptr;
-    TLR_TRY(h->stage.upload(h, act.data(), sizeof(int) * act.size(), &tmp));
-    TLR_HIP(hipMemcpyAsync(s.act, tmp, sizeof(int) * act.size(), hipMemcpyDeviceToDevice, h->stream));
-    if (!waiting.empty()) {
-      TLR_TRY(h->stage.upload(h, waiting.data(), sizeof(int) * waiting.size(), &tmp));
-      TLR_HIP(hipMemcpyAsync(s.waiting, tmp, sizeof(int) * waiting.size(), hipMemcpyDeviceToDevice,
-                             h->stream));
-    }
-    TLR_TRY(h->stage.upload(h, hdr, sizeof hdr, &tmp));
-    TLR_HIP(hipMemcpyAsync(s.counts, tmp, sizeof hdr, hipMemcpyDeviceToDevice, h->stream));
-  }
-  std::vector<int>& q = res->q;
-
-  // read-back block: counts[2], status word, pad, act[ns], q[ns], laid out for
-  // the slot capacity ns >= n
-  const int ns = s.n;
-  if (n > ns) {
-    set_error("ARA batch of %d tiles exceeds the %d workspace slots", n, ns);
+  if (n > s.n || (int)spec.slots.size() != n) {
+    set_error("ARA batch of %d tiles does not match the %d workspace slots", n, s.n);
     return TLR_ERR_STATE;
   }
-  int* pinned = nullptr;
-  TLR_TRY(h->pinned_ints(4 + 2 * (size_t)ns, &pinned));
+  Work& w = h->ws;
+  hipStream_t st = h->stream;
+  double* omega = nullptr;
+  TLR_TRY(ara_omega(h, c, &omega));
 
-  unsigned t = 0;
-  bool first = true;
-  while (!act.empty()) {
-    const int na = (int)act.size();
-    Plan plan(h);
-    const unsigned tt = t;
-    plan.launch([=]() { return launch_randn(omega, m, bs, m, c.seed, c.stream_id, tt, 0, h->stream); });
-    TLR_TRY(sample(act, omega, plan));
+  // ---- static slot descriptors, uploaded once for the run
+  for (int sl = 0; sl < n; ++sl) {
+    AraSlotDesc& d = spec.slots[sl];
+    d.y = s.y(sl);
+    d.q = s.qb(sl);
+    d.c = s.c(sl);
+    d.part1 = s.p1(sl);
+    d.part2 = s.p2(sl);
+    d.piv = s.piv + (size_t)sl * (bs + 1);
+  }
+  const size_t sbytes = sizeof(AraSlotDesc) * n;
+  const size_t zbytes = sizeof(ZSeg) * spec.zseg.size();
+  const size_t zoff = (sbytes + 255) & ~(size_t)255;
+  TLR_TRY(w.orth.ensure(h->mem, zoff + zbytes + 256));
+  char* dbase = (char*)w.orth.p;
+  {
+    void* tmp = nullptr;
+    TLR_TRY(h->stage.upload(h, spec.slots.data(), sbytes, &tmp));
+    TLR_HIP(hipMemcpyAsync(dbase, tmp, sbytes, hipMemcpyDeviceToDevice, st));
+    if (zbytes) {
+      TLR_TRY(h->stage.upload(h, spec.zseg.data(), zbytes, &tmp));
+      TLR_HIP(hipMemcpyAsync(dbase + zoff, tmp, zbytes, hipMemcpyDeviceToDevice, st));
+    }
+  }
+  const ZSeg* dzseg = (const ZSeg*)(dbase + zoff);
 
-    // block Gram-Schmidt, pass 1: Y -= Q (Q^T Y)
-    {
-      GemmBatch c1(true, false);
-      SegBatch c2;
-      for (int sl : act)
-        if (q[sl] > 0) {
-          c1.add(q[sl], bs, m, s.q(sl), m, s.y(sl), m, s.c(sl), m, -1.0, 0.0);
-          c2.add(m, bs, s.q(sl), m, s.c(sl), m, q[sl], nullptr, 1, nullptr, 1, 0, s.y(sl), m, 1.0);
-        }
-      plan.gemm(c1);
-      plan.seg(c2);
+  // ---- initial state: active list, waiting list, cleared counters
+  std::vector<int> act(order.begin(), order.begin() + s_max);
+  std::vector<int> waiting(order.begin() + s_max, order.end());
+  const int nwait = (int)waiting.size();
+  {
+    TLR_HIP(hipMemsetAsync(s.q, 0, sizeof(int) * (size_t)(s.piv - s.q), st));
+    int hdr[8] = {s_max, 0, 0, 0, 0, 0, 0, 0};
+    void* tmp = nullptr;
+    TLR_TRY(h->stage.upload(h, act.data(), sizeof(int) * act.size(), &tmp));
+    TLR_HIP(hipMemcpyAsync(s.act, tmp, sizeof(int) * act.size(), hipMemcpyDeviceToDevice, st));
+    if (nwait > 0) {
+      TLR_TRY(h->stage.upload(h, waiting.data(), sizeof(int) * nwait, &tmp));
+      TLR_HIP(hipMemcpyAsync(s.waiting, tmp, sizeof(int) * nwait, hipMemcpyDeviceToDevice, st));
     }
-    std::vector<OrthDesc> od(na);
-    for (int a = 0; a < na; ++a) {
-      const int sl = act[a];
-      od[a] = OrthDesc{s.y(sl), s.q(sl), q[sl], s.qv + sl, s.flag + sl,
-                       s.part + (size_t)sl * nrb * bs * bs * 2, s.piv + (size_t)sl * (bs + 1)};
+    TLR_TRY(h->stage.upload(h, hdr, sizeof hdr, &tmp));
+    TLR_HIP(hipMemcpyAsync(s.counts, tmp, sizeof hdr, hipMemcpyDeviceToDevice, st));
+  }
+  int* ring = nullptr;
+  TLR_TRY(h->readback_ring(&ring));
+
+  AraDev D;
+  D.slots = (const AraSlotDesc*)dbase;
+  D.act = s.act;
+  D.counts = s.counts;
+  D.q = s.q;
+  D.qnew = s.qnew;
+  D.flag = s.flag;
+  D.iters = s.iters;
+  D.qsum = s.qsum;
+  D.m = m;
+  D.bs = bs;
+  D.qcap = c.qcap;
+  D.nstrip = s.nstrip;
+  const double tau2 = c.tau * c.tau;
+  const int p_blocks = spec.rk > 0 ? (spec.rk + 31) / 32 : 0;
+  const int bps_wa = (spec.a_max + 31) / 32;
+  const int bps_z = (spec.r_max + 63) / 64;
+  const bool any_z = !spec.zseg.empty() && bps_z > 0 && spec.rk > 0;
+  int* info = h->d_info;
+
+  Known known;
+  known.count = s_max;
+  // enqueue iteration j with launch bounds derived from `known`: the active
+  // count can only grow by refills, a basis by at most bs per iteration
+  auto enqueue = [&](int j) -> tlr_status {
+    const int cb = (known.cursor >= nwait) ? known.count : s_max;
+    const int qb = std::min(c.qcap, known.qmax + bs * (j - known.iter - 1));
+    TLR_HIP(launch_randn(omega, m, bs, m, c.seed, c.stream_id, (unsigned)j, 0, st));
+    if (p_blocks > 0 || bps_wa > 0)
+      TLR_HIP(launch_ara_tn(D, 0, omega, spec.uk, spec.rk, spec.p, p_blocks, cb, bps_wa, st));
+    if (any_z) TLR_HIP(launch_ara_z(D, dzseg, spec.p, spec.rk, cb, bps_z, st));
+    hipEvent_t e1 = nullptr;
+    if (spec.events) {
+      hipEvent_t e0;
+      TLR_HIP(hipEventCreate(&e0));
+      TLR_HIP(hipEventCreate(&e1));
+      spec.events->push_back({e0, e1});
+      TLR_HIP(hipEventRecord(e0, st));
     }
-    const size_t ood = plan.stage(od.data(), sizeof(OrthDesc) * na);
-    hipStream_t st = h->stream;
-    const double tau2 = c.tau * c.tau;
-    const int r_min = c.r_min, qcap = c.qcap;
-    plan.launch(ood, [=](const char* p) { return launch_gram_dd((const OrthDesc*)p, na, m, bs, 1, st); });
-    plan.launch(ood, [=](const char* p) {
-      return launch_orth_step((const OrthDesc*)p, na, m, bs, 1, tau2, r_min, qcap, st);
-    });
-    // pass 2 on the new columns X = Q[:, qold : qold + bs]
-    {
-      GemmBatch c1(true, false);
-      SegBatch c2;
-      for (int sl : act)
-        if (q[sl] > 0) {
-          double* X = s.q(sl) + (size_t)q[sl] * m;
-          c1.add(q[sl], bs, m, s.q(sl), m, X, m, s.c(sl), m, -1.0, 0.0);
-          c2.add(m, bs, s.q(sl), m, s.c(sl), m, q[sl], nullptr, 1, nullptr, 1, 0, X, m, 1.0);
-        }
-      plan.gemm(c1);
-      plan.seg(c2);
+    TLR_HIP(launch_ara_seg(D, 0, cb, st));
+    if (e1) TLR_HIP(hipEventRecord(e1, st));
+    const int bps_q = (qb + 31) / 32;
+    if (bps_q > 0) {
+      TLR_HIP(launch_ara_tn(D, 1, nullptr, nullptr, 0, nullptr, 0, cb, bps_q, st));
+      TLR_HIP(launch_ara_seg(D, 1, cb, st));
     }
-    plan.launch(ood, [=](const char* p) { return launch_gram_dd((const OrthDesc*)p, na, m, bs, 2, st); });
-    plan.launch(ood, [=](const char* p) {
-      return launch_orth_step((const OrthDesc*)p, na, m, bs, 2, tau2, r_min, qcap, st);
-    });
-    // convergence flags -> compaction and refill on the device
-    const int nwait = (int)waiting.size(), smax = s_max;
-    int* info = h->d_info;
-    plan.launch([=]() { return launch_compact(s.act, s.counts, s.flag, s.waiting, nwait, smax, info, st); });
-    TLR_TRY(plan.run());
-    res->flops += plan.flops;
-    for (int sl : act) {
-      // two Gram matrices, pivoted factor, two projections and the R^{-1} products
-      const double qq = q[sl];
-      const double orth = 2.0 * (4.0 * m * qq * bs + 3.0 * m * (double)bs * bs);
-      res->flops_paper_orth[sl] += orth;
-      res->flops += orth;
-      res->iters[sl] += 1;
+    TLR_HIP(launch_orth_step(D, 1, tau2, c.r_min, cb, st));
+    if (bps_q > 0) {
+      TLR_HIP(launch_ara_tn(D, 2, nullptr, nullptr, 0, nullptr, 0, cb, bps_q, st));
+      TLR_HIP(launch_ara_seg(D, 2, cb, st));
     }
-    TLR_HIP(hipMemcpyAsync(pinned, s.counts, sizeof(int) * (4 + 2 * (size_t)ns),
-                           hipMemcpyDeviceToHost, h->stream));
-    TLR_TRY(h->sync_main());
-    const int cnt = pinned[0];
-    if (cnt < 0 || cnt > n) {
-      set_error("ARA compaction returned an invalid active count %d", cnt);
+    TLR_HIP(launch_orth_step(D, 2, tau2, c.r_min, cb, st));
+    TLR_HIP(launch_ara_compact(D, s.waiting, nwait, s_max, info, st));
+    TLR_HIP(hipMemcpyAsync(ring + 8 * (j & 1), s.counts, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+    TLR_HIP(hipEventRecord(h->ev_rb[j & 1], st));
+    return TLR_OK;
+  };
+
+  const long long limit = (long long)n * (c.qcap + 1) + 1;
+  int enq = 0;
+  TLR_TRY(enqueue(0));
+  for (;;) {
+    // keep one iteration queued ahead of the state being read back
+    TLR_TRY(enqueue(enq + 1));
+    ++enq;
+    if (idle) TLR_TRY(idle());
+    const int j = known.iter + 1;
+    TLR_HIP(hipEventSynchronize(h->ev_rb[j & 1]));
+    const int* r = ring + 8 * (j & 1);
+    known.iter = j;
+    known.count = r[0];
+    known.cursor = r[1];
+    known.info = r[2];
+    known.qmax = r[3];
+    if (known.count < 0 || known.count > n) {
+      set_error("ARA compaction returned an invalid active count %d", known.count);
       return TLR_ERR_DEVICE;
     }
-    if (first && info_abort && pinned[2] != 0) {
+    if (j == 0 && info_abort && known.info != 0) {
       *info_abort = true;
-      return TLR_OK;
+      break;
     }
-    first = false;
-    act.assign(pinned + 4, pinned + 4 + cnt);
-    for (int i = 0; i < n; ++i) q[i] = pinned[4 + ns + i];
-    ++t;
-    res->launches += 1;
-    if ((long long)t > (long long)n * (c.qcap + 1) + 1) {
-      set_error("ARA did not converge within %u iterations", t);
+    if (known.count == 0) break;
+    if (j > limit) {
+      set_error("ARA did not converge within %d iterations", j);
       return TLR_ERR_DEVICE;
     }
+  }
+  res->launches = known.iter + 1;
+  // the iterations enqueued past the last active one found nothing to do
+  if (spec.events)
+    while ((int)spec.events->size() > known.iter + 1) {
+      (void)hipEventDestroy(spec.events->back().first);
+      (void)hipEventDestroy(spec.events->back().second);
+      spec.events->pop_back();
+    }
+
+  // ---- results: basis widths, iteration counts, summed widths
+  const size_t stride = (size_t)(s.qnew - s.q);
+  std::vector<int> back(5 * stride);
+  TLR_HIP(hipMemcpyAsync(back.data(), s.q, sizeof(int) * back.size(), hipMemcpyDeviceToHost, st));
+  TLR_TRY(h->sync_main());
+  const int* bq = back.data();
+  const int* bit = back.data() + 3 * stride;
+  const int* bqs = back.data() + 4 * stride;
+  for (int sl = 0; sl < n; ++sl) {
+    res->q[sl] = bq[sl];
+    res->iters[sl] = bit[sl];
+    const double it = bit[sl], qs = bqs[sl];
+    // two Gram-Schmidt passes, each a projection and an update, plus the
+    // Gram matrices and the triangular solves of the Cholesky QR steps
+    const double orth = 8.0 * m * bs * qs + 6.0 * m * (double)bs * bs * it;
+    res->flops_paper_orth[sl] = orth;
+    res->flops += orth + it * spec.samp_flops[sl];
+    res->samp_bytes += it * spec.samp_bytes[sl];
+    res->samp_flops += it * spec.samp_flops[sl];
   }
   return TLR_OK;
 }

@@ -8,7 +8,14 @@
 // samples against the current bases by two passes of block Gram-Schmidt
 // whose QR steps are Cholesky QR with a double-double Gram (pass 1 pivoted
 // and thresholded), appends the new directions, flags the converged tiles
-// and compacts/refills the active subset on the device.
+// and compacts/refills the active subset.
+//
+// The loop is device-driven: the active list, its count and the basis widths
+// live in device memory and every kernel of an iteration reads them, so the
+// host enqueues iteration t + 1 before it reads back the state after
+// iteration t (one iteration of lookahead; a speculative iteration after
+// convergence finds no active tile and does nothing).  Launch sizes come
+// from host-side bounds on the active count and basis widths.
 #pragma once
 
 #include <functional>
@@ -28,25 +35,46 @@ struct AraConfig {
   unsigned stream_id = 0;   // Philox counter word 2 (column index or batch id)
 };
 
-// Per-slot buffers of one ARA batch (views into the handle's workspace).
+// Per-slot workspace of an ARA batch (views into the handle's workspace).
 struct AraSlots {
   int n = 0;
-  int m = 0, bs = 0;
-  double* Y = nullptr;   // n x (m x bs)
-  double* Q = nullptr;   // n x (m x (qcap + bs))
-  double* C = nullptr;   // n x (m x bs)
-  double* part = nullptr;
-  // contiguous read-back block: counts[2], status word copy, pad, act[n], qv[n]
-  int* counts = nullptr; // 2 (+ 2)
-  int* act = nullptr;    // n
-  int* qv = nullptr;     // n
-  int* flag = nullptr;   // n
-  int* piv = nullptr;    // n x (bs + 1)
-  int* waiting = nullptr;// n
-  size_t qstride = 0;    // doubles per slot in Q
+  int m = 0, bs = 0, nstrip = 0;
+  double* Y = nullptr;      // n x (m x bs)
+  double* Q = nullptr;      // n x (m x (qcap + bs))
+  double* C = nullptr;      // n x (m x bs)
+  double* part1 = nullptr;  // n x (nstrip x bs x bs x 2)
+  double* part2 = nullptr;
+  int* counts = nullptr;    // 8
+  int* act = nullptr;       // n
+  int* q = nullptr;         // n
+  int* qnew = nullptr;      // n
+  int* flag = nullptr;      // n
+  int* iters = nullptr;     // n
+  int* qsum = nullptr;      // n
+  int* piv = nullptr;       // n x (bs + 1)
+  int* waiting = nullptr;   // n
+  size_t qstride = 0;       // doubles per slot in Q
   double* y(int s) const { return Y + (size_t)s * m * bs; }
-  double* q(int s) const { return Q + (size_t)s * qstride; }
+  double* qb(int s) const { return Q + (size_t)s * qstride; }
   double* c(int s) const { return C + (size_t)s * m * bs; }
+  double* p1(int s) const { return part1 + (size_t)s * nstrip * bs * bs * 2; }
+  double* p2(int s) const { return part2 + (size_t)s * nstrip * bs * bs * 2; }
+};
+
+// What each slot samples, fixed for the whole run.  The caller fills the
+// sampling fields of every AraSlotDesc (a0/b0/a1/b1, W^A and Z); ara_run
+// fills the workspace fields.
+struct AraSpec {
+  std::vector<AraSlotDesc> slots;
+  std::vector<ZSeg> zseg;
+  const double* uk = nullptr;   // P = U_k*^T Omega (rk x bs) when rk > 0
+  int rk = 0;
+  double* p = nullptr;
+  int a_max = 0;                // largest W^A height over the slots
+  int r_max = 0;                // largest Z height over the slots
+  std::vector<double> samp_bytes, samp_flops;   // per slot, per iteration
+  // when set, HIP events are recorded around every sampling launch
+  std::vector<std::pair<hipEvent_t, hipEvent_t>>* events = nullptr;
 };
 
 struct AraResult {
@@ -54,21 +82,28 @@ struct AraResult {
   std::vector<int> iters;      // iterations per slot
   std::vector<double> flops_paper_orth;  // per slot: orthogonalisation flops
   long long launches = 0;      // ARA iterations (batches)
-  double flops = 0.0;          // executed flops (GEMM + orthogonalisation)
+  double flops = 0.0;          // executed flops (sampling, Gram-Schmidt, orthogonalisation)
+  double samp_bytes = 0.0, samp_flops = 0.0;   // of the sampling launches
 };
+
+// Spec of n explicit m x m tiles (tile t at tiles + t * ld * m, ld >= m):
+// Y_t = T_t Omega.
+tlr_status ara_explicit_spec(Handle* h, const AraConfig& c, int n, const double* tiles, int ld,
+                             AraSpec* spec);
 
 // Allocate the slot buffers for n slots.
 tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s);
-
-// Sample callback: add to `plan` the launches that fill Y(s) = S_s * omega
-// for every slot in `act`.
-using SampleFn = std::function<tlr_status(const std::vector<int>& act, const double* omega,
-                                          Plan& plan)>;
+// The Gaussian test-matrix buffer (m x bs) the iterations draw into.
+tlr_status ara_omega(Handle* h, const AraConfig& c, double** omega);
 
 // Run the ARA loop.  `order` lists the slots in processing order (the
 // sortRanks order); the first s_max start active.  `info_abort` is checked
 // after the first iteration (a failed diagonal factorization ends the run).
+// `idle`, when set, is called once per iteration while the host would
+// otherwise wait for the device (the factorization issues the launches of
+// the diagonal-tile stream from it).
 tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::vector<int>& order,
-                   const SampleFn& sample, AraResult* res, bool* info_abort);
+                   AraSpec& spec, AraResult* res, bool* info_abort,
+                   const std::function<tlr_status()>& idle = nullptr);
 
 }  // namespace tlr

@@ -96,19 +96,13 @@ tlr_status compress(Handle* h, const double* A, long long lda, const double* pts
     TLR_TRY(h->stage.upload(h, gd.data(), sizeof(GenDesc) * nt, &dg));
     TLR_HIP(launch_gen_tiles((const GenDesc*)dg, nt, pts, dim, h->N, m, kern, ell, diag_add, A, lda,
                              h->stream));
-    SampleFn sample = [&](const std::vector<int>& act, const double* omega, Plan& plan) -> tlr_status {
-      SegBatch y;
-      for (int sl : act)
-        y.add(m, bs, Tt + (size_t)sl * m * m, m, omega, m, m, nullptr, 1, nullptr, 1, 0, slots.y(sl), m,
-              0.0);
-      plan.seg(y);
-      return TLR_OK;
-    };
+    AraSpec spec;
+    TLR_TRY(ara_explicit_spec(h, cfg, nt, Tt, m, &spec));
     std::vector<int> order(nt);
     for (int t = 0; t < nt; ++t) order[t] = t;
     AraResult res;
     cfg.stream_id = 0x80000000u + (unsigned)bid;
-    TLR_TRY(ara_run(h, cfg, slots, order, sample, &res, nullptr));
+    TLR_TRY(ara_run(h, cfg, slots, order, spec, &res, nullptr));
     // B = T^T Q for every tile, then append Q and B to the arenas
     long long add = 0;
     for (int t = 0; t < nt; ++t) add += res.q[t];
@@ -123,8 +117,8 @@ tlr_status compress(Handle* h, const double* A, long long lda, const double* pts
       h->a_rank[(size_t)ij.first * nb + ij.second] = q;
       h->a_off[(size_t)ij.first * nb + ij.second] = col;
       if (q > 0) {
-        pb.add(m, q, m, Tt + (size_t)t * m * m, m, slots.q(t), m, h->VA + (size_t)col * m, m, 1.0, 0.0);
-        cd.push_back(CopyDesc{slots.q(t), h->UA + (size_t)col * m, m, q, m, m});
+        pb.add(m, q, m, Tt + (size_t)t * m * m, m, slots.qb(t), m, h->VA + (size_t)col * m, m, 1.0, 0.0);
+        cd.push_back(CopyDesc{slots.qb(t), h->UA + (size_t)col * m, m, q, m, m});
         maxc = std::max(maxc, q);
       }
       col += q;

@@ -224,8 +224,11 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
       TLR_HIP(hipStreamSynchronize(ds));
       TLR_TRY(w.Wd.ensure(h->mem, sizeof(double) * (size_t)m * Rk));
     }
+    // the launches of the diagonal-tile stream are issued a few at a time
+    // while the host waits on the ARA iterations of the main stream
+    Plan dplan(h, ds);
+    dplan.persist = &w.sideblob;
     {
-      Plan dplan(h, ds);
       const double* Akk = h->diagA(k);
       const int nr = h->nreal(k);
       dplan.launch([=]() { return launch_copy_shift(Akk, Lkk, m, nr, shift, ds); });
@@ -245,14 +248,21 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
       }
       TLR_TRY(dense_factor(h, dplan, !ldl, Lkk, m, m, ldl ? h->Dv + (size_t)k * m : nullptr, k * m,
                            h->invL(k)));
-      TLR_TRY(dplan.run());
+      TLR_TRY(dplan.run_some(8));
     }
     flops_paper += 2.0 * m * (double)m * Rk + (double)m * m * m / 3.0;
-    TLR_HIP(hipEventRecord(h->ev_join, ds));
     flops += (double)m * m * m / 3.0 + (double)m * m * m / 3.0;
+    auto side_done = [&]() -> tlr_status {
+      TLR_TRY(dplan.run());
+      TLR_HIP(hipEventRecord(h->ev_join, ds));
+      return TLR_OK;
+    };
 
     const int nrow = nb - k - 1;
-    if (nrow == 0) break;
+    if (nrow == 0) {
+      TLR_TRY(side_done());
+      break;
+    }
 
     // ---------------------------------------------- sortRanks (device)
     std::vector<int> order(nrow);
@@ -297,69 +307,79 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
     double* P = w.P.as<double>();
     double* Wa = w.Wa.as<double>();
     double* Z = w.Z.as<double>();
-    SampleFn sample = [&](const std::vector<int>& act, const double* omega, Plan& plan) -> tlr_status {
-      if (Rk > 0) {
-        GemmBatch pb(true, false);
-        pb.add(Rk, bs, m, h->UL[k], m, omega, m, P, Rk, 1.0, 0.0);
-        plan.gemm(pb);
-      }
-      GemmBatch wa(true, false), zb(false, false);
-      SegBatch y, y32;
+    // static sampling description of every tile of the column:
+    //   Y_i = U^A_ik W^A_i + U_i* Z_i,  W^A_i = V^A_ik^T Omega,
+    //   Z_i = -[G_ij P_j]_j,  P = U_k*^T Omega
+    AraSpec spec;
+    spec.slots.assign(nrow, AraSlotDesc{});
+    spec.samp_bytes.assign(nrow, 0.0);
+    spec.samp_flops.assign(nrow, 0.0);
+    spec.uk = h->UL[k];
+    spec.rk = Rk;
+    spec.p = P;
+    spec.events = timing ? &events : nullptr;
+    {
       long long zo = 0;
-      for (int sl : act) {
-        const int i = k + 1 + sl;
-        const int a = h->ar(i, k);
-        double* wa_s = Wa + (size_t)sl * m * bs;
-        if (a > 0) wa.add(a, bs, m, h->va(i, k), m, omega, m, wa_s, m, 1.0, 0.0);
-        const int Ri = h->R[i];
-        int k1 = 0;
-        const double* zs = nullptr;
+      for (int s = 0; s < nrow; ++s) {
+        const int i = k + 1 + s;
+        const int a = h->ar(i, k), Ri = h->R[i];
+        AraSlotDesc& d = spec.slots[s];
+        double* wa_s = Wa + (size_t)s * m * bs;
+        d.a0 = h->ua(i, k);
+        d.lda0 = m;
+        d.k0 = a;
+        d.b0 = wa_s;
+        d.ldb0 = std::max(a, 1);
+        d.va = h->va(i, k);
+        d.wa = wa_s;
+        d.a = a;
+        spec.a_max = std::max(spec.a_max, a);
+        d.lda1 = m;
+        d.ldb1 = 1;
         if (Rk > 0 && Ri > 0) {
-          // Z' = -[G_ij P_j]_j, so that Y = U^A Wa + U_i* Z'
+          double* zs = Z + zo;
+          zo += (long long)Ri * bs;
+          d.a1 = use32[s] ? (const void*)h->UL32[i] : (const void*)h->UL[i];
+          d.a1_f32 = use32[s];
+          d.k1 = Ri;
+          d.b1 = zs;
+          d.ldb1 = Ri;
+          d.z = zs;
+          d.R = Ri;
+          d.zseg = (int)spec.zseg.size();
           for (int j = 0; j < k; ++j) {
             const int rij = h->lr(i, j);
             if (rij == 0) continue;
-            zb.add(rij, bs, h->lr(k, j), gptr(i, j), rij, P + h->lo(k, j), Rk, Z + zo + h->lo(i, j),
-                   Ri, -1.0, 0.0);
+            spec.zseg.push_back(ZSeg{gptr(i, j), rij, h->lr(k, j), (int)h->lo(i, j), (int)h->lo(k, j)});
           }
-          zs = Z + zo;
-          k1 = Ri;
-          zo += (long long)Ri * bs;
+          d.nz = (int)spec.zseg.size() - d.zseg;
+          spec.r_max = std::max(spec.r_max, Ri);
         }
-        if (use32[sl]) {
-          y32.add_f32(m, bs, h->ua(i, k), m, wa_s, m, a, h->UL32[i], m, zs, std::max(Ri, 1), k1,
-                      slots.y(sl), m, 0.0);
-          ++fp32_tile_iters;
-        } else {
-          y.add(m, bs, h->ua(i, k), m, wa_s, m, a, h->UL[i], m, zs, std::max(Ri, 1), k1,
-                slots.y(sl), m, 0.0);
-        }
+        const double kk = (double)a + d.k1;
+        spec.samp_flops[s] = 2.0 * m * bs * kk;
+        spec.samp_bytes[s] = 8.0 * ((double)m * a + kk * bs + (double)m * bs) +
+                             (d.a1_f32 ? 4.0 : 8.0) * m * d.k1;
       }
-      plan.gemm(wa);
-      plan.gemm(zb);
-      if (timing && !(y.d.empty() && y32.d.empty())) {
-        hipEvent_t e0, e1;
-        TLR_HIP(hipEventCreate(&e0));
-        TLR_HIP(hipEventCreate(&e1));
-        events.push_back({e0, e1});
-        hipStream_t st = h->stream;
-        plan.launch([=]() { return hipEventRecord(e0, st); });
-        plan.seg(y);
-        plan.seg(y32);
-        plan.launch([=]() { return hipEventRecord(e1, st); });
-        samp_bytes += y.bytes + y32.bytes;
-        samp_flops += y.flops + y32.flops;
-      } else {
-        plan.seg(y);
-        plan.seg(y32);
-      }
-      return TLR_OK;
-    };
+    }
     // slots hold rows k+1.. in natural order; `order` is the sorted order
     AraResult res;
     cfg.stream_id = (unsigned)k;
     bool abort = false;
-    TLR_TRY(ara_run(h, cfg, slots, order, sample, &res, &abort));
+    TLR_TRY(ara_run(h, cfg, slots, order, spec, &res, &abort, [&]() -> tlr_status {
+      return dplan.pending() ? dplan.run_some(24) : TLR_OK;
+    }));
+    TLR_TRY(side_done());
+    // W^A, Z and P products of the iterations
+    flops += 2.0 * Rk * m * bs * (double)res.launches;
+    for (int s = 0; s < nrow; ++s) {
+      const int i = k + 1 + s;
+      double zf = 0.0;
+      for (int j = 0; j < k; ++j) zf += (double)h->lr(i, j) * h->lr(k, j);
+      flops += res.iters[s] * 2.0 * bs * ((double)h->ar(i, k) * m + zf);
+      if (use32[s]) fp32_tile_iters += res.iters[s];
+    }
+    samp_bytes += res.samp_bytes;
+    samp_flops += res.samp_flops;
     if (abort) break;
     flops += res.flops;
     ara_iters += res.launches;
@@ -396,7 +416,7 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
         const int i = k + 1 + s, qs = q[s];
         if (qs == 0) continue;
         const int a = h->ar(i, k), Ri = h->R[i];
-        const double* Qs = slots.q(s);
+        const double* Qs = slots.qb(s);
         if (Ri > 0) t1.add(Ri, qs, m, h->UL[i], m, Qs, m, T + toff[s], Ri, 1.0, 0.0);
         if (a > 0) t2.add(a, qs, m, h->ua(i, k), m, Qs, m, Ta + taoff[s], a, 1.0, 0.0);
         if (Rk > 0) {
@@ -441,7 +461,7 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
       for (int s = 0; s < nrow; ++s) {
         const int i = k + 1 + s, qs = q[s];
         if (qs == 0) continue;
-        CopyDesc c{slots.q(s), h->UL[i] + (size_t)h->R[i] * m, m, qs, m, m};
+        CopyDesc c{slots.qb(s), h->UL[i] + (size_t)h->R[i] * m, m, qs, m, m};
         if (h->mixed) {
           c.dst32 = h->UL32[i] + (size_t)h->R[i] * m;
           c.ldd32 = m;

@@ -13,11 +13,10 @@
 // direction (so global loads coalesce whatever the transposition) and fed to
 // v_mfma_f64_16x16x4f64.  A host-built block map assigns workgroups to
 // (problem, tile) pairs, so problems of any shape share one launch.
+#include "mfma_tiles.h"
 #include "tlr_internal.h"
 
 namespace tlr {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -147,12 +146,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
 // C = alpha A^T B + beta C with A stored K x M and B stored K x N (both
 // column-major, the contraction runs down their columns): the projections
 // U^T Omega, Q^T Y, V^T V, U^T Q of the method, where K is the tile height.
-// A workgroup owns a (16 FM) x (16 FN) tile of C; its eight waves take
-// interleaved 16-row slices of K.  Within a slice lane (i, g) reads rows
-// 4g..4g+3 of column i of A and of B, so both operands are read in 32-byte
-// runs down their columns, and MFMA t of the slice consumes row 4g + t: the
-// same permutation of k on both operands, so the sum is unchanged.  The eight
-// partial tiles are added in LDS in a fixed order.
+// A 512-thread workgroup owns a (16 FM) x (16 FN) tile of C (tn_tile).
 template <int FM, int FN>
 __global__ __launch_bounds__(512) void k_gemm_tn(const GemmDesc* __restrict__ descs,
                                                  const BlockMap* __restrict__ map) {
@@ -163,91 +157,10 @@ __global__ __launch_bounds__(512) void k_gemm_tn(const GemmDesc* __restrict__ de
   const int tiles_m = (d.M + TM - 1) / TM;
   const int row0 = (bm.tile % tiles_m) * TM;
   const int col0 = (bm.tile / tiles_m) * TN;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, g = lane >> 4;
-  int kbeg = 0, kend = d.K;
+  int kbeg = 0;
   if (d.flags & GEMM_TRIU_A) kbeg = (row0 / 16) * 16;
-
-  d4 acc[FM][FN];
-#pragma unroll
-  for (int a = 0; a < FM; ++a)
-#pragma unroll
-    for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-
-  const double* acol[FM];
-  const double* bcol[FN];
-  bool aok[FM], bok[FN];
-#pragma unroll
-  for (int a = 0; a < FM; ++a) {
-    const int i = row0 + a * 16 + li;
-    aok[a] = i < d.M;
-    acol[a] = d.A + (size_t)(aok[a] ? i : 0) * d.lda;
-  }
-#pragma unroll
-  for (int b = 0; b < FN; ++b) {
-    const int j = col0 + b * 16 + li;
-    bok[b] = j < d.N;
-    bcol[b] = d.B + (size_t)(bok[b] ? j : 0) * d.ldb;
-  }
-  // U slices per pass: all their loads are issued before the first MFMA, so
-  // a pass costs one memory latency instead of U (K is ~1000 and the grids
-  // of these products are small, so latency, not bandwidth, is the limit).
-  // Loads past the end of K read a clamped in-range address and are zeroed.
-  constexpr int U = 4;
-  for (int k0 = kbeg + wave * 16; k0 < kend; k0 += 16 * NW * U) {
-    double av[U][FM][4], bv[U][FN][4];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int kr = k0 + u * 16 * NW + 4 * g;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const bool kin = kr + t < kend;
-        const int kk = kin ? kr + t : kend - 1;
-#pragma unroll
-        for (int a = 0; a < FM; ++a) {
-          const double v = acol[a][kk];
-          av[u][a][t] = (aok[a] && kin) ? v : 0.0;
-        }
-#pragma unroll
-        for (int b = 0; b < FN; ++b) {
-          const double v = bcol[b][kk];
-          bv[u][b][t] = (bok[b] && kin) ? v : 0.0;
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int a = 0; a < FM; ++a)
-#pragma unroll
-          for (int b = 0; b < FN; ++b)
-            acc[a][b] =
-                __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][a][t], bv[u][b][t], acc[a][b], 0, 0, 0);
-  }
-#pragma unroll
-  for (int a = 0; a < FM; ++a)
-#pragma unroll
-    for (int b = 0; b < FN; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) red[wave][(a * FN + b) * 4 + r][lane] = acc[a][b][r];
-  __syncthreads();
-  for (int e = threadIdx.x; e < FM * FN * 4 * 64; e += 64 * NW) {
-    const int slot = e >> 6, l = e & 63;
-    const int ab = slot >> 2, r = slot & 3;
-    const int a = ab / FN, b = ab % FN;
-    const int gr = row0 + a * 16 + (l >> 4) + 4 * r;
-    const int gc = col0 + b * 16 + (l & 15);
-    if (gr >= d.M || gc >= d.N) continue;
-    double v = red[0][slot][l];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) v += red[w][slot][l];
-    double* cp = d.C + gr + (size_t)gc * d.ldc;
-    double out = d.alpha * v;
-    if (d.beta != 0.0) out += d.beta * *cp;
-    *cp = out;
-  }
+  tn_tile<FM, FN, NW>(d.A, d.lda, d.B, d.ldb, d.C, d.ldc, d.M, d.N, kbeg, d.K, d.alpha, d.beta, row0,
+                      col0, red);
 }
 
 template <bool TA, bool TB>

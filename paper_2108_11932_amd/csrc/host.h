@@ -144,7 +144,17 @@ struct Plan {
   void launch(size_t off, std::function<hipError_t(const char*)> f);
   // a launch that needs no staged data
   void launch(std::function<hipError_t()> f);
+  // Issue all launches (run) or the next max_steps of them (run_some; the
+  // first call uploads the staged bytes).  With `persist` set, the staged
+  // bytes are copied into that buffer, so a plan may stay partly unlaunched
+  // while the staging area is recycled.
   tlr_status run();
+  tlr_status run_some(size_t max_steps);
+  bool pending() const { return !steps.empty(); }
+  DevBuf* persist = nullptr;
+  size_t cursor = 0;
+  bool started = false;
+  const char* base = nullptr;
 };
 
 // Per-column workspace of the factorization.
@@ -152,11 +162,11 @@ struct Work {
   DevBuf G, W, omega, P, Z, T, Ta, H, Ball, C, Wa, Y, Q, part, ints, orth, dscale, tol,
       compact, Bt, fro;
   // buffers of the diagonal-tile stream (never touched by the main stream)
-  DevBuf Wd, dW, dtol;
+  DevBuf Wd, dW, dtol, sideblob;
   int slots = 0;   // slot capacity of the per-tile buffers
   void release_all(Mem& mem) {
     DevBuf* bufs[] = {&G, &W, &omega, &P, &Z, &T, &Ta, &H, &Ball, &C, &Wa, &Y, &Q, &part,
-                      &ints, &orth, &dscale, &tol, &compact, &Bt, &fro, &Wd, &dW, &dtol};
+                      &ints, &orth, &dscale, &tol, &compact, &Bt, &fro, &Wd, &dW, &dtol, &sideblob};
     for (DevBuf* b : bufs) b->release(mem);
   }
 };
@@ -202,6 +212,8 @@ struct tlr_matrix_s {
   bool mixed = false;             // the current factorization keeps UL32
   std::vector<double> l_fro;      // ||L_ij||_F per tile (U orthonormal: ||V_ij||_F)
   double* pin_norm = nullptr;     // pinned read-back of a column's V norms
+  int* pin_ring = nullptr;        // pinned read-back ring of the ARA iterations (2 x 8)
+  hipEvent_t ev_rb[2] = {nullptr, nullptr};
   size_t pin_norm_n = 0;
 
   Work ws;
@@ -227,6 +239,8 @@ struct tlr_matrix_s {
   tlr_status init_streams();
   tlr_status pinned_ints(size_t n, int** p);
   tlr_status pinned_norms(size_t n, double** p);
+  tlr_status readback_ring(int** p);
+  void release_host();            // pinned buffers and events
 };
 
 namespace tlr {
@@ -249,7 +263,6 @@ tlr_status dense_factor(Handle* h, struct Plan& plan, bool chol, double* A, int 
 // Kernel wrappers not declared in tlr_internal.h.
 hipError_t launch_zero_upper(double* A, int lda, int m, hipStream_t s);
 hipError_t launch_pivot_tol(const double* A, int lda, int m, double* tol, hipStream_t s);
-int gram_row_blocks(int m);
 
 // Batched ARA over a set of explicitly sampled operators: shared by the
 // factorization (Schur-complement tiles) and the compression (explicit tiles).

@@ -28,7 +28,7 @@ struct Ctx {
     h.ws.release_all(h.mem);
     h.mem.put(h.d_info);
     h.stage.release(h.mem);
-    if (h.pin_back) (void)hipHostFree(h.pin_back);
+    h.release_host();
   }
   tlr_status info(int* out) {
     TLR_TRY(h.sync());
@@ -136,27 +136,21 @@ tlr_status tlrk_ara(int m, int count, const double* tiles, double tau, int bs, i
   cfg.stream_id = 0;
   AraSlots slots;
   TLR_TRY(ara_slots(&c.h, cfg, count, &slots));
-  SampleFn sample = [&](const std::vector<int>& act, const double* omega, Plan& plan) -> tlr_status {
-    SegBatch y;
-    for (int sl : act)
-      y.add(m, bs, tiles + (size_t)sl * m * m, m, omega, m, m, nullptr, 1, nullptr, 1, 0, slots.y(sl),
-            m, 0.0);
-    plan.seg(y);
-    return TLR_OK;
-  };
+  AraSpec spec;
+  TLR_TRY(ara_explicit_spec(&c.h, cfg, count, tiles, m, &spec));
   std::vector<int> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
   AraResult res;
-  TLR_TRY(ara_run(&c.h, cfg, slots, order, sample, &res, nullptr));
+  TLR_TRY(ara_run(&c.h, cfg, slots, order, spec, &res, nullptr));
   GemmBatch pb(true, false);
   std::vector<CopyDesc> cd;
   for (int b = 0; b < count; ++b) {
     ranks[b] = res.q[b];
     iters[b] = res.iters[b];
     if (res.q[b] == 0) continue;
-    pb.add(m, res.q[b], m, tiles + (size_t)b * m * m, m, slots.q(b), m, B + (size_t)b * m * m, m, 1.0,
+    pb.add(m, res.q[b], m, tiles + (size_t)b * m * m, m, slots.qb(b), m, B + (size_t)b * m * m, m, 1.0,
            0.0);
-    cd.push_back(CopyDesc{slots.q(b), Q + (size_t)b * m * m, m, res.q[b], m, m});
+    cd.push_back(CopyDesc{slots.qb(b), Q + (size_t)b * m * m, m, res.q[b], m, m});
   }
   TLR_TRY(pb.run(&c.h));
   if (!cd.empty()) {

@@ -1,0 +1,214 @@
+// Device-side tile routines on the FP64 matrix cores, shared by the generic
+// batched products and the ARA iteration kernels.
+//
+// MFMA f64 16x16x4 operand layout (measured on gfx950): lane l supplies
+// A(l % 16, l / 16) and B(l / 16, l % 16); accumulator register r of lane l
+// holds D(l / 16 + 4 r, l % 16).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tlr {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// C(row0 : row0 + 16 FM, col0 : col0 + 16 FN) = alpha A^T B + beta C with A
+// stored K x M and B stored K x N (column-major; the contraction runs down
+// their columns), over k in [kbeg, kend).  NW waves of the workgroup take
+// interleaved 16-row slices of K; within a slice lane (i, g) reads rows
+// 4g..4g+3 of column i of A and of B, so both operands are read in 32-byte
+// runs down their columns, and MFMA t of the slice consumes row 4g + t: the
+// same permutation of k on both operands, so the sum is unchanged.  U slices
+// per pass have all their loads in flight before the first MFMA (K is ~1000
+// and the grids are small, so latency, not bandwidth, is the limit); loads
+// past the end of K read a clamped in-range address and are zeroed.  The NW
+// partial tiles are added in LDS (red, NW x FM FN 4 x 64) in a fixed order.
+// Every thread of the workgroup must call it.
+template <int FM, int FN, int NW>
+__device__ inline void tn_tile(const double* __restrict__ A, int lda, const double* __restrict__ B,
+                               int ldb, double* C, int ldc, int M, int N, int kbeg, int kend,
+                               double alpha, double beta, int row0, int col0,
+                               double (*red)[FM * FN * 4][64]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  d4 acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const double* acol[FM];
+  const double* bcol[FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a) {
+    const int i = row0 + a * 16 + li;
+    acol[a] = A + (size_t)(i < M ? i : 0) * lda;
+  }
+#pragma unroll
+  for (int b = 0; b < FN; ++b) {
+    const int j = col0 + b * 16 + li;
+    bcol[b] = B + (size_t)(j < N ? j : 0) * ldb;
+  }
+  constexpr int U = 4;
+  for (int k0 = kbeg + wave * 16; k0 < kend; k0 += 16 * NW * U) {
+    double av[U][FM][4], bv[U][FN][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int kr = k0 + u * 16 * NW + 4 * g;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int kk = min(kr + t, kend - 1);
+#pragma unroll
+        for (int a = 0; a < FM; ++a) av[u][a][t] = acol[a][kk];
+#pragma unroll
+        for (int b = 0; b < FN; ++b) bv[u][b][t] = bcol[b][kk];
+      }
+    }
+    // keep every load of the pass ahead of its first use (the scheduler
+    // would otherwise pair each load with its use and serialise the
+    // latency); rows past K are zeroed afterwards on the A side.  Columns of
+    // A past M and of B past N were read from a clamped in-range address:
+    // they only reach outputs that are not stored.
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (k0 + u * 16 * NW + 4 * g + t >= kend)
+#pragma unroll
+          for (int a = 0; a < FM; ++a) av[u][a][t] = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b)
+            acc[a][b] =
+                __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][a][t], bv[u][b][t], acc[a][b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wave][(a * FN + b) * 4 + r][lane] = acc[a][b][r];
+  __syncthreads();
+  for (int e = threadIdx.x; e < FM * FN * 4 * 64; e += 64 * NW) {
+    const int slot = e >> 6, l = e & 63;
+    const int ab = slot >> 2, r = slot & 3;
+    const int a = ab / FN, b = ab % FN;
+    const int gr = row0 + a * 16 + (l >> 4) + 4 * r;
+    const int gc = col0 + b * 16 + (l & 15);
+    if (gr >= M || gc >= N) continue;
+    double v = red[0][slot][l];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += red[w][slot][l];
+    double* cp = C + gr + (size_t)gc * ldc;
+    double out = alpha * v;
+    if (beta != 0.0) out += beta * *cp;
+    *cp = out;
+  }
+}
+
+// Streaming product of a 16-row strip (256 threads, 4 waves):
+//   C(r0 : r0 + 16, 0 : N) = beta C + A0 B0 + A1 B1,
+// A_s m x K_s column-major (A1 read as float when A1F32), B_s K_s x N,
+// N <= 16 NF.  The waves take interleaved 16-wide slices of the K range of
+// both segments, U slices per pass with all loads in flight; lane (i, g)
+// reads row i of A for the four columns k0 + 4 g + t (128-byte runs per
+// column over the 16 lanes of a group) and rows k0 + 4 g + t of column i of
+// B; MFMA t consumes k0 + 4 g + t on both operands.  The four partial strips
+// are added in LDS (red, 4 x NF 4 x 64) in a fixed order.  When ys is not
+// NULL the final strip is also left in ys[row - r0][col] (after a barrier).
+template <int NF, bool A1F32>
+__device__ inline void seg_strip(const double* A0, int lda0, const double* B0, int ldb0, int K0,
+                                 const void* A1v, int lda1, const double* B1, int ldb1, int K1,
+                                 double* C, int ldc, int M, int N, double beta, int r0,
+                                 double (*red)[NF * 4][64], double (*ys)[16 * NF + 1]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int row = r0 + li;
+  const bool rok = row < M;
+  d4 acc[NF];
+#pragma unroll
+  for (int b = 0; b < NF; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
+  constexpr int U = 4;
+#pragma unroll
+  for (int sg = 0; sg < 2; ++sg) {
+    const int K = sg ? K1 : K0;
+    if (K <= 0) continue;
+    const bool f32 = A1F32 && sg == 1;
+    const double* __restrict__ A = (sg ? (const double*)A1v : A0) + (rok ? row : 0);
+    const float* __restrict__ Af = (const float*)A1v + (rok ? row : 0);
+    const double* __restrict__ B = sg ? B1 : B0;
+    const size_t lda = sg ? lda1 : lda0, ldb = sg ? ldb1 : ldb0;
+    const double* bcol[NF];
+#pragma unroll
+    for (int b = 0; b < NF; ++b) {
+      const int c = b * 16 + li;
+      bcol[b] = B + (size_t)(c < N ? c : 0) * ldb;
+    }
+    for (int k0 = wave * 16; k0 < K; k0 += 64 * U) {
+      double av[U][4], bv[U][NF][4];
+      float af[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int kr = k0 + 64 * u + 4 * g;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int kk = min(kr + t, K - 1);
+          if (f32)
+            af[u][t] = Af[(size_t)kk * lda];
+          else
+            av[u][t] = A[(size_t)kk * lda];
+#pragma unroll
+          for (int b = 0; b < NF; ++b) bv[u][b][t] = bcol[b][kk];
+        }
+      }
+      // all loads of the pass are issued before the first use; rows past K
+      // are zeroed afterwards on the A side (rows of A past M and columns of
+      // B past N come from clamped in-range addresses and only reach outputs
+      // that are not stored)
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (f32) av[u][t] = (double)af[u][t];
+          if (k0 + 64 * u + 4 * g + t >= K) av[u][t] = 0.0;
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int b = 0; b < NF; ++b)
+            acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][t], bv[u][b][t], acc[b], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NF; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[wave][b * 4 + r][lane] = acc[b][r];
+  __syncthreads();
+  for (int e = threadIdx.x; e < NF * 4 * 64; e += 256) {
+    const int slot = e >> 6, l = e & 63;
+    const int b = slot >> 2, r = slot & 3;
+    const int rr = (l >> 4) + 4 * r;
+    const int c = b * 16 + (l & 15);
+    double v = ((red[0][slot][l] + red[1][slot][l]) + red[2][slot][l]) + red[3][slot][l];
+    if (r0 + rr < M && c < N) {
+      double* cp = C + (r0 + rr) + (size_t)c * ldc;
+      if (beta != 0.0) v += beta * *cp;
+      *cp = v;
+    } else {
+      v = 0.0;
+    }
+    if (ys) ys[rr][c] = v;
+  }
+  if (ys) __syncthreads();
+}
+
+}  // namespace tlr

@@ -133,6 +133,34 @@ tlr_status tlr_matrix_s::init_streams() {
   return TLR_OK;
 }
 
+tlr_status tlr_matrix_s::readback_ring(int** p) {
+  if (!pin_ring) {
+    if (hipHostMalloc((void**)&pin_ring, sizeof(int) * 16, hipHostMallocDefault) != hipSuccess) {
+      pin_ring = nullptr;
+      tlr::set_error("pinned host allocation failed");
+      return TLR_ERR_OOM;
+    }
+  }
+  for (int i = 0; i < 2; ++i)
+    if (!ev_rb[i]) TLR_HIP(hipEventCreateWithFlags(&ev_rb[i], hipEventDisableTiming));
+  *p = pin_ring;
+  return TLR_OK;
+}
+
+void tlr_matrix_s::release_host() {
+  if (pin_back) (void)hipHostFree(pin_back);
+  if (pin_norm) (void)hipHostFree(pin_norm);
+  if (pin_ring) (void)hipHostFree(pin_ring);
+  pin_back = nullptr;
+  pin_norm = nullptr;
+  pin_ring = nullptr;
+  pin_back_n = pin_norm_n = 0;
+  for (hipEvent_t& e : ev_rb) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
+}
+
 tlr_status tlr_matrix_s::pinned_norms(size_t n, double** p) {
   if (n > pin_norm_n) {
     if (pin_norm) (void)hipHostFree(pin_norm);
@@ -250,16 +278,34 @@ void Plan::seg(const SegBatch& b) {
   flops += b.flops;
 }
 
-tlr_status Plan::run() {
-  const char* base = nullptr;
-  if (!blob.empty()) {
-    void* dp = nullptr;
-    TLR_TRY(h->stage.upload(h, blob.data(), blob.size(), &dp, s));
-    base = (const char*)dp;
+tlr_status Plan::run() { return run_some(steps.size()); }
+
+tlr_status Plan::run_some(size_t max_steps) {
+  if (!started) {
+    started = true;
+    base = nullptr;
+    if (!blob.empty()) {
+      void* dp = nullptr;
+      TLR_TRY(h->stage.upload(h, blob.data(), blob.size(), &dp, s));
+      if (persist) {
+        if (persist->cap < blob.size()) {
+          TLR_TRY(h->sync());   // the old buffer may still be read by queued work
+          TLR_TRY(persist->ensure(h->mem, blob.size() + blob.size() / 2));
+        }
+        TLR_HIP(hipMemcpyAsync(persist->p, dp, blob.size(), hipMemcpyDeviceToDevice, s));
+        dp = persist->p;
+      }
+      base = (const char*)dp;
+    }
   }
-  for (auto& f : steps) TLR_HIP(f(base));
-  steps.clear();
-  blob.clear();
+  const size_t end = std::min(steps.size(), cursor + max_steps);
+  for (; cursor < end; ++cursor) TLR_HIP(steps[cursor](base));
+  if (cursor == steps.size()) {
+    steps.clear();
+    blob.clear();
+    cursor = 0;
+    started = false;
+  }
   return TLR_OK;
 }
 

@@ -96,25 +96,77 @@ hipError_t launch_philox_raw(unsigned* out, int n, unsigned long long seed, unsi
                              unsigned c3, hipStream_t s);
 
 // Per-tile descriptor for the orthogonalisation of one ARA block.
-struct OrthDesc {
-  const double* Y; // m x bs sample block (ld m)
-  double* Q;       // m x (qcap + bs) basis (ld m); new columns start at qold
-  int qold;        // basis width before this iteration
-  int* q;          // device basis width (updated by the pivoted Cholesky)
-  int* flag;       // set to 1 when the tile has converged
-  double* part;    // partial Gram sums: nrb x bs x bs x 2 (hi, lo)
-  int* piv;        // bs pivots, then the accepted count at [bs]
+// ---------------------------------------------------------------------------
+// Device-driven ARA iterations (Algorithm "Left Looking Cholesky TLR ARA
+// Update"): every kernel of an iteration reads the active list, its count and
+// the basis widths from device memory, so the host enqueues iterations
+// without waiting for the previous one.  Grids are sized by host-side upper
+// bounds; blocks beyond the current active set or basis width exit.
+// ---------------------------------------------------------------------------
+// Static description of one slot (one tile) for a whole ARA run.
+struct AraSlotDesc {
+  // sample Y = A0 B0 + A1 B1 (m x bs)
+  const double* a0;       // m x k0 (ld lda0): U^A_ik, or the explicit tile
+  const double* b0;       // k0 x bs (ld ldb0): W^A below, or Omega
+  const void* a1;         // m x k1 (ld lda1): the row panel U_i*, double or float
+  const double* b1;       // k1 x bs (ld ldb1): Z below
+  int lda0, ldb0, k0, lda1, ldb1, k1, a1_f32;
+  // W^A = V^A_ik^T Omega (a x bs, ld a), when a > 0
+  const double* va;
+  double* wa;
+  int a;
+  // Z = -[G_ij P_j]_j (R x bs, ld R) over segments [zseg, zseg + nz)
+  int zseg, nz, R;
+  double* z;
+  // workspace
+  double* y;              // m x bs
+  double* q;              // m x (qcap + bs) basis
+  double* c;              // m x bs, C = -Q^T Y
+  double* part1;          // Gram partials of Y per 16-row strip: nstrip x bs x bs x 2
+  double* part2;          // Gram partials of the new columns X
+  int* piv;               // pivots, then the accepted count at [bs]
+};
+// Z(zrow + r, :) = -G (rows x cols, ld rows) P(prow : prow + cols, :)
+struct ZSeg {
+  const double* g;
+  int rows, cols, zrow, prow;
+};
+// Device state of one ARA run (passed by value).
+struct AraDev {
+  const AraSlotDesc* slots;
+  int* act;     // active slots, counts[0] of them
+  int* counts;  // [0] active, [1] waiting cursor, [2] status word copy, [3] max basis width of the active slots
+  int* q;       // basis width per slot (committed by the compaction)
+  int* qnew;    // basis width after this iteration's pass 1
+  int* flag;    // converged
+  int* iters;   // iterations per slot
+  int* qsum;    // sum over iterations of the basis width before the iteration
+  int m, bs, qcap, nstrip;
 };
 // Block sizes the orthogonalisation kernels are built for (1, 2, 4, 8, 16,
 // 24, 32).
 bool orth_block_supported(int bs);
-// pass 1: Gram of the bs sample columns; pass 2: of the p new basis columns.
-hipError_t launch_gram_dd(const OrthDesc* d, int ntiles, int m, int bs, int pass, hipStream_t s);
+// mode 0: P = Uk^T Omega (P: rk x bs, ld rk, first p_blocks blocks) and
+//         W^A = V^A^T Omega per active slot (bps blocks per slot);
+// mode 1: C = -Q^T Y; mode 2: C = -Q^T X, X = Q(:, q : q + bs) (bps blocks).
+hipError_t launch_ara_tn(const AraDev& D, int mode, const double* omega, const double* uk, int rk,
+                         double* P, int p_blocks, int count_bound, int bps, hipStream_t s);
+// Z of every active slot (bps blocks of 64 rows per slot).
+hipError_t launch_ara_z(const AraDev& D, const ZSeg* segs, const double* P, int ldp,
+                        int count_bound, int bps, hipStream_t s);
+// mode 0: sample Y; mode 1: Y += Q C; mode 2: X += Q C; all write the Gram
+// partials of their output (part1 for modes 0/1, part2 for mode 2).
+hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_t s);
 // Cholesky QR step of pass 1 (pivoted, thresholded: appends the accepted
-// directions of Y to Q and sets q, flag and the pivot record) or pass 2
-// (re-orthonormalises the new columns in place), from the partial Grams.
-hipError_t launch_orth_step(const OrthDesc* d, int ntiles, int m, int bs, int pass, double tau2,
-                            int r_min, int qcap, hipStream_t s);
+// directions of Y to Q, sets qnew, flag, pivots, iteration counters and the
+// Gram partials of the new columns) or pass 2 (re-orthonormalises the new
+// columns in place).
+hipError_t launch_orth_step(const AraDev& D, int pass, double tau2, int r_min, int count_bound,
+                            hipStream_t s);
+// Commit the basis widths, compact the active list and refill it (see
+// launch_compact), and record the status word and the largest active width.
+hipError_t launch_ara_compact(const AraDev& D, const int* waiting, int nwaiting, int s_max,
+                              const int* info, hipStream_t s);
 
 // Dynamic batching: stable compaction of the active list by the convergence
 // flags (flag[slot] != 0 removes the slot), then refill from the waiting
