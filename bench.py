@@ -114,7 +114,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: the factorization is a single-GPU code path "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+              "(one GPU's share of the column step, at its real shape); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2108_11932_amd import tlr

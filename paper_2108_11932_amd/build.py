@@ -34,7 +34,8 @@ def hipcc() -> str:
 def flags(debug: bool):
     f = ["--offload-arch=" + ARCH, "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
          "-Wno-unused-result",
-         # keep hipcc from emitting packed FP32 instructions
+         # keep hipcc from emitting packed FP32 instructions, some of whose forms
+         # have given wrong results on this hardware
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include")]
     f += ["-O0", "-g"] if debug else ["-O3"]

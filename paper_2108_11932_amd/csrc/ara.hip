@@ -123,11 +123,16 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
   constexpr int NG = APPLY_ROWS / BS;
   constexpr int CPG = (BS + NG - 1) / NG;
   constexpr int XR = 64;   // rows of X staged at a time for the pass-1 strip Grams
-  __shared__ dd Gs[BS][BS + 1];
+  constexpr int GSZ = BS * (BS + 1);
+  constexpr int SMEM = (4 * GSZ > BS * (XR + 1)) ? 4 * GSZ : BS * (XR + 1);
+  // two dd copies of the Gram (read one, write the other: one barrier per
+  // step), reused for the X staging once the factor is done
+  __shared__ double smem[SMEM];
   __shared__ double Lm[BS][BS + 1];   // Lm[j][b]: multiplier of column b at step j
   __shared__ double Rs[BS][BS + 1];   // R(a, c), a <= c
-  __shared__ double Xs[BS][XR + 1];
   __shared__ int perm[BS];
+  // copy s of the Gram: (dd (*)[BS + 1])(smem + 2 * GSZ * s)
+  double (*Xs)[XR + 1] = (double (*)[XR + 1])smem;
   if ((int)blockIdx.y >= D.counts[0]) return;
   const int slot = D.act[blockIdx.y];
   const AraSlotDesc& d = D.slots[slot];
@@ -164,7 +169,7 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
       }
     }
     gv[i] = acc;
-    if (g < NG && b < BS) Gs[x][b] = acc;
+    if (g < NG && b < BS) ((dd (*)[BS + 1])smem)[x][b] = acc;
   }
   for (int e = t; e < BS * (BS + 1); e += APPLY_ROWS) {
     (&Lm[0][0])[e] = 0.0;
@@ -176,32 +181,33 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
     const int room = max(0, qcap - qold);
     unsigned taken = 0u;
     for (int j = 0; j < BS && j < room; ++j) {
+      dd (*Gr)[BS + 1] = (dd (*)[BS + 1])(smem + 2 * GSZ * (j & 1));
+      dd (*Gw)[BS + 1] = (dd (*)[BS + 1])(smem + 2 * GSZ * ((j & 1) ^ 1));
       // pivot: largest remaining diagonal, ties to the lowest column
       double vmax = -1.0;
       int pv = BS;
       for (int c = 0; c < BS; ++c) {
-        const double v = Gs[c][c].hi;
+        const double v = Gr[c][c].hi;
         if (!((taken >> c) & 1u) && v > vmax) {
           vmax = v;
           pv = c;
         }
       }
       if (!(vmax > tau2)) break;
-      const dd rinv = dd_div(dd{1.0, 0.0}, dd_sqrt(Gs[pv][pv]));
-      const dd lx = ((taken >> x) & 1u) ? dd{0.0, 0.0} : dd_mul(Gs[x][pv], rinv);
+      const dd rinv = dd_rsqrt(Gr[pv][pv]);
+      const dd lx = ((taken >> x) & 1u) ? dd{0.0, 0.0} : dd_mul(Gr[x][pv], rinv);
       dd lb[CPG];
 #pragma unroll
       for (int i = 0; i < CPG; ++i) {
         const int b = g * CPG + i;
-        lb[i] = (b < BS && !((taken >> b) & 1u)) ? dd_mul(Gs[pv][b], rinv) : dd{0.0, 0.0};
+        lb[i] = (b < BS && !((taken >> b) & 1u)) ? dd_mul(Gr[pv][b], rinv) : dd{0.0, 0.0};
       }
-      __syncthreads();
 #pragma unroll
       for (int i = 0; i < CPG; ++i) {
         const int b = g * CPG + i;
         if (g < NG && b < BS) {
           gv[i] = dd_sub(gv[i], dd_mul(lx, lb[i]));
-          Gs[x][b] = gv[i];
+          Gw[x][b] = gv[i];
           if (x == 0) Lm[j][b] = lb[i].hi + lb[i].lo;
         }
       }
@@ -234,24 +240,31 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
   } else {
     np = nc;
     for (int j = 0; j < nc; ++j) {
-      dd gj = dd_sqrt(Gs[j][j]);
-      if (gj.hi == 0.0) gj = dd{1.0, 0.0};
-      const dd rinv = dd_div(dd{1.0, 0.0}, gj);
-      const dd lx = (x > j && x < nc) ? dd_mul(Gs[x][j], rinv) : dd{0.0, 0.0};
+      dd (*Gr)[BS + 1] = (dd (*)[BS + 1])(smem + 2 * GSZ * (j & 1));
+      dd (*Gw)[BS + 1] = (dd (*)[BS + 1])(smem + 2 * GSZ * ((j & 1) ^ 1));
+      const dd gjj = Gr[j][j];
+      dd rinv, gj;
+      if (gjj.hi > 0.0) {
+        rinv = dd_rsqrt(gjj);
+        gj = dd_mul(gjj, rinv);
+      } else {
+        rinv = dd{1.0, 0.0};
+        gj = dd{1.0, 0.0};
+      }
+      const dd lx = (x > j && x < nc) ? dd_mul(Gr[x][j], rinv) : dd{0.0, 0.0};
       dd lb[CPG];
 #pragma unroll
       for (int i = 0; i < CPG; ++i) {
         const int b = g * CPG + i;
-        lb[i] = (b > j && b < nc) ? dd_mul(Gs[j][b], rinv) : (b == j ? gj : dd{0.0, 0.0});
+        lb[i] = (b > j && b < nc) ? dd_mul(Gr[j][b], rinv) : (b == j ? gj : dd{0.0, 0.0});
       }
-      __syncthreads();
 #pragma unroll
       for (int i = 0; i < CPG; ++i) {
         const int b = g * CPG + i;
         if (g < NG && b < BS) {
           if (x > j && b > j) {
             gv[i] = dd_sub(gv[i], dd_mul(lx, lb[i]));
-            Gs[x][b] = gv[i];
+            Gw[x][b] = gv[i];
           }
           if (x == 0 && b >= j) Rs[j][b] = lb[i].hi + lb[i].lo;
         }

@@ -174,6 +174,16 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   const double tau2 = c.tau * c.tau;
   const int p_blocks = spec.rk > 0 ? (spec.rk + 31) / 32 : 0;
   const int bps_wa = (spec.a_max + 31) / 32;
+  // split-K partial tiles of the TN products
+  double* tn_scratch = nullptr;
+  {
+    const long long tiles = std::max((long long)p_blocks + (long long)n * bps_wa,
+                                     (long long)n * ((c.qcap + 31) / 32));
+    size_t need = 0;
+    ara_tn_scratch(m, bs, tiles, &need);
+    TLR_TRY(w.tnpart.ensure(h->mem, sizeof(double) * std::max<size_t>(need, 1)));
+    tn_scratch = w.tnpart.as<double>();
+  }
   const int bps_z = (spec.r_max + 63) / 64;
   const bool any_z = !spec.zseg.empty() && bps_z > 0 && spec.rk > 0;
   int* info = h->d_info;
@@ -187,7 +197,8 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     const int qb = std::min(c.qcap, known.qmax + bs * (j - known.iter - 1));
     TLR_HIP(launch_randn(omega, m, bs, m, c.seed, c.stream_id, (unsigned)j, 0, st));
     if (p_blocks > 0 || bps_wa > 0)
-      TLR_HIP(launch_ara_tn(D, 0, omega, spec.uk, spec.rk, spec.p, p_blocks, cb, bps_wa, st));
+      TLR_HIP(launch_ara_tn(D, 0, omega, spec.uk, spec.rk, spec.p, p_blocks, cb, bps_wa, tn_scratch,
+                            st));
     if (any_z) TLR_HIP(launch_ara_z(D, dzseg, spec.p, spec.rk, cb, bps_z, st));
     hipEvent_t e1 = nullptr;
     if (spec.events) {
@@ -201,12 +212,12 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     if (e1) TLR_HIP(hipEventRecord(e1, st));
     const int bps_q = (qb + 31) / 32;
     if (bps_q > 0) {
-      TLR_HIP(launch_ara_tn(D, 1, nullptr, nullptr, 0, nullptr, 0, cb, bps_q, st));
+      TLR_HIP(launch_ara_tn(D, 1, nullptr, nullptr, 0, nullptr, 0, cb, bps_q, tn_scratch, st));
       TLR_HIP(launch_ara_seg(D, 1, cb, st));
     }
     TLR_HIP(launch_orth_step(D, 1, tau2, c.r_min, cb, st));
     if (bps_q > 0) {
-      TLR_HIP(launch_ara_tn(D, 2, nullptr, nullptr, 0, nullptr, 0, cb, bps_q, st));
+      TLR_HIP(launch_ara_tn(D, 2, nullptr, nullptr, 0, nullptr, 0, cb, bps_q, tn_scratch, st));
       TLR_HIP(launch_ara_seg(D, 2, cb, st));
     }
     TLR_HIP(launch_orth_step(D, 2, tau2, c.r_min, cb, st));

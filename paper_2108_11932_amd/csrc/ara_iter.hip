@@ -22,34 +22,91 @@ namespace tlr {
 
 namespace {
 
-constexpr int TN_NW = 8;
+constexpr int TN_NW = 4;
+constexpr int TN_KC = 16 * TN_NW;   // rows of K per workgroup: one 16-row slice per wave
+constexpr int TN_TM = 32;
 
-template <int FN>
-__global__ __launch_bounds__(512) void k_ara_tn(AraDev D, int mode, const double* omega,
-                                                const double* uk, int rk, double* P, int p_blocks,
-                                                int bps) {
-  constexpr int FM = 2;
-  __shared__ double red[TN_NW][FM * FN * 4][64];
-  const int m = D.m, bs = D.bs;
-  int b = blockIdx.x;
-  if (mode == 0 && b < p_blocks) {
-    tn_tile<FM, FN, TN_NW>(uk, m, omega, m, P, rk, rk, bs, 0, m, 1.0, 0.0, b * 16 * FM, 0, red);
-    return;
+// Output tile `tid` of a TN launch: operands, destination and bounds.
+struct TnTile {
+  const double* A;
+  const double* B;
+  double* C;
+  int M, ldc, row0, gtile;
+  double alpha;
+};
+__device__ inline bool tn_resolve(const AraDev& D, int mode, int tid, const double* omega,
+                                  const double* uk, int rk, double* P, int p_tiles, int tps,
+                                  TnTile* o) {
+  const int m = D.m;
+  if (mode == 0 && tid < p_tiles) {
+    *o = TnTile{uk, omega, P, rk, rk, tid * TN_TM, tid, 1.0};
+    return true;
   }
-  if (mode == 0) b -= p_blocks;
-  const int ai = b / bps, tile = b % bps;
-  if (ai >= D.counts[0]) return;
+  const int t = mode == 0 ? tid - p_tiles : tid;
+  const int ai = t / tps, tile = t % tps;
+  if (ai >= D.counts[0]) return false;
   const int slot = D.act[ai];
   const AraSlotDesc& d = D.slots[slot];
-  const int row0 = tile * 16 * FM;
+  const int row0 = tile * TN_TM;
   if (mode == 0) {
-    if (row0 >= d.a) return;
-    tn_tile<FM, FN, TN_NW>(d.va, m, omega, m, d.wa, d.a, d.a, bs, 0, m, 1.0, 0.0, row0, 0, red);
+    if (row0 >= d.a) return false;
+    *o = TnTile{d.va, omega, d.wa, d.a, d.a, row0, tid, 1.0};
   } else {
     const int q = D.q[slot];
-    if (row0 >= q) return;
+    if (row0 >= q) return false;
     const double* B = mode == 1 ? d.y : d.q + (size_t)q * m;
-    tn_tile<FM, FN, TN_NW>(d.q, m, B, m, d.c, m, q, bs, 0, m, -1.0, 0.0, row0, 0, red);
+    *o = TnTile{d.q, B, d.c, q, m, row0, tid, -1.0};
+  }
+  return true;
+}
+
+// The products of these kernels have few output tiles (a handful of active
+// tiles late in a column) and K = m, while one CU streams only a few tens of
+// GB/s: the K range is split over ceil(m / TN_KC) workgroups per output
+// tile, each storing its partial tile in scratch; k_ara_tn_sum then adds the
+// partials in a fixed order (a second launch rather than a cross-workgroup
+// handshake, whose device-scope fences are costly across the XCDs).
+template <int FN>
+__global__ __launch_bounds__(64 * TN_NW) void k_ara_tn(AraDev D, int mode, const double* omega,
+                                                        const double* uk, int rk, double* P,
+                                                        int p_tiles, int tps, double* scratch) {
+  constexpr int FM = 2, TSZ = TN_TM * 16 * FN;
+  __shared__ double red[TN_NW][FM * FN * 4][64];
+  const int m = D.m, bs = D.bs;
+  const int ks_n = (m + TN_KC - 1) / TN_KC;
+  const int ks = blockIdx.x % ks_n, tid = blockIdx.x / ks_n;
+  TnTile o;
+  if (!tn_resolve(D, mode, tid, omega, uk, rk, P, p_tiles, tps, &o)) return;
+  const int k0 = ks * TN_KC, k1 = min(m, k0 + TN_KC);
+  tn_tile<FM, FN, TN_NW, 1, true>(o.A, m, o.B, m, scratch + ((size_t)tid * ks_n + ks) * TSZ, TN_TM,
+                                  o.M, bs, k0, k1, 1.0, 0.0, o.row0, 0, red);
+}
+
+template <int FN>
+__global__ __launch_bounds__(256) void k_ara_tn_sum(AraDev D, int mode, const double* omega,
+                                                    const double* uk, int rk, double* P,
+                                                    int p_tiles, int tps, const double* scratch) {
+  constexpr int TSZ = TN_TM * 16 * FN;
+  const int m = D.m, bs = D.bs;
+  const int ks_n = (m + TN_KC - 1) / TN_KC;
+  TnTile o;
+  if (!tn_resolve(D, mode, blockIdx.x, omega, uk, rk, P, p_tiles, tps, &o)) return;
+  const double* part = scratch + (size_t)blockIdx.x * ks_n * TSZ;
+  for (int e = threadIdx.x; e < TSZ; e += 256) {
+    const int lr = e % TN_TM, lc = e / TN_TM;
+    if (o.row0 + lr >= o.M || lc >= bs) continue;
+    constexpr int CH = 16;
+    double v = 0.0;
+    for (int s0 = 0; s0 < ks_n; s0 += CH) {
+      double pv[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) pv[u] = part[(size_t)min(s0 + u, ks_n - 1) * TSZ + e];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (s0 + u < ks_n) v += pv[u];
+    }
+    o.C[o.row0 + lr + (size_t)lc * o.ldc] = o.alpha * v;
   }
 }
 
@@ -153,18 +210,32 @@ __global__ __launch_bounds__(256) void k_ara_seg(AraDev D, int mode) {
 
 }  // namespace
 
+int ara_tn_scratch(int m, int bs, long long tiles, size_t* doubles) {
+  const int ks_n = (m + TN_KC - 1) / TN_KC;
+  *doubles = (size_t)tiles * ks_n * TN_TM * (bs <= 16 ? 16 : 32);
+  return TN_TM;
+}
+
 hipError_t launch_ara_tn(const AraDev& D, int mode, const double* omega, const double* uk, int rk,
-                         double* P, int p_blocks, int count_bound, int bps, hipStream_t s) {
+                         double* P, int p_tiles, int count_bound, int tps, double* scratch,
+                         hipStream_t s) {
   if (D.bs > 32) return hipErrorInvalidValue;
-  const int pb = mode == 0 ? p_blocks : 0;
-  const long long n = pb + (long long)std::max(count_bound, 0) * std::max(bps, 0);
-  if (n <= 0) return hipSuccess;
-  if (D.bs <= 16)
-    hipLaunchKernelGGL((k_ara_tn<1>), dim3((unsigned)n), dim3(512), 0, s, D, mode, omega, uk, rk, P,
-                       pb, std::max(bps, 1));
-  else
-    hipLaunchKernelGGL((k_ara_tn<2>), dim3((unsigned)n), dim3(512), 0, s, D, mode, omega, uk, rk, P,
-                       pb, std::max(bps, 1));
+  const int pt = mode == 0 ? p_tiles : 0;
+  const int ks_n = (D.m + TN_KC - 1) / TN_KC;
+  const long long tiles = pt + (long long)std::max(count_bound, 0) * std::max(tps, 0);
+  if (tiles <= 0) return hipSuccess;
+  const int tp = std::max(tps, 1);
+  if (D.bs <= 16) {
+    hipLaunchKernelGGL((k_ara_tn<1>), dim3((unsigned)(tiles * ks_n)), dim3(64 * TN_NW), 0, s, D,
+                       mode, omega, uk, rk, P, pt, tp, scratch);
+    hipLaunchKernelGGL((k_ara_tn_sum<1>), dim3((unsigned)tiles), dim3(256), 0, s, D, mode, omega, uk,
+                       rk, P, pt, tp, scratch);
+  } else {
+    hipLaunchKernelGGL((k_ara_tn<2>), dim3((unsigned)(tiles * ks_n)), dim3(64 * TN_NW), 0, s, D,
+                       mode, omega, uk, rk, P, pt, tp, scratch);
+    hipLaunchKernelGGL((k_ara_tn_sum<2>), dim3((unsigned)tiles), dim3(256), 0, s, D, mode, omega, uk,
+                       rk, P, pt, tp, scratch);
+  }
   return hipGetLastError();
 }
 

@@ -66,6 +66,17 @@ __device__ inline dd dd_sqrt(dd a) {
 }
 
 
+// 1 / sqrt(a) for a > 0 to double-double accuracy: the FP64 estimate
+// y0 = 1 / sqrt(a.hi) and one Newton step y1 = y0 + y0 (1 - a y0^2) / 2,
+// with the residual 1 - a y0^2 formed in double-double.
+__device__ inline dd dd_rsqrt(dd a) {
+#pragma clang fp contract(off)
+  const double y0 = 1.0 / sqrt(a.hi);
+  const dd y2 = two_prod(y0, y0);
+  const dd e = dd_sub(dd{1.0, 0.0}, dd_mul(a, y2));
+  return fast_two_sum(y0, y0 * (e.hi * 0.5));
+}
+
 // One step of the compensated dot product of Ogita, Rump and Oishi (Dot2):
 // (s, c) accumulates x * y.
 __device__ inline void dot2_step(double x, double y, double& s, double& c) {

@@ -160,13 +160,13 @@ struct Plan {
 // Per-column workspace of the factorization.
 struct Work {
   DevBuf G, W, omega, P, Z, T, Ta, H, Ball, C, Wa, Y, Q, part, ints, orth, dscale, tol,
-      compact, Bt, fro;
+      compact, Bt, fro, tnpart;
   // buffers of the diagonal-tile stream (never touched by the main stream)
   DevBuf Wd, dW, dtol, sideblob;
   int slots = 0;   // slot capacity of the per-tile buffers
   void release_all(Mem& mem) {
     DevBuf* bufs[] = {&G, &W, &omega, &P, &Z, &T, &Ta, &H, &Ball, &C, &Wa, &Y, &Q, &part,
-                      &ints, &orth, &dscale, &tol, &compact, &Bt, &fro, &Wd, &dW, &dtol, &sideblob};
+                      &ints, &orth, &dscale, &tol, &compact, &Bt, &fro, &tnpart, &Wd, &dW, &dtol, &sideblob};
     for (DevBuf* b : bufs) b->release(mem);
   }
 };

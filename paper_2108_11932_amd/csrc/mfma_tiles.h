@@ -24,7 +24,9 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // past the end of K read a clamped in-range address and are zeroed.  The NW
 // partial tiles are added in LDS (red, NW x FM FN 4 x 64) in a fixed order.
 // Every thread of the workgroup must call it.
-template <int FM, int FN, int NW>
+// With LOCAL set, the raw sum (no alpha, beta or bounds) is written to the
+// dense 16 FM x 16 FN tile C (ld 16 FM) instead: a partial of a split-K sum.
+template <int FM, int FN, int NW, int U = 4, bool LOCAL = false>
 __device__ inline void tn_tile(const double* __restrict__ A, int lda, const double* __restrict__ B,
                                int ldb, double* C, int ldc, int M, int N, int kbeg, int kend,
                                double alpha, double beta, int row0, int col0,
@@ -49,7 +51,6 @@ __device__ inline void tn_tile(const double* __restrict__ A, int lda, const doub
     const int j = col0 + b * 16 + li;
     bcol[b] = B + (size_t)(j < N ? j : 0) * ldb;
   }
-  constexpr int U = 4;
   for (int k0 = kbeg + wave * 16; k0 < kend; k0 += 16 * NW * U) {
     double av[U][FM][4], bv[U][FN][4];
 #pragma unroll
@@ -99,12 +100,16 @@ __device__ inline void tn_tile(const double* __restrict__ A, int lda, const doub
     const int slot = e >> 6, l = e & 63;
     const int ab = slot >> 2, r = slot & 3;
     const int a = ab / FN, b = ab % FN;
-    const int gr = row0 + a * 16 + (l >> 4) + 4 * r;
-    const int gc = col0 + b * 16 + (l & 15);
-    if (gr >= M || gc >= N) continue;
+    const int lr = a * 16 + (l >> 4) + 4 * r, lc = b * 16 + (l & 15);
+    const int gr = row0 + lr, gc = col0 + lc;
     double v = red[0][slot][l];
 #pragma unroll
     for (int w = 1; w < NW; ++w) v += red[w][slot][l];
+    if (LOCAL) {
+      C[lr + lc * 16 * FM] = v;
+      continue;
+    }
+    if (gr >= M || gc >= N) continue;
     double* cp = C + gr + (size_t)gc * ldc;
     double out = alpha * v;
     if (beta != 0.0) out += beta * *cp;

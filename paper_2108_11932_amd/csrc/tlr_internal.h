@@ -146,11 +146,16 @@ struct AraDev {
 // Block sizes the orthogonalisation kernels are built for (1, 2, 4, 8, 16,
 // 24, 32).
 bool orth_block_supported(int bs);
-// mode 0: P = Uk^T Omega (P: rk x bs, ld rk, first p_blocks blocks) and
-//         W^A = V^A^T Omega per active slot (bps blocks per slot);
-// mode 1: C = -Q^T Y; mode 2: C = -Q^T X, X = Q(:, q : q + bs) (bps blocks).
+// mode 0: P = Uk^T Omega (P: rk x bs, ld rk, p_tiles tiles of 32 rows) and
+//         W^A = V^A^T Omega per active slot (tps tiles per slot);
+// mode 1: C = -Q^T Y; mode 2: C = -Q^T X, X = Q(:, q : q + bs) (tps tiles).
+// K is split over workgroups whose partial tiles go to scratch and are
+// summed by a second launch; ara_tn_scratch gives the doubles of scratch for
+// `tiles` output tiles (and returns the tile height).
+int ara_tn_scratch(int m, int bs, long long tiles, size_t* doubles);
 hipError_t launch_ara_tn(const AraDev& D, int mode, const double* omega, const double* uk, int rk,
-                         double* P, int p_blocks, int count_bound, int bps, hipStream_t s);
+                         double* P, int p_tiles, int count_bound, int tps, double* scratch,
+                         hipStream_t s);
 // Z of every active slot (bps blocks of 64 rows per slot).
 hipError_t launch_ara_z(const AraDev& D, const ZSeg* segs, const double* P, int ldp,
                         int count_bound, int bps, hipStream_t s);
