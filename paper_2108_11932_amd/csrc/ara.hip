@@ -238,35 +238,40 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
       }
     }
   } else {
+    // pass 2: the Gram of the new columns is within u * cond of the
+    // identity, so its Cholesky factor is taken in FP64 (the Gram itself
+    // was summed with compensation)
     np = nc;
+    double gd[CPG];
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) gd[i] = gv[i].hi + gv[i].lo;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) {
+      const int b = g * CPG + i;
+      if (g < NG && b < BS) ((double (*)[BS + 1])smem)[x][b] = gd[i];
+    }
+    __syncthreads();
     for (int j = 0; j < nc; ++j) {
-      dd (*Gr)[BS + 1] = (dd (*)[BS + 1])(smem + 2 * GSZ * (j & 1));
-      dd (*Gw)[BS + 1] = (dd (*)[BS + 1])(smem + 2 * GSZ * ((j & 1) ^ 1));
-      const dd gjj = Gr[j][j];
-      dd rinv, gj;
-      if (gjj.hi > 0.0) {
-        rinv = dd_rsqrt(gjj);
-        gj = dd_mul(gjj, rinv);
-      } else {
-        rinv = dd{1.0, 0.0};
-        gj = dd{1.0, 0.0};
+      double (*Gr)[BS + 1] = (double (*)[BS + 1])(smem + GSZ * (j & 1));
+      double (*Gw)[BS + 1] = (double (*)[BS + 1])(smem + GSZ * ((j & 1) ^ 1));
+      const double gjj = Gr[j][j];
+      double gj = 1.0, rinv = 1.0;
+      if (gjj > 0.0) {
+        gj = sqrt(gjj);
+        rinv = 1.0 / gj;
       }
-      const dd lx = (x > j && x < nc) ? dd_mul(Gr[x][j], rinv) : dd{0.0, 0.0};
-      dd lb[CPG];
+      const double lx = (x > j && x < nc) ? Gr[x][j] * rinv : 0.0;
 #pragma unroll
       for (int i = 0; i < CPG; ++i) {
         const int b = g * CPG + i;
-        lb[i] = (b > j && b < nc) ? dd_mul(Gr[j][b], rinv) : (b == j ? gj : dd{0.0, 0.0});
-      }
-#pragma unroll
-      for (int i = 0; i < CPG; ++i) {
-        const int b = g * CPG + i;
+        const double lb = (b > j && b < nc) ? Gr[j][b] * rinv : (b == j ? gj : 0.0);
         if (g < NG && b < BS) {
           if (x > j && b > j) {
-            gv[i] = dd_sub(gv[i], dd_mul(lx, lb[i]));
-            Gw[x][b] = gv[i];
+            gd[i] = fma(-lx, lb, gd[i]);
+            Gw[x][b] = gd[i];
           }
-          if (x == 0 && b >= j) Rs[j][b] = lb[i].hi + lb[i].lo;
+          if (x == 0 && b >= j) Rs[j][b] = lb;
         }
       }
       __syncthreads();
@@ -375,7 +380,7 @@ __global__ __launch_bounds__(256) void k_compact(int* act, int* counts, const in
 // compact and refill, then record the status word and the largest basis
 // width among the active slots (the host's bound for the next products).
 __global__ __launch_bounds__(256) void k_ara_compact(AraDev D, const int* waiting, int nwaiting,
-                                                     int s_max, const int* info) {
+                                                     int s_max, const int* info, int* host_out) {
   __shared__ int keep_total;
   __shared__ int scan[256];
   const int tid = threadIdx.x;
@@ -398,6 +403,13 @@ __global__ __launch_bounds__(256) void k_ara_compact(AraDev D, const int* waitin
   if (tid == 0) {
     D.counts[3] = scan[0];
     D.counts[2] = info ? *info : 0;
+  }
+  // the four counters also go straight to the host's read-back slot
+  // (pinned memory, stores at system scope)
+  if (host_out && tid < 4) {
+    const int v = tid == 0 ? D.counts[0] : tid == 1 ? D.counts[1] : tid == 2 ? (info ? *info : 0)
+                                                                             : scan[0];
+    __hip_atomic_store(host_out + tid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -472,8 +484,9 @@ hipError_t launch_orth_step(const AraDev& D, int pass, double tau2, int r_min, i
 }
 
 hipError_t launch_ara_compact(const AraDev& D, const int* waiting, int nwaiting, int s_max,
-                              const int* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_ara_compact, dim3(1), dim3(256), 0, s, D, waiting, nwaiting, s_max, info);
+                              const int* info, int* host_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_ara_compact, dim3(1), dim3(256), 0, s, D, waiting, nwaiting, s_max, info,
+                     host_out);
   return hipGetLastError();
 }
 

@@ -184,7 +184,9 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     TLR_TRY(w.tnpart.ensure(h->mem, sizeof(double) * std::max<size_t>(need, 1)));
     tn_scratch = w.tnpart.as<double>();
   }
-  const int bps_z = (spec.r_max + 63) / 64;
+  int max_pieces = 0;
+  for (const AraSlotDesc& d : spec.slots) max_pieces = std::max(max_pieces, d.nz);
+  const int bps_z = (max_pieces + 3) / 4;
   const bool any_z = !spec.zseg.empty() && bps_z > 0 && spec.rk > 0;
   int* info = h->d_info;
 
@@ -221,8 +223,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       TLR_HIP(launch_ara_seg(D, 2, cb, st));
     }
     TLR_HIP(launch_orth_step(D, 2, tau2, c.r_min, cb, st));
-    TLR_HIP(launch_ara_compact(D, s.waiting, nwait, s_max, info, st));
-    TLR_HIP(hipMemcpyAsync(ring + 8 * (j & 1), s.counts, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+    TLR_HIP(launch_ara_compact(D, s.waiting, nwait, s_max, info, ring + 8 * (j & 1), st));
     TLR_HIP(hipEventRecord(h->ev_rb[j & 1], st));
     return TLR_OK;
   };

@@ -110,56 +110,48 @@ __global__ __launch_bounds__(256) void k_ara_tn_sum(AraDev D, int mode, const do
   }
 }
 
-// 64 rows of Z per block; each output row lies in exactly one segment
-// (the rows of tile (i, j) in the panel).  The slot's segment table is
-// staged in LDS and searched there; the contraction over the segment's
-// columns loads ZCH G and P values ahead of the sums.
-constexpr int ZROWS = 64;
-constexpr int ZSEG_MAX = 1024;   // segments staged in LDS (j < k <= nb)
-constexpr int ZCH = 8;
+// Z on the matrix cores: one wave per piece (16 rows of one block G_ij P_j),
+// four pieces per workgroup.  Lane l supplies G(l % 16, t) and P(t, l % 16)
+// for t = t0 + l / 16; the k loop loads ZCH MFMA steps ahead.
+constexpr int ZCH = 4;
 
 __global__ __launch_bounds__(256) void k_ara_z(AraDev D, const ZSeg* __restrict__ segs,
                                                const double* __restrict__ P, int ldp, int bps) {
-  __shared__ int zrow[ZSEG_MAX];
-  const int ai = blockIdx.x / bps, tile = blockIdx.x % bps;
+  const int ai = blockIdx.x / bps, tb = blockIdx.x % bps;
   if (ai >= D.counts[0]) return;
   const int slot = D.act[ai];
   const AraSlotDesc& d = D.slots[slot];
-  const int r0 = tile * ZROWS;
-  if (r0 >= d.R) return;
-  const int bs = D.bs, nz = d.nz;
-  const ZSeg* sg = segs + d.zseg;
-  for (int e = threadIdx.x; e < nz && e < ZSEG_MAX; e += 256) zrow[e] = sg[e].zrow;
-  __syncthreads();
-  const int nzl = min(nz, ZSEG_MAX);
-  for (int e = threadIdx.x; e < ZROWS * bs; e += 256) {
-    const int row = r0 + (e % ZROWS), col = e / ZROWS;
-    if (row >= d.R) continue;
-    int lo = 0, hi = nzl - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (zrow[mid] <= row) lo = mid; else hi = mid - 1;
-    }
-    // a panel of more than ZSEG_MAX segments continues linearly
-    while (lo + 1 < nz && sg[lo + 1].zrow <= row) ++lo;
-    const ZSeg z = sg[lo];
-    const double* gr = z.g + (row - z.zrow);
-    const double* pc = P + z.prow + (size_t)col * ldp;
-    double v = 0.0;
-    for (int t0 = 0; t0 < z.cols; t0 += ZCH) {
-      double gv[ZCH], pv[ZCH];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int pi = tb * 4 + wave;
+  if (pi >= d.nz) return;
+  const ZSeg z = segs[d.zseg + pi];
+  const int bs = D.bs;
+  const int li = lane & 15, kq = lane >> 4;
+  const double* grow = z.g + min(li, z.rows - 1);
+  for (int n0 = 0; n0 < bs; n0 += 16) {
+    const double* pcol = P + z.prow + (size_t)min(n0 + li, bs - 1) * ldp;
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    for (int t0 = 0; t0 < z.cols; t0 += 4 * ZCH) {
+      double av[ZCH], bv[ZCH];
 #pragma unroll
       for (int u = 0; u < ZCH; ++u) {
-        const int t = min(t0 + u, z.cols - 1);
-        gv[u] = gr[(size_t)t * z.rows];
-        pv[u] = pc[t];
+        const int t = min(t0 + 4 * u + kq, z.cols - 1);
+        av[u] = grow[(size_t)t * z.ldg];
+        bv[u] = pcol[t];
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = 0; u < ZCH; ++u)
-        if (t0 + u < z.cols) v += gv[u] * pv[u];
+      for (int u = 0; u < ZCH; ++u) {
+        if (t0 + 4 * u + kq >= z.cols) av[u] = 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+      }
     }
-    d.z[row + (size_t)col * d.R] = -v;
+    // accumulator register r of lane l holds row l / 16 + 4 r, column l % 16
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = kq + 4 * r, col = n0 + li;
+      if (row < z.rows && col < bs) d.z[z.zrow + row + (size_t)col * d.R] = -acc[r];
+    }
   }
 }
 

@@ -349,8 +349,9 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
           d.zseg = (int)spec.zseg.size();
           for (int j = 0; j < k; ++j) {
             const int rij = h->lr(i, j);
-            if (rij == 0) continue;
-            spec.zseg.push_back(ZSeg{gptr(i, j), rij, h->lr(k, j), (int)h->lo(i, j), (int)h->lo(k, j)});
+            for (int r0 = 0; r0 < rij; r0 += 16)
+              spec.zseg.push_back(ZSeg{gptr(i, j) + r0, rij, std::min(16, rij - r0), h->lr(k, j),
+                                       (int)h->lo(i, j) + r0, (int)h->lo(k, j)});
           }
           d.nz = (int)spec.zseg.size() - d.zseg;
           spec.r_max = std::max(spec.r_max, Ri);
@@ -366,7 +367,7 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
     cfg.stream_id = (unsigned)k;
     bool abort = false;
     TLR_TRY(ara_run(h, cfg, slots, order, spec, &res, &abort, [&]() -> tlr_status {
-      return dplan.pending() ? dplan.run_some(24) : TLR_OK;
+      return dplan.pending() ? dplan.run_some(8) : TLR_OK;
     }));
     TLR_TRY(side_done());
     // W^A, Z and P products of the iterations

@@ -115,7 +115,7 @@ struct AraSlotDesc {
   const double* va;
   double* wa;
   int a;
-  // Z = -[G_ij P_j]_j (R x bs, ld R) over segments [zseg, zseg + nz)
+  // Z = -[G_ij P_j]_j (R x bs, ld R) over the tiles [zseg, zseg + nz)
   int zseg, nz, R;
   double* z;
   // workspace
@@ -126,10 +126,12 @@ struct AraSlotDesc {
   double* part2;          // Gram partials of the new columns X
   int* piv;               // pivots, then the accepted count at [bs]
 };
-// Z(zrow + r, :) = -G (rows x cols, ld rows) P(prow : prow + cols, :)
+// One 16-row piece of a block of Z:
+// Z(zrow + r, :) = -G(r, 0 : cols) P(prow : prow + cols, :), r < rows <= 16,
+// G column-major with leading dimension ldg.
 struct ZSeg {
   const double* g;
-  int rows, cols, zrow, prow;
+  int ldg, rows, cols, zrow, prow;
 };
 // Device state of one ARA run (passed by value).
 struct AraDev {
@@ -156,7 +158,7 @@ int ara_tn_scratch(int m, int bs, long long tiles, size_t* doubles);
 hipError_t launch_ara_tn(const AraDev& D, int mode, const double* omega, const double* uk, int rk,
                          double* P, int p_tiles, int count_bound, int tps, double* scratch,
                          hipStream_t s);
-// Z of every active slot (bps blocks of 64 rows per slot).
+// Z of every active slot (bps blocks of four Z pieces per slot).
 hipError_t launch_ara_z(const AraDev& D, const ZSeg* segs, const double* P, int ldp,
                         int count_bound, int bps, hipStream_t s);
 // mode 0: sample Y; mode 1: Y += Q C; mode 2: X += Q C; all write the Gram
@@ -169,9 +171,10 @@ hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_
 hipError_t launch_orth_step(const AraDev& D, int pass, double tau2, int r_min, int count_bound,
                             hipStream_t s);
 // Commit the basis widths, compact the active list and refill it (see
-// launch_compact), and record the status word and the largest active width.
+// launch_compact), and record the status word and the largest active width;
+// counts[0..3] are also stored to host_out (pinned host memory) when given.
 hipError_t launch_ara_compact(const AraDev& D, const int* waiting, int nwaiting, int s_max,
-                              const int* info, hipStream_t s);
+                              const int* info, int* host_out, hipStream_t s);
 
 // Dynamic batching: stable compaction of the active list by the convergence
 // flags (flag[slot] != 0 removes the slot), then refill from the waiting
