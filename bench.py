@@ -26,6 +26,40 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+# measured HBM traffic of the sampling kernel (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, calibrated on a plain copy); valid only for the kernel sources
+# it was measured on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sampling_traffic_cov2d_131k.txt")
+KERNEL_SOURCES = ["paper_2108_11932_amd/csrc/ara_iter.hip", "paper_2108_11932_amd/csrc/mfma_tiles.h",
+                  "paper_2108_11932_amd/csrc/tlr_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the sampling kernel from the committed counter
+    summary, or None when it is absent, for another workload, or taken on
+    other kernel sources."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("workload") != workload or kv.get("source_sha256") != kernel_source_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 METRIC = "TLR Cholesky time-to-solution + TFLOP/s, N=131072 eps=1e-6; FP64 vs mixed"
 
 
@@ -104,7 +138,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cov2d_131k")
     ap.add_argument("--bs", type=int, default=0, help="ARA block size (0 = the workload's)")
-    ap.add_argument("--cpu-sample", type=int, default=8192,
+    ap.add_argument("--cpu-sample", type=int, default=12288,
                     help="points of the leading block the CPU oracle factors (0 = skip)")
     ap.add_argument("--no-forms", dest="forms", action="store_false",
                     help="skip the relative-threshold FP64 / mixed-precision comparison")
@@ -196,7 +230,7 @@ def main():
         "residual": err_primary,
         "forms": forms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name),
                      "kernel": "Schur-complement sampling product Y_i -= U_i* Z_i",
                      "launches": int(smp_n / max(1, a.steps)),
                      "bytes_per_launch": smp_bytes / max(1, smp_n),

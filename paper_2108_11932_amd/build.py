@@ -3,7 +3,8 @@
 Usage: python -m paper_2108_11932_amd.build [--jobs N] [--debug]
 
 Every .hip and .cpp source under csrc/ is compiled to an object in _build/
-at the repository root and linked into paper_2108_11932_amd/libtlr.so.
+at the repository root and linked into paper_2108_11932_amd/libtlr.so,
+without a hard dependency on a HIP runtime (see hip_runtime() in tlr.py).
 The build always recompiles (it is the "does it build" check).
 """
 from __future__ import annotations
@@ -61,7 +62,10 @@ def build(jobs: int = 0, debug: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: compile_one(s, debug), srcs))
     tmp = OUT + ".tmp"
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    # no HIP runtime is linked in: the library binds to the runtime already
+    # loaded in the process (the binding loads torch's, so that one process
+    # never holds two HIP runtimes; C programs link -lamdhip64 themselves)
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-no-hip-rt", "-o", tmp] + objs
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), r.stdout))

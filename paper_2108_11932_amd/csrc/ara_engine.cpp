@@ -202,16 +202,15 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       TLR_HIP(launch_ara_tn(D, 0, omega, spec.uk, spec.rk, spec.p, p_blocks, cb, bps_wa, tn_scratch,
                             st));
     if (any_z) TLR_HIP(launch_ara_z(D, dzseg, spec.p, spec.rk, cb, bps_z, st));
-    hipEvent_t e1 = nullptr;
     if (spec.events) {
-      hipEvent_t e0;
+      hipEvent_t e0, e1;
       TLR_HIP(hipEventCreate(&e0));
       TLR_HIP(hipEventCreate(&e1));
       spec.events->push_back({e0, e1});
-      TLR_HIP(hipEventRecord(e0, st));
+      TLR_HIP(launch_ara_seg(D, 0, cb, st, e0, e1));
+    } else {
+      TLR_HIP(launch_ara_seg(D, 0, cb, st));
     }
-    TLR_HIP(launch_ara_seg(D, 0, cb, st));
-    if (e1) TLR_HIP(hipEventRecord(e1, st));
     const int bps_q = (qb + 31) / 32;
     if (bps_q > 0) {
       TLR_HIP(launch_ara_tn(D, 1, nullptr, nullptr, 0, nullptr, 0, cb, bps_q, tn_scratch, st));
@@ -259,14 +258,8 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     }
   }
   res->launches = known.iter + 1;
-  // the iterations enqueued past the last active one found nothing to do
-  if (spec.events)
-    while ((int)spec.events->size() > known.iter + 1) {
-      (void)hipEventDestroy(spec.events->back().first);
-      (void)hipEventDestroy(spec.events->back().second);
-      spec.events->pop_back();
-    }
-
+  // the iteration enqueued past the last active one found nothing to do;
+  // its (empty) sampling launch stays in the timed set, as it runs
   // ---- results: basis widths, iteration counts, summed widths
   const size_t stride = (size_t)(s.qnew - s.q);
   std::vector<int> back(5 * stride);

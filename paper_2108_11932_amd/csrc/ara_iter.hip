@@ -11,6 +11,8 @@
 //              Y_i += Q_i C_i  /  X_i += Q_i C_i                 (modes 1, 2)
 //              and the double-double Gram partials of the result per
 //              16-row strip (input of the Cholesky QR step)
+#include <hip/hip_ext.h>
+
 #include "dd.h"
 #include "mfma_tiles.h"
 #include "tlr_internal.h"
@@ -155,8 +157,11 @@ __global__ __launch_bounds__(256) void k_ara_z(AraDev D, const ZSeg* __restrict_
   }
 }
 
-template <int NF>
-__global__ __launch_bounds__(256) void k_ara_seg(AraDev D, int mode) {
+// MODE 0 (the sampling product) and modes 1, 2 are separate instantiations
+// so that profiles tell them apart.
+template <int NF, int MODE>
+__global__ __launch_bounds__(256) void k_ara_seg(AraDev D) {
+  constexpr int mode = MODE;
   __shared__ double red[4][NF * 4][64];
   __shared__ double ys[16][16 * NF + 1];
   const int ns = D.nstrip;
@@ -239,14 +244,29 @@ hipError_t launch_ara_z(const AraDev& D, const ZSeg* segs, const double* P, int 
   return hipGetLastError();
 }
 
-hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_t s) {
-  if (D.bs > 32) return hipErrorInvalidValue;
+hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_t s,
+                          hipEvent_t start, hipEvent_t stop) {
+  if (D.bs > 32 || mode < 0 || mode > 2) return hipErrorInvalidValue;
   const long long n = (long long)std::max(count_bound, 0) * D.nstrip;
   if (n <= 0) return hipSuccess;
-  if (D.bs <= 16)
-    hipLaunchKernelGGL((k_ara_seg<1>), dim3((unsigned)n), dim3(256), 0, s, D, mode);
-  else
-    hipLaunchKernelGGL((k_ara_seg<2>), dim3((unsigned)n), dim3(256), 0, s, D, mode);
+  const dim3 g((unsigned)n), b(256);
+  if (start || stop) {
+    // the events take the dispatch's own begin and end timestamps
+    if (D.bs <= 16)
+      hipExtLaunchKernelGGL((k_ara_seg<1, 0>), g, b, 0, s, start, stop, 0, D);
+    else
+      hipExtLaunchKernelGGL((k_ara_seg<2, 0>), g, b, 0, s, start, stop, 0, D);
+    return mode == 0 ? hipGetLastError() : hipErrorInvalidValue;
+  }
+  if (D.bs <= 16) {
+    if (mode == 0) hipLaunchKernelGGL((k_ara_seg<1, 0>), g, b, 0, s, D);
+    if (mode == 1) hipLaunchKernelGGL((k_ara_seg<1, 1>), g, b, 0, s, D);
+    if (mode == 2) hipLaunchKernelGGL((k_ara_seg<1, 2>), g, b, 0, s, D);
+  } else {
+    if (mode == 0) hipLaunchKernelGGL((k_ara_seg<2, 0>), g, b, 0, s, D);
+    if (mode == 1) hipLaunchKernelGGL((k_ara_seg<2, 1>), g, b, 0, s, D);
+    if (mode == 2) hipLaunchKernelGGL((k_ara_seg<2, 2>), g, b, 0, s, D);
+  }
   return hipGetLastError();
 }
 

@@ -191,7 +191,9 @@ hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, i
   if (nblocks <= 0) return hipSuccess;
   if (!trans_a && !trans_b) return launch_tt<false, false>(d_descs, d_map, nblocks, bn, s);
   if (trans_a && !trans_b) {
-    if (bn <= 16)
+    if (bn == 0)
+      hipLaunchKernelGGL((k_gemm_tn<1, 1>), dim3(nblocks), dim3(512), 0, s, d_descs, d_map);
+    else if (bn <= 16)
       hipLaunchKernelGGL((k_gemm_tn<2, 1>), dim3(nblocks), dim3(512), 0, s, d_descs, d_map);
     else
       hipLaunchKernelGGL((k_gemm_tn<2, 2>), dim3(nblocks), dim3(512), 0, s, d_descs, d_map);

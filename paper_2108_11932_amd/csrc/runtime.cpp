@@ -227,34 +227,55 @@ void Plan::launch(std::function<hipError_t()> f) {
   steps.push_back([f](const char*) { return f(); });
 }
 
-static void build_map(const GemmBatch& b, std::vector<BlockMap>* map, int* bn) {
-  int maxn = 0;
-  for (const auto& g : b.d) maxn = g.N > maxn ? g.N : maxn;
-  int TM = 64;
-  gemm_tile_shape(b.ta, b.tb, maxn, &TM, bn);
-  for (size_t i = 0; i < b.d.size(); ++i) {
-    const int tm = (b.d[i].M + TM - 1) / TM, tn = (b.d[i].N + *bn - 1) / *bn;
+// Block map of the problems `idx` of a batch with tiles TM x TN.
+static void build_map(const GemmBatch& b, const std::vector<int>& idx, int TM, int TN,
+                      std::vector<BlockMap>* map) {
+  for (int i : idx) {
+    const int tm = (b.d[i].M + TM - 1) / TM, tn = (b.d[i].N + TN - 1) / TN;
     for (int t = 0; t < tm * tn; ++t) {
-      if ((b.d[i].flags & GEMM_LOWER_C) && (t / tm) * *bn >= (t % tm) * TM + TM) continue;
-      map->push_back(BlockMap{(int)i, t});
+      if ((b.d[i].flags & GEMM_LOWER_C) && (t / tm) * TN >= (t % tm) * TM + TM) continue;
+      map->push_back(BlockMap{i, t});
     }
   }
 }
 
 void Plan::gemm(const GemmBatch& b) {
   if (b.d.empty()) return;
-  std::vector<BlockMap> map;
-  int bn = 16;
-  build_map(b, &map, &bn);
+  // TN batches are split into a class of problems that fit one 16 x 16 tile
+  // (most of the per-tile products G_ij, U_ij^T Q_i of the method) and the
+  // rest, so that small problems do not run on large, mostly idle tiles
+  std::vector<int> small, large;
+  int maxn = 0;
+  for (size_t i = 0; i < b.d.size(); ++i) {
+    const bool sm = b.ta && !b.tb && b.d[i].M <= 16 && b.d[i].N <= 16;
+    (sm ? small : large).push_back((int)i);
+    if (!sm) maxn = std::max(maxn, b.d[i].N);
+  }
   const size_t od = stage(b.d.data(), b.d.size() * sizeof(GemmDesc));
-  const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
-  const int nblk = (int)map.size();
   const bool ta = b.ta, tb = b.tb;
   hipStream_t st = s;
-  steps.push_back([=](const char* base) {
-    return launch_gemm_batched((const GemmDesc*)(base + od), (const BlockMap*)(base + om), nblk, ta,
-                               tb, bn, st);
-  });
+  if (!small.empty()) {
+    std::vector<BlockMap> map;
+    build_map(b, small, 16, 16, &map);
+    const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
+    const int nblk = (int)map.size();
+    steps.push_back([=](const char* base) {
+      return launch_gemm_batched((const GemmDesc*)(base + od), (const BlockMap*)(base + om), nblk,
+                                 ta, tb, 0, st);
+    });
+  }
+  if (!large.empty()) {
+    int TM = 64, bn = 16;
+    gemm_tile_shape(ta, tb, maxn, &TM, &bn);
+    std::vector<BlockMap> map;
+    build_map(b, large, TM, bn, &map);
+    const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
+    const int nblk = (int)map.size();
+    steps.push_back([=](const char* base) {
+      return launch_gemm_batched((const GemmDesc*)(base + od), (const BlockMap*)(base + om), nblk,
+                                 ta, tb, bn, st);
+    });
+  }
   flops += b.flops;
 }
 

@@ -47,6 +47,7 @@ int gemm_tile_n(int N);                     // BN chosen for a problem (16 or 64
 // Output tile (rows x cols) of the kernel that runs a batch with these
 // transpositions and largest N; the block map enumerates tiles of this shape.
 void gemm_tile_shape(bool trans_a, bool trans_b, int maxn, int* tm, int* tn);
+// bn = 0 selects 16 x 16 tiles (transposed A only).
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, int nblocks,
                                bool trans_a, bool trans_b, int bn, hipStream_t s);
 
@@ -163,7 +164,10 @@ hipError_t launch_ara_z(const AraDev& D, const ZSeg* segs, const double* P, int 
                         int count_bound, int bps, hipStream_t s);
 // mode 0: sample Y; mode 1: Y += Q C; mode 2: X += Q C; all write the Gram
 // partials of their output (part1 for modes 0/1, part2 for mode 2).
-hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_t s);
+// With start/stop events (mode 0 only) the events record the launch's own
+// begin and end.
+hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_t s,
+                          hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // Cholesky QR step of pass 1 (pivoted, thresholded: appends the accepted
 // directions of Y to Q, sets qnew, flag, pivots, iteration counters and the
 // Gram partials of the new columns) or pass 2 (re-orthonormalises the new

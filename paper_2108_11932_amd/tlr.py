@@ -120,12 +120,48 @@ SIGNATURES = {
 }
 
 
+_hip = None
+
+
+def hip_runtime():
+    """Make the process's HIP runtime visible to libtlr.so, which links none.
+
+    PyTorch's ROCm wheel carries its own libamdhip64; loading a second
+    runtime (the system's) beside it would give the process two HIP runtimes
+    whose devices and streams do not mix.  So torch's runtime is promoted to
+    global symbol scope (dlopen of an already loaded library returns it) and
+    libtlr.so binds to it; without torch the system runtime is used."""
+    global _hip
+    if _hip is None:
+        cands = []
+        try:
+            import torch
+            cands.append(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so"))
+        except ImportError:  # pragma: no cover
+            pass
+        rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+        cands += [os.path.join(rocm, "lib", "libamdhip64.so"), "libamdhip64.so"]
+        err = None
+        for c in cands:
+            if os.path.sep in c and not os.path.exists(c):
+                continue
+            try:
+                _hip = ctypes.CDLL(c, mode=ctypes.RTLD_GLOBAL)
+                break
+            except OSError as e:  # pragma: no cover
+                err = e
+        if _hip is None:
+            raise RuntimeError("no HIP runtime library found: %s" % err)
+    return _hip
+
+
 def lib():
     """The loaded libtlr.so; raises if it has not been built."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libtlr.so not built: run `python -m paper_2108_11932_amd.build`")
+        hip_runtime()
         l = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(l, name)
