@@ -119,9 +119,10 @@ def residual(mat, torch, nvec: int = 4, seed: int = 7) -> float:
     return float((r.norm(dim=0) / x.norm(dim=0)).max())
 
 
-def time_form(mat, w, eps_mode, precision, tlr, torch, steps, warmup):
+def time_form(mat, w, eps_mode, precision, tlr, torch, steps, warmup, bs_tail=0):
     """Warm up, then time `steps` factorizations of one form."""
-    o = tlr.opts(bs=w.bs, eps_mode=eps_mode, precision=precision, flags=tlr.FLAG_KERNEL_TIMING)
+    o = tlr.opts(bs=w.bs, bs_tail=bs_tail, eps_mode=eps_mode, precision=precision,
+                 flags=tlr.FLAG_KERNEL_TIMING)
     for _ in range(warmup):
         mat.potrf(w.eps, o)
     torch.cuda.synchronize()
@@ -138,6 +139,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cov2d_131k")
     ap.add_argument("--bs", type=int, default=0, help="ARA block size (0 = the workload's)")
+    ap.add_argument("--bs-tail", type=int, default=0,
+                    help="ARA block size after the first iteration of a column (0 = bs)")
     ap.add_argument("--cpu-sample", type=int, default=12288,
                     help="points of the leading block the CPU oracle factors (0 = skip)")
     ap.add_argument("--no-forms", dest="forms", action="store_false",
@@ -177,7 +180,7 @@ def main():
     print("[bench] input built in %.1fs, ranks %d..%d mean %.1f" % (t_build, ra.min(), ra.max(),
                                                                      ra.mean()), file=sys.stderr,
           flush=True)
-    dt, stats = time_form(mat, w, w.eps_mode, tlr.FP64, tlr, torch, a.steps, a.warmup)
+    dt, stats = time_form(mat, w, w.eps_mode, tlr.FP64, tlr, torch, a.steps, a.warmup, a.bs_tail)
     print("[bench] %d timed steps, %.1f ms each" % (a.steps, dt * 1e3), file=sys.stderr, flush=True)
     err_primary = residual(mat, torch)
     flops = float(np.mean([s["flops"] for s in stats]))
@@ -194,7 +197,7 @@ def main():
     if a.forms:
         for name, mode, prec in (("fp64_rel", 1, tlr.FP64), ("mixed_fp32_rel", 1, tlr.MIXED_FP32),
                                  ("mixed_fp32_abs", 0, tlr.MIXED_FP32)):
-            fdt, fst = time_form(mat, w, mode, prec, tlr, torch, a.steps, a.warmup)
+            fdt, fst = time_form(mat, w, mode, prec, tlr, torch, a.steps, a.warmup, a.bs_tail)
             s0 = fst[-1]
             forms[name] = {"ms_per_step": fdt * 1e3,
                            "tflops": float(np.mean([x["flops"] for x in fst])) / fdt / 1e12,
@@ -221,6 +224,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": _describe(w), "name": w.name, "N": w.n, "tile": w.m, "eps": w.eps,
                    "eps_mode": "absolute" if w.eps_mode == 0 else "relative", "bs": w.bs,
+                   "bs_tail": a.bs_tail or w.bs,
                    "precision": "fp64"},
         "time_to_solution_s": dt,
         "tflops_paper_count": flops_paper / dt / 1e12,

@@ -103,6 +103,10 @@ typedef struct {
                               a block stay below tau after orthogonalisation (>= 1) */
   unsigned long long seed; /* seed of the Philox4x32-10 test-matrix stream */
   int flags;               /* TLR_FLAG_* bits */
+  int bs_tail;             /* samples per ARA iteration after the first one of a
+                              column (0: bs); one of the bs values.  A larger
+                              value finishes the few high-rank tiles that keep
+                              a column's ARA going in fewer iterations */
 } tlr_opts;
 
 /* opts.flags: record HIP events around every launch of the Schur-complement

@@ -34,6 +34,7 @@ void tlr_opts_default(tlr_opts* o) {
   o->r_min = 1;
   o->seed = 0x5eedULL;
   o->flags = 0;
+  o->bs_tail = 0;
 }
 
 const char* tlr_last_error(void) { return tlr::last_error(); }
@@ -51,6 +52,8 @@ static tlr_status check_opts(const tlr_opts* in, tlr_opts* out) {
   TLR_ARG(out->precision == TLR_FP64 || out->precision == TLR_MIXED_FP32,
           "opts.precision must be TLR_FP64 or TLR_MIXED_FP32");
   TLR_ARG(out->r_min >= 1 && out->r_min <= out->bs, "opts.r_min must be in 1..bs");
+  TLR_ARG(out->bs_tail == 0 || (orth_block_supported(out->bs_tail) && out->r_min <= out->bs_tail),
+          "opts.bs_tail must be 0 or a supported block size >= r_min, got %d", out->bs_tail);
   TLR_ARG(std::isfinite(out->shift), "opts.shift must be finite");
   return TLR_OK;
 }

@@ -154,6 +154,10 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
     if (g < NG && b < nc && x < nc) {
       const int lo = min(x, b), hi = max(x, b);
       const double* pp = part + (size_t)(lo + hi * BS) * 2;
+      // compensated summation (Sum2 of Ogita, Rump and Oishi): the running
+      // sum is the only dependency chain, the rounding errors and the low
+      // parts are gathered beside it
+      double sh = 0.0, sc = 0.0;
       for (int rb0 = 0; rb0 < nrb; rb0 += PCH) {
         double ph[PCH], pl[PCH];
 #pragma unroll
@@ -165,8 +169,13 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < PCH; ++u)
-          if (rb0 + u < nrb) acc = dd_add(acc, dd{ph[u], pl[u]});
+          if (rb0 + u < nrb) {
+            const dd t = two_sum(sh, ph[u]);
+            sh = t.hi;
+            sc += t.lo + pl[u];
+          }
       }
+      acc = fast_two_sum(sh, sc);
     }
     gv[i] = acc;
     if (g < NG && b < BS) ((dd (*)[BS + 1])smem)[x][b] = acc;
@@ -183,13 +192,18 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
     for (int j = 0; j < BS && j < room; ++j) {
       dd (*Gr)[BS + 1] = (dd (*)[BS + 1])(smem + 2 * GSZ * (j & 1));
       dd (*Gw)[BS + 1] = (dd (*)[BS + 1])(smem + 2 * GSZ * ((j & 1) ^ 1));
-      // pivot: largest remaining diagonal, ties to the lowest column
+      // pivot: largest remaining diagonal, ties to the lowest column (the
+      // diagonal is read in one batch of LDS loads before the scan)
+      double dg[BS];
+#pragma unroll
+      for (int c = 0; c < BS; ++c) dg[c] = Gr[c][c].hi;
+      __builtin_amdgcn_sched_barrier(0);
       double vmax = -1.0;
       int pv = BS;
+#pragma unroll
       for (int c = 0; c < BS; ++c) {
-        const double v = Gr[c][c].hi;
-        if (!((taken >> c) & 1u) && v > vmax) {
-          vmax = v;
+        if (!((taken >> c) & 1u) && dg[c] > vmax) {
+          vmax = dg[c];
           pv = c;
         }
       }
@@ -283,9 +297,12 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
   const int r = blockIdx.x * APPLY_ROWS + t;
   if (np == 0) return;
   double* dst = d.q + (size_t)qold * m;
-  double xv[BS];
+  double xv[BS], rd[BS];
 #pragma unroll
-  for (int a = 0; a < BS; ++a) xv[a] = 0.0;
+  for (int a = 0; a < BS; ++a) {
+    xv[a] = 0.0;
+    rd[a] = (a < np) ? 1.0 / Rs[a][a] : 0.0;   // off the substitution's dependency chain
+  }
   if (r < m) {
 #pragma unroll
     for (int a = 0; a < BS; ++a)
@@ -296,7 +313,7 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
         double v = xv[c];
 #pragma unroll
         for (int a = 0; a < c; ++a) v = fma(-xv[a], Rs[a][c], v);
-        v = v / Rs[c][c];
+        v *= rd[c];
         xv[c] = v;
         dst[r + (size_t)c * m] = v;
       }

@@ -9,7 +9,7 @@ static size_t al(size_t n) { return (n + 63) & ~(size_t)63; }
 
 tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   Work& w = h->ws;
-  const int m = c.m, bs = c.bs;
+  const int m = c.m, bs = c.bs_max();
   const int nstrip = (m + 15) / 16;
   s->n = n;
   s->m = m;
@@ -53,7 +53,7 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
 }
 
 tlr_status ara_omega(Handle* h, const AraConfig& c, double** omega) {
-  TLR_TRY(h->ws.omega.ensure(h->mem, sizeof(double) * (size_t)c.m * c.bs));
+  TLR_TRY(h->ws.omega.ensure(h->mem, sizeof(double) * (size_t)c.m * c.bs_max()));
   *omega = h->ws.omega.as<double>();
   return TLR_OK;
 }
@@ -62,10 +62,11 @@ tlr_status ara_explicit_spec(Handle* h, const AraConfig& c, int n, const double*
                              AraSpec* spec) {
   double* omega = nullptr;
   TLR_TRY(ara_omega(h, c, &omega));
-  const int m = c.m, bs = c.bs;
+  const int m = c.m;
   spec->slots.assign(n, AraSlotDesc{});
-  spec->samp_flops.assign(n, 2.0 * m * (double)m * bs);
-  spec->samp_bytes.assign(n, 8.0 * ((double)m * m + 2.0 * m * bs));
+  spec->samp_flops_col.assign(n, 2.0 * m * (double)m);
+  spec->samp_bytes.assign(n, 8.0 * (double)m * m);
+  spec->samp_bytes_col.assign(n, 16.0 * m);
   for (int t = 0; t < n; ++t) {
     AraSlotDesc& d = spec->slots[t];
     d.a0 = tiles + (size_t)t * ld * m;
@@ -96,7 +97,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
                    AraSpec& spec, AraResult* res, bool* info_abort,
                    const std::function<tlr_status()>& idle) {
   const int n = (int)order.size();
-  const int m = c.m, bs = c.bs;
+  const int m = c.m, bs = c.bs_max();
   const int s_max = c.s_max > 0 ? std::min(c.s_max, n) : n;
   res->q.assign(n, 0);
   res->iters.assign(n, 0);
@@ -195,9 +196,10 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   // enqueue iteration j with launch bounds derived from `known`: the active
   // count can only grow by refills, a basis by at most bs per iteration
   auto enqueue = [&](int j) -> tlr_status {
+    D.bs = c.bs_at(j);
     const int cb = (known.cursor >= nwait) ? known.count : s_max;
     const int qb = std::min(c.qcap, known.qmax + bs * (j - known.iter - 1));
-    TLR_HIP(launch_randn(omega, m, bs, m, c.seed, c.stream_id, (unsigned)j, 0, st));
+    TLR_HIP(launch_randn(omega, m, D.bs, m, c.seed, c.stream_id, (unsigned)j, 0, st));
     if (p_blocks > 0 || bps_wa > 0)
       TLR_HIP(launch_ara_tn(D, 0, omega, spec.uk, spec.rk, spec.p, p_blocks, cb, bps_wa, tn_scratch,
                             st));
@@ -272,13 +274,16 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     res->q[sl] = bq[sl];
     res->iters[sl] = bit[sl];
     const double it = bit[sl], qs = bqs[sl];
+    // samples drawn: bs in the first iteration, bs_tail in the others
+    const double cols = it > 0 ? c.bs + (it - 1) * c.bs_at(1) : 0.0;
+    const double b2 = it > 0 ? (double)c.bs * c.bs + (it - 1) * (double)c.bs_at(1) * c.bs_at(1) : 0.0;
     // two Gram-Schmidt passes, each a projection and an update, plus the
     // Gram matrices and the triangular solves of the Cholesky QR steps
-    const double orth = 8.0 * m * bs * qs + 6.0 * m * (double)bs * bs * it;
+    const double orth = 8.0 * m * (cols / std::max(it, 1.0)) * qs + 6.0 * m * b2;
     res->flops_paper_orth[sl] = orth;
-    res->flops += orth + it * spec.samp_flops[sl];
-    res->samp_bytes += it * spec.samp_bytes[sl];
-    res->samp_flops += it * spec.samp_flops[sl];
+    res->flops += orth + cols * spec.samp_flops_col[sl];
+    res->samp_bytes += it * spec.samp_bytes[sl] + cols * spec.samp_bytes_col[sl];
+    res->samp_flops += cols * spec.samp_flops_col[sl];
   }
   return TLR_OK;
 }

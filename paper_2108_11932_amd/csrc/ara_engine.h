@@ -26,13 +26,16 @@ namespace tlr {
 
 struct AraConfig {
   int m = 0;          // rows of every operator
-  int bs = 16;        // samples per iteration
+  int bs = 16;        // samples per iteration (the first iteration)
+  int bs_tail = 0;    // samples per iteration after the first (0: bs)
   int qcap = 0;       // basis capacity (columns)
   double tau = 0.0;   // absolute 2-norm threshold
   int r_min = 1;
   int s_max = 0;      // active subset size (<= 0: all)
   unsigned long long seed = 0;
   unsigned stream_id = 0;   // Philox counter word 2 (column index or batch id)
+  int bs_at(int iter) const { return (iter == 0 || bs_tail <= 0) ? bs : bs_tail; }
+  int bs_max() const { return bs_tail > bs ? bs_tail : bs; }
 };
 
 // Per-slot workspace of an ARA batch (views into the handle's workspace).
@@ -72,7 +75,9 @@ struct AraSpec {
   double* p = nullptr;
   int a_max = 0;                // largest W^A height over the slots
   int r_max = 0;                // largest Z height over the slots
-  std::vector<double> samp_bytes, samp_flops;   // per slot, per iteration
+  // sampling cost per slot: bytes per iteration = samp_bytes + samp_bytes_col
+  // * (samples of the iteration); flops = samp_flops_col * samples
+  std::vector<double> samp_bytes, samp_bytes_col, samp_flops_col;
   // when set, HIP events are recorded around every sampling launch
   std::vector<std::pair<hipEvent_t, hipEvent_t>>* events = nullptr;
 };

@@ -74,6 +74,7 @@ tlr_status compress(Handle* h, const double* A, long long lda, const double* pts
   AraConfig cfg;
   cfg.m = m;
   cfg.bs = bs;
+  cfg.bs_tail = o.bs_tail;
   cfg.qcap = m;
   cfg.tau = eps;
   cfg.r_min = o.r_min;

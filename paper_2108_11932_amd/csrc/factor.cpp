@@ -161,6 +161,7 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
   AraConfig cfg;
   cfg.m = m;
   cfg.bs = bs;
+  cfg.bs_tail = o.bs_tail;
   cfg.qcap = m;
   cfg.tau = tau;
   cfg.r_min = o.r_min;
@@ -297,12 +298,13 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
       }
 
     // ---------------------------------------------- cholARAUpdate
-    TLR_TRY(w.P.ensure(h->mem, sizeof(double) * (size_t)std::max(Rk, 1) * bs));
-    TLR_TRY(w.Wa.ensure(h->mem, sizeof(double) * (size_t)nrow * m * bs));
+    const int bsm = cfg.bs_max();
+    TLR_TRY(w.P.ensure(h->mem, sizeof(double) * (size_t)std::max(Rk, 1) * bsm));
+    TLR_TRY(w.Wa.ensure(h->mem, sizeof(double) * (size_t)nrow * m * bsm));
     {
       long long zt = 0;
       for (int s = 0; s < nrow; ++s) zt += h->R[k + 1 + s];
-      TLR_TRY(w.Z.ensure(h->mem, sizeof(double) * (size_t)std::max(zt, 1LL) * bs));
+      TLR_TRY(w.Z.ensure(h->mem, sizeof(double) * (size_t)std::max(zt, 1LL) * bsm));
     }
     double* P = w.P.as<double>();
     double* Wa = w.Wa.as<double>();
@@ -313,7 +315,8 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
     AraSpec spec;
     spec.slots.assign(nrow, AraSlotDesc{});
     spec.samp_bytes.assign(nrow, 0.0);
-    spec.samp_flops.assign(nrow, 0.0);
+    spec.samp_bytes_col.assign(nrow, 0.0);
+    spec.samp_flops_col.assign(nrow, 0.0);
     spec.uk = h->UL[k];
     spec.rk = Rk;
     spec.p = P;
@@ -324,7 +327,7 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
         const int i = k + 1 + s;
         const int a = h->ar(i, k), Ri = h->R[i];
         AraSlotDesc& d = spec.slots[s];
-        double* wa_s = Wa + (size_t)s * m * bs;
+        double* wa_s = Wa + (size_t)s * m * bsm;
         d.a0 = h->ua(i, k);
         d.lda0 = m;
         d.k0 = a;
@@ -338,7 +341,7 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
         d.ldb1 = 1;
         if (Rk > 0 && Ri > 0) {
           double* zs = Z + zo;
-          zo += (long long)Ri * bs;
+          zo += (long long)Ri * bsm;
           d.a1 = use32[s] ? (const void*)h->UL32[i] : (const void*)h->UL[i];
           d.a1_f32 = use32[s];
           d.k1 = Ri;
@@ -357,9 +360,9 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
           spec.r_max = std::max(spec.r_max, Ri);
         }
         const double kk = (double)a + d.k1;
-        spec.samp_flops[s] = 2.0 * m * bs * kk;
-        spec.samp_bytes[s] = 8.0 * ((double)m * a + kk * bs + (double)m * bs) +
-                             (d.a1_f32 ? 4.0 : 8.0) * m * d.k1;
+        spec.samp_flops_col[s] = 2.0 * m * kk;
+        spec.samp_bytes[s] = 8.0 * m * a + (d.a1_f32 ? 4.0 : 8.0) * m * d.k1;
+        spec.samp_bytes_col[s] = 8.0 * (kk + m);
       }
     }
     // slots hold rows k+1.. in natural order; `order` is the sorted order
@@ -371,12 +374,13 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
     }));
     TLR_TRY(side_done());
     // W^A, Z and P products of the iterations
-    flops += 2.0 * Rk * m * bs * (double)res.launches;
+    flops += 2.0 * Rk * m * (cfg.bs + (res.launches - 1.0) * cfg.bs_at(1));
     for (int s = 0; s < nrow; ++s) {
       const int i = k + 1 + s;
       double zf = 0.0;
       for (int j = 0; j < k; ++j) zf += (double)h->lr(i, j) * h->lr(k, j);
-      flops += res.iters[s] * 2.0 * bs * ((double)h->ar(i, k) * m + zf);
+      const double cols = res.iters[s] > 0 ? cfg.bs + (res.iters[s] - 1.0) * cfg.bs_at(1) : 0.0;
+      flops += cols * 2.0 * ((double)h->ar(i, k) * m + zf);
       if (use32[s]) fp32_tile_iters += res.iters[s];
     }
     samp_bytes += res.samp_bytes;
@@ -508,7 +512,8 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
       // Eq. (2) per iteration, the same for the projection, orthogonalisation,
       // triangular solve)
       const double ext = (double)h->R[i] - q[s] + Rk + h->ar(i, k);
-      flops_paper += res.iters[s] * 4.0 * m * bs * ext + 4.0 * m * q[s] * ext +
+      const double cols = res.iters[s] > 0 ? cfg.bs + (res.iters[s] - 1.0) * cfg.bs_at(1) : 0.0;
+      flops_paper += cols * 4.0 * m * ext + 4.0 * m * q[s] * ext +
                      res.flops_paper_orth[s] + (double)m * m * q[s];
       bytes_alg += res.iters[s] * 8.0 * m * ((double)h->R[i] - q[s] + h->ar(i, k));
       tile_iters += res.iters[s];

@@ -110,6 +110,24 @@ def test_cholesky_matches_oracle_invariants(n, m, eps):
             assert rg[i, k] >= int(np.sum(sv > e * (1 + 1e-8) + 1e-14 * scale))
 
 
+@pytest.mark.parametrize("bs,bs_tail", [(16, 32), (8, 24)])
+def test_larger_tail_block_keeps_accuracy(bs, bs_tail):
+    # later ARA iterations of a column drawing more samples: same bounds
+    pts, a = _cov(2048, 19)
+    eps = 1e-6
+    t = otlr.compress_dense(a, 256, eps)
+    mat = _upload(t)
+    st = mat.potrf(eps, tlr.opts(bs=bs, bs_tail=bs_tail))
+    l = oracle_tlr(mat, tlr.FACTOR)
+    res = _residual_tiles(t, l)
+    for k in range(t.nb):
+        for i in range(k + 1, t.nb):
+            assert np.linalg.norm(res[t.blk(i), t.blk(k)], 2) <= 4 * eps
+    assert np.linalg.norm(res, 2) <= 2 * math.sqrt(t.nb) * eps
+    ref = otlr.tlr_cholesky(t, eps)
+    assert mat.ranks(tlr.FACTOR).sum() <= 1.10 * ref.ranks().sum() + t.nb
+
+
 def test_dynamic_batching_subset_gives_same_quality():
     pts, a = _cov(2048, 5)
     eps = 1e-6
