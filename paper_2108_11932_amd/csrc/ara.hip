@@ -71,6 +71,23 @@ __global__ void k_philox_raw(unsigned* out, int n, unsigned k0, unsigned k1, uns
   out[4 * c + 3] = w.w;
 }
 
+// Value of a double in lane `lane` (wave-uniform) of the wave.
+__device__ inline double lane_value(double v, int lane) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Largest unsigned key over each row of 16 lanes (rotations within the row).
+__device__ inline unsigned row_max16(unsigned k) {
+  k = max(k, (unsigned)__builtin_amdgcn_update_dpp(0, (int)k, 0x128, 0xf, 0xf, false));  // row_ror:8
+  k = max(k, (unsigned)__builtin_amdgcn_update_dpp(0, (int)k, 0x124, 0xf, 0xf, false));  // row_ror:4
+  k = max(k, (unsigned)__builtin_amdgcn_update_dpp(0, (int)k, 0x122, 0xf, 0xf, false));  // row_ror:2
+  k = max(k, (unsigned)__builtin_amdgcn_update_dpp(0, (int)k, 0x121, 0xf, 0xf, false));  // row_ror:1
+  return k;
+}
+
 // Gram partials of a block of rows, one 16-row strip at a time: X (ld ldx)
 // holds rows [0, 16 nstrips) of the block in LDS, part receives, for strip
 // s, the Dot2 sums of X(16 s : 16 s + 16, a) . X(.., b) for a <= b < nc as
@@ -112,10 +129,12 @@ __device__ inline void strip_grams(const double* X, int ldx, int nstrips, int nc
 // the columns are replaced in place.
 //
 // The dd Gram is spread over the workgroup: thread t = x + BS g holds row x,
-// columns g CPG .. g CPG + CPG - 1, in registers, and mirrors them to LDS,
-// from which every thread reads the pivot column at each step (one LDS
-// exchange and two barriers per step; symmetry is exact because the
-// partial sums are shared and the dd product is commutative).
+// columns g CPG .. g CPG + CPG - 1, in registers, and mirrors them to one
+// of two LDS copies (read one, write the other: one barrier per step).  At
+// each step every wave finds the pivot on its own (a lane per column and a
+// reduction across lanes) and every thread reads the pivot row from LDS;
+// symmetry is exact because the partial sums are shared and the dd product
+// is commutative.
 constexpr int APPLY_ROWS = 256;
 
 template <int BS, bool PIV>
@@ -128,7 +147,8 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
   // two dd copies of the Gram (read one, write the other: one barrier per
   // step), reused for the X staging once the factor is done
   __shared__ double smem[SMEM];
-  __shared__ double Lm[BS][BS + 1];   // Lm[j][b]: multiplier of column b at step j
+  __shared__ double Lm[BS][BS + 1];   // Lm[j][b]: Schur-complement row of the pivot of step j
+  __shared__ double dpiv[BS];         // its diagonal (pass 1)
   __shared__ double Rs[BS][BS + 1];   // R(a, c), a <= c
   __shared__ int perm[BS];
   // copy s of the Gram: (dd (*)[BS + 1])(smem + 2 * GSZ * s)
@@ -139,13 +159,13 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
   const int m = D.m, qcap = D.qcap, nrb = D.nstrip;
   const int qold = D.q[slot];
   const double* part = PIV ? d.part1 : d.part2;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63;
   const int x = t % BS, g = t / BS;
   const int nc = PIV ? BS : d.piv[BS];
   if (nc == 0) return;
   // ---- sum of the partial Gram matrices (stored for a <= b)
   // (loads in chunks of PCH partials, all in flight before the sums)
-  constexpr int PCH = 16;
+  constexpr int PCH = 32;
   dd gv[CPG];
 #pragma unroll
   for (int i = 0; i < CPG; ++i) {
@@ -192,39 +212,52 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
     for (int j = 0; j < BS && j < room; ++j) {
       dd (*Gr)[BS + 1] = (dd (*)[BS + 1])(smem + 2 * GSZ * (j & 1));
       dd (*Gw)[BS + 1] = (dd (*)[BS + 1])(smem + 2 * GSZ * ((j & 1) ^ 1));
-      // pivot: largest remaining diagonal, ties to the lowest column (the
-      // diagonal is read in one batch of LDS loads before the scan)
-      double dg[BS];
-#pragma unroll
-      for (int c = 0; c < BS; ++c) dg[c] = Gr[c][c].hi;
-      __builtin_amdgcn_sched_barrier(0);
-      double vmax = -1.0;
-      int pv = BS;
-#pragma unroll
-      for (int c = 0; c < BS; ++c) {
-        if (!((taken >> c) & 1u) && dg[c] > vmax) {
-          vmax = dg[c];
-          pv = c;
-        }
+      // pivot.  Lane c of a row of 16 lanes (lane c of the first two rows
+      // when BS > 16) holds column c's key: the upper word of its remaining
+      // diagonal (positive, so the bits order like the values) with the
+      // low five bits replaced by 31 - c; taken columns and non-positive
+      // diagonals have key 0.  The largest key names a column whose
+      // diagonal is within a relative 2^-15 of the largest, ties to the
+      // lowest column.  Every lane forms the reciprocal of its diagonal
+      // beside the reduction; the pivot's comes from the pivot's lane.
+      const int cl = (BS > 16) ? (lane & 31) : (lane & 15);
+      dd dc{1.0, 0.0};
+      unsigned key = 0u;
+      if (cl < BS) {
+        dc = Gr[cl][cl];
+        if (!((taken >> cl) & 1u) && dc.hi > 0.0)
+          key = ((unsigned)((unsigned long long)__double_as_longlong(dc.hi) >> 32) & ~31u) |
+                (31u - (unsigned)cl);
       }
-      if (!(vmax > tau2)) break;
-      const dd rinv = dd_rsqrt(Gr[pv][pv]);
-      const dd lx = ((taken >> x) & 1u) ? dd{0.0, 0.0} : dd_mul(Gr[x][pv], rinv);
-      dd lb[CPG];
-#pragma unroll
-      for (int i = 0; i < CPG; ++i) {
-        const int b = g * CPG + i;
-        lb[i] = (b < BS && !((taken >> b) & 1u)) ? dd_mul(Gr[pv][b], rinv) : dd{0.0, 0.0};
-      }
+      dd ic = dd_recip(dc);
+      key = row_max16(key);
+      unsigned kmax = __builtin_amdgcn_readlane(key, 0);
+      if (BS > 16) kmax = max(kmax, (unsigned)__builtin_amdgcn_readlane(key, 16));
+      // keep the reciprocal ahead of the exit test (the compiler would sink
+      // it past the branch, onto the dependency chain of the update)
+      asm volatile("" : "+v"(ic.hi), "+v"(ic.lo));
+      if (kmax == 0u) break;
+      const int pv = 31 - (int)(kmax & 31u);
+      const dd dpp{lane_value(dc.hi, pv), lane_value(dc.lo, pv)};
+      if (!(dpp.hi > tau2)) break;
+      const dd invd{lane_value(ic.hi, pv), lane_value(ic.lo, pv)};
+      // Schur update G(x, b) -= G(x, pv) G(pv, b) / d, d = G(pv, pv).  The
+      // row of R is G(pv, b) / sqrt(d); its unscaled values and d are kept
+      // and scaled after the loop, off the dependency chain.
+      const dd gx = ((taken >> x) & 1u) ? dd{0.0, 0.0} : Gr[x][pv];
 #pragma unroll
       for (int i = 0; i < CPG; ++i) {
         const int b = g * CPG + i;
         if (g < NG && b < BS) {
-          gv[i] = dd_sub(gv[i], dd_mul(lx, lb[i]));
+          const bool tb = (taken >> b) & 1u;
+          const dd gpb = tb ? dd{0.0, 0.0} : Gr[pv][b];
+          const dd pr = dd_mul(gx, gpb);
+          gv[i] = dd_sub_sloppy(gv[i], dd_mul(pr, invd));
           Gw[x][b] = gv[i];
-          if (x == 0) Lm[j][b] = lb[i].hi + lb[i].lo;
+          if (x == 0) Lm[j][b] = gpb.hi + gpb.lo;
         }
       }
+      if (t == 0) dpiv[j] = dpp.hi + dpp.lo;
       if (t == 0) perm[j] = pv;
       taken |= 1u << pv;
       np = j + 1;
@@ -236,10 +269,10 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
         if (!((taken >> c) & 1u)) perm[nxt++] = c;
     }
     __syncthreads();
-    // R in pivot order: R(jj, i) = Lm[jj][perm[i]] for i >= jj
+    // R in pivot order: R(jj, i) = Lm[jj][perm[i]] / sqrt(d_jj) for i >= jj
     for (int e = t; e < BS * BS; e += APPLY_ROWS) {
       const int jj = e % BS, i = e / BS;
-      if (jj < np && i < np && i >= jj) Rs[jj][i] = Lm[jj][perm[i]];
+      if (jj < np && i < np && i >= jj) Rs[jj][i] = Lm[jj][perm[i]] / sqrt(dpiv[jj]);
     }
     if (blockIdx.x == 0) {
       if (t < BS) d.piv[t] = perm[t];

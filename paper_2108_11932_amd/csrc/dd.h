@@ -77,6 +77,25 @@ __device__ inline dd dd_rsqrt(dd a) {
   return fast_two_sum(y0, y0 * (e.hi * 0.5));
 }
 
+// 1 / a to double-double accuracy: y0 = 1 / a.hi and one Newton step, the
+// residual 1 - a y0 formed with an FMA (exact for the high part).
+__device__ inline dd dd_recip(dd a) {
+#pragma clang fp contract(off)
+  const double y0 = 1.0 / a.hi;
+  const double r = fma(-a.hi, y0, 1.0) - a.lo * y0;
+  return fast_two_sum(y0, y0 * r);
+}
+
+// a - b with the error bounded by about u^2 (|a| + |b|) (Dekker's add
+// without the second error-free transformation of the low parts): enough
+// where absolute accuracy against the operands is what counts.
+__device__ inline dd dd_sub_sloppy(dd a, dd b) {
+#pragma clang fp contract(off)
+  dd s = two_sum(a.hi, -b.hi);
+  s.lo += a.lo - b.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+
 // One step of the compensated dot product of Ogita, Rump and Oishi (Dot2):
 // (s, c) accumulates x * y.
 __device__ inline void dot2_step(double x, double y, double& s, double& c) {
