@@ -5,11 +5,12 @@
 // The diagonal tile factorization is the "chol" (Algorithm "Left Looking TLR
 // Cholesky") and "ldl" (Algorithm "Left Looking TLR LDL^T", unpivoted with
 // scalar pivots) step of the paper.  The tile is factored by blocks of 32
-// columns: one wave factors the 32 x 32 diagonal block in registers and also
-// writes its inverse; the panel below (L21 = A21 L11^{-T}) and the trailing
-// update then run as MFMA GEMMs.  The block inverses are reused to assemble
-// L_kk^{-1}, so the batched triangular solve of a column ("batchTrsm", one
-// triangle shared by every tile) becomes one product.
+// columns: one launch per block factors the 32 x 32 diagonal block and
+// solves the panel below it (L21 = A21 L11^{-T}), the trailing update runs
+// as an MFMA GEMM.  The diagonal-block inverses, taken afterwards for all
+// blocks in one launch, seed the assembly of L_kk^{-1}, so the batched
+// triangular solve of a column ("batchTrsm", one triangle shared by every
+// tile) becomes one product.
 #include "tlr_internal.h"
 
 namespace tlr {
@@ -27,69 +28,144 @@ __device__ __forceinline__ double lane_bcast(double v, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Factor the diagonal block (p0, p0) of A (w <= 32) in place: Cholesky, or
-// unit LDL^T with the pivots in dvec[p0..]; write the inverse of the lower
-// factor into Inv (ld ldi).
+// Panel step of the blocked right-looking factorization.  Every workgroup
+// (one wave) factors the w x w (w <= 32) diagonal block at (p0, p0) of A on
+// its own -- Cholesky, or unit LDL^T with scalar pivots -- and then solves
+// for its 64 rows of the panel below: Cholesky L21 = A21 L11^{-T} in place;
+// LDL^T W21 = A21 L11^{-T} into W (row p0 + w + i at W[i], ld ldw) and
+// L21 = W21 D^{-1} in place.  The factorization is deterministic, so every
+// workgroup reaches the same L11; workgroup 0 stores the pivots, the
+// failure record and L11 itself -- not into A, whose diagonal block the
+// other workgroups may still be reading, but into Lst (ld ldst, zeros above
+// the diagonal), from where the diagonal-block inversion moves it into A.
 //
-// One wave; lane r holds row r of the block in registers (rows and columns
-// beyond w are the identity, which leaves the real part unchanged; lanes
-// 32..63 carry copies and store nothing).  Both loops are unrolled, so every
-// register index is a constant and every cross-lane value is a readlane into
-// scalar registers: no LDS round trip sits on the dependency chain.
-// Right-looking: step j takes d = a_jj from lane j, each lane its own a_rj,
-// and subtracts (a_rj / d) a_cj from a_rc, a_cj read from lane c.  The
-// inverse X = L^{-1} is a forward substitution with row i of X on lane i:
-// lane p finishes row p, whose entries are then read from lane p.
+// Factor: lanes r and r + 32 hold the two halves of row r of the block in
+// registers (rows and columns beyond w are the identity, which leaves the
+// real part unchanged).  Right-looking: at step j the lanes holding column
+// j put it into LDS, and by symmetry that column is also row j, so each
+// lane reads d = S(j, j), its own S(r, j) and the S(c, j) of its half as
+// LDS broadcasts and subtracts S(r, j) S(c, j) / d from S(r, c); column j
+// of the factor goes to LDS at once.  Two column buffers alternate, one
+// barrier per step.  Solve: thread i takes row p0 + w + 64 b
+// + i of A21 and runs the forward substitution against L11 (LDS) along it.
 template <bool CHOL>
-__global__ __launch_bounds__(64) void k_diag_block(double* A, int lda, int p0, int w, double* Inv,
-                                                   int ldi, double* dvec, int* info, int row_base,
+__global__ __launch_bounds__(64) void k_chol_panel(double* A, int lda, int m, int p0, int w,
+                                                   double* W, int ldw, double* Lst, int ldst,
+                                                   double* dvec, int* info, int row_base,
                                                    const double* tolp) {
-  const int r = threadIdx.x & (ND - 1);
-  const bool act = threadIdx.x < ND;
-  double row[ND];
+  __shared__ double colb[2][ND];
+  __shared__ double Ls[ND][ND + 1];   // Ls[r][q] = L(r, q), q <= r
+  __shared__ double Rd[ND];           // 1 / L(c, c) (Cholesky)
+  __shared__ double Ds[ND];           // LDL^T pivots
+  const int lane = threadIdx.x;
+  const int r = lane & (ND - 1);
+  const int hf = lane >> 5;         // this lane holds columns [16 hf, 16 hf + 16) of row r
+  const bool act = lane < ND;
+  constexpr int HC = ND / 2;
+  double row[HC];
 #pragma unroll
-  for (int c = 0; c < ND; ++c) {
+  for (int cc = 0; cc < HC; ++cc) {
+    const int c = HC * hf + cc;
     double v = (r == c) ? 1.0 : 0.0;
     if (r < w && c < w && c <= r) v = A[(p0 + r) + (size_t)(p0 + c) * lda];
-    row[c] = v;
+    row[cc] = v;
   }
   const double tol = CHOL ? 0.0 : *tolp;
   int bad_row = 0;
-  double dpiv = 1.0;   // this lane's pivot d_r
 #pragma unroll
   for (int j = 0; j < ND; ++j) {
-    double d = lane_bcast(row[j], j);
+    double* cb = colb[j & 1];
+    if (hf == j / HC) cb[r] = row[j % HC];
+    __syncthreads();
+    double d = cb[j];
     const bool bad = CHOL ? !(d > 0.0) : !(fabs(d) > tol);
     if (bad) {
       if (j < w && bad_row == 0) bad_row = row_base + p0 + j + 1;
       d = 1.0;
     }
-    const double a = row[j];     // a_rj (unscaled)
-    const double mr = a / d;     // l_rj of the unit factor
+    const double a = cb[r];              // S(r, j)
+    const double mr = a * (1.0 / d);     // l_rj of the unit factor
+    // every column of the half (finished columns and the upper triangle
+    // only collect values that are never read again)
 #pragma unroll
-    for (int c = j + 1; c < ND; ++c) row[c] -= mr * lane_bcast(a, c);
-    if (r == j) dpiv = d;
+    for (int cc = 0; cc < HC; ++cc) row[cc] = fma(-mr, cb[HC * hf + cc], row[cc]);
+    double lv;
     if (CHOL) {
       const double sq = sqrt(d);
-      row[j] = (r == j) ? sq : (r > j ? a / sq : 0.0);
+      lv = (r == j) ? sq : (r > j ? a / sq : 0.0);
+      if (lane == j) Rd[j] = 1.0 / sq;
     } else {
-      row[j] = (r == j) ? 1.0 : (r > j ? mr : 0.0);
+      lv = (r == j) ? 1.0 : (r > j ? mr : 0.0);
+      if (lane == j) Ds[j] = d;
     }
-    __builtin_amdgcn_sched_barrier(0);   // keep the scalar broadcasts of a step together
+    if (act) Ls[r][j] = lv;
   }
-  if (bad_row && threadIdx.x == 0) atomicCAS(info, 0, bad_row);
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (bad_row && lane == 0) atomicCAS(info, 0, bad_row);
 #pragma unroll
-  for (int p = 0; p < ND; ++p)
-    if (act && r < w && p < w) A[(p0 + r) + (size_t)(p0 + p) * lda] = (p <= r) ? row[p] : 0.0;
-  if (!CHOL && act && r < w) dvec[p0 + r] = dpiv;
-  // X = L^{-1}: at step p lane p scales its row by 1 / L(p, p); rows i > p
-  // then lose L(i, p) X(p, :) (X(p, c) = 0 for c > p).
+    for (int q = 0; q < ND; ++q)
+      if (act && r < w && q < w) Lst[r + (size_t)q * ldst] = (q <= r) ? Ls[r][q] : 0.0;
+    if (!CHOL && act && r < w) dvec[p0 + r] = Ds[r];
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 64 + lane;
+  const int gr = p0 + w + i;
+  if (gr >= m) return;
   double x[ND];
 #pragma unroll
-  for (int c = 0; c < ND; ++c) x[c] = (r == c) ? 1.0 : 0.0;
+  for (int c = 0; c < ND; ++c) x[c] = (c < w) ? A[gr + (size_t)(p0 + c) * lda] : 0.0;
+#pragma unroll
+  for (int c = 0; c < ND; ++c) {
+    double v = x[c];
+#pragma unroll
+    for (int q = 0; q < c; ++q) v = fma(-x[q], Ls[c][q], v);
+    x[c] = CHOL ? v * Rd[c] : v;
+    // x[c] is finished here and row c + 1 of L11 is read only afterwards
+    // (the compiler would otherwise read every row first and sink the
+    // arithmetic to the stores, holding ~500 values in registers)
+    asm volatile("" : "+v"(x[c])::"memory");
+  }
+#pragma unroll
+  for (int c = 0; c < ND; ++c) {
+    if (c < w) {
+      if (CHOL) {
+        A[gr + (size_t)(p0 + c) * lda] = x[c];
+      } else {
+        W[i + (size_t)c * ldw] = x[c];
+        A[gr + (size_t)(p0 + c) * lda] = x[c] / Ds[c];
+      }
+    }
+  }
+}
+
+// Diagonal blocks of a factored m x m tile, one wave per block (block b at
+// (32 b, 32 b)): the panel steps left each lower factor L_bb in Inv; it is
+// moved into A (zeros above its diagonal) and replaced in Inv by its
+// inverse (unit diagonal when UNIT).  Lane r holds row r of the block and
+// row r of X = L^{-1}: at step p lane p scales its row of X by 1 / L(p, p),
+// then rows i > p lose L(i, p) X(p, :), with X(p, :) read from lane p.
+template <bool UNIT>
+__global__ __launch_bounds__(64) void k_diag_finish(double* A, int lda, int m, double* Inv,
+                                                    int ldi) {
+  const int p0 = blockIdx.x * ND;
+  const int w = min(ND, m - p0);
+  const int r = threadIdx.x & (ND - 1);
+  const bool act = threadIdx.x < ND;
+  double row[ND], x[ND];
+#pragma unroll
+  for (int c = 0; c < ND; ++c) {
+    double v = (r == c) ? 1.0 : 0.0;
+    if (r < w && c < w && c <= r) v = Inv[(p0 + r) + (size_t)(p0 + c) * ldi];
+    row[c] = (UNIT && r == c) ? 1.0 : v;
+    x[c] = (r == c) ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < ND; ++c)
+    if (act && r < w && c < w) A[(p0 + r) + (size_t)(p0 + c) * lda] = (c <= r) ? row[c] : 0.0;
 #pragma unroll
   for (int p = 0; p < ND; ++p) {
-    if (CHOL) {
+    if (!UNIT) {
       const double inv = 1.0 / row[p];
       if (r == p) {
 #pragma unroll
@@ -103,7 +179,7 @@ __global__ __launch_bounds__(64) void k_diag_block(double* A, int lda, int p0, i
   }
 #pragma unroll
   for (int c = 0; c < ND; ++c)
-    if (act && r < w && c < w) Inv[r + (size_t)c * ldi] = (r >= c) ? x[c] : 0.0;
+    if (act && r < w && c < w) Inv[(p0 + r) + (size_t)(p0 + c) * ldi] = (r >= c) ? x[c] : 0.0;
 }
 
 // out(r, c) = in(r, c) * s[c] or / s[c] (column scaling, LDL^T panels).
@@ -161,16 +237,29 @@ __global__ __launch_bounds__(64) void k_trsm_diag(const double* L, int ldl, doub
 
 int diag_block_size() { return ND; }
 
-hipError_t launch_diag_block(bool chol, double* A, int lda, int p0, int w, double* Inv, int ldi,
-                             double* dvec, int* info, int row_base, const double* tolp,
-                             hipStream_t s) {
-  if (w <= 0 || w > ND) return hipErrorInvalidValue;
+hipError_t launch_chol_panel(bool chol, double* A, int lda, int m, int p0, int w, double* W,
+                             int ldw, double* Lst, int ldst, double* dvec, int* info, int row_base,
+                             const double* tolp, hipStream_t s) {
+  if (w <= 0 || w > ND || p0 < 0 || p0 + w > m || ldst < w) return hipErrorInvalidValue;
+  const int rem = m - p0 - w;
+  const unsigned nwg = (unsigned)(rem > 0 ? (rem + 63) / 64 : 1);
   if (chol)
-    hipLaunchKernelGGL(k_diag_block<true>, dim3(1), dim3(64), 0, s, A, lda, p0, w, Inv, ldi, dvec,
-                       info, row_base, tolp);
+    hipLaunchKernelGGL(k_chol_panel<true>, dim3(nwg), dim3(64), 0, s, A, lda, m, p0, w, W, ldw,
+                       Lst, ldst, dvec, info, row_base, tolp);
   else
-    hipLaunchKernelGGL(k_diag_block<false>, dim3(1), dim3(64), 0, s, A, lda, p0, w, Inv, ldi,
-                       dvec, info, row_base, tolp);
+    hipLaunchKernelGGL(k_chol_panel<false>, dim3(nwg), dim3(64), 0, s, A, lda, m, p0, w, W, ldw,
+                       Lst, ldst, dvec, info, row_base, tolp);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_finish(bool unit, double* A, int lda, int m, double* Inv, int ldi,
+                              hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const unsigned nblk = (unsigned)((m + ND - 1) / ND);
+  if (unit)
+    hipLaunchKernelGGL(k_diag_finish<true>, dim3(nblk), dim3(64), 0, s, A, lda, m, Inv, ldi);
+  else
+    hipLaunchKernelGGL(k_diag_finish<false>, dim3(nblk), dim3(64), 0, s, A, lda, m, Inv, ldi);
   return hipGetLastError();
 }
 

@@ -391,35 +391,23 @@ tlr_status dense_factor(Handle* h, Plan& plan, bool chol, double* A, int lda, in
   const int nd = diag_block_size();
   for (int p0 = 0; p0 < m; p0 += nd) {
     const int wd = m - p0 < nd ? m - p0 : nd;
-    double* inv = Linv + p0 + (size_t)p0 * m;
+    double* lst = Linv + p0 + (size_t)p0 * m;
     plan.launch([=]() {
-      return launch_diag_block(chol, A, lda, p0, wd, inv, m, d, info, row_base, tol, s);
+      return launch_chol_panel(chol, A, lda, m, p0, wd, W, m, lst, m, d, info, row_base, tol, s);
     });
     const int rem = m - p0 - wd;
     if (rem <= 0) continue;
     double* a21 = A + (p0 + wd) + (size_t)p0 * lda;
     double* a22 = A + (p0 + wd) + (size_t)(p0 + wd) * lda;
-    if (chol) {
-      // L21 = A21 L11^{-T}, in place: one column tile (wd <= 32 < 64), every
-      // workgroup reads its own rows before writing them
-      GemmBatch p(false, true);
-      p.add(rem, wd, wd, a21, lda, inv, m, a21, lda, 1.0, 0.0);
-      plan.gemm(p);
-      GemmBatch t(false, true);
+    // trailing update: A22 -= L21 L21^T, or A22 -= W21 L21^T (LDL^T)
+    GemmBatch t(false, true);
+    if (chol)
       t.add(rem, rem, wd, a21, lda, a21, lda, a22, lda, -1.0, 1.0, GEMM_LOWER_C);
-      plan.gemm(t);
-    } else {
-      // W21 = A21 L11^{-T} = L21 D, L21 = W21 D^{-1}, A22 -= W21 L21^T
-      GemmBatch p(false, true);
-      p.add(rem, wd, wd, a21, lda, inv, m, W, m, 1.0, 0.0);
-      plan.gemm(p);
-      const double* dp = d + p0;
-      plan.launch([=]() { return launch_scale_cols(W, m, a21, lda, dp, rem, wd, true, s); });
-      GemmBatch t(false, true);
+    else
       t.add(rem, rem, wd, W, m, a21, lda, a22, lda, -1.0, 1.0, GEMM_LOWER_C);
-      plan.gemm(t);
-    }
+    plan.gemm(t);
   }
+  plan.launch([=]() { return launch_diag_finish(!chol, A, lda, m, Linv, m, s); });
   plan.launch([=]() { return launch_zero_upper(A, lda, m, s); });
   inverse_assemble(plan, A, lda, m, Linv, W);
   return TLR_OK;

@@ -70,13 +70,21 @@ hipError_t launch_sample_nn(const SegDesc* d, const BlockMap* map, int nblocks, 
 // ---------------------------------------------------------------------------
 // Width of the diagonal blocks the factorization kernel handles (32).
 int diag_block_size();
-// Factor the w x w (w <= diag_block_size()) diagonal block at (p0, p0) of A in place
-// (Cholesky, or unit LDL^T with pivots into dvec[p0..]) and write the inverse
-// of its lower factor to Inv (ld ldi).  info (device int) receives the
-// 1-based row (row_base + p0 + j + 1) of the first failing pivot.
-hipError_t launch_diag_block(bool chol, double* A, int lda, int p0, int w, double* Inv, int ldi,
-                             double* dvec, int* info, int row_base, const double* tolp,
-                             hipStream_t s);
+// Panel step of the blocked factorization of the m x m tile A: factor the
+// w x w (w <= diag_block_size()) diagonal block at (p0, p0) (Cholesky, or
+// unit LDL^T with pivots into dvec[p0..]) and solve the panel below it:
+// Cholesky L21 = A21 L11^{-T}; LDL^T W21 = A21 L11^{-T} into W (ld ldw, row
+// p0 + w at W[0]) and L21 = W21 D^{-1}.  L11 goes to Lst (ld ldst), not
+// into A.  info (device int) receives the 1-based row (row_base + p0 + j +
+// 1) of the first failing pivot; tolp is the LDL^T pivot tolerance (device).
+hipError_t launch_chol_panel(bool chol, double* A, int lda, int m, int p0, int w, double* W,
+                             int ldw, double* Lst, int ldst, double* dvec, int* info, int row_base,
+                             const double* tolp, hipStream_t s);
+// After the panel steps, with every diagonal-block factor L_bb left in Inv
+// at (32 b, 32 b): move each into A (zeros above its diagonal) and replace
+// it in Inv by its inverse (unit diagonal when unit).
+hipError_t launch_diag_finish(bool unit, double* A, int lda, int m, double* Inv, int ldi,
+                              hipStream_t s);
 // out(r, c) = in(r, c) * s[c] (or / s[c]).
 hipError_t launch_scale_cols(const double* in, int ldi, double* out, int ldo, const double* sc,
                              int rows, int cols, bool inverse, hipStream_t s);
