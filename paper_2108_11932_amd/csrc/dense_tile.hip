@@ -45,8 +45,7 @@ __device__ __forceinline__ double lane_bcast(double v, int lane) {
 // j put it into LDS, and by symmetry that column is also row j, so each
 // lane reads d = S(j, j), its own S(r, j) and the S(c, j) of its half as
 // LDS broadcasts and subtracts S(r, j) S(c, j) / d from S(r, c); column j
-// of the factor goes to LDS at once.  Two column buffers alternate, one
-// barrier per step.  Solve: thread i takes row p0 + w + 64 b
+// of the factor goes to LDS at once.  Two column buffers alternate.  Solve: thread i takes row p0 + w + 64 b
 // + i of A21 and runs the forward substitution against L11 (LDS) along it.
 template <bool CHOL>
 __global__ __launch_bounds__(64) void k_chol_panel(double* A, int lda, int m, int p0, int w,
@@ -76,24 +75,44 @@ __global__ __launch_bounds__(64) void k_chol_panel(double* A, int lda, int m, in
   for (int j = 0; j < ND; ++j) {
     double* cb = colb[j & 1];
     if (hf == j / HC) cb[r] = row[j % HC];
-    __syncthreads();
+    // the workgroup is one wave, whose LDS operations complete in issue
+    // order: the reads below see the write above without a wait for it
+    __builtin_amdgcn_wave_barrier();
+    // all reads of the step in flight at once
     double d = cb[j];
+    const double a = cb[r];              // S(r, j)
+    double cv[HC];
+#pragma unroll
+    for (int cc = 0; cc < HC; ++cc) cv[cc] = cb[HC * hf + cc];
+    __builtin_amdgcn_sched_barrier(0);
     const bool bad = CHOL ? !(d > 0.0) : !(fabs(d) > tol);
     if (bad) {
       if (j < w && bad_row == 0) bad_row = row_base + p0 + j + 1;
       d = 1.0;
     }
-    const double a = cb[r];              // S(r, j)
-    const double mr = a * (1.0 / d);     // l_rj of the unit factor
+    // 1/sqrt(d) (Cholesky) or 1/d from the hardware estimate and two Newton
+    // steps: a handful of FMAs instead of the division and square-root
+    // sequences on the step's dependency chain
+    double rs = 0.0, rd;
+    if (CHOL) {
+      rs = __builtin_amdgcn_rsq(d);
+#pragma unroll
+      for (int it = 0; it < 2; ++it) rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+      rd = rs * rs;
+    } else {
+      rd = __builtin_amdgcn_rcp(d);
+#pragma unroll
+      for (int it = 0; it < 2; ++it) rd = fma(rd, fma(-d, rd, 1.0), rd);
+    }
+    const double mr = a * rd;            // l_rj of the unit factor
     // every column of the half (finished columns and the upper triangle
     // only collect values that are never read again)
 #pragma unroll
-    for (int cc = 0; cc < HC; ++cc) row[cc] = fma(-mr, cb[HC * hf + cc], row[cc]);
+    for (int cc = 0; cc < HC; ++cc) row[cc] = fma(-mr, cv[cc], row[cc]);
     double lv;
     if (CHOL) {
-      const double sq = sqrt(d);
-      lv = (r == j) ? sq : (r > j ? a / sq : 0.0);
-      if (lane == j) Rd[j] = 1.0 / sq;
+      lv = (r == j) ? d * rs : (r > j ? a * rs : 0.0);
+      if (lane == j) Rd[j] = rs;
     } else {
       lv = (r == j) ? 1.0 : (r > j ? mr : 0.0);
       if (lane == j) Ds[j] = d;
