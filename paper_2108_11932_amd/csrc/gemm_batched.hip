@@ -163,6 +163,24 @@ __global__ __launch_bounds__(512) void k_gemm_tn(const GemmDesc* __restrict__ de
                       col0, red);
 }
 
+// The same product streamed through LDS with coalesced loads (tn_lds_tile):
+// a BM x BN tile per 256-thread workgroup, 64-row chunks.  For batches whose
+// problems meet its alignment requirements (K even, even leading
+// dimensions, 16-byte aligned operands, no flags).
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void k_gemm_tn_lds(const GemmDesc* __restrict__ descs,
+                                                     const BlockMap* __restrict__ map) {
+  constexpr int KC = 64;
+  __shared__ double smem[tn_lds_smem<BM, BN, KC>()];
+  const BlockMap bm = map[blockIdx.x];
+  const GemmDesc d = descs[bm.desc];
+  const int tiles_m = (d.M + BM - 1) / BM;
+  const int row0 = (bm.tile % tiles_m) * BM;
+  const int col0 = (bm.tile / tiles_m) * BN;
+  tn_lds_tile<BM, BN, KC>(d.A, d.lda, d.B, d.ldb, d.C, d.ldc, d.M, d.N, d.K, d.alpha, d.beta, row0,
+                          col0, smem);
+}
+
 template <bool TA, bool TB>
 hipError_t launch_tt(const GemmDesc* d, const BlockMap* map, int nblocks, int bn, hipStream_t s) {
   if (bn == 64)
@@ -184,6 +202,25 @@ void gemm_tile_shape(bool trans_a, bool trans_b, int maxn, int* tm, int* tn) {
     *tm = 64;
     *tn = gemm_tile_n(maxn);
   }
+}
+
+hipError_t launch_gemm_tn_lds(const GemmDesc* d_descs, const BlockMap* d_map, int nblocks, int bm,
+                              int bn, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (bm == 16 && bn == 16)
+    hipLaunchKernelGGL((k_gemm_tn_lds<16, 16>), dim3(nblocks), dim3(256), 0, s, d_descs, d_map);
+  else if (bm == 64 && bn == 16)
+    hipLaunchKernelGGL((k_gemm_tn_lds<64, 16>), dim3(nblocks), dim3(256), 0, s, d_descs, d_map);
+  else if (bm == 64 && bn == 32)
+    hipLaunchKernelGGL((k_gemm_tn_lds<64, 32>), dim3(nblocks), dim3(256), 0, s, d_descs, d_map);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+bool gemm_tn_lds_ok(const GemmDesc& d) {
+  return d.flags == 0 && d.K >= 2 && (d.K & 1) == 0 && (d.lda & 1) == 0 && (d.ldb & 1) == 0 &&
+         ((reinterpret_cast<uintptr_t>(d.A) | reinterpret_cast<uintptr_t>(d.B)) & 15) == 0;
 }
 
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, int nblocks,

@@ -216,4 +216,136 @@ __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, i
   if (ys) __syncthreads();
 }
 
+// C(row0 : row0 + BM, col0 : col0 + BN) = alpha A^T B + beta C with A stored
+// K x M and B stored K x N (column-major, the contraction running down the
+// columns), streamed through LDS in chunks of KC rows.  The loads are
+// coalesced: KC / 2 consecutive threads read one column's KC-row run as
+// 16-byte pairs (whole cache lines per instruction), the next chunk is
+// loaded into registers while the MFMAs consume the current one from LDS,
+// and the four waves split each chunk's 16-row slices; their partial tiles
+// are added in LDS at the end.  Requires K even and >= 2, lda and ldb even,
+// A and B 16-byte aligned.  Columns of A past M and of B past N are read
+// from a clamped in-range column and only reach outputs that are not
+// stored.  256 threads; smem holds tn_lds_smem<BM, BN, KC>() doubles.
+template <int BM, int BN, int KC>
+constexpr int tn_lds_smem() {
+  return ((BM + BN) * (KC + 2) > 3 * (BM / 16) * (BN / 16) * 4 * 64)
+             ? (BM + BN) * (KC + 2)
+             : 3 * (BM / 16) * (BN / 16) * 4 * 64;
+}
+
+template <int BM, int BN, int KC>
+__device__ inline void tn_lds_tile(const double* __restrict__ A, int lda,
+                                   const double* __restrict__ B, int ldb, double* C, int ldc,
+                                   int M, int N, int K, double alpha, double beta, int row0,
+                                   int col0, double* smem) {
+  constexpr int FM = BM / 16, FN = BN / 16, LDK = KC + 2;
+  constexpr int TPC = KC / 2;          // threads per column run (one 16-byte pair each)
+  constexpr int CPR = 256 / TPC;       // columns per load round
+  constexpr int AL = BM / CPR, BL = BN / CPR;
+  static_assert(BM % CPR == 0 && BN % CPR == 0, "tile and chunk do not match the loader");
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  double* As = smem;                   // As[c * LDK + k]
+  double* Bs = smem + BM * LDK;
+  const int lc = t / TPC, lk = (t % TPC) * 2;
+  double2 ra[AL], rb[BL];
+  auto load = [&](int k0) {
+    const int kk = min(k0 + lk, K - 2);
+#pragma unroll
+    for (int u = 0; u < AL; ++u) {
+      const int c = min(row0 + lc + u * CPR, M - 1);
+      ra[u] = *(const double2*)(A + (size_t)c * lda + kk);
+    }
+#pragma unroll
+    for (int u = 0; u < BL; ++u) {
+      const int c = min(col0 + lc + u * CPR, N - 1);
+      rb[u] = *(const double2*)(B + (size_t)c * ldb + kk);
+    }
+  };
+  auto store = [&](int k0) {
+    const bool ok = k0 + lk < K;   // K even: a pair is wholly inside or outside
+#pragma unroll
+    for (int u = 0; u < AL; ++u)
+      *(double2*)(As + (lc + u * CPR) * LDK + lk) = ok ? ra[u] : double2{0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < BL; ++u)
+      *(double2*)(Bs + (lc + u * CPR) * LDK + lk) = ok ? rb[u] : double2{0.0, 0.0};
+  };
+  d4 acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    __syncthreads();   // the previous chunk's LDS reads are done
+    store(k0);
+    __syncthreads();
+    if (k0 + KC < K) load(k0 + KC);
+    // lane (i, g) takes rows kb .. kb + 3 of column i; MFMA tt consumes row
+    // kb + tt on both operands
+#pragma unroll
+    for (int sl = wave; sl < KC / 16; sl += 4) {
+      const int kb = sl * 16 + 4 * g;
+      double av[FM][4], bv[FN][4];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+        const double2 x = *(const double2*)(As + (a * 16 + li) * LDK + kb);
+        const double2 y = *(const double2*)(As + (a * 16 + li) * LDK + kb + 2);
+        av[a][0] = x.x;
+        av[a][1] = x.y;
+        av[a][2] = y.x;
+        av[a][3] = y.y;
+      }
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const double2 x = *(const double2*)(Bs + (b * 16 + li) * LDK + kb);
+        const double2 y = *(const double2*)(Bs + (b * 16 + li) * LDK + kb + 2);
+        bv[b][0] = x.x;
+        bv[b][1] = x.y;
+        bv[b][2] = y.x;
+        bv[b][3] = y.y;
+      }
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a][tt], bv[b][tt], acc[a][b], 0, 0, 0);
+    }
+  }
+  // waves 1..3 park their partial tiles in LDS, wave 0 adds them (fixed order)
+  __syncthreads();
+  if (wave > 0) {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          smem[((wave - 1) * FM * FN * 4 + (a * FN + b) * 4 + r) * 64 + lane] = acc[a][b][r];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double v = acc[a][b][r];
+#pragma unroll
+        for (int w = 0; w < 3; ++w) v += smem[(w * FM * FN * 4 + (a * FN + b) * 4 + r) * 64 + lane];
+        const int gr = row0 + a * 16 + g + 4 * r, gc = col0 + b * 16 + li;
+        if (gr < M && gc < N) {
+          double* cp = C + gr + (size_t)gc * ldc;
+          double out = alpha * v;
+          if (beta != 0.0) out += beta * *cp;
+          *cp = out;
+        }
+      }
+}
+
 }  // namespace tlr

@@ -254,6 +254,32 @@ void Plan::gemm(const GemmBatch& b) {
   const size_t od = stage(b.d.data(), b.d.size() * sizeof(GemmDesc));
   const bool ta = b.ta, tb = b.tb;
   hipStream_t st = s;
+  // transposed-A classes whose problems allow it run on the LDS-staged
+  // kernel (coalesced loads), else on the register-tiled one
+  auto lds_ok = [&](const std::vector<int>& idx) {
+    if (!(ta && !tb)) return false;
+    for (int i : idx)
+      if (!gemm_tn_lds_ok(b.d[i])) return false;
+    return true;
+  };
+  auto push_lds = [&](const std::vector<int>& idx, int bm, int bn) {
+    std::vector<BlockMap> map;
+    build_map(b, idx, bm, bn, &map);
+    const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
+    const int nblk = (int)map.size();
+    steps.push_back([=](const char* base) {
+      return launch_gemm_tn_lds((const GemmDesc*)(base + od), (const BlockMap*)(base + om), nblk, bm,
+                                bn, st);
+    });
+  };
+  if (!small.empty() && lds_ok(small)) {
+    push_lds(small, 16, 16);
+    small.clear();
+  }
+  if (!large.empty() && lds_ok(large)) {
+    push_lds(large, 64, maxn <= 16 ? 16 : 32);
+    large.clear();
+  }
   if (!small.empty()) {
     std::vector<BlockMap> map;
     build_map(b, small, 16, 16, &map);

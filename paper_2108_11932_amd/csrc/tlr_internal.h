@@ -48,6 +48,11 @@ int gemm_tile_n(int N);                     // BN chosen for a problem (16 or 64
 // transpositions and largest N; the block map enumerates tiles of this shape.
 void gemm_tile_shape(bool trans_a, bool trans_b, int maxn, int* tm, int* tn);
 // bn = 0 selects 16 x 16 tiles (transposed A only).
+// Transposed-A batches streamed through LDS: tiles bm x bn in {16 x 16,
+// 64 x 16, 64 x 32}; every problem must pass gemm_tn_lds_ok.
+bool gemm_tn_lds_ok(const GemmDesc& d);
+hipError_t launch_gemm_tn_lds(const GemmDesc* d_descs, const BlockMap* d_map, int nblocks, int bm,
+                              int bn, hipStream_t s);
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, int nblocks,
                                bool trans_a, bool trans_b, int bn, hipStream_t s);
 

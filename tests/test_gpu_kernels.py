@@ -46,6 +46,33 @@ def test_gemm_batched_ragged(ta, tb):
         np.testing.assert_allclose(got, ref, rtol=0, atol=tol)
 
 
+def test_gemm_tn_streamed_ragged():
+    """Transposed-A batches whose problems all have an even K (and so even
+    leading dimensions) run on the LDS-streamed kernel: ragged M, N, K around
+    its 16 / 64-wide tiles and 64-row chunks, N past 32, beta 0 / 1 / -0.5."""
+    rng = np.random.default_rng(77)
+    sizes = [(1, 1, 2), (3, 17, 6), (16, 16, 64), (12, 12, 1024), (65, 15, 4), (130, 70, 34),
+             (64, 33, 130), (200, 16, 300), (16, 64, 2), (1, 300, 2), (400, 16, 1024),
+             (17, 5, 66)]
+    probs, refs, outs = [], [], []
+    for (M, N, K) in sizes:
+        A = rng.standard_normal((K, M))
+        B = rng.standard_normal((K, N))
+        C = rng.standard_normal((M, N))
+        alpha, beta = rng.uniform(-2, 2), [0.0, 1.0, -0.5][len(probs) % 3]
+        ref = alpha * (A.T @ B) + beta * C
+        dA, dB, dC = dev(A), dev(B), dev(C)
+        probs.append(dict(M=M, N=N, K=K, A=dA, lda=K, B=dB, ldb=K, C=dC, ldc=M, alpha=alpha,
+                          beta=beta))
+        refs.append(ref)
+        outs.append((dC, M, N, np.abs(A).max() * np.abs(B).max() * K))
+    tlr.gemm_batched(True, False, probs)
+    for ref, (dC, M, N, scale) in zip(refs, outs):
+        got = host(dC, M, N)
+        tol = 4 * (M + 64) * U64 * (scale + np.abs(ref).max() + 1)
+        np.testing.assert_allclose(got, ref, rtol=0, atol=tol)
+
+
 @pytest.mark.parametrize("m", [1, 7, 64, 65, 200, 256, 513])
 def test_potrf_tile_matches_lapack(m):
     g = _rand((m, m), m)
