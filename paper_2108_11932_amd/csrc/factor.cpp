@@ -437,8 +437,10 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
                0.0);
       }
       if (Rk > 0 && sq > 0) b2.add(m, (int)sq, Rk, h->UL[k], m, H, Rk, Ball, m, -1.0, 1.0);
+      // t1 and t2 stream the same basis blocks Q_i: one batch
+      for (const GemmDesc& d : t2.d) t1.d.push_back(d);
+      t1.flops += t2.flops;
       plan.gemm(t1);
-      plan.gemm(t2);
       plan.gemm(hb);
       plan.gemm(b1);
       plan.gemm(b2);

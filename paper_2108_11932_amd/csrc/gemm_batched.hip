@@ -164,9 +164,9 @@ __global__ __launch_bounds__(512) void k_gemm_tn(const GemmDesc* __restrict__ de
 }
 
 // The same product streamed through LDS with coalesced loads (tn_lds_tile):
-// a BM x BN tile per 256-thread workgroup, 64-row chunks.  For batches whose
-// problems meet its alignment requirements (K even, even leading
-// dimensions, 16-byte aligned operands, no flags).
+// a BM x BN tile per 256-thread workgroup, 64-row chunks.  For problems
+// that meet its alignment requirements (K even, even leading dimensions,
+// 16-byte aligned operands, no flags but GEMM_STORE_T).
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm_tn_lds(const GemmDesc* __restrict__ descs,
                                                      const BlockMap* __restrict__ map) {
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn_lds(const GemmDesc* __restrict_
   const int row0 = (bm.tile % tiles_m) * BM;
   const int col0 = (bm.tile / tiles_m) * BN;
   tn_lds_tile<BM, BN, KC>(d.A, d.lda, d.B, d.ldb, d.C, d.ldc, d.M, d.N, d.K, d.alpha, d.beta, row0,
-                          col0, smem);
+                          col0, (d.flags & GEMM_STORE_T) != 0, smem);
 }
 
 template <bool TA, bool TB>
@@ -219,7 +219,7 @@ hipError_t launch_gemm_tn_lds(const GemmDesc* d_descs, const BlockMap* d_map, in
 }
 
 bool gemm_tn_lds_ok(const GemmDesc& d) {
-  return d.flags == 0 && d.K >= 2 && (d.K & 1) == 0 && (d.lda & 1) == 0 && (d.ldb & 1) == 0 &&
+  return (d.flags & ~GEMM_STORE_T) == 0 && d.K >= 2 && (d.K & 1) == 0 && (d.lda & 1) == 0 && (d.ldb & 1) == 0 &&
          ((reinterpret_cast<uintptr_t>(d.A) | reinterpret_cast<uintptr_t>(d.B)) & 15) == 0;
 }
 

@@ -226,7 +226,8 @@ __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, i
 // are added in LDS at the end.  Requires K even and >= 2, lda and ldb even,
 // A and B 16-byte aligned.  Columns of A past M and of B past N are read
 // from a clamped in-range column and only reach outputs that are not
-// stored.  256 threads; smem holds tn_lds_smem<BM, BN, KC>() doubles.
+// stored.  With store_t the tile goes to C transposed (element (r, c) at
+// C[c + r ldc]).  256 threads; smem holds tn_lds_smem<BM, BN, KC>() doubles.
 template <int BM, int BN, int KC>
 constexpr int tn_lds_smem() {
   return ((BM + BN) * (KC + 2) > 3 * (BM / 16) * (BN / 16) * 4 * 64)
@@ -238,7 +239,7 @@ template <int BM, int BN, int KC>
 __device__ inline void tn_lds_tile(const double* __restrict__ A, int lda,
                                    const double* __restrict__ B, int ldb, double* C, int ldc,
                                    int M, int N, int K, double alpha, double beta, int row0,
-                                   int col0, double* smem) {
+                                   int col0, bool store_t, double* smem) {
   constexpr int FM = BM / 16, FN = BN / 16, LDK = KC + 2;
   constexpr int TPC = KC / 2;          // threads per column run (one 16-byte pair each)
   constexpr int CPR = 256 / TPC;       // columns per load round
@@ -340,7 +341,7 @@ __device__ inline void tn_lds_tile(const double* __restrict__ A, int lda,
         for (int w = 0; w < 3; ++w) v += smem[(w * FM * FN * 4 + (a * FN + b) * 4 + r) * 64 + lane];
         const int gr = row0 + a * 16 + g + 4 * r, gc = col0 + b * 16 + li;
         if (gr < M && gc < N) {
-          double* cp = C + gr + (size_t)gc * ldc;
+          double* cp = store_t ? C + gc + (size_t)gr * ldc : C + gr + (size_t)gc * ldc;
           double out = alpha * v;
           if (beta != 0.0) out += beta * *cp;
           *cp = out;

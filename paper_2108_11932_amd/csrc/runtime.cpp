@@ -228,12 +228,12 @@ void Plan::launch(std::function<hipError_t()> f) {
 }
 
 // Block map of the problems `idx` of a batch with tiles TM x TN.
-static void build_map(const GemmBatch& b, const std::vector<int>& idx, int TM, int TN,
+static void build_map(const std::vector<GemmDesc>& d, const std::vector<int>& idx, int TM, int TN,
                       std::vector<BlockMap>* map) {
   for (int i : idx) {
-    const int tm = (b.d[i].M + TM - 1) / TM, tn = (b.d[i].N + TN - 1) / TN;
+    const int tm = (d[i].M + TM - 1) / TM, tn = (d[i].N + TN - 1) / TN;
     for (int t = 0; t < tm * tn; ++t) {
-      if ((b.d[i].flags & GEMM_LOWER_C) && (t / tm) * TN >= (t % tm) * TM + TM) continue;
+      if ((d[i].flags & GEMM_LOWER_C) && (t / tm) * TN >= (t % tm) * TM + TM) continue;
       map->push_back(BlockMap{i, t});
     }
   }
@@ -241,66 +241,77 @@ static void build_map(const GemmBatch& b, const std::vector<int>& idx, int TM, i
 
 void Plan::gemm(const GemmBatch& b) {
   if (b.d.empty()) return;
-  // TN batches are split into a class of problems that fit one 16 x 16 tile
-  // (most of the per-tile products G_ij, U_ij^T Q_i of the method) and the
-  // rest, so that small problems do not run on large, mostly idle tiles
-  std::vector<int> small, large;
-  int maxn = 0;
-  for (size_t i = 0; i < b.d.size(); ++i) {
-    const bool sm = b.ta && !b.tb && b.d[i].M <= 16 && b.d[i].N <= 16;
-    (sm ? small : large).push_back((int)i);
-    if (!sm) maxn = std::max(maxn, b.d[i].N);
-  }
-  const size_t od = stage(b.d.data(), b.d.size() * sizeof(GemmDesc));
   const bool ta = b.ta, tb = b.tb;
   hipStream_t st = s;
-  // transposed-A classes whose problems allow it run on the LDS-staged
-  // kernel (coalesced loads), else on the register-tiled one
-  auto lds_ok = [&](const std::vector<int>& idx) {
-    if (!(ta && !tb)) return false;
-    for (int i : idx)
-      if (!gemm_tn_lds_ok(b.d[i])) return false;
-    return true;
-  };
-  auto push_lds = [&](const std::vector<int>& idx, int bm, int bn) {
+  // Transposed-A problems that meet the LDS-streamed kernel's requirements
+  // run on it (coalesced loads), oriented so that the operand with more
+  // columns is A (a product with more columns than rows is formed
+  // transposed and stored back transposed); the others run on the
+  // register-tiled kernels.  Each kernel takes classes by tile shape, so
+  // that small problems (most of the per-tile products G_ij, U_ij^T Q_i of
+  // the method) do not run on large, mostly idle tiles.
+  std::vector<GemmDesc> dv = b.d;
+  std::vector<int> l16, l64n, l64w, small, large;
+  long long n64n = 0, n64w = 0;   // workgroups of the narrow / wide classes on large tiles
+  int maxn = 0;
+  for (size_t i = 0; i < dv.size(); ++i) {
+    GemmDesc& d = dv[i];
+    if (ta && !tb && gemm_tn_lds_ok(d)) {
+      if (d.N > d.M && d.N > 16) {
+        std::swap(d.A, d.B);
+        std::swap(d.lda, d.ldb);
+        std::swap(d.M, d.N);
+        d.flags |= GEMM_STORE_T;
+      }
+      if (d.M <= 16 && d.N <= 16) {
+        l16.push_back((int)i);
+      } else if (d.N <= 16) {
+        l64n.push_back((int)i);
+        n64n += (d.M + 63) / 64;
+      } else {
+        l64w.push_back((int)i);
+        n64w += (long long)((d.M + 63) / 64) * ((d.N + 31) / 32);
+      }
+      continue;
+    }
+    const bool sm = ta && !tb && d.M <= 16 && d.N <= 16;
+    (sm ? small : large).push_back((int)i);
+    if (!sm) maxn = std::max(maxn, d.N);
+  }
+  // A class too small to give every CU a large tile runs on 16 x 16 tiles
+  // instead: a workgroup's chunks are sequential, so with few workgroups
+  // the launch takes the latency of one large tile's K loop.
+  constexpr long long kFill = 256;
+  if (n64n < kFill) {
+    l16.insert(l16.end(), l64n.begin(), l64n.end());
+    l64n.clear();
+  }
+  if (n64w < kFill) {
+    l16.insert(l16.end(), l64w.begin(), l64w.end());
+    l64w.clear();
+  }
+  const size_t od = stage(dv.data(), dv.size() * sizeof(GemmDesc));
+  auto push = [&](const std::vector<int>& idx, int tm, int tn, bool lds, int bn) {
+    if (idx.empty()) return;
     std::vector<BlockMap> map;
-    build_map(b, idx, bm, bn, &map);
+    build_map(dv, idx, tm, tn, &map);
     const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
     const int nblk = (int)map.size();
     steps.push_back([=](const char* base) {
-      return launch_gemm_tn_lds((const GemmDesc*)(base + od), (const BlockMap*)(base + om), nblk, bm,
-                                bn, st);
+      const GemmDesc* pd = (const GemmDesc*)(base + od);
+      const BlockMap* pm = (const BlockMap*)(base + om);
+      return lds ? launch_gemm_tn_lds(pd, pm, nblk, tm, tn, st)
+                 : launch_gemm_batched(pd, pm, nblk, ta, tb, bn, st);
     });
   };
-  if (!small.empty() && lds_ok(small)) {
-    push_lds(small, 16, 16);
-    small.clear();
-  }
-  if (!large.empty() && lds_ok(large)) {
-    push_lds(large, 64, maxn <= 16 ? 16 : 32);
-    large.clear();
-  }
-  if (!small.empty()) {
-    std::vector<BlockMap> map;
-    build_map(b, small, 16, 16, &map);
-    const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
-    const int nblk = (int)map.size();
-    steps.push_back([=](const char* base) {
-      return launch_gemm_batched((const GemmDesc*)(base + od), (const BlockMap*)(base + om), nblk,
-                                 ta, tb, 0, st);
-    });
-  }
+  push(l16, 16, 16, true, 0);
+  push(l64n, 64, 16, true, 0);
+  push(l64w, 64, 32, true, 0);
+  push(small, 16, 16, false, 0);
   if (!large.empty()) {
     int TM = 64, bn = 16;
     gemm_tile_shape(ta, tb, maxn, &TM, &bn);
-    std::vector<BlockMap> map;
-    build_map(b, large, TM, bn, &map);
-    const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
-    const int nblk = (int)map.size();
-    steps.push_back([=](const char* base) {
-      return launch_gemm_batched((const GemmDesc*)(base + od), (const BlockMap*)(base + om), nblk,
-                                 ta, tb, bn, st);
-    });
+    push(large, TM, bn, false, bn);
   }
   flops += b.flops;
 }

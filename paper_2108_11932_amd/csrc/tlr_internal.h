@@ -33,6 +33,9 @@ constexpr int GEMM_TRIL_A = 2;
 // op(A) is upper triangular (k >= row): the K loop starts at the tile's
 // first row.
 constexpr int GEMM_TRIU_A = 4;
+// C receives the transpose of the product (element (r, c) of op(A) op(B) at
+// C[c + r ldc]); transposed-A products on the LDS-streamed kernel only.
+constexpr int GEMM_STORE_T = 8;
 
 // One entry per launched workgroup: x = descriptor index, y = output tile
 // index inside that descriptor (row tiles vary fastest).
