@@ -138,7 +138,7 @@ __device__ inline void strip_grams(const double* X, int ldx, int nstrips, int nc
 constexpr int APPLY_ROWS = 256;
 
 template <int BS, bool PIV>
-__global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2, int r_min) {
+__global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, int r_min) {
   constexpr int NG = APPLY_ROWS / BS;
   constexpr int CPG = (BS + NG - 1) / NG;
   constexpr int XR = 64;   // rows of X staged at a time for the pass-1 strip Grams
@@ -158,6 +158,7 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, double tau2,
   const AraSlotDesc& d = D.slots[slot];
   const int m = D.m, qcap = D.qcap, nrb = D.nstrip;
   const int qold = D.q[slot];
+  const double tau2 = d.tau2;
   const double* part = PIV ? d.part1 : d.part2;
   const int t = threadIdx.x, lane = t & 63;
   const int x = t % BS, g = t / BS;
@@ -520,15 +521,13 @@ bool orth_block_supported(int bs) {
   return bs == 1 || bs == 2 || bs == 4 || bs == 8 || bs == 16 || bs == 24 || bs == 32;
 }
 
-hipError_t launch_orth_step(const AraDev& D, int pass, double tau2, int r_min, int count_bound,
-                            hipStream_t s) {
+hipError_t launch_orth_step(const AraDev& D, int pass, int r_min, int count_bound, hipStream_t s) {
   if (count_bound <= 0) return hipSuccess;
   const dim3 grid((D.m + APPLY_ROWS - 1) / APPLY_ROWS, count_bound);
   if (pass == 1) {
-    TLR_BS_DISPATCH(D.bs, (k_orth_step<BS_ARG, true>), grid, dim3(APPLY_ROWS), 0, s, D, tau2, r_min);
+    TLR_BS_DISPATCH(D.bs, (k_orth_step<BS_ARG, true>), grid, dim3(APPLY_ROWS), 0, s, D, r_min);
   } else {
-    TLR_BS_DISPATCH(D.bs, (k_orth_step<BS_ARG, false>), grid, dim3(APPLY_ROWS), 0, s, D, tau2,
-                    r_min);
+    TLR_BS_DISPATCH(D.bs, (k_orth_step<BS_ARG, false>), grid, dim3(APPLY_ROWS), 0, s, D, r_min);
   }
   return hipGetLastError();
 }

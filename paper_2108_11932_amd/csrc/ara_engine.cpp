@@ -102,6 +102,9 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   res->q.assign(n, 0);
   res->iters.assign(n, 0);
   res->flops_paper_orth.assign(n, 0.0);
+  res->flops_slot.assign(n, 0.0);
+  res->samp_bytes_slot.assign(n, 0.0);
+  res->samp_flops_slot.assign(n, 0.0);
   if (info_abort) *info_abort = false;
   if (n == 0) return TLR_OK;
   if (n > s.n || (int)spec.slots.size() != n) {
@@ -116,6 +119,8 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   // ---- static slot descriptors, uploaded once for the run
   for (int sl = 0; sl < n; ++sl) {
     AraSlotDesc& d = spec.slots[sl];
+    const double tau = spec.tau.empty() ? c.tau : spec.tau[sl];
+    d.tau2 = tau * tau;
     d.y = s.y(sl);
     d.q = s.qb(sl);
     d.c = s.c(sl);
@@ -123,10 +128,16 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     d.part2 = s.p2(sl);
     d.piv = s.piv + (size_t)sl * (bs + 1);
   }
+  // 32-row tiles of the P products of every group
+  std::vector<PTile> ptiles;
+  for (const PGroup& g : spec.pg)
+    for (int r0 = 0; r0 < g.rk; r0 += 32) ptiles.push_back(PTile{g.uk, spec.p + g.roff, g.rk, r0});
   const size_t sbytes = sizeof(AraSlotDesc) * n;
   const size_t zbytes = sizeof(ZSeg) * spec.zseg.size();
+  const size_t pbytes = sizeof(PTile) * ptiles.size();
   const size_t zoff = (sbytes + 255) & ~(size_t)255;
-  TLR_TRY(w.orth.ensure(h->mem, zoff + zbytes + 256));
+  const size_t poff = zoff + ((zbytes + 255) & ~(size_t)255);
+  TLR_TRY(w.orth.ensure(h->mem, poff + pbytes + 256));
   char* dbase = (char*)w.orth.p;
   {
     void* tmp = nullptr;
@@ -136,8 +147,13 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       TLR_TRY(h->stage.upload(h, spec.zseg.data(), zbytes, &tmp));
       TLR_HIP(hipMemcpyAsync(dbase + zoff, tmp, zbytes, hipMemcpyDeviceToDevice, st));
     }
+    if (pbytes) {
+      TLR_TRY(h->stage.upload(h, ptiles.data(), pbytes, &tmp));
+      TLR_HIP(hipMemcpyAsync(dbase + poff, tmp, pbytes, hipMemcpyDeviceToDevice, st));
+    }
   }
   const ZSeg* dzseg = (const ZSeg*)(dbase + zoff);
+  const PTile* dptiles = (const PTile*)(dbase + poff);
 
   // ---- initial state: active list, waiting list, cleared counters
   std::vector<int> act(order.begin(), order.begin() + s_max);
@@ -172,8 +188,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   D.bs = bs;
   D.qcap = c.qcap;
   D.nstrip = s.nstrip;
-  const double tau2 = c.tau * c.tau;
-  const int p_blocks = spec.rk > 0 ? (spec.rk + 31) / 32 : 0;
+  const int p_blocks = (int)ptiles.size();
   const int bps_wa = (spec.a_max + 31) / 32;
   // split-K partial tiles of the TN products
   double* tn_scratch = nullptr;
@@ -188,7 +203,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   int max_pieces = 0;
   for (const AraSlotDesc& d : spec.slots) max_pieces = std::max(max_pieces, d.nz);
   const int bps_z = (max_pieces + 3) / 4;
-  const bool any_z = !spec.zseg.empty() && bps_z > 0 && spec.rk > 0;
+  const bool any_z = !spec.zseg.empty() && bps_z > 0 && p_blocks > 0;
   int* info = h->d_info;
 
   Known known;
@@ -201,9 +216,8 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     const int qb = std::min(c.qcap, known.qmax + bs * (j - known.iter - 1));
     TLR_HIP(launch_randn(omega, m, D.bs, m, c.seed, c.stream_id, (unsigned)j, 0, st));
     if (p_blocks > 0 || bps_wa > 0)
-      TLR_HIP(launch_ara_tn(D, 0, omega, spec.uk, spec.rk, spec.p, p_blocks, cb, bps_wa, tn_scratch,
-                            st));
-    if (any_z) TLR_HIP(launch_ara_z(D, dzseg, spec.p, spec.rk, cb, bps_z, st));
+      TLR_HIP(launch_ara_tn(D, 0, omega, dptiles, p_blocks, spec.ldp, cb, bps_wa, tn_scratch, st));
+    if (any_z) TLR_HIP(launch_ara_z(D, dzseg, spec.p, spec.ldp, cb, bps_z, st));
     if (spec.events) {
       hipEvent_t e0, e1;
       TLR_HIP(hipEventCreate(&e0));
@@ -215,15 +229,15 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     }
     const int bps_q = (qb + 31) / 32;
     if (bps_q > 0) {
-      TLR_HIP(launch_ara_tn(D, 1, nullptr, nullptr, 0, nullptr, 0, cb, bps_q, tn_scratch, st));
+      TLR_HIP(launch_ara_tn(D, 1, nullptr, nullptr, 0, 0, cb, bps_q, tn_scratch, st));
       TLR_HIP(launch_ara_seg(D, 1, cb, st));
     }
-    TLR_HIP(launch_orth_step(D, 1, tau2, c.r_min, cb, st));
+    TLR_HIP(launch_orth_step(D, 1, c.r_min, cb, st));
     if (bps_q > 0) {
-      TLR_HIP(launch_ara_tn(D, 2, nullptr, nullptr, 0, nullptr, 0, cb, bps_q, tn_scratch, st));
+      TLR_HIP(launch_ara_tn(D, 2, nullptr, nullptr, 0, 0, cb, bps_q, tn_scratch, st));
       TLR_HIP(launch_ara_seg(D, 2, cb, st));
     }
-    TLR_HIP(launch_orth_step(D, 2, tau2, c.r_min, cb, st));
+    TLR_HIP(launch_orth_step(D, 2, c.r_min, cb, st));
     TLR_HIP(launch_ara_compact(D, s.waiting, nwait, s_max, info, ring + 8 * (j & 1), st));
     TLR_HIP(hipEventRecord(h->ev_rb[j & 1], st));
     return TLR_OK;
@@ -281,9 +295,12 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     // Gram matrices and the triangular solves of the Cholesky QR steps
     const double orth = 8.0 * m * (cols / std::max(it, 1.0)) * qs + 6.0 * m * b2;
     res->flops_paper_orth[sl] = orth;
-    res->flops += orth + cols * spec.samp_flops_col[sl];
-    res->samp_bytes += it * spec.samp_bytes[sl] + cols * spec.samp_bytes_col[sl];
-    res->samp_flops += cols * spec.samp_flops_col[sl];
+    res->flops_slot[sl] = orth + cols * spec.samp_flops_col[sl];
+    res->samp_bytes_slot[sl] = it * spec.samp_bytes[sl] + cols * spec.samp_bytes_col[sl];
+    res->samp_flops_slot[sl] = cols * spec.samp_flops_col[sl];
+    res->flops += res->flops_slot[sl];
+    res->samp_bytes += res->samp_bytes_slot[sl];
+    res->samp_flops += res->samp_flops_slot[sl];
   }
   return TLR_OK;
 }

@@ -64,15 +64,24 @@ struct AraSlots {
   double* p2(int s) const { return part2 + (size_t)s * nstrip * bs * bs * 2; }
 };
 
+// P_g = U_g^T Omega of one problem of the batch (U_g m x rk, its row-k
+// panel), stored in rows [roff, roff + rk) of the shared P.
+struct PGroup {
+  const double* uk;
+  int rk, roff;
+};
+
 // What each slot samples, fixed for the whole run.  The caller fills the
-// sampling fields of every AraSlotDesc (a0/b0/a1/b1, W^A and Z); ara_run
-// fills the workspace fields.
+// sampling fields of every AraSlotDesc (a0/b0/a1/b1, W^A and Z, whose
+// pieces address P by absolute row); ara_run fills the workspace fields
+// and the thresholds.
 struct AraSpec {
   std::vector<AraSlotDesc> slots;
   std::vector<ZSeg> zseg;
-  const double* uk = nullptr;   // P = U_k*^T Omega (rk x bs) when rk > 0
-  int rk = 0;
-  double* p = nullptr;
+  std::vector<PGroup> pg;       // the P products (none for explicit tiles)
+  double* p = nullptr;          // P of every group, leading dimension ldp
+  int ldp = 0;
+  std::vector<double> tau;      // per-slot absolute threshold (empty: the config's)
   int a_max = 0;                // largest W^A height over the slots
   int r_max = 0;                // largest Z height over the slots
   // sampling cost per slot: bytes per iteration = samp_bytes + samp_bytes_col
@@ -89,6 +98,8 @@ struct AraResult {
   long long launches = 0;      // ARA iterations (batches)
   double flops = 0.0;          // executed flops (sampling, Gram-Schmidt, orthogonalisation)
   double samp_bytes = 0.0, samp_flops = 0.0;   // of the sampling launches
+  // the same per slot
+  std::vector<double> flops_slot, samp_bytes_slot, samp_flops_slot;
 };
 
 // Spec of n explicit m x m tiles (tile t at tiles + t * ld * m, ld >= m):

@@ -37,11 +37,11 @@ struct TnTile {
   double alpha;
 };
 __device__ inline bool tn_resolve(const AraDev& D, int mode, int tid, const double* omega,
-                                  const double* uk, int rk, double* P, int p_tiles, int tps,
-                                  TnTile* o) {
+                                  const PTile* ptiles, int p_tiles, int ldp, int tps, TnTile* o) {
   const int m = D.m;
   if (mode == 0 && tid < p_tiles) {
-    *o = TnTile{uk, omega, P, rk, rk, tid * TN_TM, tid, 1.0};
+    const PTile& pt = ptiles[tid];
+    *o = TnTile{pt.A, omega, pt.C, pt.M, ldp, pt.row0, tid, 1.0};
     return true;
   }
   const int t = mode == 0 ? tid - p_tiles : tid;
@@ -70,15 +70,15 @@ __device__ inline bool tn_resolve(const AraDev& D, int mode, int tid, const doub
 // handshake, whose device-scope fences are costly across the XCDs).
 template <int FN>
 __global__ __launch_bounds__(64 * TN_NW) void k_ara_tn(AraDev D, int mode, const double* omega,
-                                                        const double* uk, int rk, double* P,
-                                                        int p_tiles, int tps, double* scratch) {
+                                                        const PTile* ptiles, int p_tiles, int ldp,
+                                                        int tps, double* scratch) {
   constexpr int FM = 2, TSZ = TN_TM * 16 * FN;
   __shared__ double red[TN_NW][FM * FN * 4][64];
   const int m = D.m, bs = D.bs;
   const int ks_n = (m + TN_KC - 1) / TN_KC;
   const int ks = blockIdx.x % ks_n, tid = blockIdx.x / ks_n;
   TnTile o;
-  if (!tn_resolve(D, mode, tid, omega, uk, rk, P, p_tiles, tps, &o)) return;
+  if (!tn_resolve(D, mode, tid, omega, ptiles, p_tiles, ldp, tps, &o)) return;
   const int k0 = ks * TN_KC, k1 = min(m, k0 + TN_KC);
   tn_tile<FM, FN, TN_NW, 1, true>(o.A, m, o.B, m, scratch + ((size_t)tid * ks_n + ks) * TSZ, TN_TM,
                                   o.M, bs, k0, k1, 1.0, 0.0, o.row0, 0, red);
@@ -86,13 +86,13 @@ __global__ __launch_bounds__(64 * TN_NW) void k_ara_tn(AraDev D, int mode, const
 
 template <int FN>
 __global__ __launch_bounds__(256) void k_ara_tn_sum(AraDev D, int mode, const double* omega,
-                                                    const double* uk, int rk, double* P,
-                                                    int p_tiles, int tps, const double* scratch) {
+                                                    const PTile* ptiles, int p_tiles, int ldp,
+                                                    int tps, const double* scratch) {
   constexpr int TSZ = TN_TM * 16 * FN;
   const int m = D.m, bs = D.bs;
   const int ks_n = (m + TN_KC - 1) / TN_KC;
   TnTile o;
-  if (!tn_resolve(D, mode, blockIdx.x, omega, uk, rk, P, p_tiles, tps, &o)) return;
+  if (!tn_resolve(D, mode, blockIdx.x, omega, ptiles, p_tiles, ldp, tps, &o)) return;
   const double* part = scratch + (size_t)blockIdx.x * ks_n * TSZ;
   for (int e = threadIdx.x; e < TSZ; e += 256) {
     const int lr = e % TN_TM, lc = e / TN_TM;
@@ -213,8 +213,8 @@ int ara_tn_scratch(int m, int bs, long long tiles, size_t* doubles) {
   return TN_TM;
 }
 
-hipError_t launch_ara_tn(const AraDev& D, int mode, const double* omega, const double* uk, int rk,
-                         double* P, int p_tiles, int count_bound, int tps, double* scratch,
+hipError_t launch_ara_tn(const AraDev& D, int mode, const double* omega, const PTile* ptiles,
+                         int p_tiles, int ldp, int count_bound, int tps, double* scratch,
                          hipStream_t s) {
   if (D.bs > 32) return hipErrorInvalidValue;
   const int pt = mode == 0 ? p_tiles : 0;
@@ -224,14 +224,14 @@ hipError_t launch_ara_tn(const AraDev& D, int mode, const double* omega, const d
   const int tp = std::max(tps, 1);
   if (D.bs <= 16) {
     hipLaunchKernelGGL((k_ara_tn<1>), dim3((unsigned)(tiles * ks_n)), dim3(64 * TN_NW), 0, s, D,
-                       mode, omega, uk, rk, P, pt, tp, scratch);
-    hipLaunchKernelGGL((k_ara_tn_sum<1>), dim3((unsigned)tiles), dim3(256), 0, s, D, mode, omega, uk,
-                       rk, P, pt, tp, scratch);
+                       mode, omega, ptiles, pt, ldp, tp, scratch);
+    hipLaunchKernelGGL((k_ara_tn_sum<1>), dim3((unsigned)tiles), dim3(256), 0, s, D, mode, omega,
+                       ptiles, pt, ldp, tp, scratch);
   } else {
     hipLaunchKernelGGL((k_ara_tn<2>), dim3((unsigned)(tiles * ks_n)), dim3(64 * TN_NW), 0, s, D,
-                       mode, omega, uk, rk, P, pt, tp, scratch);
-    hipLaunchKernelGGL((k_ara_tn_sum<2>), dim3((unsigned)tiles), dim3(256), 0, s, D, mode, omega, uk,
-                       rk, P, pt, tp, scratch);
+                       mode, omega, ptiles, pt, ldp, tp, scratch);
+    hipLaunchKernelGGL((k_ara_tn_sum<2>), dim3((unsigned)tiles), dim3(256), 0, s, D, mode, omega,
+                       ptiles, pt, ldp, tp, scratch);
   }
   return hipGetLastError();
 }

@@ -19,6 +19,8 @@
 // column.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <memory>
 
 #include "ara_engine.h"
 
@@ -109,441 +111,462 @@ static tlr_status input_norms(Handle* h) {
   return TLR_OK;
 }
 
-tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bool ldl) {
-  const int m = h->m, nb = h->nb, bs = o.bs;
+namespace {
+
+// One problem of a (possibly batched) factorization and its column state.
+struct Prob {
+  Handle* h = nullptr;
+  double tau = 0.0, shift = 0.0;
+  double* pin_norm = nullptr;
+  int* pin_order = nullptr;
+  bool done = false;
+  double flops = 0.0, flops_paper = 0.0, bytes_alg = 0.0, samp_bytes = 0.0, samp_flops = 0.0;
+  long long ara_iters = 0, tile_iters = 0, fp32_tile_iters = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  std::vector<long long> goff;
+  // column k
+  int Rk = 0, nrow = 0, base = 0, roff = 0;
+  double* G = nullptr;
+  std::unique_ptr<Plan> dplan;
+  std::vector<int> order;
+  std::vector<char> use32;
+  const double* gptr(int i, int j) const {
+    const long long go = goff[(size_t)i * h->nb + j];
+    return go >= 0 ? G + go : G;
+  }
+};
+
+constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
+
+// Set-up of one problem: factor storage, streams, thresholds, initial panel
+// capacities.
+tlr_status prob_init(Prob& p, double eps, const tlr_opts& o, bool ldl) {
+  Handle* h = p.h;
+  const int m = h->m, nb = h->nb;
   free_factor(h);
   if (!h->Ld) {
-    void* p = nullptr;
-    TLR_TRY(h->mem.get(&p, sizeof(double) * (size_t)nb * m * m));
-    h->Ld = (double*)p;
+    void* q = nullptr;
+    TLR_TRY(h->mem.get(&q, sizeof(double) * (size_t)nb * m * m));
+    h->Ld = (double*)q;
   }
   if (!h->Li) {
-    void* p = nullptr;
-    TLR_TRY(h->mem.get(&p, sizeof(double) * (size_t)nb * m * m));
-    h->Li = (double*)p;
+    void* q = nullptr;
+    TLR_TRY(h->mem.get(&q, sizeof(double) * (size_t)nb * m * m));
+    h->Li = (double*)q;
   }
   TLR_TRY(h->init_streams());
   if (ldl && !h->Dv) {
-    void* p = nullptr;
-    TLR_TRY(h->mem.get(&p, sizeof(double) * (size_t)nb * m));
-    h->Dv = (double*)p;
+    void* q = nullptr;
+    TLR_TRY(h->mem.get(&q, sizeof(double) * (size_t)nb * m));
+    h->Dv = (double*)q;
   }
-  double tau = eps;
+  p.tau = eps;
   if (o.eps_mode == TLR_EPS_REL) {
     if (h->norm_a <= 0.0) TLR_TRY(estimate_norm(h, &h->norm_a));
-    tau = eps * h->norm_a;
+    p.tau = eps * h->norm_a;
   }
-  const double shift = o.shift < 0.0 ? tau : o.shift;
+  p.shift = o.shift < 0.0 ? p.tau : o.shift;
   TLR_HIP(hipMemsetAsync(h->d_info, 0, sizeof(int), h->stream));
   // mixed precision: FP32 panels for the tiles whose FP32 rounding stays
   // below tau / 16 (the LDL^T variant samples in FP64 throughout)
   h->mixed = o.precision == TLR_MIXED_FP32 && !ldl;
-  const double u32 = 5.9604644775390625e-08;   // 2^-24
   if (h->mixed && h->a_fro.empty()) TLR_TRY(input_norms(h));
   h->l_fro.assign((size_t)nb * nb, 0.0);
-  double* pin_norm = nullptr;
-  if (h->mixed) TLR_TRY(h->pinned_norms((size_t)std::max(nb, 1), &pin_norm));
-  long long fp32_tile_iters = 0;
-
+  if (h->mixed) TLR_TRY(h->pinned_norms((size_t)std::max(nb, 1), &p.pin_norm));
+  TLR_TRY(h->pinned_ints((size_t)std::max(nb, 1), &p.pin_order));
   // initial panel capacities from the input ranks (a large rank in A tends to
   // stay large in L, Section 4.2)
   for (int i = 1; i < nb; ++i) {
-    long long s = 0;
-    for (int j = 0; j < i; ++j) s += h->ar(i, j);
-    long long c = (long long)(1.25 * s) + 32;
+    long long sum = 0;
+    for (int j = 0; j < i; ++j) sum += h->ar(i, j);
+    long long c = (long long)(1.25 * sum) + 32;
     c = std::min(c, (long long)i * m);
     TLR_TRY(grow_row(h, i, (int)c));
   }
+  p.goff.assign((size_t)nb * nb, -1);
+  return TLR_OK;
+}
 
+// Column k, before the ARA: G_ij = V_ij^T (D_j) V_kj, the diagonal-tile
+// work queued for the side stream, and the device sortRanks of the column's
+// tiles into `order_out` (read back after the caller's synchronisation).
+tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
+  Handle* h = p.h;
+  const int m = h->m, nb = h->nb;
   Work& w = h->ws;
-  double flops = 0.0, flops_paper = 0.0, bytes_alg = 0.0;
-  long long ara_iters = 0, tile_iters = 0;
-  AraConfig cfg;
-  cfg.m = m;
-  cfg.bs = bs;
-  cfg.bs_tail = o.bs_tail;
-  cfg.qcap = m;
-  cfg.tau = tau;
-  cfg.r_min = o.r_min;
-  cfg.s_max = o.max_active;
-  cfg.seed = o.seed;
-  AraSlots slots;
-  TLR_TRY(ara_slots(h, cfg, std::max(1, nb - 1), &slots));
-
-  const bool timing = (o.flags & TLR_FLAG_KERNEL_TIMING) != 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-  double samp_bytes = 0.0, samp_flops = 0.0;
-  std::vector<long long> goff((size_t)nb * nb, -1);
-  for (int k = 0; k < nb; ++k) {
-    const int Rk = h->R[k];
-    // ---------------------------------------------- G_ij = V_ij^T (D_j) V_kj
-    const double* Vk = h->VL[k];
-    if (ldl && Rk > 0) {
-      TLR_TRY(w.W.ensure(h->mem, sizeof(double) * (size_t)m * Rk));
+  p.Rk = h->R[k];
+  const int Rk = p.Rk;
+  // ---------------------------------------------- G_ij = V_ij^T (D_j) V_kj
+  const double* Vk = h->VL[k];
+  if (ldl && Rk > 0) {
+    TLR_TRY(w.W.ensure(h->mem, sizeof(double) * (size_t)m * Rk));
+    for (int j = 0; j < k; ++j) {
+      const int r = h->lr(k, j);
+      if (r == 0) continue;
+      TLR_HIP(launch_scale_rows(h->vl(k, j), m, w.W.as<double>() + h->lo(k, j) * m, m,
+                                h->Dv + (size_t)j * m, m, r, false, h->stream));
+    }
+    Vk = w.W.as<double>();
+  }
+  long long gtot = 0;
+  for (int i = k; i < nb; ++i)
+    for (int j = 0; j < k; ++j) {
+      const int a = h->lr(i, j), b = h->lr(k, j);
+      p.goff[(size_t)i * nb + j] = (a > 0 && b > 0) ? gtot : -1;
+      if (a > 0 && b > 0) gtot += (long long)a * b;
+    }
+  TLR_TRY(w.G.ensure(h->mem, sizeof(double) * (size_t)std::max(gtot, 1LL)));
+  p.G = w.G.as<double>();
+  {
+    GemmBatch g(true, false);
+    for (int i = k; i < nb; ++i)
+      for (int j = 0; j < k; ++j) {
+        const long long go = p.goff[(size_t)i * nb + j];
+        if (go < 0) continue;
+        const int a = h->lr(i, j), b = h->lr(k, j);
+        g.add(a, b, m, h->vl(i, j), m, Vk + h->lo(k, j) * m, m, p.G + go, a, 1.0, 0.0);
+      }
+    TLR_TRY(g.run(h));
+    p.flops += g.flops;
+  }
+  // ---------------------------------------------- updateDense + chol / ldl
+  // on the diagonal-tile stream: they need only the G blocks and row k's
+  // panels, and the column's ARA needs L_kk only at the triangular solve
+  double* Lkk = h->diagL(k);
+  hipStream_t ds = h->side;
+  TLR_HIP(hipEventRecord(h->ev_fork, h->stream));
+  TLR_HIP(hipStreamWaitEvent(ds, h->ev_fork, 0));
+  if (Rk > 0 && w.Wd.cap < sizeof(double) * (size_t)m * Rk) {
+    TLR_HIP(hipStreamSynchronize(ds));
+    TLR_TRY(w.Wd.ensure(h->mem, sizeof(double) * (size_t)m * Rk));
+  }
+  // the launches of the diagonal-tile stream are issued a few at a time
+  // while the host waits on the ARA iterations of the main stream
+  p.dplan.reset(new Plan(h, ds));
+  Plan& dplan = *p.dplan;
+  dplan.persist = &w.sideblob;
+  {
+    const double* Akk = h->diagA(k);
+    const int nr = h->nreal(k);
+    const double shift = p.shift;
+    dplan.launch([=]() { return launch_copy_shift(Akk, Lkk, m, nr, shift, ds); });
+    if (Rk > 0) {
+      double* Wd = w.Wd.as<double>();
+      GemmBatch wb(false, false);
       for (int j = 0; j < k; ++j) {
         const int r = h->lr(k, j);
         if (r == 0) continue;
-        TLR_HIP(launch_scale_rows(h->vl(k, j), m, w.W.as<double>() + h->lo(k, j) * m, m,
-                                  h->Dv + (size_t)j * m, m, r, false, h->stream));
+        wb.add(m, r, r, h->ul(k, j), m, p.gptr(k, j), r, Wd + h->lo(k, j) * m, m, 1.0, 0.0);
       }
-      Vk = w.W.as<double>();
+      dplan.gemm(wb);
+      GemmBatch up(false, true);
+      up.add(m, m, Rk, Wd, m, h->UL[k], m, Lkk, m, -1.0, 1.0, GEMM_LOWER_C);
+      dplan.gemm(up);
+      p.flops += wb.flops + up.flops / 2;
     }
-    long long gtot = 0;
-    for (int i = k; i < nb; ++i)
+    TLR_TRY(dense_factor(h, dplan, !ldl, Lkk, m, m, ldl ? h->Dv + (size_t)k * m : nullptr, k * m,
+                         h->invL(k)));
+    TLR_TRY(dplan.run_some(8));
+  }
+  p.flops_paper += 2.0 * m * (double)m * Rk + (double)m * m * m / 3.0;
+  p.flops += (double)m * m * m / 3.0 + (double)m * m * m / 3.0;
+  p.nrow = nb - k - 1;
+  // ---------------------------------------------- sortRanks (device)
+  if (p.nrow > 0) {
+    const int nrow = p.nrow;
+    std::vector<int> rk(nrow), rows(nrow);
+    for (int s = 0; s < nrow; ++s) {
+      rk[s] = h->ar(k + 1 + s, k);
+      rows[s] = s;
+    }
+    void* dr = nullptr;
+    void* dw = nullptr;
+    TLR_TRY(h->stage.upload(h, rk.data(), sizeof(int) * nrow, &dr));
+    TLR_TRY(h->stage.upload(h, rows.data(), sizeof(int) * nrow, &dw));
+    TLR_HIP(launch_sort_ranks((const int*)dr, (const int*)dw, nrow, order_out, h->stream));
+    TLR_HIP(hipMemcpyAsync(p.pin_order, order_out, sizeof(int) * nrow, hipMemcpyDeviceToHost,
+                           h->stream));
+  }
+  return TLR_OK;
+}
+
+tlr_status side_done(Prob& p) {
+  if (!p.dplan) return TLR_OK;
+  TLR_TRY(p.dplan->run());
+  TLR_HIP(hipEventRecord(p.h->ev_join, p.h->side));
+  p.dplan.reset();
+  return TLR_OK;
+}
+
+// After the synchronisation that follows col_begin: the sorted order, the V
+// norms of column k - 1 (mixed precision) and the per-tile precision choice.
+void col_order(Prob& p, int k) {
+  Handle* h = p.h;
+  const int nb = h->nb, nrow = p.nrow;
+  p.order.assign(p.pin_order, p.pin_order + nrow);
+  if (h->mixed && k > 0)
+    for (int s = 0; s < nrow + 1; ++s) h->l_fro[(size_t)(k + s) * nb + (k - 1)] = p.pin_norm[s];
+  p.use32.assign(nrow, 0);
+  if (h->mixed)
+    for (int s = 0; s < nrow; ++s) {
+      const int i = k + 1 + s;
+      double nu = h->a_fro[(size_t)i * nb + k];
+      for (int j = 0; j < k; ++j) nu += h->l_fro[(size_t)i * nb + j] * h->l_fro[(size_t)k * nb + j];
+      p.use32[s] = (kU32 * nu <= p.tau / 16.0) ? 1 : 0;
+    }
+}
+
+// The sampling description of problem p's tiles of column k, appended to the
+// pooled spec at slots [p.base, p.base + p.nrow) and P rows [p.roff, ...).
+tlr_status col_spec(Prob& p, int k, int bsm, AraSpec& spec) {
+  Handle* h = p.h;
+  const int m = h->m, nrow = p.nrow, Rk = p.Rk;
+  Work& w = h->ws;
+  TLR_TRY(w.Wa.ensure(h->mem, sizeof(double) * (size_t)nrow * m * bsm));
+  {
+    long long zt = 0;
+    for (int s = 0; s < nrow; ++s) zt += h->R[k + 1 + s];
+    TLR_TRY(w.Z.ensure(h->mem, sizeof(double) * (size_t)std::max(zt, 1LL) * bsm));
+  }
+  double* Wa = w.Wa.as<double>();
+  double* Z = w.Z.as<double>();
+  // static sampling description of every tile of the column:
+  //   Y_i = U^A_ik W^A_i + U_i* Z_i,  W^A_i = V^A_ik^T Omega,
+  //   Z_i = -[G_ij P_j]_j,  P = U_k*^T Omega
+  if (Rk > 0) spec.pg.push_back(PGroup{h->UL[k], Rk, p.roff});
+  long long zo = 0;
+  for (int s = 0; s < nrow; ++s) {
+    const int i = k + 1 + s;
+    const int a = h->ar(i, k), Ri = h->R[i];
+    AraSlotDesc& d = spec.slots[p.base + s];
+    double* wa_s = Wa + (size_t)s * m * bsm;
+    d.a0 = h->ua(i, k);
+    d.lda0 = m;
+    d.k0 = a;
+    d.b0 = wa_s;
+    d.ldb0 = std::max(a, 1);
+    d.va = h->va(i, k);
+    d.wa = wa_s;
+    d.a = a;
+    spec.a_max = std::max(spec.a_max, a);
+    d.lda1 = m;
+    d.ldb1 = 1;
+    if (Rk > 0 && Ri > 0) {
+      double* zs = Z + zo;
+      zo += (long long)Ri * bsm;
+      d.a1 = p.use32[s] ? (const void*)h->UL32[i] : (const void*)h->UL[i];
+      d.a1_f32 = p.use32[s];
+      d.k1 = Ri;
+      d.b1 = zs;
+      d.ldb1 = Ri;
+      d.z = zs;
+      d.R = Ri;
+      d.zseg = (int)spec.zseg.size();
       for (int j = 0; j < k; ++j) {
-        const int a = h->lr(i, j), b = h->lr(k, j);
-        goff[(size_t)i * nb + j] = (a > 0 && b > 0) ? gtot : -1;
-        if (a > 0 && b > 0) gtot += (long long)a * b;
+        const int rij = h->lr(i, j);
+        for (int r0 = 0; r0 < rij; r0 += 16)
+          spec.zseg.push_back(ZSeg{p.gptr(i, j) + r0, rij, std::min(16, rij - r0), h->lr(k, j),
+                                   (int)h->lo(i, j) + r0, p.roff + (int)h->lo(k, j)});
       }
-    TLR_TRY(w.G.ensure(h->mem, sizeof(double) * (size_t)std::max(gtot, 1LL)));
-    double* G = w.G.as<double>();
-    {
-      GemmBatch g(true, false);
-      for (int i = k; i < nb; ++i)
-        for (int j = 0; j < k; ++j) {
-          const long long go = goff[(size_t)i * nb + j];
-          if (go < 0) continue;
-          const int a = h->lr(i, j), b = h->lr(k, j);
-          g.add(a, b, m, h->vl(i, j), m, Vk + h->lo(k, j) * m, m, G + go, a, 1.0, 0.0);
-        }
-      TLR_TRY(g.run(h));
-      flops += g.flops;
+      d.nz = (int)spec.zseg.size() - d.zseg;
+      spec.r_max = std::max(spec.r_max, Ri);
     }
-    auto gptr = [&](int i, int j) -> const double* {
-      const long long go = goff[(size_t)i * nb + j];
-      return go >= 0 ? G + go : G;
-    };
+    const double kk = (double)a + d.k1;
+    spec.samp_flops_col[p.base + s] = 2.0 * m * kk;
+    spec.samp_bytes[p.base + s] = 8.0 * m * a + (d.a1_f32 ? 4.0 : 8.0) * m * d.k1;
+    spec.samp_bytes_col[p.base + s] = 8.0 * (kk + m);
+    spec.tau[p.base + s] = p.tau;
+  }
+  return TLR_OK;
+}
 
-    // ---------------------------------------------- updateDense + chol / ldl
-    // on the diagonal-tile stream: they need only the G blocks and row k's
-    // panels, and the column's ARA needs L_kk only at the triangular solve
-    double* Lkk = h->diagL(k);
-    hipStream_t ds = h->side;
-    TLR_HIP(hipEventRecord(h->ev_fork, h->stream));
-    TLR_HIP(hipStreamWaitEvent(ds, h->ev_fork, 0));
-    if (Rk > 0 && w.Wd.cap < sizeof(double) * (size_t)m * Rk) {
-      TLR_HIP(hipStreamSynchronize(ds));
-      TLR_TRY(w.Wd.ensure(h->mem, sizeof(double) * (size_t)m * Rk));
-    }
-    // the launches of the diagonal-tile stream are issued a few at a time
-    // while the host waits on the ARA iterations of the main stream
-    Plan dplan(h, ds);
-    dplan.persist = &w.sideblob;
-    {
-      const double* Akk = h->diagA(k);
-      const int nr = h->nreal(k);
-      dplan.launch([=]() { return launch_copy_shift(Akk, Lkk, m, nr, shift, ds); });
+// Column k, after the ARA: projection B_i = S_ik^T Q_i, batched triangular
+// solve with L_kk, and the append of U_ik = Q_i, V_ik to the row panels.
+tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraSlots& slots,
+                      const AraResult& res) {
+  Handle* h = p.h;
+  const int m = h->m, nb = h->nb, nrow = p.nrow, Rk = p.Rk;
+  Work& w = h->ws;
+  // W^A, Z and P products of the iterations (P counted for the problem's
+  // share of the launches: the iterations its tiles took part in)
+  int launches = 0;
+  for (int s = 0; s < nrow; ++s) launches = std::max(launches, res.iters[p.base + s]);
+  if (launches > 0) p.flops += 2.0 * Rk * m * (cfg.bs + (launches - 1.0) * cfg.bs_at(1));
+  std::vector<int> q(nrow), it(nrow);
+  for (int s = 0; s < nrow; ++s) {
+    const int i = k + 1 + s, sl = p.base + s;
+    q[s] = res.q[sl];
+    it[s] = res.iters[sl];
+    double zf = 0.0;
+    for (int j = 0; j < k; ++j) zf += (double)h->lr(i, j) * h->lr(k, j);
+    const double cols = it[s] > 0 ? cfg.bs + (it[s] - 1.0) * cfg.bs_at(1) : 0.0;
+    p.flops += cols * 2.0 * ((double)h->ar(i, k) * m + zf);
+    if (p.use32[s]) p.fp32_tile_iters += it[s];
+    p.flops += res.flops_slot[sl];
+    p.samp_bytes += res.samp_bytes_slot[sl];
+    p.samp_flops += res.samp_flops_slot[sl];
+  }
+  p.ara_iters += launches;
+
+  // ---------------------------------------------- projection  B_i = S_ik^T Q_i
+  std::vector<long long> boff(nrow), toff(nrow), taoff(nrow);
+  long long sq = 0, st_ = 0, sta = 0;
+  for (int s = 0; s < nrow; ++s) {
+    const int i = k + 1 + s;
+    boff[s] = sq;
+    toff[s] = st_;
+    taoff[s] = sta;
+    sq += q[s];
+    st_ += (long long)h->R[i] * q[s];
+    sta += (long long)h->ar(i, k) * q[s];
+  }
+  TLR_TRY(w.T.ensure(h->mem, sizeof(double) * (size_t)std::max(st_, 1LL)));
+  TLR_TRY(w.Ta.ensure(h->mem, sizeof(double) * (size_t)std::max(sta, 1LL)));
+  TLR_TRY(w.H.ensure(h->mem, sizeof(double) * (size_t)std::max((long long)Rk * sq, 1LL)));
+  TLR_TRY(w.Ball.ensure(h->mem, sizeof(double) * (size_t)std::max((long long)m * sq, 1LL)));
+  double* T = w.T.as<double>();
+  double* Ta = w.Ta.as<double>();
+  double* H = w.H.as<double>();
+  double* Ball = w.Ball.as<double>();
+  TLR_TRY(w.Bt.ensure(h->mem, sizeof(double) * (size_t)std::max((long long)m * sq, 1LL)));
+  double* Bt = w.Bt.as<double>();
+  for (int s = 0; s < nrow; ++s)
+    if (q[s] > 0) TLR_TRY(grow_row(h, k + 1 + s, q[s]));
+  Plan plan(h);
+  {
+    GemmBatch t1(true, false), t2(true, false), hb(true, false), b1(false, false), b2(false, false);
+    for (int s = 0; s < nrow; ++s) {
+      const int i = k + 1 + s, qs = q[s];
+      if (qs == 0) continue;
+      const int a = h->ar(i, k), Ri = h->R[i];
+      const double* Qs = slots.qb(p.base + s);
+      if (Ri > 0) t1.add(Ri, qs, m, h->UL[i], m, Qs, m, T + toff[s], Ri, 1.0, 0.0);
+      if (a > 0) t2.add(a, qs, m, h->ua(i, k), m, Qs, m, Ta + taoff[s], a, 1.0, 0.0);
       if (Rk > 0) {
-        double* Wd = w.Wd.as<double>();
-        GemmBatch wb(false, false);
         for (int j = 0; j < k; ++j) {
-          const int r = h->lr(k, j);
-          if (r == 0) continue;
-          wb.add(m, r, r, h->ul(k, j), m, gptr(k, j), r, Wd + h->lo(k, j) * m, m, 1.0, 0.0);
+          const int rkj = h->lr(k, j);
+          if (rkj == 0) continue;
+          const int rij = h->lr(i, j);
+          hb.add(rkj, qs, rij, p.gptr(i, j), rij, T + toff[s] + (rij > 0 ? h->lo(i, j) : 0),
+                 std::max(Ri, 1), H + boff[s] * Rk + h->lo(k, j), Rk, 1.0, 0.0);
         }
-        dplan.gemm(wb);
-        GemmBatch up(false, true);
-        up.add(m, m, Rk, Wd, m, h->UL[k], m, Lkk, m, -1.0, 1.0, GEMM_LOWER_C);
-        dplan.gemm(up);
-        flops += wb.flops + up.flops / 2;
       }
-      TLR_TRY(dense_factor(h, dplan, !ldl, Lkk, m, m, ldl ? h->Dv + (size_t)k * m : nullptr, k * m,
-                           h->invL(k)));
-      TLR_TRY(dplan.run_some(8));
+      b1.add(m, qs, a, h->va(i, k), m, Ta + taoff[s], std::max(a, 1), Ball + boff[s] * m, m, 1.0,
+             0.0);
     }
-    flops_paper += 2.0 * m * (double)m * Rk + (double)m * m * m / 3.0;
-    flops += (double)m * m * m / 3.0 + (double)m * m * m / 3.0;
-    auto side_done = [&]() -> tlr_status {
-      TLR_TRY(dplan.run());
-      TLR_HIP(hipEventRecord(h->ev_join, ds));
-      return TLR_OK;
-    };
-
-    const int nrow = nb - k - 1;
-    if (nrow == 0) {
-      TLR_TRY(side_done());
-      break;
-    }
-
-    // ---------------------------------------------- sortRanks (device)
-    std::vector<int> order(nrow);
-    {
-      std::vector<int> rk(nrow), rows(nrow);
-      for (int s = 0; s < nrow; ++s) {
-        rk[s] = h->ar(k + 1 + s, k);
-        rows[s] = s;
-      }
-      void* dr = nullptr;
-      void* dw = nullptr;
-      TLR_TRY(h->stage.upload(h, rk.data(), sizeof(int) * nrow, &dr));
-      TLR_TRY(h->stage.upload(h, rows.data(), sizeof(int) * nrow, &dw));
-      TLR_HIP(launch_sort_ranks((const int*)dr, (const int*)dw, nrow, slots.waiting, h->stream));
-      int* pin = nullptr;
-      TLR_TRY(h->pinned_ints(nrow, &pin));
-      TLR_HIP(hipMemcpyAsync(pin, slots.waiting, sizeof(int) * nrow, hipMemcpyDeviceToHost,
-                             h->stream));
-      TLR_TRY(h->sync_main());
-      order.assign(pin, pin + nrow);
-    }
-    // the V norms of column k - 1 arrived with that sync
-    if (h->mixed && k > 0)
-      for (int s = 0; s < nrow + 1; ++s) h->l_fro[(size_t)(k + s) * nb + (k - 1)] = pin_norm[s];
-    std::vector<char> use32(nrow, 0);
-    if (h->mixed)
-      for (int s = 0; s < nrow; ++s) {
-        const int i = k + 1 + s;
-        double nu = h->a_fro[(size_t)i * nb + k];
-        for (int j = 0; j < k; ++j) nu += h->l_fro[(size_t)i * nb + j] * h->l_fro[(size_t)k * nb + j];
-        use32[s] = (u32 * nu <= tau / 16.0) ? 1 : 0;
-      }
-
-    // ---------------------------------------------- cholARAUpdate
-    const int bsm = cfg.bs_max();
-    TLR_TRY(w.P.ensure(h->mem, sizeof(double) * (size_t)std::max(Rk, 1) * bsm));
-    TLR_TRY(w.Wa.ensure(h->mem, sizeof(double) * (size_t)nrow * m * bsm));
-    {
-      long long zt = 0;
-      for (int s = 0; s < nrow; ++s) zt += h->R[k + 1 + s];
-      TLR_TRY(w.Z.ensure(h->mem, sizeof(double) * (size_t)std::max(zt, 1LL) * bsm));
-    }
-    double* P = w.P.as<double>();
-    double* Wa = w.Wa.as<double>();
-    double* Z = w.Z.as<double>();
-    // static sampling description of every tile of the column:
-    //   Y_i = U^A_ik W^A_i + U_i* Z_i,  W^A_i = V^A_ik^T Omega,
-    //   Z_i = -[G_ij P_j]_j,  P = U_k*^T Omega
-    AraSpec spec;
-    spec.slots.assign(nrow, AraSlotDesc{});
-    spec.samp_bytes.assign(nrow, 0.0);
-    spec.samp_bytes_col.assign(nrow, 0.0);
-    spec.samp_flops_col.assign(nrow, 0.0);
-    spec.uk = h->UL[k];
-    spec.rk = Rk;
-    spec.p = P;
-    spec.events = timing ? &events : nullptr;
-    {
-      long long zo = 0;
-      for (int s = 0; s < nrow; ++s) {
-        const int i = k + 1 + s;
-        const int a = h->ar(i, k), Ri = h->R[i];
-        AraSlotDesc& d = spec.slots[s];
-        double* wa_s = Wa + (size_t)s * m * bsm;
-        d.a0 = h->ua(i, k);
-        d.lda0 = m;
-        d.k0 = a;
-        d.b0 = wa_s;
-        d.ldb0 = std::max(a, 1);
-        d.va = h->va(i, k);
-        d.wa = wa_s;
-        d.a = a;
-        spec.a_max = std::max(spec.a_max, a);
-        d.lda1 = m;
-        d.ldb1 = 1;
-        if (Rk > 0 && Ri > 0) {
-          double* zs = Z + zo;
-          zo += (long long)Ri * bsm;
-          d.a1 = use32[s] ? (const void*)h->UL32[i] : (const void*)h->UL[i];
-          d.a1_f32 = use32[s];
-          d.k1 = Ri;
-          d.b1 = zs;
-          d.ldb1 = Ri;
-          d.z = zs;
-          d.R = Ri;
-          d.zseg = (int)spec.zseg.size();
-          for (int j = 0; j < k; ++j) {
-            const int rij = h->lr(i, j);
-            for (int r0 = 0; r0 < rij; r0 += 16)
-              spec.zseg.push_back(ZSeg{gptr(i, j) + r0, rij, std::min(16, rij - r0), h->lr(k, j),
-                                       (int)h->lo(i, j) + r0, (int)h->lo(k, j)});
-          }
-          d.nz = (int)spec.zseg.size() - d.zseg;
-          spec.r_max = std::max(spec.r_max, Ri);
-        }
-        const double kk = (double)a + d.k1;
-        spec.samp_flops_col[s] = 2.0 * m * kk;
-        spec.samp_bytes[s] = 8.0 * m * a + (d.a1_f32 ? 4.0 : 8.0) * m * d.k1;
-        spec.samp_bytes_col[s] = 8.0 * (kk + m);
-      }
-    }
-    // slots hold rows k+1.. in natural order; `order` is the sorted order
-    AraResult res;
-    cfg.stream_id = (unsigned)k;
-    bool abort = false;
-    TLR_TRY(ara_run(h, cfg, slots, order, spec, &res, &abort, [&]() -> tlr_status {
-      return dplan.pending() ? dplan.run_some(8) : TLR_OK;
-    }));
-    TLR_TRY(side_done());
-    // W^A, Z and P products of the iterations
-    flops += 2.0 * Rk * m * (cfg.bs + (res.launches - 1.0) * cfg.bs_at(1));
-    for (int s = 0; s < nrow; ++s) {
-      const int i = k + 1 + s;
-      double zf = 0.0;
-      for (int j = 0; j < k; ++j) zf += (double)h->lr(i, j) * h->lr(k, j);
-      const double cols = res.iters[s] > 0 ? cfg.bs + (res.iters[s] - 1.0) * cfg.bs_at(1) : 0.0;
-      flops += cols * 2.0 * ((double)h->ar(i, k) * m + zf);
-      if (use32[s]) fp32_tile_iters += res.iters[s];
-    }
-    samp_bytes += res.samp_bytes;
-    samp_flops += res.samp_flops;
-    if (abort) break;
-    flops += res.flops;
-    ara_iters += res.launches;
-
-    // ---------------------------------------------- projection  B_i = S_ik^T Q_i
-    const std::vector<int>& q = res.q;
-    std::vector<long long> boff(nrow), toff(nrow), taoff(nrow);
-    long long sq = 0, st_ = 0, sta = 0;
-    for (int s = 0; s < nrow; ++s) {
-      const int i = k + 1 + s;
-      boff[s] = sq;
-      toff[s] = st_;
-      taoff[s] = sta;
-      sq += q[s];
-      st_ += (long long)h->R[i] * q[s];
-      sta += (long long)h->ar(i, k) * q[s];
-    }
-    TLR_TRY(w.T.ensure(h->mem, sizeof(double) * (size_t)std::max(st_, 1LL)));
-    TLR_TRY(w.Ta.ensure(h->mem, sizeof(double) * (size_t)std::max(sta, 1LL)));
-    TLR_TRY(w.H.ensure(h->mem, sizeof(double) * (size_t)std::max((long long)Rk * sq, 1LL)));
-    TLR_TRY(w.Ball.ensure(h->mem, sizeof(double) * (size_t)std::max((long long)m * sq, 1LL)));
-    double* T = w.T.as<double>();
-    double* Ta = w.Ta.as<double>();
-    double* H = w.H.as<double>();
-    double* Ball = w.Ball.as<double>();
-    TLR_TRY(w.Bt.ensure(h->mem, sizeof(double) * (size_t)std::max((long long)m * sq, 1LL)));
-    double* Bt = w.Bt.as<double>();
-    for (int s = 0; s < nrow; ++s)
-      if (q[s] > 0) TLR_TRY(grow_row(h, k + 1 + s, q[s]));
-    Plan plan(h);
-    {
-      GemmBatch t1(true, false), t2(true, false), hb(true, false), b1(false, false), b2(false, false);
-      for (int s = 0; s < nrow; ++s) {
-        const int i = k + 1 + s, qs = q[s];
-        if (qs == 0) continue;
-        const int a = h->ar(i, k), Ri = h->R[i];
-        const double* Qs = slots.qb(s);
-        if (Ri > 0) t1.add(Ri, qs, m, h->UL[i], m, Qs, m, T + toff[s], Ri, 1.0, 0.0);
-        if (a > 0) t2.add(a, qs, m, h->ua(i, k), m, Qs, m, Ta + taoff[s], a, 1.0, 0.0);
-        if (Rk > 0) {
-          for (int j = 0; j < k; ++j) {
-            const int rkj = h->lr(k, j);
-            if (rkj == 0) continue;
-            const int rij = h->lr(i, j);
-            hb.add(rkj, qs, rij, gptr(i, j), rij, T + toff[s] + (rij > 0 ? h->lo(i, j) : 0),
-                   std::max(Ri, 1), H + boff[s] * Rk + h->lo(k, j), Rk, 1.0, 0.0);
-          }
-        }
-        b1.add(m, qs, a, h->va(i, k), m, Ta + taoff[s], std::max(a, 1), Ball + boff[s] * m, m, 1.0,
-               0.0);
-      }
-      if (Rk > 0 && sq > 0) b2.add(m, (int)sq, Rk, h->UL[k], m, H, Rk, Ball, m, -1.0, 1.0);
-      // t1 and t2 stream the same basis blocks Q_i: one batch
-      for (const GemmDesc& d : t2.d) t1.d.push_back(d);
-      t1.flops += t2.flops;
-      plan.gemm(t1);
-      plan.gemm(hb);
-      plan.gemm(b1);
-      plan.gemm(b2);
-    }
-    // ---------------------------------------------- batchTrsm (+ batchIDMult)
-    // V = L_kk^{-1} B for every tile of the column: one triangular product
-    {
-      hipStream_t st = h->stream;
-      hipEvent_t ej = h->ev_join;
-      plan.launch([=]() { return hipStreamWaitEvent(st, ej, 0); });
-      GemmBatch tb(false, false);
-      tb.add(m, (int)sq, m, h->invL(k), m, Ball, m, Bt, m, 1.0, 0.0, GEMM_TRIL_A);
-      plan.gemm(tb);
-      if (ldl && sq > 0) {
-        const double* dk = h->Dv + (size_t)k * m;
-        const int n = (int)sq;
-        plan.launch([=]() { return launch_scale_rows(Bt, m, Bt, m, dk, m, n, true, st); });
-      }
-    }
-    flops += (double)m * m * sq;
-    // ---------------------------------------------- updateTiles
-    {
-      std::vector<CopyDesc> cd;
-      int maxc = 0;
-      for (int s = 0; s < nrow; ++s) {
-        const int i = k + 1 + s, qs = q[s];
-        if (qs == 0) continue;
-        CopyDesc c{slots.qb(s), h->UL[i] + (size_t)h->R[i] * m, m, qs, m, m};
-        if (h->mixed) {
-          c.dst32 = h->UL32[i] + (size_t)h->R[i] * m;
-          c.ldd32 = m;
-        }
-        cd.push_back(c);
-        cd.push_back(CopyDesc{Bt + boff[s] * m, h->VL[i] + (size_t)h->R[i] * m, m, qs, m, m});
-        maxc = std::max(maxc, qs);
-      }
-      if (!cd.empty()) {
-        const size_t off = plan.stage(cd.data(), sizeof(CopyDesc) * cd.size());
-        const int n = (int)cd.size();
-        hipStream_t st = h->stream;
-        plan.launch(off, [=](const char* p) {
-          return launch_copy_batched((const CopyDesc*)p, n, maxc, st);
-        });
-      }
-    }
-    if (h->mixed) {
-      // ||L_ik||_F = ||V_ik||_F (U_ik orthonormal), read back with the next
-      // column's first synchronisation
-      TLR_TRY(w.fro.ensure(h->mem, sizeof(double) * (size_t)std::max(nrow, 1)));
-      double* fro = w.fro.as<double>();
-      std::vector<NormDesc> nd;
-      for (int s = 0; s < nrow; ++s)
-        nd.push_back(NormDesc{Bt + boff[s] * m, m, q[s], m, fro + s});
-      const size_t off = plan.stage(nd.data(), sizeof(NormDesc) * nd.size());
-      const int n = nrow;
-      hipStream_t st = h->stream;
-      double* pn = pin_norm;
-      plan.launch(off, [=](const char* p) { return launch_fro_norms((const NormDesc*)p, n, st); });
-      plan.launch([=]() {
-        return hipMemcpyAsync(pn, fro, sizeof(double) * n, hipMemcpyDeviceToHost, st);
-      });
-    }
-    TLR_TRY(plan.run());
-    flops += plan.flops;
-    for (int s = 0; s < nrow; ++s) {
-      const int i = k + 1 + s;
-      h->l_rank[(size_t)i * nb + k] = q[s];
-      h->l_off[(size_t)i * nb + k] = h->R[i];
-      h->R[i] += q[s];
-      // operation count of the paper's formulation (four-product sampling of
-      // Eq. (2) per iteration, the same for the projection, orthogonalisation,
-      // triangular solve)
-      const double ext = (double)h->R[i] - q[s] + Rk + h->ar(i, k);
-      const double cols = res.iters[s] > 0 ? cfg.bs + (res.iters[s] - 1.0) * cfg.bs_at(1) : 0.0;
-      flops_paper += cols * 4.0 * m * ext + 4.0 * m * q[s] * ext +
-                     res.flops_paper_orth[s] + (double)m * m * q[s];
-      bytes_alg += res.iters[s] * 8.0 * m * ((double)h->R[i] - q[s] + h->ar(i, k));
-      tile_iters += res.iters[s];
+    if (Rk > 0 && sq > 0) b2.add(m, (int)sq, Rk, h->UL[k], m, H, Rk, Ball, m, -1.0, 1.0);
+    // t1 and t2 stream the same basis blocks Q_i: one batch
+    for (const GemmDesc& d : t2.d) t1.d.push_back(d);
+    t1.flops += t2.flops;
+    plan.gemm(t1);
+    plan.gemm(hb);
+    plan.gemm(b1);
+    plan.gemm(b2);
+  }
+  // ---------------------------------------------- batchTrsm (+ batchIDMult)
+  // V = L_kk^{-1} B for every tile of the column: one triangular product
+  {
+    hipStream_t st = h->stream;
+    hipEvent_t ej = h->ev_join;
+    plan.launch([=]() { return hipStreamWaitEvent(st, ej, 0); });
+    GemmBatch tb(false, false);
+    tb.add(m, (int)sq, m, h->invL(k), m, Ball, m, Bt, m, 1.0, 0.0, GEMM_TRIL_A);
+    plan.gemm(tb);
+    if (ldl && sq > 0) {
+      const double* dk = h->Dv + (size_t)k * m;
+      const int n = (int)sq;
+      plan.launch([=]() { return launch_scale_rows(Bt, m, Bt, m, dk, m, n, true, st); });
     }
   }
-  TLR_HIP(hipEventRecord(h->ev_join, h->side));
-  TLR_HIP(hipStreamWaitEvent(h->stream, h->ev_join, 0));
-  TLR_TRY(h->sync());
+  p.flops += (double)m * m * sq;
+  // ---------------------------------------------- updateTiles
+  {
+    std::vector<CopyDesc> cd;
+    int maxc = 0;
+    for (int s = 0; s < nrow; ++s) {
+      const int i = k + 1 + s, qs = q[s];
+      if (qs == 0) continue;
+      CopyDesc c{slots.qb(p.base + s), h->UL[i] + (size_t)h->R[i] * m, m, qs, m, m};
+      if (h->mixed) {
+        c.dst32 = h->UL32[i] + (size_t)h->R[i] * m;
+        c.ldd32 = m;
+      }
+      cd.push_back(c);
+      cd.push_back(CopyDesc{Bt + boff[s] * m, h->VL[i] + (size_t)h->R[i] * m, m, qs, m, m});
+      maxc = std::max(maxc, qs);
+    }
+    if (!cd.empty()) {
+      const size_t off = plan.stage(cd.data(), sizeof(CopyDesc) * cd.size());
+      const int n = (int)cd.size();
+      hipStream_t st = h->stream;
+      plan.launch(off, [=](const char* ptr) {
+        return launch_copy_batched((const CopyDesc*)ptr, n, maxc, st);
+      });
+    }
+  }
+  if (h->mixed) {
+    // ||L_ik||_F = ||V_ik||_F (U_ik orthonormal), read back with the next
+    // column's first synchronisation
+    TLR_TRY(w.fro.ensure(h->mem, sizeof(double) * (size_t)std::max(nrow, 1)));
+    double* fro = w.fro.as<double>();
+    std::vector<NormDesc> nd;
+    for (int s = 0; s < nrow; ++s)
+      nd.push_back(NormDesc{Bt + boff[s] * m, m, q[s], m, fro + s});
+    const size_t off = plan.stage(nd.data(), sizeof(NormDesc) * nd.size());
+    const int n = nrow;
+    hipStream_t st = h->stream;
+    double* pn = p.pin_norm;
+    plan.launch(off, [=](const char* ptr) { return launch_fro_norms((const NormDesc*)ptr, n, st); });
+    plan.launch([=]() {
+      return hipMemcpyAsync(pn, fro, sizeof(double) * n, hipMemcpyDeviceToHost, st);
+    });
+  }
+  TLR_TRY(plan.run());
+  p.flops += plan.flops;
+  for (int s = 0; s < nrow; ++s) {
+    const int i = k + 1 + s;
+    h->l_rank[(size_t)i * nb + k] = q[s];
+    h->l_off[(size_t)i * nb + k] = h->R[i];
+    h->R[i] += q[s];
+    // operation count of the paper's formulation (four-product sampling of
+    // Eq. (2) per iteration, the same for the projection, orthogonalisation,
+    // triangular solve)
+    const double ext = (double)h->R[i] - q[s] + Rk + h->ar(i, k);
+    const double cols = it[s] > 0 ? cfg.bs + (it[s] - 1.0) * cfg.bs_at(1) : 0.0;
+    p.flops_paper += cols * 4.0 * m * ext + 4.0 * m * q[s] * ext +
+                     res.flops_paper_orth[p.base + s] + (double)m * m * q[s];
+    p.bytes_alg += it[s] * 8.0 * m * ((double)h->R[i] - q[s] + h->ar(i, k));
+    p.tile_iters += it[s];
+  }
+  return TLR_OK;
+}
+
+// Statistics and status of a finished problem.
+tlr_status prob_finish(Prob& p, const tlr_opts& o, bool ldl, tlr_stats* st) {
+  Handle* h = p.h;
+  const int m = h->m, nb = h->nb;
   double samp_ms = 0.0;
-  for (auto& ev : events) {
+  for (auto& ev : p.events) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) samp_ms += ms;
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
   }
+  const long long nev = (long long)p.events.size();
+  p.events.clear();
   int info = 0;
   TLR_HIP(hipMemcpy(&info, h->d_info, sizeof(int), hipMemcpyDeviceToHost));
   if (st) {
     std::memset(st, 0, sizeof *st);
     st->info = info;
-    st->tau = tau;
+    st->tau = p.tau;
     st->norm_a = o.eps_mode == TLR_EPS_REL ? h->norm_a : 0.0;
-    st->flops = flops;
-    st->flops_paper = flops_paper;
-    st->bytes_alg = bytes_alg;
-    st->ara_iters = ara_iters;
-    st->tile_iters = tile_iters;
-    st->fp32_tile_iters = fp32_tile_iters;
+    st->flops = p.flops;
+    st->flops_paper = p.flops_paper;
+    st->bytes_alg = p.bytes_alg;
+    st->ara_iters = p.ara_iters;
+    st->tile_iters = p.tile_iters;
+    st->fp32_tile_iters = p.fp32_tile_iters;
     long long cnt = 0, tot = 0, full = 0;
     int mx = 0;
     for (int i = 0; i < nb; ++i)
@@ -558,10 +581,10 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
     st->mean_rank = cnt ? (double)tot / cnt : 0.0;
     st->full_rank_tiles = full;
     st->factor_bytes = 8.0 * ((double)nb * m * m + 2.0 * m * (double)tot);
-    st->sample_launches = (long long)events.size();
+    st->sample_launches = nev;
     st->sample_ms = samp_ms;
-    st->sample_bytes = samp_bytes;
-    st->sample_flops = samp_flops;
+    st->sample_bytes = p.samp_bytes;
+    st->sample_flops = p.samp_flops;
   }
   if (info != 0) {
     h->factored = 0;
@@ -571,6 +594,164 @@ tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bo
   }
   h->factored = ldl ? 2 : 1;
   return TLR_OK;
+}
+
+// Problems of one tile size, stepped through the columns together: at step
+// k every problem with more than k block columns does its column k, and the
+// ARA of all their Schur-complement tiles is one pooled run (the union of
+// the active tiles of every problem in each launch).  Everything runs on
+// the first problem's (shared) main stream; each problem keeps its own
+// diagonal-tile stream.
+tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o, bool ldl,
+                           tlr_stats* stats, const std::vector<int>& idx) {
+  Handle* lead = ps[idx[0]].h;
+  const int m = lead->m, bs = o.bs;
+  int nbmax = 0, slots_max = 1;
+  for (int pi : idx) {
+    TLR_TRY(prob_init(ps[pi], eps, o, ldl));
+    nbmax = std::max(nbmax, ps[pi].h->nb);
+  }
+  for (int k = 0; k < nbmax; ++k) {
+    int tot = 0;
+    for (int pi : idx)
+      if (k < ps[pi].h->nb) tot += ps[pi].h->nb - k - 1;
+    slots_max = std::max(slots_max, tot);
+  }
+  AraConfig cfg;
+  cfg.m = m;
+  cfg.bs = bs;
+  cfg.bs_tail = o.bs_tail;
+  cfg.qcap = m;
+  cfg.tau = ps[idx[0]].tau;
+  cfg.r_min = o.r_min;
+  cfg.s_max = o.max_active;
+  cfg.seed = o.seed;
+  AraSlots slots;
+  TLR_TRY(ara_slots(lead, cfg, slots_max, &slots));
+  const bool timing = (o.flags & TLR_FLAG_KERNEL_TIMING) != 0;
+  const bool single = idx.size() == 1;
+
+  for (int k = 0; k < nbmax; ++k) {
+    std::vector<int> live;
+    for (int pi : idx)
+      if (!ps[pi].done && k < ps[pi].h->nb) live.push_back(pi);
+    if (live.empty()) break;
+    // ---- G, diagonal-tile stream, device sortRanks of every problem
+    int base = 0;
+    for (int pi : live) {
+      Prob& p = ps[pi];
+      p.base = base;
+      TLR_TRY(col_begin(p, k, ldl, slots.waiting + base));
+      base += p.nrow;
+    }
+    const int total = base;
+    // one synchronisation for every problem's order (and norms)
+    TLR_TRY(lead->sync_main());
+    std::vector<int> order;
+    {
+      // pooled sortRanks: descending input rank; ties by problem, then by
+      // each problem's own order (one problem: its device order unchanged)
+      std::vector<std::pair<int, int>> key;   // (rank, global slot)
+      for (int pi : live) {
+        Prob& p = ps[pi];
+        col_order(p, k);
+        for (int s : p.order) key.push_back({p.h->ar(k + 1 + s, k), p.base + s});
+      }
+      std::stable_sort(key.begin(), key.end(),
+                       [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+                         return a.first > b.first;
+                       });
+      for (auto& kv : key) order.push_back(kv.second);
+    }
+    for (int pi : live)
+      if (ps[pi].nrow == 0) {
+        TLR_TRY(side_done(ps[pi]));
+        ps[pi].done = true;
+      }
+    if (total == 0) continue;
+    // ---- pooled ARA of every problem's column-k tiles
+    const int bsm = cfg.bs_max();
+    AraSpec spec;
+    spec.slots.assign(total, AraSlotDesc{});
+    spec.samp_bytes.assign(total, 0.0);
+    spec.samp_bytes_col.assign(total, 0.0);
+    spec.samp_flops_col.assign(total, 0.0);
+    spec.tau.assign(total, 0.0);
+    int prow = 0;
+    for (int pi : live) {
+      Prob& p = ps[pi];
+      if (p.nrow == 0) continue;
+      p.roff = prow;
+      prow += p.Rk;
+    }
+    Work& lw = lead->ws;
+    TLR_TRY(lw.P.ensure(lead->mem, sizeof(double) * (size_t)std::max(prow, 1) * bsm));
+    spec.p = lw.P.as<double>();
+    spec.ldp = std::max(prow, 1);
+    spec.events = timing ? &ps[idx[0]].events : nullptr;
+    for (int pi : live) {
+      Prob& p = ps[pi];
+      if (p.nrow > 0) TLR_TRY(col_spec(p, k, bsm, spec));
+    }
+    AraResult res;
+    cfg.stream_id = (unsigned)k;
+    bool abort = false;
+    TLR_TRY(ara_run(lead, cfg, slots, order, spec, &res, single ? &abort : nullptr,
+                    [&]() -> tlr_status {
+                      for (int pi : live)
+                        if (ps[pi].dplan && ps[pi].dplan->pending())
+                          TLR_TRY(ps[pi].dplan->run_some(8));
+                      return TLR_OK;
+                    }));
+    for (int pi : live) TLR_TRY(side_done(ps[pi]));
+    if (abort) {
+      ps[idx[0]].done = true;
+      break;
+    }
+    for (int pi : live) {
+      Prob& p = ps[pi];
+      if (p.nrow == 0) continue;
+      TLR_TRY(col_finish(p, k, ldl, cfg, slots, res));
+    }
+  }
+  for (int pi : idx) {
+    Handle* h = ps[pi].h;
+    TLR_HIP(hipEventRecord(h->ev_join, h->side));
+    TLR_HIP(hipStreamWaitEvent(h->stream, h->ev_join, 0));
+  }
+  for (int pi : idx) TLR_TRY(ps[pi].h->sync());
+  tlr_status first = TLR_OK;
+  for (int pi : idx) {
+    const tlr_status s = prob_finish(ps[pi], o, ldl, stats ? stats + pi : nullptr);
+    if (first == TLR_OK && s != TLR_OK) first = s;
+  }
+  return first;
+}
+
+}  // namespace
+
+tlr_status factorize_batch(Handle* const* hs, int count, double eps, const tlr_opts& o,
+                           tlr_stats* st, bool ldl) {
+  std::vector<Prob> ps(count);
+  for (int i = 0; i < count; ++i) ps[i].h = hs[i];
+  // problems of one tile size run together (the ARA kernels take one m)
+  std::vector<int> ms;
+  for (int i = 0; i < count; ++i)
+    if (std::find(ms.begin(), ms.end(), hs[i]->m) == ms.end()) ms.push_back(hs[i]->m);
+  tlr_status first = TLR_OK;
+  for (int m : ms) {
+    std::vector<int> idx;
+    for (int i = 0; i < count; ++i)
+      if (hs[i]->m == m) idx.push_back(i);
+    const tlr_status s = factorize_group(ps, eps, o, ldl, st, idx);
+    if (s < 0 && s != TLR_ERR_NOT_SPD && s != TLR_ERR_ZERO_PIVOT) return s;
+    if (first == TLR_OK && s != TLR_OK) first = s;
+  }
+  return first;
+}
+
+tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bool ldl) {
+  return factorize_batch(&h, 1, eps, o, st, ldl);
 }
 
 }  // namespace tlr

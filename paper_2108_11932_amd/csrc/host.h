@@ -269,6 +269,11 @@ hipError_t launch_pivot_tol(const double* A, int lda, int m, double* tol, hipStr
 struct AraProblem;
 
 tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bool ldl);
+// count problems at once (st: count entries or NULL); problems of one tile
+// size step through their columns together with pooled ARA launches.  All
+// handles must use the same main stream.
+tlr_status factorize_batch(Handle* const* hs, int count, double eps, const tlr_opts& o,
+                           tlr_stats* st, bool ldl);
 tlr_status compress(Handle* h, const double* A, long long lda, const double* pts, int dim,
                     int kernel, double ell, double diag_add, double eps, const tlr_opts& o);
 tlr_status estimate_norm(Handle* h, double* out);

@@ -135,6 +135,7 @@ struct AraSlotDesc {
   // Z = -[G_ij P_j]_j (R x bs, ld R) over the tiles [zseg, zseg + nz)
   int zseg, nz, R;
   double* z;
+  double tau2;            // squared absolute threshold of this tile
   // workspace
   double* y;              // m x bs
   double* q;              // m x (qcap + bs) basis
@@ -142,6 +143,13 @@ struct AraSlotDesc {
   double* part1;          // Gram partials of Y per 16-row strip: nstrip x bs x bs x 2
   double* part2;          // Gram partials of the new columns X
   int* piv;               // pivots, then the accepted count at [bs]
+};
+// One 32-row tile of a product P_g = U_g^T Omega (U_g m x M, ld m) stored at
+// C (leading dimension ldp) from row row0: the P of one problem of a batch.
+struct PTile {
+  const double* A;
+  double* C;
+  int M, row0;
 };
 // One 16-row piece of a block of Z:
 // Z(zrow + r, :) = -G(r, 0 : cols) P(prow : prow + cols, :), r < rows <= 16,
@@ -165,15 +173,16 @@ struct AraDev {
 // Block sizes the orthogonalisation kernels are built for (1, 2, 4, 8, 16,
 // 24, 32).
 bool orth_block_supported(int bs);
-// mode 0: P = Uk^T Omega (P: rk x bs, ld rk, p_tiles tiles of 32 rows) and
-//         W^A = V^A^T Omega per active slot (tps tiles per slot);
+// mode 0: the P tiles (P_g = U_g^T Omega, one group of tiles per problem,
+//         all stored with leading dimension ldp) and W^A = V^A^T Omega per
+//         active slot (tps tiles per slot);
 // mode 1: C = -Q^T Y; mode 2: C = -Q^T X, X = Q(:, q : q + bs) (tps tiles).
 // K is split over workgroups whose partial tiles go to scratch and are
 // summed by a second launch; ara_tn_scratch gives the doubles of scratch for
 // `tiles` output tiles (and returns the tile height).
 int ara_tn_scratch(int m, int bs, long long tiles, size_t* doubles);
-hipError_t launch_ara_tn(const AraDev& D, int mode, const double* omega, const double* uk, int rk,
-                         double* P, int p_tiles, int count_bound, int tps, double* scratch,
+hipError_t launch_ara_tn(const AraDev& D, int mode, const double* omega, const PTile* ptiles,
+                         int p_tiles, int ldp, int count_bound, int tps, double* scratch,
                          hipStream_t s);
 // Z of every active slot (bps blocks of four Z pieces per slot).
 hipError_t launch_ara_z(const AraDev& D, const ZSeg* segs, const double* P, int ldp,
@@ -188,8 +197,8 @@ hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_
 // directions of Y to Q, sets qnew, flag, pivots, iteration counters and the
 // Gram partials of the new columns) or pass 2 (re-orthonormalises the new
 // columns in place).
-hipError_t launch_orth_step(const AraDev& D, int pass, double tau2, int r_min, int count_bound,
-                            hipStream_t s);
+// The threshold of each tile is its slot's tau2.
+hipError_t launch_orth_step(const AraDev& D, int pass, int r_min, int count_bound, hipStream_t s);
 // Commit the basis widths, compact the active list and refill it (see
 // launch_compact), and record the status word and the largest active width;
 // counts[0..3] are also stored to host_out (pinned host memory) when given.
