@@ -194,6 +194,25 @@ tlr_status tlr_potrf(tlr_matrix_t A, double eps, const tlr_opts* opts, tlr_stats
 tlr_status tlr_ldlt(tlr_matrix_t A, double eps, const tlr_opts* opts, double* D, tlr_stats* stats,
                     void* stream);
 
+/* Batched form of tlr_potrf (ldl = 0) and tlr_ldlt (ldl != 0) over count
+ * independent matrices (dynamic batching across problems, Section 4.2; the
+ * batching of many factorizations the conclusions, Section 7, propose).
+ * Matrices of one tile size step through their block columns together: at
+ * step k every matrix with more than k block columns does its column k, and
+ * the ARA of all their Schur-complement tiles is one pooled set of launches
+ * over the union of the active tiles, ordered by input rank (sortRanks over
+ * the union); matrices of different tile sizes form separate groups.  Each
+ * tile keeps its own matrix's threshold (eps, or eps ||A|| in relative
+ * mode).  Every matrix is set to `stream`; each keeps its own diagonal-tile
+ * stream.  A: count distinct handles.  D: NULL, or count device pointers
+ * (N_i doubles each, NULL entries allowed) that receive the LDL^T pivots.
+ * stats: NULL or count entries; stats[i].info is the failing row of matrix
+ * i.  Returns TLR_OK, or the first failure (TLR_ERR_NOT_SPD /
+ * TLR_ERR_ZERO_PIVOT leave the other matrices' factors usable). */
+tlr_status tlr_factor_batched(int count, tlr_matrix_t* A, int ldl, double eps,
+                              const tlr_opts* opts, double* const* D, tlr_stats* stats,
+                              void* stream);
+
 /* B <- (L L^T)^{-1} B or (L D L^T)^{-1} B with the factor held by the handle
  * (Algorithm "TLR Triangular Solve" and its transpose).  B is N x nrhs,
  * device memory, leading dimension ldb >= N.  TLR_ERR_STATE if the handle

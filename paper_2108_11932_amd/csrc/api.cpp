@@ -256,6 +256,35 @@ tlr_status tlr_ldlt(tlr_matrix_t A, double eps, const tlr_opts* opts, double* D,
   return factor_entry(A, eps, opts, stats, true, D);
 }
 
+tlr_status tlr_factor_batched(int count, tlr_matrix_t* A, int ldl, double eps,
+                              const tlr_opts* opts, double* const* D, tlr_stats* stats,
+                              void* stream) {
+  TLR_ARG(count > 0 && A, "empty batch");
+  TLR_ARG(eps > 0.0 && std::isfinite(eps), "eps must be positive");
+  for (int i = 0; i < count; ++i) {
+    TLR_ARG(A[i], "NULL handle in the batch");
+    for (int j = 0; j < i; ++j) TLR_ARG(A[j] != A[i], "a handle appears twice in the batch");
+    TLR_ARG(A[i]->dev == A[0]->dev, "the batch spans several devices");
+  }
+  tlr_opts o;
+  TLR_TRY(check_opts(opts, &o));
+  if (stats) std::memset(stats, 0, sizeof(tlr_stats) * count);
+  for (int i = 0; i < count; ++i) A[i]->stream = A[i]->mem.stream = (hipStream_t)stream;
+  tlr_status st = factorize_batch(A, count, eps, o, stats, ldl != 0);
+  if (ldl && D)
+    for (int i = 0; i < count; ++i)
+      if (D[i] && A[i]->factored == 2)
+        TLR_HIP(hipMemcpyAsync(D[i], A[i]->Dv, sizeof(double) * A[i]->N, hipMemcpyDeviceToDevice,
+                               A[i]->stream));
+  if (ldl && D) {
+    const tlr_status s2 = A[0]->sync();
+    if (st == TLR_OK) st = s2;
+  }
+  if (st < 0 && st != TLR_ERR_NOT_SPD && st != TLR_ERR_ZERO_PIVOT && st != TLR_ERR_ARG)
+    for (int i = 0; i < count; ++i) A[i]->factored = 0;
+  return st;
+}
+
 tlr_status tlr_solve(tlr_matrix_t A, int nrhs, double* B, long long ldb, void* stream) {
   TLR_ARG(A && B, "NULL argument");
   TLR_ARG(nrhs >= 0, "nrhs must be non-negative");

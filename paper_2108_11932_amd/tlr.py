@@ -98,6 +98,8 @@ SIGNATURES = {
                                  ctypes.POINTER(Allocator), _P, ctypes.POINTER(_P)]),
     "tlr_potrf": (_I, [_P, _D, ctypes.POINTER(Opts), ctypes.POINTER(Stats), _P]),
     "tlr_ldlt": (_I, [_P, _D, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P]),
+    "tlr_factor_batched": (_I, [_I, ctypes.POINTER(_P), _I, _D, ctypes.POINTER(Opts),
+                                ctypes.POINTER(_P), ctypes.POINTER(Stats), _P]),
     "tlr_solve": (_I, [_P, _I, _P, _LL, _P]),
     "tlr_matvec": (_I, [_P, _I, _P, _LL, _P, _LL, _P]),
     "tlr_get_info": (_I, [_P, _LLP, _IP, _IP, _IP]),
@@ -396,6 +398,23 @@ class TLRMatrix:
             self.close()
         except Exception:
             pass
+
+
+def factor_batched(mats, eps: float, o: Optional[Opts] = None, ldl: bool = False):
+    """tlr_factor_batched over a list of TLRMatrix: returns (status, list of
+    stats dicts, list of pivot tensors (LDL^T) or None)."""
+    torch = _torch()
+    n = len(mats)
+    hs = (_P * n)(*[mt.h for mt in mats])
+    sts = (Stats * n)()
+    dl = None
+    darr = None
+    if ldl:
+        dl = [torch.empty(mt.n, dtype=torch.float64, device="cuda") for mt in mats]
+        darr = (_P * n)(*[ctypes.c_void_p(d.data_ptr()) for d in dl])
+    s = lib().tlr_factor_batched(n, hs, int(ldl), eps, ctypes.byref(o or opts()), darr, sts,
+                                 _stream())
+    return s, [st.as_dict() for st in sts], dl
 
 
 def _to_colmajor(b):
