@@ -132,6 +132,51 @@ def time_form(mat, w, eps_mode, precision, tlr, torch, steps, warmup, bs_tail=0)
     return (time.perf_counter() - t0) / steps, stats
 
 
+def batched_form(tlr, torch, wl, count: int, m: int):
+    """The batched workload (count independent 2D problems of uneven N,
+    relative eps 1e-6): one tlr_factor_batched call over all of them (FP64
+    and FP32-sampling) against the same problems factored one by one."""
+    ws = wl.batched_2d(count=count, m=m)
+    mats = []
+    for w in ws:
+        mats.append(tlr.TLRMatrix.compress_kernel(w.points, w.kernel, w.ell, w.diag_add, w.m, w.eps,
+                                                  tlr.opts(bs=w.bs, eps_mode=w.eps_mode)))
+    o64 = tlr.opts(bs=ws[0].bs, eps_mode=tlr.EPS_REL, precision=tlr.FP64)
+    o32 = tlr.opts(bs=ws[0].bs, eps_mode=tlr.EPS_REL, precision=tlr.MIXED_FP32)
+
+    def timed(f):
+        f()   # warm-up (workspaces, code objects)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = f()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    def seq():
+        return [mt.potrf(ws[0].eps, o64) for mt in mats]
+
+    def bat(o):
+        def run():
+            s, sts, _ = tlr.factor_batched(mats, ws[0].eps, o)
+            if s != 0:
+                raise RuntimeError("batched factorization failed: %d" % s)
+            return sts
+        return run
+
+    t_seq, _ = timed(seq)
+    t_b64, st_b64 = timed(bat(o64))
+    t_b32, st_b32 = timed(bat(o32))
+    flops = sum(x["flops"] for x in st_b64)
+    ns = [w.n for w in ws]
+    for mt in mats:
+        mt.close()
+    return {"count": count, "tile": m, "N_min": min(ns), "N_max": max(ns), "N_total": sum(ns),
+            "eps": ws[0].eps, "eps_mode": "relative",
+            "sequential_fp64_s": t_seq, "batched_fp64_s": t_b64, "batched_mixed_fp32_s": t_b32,
+            "speedup_fp64": t_seq / t_b64, "speedup_mixed": t_seq / t_b32,
+            "batched_fp64_tflops": flops / t_b64 / 1e12}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +190,8 @@ def main():
                     help="points of the leading block the CPU oracle factors (0 = skip)")
     ap.add_argument("--no-forms", dest="forms", action="store_false",
                     help="skip the relative-threshold FP64 / mixed-precision comparison")
+    ap.add_argument("--batched", type=int, default=96,
+                    help="problems of the batched workload timed after the main line (0 = skip)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM "
                          "byte counters against a kernel of known traffic)")
@@ -241,6 +288,13 @@ def main():
                      "avg_launch_us": smp_ms * 1e3 / max(1, smp_n)},
     }
     mat.close()
+    if a.batched > 0:
+        print("[bench] batched workload: %d problems" % a.batched, file=sys.stderr, flush=True)
+        line["batched"] = batched_form(tlr, torch, wl, a.batched, 512)
+        b = line["batched"]
+        print("[bench] batched: sequential %.3fs, batched fp64 %.3fs (x%.2f), mixed %.3fs (x%.2f)"
+              % (b["sequential_fp64_s"], b["batched_fp64_s"], b["speedup_fp64"],
+                 b["batched_mixed_fp32_s"], b["speedup_mixed"]), file=sys.stderr, flush=True)
     if a.cpu_sample > 0:
         print("[bench] CPU oracle on a %d-point sample" % a.cpu_sample, file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, min(a.cpu_sample, w.n), tlr, torch)
