@@ -11,6 +11,7 @@
 //                       compaction + refill of the active subset
 //  * sortRanks       -- order of the tiles of a column by input rank
 #include "dd.h"
+#include "mfma_tiles.h"
 #include "tlr_internal.h"
 
 // The double-double arithmetic below relies on error-free transformations
@@ -104,7 +105,7 @@ __device__ inline void strip_grams(const double* X, int ldx, int nstrips, int nc
     double sh = 0.0, sl = 0.0;
     for (int r = 0; r < 16; ++r) dot2_step(X[16 * st + r + a * ldx], X[16 * st + r + b * ldx], sh, sl);
     const dd v = fast_two_sum(sh, sl);
-    double* o = part + (size_t)st * bs * bs * 2 + (a + b * bs) * 2;
+    gdouble* o = gmem(part) + (size_t)st * bs * bs * 2 + (a + b * bs) * 2;
     o[0] = v.hi;
     o[1] = v.lo;
   }
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, int r_min) {
     dd acc{0.0, 0.0};
     if (g < NG && b < nc && x < nc) {
       const int lo = min(x, b), hi = max(x, b);
-      const double* pp = part + (size_t)(lo + hi * BS) * 2;
+      const gdouble* pp = gmem(part) + (size_t)(lo + hi * BS) * 2;
       // compensated summation (Sum2 of Ogita, Rump and Oishi): the running
       // sum is the only dependency chain, the rounding errors and the low
       // parts are gathered beside it
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, int r_min) {
         double ph[PCH], pl[PCH];
 #pragma unroll
         for (int u = 0; u < PCH; ++u) {
-          const double* q2 = pp + (size_t)min(rb0 + u, nrb - 1) * BS * BS * 2;
+          const gdouble* q2 = pp + (size_t)min(rb0 + u, nrb - 1) * BS * BS * 2;
           ph[u] = q2[0];
           pl[u] = q2[1];
         }
@@ -330,7 +331,8 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, int r_min) {
   // (pass 2, in place), by forward substitution along the row
   const int r = blockIdx.x * APPLY_ROWS + t;
   if (np == 0) return;
-  double* dst = d.q + (size_t)qold * m;
+  gdouble* dst = gmem(d.q) + (size_t)qold * m;
+  const gdouble* ysrc = gmem(d.y);
   double xv[BS], rd[BS];
 #pragma unroll
   for (int a = 0; a < BS; ++a) {
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, int r_min) {
   if (r < m) {
 #pragma unroll
     for (int a = 0; a < BS; ++a)
-      if (a < np) xv[a] = PIV ? d.y[r + (size_t)perm[a] * m] : dst[r + (size_t)a * m];
+      if (a < np) xv[a] = PIV ? ysrc[r + (size_t)perm[a] * m] : dst[r + (size_t)a * m];
 #pragma unroll
     for (int c = 0; c < BS; ++c) {
       if (c < np) {

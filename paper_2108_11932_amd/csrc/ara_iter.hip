@@ -102,13 +102,13 @@ __global__ __launch_bounds__(256) void k_ara_tn_sum(AraDev D, int mode, const do
     for (int s0 = 0; s0 < ks_n; s0 += CH) {
       double pv[CH];
 #pragma unroll
-      for (int u = 0; u < CH; ++u) pv[u] = part[(size_t)min(s0 + u, ks_n - 1) * TSZ + e];
+      for (int u = 0; u < CH; ++u) pv[u] = gmem(part)[(size_t)min(s0 + u, ks_n - 1) * TSZ + e];
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < CH; ++u)
         if (s0 + u < ks_n) v += pv[u];
     }
-    o.C[o.row0 + lr + (size_t)lc * o.ldc] = o.alpha * v;
+    gmem(o.C)[o.row0 + lr + (size_t)lc * o.ldc] = o.alpha * v;
   }
 }
 
@@ -129,9 +129,9 @@ __global__ __launch_bounds__(256) void k_ara_z(AraDev D, const ZSeg* __restrict_
   const ZSeg z = segs[d.zseg + pi];
   const int bs = D.bs;
   const int li = lane & 15, kq = lane >> 4;
-  const double* grow = z.g + min(li, z.rows - 1);
+  const gdouble* grow = gmem(z.g) + min(li, z.rows - 1);
   for (int n0 = 0; n0 < bs; n0 += 16) {
-    const double* pcol = P + z.prow + (size_t)min(n0 + li, bs - 1) * ldp;
+    const gdouble* pcol = gmem(P) + z.prow + (size_t)min(n0 + li, bs - 1) * ldp;
     d4 acc = d4{0.0, 0.0, 0.0, 0.0};
     for (int t0 = 0; t0 < z.cols; t0 += 4 * ZCH) {
       double av[ZCH], bv[ZCH];
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_ara_z(AraDev D, const ZSeg* __restrict_
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = kq + 4 * r, col = n0 + li;
-      if (row < z.rows && col < bs) d.z[z.zrow + row + (size_t)col * d.R] = -acc[r];
+      if (row < z.rows && col < bs) gmem(d.z)[z.zrow + row + (size_t)col * d.R] = -acc[r];
     }
   }
 }
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_ara_seg(AraDev D) {
   }
   // Gram partials of the strip (Dot2 over its 16 rows), pairs a <= b
   const int npairs = bs * (bs + 1) / 2;
-  double* out = part + (size_t)strip * bs * bs * 2;
+  gdouble* out = gmem(part) + (size_t)strip * bs * bs * 2;
   for (int pr = threadIdx.x; pr < npairs; pr += 256) {
     int b = (int)((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
     while (b * (b + 1) / 2 > pr) --b;

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
       const int gr = row0 + ar[j], gk = k0 + ak[j];
       double v = 0.0;
       if (gr < d.M && gk < d.K)
-        v = TA ? d.A[gk + (size_t)gr * d.lda] : d.A[gr + (size_t)gk * d.lda];
+        v = TA ? gmem(d.A)[gk + (size_t)gr * d.lda] : gmem(d.A)[gr + (size_t)gk * d.lda];
       ra[j] = v;
     }
 #pragma unroll
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
       const int gc = col0 + bc[j], gk = k0 + bk[j];
       double v = 0.0;
       if (gc < d.N && gk < d.K)
-        v = TB ? d.B[gc + (size_t)gk * d.ldb] : d.B[gk + (size_t)gc * d.ldb];
+        v = TB ? gmem(d.B)[gc + (size_t)gk * d.ldb] : gmem(d.B)[gk + (size_t)gc * d.ldb];
       rb[j] = v;
     }
   };
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
       for (int r = 0; r < 4; ++r) {
         const int gr = row0 + wr0 + a * 16 + lk + 4 * r;
         if (gr >= d.M) continue;
-        double* cp = d.C + gr + (size_t)gc * d.ldc;
+        gdouble* cp = gmem(d.C) + gr + (size_t)gc * d.ldc;
         double v = d.alpha * acc[a][b][r];
         if (d.beta != 0.0) v += d.beta * *cp;
         *cp = v;

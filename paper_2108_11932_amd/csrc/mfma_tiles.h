@@ -12,6 +12,21 @@ namespace tlr {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// Global-memory views of the pointers the kernels find in descriptors: the
+// compiler cannot tell their address space and would emit flat accesses,
+// whose completion counter is the one LDS accesses use, so that every wait
+// for an LDS read would also wait for all outstanding memory loads.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) float gfloat;
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) dv2 gdv2;
+typedef __attribute__((address_space(1))) int gint;
+__device__ inline const gdouble* gmem(const double* p) { return (const gdouble*)p; }
+__device__ inline gdouble* gmem(double* p) { return (gdouble*)p; }
+__device__ inline const gfloat* gmem(const float* p) { return (const gfloat*)p; }
+__device__ inline gint* gmem(int* p) { return (gint*)p; }
+__device__ inline const gint* gmem(const int* p) { return (const gint*)p; }
+
 // C(row0 : row0 + 16 FM, col0 : col0 + 16 FN) = alpha A^T B + beta C with A
 // stored K x M and B stored K x N (column-major; the contraction runs down
 // their columns), over k in [kbeg, kend).  NW waves of the workgroup take
@@ -39,17 +54,17 @@ __device__ inline void tn_tile(const double* __restrict__ A, int lda, const doub
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const double* acol[FM];
-  const double* bcol[FN];
+  const gdouble* acol[FM];
+  const gdouble* bcol[FN];
 #pragma unroll
   for (int a = 0; a < FM; ++a) {
     const int i = row0 + a * 16 + li;
-    acol[a] = A + (size_t)(i < M ? i : 0) * lda;
+    acol[a] = gmem(A) + (size_t)(i < M ? i : 0) * lda;
   }
 #pragma unroll
   for (int b = 0; b < FN; ++b) {
     const int j = col0 + b * 16 + li;
-    bcol[b] = B + (size_t)(j < N ? j : 0) * ldb;
+    bcol[b] = gmem(B) + (size_t)(j < N ? j : 0) * ldb;
   }
   for (int k0 = kbeg + wave * 16; k0 < kend; k0 += 16 * NW * U) {
     double av[U][FM][4], bv[U][FN][4];
@@ -106,11 +121,11 @@ __device__ inline void tn_tile(const double* __restrict__ A, int lda, const doub
 #pragma unroll
     for (int w = 1; w < NW; ++w) v += red[w][slot][l];
     if (LOCAL) {
-      C[lr + lc * 16 * FM] = v;
+      gmem(C)[lr + lc * 16 * FM] = v;
       continue;
     }
     if (gr >= M || gc >= N) continue;
-    double* cp = C + gr + (size_t)gc * ldc;
+    gdouble* cp = gmem(C) + gr + (size_t)gc * ldc;
     double out = alpha * v;
     if (beta != 0.0) out += beta * *cp;
     *cp = out;
@@ -145,11 +160,11 @@ __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, i
     const int K = sg ? K1 : K0;
     if (K <= 0) continue;
     const bool f32 = A1F32 && sg == 1;
-    const double* __restrict__ A = (sg ? (const double*)A1v : A0) + (rok ? row : 0);
-    const float* __restrict__ Af = (const float*)A1v + (rok ? row : 0);
-    const double* __restrict__ B = sg ? B1 : B0;
+    const gdouble* __restrict__ A = gmem(sg ? (const double*)A1v : A0) + (rok ? row : 0);
+    const gfloat* __restrict__ Af = gmem((const float*)A1v) + (rok ? row : 0);
+    const gdouble* __restrict__ B = gmem(sg ? B1 : B0);
     const size_t lda = sg ? lda1 : lda0, ldb = sg ? ldb1 : ldb0;
-    const double* bcol[NF];
+    const gdouble* bcol[NF];
 #pragma unroll
     for (int b = 0; b < NF; ++b) {
       const int c = b * 16 + li;
@@ -205,7 +220,7 @@ __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, i
     const int c = b * 16 + (l & 15);
     double v = ((red[0][slot][l] + red[1][slot][l]) + red[2][slot][l]) + red[3][slot][l];
     if (r0 + rr < M && c < N) {
-      double* cp = C + (r0 + rr) + (size_t)c * ldc;
+      gdouble* cp = gmem(C) + (r0 + rr) + (size_t)c * ldc;
       if (beta != 0.0) v += beta * *cp;
       *cp = v;
     } else {
@@ -256,12 +271,14 @@ __device__ inline void tn_lds_tile(const double* __restrict__ A, int lda,
 #pragma unroll
     for (int u = 0; u < AL; ++u) {
       const int c = min(row0 + lc + u * CPR, M - 1);
-      ra[u] = *(const double2*)(A + (size_t)c * lda + kk);
+      const dv2 v = *(const gdv2*)(gmem(A) + (size_t)c * lda + kk);
+      ra[u] = double2{v.x, v.y};
     }
 #pragma unroll
     for (int u = 0; u < BL; ++u) {
       const int c = min(col0 + lc + u * CPR, N - 1);
-      rb[u] = *(const double2*)(B + (size_t)c * ldb + kk);
+      const dv2 v = *(const gdv2*)(gmem(B) + (size_t)c * ldb + kk);
+      rb[u] = double2{v.x, v.y};
     }
   };
   auto store = [&](int k0) {
@@ -341,7 +358,7 @@ __device__ inline void tn_lds_tile(const double* __restrict__ A, int lda,
         for (int w = 0; w < 3; ++w) v += smem[(w * FM * FN * 4 + (a * FN + b) * 4 + r) * 64 + lane];
         const int gr = row0 + a * 16 + g + 4 * r, gc = col0 + b * 16 + li;
         if (gr < M && gc < N) {
-          double* cp = store_t ? C + gc + (size_t)gr * ldc : C + gr + (size_t)gc * ldc;
+          gdouble* cp = store_t ? gmem(C) + gc + (size_t)gr * ldc : gmem(C) + gr + (size_t)gc * ldc;
           double out = alpha * v;
           if (beta != 0.0) out += beta * *cp;
           *cp = out;
