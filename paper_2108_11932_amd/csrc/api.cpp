@@ -391,6 +391,7 @@ tlr_status tlr_get_pivots(tlr_matrix_t A, double* d) {
 
 tlr_status tlr_destroy(tlr_matrix_t A) {
   if (!A) return TLR_OK;
+  A->worker.reset();
   (void)hipStreamSynchronize(A->stream);
   free_factor(A);
   Mem& mem = A->mem;

@@ -128,6 +128,8 @@ struct Prob {
   int Rk = 0, nrow = 0, base = 0, roff = 0;
   double* G = nullptr;
   std::unique_ptr<Plan> dplan;
+  bool side_pending = false;   // the side worker holds this column's launches
+  bool host_order = false;     // this column's order was taken on the host
   std::vector<int> order;
   std::vector<char> use32;
   const double* gptr(int i, int j) const {
@@ -266,13 +268,36 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
     }
     TLR_TRY(dense_factor(h, dplan, !ldl, Lkk, m, m, ldl ? h->Dv + (size_t)k * m : nullptr, k * m,
                          h->invL(k)));
-    TLR_TRY(dplan.run_some(8));
+    // the staged descriptors go up from this thread; the launches are
+    // issued by the handle's side worker, which also records the join
+    TLR_TRY(dplan.run_some(0));
+    if (!h->worker) h->worker.reset(new SideWorker(h->dev));
+    std::shared_ptr<Plan> plan(p.dplan.release());
+    hipEvent_t ej = h->ev_join;
+    h->worker->submit([plan, ej, ds]() -> tlr_status {
+      TLR_TRY(plan->run());
+      TLR_HIP(hipEventRecord(ej, ds));
+      return TLR_OK;
+    });
+    p.side_pending = true;
   }
   p.flops_paper += 2.0 * m * (double)m * Rk + (double)m * m * m / 3.0;
   p.flops += (double)m * m * m / 3.0 + (double)m * m * m / 3.0;
   p.nrow = nb - k - 1;
-  // ---------------------------------------------- sortRanks (device)
-  if (p.nrow > 0) {
+  // ---------------------------------------------- sortRanks
+  // Without mixed precision nothing else of the previous column is needed
+  // on the host, so the order (descending input rank, ties by row) is taken
+  // here and the device queue is not drained; the mixed form sorts on the
+  // device and reads the order back with the previous column's V norms.
+  p.host_order = !h->mixed;
+  p.order.clear();
+  if (p.nrow > 0 && p.host_order) {
+    p.order.resize(p.nrow);
+    for (int s = 0; s < p.nrow; ++s) p.order[s] = s;
+    std::stable_sort(p.order.begin(), p.order.end(), [&](int a, int b) {
+      return h->ar(k + 1 + a, k) > h->ar(k + 1 + b, k);
+    });
+  } else if (p.nrow > 0) {
     const int nrow = p.nrow;
     std::vector<int> rk(nrow), rows(nrow);
     for (int s = 0; s < nrow; ++s) {
@@ -291,11 +316,9 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
 }
 
 tlr_status side_done(Prob& p) {
-  if (!p.dplan) return TLR_OK;
-  TLR_TRY(p.dplan->run());
-  TLR_HIP(hipEventRecord(p.h->ev_join, p.h->side));
-  p.dplan.reset();
-  return TLR_OK;
+  if (!p.side_pending) return TLR_OK;
+  p.side_pending = false;
+  return p.h->worker->wait();
 }
 
 // After the synchronisation that follows col_begin: the sorted order, the V
@@ -303,7 +326,7 @@ tlr_status side_done(Prob& p) {
 void col_order(Prob& p, int k) {
   Handle* h = p.h;
   const int nb = h->nb, nrow = p.nrow;
-  p.order.assign(p.pin_order, p.pin_order + nrow);
+  if (!p.host_order) p.order.assign(p.pin_order, p.pin_order + nrow);
   if (h->mixed && k > 0)
     for (int s = 0; s < nrow + 1; ++s) h->l_fro[(size_t)(k + s) * nb + (k - 1)] = p.pin_norm[s];
   p.use32.assign(nrow, 0);
@@ -645,8 +668,11 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
       base += p.nrow;
     }
     const int total = base;
-    // one synchronisation for every problem's order (and norms)
-    TLR_TRY(lead->sync_main());
+    // one synchronisation for the orders (and norms) read back from the
+    // device, if any problem needs them
+    bool need_sync = false;
+    for (int pi : live) need_sync = need_sync || (!ps[pi].host_order && ps[pi].nrow > 0);
+    if (need_sync) TLR_TRY(lead->sync_main());
     std::vector<int> order;
     {
       // pooled sortRanks: descending input rank; ties by problem, then by
@@ -696,13 +722,7 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
     AraResult res;
     cfg.stream_id = (unsigned)k;
     bool abort = false;
-    TLR_TRY(ara_run(lead, cfg, slots, order, spec, &res, single ? &abort : nullptr,
-                    [&]() -> tlr_status {
-                      for (int pi : live)
-                        if (ps[pi].dplan && ps[pi].dplan->pending())
-                          TLR_TRY(ps[pi].dplan->run_some(8));
-                      return TLR_OK;
-                    }));
+    TLR_TRY(ara_run(lead, cfg, slots, order, spec, &res, single ? &abort : nullptr));
     for (int pi : live) TLR_TRY(side_done(ps[pi]));
     if (abort) {
       ps[idx[0]].done = true;

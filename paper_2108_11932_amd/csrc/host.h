@@ -4,10 +4,15 @@
 
 #include <hip/hip_runtime.h>
 
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <functional>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/tlr.h"
@@ -157,6 +162,27 @@ struct Plan {
   const char* base = nullptr;
 };
 
+// A host thread that issues the launches of the diagonal-tile stream, so
+// that the thread driving the ARA iterations spends no time on them.  Tasks
+// run in submission order on device `dev`.
+class SideWorker {
+ public:
+  explicit SideWorker(int dev);
+  ~SideWorker();
+  void submit(std::function<tlr_status()> f);
+  // Until every submitted task has run; the first failure since the last wait.
+  tlr_status wait();
+
+ private:
+  void loop(int dev);
+  std::mutex mu_;
+  std::condition_variable cv_, idle_cv_;
+  std::deque<std::function<tlr_status()>> q_;
+  bool stop_ = false, busy_ = false;
+  tlr_status err_ = TLR_OK;
+  std::thread th_;
+};
+
 // Per-column workspace of the factorization.
 struct Work {
   DevBuf G, W, omega, P, Z, T, Ta, H, Ball, C, Wa, Y, Q, part, ints, orth, dscale, tol,
@@ -184,6 +210,7 @@ struct tlr_matrix_s {
   hipStream_t stream = nullptr;   // caller's stream: everything is ordered on it
   hipStream_t side = nullptr;     // library stream for the diagonal tiles (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  std::unique_ptr<tlr::SideWorker> worker;   // issues the side-stream launches
   Staging stage;
   int* pin_back = nullptr;        // pinned read-back area
   size_t pin_back_n = 0;

@@ -112,6 +112,55 @@ tlr_status Staging::upload(Handle* h, const void* data, size_t bytes, void** dpt
 
 }  // namespace tlr
 
+namespace tlr {
+
+SideWorker::SideWorker(int dev) : th_([this, dev]() { loop(dev); }) {}
+
+SideWorker::~SideWorker() {
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    stop_ = true;
+  }
+  cv_.notify_all();
+  th_.join();
+}
+
+void SideWorker::submit(std::function<tlr_status()> f) {
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    q_.push_back(std::move(f));
+  }
+  cv_.notify_one();
+}
+
+tlr_status SideWorker::wait() {
+  std::unique_lock<std::mutex> lk(mu_);
+  idle_cv_.wait(lk, [this]() { return q_.empty() && !busy_; });
+  const tlr_status e = err_;
+  err_ = TLR_OK;
+  return e;
+}
+
+void SideWorker::loop(int dev) {
+  (void)hipSetDevice(dev);
+  std::unique_lock<std::mutex> lk(mu_);
+  for (;;) {
+    cv_.wait(lk, [this]() { return stop_ || !q_.empty(); });
+    if (q_.empty()) return;   // stop requested and nothing left
+    std::function<tlr_status()> f = std::move(q_.front());
+    q_.pop_front();
+    busy_ = true;
+    lk.unlock();
+    const tlr_status e = f();
+    lk.lock();
+    busy_ = false;
+    if (err_ == TLR_OK && e != TLR_OK) err_ = e;
+    if (q_.empty()) idle_cv_.notify_all();
+  }
+}
+
+}  // namespace tlr
+
 tlr_status tlr_matrix_s::sync() {
   TLR_HIP(hipStreamSynchronize(stream));
   if (side) TLR_HIP(hipStreamSynchronize(side));
