@@ -254,7 +254,8 @@ def main():
     if a.forms:
         for name, mode, prec in (("fp64_rel", 1, tlr.FP64), ("mixed_fp32_rel", 1, tlr.MIXED_FP32),
                                  ("mixed_fp32_abs", 0, tlr.MIXED_FP32)):
-            fdt, fst = time_form(mat, w, mode, prec, tlr, torch, a.steps, a.warmup, a.bs_tail)
+            fdt, fst = time_form(mat, w, mode, prec, tlr, torch, a.steps, a.warmup, a.bs_tail,
+                                 False)
             s0 = fst[-1]
             forms[name] = {"ms_per_step": fdt * 1e3,
                            "tflops": float(np.mean([x["flops"] for x in fst])) / fdt / 1e12,
