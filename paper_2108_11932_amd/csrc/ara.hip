@@ -61,6 +61,27 @@ __global__ void k_randn(double* out, int rows, int cols, int ld, unsigned k0, un
   }
 }
 
+// The test matrices of iterations t0 .. t0 + nt - 1 (blockIdx.y = t - t0),
+// each rows x cols_t with cols_t = cols0 for t = 0 and cols1 after, the
+// same values as k_randn with that t; matrix t - t0 at out + (t - t0) * stride.
+__global__ void k_randn_iters(double* out, int rows, size_t stride, int cols0, int cols1,
+                              unsigned k0, unsigned k1, unsigned k, unsigned t0, unsigned strm) {
+  const unsigned t = t0 + blockIdx.y;
+  const int cols = t == 0 ? cols0 : cols1;
+  const long long n = (long long)rows * cols;
+  const long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (2 * c >= n) return;
+  const uint4 w = philox10(make_uint4((unsigned)c, t, k, strm), k0, k1);
+  const double u1 = 1.0 - u53(w.x, w.y);
+  const double u2 = u53(w.z, w.w);
+  const double rad = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincos(6.283185307179586476925286766559 * u2, &sn, &cs);
+  double* o = out + (size_t)blockIdx.y * stride;
+  o[2 * c] = rad * cs;
+  if (2 * c + 1 < n) o[2 * c + 1] = rad * sn;
+}
+
 __global__ void k_philox_raw(unsigned* out, int n, unsigned k0, unsigned k1, unsigned c1,
                              unsigned c2, unsigned c3) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -489,6 +510,17 @@ hipError_t launch_randn(double* out, int rows, int cols, int ld, unsigned long l
   hipLaunchKernelGGL(k_randn, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, out, rows,
                      cols, ld, (unsigned)(seed & 0xffffffffu), (unsigned)(seed >> 32), k, t,
                      stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_randn_iters(double* out, int rows, size_t stride, int cols0, int cols1,
+                              unsigned long long seed, unsigned k, unsigned t0, int nt,
+                              unsigned stream, hipStream_t s) {
+  const long long pairs = ((long long)rows * (cols0 > cols1 ? cols0 : cols1) + 1) / 2;
+  if (pairs <= 0 || nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_randn_iters, dim3((unsigned)((pairs + 255) / 256), (unsigned)nt), dim3(256),
+                     0, s, out, rows, stride, cols0, cols1, (unsigned)(seed & 0xffffffffu),
+                     (unsigned)(seed >> 32), k, t0, stream);
   return hipGetLastError();
 }
 

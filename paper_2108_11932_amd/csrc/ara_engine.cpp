@@ -53,7 +53,7 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
 }
 
 tlr_status ara_omega(Handle* h, const AraConfig& c, double** omega) {
-  TLR_TRY(h->ws.omega.ensure(h->mem, sizeof(double) * (size_t)c.m * c.bs_max()));
+  TLR_TRY(h->ws.omega.ensure(h->mem, sizeof(double) * kOmegaBatch * (size_t)c.m * c.bs_max()));
   *omega = h->ws.omega.as<double>();
   return TLR_OK;
 }
@@ -153,6 +153,9 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     }
   }
   const ZSeg* dzseg = (const ZSeg*)(dbase + zoff);
+  bool omega_in_slots = false;
+  for (const AraSlotDesc& d : spec.slots)
+    omega_in_slots = omega_in_slots || d.b0 == omega || d.b1 == omega;
   const PTile* dptiles = (const PTile*)(dbase + poff);
 
   // ---- initial state: active list, waiting list, cleared counters
@@ -214,9 +217,21 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     D.bs = c.bs_at(j);
     const int cb = (known.cursor >= nwait) ? known.count : s_max;
     const int qb = std::min(c.qcap, known.qmax + bs * (j - known.iter - 1));
-    TLR_HIP(launch_randn(omega, m, D.bs, m, c.seed, c.stream_id, (unsigned)j, 0, st));
+    // the samples of the explicit tiles read the test matrix through their
+    // descriptors (one buffer, drawn every iteration); the sampling through
+    // P and W^A draws the matrices of kOmegaBatch iterations at a time
+    const double* om = omega;
+    if (omega_in_slots) {
+      TLR_HIP(launch_randn(omega, m, D.bs, m, c.seed, c.stream_id, (unsigned)j, 0, st));
+    } else {
+      const size_t ostride = (size_t)m * bs;
+      if (j % kOmegaBatch == 0)
+        TLR_HIP(launch_randn_iters(omega, m, ostride, c.bs_at(0), c.bs_at(1), c.seed, c.stream_id,
+                                   (unsigned)j, kOmegaBatch, 0, st));
+      om = omega + (size_t)(j % kOmegaBatch) * ostride;
+    }
     if (p_blocks > 0 || bps_wa > 0)
-      TLR_HIP(launch_ara_tn(D, 0, omega, dptiles, p_blocks, spec.ldp, cb, bps_wa, tn_scratch, st));
+      TLR_HIP(launch_ara_tn(D, 0, om, dptiles, p_blocks, spec.ldp, cb, bps_wa, tn_scratch, st));
     if (any_z) TLR_HIP(launch_ara_z(D, dzseg, spec.p, spec.ldp, cb, bps_z, st));
     if (spec.events) {
       hipEvent_t e0, e1;

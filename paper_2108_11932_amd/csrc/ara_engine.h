@@ -109,7 +109,10 @@ tlr_status ara_explicit_spec(Handle* h, const AraConfig& c, int n, const double*
 
 // Allocate the slot buffers for n slots.
 tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s);
-// The Gaussian test-matrix buffer (m x bs) the iterations draw into.
+// The Gaussian test-matrix buffer the iterations draw into: kOmegaBatch
+// matrices of m x bs_max (the test matrices of that many consecutive
+// iterations are drawn by one launch); explicit tiles use the first.
+constexpr int kOmegaBatch = 16;
 tlr_status ara_omega(Handle* h, const AraConfig& c, double** omega);
 
 // Run the ARA loop.  `order` lists the slots in processing order (the

@@ -109,6 +109,13 @@ hipError_t launch_trsm_diag(const double* L, int ldl, double* B, int ldb, int p,
 // (e >> 1, t, k, stream) under key (seed lo, seed hi).
 hipError_t launch_randn(double* out, int rows, int cols, int ld, unsigned long long seed, unsigned k,
                         unsigned t, unsigned stream, hipStream_t s);
+// The test matrices of nt consecutive iterations t0 .. t0 + nt - 1 in one
+// launch (rows x cols0 for iteration 0, rows x cols1 after, leading
+// dimension rows, matrix t - t0 at out + (t - t0) * stride): the values
+// launch_randn gives for each t.
+hipError_t launch_randn_iters(double* out, int rows, size_t stride, int cols0, int cols1,
+                              unsigned long long seed, unsigned k, unsigned t0, int nt,
+                              unsigned stream, hipStream_t s);
 hipError_t launch_philox_raw(unsigned* out, int n, unsigned long long seed, unsigned c1, unsigned c2,
                              unsigned c3, hipStream_t s);
 
