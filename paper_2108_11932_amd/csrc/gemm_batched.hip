@@ -165,8 +165,7 @@ __global__ __launch_bounds__(512) void k_gemm_tn(const GemmDesc* __restrict__ de
 
 // The same product streamed through LDS with coalesced loads (tn_lds_tile):
 // a BM x BN tile per 256-thread workgroup, 64-row chunks.  For problems
-// that meet its alignment requirements (K even, even leading dimensions,
-// 16-byte aligned operands, no flags but GEMM_STORE_T).
+// with K >= 1 and no flags but GEMM_STORE_T.
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm_tn_lds(const GemmDesc* __restrict__ descs,
                                                      const BlockMap* __restrict__ map) {
@@ -218,10 +217,7 @@ hipError_t launch_gemm_tn_lds(const GemmDesc* d_descs, const BlockMap* d_map, in
   return hipGetLastError();
 }
 
-bool gemm_tn_lds_ok(const GemmDesc& d) {
-  return (d.flags & ~GEMM_STORE_T) == 0 && d.K >= 2 && (d.K & 1) == 0 && (d.lda & 1) == 0 && (d.ldb & 1) == 0 &&
-         ((reinterpret_cast<uintptr_t>(d.A) | reinterpret_cast<uintptr_t>(d.B)) & 15) == 0;
-}
+bool gemm_tn_lds_ok(const GemmDesc& d) { return (d.flags & ~GEMM_STORE_T) == 0 && d.K >= 1; }
 
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, int nblocks,
                                bool trans_a, bool trans_b, int bn, hipStream_t s) {

@@ -238,8 +238,9 @@ __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, i
 // 16-byte pairs (whole cache lines per instruction), the next chunk is
 // loaded into registers while the MFMAs consume the current one from LDS,
 // and the four waves split each chunk's 16-row slices; their partial tiles
-// are added in LDS at the end.  Requires K even and >= 2, lda and ldb even,
-// A and B 16-byte aligned.  Columns of A past M and of B past N are read
+// are added in LDS at the end.  16-byte loads when K and the leading
+// dimensions are even and A, B 16-byte aligned, 8-byte loads otherwise; K >=
+// 1.  Columns of A past M and of B past N are read
 // from a clamped in-range column and only reach outputs that are not
 // stored.  With store_t the tile goes to C transposed (element (r, c) at
 // C[c + r ldc]).  256 threads; smem holds tn_lds_smem<BM, BN, KC>() doubles.
@@ -266,29 +267,50 @@ __device__ inline void tn_lds_tile(const double* __restrict__ A, int lda,
   double* Bs = smem + BM * LDK;
   const int lc = t / TPC, lk = (t % TPC) * 2;
   double2 ra[AL], rb[BL];
+  // 16-byte loads when K and the leading dimensions are even and the
+  // operands 16-byte aligned (a pair of rows is then wholly inside or
+  // outside K), else two 8-byte loads per pair
+  const bool vec = (K & 1) == 0 && (lda & 1) == 0 && (ldb & 1) == 0 &&
+                   ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0;
   auto load = [&](int k0) {
-    const int kk = min(k0 + lk, K - 2);
+    if (vec) {
+      const int kk = min(k0 + lk, K - 2);
 #pragma unroll
-    for (int u = 0; u < AL; ++u) {
-      const int c = min(row0 + lc + u * CPR, M - 1);
-      const dv2 v = *(const gdv2*)(gmem(A) + (size_t)c * lda + kk);
-      ra[u] = double2{v.x, v.y};
-    }
+      for (int u = 0; u < AL; ++u) {
+        const int c = min(row0 + lc + u * CPR, M - 1);
+        const dv2 v = *(const gdv2*)(gmem(A) + (size_t)c * lda + kk);
+        ra[u] = double2{v.x, v.y};
+      }
 #pragma unroll
-    for (int u = 0; u < BL; ++u) {
-      const int c = min(col0 + lc + u * CPR, N - 1);
-      const dv2 v = *(const gdv2*)(gmem(B) + (size_t)c * ldb + kk);
-      rb[u] = double2{v.x, v.y};
+      for (int u = 0; u < BL; ++u) {
+        const int c = min(col0 + lc + u * CPR, N - 1);
+        const dv2 v = *(const gdv2*)(gmem(B) + (size_t)c * ldb + kk);
+        rb[u] = double2{v.x, v.y};
+      }
+    } else {
+      const int k0c = min(k0 + lk, K - 1), k1c = min(k0 + lk + 1, K - 1);
+#pragma unroll
+      for (int u = 0; u < AL; ++u) {
+        const gdouble* col = gmem(A) + (size_t)min(row0 + lc + u * CPR, M - 1) * lda;
+        ra[u] = double2{col[k0c], col[k1c]};
+      }
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const gdouble* col = gmem(B) + (size_t)min(col0 + lc + u * CPR, N - 1) * ldb;
+        rb[u] = double2{col[k0c], col[k1c]};
+      }
     }
   };
   auto store = [&](int k0) {
-    const bool ok = k0 + lk < K;   // K even: a pair is wholly inside or outside
+    const bool ok0 = k0 + lk < K, ok1 = k0 + lk + 1 < K;
 #pragma unroll
     for (int u = 0; u < AL; ++u)
-      *(double2*)(As + (lc + u * CPR) * LDK + lk) = ok ? ra[u] : double2{0.0, 0.0};
+      *(double2*)(As + (lc + u * CPR) * LDK + lk) =
+          double2{ok0 ? ra[u].x : 0.0, ok1 ? ra[u].y : 0.0};
 #pragma unroll
     for (int u = 0; u < BL; ++u)
-      *(double2*)(Bs + (lc + u * CPR) * LDK + lk) = ok ? rb[u] : double2{0.0, 0.0};
+      *(double2*)(Bs + (lc + u * CPR) * LDK + lk) =
+          double2{ok0 ? rb[u].x : 0.0, ok1 ? rb[u].y : 0.0};
   };
   d4 acc[FM][FN];
 #pragma unroll
