@@ -178,6 +178,34 @@ def batched_form(tlr, torch, wl, count: int, m: int):
             "batched_fp64_tflops": flops / t_b64 / 1e12}
 
 
+def ldlt_form(tlr, torch, wl, steps: int):
+    """The 3D Matern workload (N = 131072, tile 1024, eps 1e-4 absolute,
+    ARA block 32, diagonal shift -1e-2 ||A||, indefinite): TLR LDL^T."""
+    w = wl.standard("matern3d_131k")
+    t0 = time.perf_counter()
+    mat = tlr.TLRMatrix.compress_kernel(w.points, w.kernel, w.ell, w.diag_add, w.m, w.eps,
+                                        tlr.opts(bs=w.bs))
+    t_build = time.perf_counter() - t0
+    o = tlr.opts(bs=w.bs, eps_mode=w.eps_mode)
+    mat.ldlt(w.eps, o)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = [mat.ldlt(w.eps, o)[0] for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ra = mat.ranks(tlr.INPUT)[np.tril_indices(mat.nb, -1)]
+    rl = mat.ranks(tlr.FACTOR)[np.tril_indices(mat.nb, -1)]
+    out = {"workload": _describe(w), "N": w.n, "tile": w.m, "eps": w.eps, "bs": w.bs,
+           "shift": -w.diag_add, "ms_per_step": dt * 1e3,
+           "tflops": float(np.mean([x["flops"] for x in sts])) / dt / 1e12,
+           "residual": residual(mat, torch), "input_build_s": t_build,
+           "ranks_input": {"min": int(ra.min()), "mean": float(ra.mean()), "max": int(ra.max())},
+           "ranks_factor": {"min": int(rl.min()), "mean": float(rl.mean()), "max": int(rl.max())},
+           "ara_iterations": int(sts[-1]["ara_iters"])}
+    mat.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +222,8 @@ def main():
     ap.add_argument("--no-kernel-timing", dest="kernel_timing", action="store_false",
                     help="skip the second pass that times the sampling launches with their own "
                          "events (no roofline figures)")
+    ap.add_argument("--no-ldlt", dest="ldlt", action="store_false",
+                    help="skip the LDL^T line (3D Matern, indefinite) after the main line")
     ap.add_argument("--batched", type=int, default=96,
                     help="problems of the batched workload timed after the main line (0 = skip)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -300,6 +330,13 @@ def main():
                      "events_pass_ms_per_step": dt_ev * 1e3},
     }
     mat.close()
+    if a.ldlt:
+        print("[bench] LDL^T workload (3D Matern, N=131072)", file=sys.stderr, flush=True)
+        line["ldlt"] = ldlt_form(tlr, torch, wl, max(1, min(a.steps, 2)))
+        print("[bench] ldlt: %.1f ms, residual %.3g, ranks mean %.1f max %d"
+              % (line["ldlt"]["ms_per_step"], line["ldlt"]["residual"],
+                 line["ldlt"]["ranks_factor"]["mean"], line["ldlt"]["ranks_factor"]["max"]),
+              file=sys.stderr, flush=True)
     if a.batched > 0:
         print("[bench] batched workload: %d problems" % a.batched, file=sys.stderr, flush=True)
         line["batched"] = batched_form(tlr, torch, wl, a.batched, 512)

@@ -131,9 +131,25 @@ def covariance_2d(n: int, m: int, eps: float, seed: int, eps_mode: int = EPS_ABS
 
 
 # Diagonal shift of the 3D Matern workload: -1e-2 times an estimate of
-# ||A||_2 (the mean absolute row sum over 1024 seeded rows of the unshifted
-# 131072-point matrix).  Recomputed by tests/golden/make_shift.py.
+# ||A||_2, the mean absolute row sum over 1024 seeded rows of the unshifted
+# matrix (matern3d_norm_estimate).
 MATERN3D_SHIFT_FRACTION = 1e-2
+
+
+def matern3d_norm_estimate(points: np.ndarray, ell: float = 0.2, rows: int = 1024,
+                           seed: int = 5) -> float:
+    """Mean absolute row sum of the Matern-1.5 kernel matrix over `rows`
+    rows drawn by default_rng(seed) (the kernel is positive, so this is the
+    mean row sum; it lies between the smallest and the largest row sum, and
+    for these smooth kernels close to ||A||_2)."""
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(points.shape[0], size=min(rows, points.shape[0]), replace=False)
+    s = 3.0 ** 0.5 / ell
+    tot = 0.0
+    for i in idx:
+        r = np.sqrt(((points - points[i]) ** 2).sum(axis=1)) * s
+        tot += float(((1.0 + r) * np.exp(-r)).sum())
+    return tot / len(idx)
 
 
 def matern_3d(n: int, m: int, eps: float, seed: int, shift: float = 0.0,
@@ -173,6 +189,8 @@ def standard(name: str) -> Workload:
     cov2d_32k    : N=32768, 256x128 grid, tile 512, eps 1e-6, seed 2
     cov2d_32k_lo : same points, eps 1e-2
     cov2d_131k   : N=131072, 512x256 grid, tile 1024, eps 1e-6, seed 3
+    matern3d_131k: N=131072, 64x64x32 grid, 3D Matern-1.5 (ell 0.2), tile
+                   1024, eps 1e-4, bs 32, diagonal shift -1e-2 ||A|| (LDL^T)
     """
     if name == "cov2d_4k":
         return covariance_2d(4096, 256, 1e-6, 1, name=name)
@@ -182,4 +200,8 @@ def standard(name: str) -> Workload:
         return covariance_2d(32768, 512, 1e-2, 2, name=name)
     if name == "cov2d_131k":
         return covariance_2d(131072, 1024, 1e-6, 3, name=name)
+    if name == "matern3d_131k":
+        w = matern_3d(131072, 1024, 1e-4, 4, name=name)
+        w.diag_add = -MATERN3D_SHIFT_FRACTION * matern3d_norm_estimate(w.points)
+        return w
     raise KeyError(name)
