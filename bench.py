@@ -119,10 +119,12 @@ def residual(mat, torch, nvec: int = 4, seed: int = 7) -> float:
     return float((r.norm(dim=0) / x.norm(dim=0)).max())
 
 
-def time_form(mat, w, eps_mode, precision, tlr, torch, steps, warmup, bs_tail=0, timing=True):
+def time_form(mat, w, eps_mode, precision, tlr, torch, steps, warmup, bs_tail=0, tail_active=0,
+              timing=True):
     """Warm up, then time `steps` factorizations of one form (with the
     sampling launches timed by their own events when `timing`)."""
-    o = tlr.opts(bs=w.bs, bs_tail=bs_tail, eps_mode=eps_mode, precision=precision,
+    o = tlr.opts(bs=w.bs, bs_tail=bs_tail, tail_active=tail_active, eps_mode=eps_mode,
+                 precision=precision,
                  flags=tlr.FLAG_KERNEL_TIMING if timing else 0)
     for _ in range(warmup):
         mat.potrf(w.eps, o)
@@ -215,6 +217,9 @@ def main():
     ap.add_argument("--bs", type=int, default=0, help="ARA block size (0 = the workload's)")
     ap.add_argument("--bs-tail", type=int, default=0,
                     help="ARA block size after the first iteration of a column (0 = bs)")
+    ap.add_argument("--tail-active", type=int, default=0,
+                    help="use --bs-tail only once at most this many tiles of a column are active "
+                         "(0 = from the second iteration on)")
     ap.add_argument("--cpu-sample", type=int, default=12288,
                     help="points of the leading block the CPU oracle factors (0 = skip)")
     ap.add_argument("--no-forms", dest="forms", action="store_false",
@@ -265,9 +270,9 @@ def main():
     # percent of the step); the sampling kernel's durations come from the
     # dispatches' own events in a second pass of the same number of steps
     dt, stats = time_form(mat, w, w.eps_mode, tlr.FP64, tlr, torch, a.steps, a.warmup, a.bs_tail,
-                          False)
+                          a.tail_active, False)
     print("[bench] %d timed steps, %.1f ms each" % (a.steps, dt * 1e3), file=sys.stderr, flush=True)
-    dt_ev, stats_ev = (time_form(mat, w, w.eps_mode, tlr.FP64, tlr, torch, a.steps, 0, a.bs_tail, True)
+    dt_ev, stats_ev = (time_form(mat, w, w.eps_mode, tlr.FP64, tlr, torch, a.steps, 0, a.bs_tail, a.tail_active, True)
                        if a.kernel_timing else (0.0, []))
     err_primary = residual(mat, torch)
     flops = float(np.mean([s["flops"] for s in stats]))
@@ -285,7 +290,7 @@ def main():
         for name, mode, prec in (("fp64_rel", 1, tlr.FP64), ("mixed_fp32_rel", 1, tlr.MIXED_FP32),
                                  ("mixed_fp32_abs", 0, tlr.MIXED_FP32)):
             fdt, fst = time_form(mat, w, mode, prec, tlr, torch, a.steps, a.warmup, a.bs_tail,
-                                 False)
+                                 a.tail_active, False)
             s0 = fst[-1]
             forms[name] = {"ms_per_step": fdt * 1e3,
                            "tflops": float(np.mean([x["flops"] for x in fst])) / fdt / 1e12,
@@ -312,7 +317,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": _describe(w), "name": w.name, "N": w.n, "tile": w.m, "eps": w.eps,
                    "eps_mode": "absolute" if w.eps_mode == 0 else "relative", "bs": w.bs,
-                   "bs_tail": a.bs_tail or w.bs,
+                   "bs_tail": a.bs_tail or w.bs, "tail_active": a.tail_active,
                    "precision": "fp64"},
         "time_to_solution_s": dt,
         "tflops_paper_count": flops_paper / dt / 1e12,

@@ -107,6 +107,11 @@ typedef struct {
                               column (0: bs); one of the bs values.  A larger
                               value finishes the few high-rank tiles that keep
                               a column's ARA going in fewer iterations */
+  int tail_active;         /* > 0: bs_tail is used only by the iterations that
+                              start with at most this many tiles of the column
+                              still active (as known to the host two iterations
+                              earlier); the others draw bs.  0: every iteration
+                              after the first draws bs_tail */
 } tlr_opts;
 
 /* opts.flags: record HIP events around every launch of the Schur-complement

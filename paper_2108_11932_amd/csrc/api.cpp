@@ -35,6 +35,7 @@ void tlr_opts_default(tlr_opts* o) {
   o->seed = 0x5eedULL;
   o->flags = 0;
   o->bs_tail = 0;
+  o->tail_active = 0;
 }
 
 const char* tlr_last_error(void) { return tlr::last_error(); }
@@ -54,6 +55,7 @@ static tlr_status check_opts(const tlr_opts* in, tlr_opts* out) {
   TLR_ARG(out->r_min >= 1 && out->r_min <= out->bs, "opts.r_min must be in 1..bs");
   TLR_ARG(out->bs_tail == 0 || (orth_block_supported(out->bs_tail) && out->r_min <= out->bs_tail),
           "opts.bs_tail must be 0 or a supported block size >= r_min, got %d", out->bs_tail);
+  TLR_ARG(out->tail_active >= 0, "opts.tail_active must be >= 0, got %d", out->tail_active);
   TLR_ARG(std::isfinite(out->shift), "opts.shift must be finite");
   return TLR_OK;
 }

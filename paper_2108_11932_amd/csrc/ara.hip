@@ -304,7 +304,8 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, int r_min) {
         D.qnew[slot] = qold + np;
         D.flag[slot] = ((np <= BS - r_min) || (qold + np >= qcap)) ? 1 : 0;
         D.iters[slot] += 1;
-        D.qsum[slot] += qold;
+        D.qsum[slot] += qold * BS;
+        D.ncol[slot] += BS;
       }
     }
   } else {

@@ -2,6 +2,7 @@
 #include "ara_engine.h"
 
 #include <algorithm>
+#include <cstring>
 
 namespace tlr {
 
@@ -24,7 +25,7 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   if (fresh_q) TLR_HIP(hipMemsetAsync(w.Q.p, 0, w.Q.cap, h->stream));
   const size_t pn = nn * nstrip * bs * bs * 2;
   TLR_TRY(w.part.ensure(h->mem, sizeof(double) * 2 * pn));
-  const size_t nint = 8 + 6 * al(nn) + al(nn * (bs + 1)) + al(nn) + 64;
+  const size_t nint = 8 + 8 * al(nn) + al(nn * (bs + 1)) + 64;
   TLR_TRY(w.ints.ensure(h->mem, sizeof(int) * nint));
   s->Y = w.Y.as<double>();
   s->C = w.C.as<double>();
@@ -36,7 +37,7 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   ip += 8;
   s->act = ip;
   ip += al(nn);
-  s->q = ip;   // q, qnew, flag, iters, qsum are contiguous (cleared together)
+  s->q = ip;   // q, qnew, flag, iters, qsum, ncol are contiguous (cleared together)
   ip += al(nn);
   s->qnew = ip;
   ip += al(nn);
@@ -46,9 +47,11 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   ip += al(nn);
   s->qsum = ip;
   ip += al(nn);
+  s->ncol = ip;
+  ip += al(nn);
+  s->waiting = ip;   // counts .. waiting are written by one upload per run
+  ip += al(nn);
   s->piv = ip;
-  ip += al(nn * (bs + 1));
-  s->waiting = ip;
   return TLR_OK;
 }
 
@@ -101,6 +104,8 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   const int s_max = c.s_max > 0 ? std::min(c.s_max, n) : n;
   res->q.assign(n, 0);
   res->iters.assign(n, 0);
+  res->cols.assign(n, 0);
+  res->iter_bs.clear();
   res->flops_paper_orth.assign(n, 0.0);
   res->flops_slot.assign(n, 0.0);
   res->samp_bytes_slot.assign(n, 0.0);
@@ -140,17 +145,12 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   TLR_TRY(w.orth.ensure(h->mem, poff + pbytes + 256));
   char* dbase = (char*)w.orth.p;
   {
-    void* tmp = nullptr;
-    TLR_TRY(h->stage.upload(h, spec.slots.data(), sbytes, &tmp));
-    TLR_HIP(hipMemcpyAsync(dbase, tmp, sbytes, hipMemcpyDeviceToDevice, st));
-    if (zbytes) {
-      TLR_TRY(h->stage.upload(h, spec.zseg.data(), zbytes, &tmp));
-      TLR_HIP(hipMemcpyAsync(dbase + zoff, tmp, zbytes, hipMemcpyDeviceToDevice, st));
-    }
-    if (pbytes) {
-      TLR_TRY(h->stage.upload(h, ptiles.data(), pbytes, &tmp));
-      TLR_HIP(hipMemcpyAsync(dbase + poff, tmp, pbytes, hipMemcpyDeviceToDevice, st));
-    }
+    // slot descriptors, Z pieces and P tiles: one copy
+    std::vector<char> blob(poff + pbytes);
+    std::memcpy(blob.data(), spec.slots.data(), sbytes);
+    if (zbytes) std::memcpy(blob.data() + zoff, spec.zseg.data(), zbytes);
+    if (pbytes) std::memcpy(blob.data() + poff, ptiles.data(), pbytes);
+    TLR_TRY(h->stage.upload_to(h, blob.data(), blob.size(), dbase, st));
   }
   const ZSeg* dzseg = (const ZSeg*)(dbase + zoff);
   bool omega_in_slots = false;
@@ -163,17 +163,14 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   std::vector<int> waiting(order.begin() + s_max, order.end());
   const int nwait = (int)waiting.size();
   {
-    TLR_HIP(hipMemsetAsync(s.q, 0, sizeof(int) * (size_t)(s.piv - s.q), st));
-    int hdr[8] = {s_max, 0, 0, 0, 0, 0, 0, 0};
-    void* tmp = nullptr;
-    TLR_TRY(h->stage.upload(h, act.data(), sizeof(int) * act.size(), &tmp));
-    TLR_HIP(hipMemcpyAsync(s.act, tmp, sizeof(int) * act.size(), hipMemcpyDeviceToDevice, st));
-    if (nwait > 0) {
-      TLR_TRY(h->stage.upload(h, waiting.data(), sizeof(int) * nwait, &tmp));
-      TLR_HIP(hipMemcpyAsync(s.waiting, tmp, sizeof(int) * nwait, hipMemcpyDeviceToDevice, st));
-    }
-    TLR_TRY(h->stage.upload(h, hdr, sizeof hdr, &tmp));
-    TLR_HIP(hipMemcpyAsync(s.counts, tmp, sizeof hdr, hipMemcpyDeviceToDevice, st));
+    // header, active list, cleared per-slot counters and the waiting list
+    // are contiguous: one copy
+    const size_t wo = (size_t)(s.waiting - s.counts);
+    std::vector<int> blob(wo + nwait, 0);
+    blob[0] = s_max;
+    std::copy(act.begin(), act.end(), blob.begin() + (s.act - s.counts));
+    std::copy(waiting.begin(), waiting.end(), blob.begin() + wo);
+    TLR_TRY(h->stage.upload_to(h, blob.data(), sizeof(int) * blob.size(), s.counts, st));
   }
   int* ring = nullptr;
   TLR_TRY(h->readback_ring(&ring));
@@ -187,6 +184,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   D.flag = s.flag;
   D.iters = s.iters;
   D.qsum = s.qsum;
+  D.ncol = s.ncol;
   D.m = m;
   D.bs = bs;
   D.qcap = c.qcap;
@@ -214,7 +212,8 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   // enqueue iteration j with launch bounds derived from `known`: the active
   // count can only grow by refills, a basis by at most bs per iteration
   auto enqueue = [&](int j) -> tlr_status {
-    D.bs = c.bs_at(j);
+    D.bs = c.bs_for(j, known.count);
+    res->iter_bs.push_back(D.bs);
     const int cb = (known.cursor >= nwait) ? known.count : s_max;
     const int qb = std::min(c.qcap, known.qmax + bs * (j - known.iter - 1));
     // the samples of the explicit tiles read the test matrix through their
@@ -226,7 +225,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     } else {
       const size_t ostride = (size_t)m * bs;
       if (j % kOmegaBatch == 0)
-        TLR_HIP(launch_randn_iters(omega, m, ostride, c.bs_at(0), c.bs_at(1), c.seed, c.stream_id,
+        TLR_HIP(launch_randn_iters(omega, m, ostride, c.bs, bs, c.seed, c.stream_id,
                                    (unsigned)j, kOmegaBatch, 0, st));
       om = omega + (size_t)(j % kOmegaBatch) * ostride;
     }
@@ -293,22 +292,27 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   // its (empty) sampling launch stays in the timed set, as it runs
   // ---- results: basis widths, iteration counts, summed widths
   const size_t stride = (size_t)(s.qnew - s.q);
-  std::vector<int> back(5 * stride);
+  std::vector<int> back(6 * stride);
   TLR_HIP(hipMemcpyAsync(back.data(), s.q, sizeof(int) * back.size(), hipMemcpyDeviceToHost, st));
   TLR_TRY(h->sync_main());
   const int* bq = back.data();
   const int* bit = back.data() + 3 * stride;
   const int* bqs = back.data() + 4 * stride;
+  const int* bnc = back.data() + 5 * stride;
+  const double b0 = c.bs, b1 = c.bs_tail > 0 ? c.bs_tail : c.bs;
   for (int sl = 0; sl < n; ++sl) {
     res->q[sl] = bq[sl];
     res->iters[sl] = bit[sl];
-    const double it = bit[sl], qs = bqs[sl];
-    // samples drawn: bs in the first iteration, bs_tail in the others
-    const double cols = it > 0 ? c.bs + (it - 1) * c.bs_at(1) : 0.0;
-    const double b2 = it > 0 ? (double)c.bs * c.bs + (it - 1) * (double)c.bs_at(1) * c.bs_at(1) : 0.0;
+    res->cols[sl] = bnc[sl];
+    // samples drawn, and the sum of their squares per iteration (every
+    // iteration draws b0 or b1 samples)
+    const double it = bit[sl], qs = bqs[sl], cols = bnc[sl];
+    const double n1 = b1 != b0 ? (cols - b0 * it) / (b1 - b0) : 0.0;
+    const double b2 = (it - n1) * b0 * b0 + n1 * b1 * b1;
     // two Gram-Schmidt passes, each a projection and an update, plus the
     // Gram matrices and the triangular solves of the Cholesky QR steps
-    const double orth = 8.0 * m * (cols / std::max(it, 1.0)) * qs + 6.0 * m * b2;
+    // (qs: the sum over iterations of samples times prior basis width)
+    const double orth = 8.0 * m * qs + 6.0 * m * b2;
     res->flops_paper_orth[sl] = orth;
     res->flops_slot[sl] = orth + cols * spec.samp_flops_col[sl];
     res->samp_bytes_slot[sl] = it * spec.samp_bytes[sl] + cols * spec.samp_bytes_col[sl];

@@ -28,13 +28,18 @@ struct AraConfig {
   int m = 0;          // rows of every operator
   int bs = 16;        // samples per iteration (the first iteration)
   int bs_tail = 0;    // samples per iteration after the first (0: bs)
+  int tail_active = 0;   // > 0: bs_tail only while at most this many tiles are active
   int qcap = 0;       // basis capacity (columns)
   double tau = 0.0;   // absolute 2-norm threshold
   int r_min = 1;
   int s_max = 0;      // active subset size (<= 0: all)
   unsigned long long seed = 0;
   unsigned stream_id = 0;   // Philox counter word 2 (column index or batch id)
-  int bs_at(int iter) const { return (iter == 0 || bs_tail <= 0) ? bs : bs_tail; }
+  // samples drawn by iteration `iter`, `active` tiles being active at its start
+  int bs_for(int iter, int active) const {
+    if (iter == 0 || bs_tail <= 0) return bs;
+    return (tail_active <= 0 || active <= tail_active) ? bs_tail : bs;
+  }
   int bs_max() const { return bs_tail > bs ? bs_tail : bs; }
 };
 
@@ -54,6 +59,7 @@ struct AraSlots {
   int* flag = nullptr;      // n
   int* iters = nullptr;     // n
   int* qsum = nullptr;      // n
+  int* ncol = nullptr;      // n: samples drawn per slot
   int* piv = nullptr;       // n x (bs + 1)
   int* waiting = nullptr;   // n
   size_t qstride = 0;       // doubles per slot in Q
@@ -94,6 +100,8 @@ struct AraSpec {
 struct AraResult {
   std::vector<int> q;          // final basis width per slot
   std::vector<int> iters;      // iterations per slot
+  std::vector<int> cols;       // samples drawn per slot
+  std::vector<int> iter_bs;    // samples per slot of every launched iteration
   std::vector<double> flops_paper_orth;  // per slot: orthogonalisation flops
   long long launches = 0;      // ARA iterations (batches)
   double flops = 0.0;          // executed flops (sampling, Gram-Schmidt, orthogonalisation)

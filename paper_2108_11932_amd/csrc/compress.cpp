@@ -75,6 +75,7 @@ tlr_status compress(Handle* h, const double* A, long long lda, const double* pts
   cfg.m = m;
   cfg.bs = bs;
   cfg.bs_tail = o.bs_tail;
+  cfg.tail_active = o.tail_active;
   cfg.qcap = m;
   cfg.tau = eps;
   cfg.r_min = o.r_min;

@@ -26,7 +26,13 @@
 
 namespace tlr {
 
+static void release_retired(Handle* h) {
+  for (void* p : h->retired) h->mem.put(p);
+  h->retired.clear();
+}
+
 void free_factor(Handle* h) {
+  release_retired(h);
   for (double* p : h->UL) h->mem.put(p);
   for (double* p : h->VL) h->mem.put(p);
   for (float* p : h->UL32) h->mem.put(p);
@@ -40,7 +46,11 @@ void free_factor(Handle* h) {
   h->factored = 0;
 }
 
-// Make room for `extra` more columns in block row i's panels.
+// Make room for `extra` more columns in block row i's panels.  The copy is
+// ordered on the main stream after every queued use of the old panels (the
+// diagonal-tile stream reads only rows <= k, which are never grown after
+// their column); the old panels are retired rather than freed, so the queue
+// is not drained.
 static tlr_status grow_row(Handle* h, int i, int extra) {
   const int need = h->R[i] + extra;
   if (need <= h->cap[i]) return TLR_OK;
@@ -70,10 +80,8 @@ static tlr_status grow_row(Handle* h, int i, int extra) {
     if (h->mixed)
       TLR_HIP(hipMemcpyAsync(u32, h->UL32[i], bytes / 2, hipMemcpyDeviceToDevice, h->stream));
   }
-  TLR_TRY(h->sync());
-  h->mem.put(h->UL[i]);
-  h->mem.put(h->VL[i]);
-  h->mem.put(h->UL32[i]);
+  for (void* old : {(void*)h->UL[i], (void*)h->VL[i], (void*)h->UL32[i]})
+    if (old) h->retired.push_back(old);
   h->UL[i] = (double*)u;
   h->VL[i] = (double*)v;
   h->UL32[i] = (float*)u32;
@@ -414,7 +422,9 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
   // share of the launches: the iterations its tiles took part in)
   int launches = 0;
   for (int s = 0; s < nrow; ++s) launches = std::max(launches, res.iters[p.base + s]);
-  if (launches > 0) p.flops += 2.0 * Rk * m * (cfg.bs + (launches - 1.0) * cfg.bs_at(1));
+  double cols_launched = 0.0;
+  for (int j = 0; j < launches && j < (int)res.iter_bs.size(); ++j) cols_launched += res.iter_bs[j];
+  p.flops += 2.0 * Rk * m * cols_launched;
   std::vector<int> q(nrow), it(nrow);
   for (int s = 0; s < nrow; ++s) {
     const int i = k + 1 + s, sl = p.base + s;
@@ -422,7 +432,7 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
     it[s] = res.iters[sl];
     double zf = 0.0;
     for (int j = 0; j < k; ++j) zf += (double)h->lr(i, j) * h->lr(k, j);
-    const double cols = it[s] > 0 ? cfg.bs + (it[s] - 1.0) * cfg.bs_at(1) : 0.0;
+    const double cols = res.cols[sl];
     p.flops += cols * 2.0 * ((double)h->ar(i, k) * m + zf);
     if (p.use32[s]) p.fp32_tile_iters += it[s];
     p.flops += res.flops_slot[sl];
@@ -455,7 +465,18 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
   double* Bt = w.Bt.as<double>();
   for (int s = 0; s < nrow; ++s)
     if (q[s] > 0) TLR_TRY(grow_row(h, k + 1 + s, q[s]));
+  // partial products of the split long products (at most 8 slices of
+  // m x sq); growing it waits for both streams, whose queued work may read
+  // the old buffer (the diagonal-tile stream has no launches left to issue)
+  {
+    const size_t need = sizeof(double) * 8 * (size_t)m * (size_t)std::max(sq, 1LL);
+    if (w.splitk.cap < need) {
+      TLR_TRY(h->sync());
+      TLR_TRY(w.splitk.ensure(h->mem, need));
+    }
+  }
   Plan plan(h);
+  plan.splitk = &w.splitk;
   {
     GemmBatch t1(true, false), t2(true, false), hb(true, false), b1(false, false), b2(false, false);
     for (int s = 0; s < nrow; ++s) {
@@ -555,7 +576,7 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
     // Eq. (2) per iteration, the same for the projection, orthogonalisation,
     // triangular solve)
     const double ext = (double)h->R[i] - q[s] + Rk + h->ar(i, k);
-    const double cols = it[s] > 0 ? cfg.bs + (it[s] - 1.0) * cfg.bs_at(1) : 0.0;
+    const double cols = res.cols[p.base + s];
     p.flops_paper += cols * 4.0 * m * ext + 4.0 * m * q[s] * ext +
                      res.flops_paper_orth[p.base + s] + (double)m * m * q[s];
     p.bytes_alg += it[s] * 8.0 * m * ((double)h->R[i] - q[s] + h->ar(i, k));
@@ -644,6 +665,7 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
   cfg.m = m;
   cfg.bs = bs;
   cfg.bs_tail = o.bs_tail;
+  cfg.tail_active = o.tail_active;
   cfg.qcap = m;
   cfg.tau = ps[idx[0]].tau;
   cfg.r_min = o.r_min;
@@ -740,6 +762,7 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
     TLR_HIP(hipStreamWaitEvent(h->stream, h->ev_join, 0));
   }
   for (int pi : idx) TLR_TRY(ps[pi].h->sync());
+  for (int pi : idx) release_retired(ps[pi].h);
   tlr_status first = TLR_OK;
   for (int pi : idx) {
     const tlr_status s = prob_finish(ps[pi], o, ldl, stats ? stats + pi : nullptr);

@@ -13,6 +13,8 @@
 // direction (so global loads coalesce whatever the transposition) and fed to
 // v_mfma_f64_16x16x4f64.  A host-built block map assigns workgroups to
 // (problem, tile) pairs, so problems of any shape share one launch.
+#include <algorithm>
+
 #include "mfma_tiles.h"
 #include "tlr_internal.h"
 
@@ -21,15 +23,20 @@ namespace tlr {
 namespace {
 
 constexpr int BM = 64;
-constexpr int BK = 16;
 constexpr int PAD = 2;
 
 // MFMA f64 16x16x4 operand layout (measured on gfx950): lane l supplies
 // A(l % 16, l / 16) and B(l / 16, l % 16); accumulator register r of lane l
 // holds D(l / 16 + 4 r, l % 16).
-template <bool TA, bool TB, int BN>
+//
+// BK is the depth of one K slice.  A slice's loads are in flight while the
+// previous slice's MFMAs run, and with few workgroups (a long product over
+// m = 1024 with only ~160 output tiles) every slice costs about one memory
+// latency: long contractions take BK = 64, short ones (K <= 32) BK = 16.
+template <bool TA, bool TB, int BN, int BK>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs,
                                               const BlockMap* __restrict__ map) {
+  static_assert(BK == 16 || BK == 32 || BK == 64, "slice depth");
   constexpr int WAVES_N = (BN == 64) ? 2 : 1;
   constexpr int WAVES_M = 4 / WAVES_N;
   constexpr int WM = BM / WAVES_M;   // rows per wave: 32 or 16
@@ -47,7 +54,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   const int col0 = (bm.tile / tiles_m) * BN;
   if ((d.flags & GEMM_LOWER_C) && col0 >= row0 + BM) return;
   int kbeg = 0, kend = d.K;
-  if (d.flags & GEMM_TRIL_A) kend = min(kend, row0 + BM);
+  if (d.flags & GEMM_TRIL_A) kend = min(kend, row0 + BM - d.koff);
   if (d.flags & GEMM_TRIU_A) kbeg = (row0 / BK) * BK;
 
   const int tid = threadIdx.x;
@@ -69,22 +76,25 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   // latency per slice is hidden behind the compute and the barriers.
   // op(A)(row0 + r, k0 + kk) is staged as 64 x 16, op(B)(k0 + kk, col0 + c)
   // as 16 x BN; every thread owns fixed (r, kk) / (kk, c) positions.
-  constexpr int NBL = BN / 16;
-  int ar[4], ak[4], bc[NBL], bk[NBL];
+  // (the loads of a wave run down the stored columns: 64 rows of op(A) for
+  // A, BK consecutive k for A^T and B, BN consecutive columns for B^T)
+  constexpr int NAL = BM * BK / 256;
+  constexpr int NBL = BK * BN / 256;
+  int ar[NAL], ak[NAL], bc[NBL], bk[NBL];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < NAL; ++j) {
     if (!TA) { ar[j] = tid & 63; ak[j] = (tid >> 6) + 4 * j; }
-    else     { ak[j] = tid & 15; ar[j] = (tid >> 4) + 16 * j; }
+    else     { ak[j] = tid % BK; ar[j] = tid / BK + (256 / BK) * j; }
   }
 #pragma unroll
   for (int j = 0; j < NBL; ++j) {
-    if (!TB) { bk[j] = tid & 15; bc[j] = (tid >> 4) + 16 * j; }
+    if (!TB) { bk[j] = tid % BK; bc[j] = tid / BK + (256 / BK) * j; }
     else     { bc[j] = tid % BN; bk[j] = tid / BN + (256 / BN) * j; }
   }
-  double ra[4], rb[NBL];
+  double ra[NAL], rb[NBL];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NAL; ++j) {
       const int gr = row0 + ar[j], gk = k0 + ak[j];
       double v = 0.0;
       if (gr < d.M && gk < d.K)
@@ -103,7 +113,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   if (kbeg < kend) load(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) sA[ak[j]][ar[j]] = ra[j];
+    for (int j = 0; j < NAL; ++j) sA[ak[j]][ar[j]] = ra[j];
 #pragma unroll
     for (int j = 0; j < NBL; ++j) sB[bk[j]][bc[j]] = rb[j];
     __syncthreads();
@@ -181,15 +191,45 @@ __global__ __launch_bounds__(256) void k_gemm_tn_lds(const GemmDesc* __restrict_
 }
 
 template <bool TA, bool TB>
-hipError_t launch_tt(const GemmDesc* d, const BlockMap* map, int nblocks, int bn, hipStream_t s) {
-  if (bn == 64)
-    hipLaunchKernelGGL((k_gemm<TA, TB, 64>), dim3(nblocks), dim3(256), 0, s, d, map);
+hipError_t launch_tt(const GemmDesc* d, const BlockMap* map, int nblocks, int bn, int bk,
+                     hipStream_t s) {
+  if (bn == 64 && bk == 64)
+    hipLaunchKernelGGL((k_gemm<TA, TB, 64, 64>), dim3(nblocks), dim3(256), 0, s, d, map);
+  else if (bn == 64)
+    hipLaunchKernelGGL((k_gemm<TA, TB, 64, 16>), dim3(nblocks), dim3(256), 0, s, d, map);
+  else if (bk == 64)
+    hipLaunchKernelGGL((k_gemm<TA, TB, 16, 64>), dim3(nblocks), dim3(256), 0, s, d, map);
   else
-    hipLaunchKernelGGL((k_gemm<TA, TB, 16>), dim3(nblocks), dim3(256), 0, s, d, map);
+    hipLaunchKernelGGL((k_gemm<TA, TB, 16, 16>), dim3(nblocks), dim3(256), 0, s, d, map);
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_splitk_sum(double* C, int ldc, int M, int N,
+                                                    const double* __restrict__ part, int S,
+                                                    double alpha, double beta) {
+  const size_t mn = (size_t)M * N;
+  for (size_t e = blockIdx.x * 256ull + threadIdx.x; e < mn; e += (size_t)gridDim.x * 256) {
+    const int r = (int)(e % M), c = (int)(e / M);
+    double v = 0.0;
+    for (int s = 0; s < S; ++s) v += gmem(part)[e + (size_t)s * mn];
+    gdouble* cp = gmem(C) + r + (size_t)c * ldc;
+    v *= alpha;
+    if (beta != 0.0) v += beta * *cp;
+    *cp = v;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_splitk_sum(double* C, int ldc, int M, int N, const double* part, int S,
+                             double alpha, double beta, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const long long mn = (long long)M * N;
+  const unsigned blocks = (unsigned)std::min<long long>((mn + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_splitk_sum, dim3(blocks), dim3(256), 0, s, C, ldc, M, N, part, S, alpha,
+                     beta);
+  return hipGetLastError();
+}
 
 int gemm_tile_n(int N) { return N <= 16 ? 16 : 64; }
 
@@ -220,9 +260,10 @@ hipError_t launch_gemm_tn_lds(const GemmDesc* d_descs, const BlockMap* d_map, in
 bool gemm_tn_lds_ok(const GemmDesc& d) { return (d.flags & ~GEMM_STORE_T) == 0 && d.K >= 1; }
 
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, int nblocks,
-                               bool trans_a, bool trans_b, int bn, hipStream_t s) {
+                               bool trans_a, bool trans_b, int bn, int max_k, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  if (!trans_a && !trans_b) return launch_tt<false, false>(d_descs, d_map, nblocks, bn, s);
+  const int bk = max_k > 32 ? 64 : 16;
+  if (!trans_a && !trans_b) return launch_tt<false, false>(d_descs, d_map, nblocks, bn, bk, s);
   if (trans_a && !trans_b) {
     if (bn == 0)
       hipLaunchKernelGGL((k_gemm_tn<1, 1>), dim3(nblocks), dim3(512), 0, s, d_descs, d_map);
@@ -232,8 +273,8 @@ hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, i
       hipLaunchKernelGGL((k_gemm_tn<2, 2>), dim3(nblocks), dim3(512), 0, s, d_descs, d_map);
     return hipGetLastError();
   }
-  if (!trans_a && trans_b) return launch_tt<false, true>(d_descs, d_map, nblocks, bn, s);
-  return launch_tt<true, true>(d_descs, d_map, nblocks, bn, s);
+  if (!trans_a && trans_b) return launch_tt<false, true>(d_descs, d_map, nblocks, bn, bk, s);
+  return launch_tt<true, true>(d_descs, d_map, nblocks, bn, bk, s);
 }
 
 }  // namespace tlr

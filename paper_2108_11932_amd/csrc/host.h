@@ -76,6 +76,10 @@ struct Staging {
   // handle's main stream); returns the device address.
   tlr_status upload(Handle* h, const void* data, size_t bytes, void** dptr,
                     hipStream_t s = nullptr);
+  // Copy `bytes` of host data straight into the device buffer `dst` (one
+  // copy, through the pinned host ring).
+  tlr_status upload_to(Handle* h, const void* data, size_t bytes, void* dst,
+                       hipStream_t s = nullptr);
 };
 
 // One batch of GEMMs with uniform transposition.
@@ -157,6 +161,10 @@ struct Plan {
   tlr_status run_some(size_t max_steps);
   bool pending() const { return !steps.empty(); }
   DevBuf* persist = nullptr;
+  // With `splitk` set, a batch of one long product with few output tiles
+  // may be computed as partial products over K slices in this buffer (when
+  // it is large enough), followed by their sum.
+  DevBuf* splitk = nullptr;
   size_t cursor = 0;
   bool started = false;
   const char* base = nullptr;
@@ -186,13 +194,14 @@ class SideWorker {
 // Per-column workspace of the factorization.
 struct Work {
   DevBuf G, W, omega, P, Z, T, Ta, H, Ball, C, Wa, Y, Q, part, ints, orth, dscale, tol,
-      compact, Bt, fro, tnpart;
+      compact, Bt, fro, tnpart, splitk;
   // buffers of the diagonal-tile stream (never touched by the main stream)
   DevBuf Wd, dW, dtol, sideblob;
   int slots = 0;   // slot capacity of the per-tile buffers
   void release_all(Mem& mem) {
     DevBuf* bufs[] = {&G, &W, &omega, &P, &Z, &T, &Ta, &H, &Ball, &C, &Wa, &Y, &Q, &part,
-                      &ints, &orth, &dscale, &tol, &compact, &Bt, &fro, &tnpart, &Wd, &dW, &dtol, &sideblob};
+                      &ints, &orth, &dscale, &tol, &compact, &Bt, &fro, &tnpart, &splitk, &Wd,
+                      &dW, &dtol, &sideblob};
     for (DevBuf* b : bufs) b->release(mem);
   }
 };
@@ -236,6 +245,10 @@ struct tlr_matrix_s {
   std::vector<int> R, cap;        // panel width and capacity per block row
   std::vector<double*> UL, VL;
   std::vector<float*> UL32;       // FP32 copies of the U panels (mixed precision)
+  // panels replaced by larger ones during a factorization: queued work may
+  // still read them, so they are released once the factorization has
+  // synchronised (or with the factor)
+  std::vector<void*> retired;
   bool mixed = false;             // the current factorization keeps UL32
   std::vector<double> l_fro;      // ||L_ij||_F per tile (U orthonormal: ||V_ij||_F)
   double* pin_norm = nullptr;     // pinned read-back of a column's V norms

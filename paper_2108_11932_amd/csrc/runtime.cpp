@@ -110,6 +110,26 @@ tlr_status Staging::upload(Handle* h, const void* data, size_t bytes, void** dpt
   return TLR_OK;
 }
 
+tlr_status Staging::upload_to(Handle* h, const void* data, size_t bytes, void* dst,
+                              hipStream_t s) {
+  if (bytes == 0) return TLR_OK;
+  const size_t need = (bytes + 255) & ~(size_t)255;
+  if (used + need > cap) {
+    TLR_TRY(h->sync());
+    if (need > cap) {
+      Mem& mem = h->mem;
+      release(mem);
+      TLR_TRY(init(mem, need * 2));
+    }
+  }
+  // the host bytes stay untouched until the ring wraps, which waits for
+  // the queued copies first
+  std::memcpy(host + used, data, bytes);
+  TLR_HIP(hipMemcpyAsync(dst, host + used, bytes, hipMemcpyHostToDevice, s ? s : h->stream));
+  used += need;
+  return TLR_OK;
+}
+
 }  // namespace tlr
 
 namespace tlr {
@@ -344,13 +364,15 @@ void Plan::gemm(const GemmBatch& b) {
     if (idx.empty()) return;
     std::vector<BlockMap> map;
     build_map(dv, idx, tm, tn, &map);
+    int maxk = 0;
+    for (int i : idx) maxk = std::max(maxk, dv[i].K);
     const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
     const int nblk = (int)map.size();
     steps.push_back([=](const char* base) {
       const GemmDesc* pd = (const GemmDesc*)(base + od);
       const BlockMap* pm = (const BlockMap*)(base + om);
       return lds ? launch_gemm_tn_lds(pd, pm, nblk, tm, tn, st)
-                 : launch_gemm_batched(pd, pm, nblk, ta, tb, bn, st);
+                 : launch_gemm_batched(pd, pm, nblk, ta, tb, bn, maxk, st);
     });
   };
   push(l16, 16, 16, true, 0);
@@ -360,7 +382,57 @@ void Plan::gemm(const GemmBatch& b) {
   if (!large.empty()) {
     int TM = 64, bn = 16;
     gemm_tile_shape(ta, tb, maxn, &TM, &bn);
-    push(large, TM, bn, false, bn);
+    // One long product with few output tiles (the triangular solve with
+    // L_kk^{-1}, the U_k* term of the projection: ~160 tiles of 64 x 64 and
+    // K ~ 1000) leaves a third of the CUs idle and each busy one on a long
+    // K loop: its K range is cut into slices of 64-multiples whose partial
+    // products go to the split buffer and are added in a fixed order.
+    int S = 1, kc = 0;
+    if (splitk && !ta && large.size() == 1) {
+      const GemmDesc& d = dv[large[0]];
+      const long long tiles = (long long)((d.M + TM - 1) / TM) * ((d.N + bn - 1) / bn);
+      if ((d.flags & ~GEMM_TRIL_A) == 0 && tiles < kFill && d.K >= 256) {
+        S = (int)std::min<long long>(std::min<long long>((2 * kFill + tiles - 1) / tiles, d.K / 128), 8);
+        kc = ((d.K + S - 1) / S + 63) / 64 * 64;
+        S = (d.K + kc - 1) / kc;
+        if ((size_t)S * d.M * d.N * sizeof(double) > splitk->cap) S = 1;
+      }
+    }
+    if (S >= 2) {
+      const GemmDesc d = dv[large[0]];
+      double* part = splitk->as<double>();
+      std::vector<GemmDesc> sd;
+      for (int s = 0; s < S; ++s) {
+        GemmDesc e = d;
+        const int k0 = s * kc;
+        e.A = d.A + (size_t)k0 * d.lda;
+        e.B = tb ? d.B + (size_t)k0 * d.ldb : d.B + k0;
+        e.K = std::min(d.K, k0 + kc) - k0;
+        e.C = part + (size_t)s * d.M * d.N;
+        e.ldc = d.M;
+        e.alpha = 1.0;
+        e.beta = 0.0;
+        e.koff = k0;
+        sd.push_back(e);
+      }
+      std::vector<int> idx(S);
+      for (int s = 0; s < S; ++s) idx[s] = s;
+      std::vector<BlockMap> map;
+      build_map(sd, idx, TM, bn, &map);
+      const size_t osd = stage(sd.data(), sd.size() * sizeof(GemmDesc));
+      const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
+      const int nblk = (int)map.size();
+      const int maxk = kc;
+      steps.push_back([=](const char* base) {
+        return launch_gemm_batched((const GemmDesc*)(base + osd), (const BlockMap*)(base + om), nblk,
+                                   ta, tb, bn, maxk, st);
+      });
+      steps.push_back([=](const char*) {
+        return launch_splitk_sum(d.C, d.ldc, d.M, d.N, part, S, d.alpha, d.beta, st);
+      });
+    } else {
+      push(large, TM, bn, false, bn);
+    }
   }
   flops += b.flops;
 }
@@ -393,14 +465,15 @@ tlr_status Plan::run_some(size_t max_steps) {
     base = nullptr;
     if (!blob.empty()) {
       void* dp = nullptr;
-      TLR_TRY(h->stage.upload(h, blob.data(), blob.size(), &dp, s));
       if (persist) {
         if (persist->cap < blob.size()) {
           TLR_TRY(h->sync());   // the old buffer may still be read by queued work
           TLR_TRY(persist->ensure(h->mem, blob.size() + blob.size() / 2));
         }
-        TLR_HIP(hipMemcpyAsync(persist->p, dp, blob.size(), hipMemcpyDeviceToDevice, s));
+        TLR_TRY(h->stage.upload_to(h, blob.data(), blob.size(), persist->p, s));
         dp = persist->p;
+      } else {
+        TLR_TRY(h->stage.upload(h, blob.data(), blob.size(), &dp, s));
       }
       base = (const char*)dp;
     }

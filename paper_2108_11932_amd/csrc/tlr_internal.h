@@ -24,6 +24,7 @@ struct GemmDesc {
   int lda, ldb, ldc;
   int flags;   // GEMM_* bits
   double alpha, beta;
+  int koff;    // K offset of this slice of a split contraction (triangle clipping)
 };
 // Only output tiles that reach the lower triangle (row >= col) are computed.
 constexpr int GEMM_LOWER_C = 1;
@@ -56,8 +57,14 @@ void gemm_tile_shape(bool trans_a, bool trans_b, int maxn, int* tm, int* tn);
 bool gemm_tn_lds_ok(const GemmDesc& d);
 hipError_t launch_gemm_tn_lds(const GemmDesc* d_descs, const BlockMap* d_map, int nblocks, int bm,
                               int bn, hipStream_t s);
+// C = alpha * sum_s part_s + beta * C over an M x N block, the S partial
+// products stored one after another (M x N each, leading dimension M) and
+// added in order s = 0, 1, ...
+hipError_t launch_splitk_sum(double* C, int ldc, int M, int N, const double* part, int S,
+                             double alpha, double beta, hipStream_t s);
+// max_k: the largest K of the batch (picks the depth of the K slices).
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, int nblocks,
-                               bool trans_a, bool trans_b, int bn, hipStream_t s);
+                               bool trans_a, bool trans_b, int bn, int max_k, hipStream_t s);
 
 // Two-segment product with a narrow right-hand side (N <= 32):
 // C = beta C + A[0] B[0] + A[1] B[1]; a segment with K = 0 is skipped.
@@ -174,7 +181,8 @@ struct AraDev {
   int* qnew;    // basis width after this iteration's pass 1
   int* flag;    // converged
   int* iters;   // iterations per slot
-  int* qsum;    // sum over iterations of the basis width before the iteration
+  int* qsum;    // sum over iterations of the samples times the prior basis width
+  int* ncol;    // samples drawn per slot
   int m, bs, qcap, nstrip;
 };
 // Block sizes the orthogonalisation kernels are built for (1, 2, 4, 8, 16,

@@ -42,7 +42,8 @@ class TLRError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("bs", ctypes.c_int), ("eps_mode", ctypes.c_int), ("precision", ctypes.c_int),
                 ("shift", ctypes.c_double), ("max_active", ctypes.c_int), ("r_min", ctypes.c_int),
-                ("seed", ctypes.c_ulonglong), ("flags", ctypes.c_int), ("bs_tail", ctypes.c_int)]
+                ("seed", ctypes.c_ulonglong), ("flags", ctypes.c_int), ("bs_tail", ctypes.c_int),
+                ("tail_active", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -110,14 +110,15 @@ def test_cholesky_matches_oracle_invariants(n, m, eps):
             assert rg[i, k] >= int(np.sum(sv > e * (1 + 1e-8) + 1e-14 * scale))
 
 
-@pytest.mark.parametrize("bs,bs_tail", [(16, 32), (8, 24)])
-def test_larger_tail_block_keeps_accuracy(bs, bs_tail):
-    # later ARA iterations of a column drawing more samples: same bounds
+@pytest.mark.parametrize("bs,bs_tail,tail_active", [(16, 32, 0), (8, 24, 0), (16, 32, 2)])
+def test_larger_tail_block_keeps_accuracy(bs, bs_tail, tail_active):
+    # later ARA iterations of a column drawing more samples (all of them, or
+    # only those with at most tail_active tiles left): same bounds
     pts, a = _cov(2048, 19)
     eps = 1e-6
     t = otlr.compress_dense(a, 256, eps)
     mat = _upload(t)
-    st = mat.potrf(eps, tlr.opts(bs=bs, bs_tail=bs_tail))
+    st = mat.potrf(eps, tlr.opts(bs=bs, bs_tail=bs_tail, tail_active=tail_active))
     l = oracle_tlr(mat, tlr.FACTOR)
     res = _residual_tiles(t, l)
     for k in range(t.nb):

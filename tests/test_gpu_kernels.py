@@ -22,11 +22,21 @@ def _rand(shape, seed):
     return np.random.default_rng(seed).standard_normal(shape)
 
 
+_GEMM_SIZES = {
+    # batches whose largest K exceeds 32 run with 64-deep K slices
+    "long": [(1, 1, 1), (3, 17, 5), (64, 16, 64), (65, 15, 4), (130, 70, 33), (7, 129, 0),
+             (200, 16, 300), (16, 64, 1), (1, 300, 2), (70, 64, 1030)],
+    # the others with 16-deep slices
+    "short": [(1, 1, 1), (3, 17, 5), (65, 15, 4), (130, 70, 32), (7, 129, 0), (16, 64, 1),
+              (1, 300, 2), (70, 64, 17)],
+}
+
+
+@pytest.mark.parametrize("kind", ["long", "short"])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
-def test_gemm_batched_ragged(ta, tb):
+def test_gemm_batched_ragged(ta, tb, kind):
     rng = np.random.default_rng(10 + 2 * ta + tb)
-    sizes = [(1, 1, 1), (3, 17, 5), (64, 16, 64), (65, 15, 4), (130, 70, 33), (7, 129, 0),
-             (200, 16, 300), (16, 64, 1), (1, 300, 2)]
+    sizes = _GEMM_SIZES[kind]
     probs, refs, outs = [], [], []
     for (M, N, K) in sizes:
         A = rng.standard_normal((K, M) if ta else (M, K))
