@@ -158,48 +158,55 @@ __global__ __launch_bounds__(256) void k_ara_z(AraDev D, const ZSeg* __restrict_
 }
 
 // MODE 0 (the sampling product) and modes 1, 2 are separate instantiations
-// so that profiles tell them apart.
-template <int NF, int MODE>
+// so that profiles tell them apart.  A workgroup computes FM 16-row strips
+// of one tile: FM = 4 (64-row strips) reads 512 contiguous bytes of every
+// panel column and each test-matrix row once for four row blocks, where
+// enough tiles are active to keep the CUs busy; FM = 1 spreads few tiles over
+// four times more workgroups.  Both give the same Y bit for bit.
+template <int NF, int MODE, int FM>
 __global__ __launch_bounds__(256) void k_ara_seg(AraDev D) {
   constexpr int mode = MODE;
-  __shared__ double red[4][NF * 4][64];
-  __shared__ double ys[16][16 * NF + 1];
+  __shared__ double red[4][FM * NF * 4][64];
+  __shared__ double ys[16 * FM][16 * NF + 1];
   const int ns = D.nstrip;
-  const int ai = blockIdx.x / ns, strip = blockIdx.x % ns;
+  const int nblk = (ns + FM - 1) / FM;
+  const int ai = blockIdx.x / nblk, blk = blockIdx.x % nblk;
   if (ai >= D.counts[0]) return;
   const int slot = D.act[ai];
   const AraSlotDesc& d = D.slots[slot];
   const int m = D.m, bs = D.bs;
-  const int r0 = strip * 16;
+  const int r0 = blk * 16 * FM;
   double* part;
   if (mode == 0) {
     if (d.a1_f32)
-      seg_strip<NF, true>(d.a0, d.lda0, d.b0, d.ldb0, d.k0, d.a1, d.lda1, d.b1, d.ldb1, d.k1, d.y, m,
-                          m, bs, 0.0, r0, red, ys);
+      seg_strip<NF, true, FM>(d.a0, d.lda0, d.b0, d.ldb0, d.k0, d.a1, d.lda1, d.b1, d.ldb1, d.k1,
+                              d.y, m, m, bs, 0.0, r0, red, ys);
     else
-      seg_strip<NF, false>(d.a0, d.lda0, d.b0, d.ldb0, d.k0, d.a1, d.lda1, d.b1, d.ldb1, d.k1, d.y,
-                           m, m, bs, 0.0, r0, red, ys);
+      seg_strip<NF, false, FM>(d.a0, d.lda0, d.b0, d.ldb0, d.k0, d.a1, d.lda1, d.b1, d.ldb1, d.k1,
+                               d.y, m, m, bs, 0.0, r0, red, ys);
     part = d.part1;
   } else {
     const int q = D.q[slot];
     if (q == 0) return;
     double* dst = mode == 1 ? d.y : d.q + (size_t)q * m;
-    seg_strip<NF, false>(d.q, m, d.c, m, q, nullptr, 1, nullptr, 1, 0, dst, m, m, bs, 1.0, r0, red,
-                         ys);
+    seg_strip<NF, false, FM>(d.q, m, d.c, m, q, nullptr, 1, nullptr, 1, 0, dst, m, m, bs, 1.0, r0,
+                             red, ys);
     part = mode == 1 ? d.part1 : d.part2;
   }
-  // Gram partials of the strip (Dot2 over its 16 rows), pairs a <= b
+  // Gram partials of each 16-row strip (Dot2 over its rows), pairs a <= b
   const int npairs = bs * (bs + 1) / 2;
-  gdouble* out = gmem(part) + (size_t)strip * bs * bs * 2;
-  for (int pr = threadIdx.x; pr < npairs; pr += 256) {
+  const int s0 = blk * FM, nsub = min(FM, ns - s0);
+  for (int e = threadIdx.x; e < nsub * npairs; e += 256) {
+    const int sub = e / npairs, pr = e % npairs;
     int b = (int)((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
     while (b * (b + 1) / 2 > pr) --b;
     while ((b + 1) * (b + 2) / 2 <= pr) ++b;
     const int a = pr - b * (b + 1) / 2;
     double sh = 0.0, sl = 0.0;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) dot2_step(ys[r][a], ys[r][b], sh, sl);
+    for (int r = 0; r < 16; ++r) dot2_step(ys[16 * sub + r][a], ys[16 * sub + r][b], sh, sl);
     const dd v = fast_two_sum(sh, sl);
+    gdouble* out = gmem(part) + (size_t)(s0 + sub) * bs * bs * 2;
     out[(a + b * bs) * 2 + 0] = v.hi;
     out[(a + b * bs) * 2 + 1] = v.lo;
   }
@@ -244,30 +251,38 @@ hipError_t launch_ara_z(const AraDev& D, const ZSeg* segs, const double* P, int 
   return hipGetLastError();
 }
 
-hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_t s,
-                          hipEvent_t start, hipEvent_t stop) {
-  if (D.bs > 32 || mode < 0 || mode > 2) return hipErrorInvalidValue;
-  const long long n = (long long)std::max(count_bound, 0) * D.nstrip;
-  if (n <= 0) return hipSuccess;
+namespace {
+// the sampling product runs on 64-row strips once this many workgroups of
+// them fill the launch
+constexpr long long kTallWgs = 512;
+
+template <int NF, int FM>
+hipError_t seg_launch(const AraDev& D, int mode, int count_bound, hipStream_t s, hipEvent_t start,
+                      hipEvent_t stop) {
+  const long long n = (long long)count_bound * ((D.nstrip + FM - 1) / FM);
   const dim3 g((unsigned)n), b(256);
   if (start || stop) {
     // the events take the dispatch's own begin and end timestamps
-    if (D.bs <= 16)
-      hipExtLaunchKernelGGL((k_ara_seg<1, 0>), g, b, 0, s, start, stop, 0, D);
-    else
-      hipExtLaunchKernelGGL((k_ara_seg<2, 0>), g, b, 0, s, start, stop, 0, D);
+    hipExtLaunchKernelGGL((k_ara_seg<NF, 0, FM>), g, b, 0, s, start, stop, 0, D);
     return mode == 0 ? hipGetLastError() : hipErrorInvalidValue;
   }
-  if (D.bs <= 16) {
-    if (mode == 0) hipLaunchKernelGGL((k_ara_seg<1, 0>), g, b, 0, s, D);
-    if (mode == 1) hipLaunchKernelGGL((k_ara_seg<1, 1>), g, b, 0, s, D);
-    if (mode == 2) hipLaunchKernelGGL((k_ara_seg<1, 2>), g, b, 0, s, D);
-  } else {
-    if (mode == 0) hipLaunchKernelGGL((k_ara_seg<2, 0>), g, b, 0, s, D);
-    if (mode == 1) hipLaunchKernelGGL((k_ara_seg<2, 1>), g, b, 0, s, D);
-    if (mode == 2) hipLaunchKernelGGL((k_ara_seg<2, 2>), g, b, 0, s, D);
-  }
+  if (mode == 0) hipLaunchKernelGGL((k_ara_seg<NF, 0, FM>), g, b, 0, s, D);
+  if (mode == 1) hipLaunchKernelGGL((k_ara_seg<NF, 1, 1>), g, b, 0, s, D);
+  if (mode == 2) hipLaunchKernelGGL((k_ara_seg<NF, 2, 1>), g, b, 0, s, D);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_t s,
+                          hipEvent_t start, hipEvent_t stop) {
+  if (D.bs > 32 || mode < 0 || mode > 2) return hipErrorInvalidValue;
+  if ((long long)std::max(count_bound, 0) * D.nstrip <= 0) return hipSuccess;
+  const bool tall = mode == 0 && (long long)count_bound * ((D.nstrip + 3) / 4) >= kTallWgs;
+  if (D.bs <= 16)
+    return tall ? seg_launch<1, 4>(D, mode, count_bound, s, start, stop)
+                : seg_launch<1, 1>(D, mode, count_bound, s, start, stop);
+  return tall ? seg_launch<2, 4>(D, mode, count_bound, s, start, stop)
+              : seg_launch<2, 1>(D, mode, count_bound, s, start, stop);
 }
 
 }  // namespace tlr

@@ -132,36 +132,48 @@ __device__ inline void tn_tile(const double* __restrict__ A, int lda, const doub
   }
 }
 
-// Streaming product of a 16-row strip (256 threads, 4 waves):
-//   C(r0 : r0 + 16, 0 : N) = beta C + A0 B0 + A1 B1,
+// Streaming product of a strip of 16 FM rows (256 threads, 4 waves):
+//   C(r0 : r0 + 16 FM, 0 : N) = beta C + A0 B0 + A1 B1,
 // A_s m x K_s column-major (A1 read as float when A1F32), B_s K_s x N,
 // N <= 16 NF.  The waves take interleaved 16-wide slices of the K range of
 // both segments, U slices per pass with all loads in flight; lane (i, g)
-// reads row i of A for the four columns k0 + 4 g + t (128-byte runs per
-// column over the 16 lanes of a group) and rows k0 + 4 g + t of column i of
-// B; MFMA t consumes k0 + 4 g + t on both operands.  The four partial strips
-// are added in LDS (red, 4 x NF 4 x 64) in a fixed order.  When ys is not
-// NULL the final strip is also left in ys[row - r0][col] (after a barrier).
-template <int NF, bool A1F32>
+// reads rows i + 16 f of A for the four columns k0 + 4 g + t (128-byte runs
+// per column over the 16 lanes of a group, FM of them one after another down
+// the column) and rows k0 + 4 g + t of column i of B, which serve all FM row
+// blocks; MFMA t consumes k0 + 4 g + t on both operands.  The four partial
+// strips are added in LDS (red, 4 x FM NF 4 x 64) in a fixed order.  When ys
+// is not NULL the final strip is also left in ys[row - r0][col] (after a
+// barrier).
+template <int NF, bool A1F32, int FM = 1>
 __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, int ldb0, int K0,
                                  const void* A1v, int lda1, const double* B1, int ldb1, int K1,
                                  double* C, int ldc, int M, int N, double beta, int r0,
-                                 double (*red)[NF * 4][64], double (*ys)[16 * NF + 1]) {
+                                 double (*red)[FM * NF * 4][64], double (*ys)[16 * NF + 1]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
-  const int row = r0 + li;
-  const bool rok = row < M;
-  d4 acc[NF];
+  // rows r0 + 16 f + li (f < FM); rows past M read row 0 and are not stored
+  int rowc[FM];
 #pragma unroll
-  for (int b = 0; b < NF; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
-  constexpr int U = 4;
+  for (int f = 0; f < FM; ++f) {
+    const int row = r0 + 16 * f + li;
+    rowc[f] = row < M ? row : 0;
+  }
+  d4 acc[FM][NF];
+#pragma unroll
+  for (int f = 0; f < FM; ++f)
+#pragma unroll
+    for (int b = 0; b < NF; ++b) acc[f][b] = d4{0.0, 0.0, 0.0, 0.0};
+  // 64-row K blocks per round of loads: every wave walks the same sequence
+  // of K blocks whatever FM, so the accumulation order of an output does
+  // not depend on the strip height
+  constexpr int U = FM == 1 ? 4 : 2;
 #pragma unroll
   for (int sg = 0; sg < 2; ++sg) {
     const int K = sg ? K1 : K0;
     if (K <= 0) continue;
     const bool f32 = A1F32 && sg == 1;
-    const gdouble* __restrict__ A = gmem(sg ? (const double*)A1v : A0) + (rok ? row : 0);
-    const gfloat* __restrict__ Af = gmem((const float*)A1v) + (rok ? row : 0);
+    const gdouble* __restrict__ A = gmem(sg ? (const double*)A1v : A0);
+    const gfloat* __restrict__ Af = gmem((const float*)A1v);
     const gdouble* __restrict__ B = gmem(sg ? B1 : B0);
     const size_t lda = sg ? lda1 : lda0, ldb = sg ? ldb1 : ldb0;
     const gdouble* bcol[NF];
@@ -171,18 +183,21 @@ __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, i
       bcol[b] = B + (size_t)(c < N ? c : 0) * ldb;
     }
     for (int k0 = wave * 16; k0 < K; k0 += 64 * U) {
-      double av[U][4], bv[U][NF][4];
-      float af[U][4];
+      double av[U][4][FM], bv[U][NF][4];
+      float af[U][4][FM];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int kr = k0 + 64 * u + 4 * g;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int kk = min(kr + t, K - 1);
-          if (f32)
-            af[u][t] = Af[(size_t)kk * lda];
-          else
-            av[u][t] = A[(size_t)kk * lda];
+#pragma unroll
+          for (int f = 0; f < FM; ++f) {
+            if (f32)
+              af[u][t][f] = Af[rowc[f] + (size_t)kk * lda];
+            else
+              av[u][t][f] = A[rowc[f] + (size_t)kk * lda];
+          }
 #pragma unroll
           for (int b = 0; b < NF; ++b) bv[u][b][t] = bcol[b][kk];
         }
@@ -195,28 +210,35 @@ __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, i
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          if (f32) av[u][t] = (double)af[u][t];
-          if (k0 + 64 * u + 4 * g + t >= K) av[u][t] = 0.0;
-        }
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int f = 0; f < FM; ++f) {
+            if (f32) av[u][t][f] = (double)af[u][t][f];
+            if (k0 + 64 * u + 4 * g + t >= K) av[u][t][f] = 0.0;
+          }
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-          for (int b = 0; b < NF; ++b)
-            acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][t], bv[u][b][t], acc[b], 0, 0, 0);
+          for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int b = 0; b < NF; ++b)
+              acc[f][b] =
+                  __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][t][f], bv[u][b][t], acc[f][b], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int b = 0; b < NF; ++b)
+  for (int f = 0; f < FM; ++f)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) red[wave][b * 4 + r][lane] = acc[b][r];
+    for (int b = 0; b < NF; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wave][(f * NF + b) * 4 + r][lane] = acc[f][b][r];
   __syncthreads();
-  for (int e = threadIdx.x; e < NF * 4 * 64; e += 256) {
+  for (int e = threadIdx.x; e < FM * NF * 4 * 64; e += 256) {
     const int slot = e >> 6, l = e & 63;
-    const int b = slot >> 2, r = slot & 3;
-    const int rr = (l >> 4) + 4 * r;
+    const int f = slot / (NF * 4), b = (slot >> 2) % NF, r = slot & 3;
+    const int rr = 16 * f + (l >> 4) + 4 * r;
     const int c = b * 16 + (l & 15);
     double v = ((red[0][slot][l] + red[1][slot][l]) + red[2][slot][l]) + red[3][slot][l];
     if (r0 + rr < M && c < N) {
