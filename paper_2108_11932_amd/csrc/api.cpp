@@ -410,6 +410,7 @@ tlr_status tlr_destroy(tlr_matrix_t A) {
   A->release_host();
   if (A->ev_fork) (void)hipEventDestroy(A->ev_fork);
   if (A->ev_join) (void)hipEventDestroy(A->ev_join);
+  if (A->ev_gnext) (void)hipEventDestroy(A->ev_gnext);
   if (A->side) (void)hipStreamDestroy(A->side);
   delete A;
   return TLR_OK;

@@ -134,13 +134,27 @@ struct Prob {
   std::vector<long long> goff;
   // column k
   int Rk = 0, nrow = 0, base = 0, roff = 0;
+  // G_ij of the column: blocks j < k - 1 at G + goff, the blocks of the
+  // newest column j = jk = k - 1 at Gk + gkoff[i] (Cholesky), or all of
+  // them at G + goff (jk = -1)
   double* G = nullptr;
-  std::unique_ptr<Plan> dplan;
+  double* Gk = nullptr;
+  int jk = -1;
+  std::vector<long long> gkoff;
+  // blocks j < k of column k + 1, formed ahead on the diagonal-tile stream
+  int ahead = -1;
+  double* Gnext = nullptr;
+  std::vector<long long> goff_next;
+  std::unique_ptr<Plan> dplan, gplan;
   bool side_pending = false;   // the side worker holds this column's launches
   bool host_order = false;     // this column's order was taken on the host
   std::vector<int> order;
   std::vector<char> use32;
   const double* gptr(int i, int j) const {
+    if (j == jk) {
+      const long long go = gkoff[i];
+      return go >= 0 ? Gk + go : Gk;
+    }
     const long long go = goff[(size_t)i * h->nb + j];
     return go >= 0 ? G + go : G;
   }
@@ -194,6 +208,8 @@ tlr_status prob_init(Prob& p, double eps, const tlr_opts& o, bool ldl) {
     TLR_TRY(grow_row(h, i, (int)c));
   }
   p.goff.assign((size_t)nb * nb, -1);
+  p.ahead = -1;
+  p.jk = -1;
   return TLR_OK;
 }
 
@@ -218,16 +234,18 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
     }
     Vk = w.W.as<double>();
   }
-  long long gtot = 0;
-  for (int i = k; i < nb; ++i)
-    for (int j = 0; j < k; ++j) {
-      const int a = h->lr(i, j), b = h->lr(k, j);
-      p.goff[(size_t)i * nb + j] = (a > 0 && b > 0) ? gtot : -1;
-      if (a > 0 && b > 0) gtot += (long long)a * b;
-    }
-  TLR_TRY(w.G.ensure(h->mem, sizeof(double) * (size_t)std::max(gtot, 1LL)));
-  p.G = w.G.as<double>();
-  {
+  if (ldl) {
+    // every block on the main stream (the LDL^T products scale V_kj by D_j)
+    p.jk = -1;
+    long long gtot = 0;
+    for (int i = k; i < nb; ++i)
+      for (int j = 0; j < k; ++j) {
+        const int a = h->lr(i, j), b = h->lr(k, j);
+        p.goff[(size_t)i * nb + j] = (a > 0 && b > 0) ? gtot : -1;
+        if (a > 0 && b > 0) gtot += (long long)a * b;
+      }
+    TLR_TRY(w.G.ensure(h->mem, sizeof(double) * (size_t)std::max(gtot, 1LL)));
+    p.G = w.G.as<double>();
     GemmBatch g(true, false);
     for (int i = k; i < nb; ++i)
       for (int j = 0; j < k; ++j) {
@@ -238,6 +256,59 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
       }
     TLR_TRY(g.run(h));
     p.flops += g.flops;
+  } else {
+    // blocks j < k - 1: formed ahead on the diagonal-tile stream during the
+    // previous column (their panels were final), else here
+    DevBuf& gbuf = (k & 1) ? w.G2 : w.G;
+    if (p.ahead == k) {
+      for (int i = k; i < nb; ++i)
+        for (int j = 0; j < k - 1; ++j) p.goff[(size_t)i * nb + j] = p.goff_next[(size_t)i * nb + j];
+      p.G = p.Gnext;
+      TLR_HIP(hipStreamWaitEvent(h->stream, h->ev_gnext, 0));
+    } else {
+      long long gtot = 0;
+      for (int i = k; i < nb; ++i)
+        for (int j = 0; j < k - 1; ++j) {
+          const int a = h->lr(i, j), b = h->lr(k, j);
+          p.goff[(size_t)i * nb + j] = (a > 0 && b > 0) ? gtot : -1;
+          if (a > 0 && b > 0) gtot += (long long)a * b;
+        }
+      TLR_TRY(gbuf.ensure(h->mem, sizeof(double) * (size_t)std::max(gtot, 1LL)));
+      p.G = gbuf.as<double>();
+      GemmBatch g(true, false);
+      for (int i = k; i < nb; ++i)
+        for (int j = 0; j < k - 1; ++j) {
+          const long long go = p.goff[(size_t)i * nb + j];
+          if (go < 0) continue;
+          const int a = h->lr(i, j), b = h->lr(k, j);
+          g.add(a, b, m, h->vl(i, j), m, Vk + h->lo(k, j) * m, m, p.G + go, a, 1.0, 0.0);
+        }
+      TLR_TRY(g.run(h));
+      p.flops += g.flops;
+    }
+    p.ahead = -1;
+    // blocks of the newest column j = k - 1
+    p.jk = k - 1;
+    p.gkoff.assign(nb, -1);
+    if (k >= 1) {
+      const int j = k - 1;
+      long long gk = 0;
+      for (int i = k; i < nb; ++i) {
+        const int a = h->lr(i, j), b = h->lr(k, j);
+        p.gkoff[i] = (a > 0 && b > 0) ? gk : -1;
+        if (a > 0 && b > 0) gk += (long long)a * b;
+      }
+      TLR_TRY(w.Gk.ensure(h->mem, sizeof(double) * (size_t)std::max(gk, 1LL)));
+      p.Gk = w.Gk.as<double>();
+      GemmBatch g(true, false);
+      for (int i = k; i < nb; ++i) {
+        if (p.gkoff[i] < 0) continue;
+        const int a = h->lr(i, j), b = h->lr(k, j);
+        g.add(a, b, m, h->vl(i, j), m, Vk + h->lo(k, j) * m, m, p.Gk + p.gkoff[i], a, 1.0, 0.0);
+      }
+      TLR_TRY(g.run(h));
+      p.flops += g.flops;
+    }
   }
   // ---------------------------------------------- updateDense + chol / ldl
   // on the diagonal-tile stream: they need only the G blocks and row k's
@@ -279,12 +350,51 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
     // the staged descriptors go up from this thread; the launches are
     // issued by the handle's side worker, which also records the join
     TLR_TRY(dplan.run_some(0));
+    // lookahead (Cholesky): the blocks j < k of column k + 1's G read only
+    // panels that are final, so they are formed on this stream after the
+    // diagonal tile, while the main stream runs this column's iterations;
+    // their buffer was last read by column k - 1, whose launches precede
+    // the fork above
+    p.gplan.reset();
+    if (!ldl && k + 1 < nb && k >= 1) {
+      const int kn = k + 1;
+      p.goff_next.assign((size_t)nb * nb, -1);
+      long long gt = 0;
+      for (int i = kn; i < nb; ++i)
+        for (int j = 0; j < k; ++j) {
+          const int a = h->lr(i, j), b = h->lr(kn, j);
+          p.goff_next[(size_t)i * nb + j] = (a > 0 && b > 0) ? gt : -1;
+          if (a > 0 && b > 0) gt += (long long)a * b;
+        }
+      DevBuf& nbuf = (kn & 1) ? w.G2 : w.G;
+      TLR_TRY(nbuf.ensure(h->mem, sizeof(double) * (size_t)std::max(gt, 1LL)));
+      p.Gnext = nbuf.as<double>();
+      GemmBatch g(true, false);
+      for (int i = kn; i < nb; ++i)
+        for (int j = 0; j < k; ++j) {
+          const long long go = p.goff_next[(size_t)i * nb + j];
+          if (go < 0) continue;
+          const int a = h->lr(i, j), b = h->lr(kn, j);
+          g.add(a, b, m, h->vl(i, j), m, h->vl(kn, j), m, p.Gnext + go, a, 1.0, 0.0);
+        }
+      p.gplan.reset(new Plan(h, ds));
+      p.gplan->persist = &w.sideblob2;
+      p.gplan->gemm(g);
+      TLR_TRY(p.gplan->run_some(0));
+      p.flops += g.flops;
+      p.ahead = kn;
+    }
     if (!h->worker) h->worker.reset(new SideWorker(h->dev));
     std::shared_ptr<Plan> plan(p.dplan.release());
-    hipEvent_t ej = h->ev_join;
-    h->worker->submit([plan, ej, ds]() -> tlr_status {
+    std::shared_ptr<Plan> gplan(p.gplan.release());
+    hipEvent_t ej = h->ev_join, eg = h->ev_gnext;
+    h->worker->submit([plan, gplan, ej, eg, ds]() -> tlr_status {
       TLR_TRY(plan->run());
       TLR_HIP(hipEventRecord(ej, ds));
+      if (gplan) {
+        TLR_TRY(gplan->run());
+        TLR_HIP(hipEventRecord(eg, ds));
+      }
       return TLR_OK;
     });
     p.side_pending = true;

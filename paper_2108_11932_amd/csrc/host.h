@@ -194,14 +194,14 @@ class SideWorker {
 // Per-column workspace of the factorization.
 struct Work {
   DevBuf G, W, omega, P, Z, T, Ta, H, Ball, C, Wa, Y, Q, part, ints, orth, dscale, tol,
-      compact, Bt, fro, tnpart, splitk;
+      compact, Bt, fro, tnpart, splitk, G2, Gk;
   // buffers of the diagonal-tile stream (never touched by the main stream)
-  DevBuf Wd, dW, dtol, sideblob;
+  DevBuf Wd, dW, dtol, sideblob, sideblob2;
   int slots = 0;   // slot capacity of the per-tile buffers
   void release_all(Mem& mem) {
     DevBuf* bufs[] = {&G, &W, &omega, &P, &Z, &T, &Ta, &H, &Ball, &C, &Wa, &Y, &Q, &part,
-                      &ints, &orth, &dscale, &tol, &compact, &Bt, &fro, &tnpart, &splitk, &Wd,
-                      &dW, &dtol, &sideblob};
+                      &ints, &orth, &dscale, &tol, &compact, &Bt, &fro, &tnpart, &splitk, &G2,
+                      &Gk, &Wd, &dW, &dtol, &sideblob, &sideblob2};
     for (DevBuf* b : bufs) b->release(mem);
   }
 };
@@ -218,7 +218,7 @@ struct tlr_matrix_s {
   Mem mem;
   hipStream_t stream = nullptr;   // caller's stream: everything is ordered on it
   hipStream_t side = nullptr;     // library stream for the diagonal tiles (default priority)
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gnext = nullptr;
   std::unique_ptr<tlr::SideWorker> worker;   // issues the side-stream launches
   Staging stage;
   int* pin_back = nullptr;        // pinned read-back area

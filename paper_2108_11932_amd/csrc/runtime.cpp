@@ -198,6 +198,7 @@ tlr_status tlr_matrix_s::init_streams() {
     TLR_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
     TLR_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
     TLR_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    TLR_HIP(hipEventCreateWithFlags(&ev_gnext, hipEventDisableTiming));
   }
   return TLR_OK;
 }
