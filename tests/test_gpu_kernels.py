@@ -202,6 +202,31 @@ def test_ara_threshold_and_eckart_young():
     assert over <= 2
 
 
+def test_ara_wide_launch_matches_narrow_launches():
+    """A launch with enough active tiles samples on 64-row strips, narrower
+    ones on 16-row strips; the accumulation order is the same, so a tile's
+    basis and projection do not depend on how many tiles share its
+    launches.  m = 80 leaves a ragged last strip block."""
+    import torch
+    m, count, tau = 80, 300, 1e-9
+    mats = [3.0 * _lowrank_tile(m, t % 23, 500 + t) if t % 23 else np.zeros((m, m))
+            for t in range(count)]
+    tiles = torch.stack([dev(a).reshape(m, m) for a in mats])
+    Q, B, ranks, iters = tlr.ara(tiles, tau, bs=16, seed=11)
+    for lo in range(0, count, 100):
+        q2, b2, r2, it2 = tlr.ara(tiles[lo:lo + 100].contiguous(), tau, bs=16, seed=11)
+        assert list(r2) == list(ranks[lo:lo + 100])
+        assert list(it2) == list(iters[lo:lo + 100])
+        assert torch.equal(q2.cpu(), Q[lo:lo + 100].cpu())
+        assert torch.equal(b2.cpu(), B[lo:lo + 100].cpu())
+    for t in range(count):
+        r = t % 23
+        assert ranks[t] == r
+        q = host(Q[t].reshape(-1), m, m)[:, :r]
+        b = host(B[t].reshape(-1), m, m)[:, :r]
+        assert np.linalg.norm(mats[t] - q @ b.T, 2) < 1e-10
+
+
 def test_sort_ranks_bit_exact():
     rng = np.random.default_rng(3)
     for n in (1, 5, 127, 300):
