@@ -223,32 +223,49 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
   p.Rk = h->R[k];
   const int Rk = p.Rk;
   // ---------------------------------------------- G_ij = V_ij^T (D_j) V_kj
+  // Blocks j < k - 1 are formed ahead on the diagonal-tile stream during the
+  // previous column (their panels and pivots were final), else here; the
+  // blocks of the newest column j = k - 1 are formed here.  LDL^T multiplies
+  // by V_kj D_j, the row panel scaled block by block.
+  const bool ahead = p.ahead == k;
+  p.ahead = -1;
   const double* Vk = h->VL[k];
   if (ldl && Rk > 0) {
     TLR_TRY(w.W.ensure(h->mem, sizeof(double) * (size_t)m * Rk));
-    for (int j = 0; j < k; ++j) {
-      const int r = h->lr(k, j);
-      if (r == 0) continue;
-      TLR_HIP(launch_scale_rows(h->vl(k, j), m, w.W.as<double>() + h->lo(k, j) * m, m,
-                                h->Dv + (size_t)j * m, m, r, false, h->stream));
+    // the columns to scale: the newest block only when the others were
+    // formed ahead, else the whole panel
+    const int c0 = (ahead && k >= 1 && h->lr(k, k - 1) > 0) ? (int)h->lo(k, k - 1) : (ahead ? Rk : 0);
+    if (c0 < Rk) {
+      std::vector<int> colj;
+      for (int j = 0; j < k; ++j)
+        for (int c = 0; c < h->lr(k, j); ++c)
+          if (h->lo(k, j) + c >= c0) colj.push_back(j);
+      void* dcol = nullptr;
+      TLR_TRY(h->stage.upload(h, colj.data(), sizeof(int) * colj.size(), &dcol));
+      TLR_HIP(launch_scale_panel(h->VL[k] + (size_t)c0 * m, m, w.W.as<double>() + (size_t)c0 * m,
+                                 m, m, (int)colj.size(), (const int*)dcol, h->Dv, h->stream));
     }
     Vk = w.W.as<double>();
   }
-  if (ldl) {
-    // every block on the main stream (the LDL^T products scale V_kj by D_j)
-    p.jk = -1;
+  DevBuf& gbuf = (k & 1) ? w.G2 : w.G;
+  if (ahead) {
+    for (int i = k; i < nb; ++i)
+      for (int j = 0; j < k - 1; ++j) p.goff[(size_t)i * nb + j] = p.goff_next[(size_t)i * nb + j];
+    p.G = p.Gnext;
+    TLR_HIP(hipStreamWaitEvent(h->stream, h->ev_gnext, 0));
+  } else {
     long long gtot = 0;
     for (int i = k; i < nb; ++i)
-      for (int j = 0; j < k; ++j) {
+      for (int j = 0; j < k - 1; ++j) {
         const int a = h->lr(i, j), b = h->lr(k, j);
         p.goff[(size_t)i * nb + j] = (a > 0 && b > 0) ? gtot : -1;
         if (a > 0 && b > 0) gtot += (long long)a * b;
       }
-    TLR_TRY(w.G.ensure(h->mem, sizeof(double) * (size_t)std::max(gtot, 1LL)));
-    p.G = w.G.as<double>();
+    TLR_TRY(gbuf.ensure(h->mem, sizeof(double) * (size_t)std::max(gtot, 1LL)));
+    p.G = gbuf.as<double>();
     GemmBatch g(true, false);
     for (int i = k; i < nb; ++i)
-      for (int j = 0; j < k; ++j) {
+      for (int j = 0; j < k - 1; ++j) {
         const long long go = p.goff[(size_t)i * nb + j];
         if (go < 0) continue;
         const int a = h->lr(i, j), b = h->lr(k, j);
@@ -256,59 +273,27 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
       }
     TLR_TRY(g.run(h));
     p.flops += g.flops;
-  } else {
-    // blocks j < k - 1: formed ahead on the diagonal-tile stream during the
-    // previous column (their panels were final), else here
-    DevBuf& gbuf = (k & 1) ? w.G2 : w.G;
-    if (p.ahead == k) {
-      for (int i = k; i < nb; ++i)
-        for (int j = 0; j < k - 1; ++j) p.goff[(size_t)i * nb + j] = p.goff_next[(size_t)i * nb + j];
-      p.G = p.Gnext;
-      TLR_HIP(hipStreamWaitEvent(h->stream, h->ev_gnext, 0));
-    } else {
-      long long gtot = 0;
-      for (int i = k; i < nb; ++i)
-        for (int j = 0; j < k - 1; ++j) {
-          const int a = h->lr(i, j), b = h->lr(k, j);
-          p.goff[(size_t)i * nb + j] = (a > 0 && b > 0) ? gtot : -1;
-          if (a > 0 && b > 0) gtot += (long long)a * b;
-        }
-      TLR_TRY(gbuf.ensure(h->mem, sizeof(double) * (size_t)std::max(gtot, 1LL)));
-      p.G = gbuf.as<double>();
-      GemmBatch g(true, false);
-      for (int i = k; i < nb; ++i)
-        for (int j = 0; j < k - 1; ++j) {
-          const long long go = p.goff[(size_t)i * nb + j];
-          if (go < 0) continue;
-          const int a = h->lr(i, j), b = h->lr(k, j);
-          g.add(a, b, m, h->vl(i, j), m, Vk + h->lo(k, j) * m, m, p.G + go, a, 1.0, 0.0);
-        }
-      TLR_TRY(g.run(h));
-      p.flops += g.flops;
+  }
+  p.jk = k - 1;
+  p.gkoff.assign(nb, -1);
+  if (k >= 1) {
+    const int j = k - 1;
+    long long gk = 0;
+    for (int i = k; i < nb; ++i) {
+      const int a = h->lr(i, j), b = h->lr(k, j);
+      p.gkoff[i] = (a > 0 && b > 0) ? gk : -1;
+      if (a > 0 && b > 0) gk += (long long)a * b;
     }
-    p.ahead = -1;
-    // blocks of the newest column j = k - 1
-    p.jk = k - 1;
-    p.gkoff.assign(nb, -1);
-    if (k >= 1) {
-      const int j = k - 1;
-      long long gk = 0;
-      for (int i = k; i < nb; ++i) {
-        const int a = h->lr(i, j), b = h->lr(k, j);
-        p.gkoff[i] = (a > 0 && b > 0) ? gk : -1;
-        if (a > 0 && b > 0) gk += (long long)a * b;
-      }
-      TLR_TRY(w.Gk.ensure(h->mem, sizeof(double) * (size_t)std::max(gk, 1LL)));
-      p.Gk = w.Gk.as<double>();
-      GemmBatch g(true, false);
-      for (int i = k; i < nb; ++i) {
-        if (p.gkoff[i] < 0) continue;
-        const int a = h->lr(i, j), b = h->lr(k, j);
-        g.add(a, b, m, h->vl(i, j), m, Vk + h->lo(k, j) * m, m, p.Gk + p.gkoff[i], a, 1.0, 0.0);
-      }
-      TLR_TRY(g.run(h));
-      p.flops += g.flops;
+    TLR_TRY(w.Gk.ensure(h->mem, sizeof(double) * (size_t)std::max(gk, 1LL)));
+    p.Gk = w.Gk.as<double>();
+    GemmBatch g(true, false);
+    for (int i = k; i < nb; ++i) {
+      if (p.gkoff[i] < 0) continue;
+      const int a = h->lr(i, j), b = h->lr(k, j);
+      g.add(a, b, m, h->vl(i, j), m, Vk + h->lo(k, j) * m, m, p.Gk + p.gkoff[i], a, 1.0, 0.0);
     }
+    TLR_TRY(g.run(h));
+    p.flops += g.flops;
   }
   // ---------------------------------------------- updateDense + chol / ldl
   // on the diagonal-tile stream: they need only the G blocks and row k's
@@ -356,7 +341,7 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
     // their buffer was last read by column k - 1, whose launches precede
     // the fork above
     p.gplan.reset();
-    if (!ldl && k + 1 < nb && k >= 1) {
+    if (k + 1 < nb && k >= 1) {
       const int kn = k + 1;
       p.goff_next.assign((size_t)nb * nb, -1);
       long long gt = 0;
@@ -369,16 +354,36 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
       DevBuf& nbuf = (kn & 1) ? w.G2 : w.G;
       TLR_TRY(nbuf.ensure(h->mem, sizeof(double) * (size_t)std::max(gt, 1LL)));
       p.Gnext = nbuf.as<double>();
+      p.gplan.reset(new Plan(h, ds));
+      p.gplan->persist = &w.sideblob2;
+      // LDL^T: the blocks j < k of row k + 1's panel scaled by D_j (D_k is
+      // being formed on this stream, before these launches)
+      const double* Vn = h->VL[kn];
+      if (ldl) {
+        std::vector<int> colj;
+        for (int j = 0; j < k; ++j)
+          for (int c = 0; c < h->lr(kn, j); ++c) colj.push_back(j);
+        if (!colj.empty()) {
+          TLR_TRY(w.Wn.ensure(h->mem, sizeof(double) * (size_t)m * colj.size()));
+          double* Wn = w.Wn.as<double>();
+          const double* src = h->VL[kn];
+          const double* Dv = h->Dv;
+          const int nc = (int)colj.size();
+          const size_t off = p.gplan->stage(colj.data(), sizeof(int) * colj.size());
+          p.gplan->launch(off, [=](const char* ptr) {
+            return launch_scale_panel(src, m, Wn, m, m, nc, (const int*)ptr, Dv, ds);
+          });
+          Vn = Wn;
+        }
+      }
       GemmBatch g(true, false);
       for (int i = kn; i < nb; ++i)
         for (int j = 0; j < k; ++j) {
           const long long go = p.goff_next[(size_t)i * nb + j];
           if (go < 0) continue;
           const int a = h->lr(i, j), b = h->lr(kn, j);
-          g.add(a, b, m, h->vl(i, j), m, h->vl(kn, j), m, p.Gnext + go, a, 1.0, 0.0);
+          g.add(a, b, m, h->vl(i, j), m, Vn + h->lo(kn, j) * m, m, p.Gnext + go, a, 1.0, 0.0);
         }
-      p.gplan.reset(new Plan(h, ds));
-      p.gplan->persist = &w.sideblob2;
       p.gplan->gemm(g);
       TLR_TRY(p.gplan->run_some(0));
       p.flops += g.flops;

@@ -196,12 +196,12 @@ struct Work {
   DevBuf G, W, omega, P, Z, T, Ta, H, Ball, C, Wa, Y, Q, part, ints, orth, dscale, tol,
       compact, Bt, fro, tnpart, splitk, G2, Gk;
   // buffers of the diagonal-tile stream (never touched by the main stream)
-  DevBuf Wd, dW, dtol, sideblob, sideblob2;
+  DevBuf Wd, dW, dtol, sideblob, sideblob2, Wn;
   int slots = 0;   // slot capacity of the per-tile buffers
   void release_all(Mem& mem) {
     DevBuf* bufs[] = {&G, &W, &omega, &P, &Z, &T, &Ta, &H, &Ball, &C, &Wa, &Y, &Q, &part,
                       &ints, &orth, &dscale, &tol, &compact, &Bt, &fro, &tnpart, &splitk, &G2,
-                      &Gk, &Wd, &dW, &dtol, &sideblob, &sideblob2};
+                      &Gk, &Wd, &dW, &dtol, &sideblob, &sideblob2, &Wn};
     for (DevBuf* b : bufs) b->release(mem);
   }
 };

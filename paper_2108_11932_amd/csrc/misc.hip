@@ -62,6 +62,17 @@ __global__ void k_scale_rows(const double* in, int ldi, double* out, int ldo, co
   out[r + (size_t)c * ldo] = inverse ? v / dg[r] : v * dg[r];
 }
 
+// W(:, c) = V(:, c) * D_{colj[c]} (rows scaled by the pivots of the column's
+// block: the V_kj D_j of a whole LDL^T row panel in one launch).
+__global__ void k_scale_panel(const double* __restrict__ V, int ldv, double* __restrict__ W,
+                              int ldw, int m, int ncols, const int* __restrict__ colj,
+                              const double* __restrict__ Dv) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= (long long)m * ncols) return;
+  const int r = (int)(e % m), c = (int)(e / m);
+  W[r + (size_t)c * ldw] = V[r + (size_t)c * ldv] * Dv[(size_t)colj[c] * m + r];
+}
+
 __global__ void k_zero_upper(double* A, int lda, int m) {
   const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (e >= (long long)m * m) return;
@@ -159,6 +170,15 @@ hipError_t launch_scale_rows(const double* in, int ldi, double* out, int ldo, co
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, ldi, out,
                      ldo, dg, rows, cols, inverse ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_panel(const double* V, int ldv, double* W, int ldw, int m, int ncols,
+                              const int* colj, const double* Dv, hipStream_t s) {
+  const long long n = (long long)m * ncols;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_panel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, V, ldv, W,
+                     ldw, m, ncols, colj, Dv);
   return hipGetLastError();
 }
 

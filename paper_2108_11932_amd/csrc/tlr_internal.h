@@ -251,6 +251,9 @@ hipError_t launch_copy_batched(const CopyDesc* d, int n, int max_cols, hipStream
 // dst = src (m x m) + shift on the first nreal diagonal entries.
 hipError_t launch_copy_shift(const double* src, double* dst, int m, int nreal, double shift,
                              hipStream_t s);
+// W(:, c) = V(:, c) .* Dv(:, colj[c]) (Dv m x nb, colj device, ncols entries).
+hipError_t launch_scale_panel(const double* V, int ldv, double* W, int ldw, int m, int ncols,
+                              const int* colj, const double* Dv, hipStream_t s);
 // out(r, c) = d[r] * in(r, c) (row scaling) or in(r, c) / d[r].
 hipError_t launch_scale_rows(const double* in, int ldi, double* out, int ldo, const double* d,
                              int rows, int cols, bool inverse, hipStream_t s);
