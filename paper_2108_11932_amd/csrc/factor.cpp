@@ -590,10 +590,11 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
       TLR_TRY(w.splitk.ensure(h->mem, need));
     }
   }
-  Plan plan(h);
-  plan.splitk = &w.splitk;
+  // The products that need only the bases go out first, so the GPU works on
+  // them while the host builds the per-block batch of the update term.
   {
-    GemmBatch t1(true, false), t2(true, false), hb(true, false), b1(false, false), b2(false, false);
+    Plan first(h);
+    GemmBatch t1(true, false), t2(true, false), b1(false, false);
     for (int s = 0; s < nrow; ++s) {
       const int i = k + 1 + s, qs = q[s];
       if (qs == 0) continue;
@@ -601,7 +602,26 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
       const double* Qs = slots.qb(p.base + s);
       if (Ri > 0) t1.add(Ri, qs, m, h->UL[i], m, Qs, m, T + toff[s], Ri, 1.0, 0.0);
       if (a > 0) t2.add(a, qs, m, h->ua(i, k), m, Qs, m, Ta + taoff[s], a, 1.0, 0.0);
-      if (Rk > 0) {
+      b1.add(m, qs, a, h->va(i, k), m, Ta + taoff[s], std::max(a, 1), Ball + boff[s] * m, m, 1.0,
+             0.0);
+    }
+    // t1 and t2 stream the same basis blocks Q_i: one batch
+    for (const GemmDesc& d : t2.d) t1.d.push_back(d);
+    t1.flops += t2.flops;
+    first.gemm(t1);
+    first.gemm(b1);
+    TLR_TRY(first.run());
+    p.flops += first.flops;
+  }
+  Plan plan(h);
+  plan.splitk = &w.splitk;
+  {
+    GemmBatch hb(true, false), b2(false, false);
+    if (Rk > 0) {
+      for (int s = 0; s < nrow; ++s) {
+        const int i = k + 1 + s, qs = q[s];
+        if (qs == 0) continue;
+        const int Ri = h->R[i];
         for (int j = 0; j < k; ++j) {
           const int rkj = h->lr(k, j);
           if (rkj == 0) continue;
@@ -610,16 +630,9 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
                  std::max(Ri, 1), H + boff[s] * Rk + h->lo(k, j), Rk, 1.0, 0.0);
         }
       }
-      b1.add(m, qs, a, h->va(i, k), m, Ta + taoff[s], std::max(a, 1), Ball + boff[s] * m, m, 1.0,
-             0.0);
     }
     if (Rk > 0 && sq > 0) b2.add(m, (int)sq, Rk, h->UL[k], m, H, Rk, Ball, m, -1.0, 1.0);
-    // t1 and t2 stream the same basis blocks Q_i: one batch
-    for (const GemmDesc& d : t2.d) t1.d.push_back(d);
-    t1.flops += t2.flops;
-    plan.gemm(t1);
     plan.gemm(hb);
-    plan.gemm(b1);
     plan.gemm(b2);
   }
   // ---------------------------------------------- batchTrsm (+ batchIDMult)
