@@ -335,71 +335,12 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
     // the staged descriptors go up from this thread; the launches are
     // issued by the handle's side worker, which also records the join
     TLR_TRY(dplan.run_some(0));
-    // lookahead (Cholesky): the blocks j < k of column k + 1's G read only
-    // panels that are final, so they are formed on this stream after the
-    // diagonal tile, while the main stream runs this column's iterations;
-    // their buffer was last read by column k - 1, whose launches precede
-    // the fork above
-    p.gplan.reset();
-    if (k + 1 < nb && k >= 1) {
-      const int kn = k + 1;
-      p.goff_next.assign((size_t)nb * nb, -1);
-      long long gt = 0;
-      for (int i = kn; i < nb; ++i)
-        for (int j = 0; j < k; ++j) {
-          const int a = h->lr(i, j), b = h->lr(kn, j);
-          p.goff_next[(size_t)i * nb + j] = (a > 0 && b > 0) ? gt : -1;
-          if (a > 0 && b > 0) gt += (long long)a * b;
-        }
-      DevBuf& nbuf = (kn & 1) ? w.G2 : w.G;
-      TLR_TRY(nbuf.ensure(h->mem, sizeof(double) * (size_t)std::max(gt, 1LL)));
-      p.Gnext = nbuf.as<double>();
-      p.gplan.reset(new Plan(h, ds));
-      p.gplan->persist = &w.sideblob2;
-      // LDL^T: the blocks j < k of row k + 1's panel scaled by D_j (D_k is
-      // being formed on this stream, before these launches)
-      const double* Vn = h->VL[kn];
-      if (ldl) {
-        std::vector<int> colj;
-        for (int j = 0; j < k; ++j)
-          for (int c = 0; c < h->lr(kn, j); ++c) colj.push_back(j);
-        if (!colj.empty()) {
-          TLR_TRY(w.Wn.ensure(h->mem, sizeof(double) * (size_t)m * colj.size()));
-          double* Wn = w.Wn.as<double>();
-          const double* src = h->VL[kn];
-          const double* Dv = h->Dv;
-          const int nc = (int)colj.size();
-          const size_t off = p.gplan->stage(colj.data(), sizeof(int) * colj.size());
-          p.gplan->launch(off, [=](const char* ptr) {
-            return launch_scale_panel(src, m, Wn, m, m, nc, (const int*)ptr, Dv, ds);
-          });
-          Vn = Wn;
-        }
-      }
-      GemmBatch g(true, false);
-      for (int i = kn; i < nb; ++i)
-        for (int j = 0; j < k; ++j) {
-          const long long go = p.goff_next[(size_t)i * nb + j];
-          if (go < 0) continue;
-          const int a = h->lr(i, j), b = h->lr(kn, j);
-          g.add(a, b, m, h->vl(i, j), m, Vn + h->lo(kn, j) * m, m, p.Gnext + go, a, 1.0, 0.0);
-        }
-      p.gplan->gemm(g);
-      TLR_TRY(p.gplan->run_some(0));
-      p.flops += g.flops;
-      p.ahead = kn;
-    }
     if (!h->worker) h->worker.reset(new SideWorker(h->dev));
     std::shared_ptr<Plan> plan(p.dplan.release());
-    std::shared_ptr<Plan> gplan(p.gplan.release());
-    hipEvent_t ej = h->ev_join, eg = h->ev_gnext;
-    h->worker->submit([plan, gplan, ej, eg, ds]() -> tlr_status {
+    hipEvent_t ej = h->ev_join;
+    h->worker->submit([plan, ej, ds]() -> tlr_status {
       TLR_TRY(plan->run());
       TLR_HIP(hipEventRecord(ej, ds));
-      if (gplan) {
-        TLR_TRY(gplan->run());
-        TLR_HIP(hipEventRecord(eg, ds));
-      }
       return TLR_OK;
     });
     p.side_pending = true;
@@ -434,6 +375,75 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
     TLR_HIP(launch_sort_ranks((const int*)dr, (const int*)dw, nrow, order_out, h->stream));
     TLR_HIP(hipMemcpyAsync(p.pin_order, order_out, sizeof(int) * nrow, hipMemcpyDeviceToHost,
                            h->stream));
+  }
+  return TLR_OK;
+}
+
+// Lookahead: the blocks j < k of column k + 1's G read only panels (and,
+// for LDL^T, pivots) that are final, so they are formed on the diagonal-tile
+// stream after column k's diagonal tile, while the main stream runs column
+// k's iterations; the host builds the batch in the first wait of those
+// iterations.  Their buffer was last read by column k - 1, whose launches
+// precede column k's fork to that stream.
+tlr_status col_lookahead(Prob& p, int k, bool ldl) {
+  Handle* h = p.h;
+  const int m = h->m, nb = h->nb;
+  Work& w = h->ws;
+  hipStream_t ds = h->side;
+  if (k + 1 < nb && k >= 1) {
+    const int kn = k + 1;
+    p.goff_next.assign((size_t)nb * nb, -1);
+    long long gt = 0;
+    for (int i = kn; i < nb; ++i)
+      for (int j = 0; j < k; ++j) {
+        const int a = h->lr(i, j), b = h->lr(kn, j);
+        p.goff_next[(size_t)i * nb + j] = (a > 0 && b > 0) ? gt : -1;
+        if (a > 0 && b > 0) gt += (long long)a * b;
+      }
+    DevBuf& nbuf = (kn & 1) ? w.G2 : w.G;
+    TLR_TRY(nbuf.ensure(h->mem, sizeof(double) * (size_t)std::max(gt, 1LL)));
+    p.Gnext = nbuf.as<double>();
+    p.gplan.reset(new Plan(h, ds));
+    p.gplan->persist = &w.sideblob2;
+    // LDL^T: the blocks j < k of row k + 1's panel scaled by D_j (D_k is
+    // being formed on this stream, before these launches)
+    const double* Vn = h->VL[kn];
+    if (ldl) {
+      std::vector<int> colj;
+      for (int j = 0; j < k; ++j)
+        for (int c = 0; c < h->lr(kn, j); ++c) colj.push_back(j);
+      if (!colj.empty()) {
+        TLR_TRY(w.Wn.ensure(h->mem, sizeof(double) * (size_t)m * colj.size()));
+        double* Wn = w.Wn.as<double>();
+        const double* src = h->VL[kn];
+        const double* Dv = h->Dv;
+        const int nc = (int)colj.size();
+        const size_t off = p.gplan->stage(colj.data(), sizeof(int) * colj.size());
+        p.gplan->launch(off, [=](const char* ptr) {
+          return launch_scale_panel(src, m, Wn, m, m, nc, (const int*)ptr, Dv, ds);
+        });
+        Vn = Wn;
+      }
+    }
+    GemmBatch g(true, false);
+    for (int i = kn; i < nb; ++i)
+      for (int j = 0; j < k; ++j) {
+        const long long go = p.goff_next[(size_t)i * nb + j];
+        if (go < 0) continue;
+        const int a = h->lr(i, j), b = h->lr(kn, j);
+        g.add(a, b, m, h->vl(i, j), m, Vn + h->lo(kn, j) * m, m, p.Gnext + go, a, 1.0, 0.0);
+      }
+    p.gplan->gemm(g);
+    TLR_TRY(p.gplan->run_some(0));
+    p.flops += g.flops;
+    p.ahead = kn;
+    std::shared_ptr<Plan> gplan(p.gplan.release());
+    hipEvent_t eg = h->ev_gnext;
+    h->worker->submit([gplan, eg, ds]() -> tlr_status {
+      TLR_TRY(gplan->run());
+      TLR_HIP(hipEventRecord(eg, ds));
+      return TLR_OK;
+    });
   }
   return TLR_OK;
 }
@@ -872,7 +882,17 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
     AraResult res;
     cfg.stream_id = (unsigned)k;
     bool abort = false;
-    TLR_TRY(ara_run(lead, cfg, slots, order, spec, &res, single ? &abort : nullptr));
+    // the first wait of the iterations builds the next column's lookahead
+    bool looked = false;
+    auto lookahead = [&]() -> tlr_status {
+      if (looked) return TLR_OK;
+      looked = true;
+      for (int pi : live)
+        if (!ps[pi].done) TLR_TRY(col_lookahead(ps[pi], k, ldl));
+      return TLR_OK;
+    };
+    TLR_TRY(ara_run(lead, cfg, slots, order, spec, &res, single ? &abort : nullptr, lookahead));
+    TLR_TRY(lookahead());
     for (int pi : live) TLR_TRY(side_done(ps[pi]));
     if (abort) {
       ps[idx[0]].done = true;
