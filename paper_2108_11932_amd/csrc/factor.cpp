@@ -298,16 +298,58 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
   // ---------------------------------------------- updateDense + chol / ldl
   // on the diagonal-tile stream: they need only the G blocks and row k's
   // panels, and the column's ARA needs L_kk only at the triangular solve
+  TLR_HIP(hipEventRecord(h->ev_fork, h->stream));
+  TLR_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+  p.flops_paper += 2.0 * m * (double)m * Rk + (double)m * m * m / 3.0;
+  p.flops += (double)m * m * m / 3.0 + (double)m * m * m / 3.0;
+  p.nrow = nb - k - 1;
+  // ---------------------------------------------- sortRanks
+  // Without mixed precision nothing else of the previous column is needed
+  // on the host, so the order (descending input rank, ties by row) is taken
+  // here and the device queue is not drained; the mixed form sorts on the
+  // device and reads the order back with the previous column's V norms.
+  p.host_order = !h->mixed;
+  p.order.clear();
+  if (p.nrow > 0 && p.host_order) {
+    p.order.resize(p.nrow);
+    for (int s = 0; s < p.nrow; ++s) p.order[s] = s;
+    std::stable_sort(p.order.begin(), p.order.end(), [&](int a, int b) {
+      return h->ar(k + 1 + a, k) > h->ar(k + 1 + b, k);
+    });
+  } else if (p.nrow > 0) {
+    const int nrow = p.nrow;
+    std::vector<int> rk(nrow), rows(nrow);
+    for (int s = 0; s < nrow; ++s) {
+      rk[s] = h->ar(k + 1 + s, k);
+      rows[s] = s;
+    }
+    void* dr = nullptr;
+    void* dw = nullptr;
+    TLR_TRY(h->stage.upload(h, rk.data(), sizeof(int) * nrow, &dr));
+    TLR_TRY(h->stage.upload(h, rows.data(), sizeof(int) * nrow, &dw));
+    TLR_HIP(launch_sort_ranks((const int*)dr, (const int*)dw, nrow, order_out, h->stream));
+    TLR_HIP(hipMemcpyAsync(p.pin_order, order_out, sizeof(int) * nrow, hipMemcpyDeviceToHost,
+                           h->stream));
+  }
+  return TLR_OK;
+}
+
+// The launches of column k's diagonal tile (dense update, factorization,
+// inverse) on the diagonal-tile stream, which waits for the fork recorded by
+// col_begin.  The host builds them in the first wait of the column's
+// iterations (the main stream then holds two iterations of work); the
+// column's iterations need L_kk only at the triangular solve.
+tlr_status col_diag(Prob& p, int k, bool ldl) {
+  Handle* h = p.h;
+  const int m = h->m;
+  const int Rk = p.Rk;
+  Work& w = h->ws;
   double* Lkk = h->diagL(k);
   hipStream_t ds = h->side;
-  TLR_HIP(hipEventRecord(h->ev_fork, h->stream));
-  TLR_HIP(hipStreamWaitEvent(ds, h->ev_fork, 0));
   if (Rk > 0 && w.Wd.cap < sizeof(double) * (size_t)m * Rk) {
     TLR_HIP(hipStreamSynchronize(ds));
     TLR_TRY(w.Wd.ensure(h->mem, sizeof(double) * (size_t)m * Rk));
   }
-  // the launches of the diagonal-tile stream are issued a few at a time
-  // while the host waits on the ARA iterations of the main stream
   p.dplan.reset(new Plan(h, ds));
   Plan& dplan = *p.dplan;
   dplan.persist = &w.sideblob;
@@ -344,37 +386,6 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
       return TLR_OK;
     });
     p.side_pending = true;
-  }
-  p.flops_paper += 2.0 * m * (double)m * Rk + (double)m * m * m / 3.0;
-  p.flops += (double)m * m * m / 3.0 + (double)m * m * m / 3.0;
-  p.nrow = nb - k - 1;
-  // ---------------------------------------------- sortRanks
-  // Without mixed precision nothing else of the previous column is needed
-  // on the host, so the order (descending input rank, ties by row) is taken
-  // here and the device queue is not drained; the mixed form sorts on the
-  // device and reads the order back with the previous column's V norms.
-  p.host_order = !h->mixed;
-  p.order.clear();
-  if (p.nrow > 0 && p.host_order) {
-    p.order.resize(p.nrow);
-    for (int s = 0; s < p.nrow; ++s) p.order[s] = s;
-    std::stable_sort(p.order.begin(), p.order.end(), [&](int a, int b) {
-      return h->ar(k + 1 + a, k) > h->ar(k + 1 + b, k);
-    });
-  } else if (p.nrow > 0) {
-    const int nrow = p.nrow;
-    std::vector<int> rk(nrow), rows(nrow);
-    for (int s = 0; s < nrow; ++s) {
-      rk[s] = h->ar(k + 1 + s, k);
-      rows[s] = s;
-    }
-    void* dr = nullptr;
-    void* dw = nullptr;
-    TLR_TRY(h->stage.upload(h, rk.data(), sizeof(int) * nrow, &dr));
-    TLR_TRY(h->stage.upload(h, rows.data(), sizeof(int) * nrow, &dw));
-    TLR_HIP(launch_sort_ranks((const int*)dr, (const int*)dw, nrow, order_out, h->stream));
-    TLR_HIP(hipMemcpyAsync(p.pin_order, order_out, sizeof(int) * nrow, hipMemcpyDeviceToHost,
-                           h->stream));
   }
   return TLR_OK;
 }
@@ -849,8 +860,10 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
                        });
       for (auto& kv : key) order.push_back(kv.second);
     }
+    // a problem at its last column has only its diagonal tile left
     for (int pi : live)
       if (ps[pi].nrow == 0) {
+        TLR_TRY(col_diag(ps[pi], k, ldl));
         TLR_TRY(side_done(ps[pi]));
         ps[pi].done = true;
       }
@@ -888,7 +901,10 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
       if (looked) return TLR_OK;
       looked = true;
       for (int pi : live)
-        if (!ps[pi].done) TLR_TRY(col_lookahead(ps[pi], k, ldl));
+        if (!ps[pi].done) {
+          TLR_TRY(col_diag(ps[pi], k, ldl));
+          TLR_TRY(col_lookahead(ps[pi], k, ldl));
+        }
       return TLR_OK;
     };
     TLR_TRY(ara_run(lead, cfg, slots, order, spec, &res, single ? &abort : nullptr, lookahead));
