@@ -533,6 +533,36 @@ hipError_t launch_philox_raw(unsigned* out, int n, unsigned long long seed, unsi
   return hipGetLastError();
 }
 
+namespace {
+__global__ void k_mixed_guard(AraSlotDesc* slots, const GuardDesc* __restrict__ g, int n,
+                              int* f32) {
+#pragma clang fp contract(off)
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= n) return;
+  const GuardDesc d = g[sl];
+  double nu = d.nu;
+  if (d.irow >= 0) {
+    const double prod = d.fro[d.irow] * d.fro[0];
+    nu = nu + prod;
+  }
+  // u32 = 2^-24, the unit roundoff of the FP32 panels
+  const int use = (d.a1_32 != nullptr && 5.9604644775390625e-08 * nu <= d.thr) ? 1 : 0;
+  if (use) {
+    slots[sl].a1 = d.a1_32;
+    slots[sl].a1_f32 = 1;
+  }
+  f32[sl] = use;
+}
+}  // namespace
+
+hipError_t launch_mixed_guard(AraSlotDesc* slots, const GuardDesc* g, int n, int* f32,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mixed_guard, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, slots, g, n,
+                     f32);
+  return hipGetLastError();
+}
+
 // KERNEL is a template-id whose block-size argument is spelled BS_ARG.
 #define TLR_BS_CASE(v, KERNEL, ...)                    \
   case v: {                                            \

@@ -25,7 +25,7 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   if (fresh_q) TLR_HIP(hipMemsetAsync(w.Q.p, 0, w.Q.cap, h->stream));
   const size_t pn = nn * nstrip * bs * bs * 2;
   TLR_TRY(w.part.ensure(h->mem, sizeof(double) * 2 * pn));
-  const size_t nint = 8 + 8 * al(nn) + al(nn * (bs + 1)) + 64;
+  const size_t nint = 8 + 9 * al(nn) + al(nn * (bs + 1)) + 64;
   TLR_TRY(w.ints.ensure(h->mem, sizeof(int) * nint));
   s->Y = w.Y.as<double>();
   s->C = w.C.as<double>();
@@ -37,7 +37,7 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   ip += 8;
   s->act = ip;
   ip += al(nn);
-  s->q = ip;   // q, qnew, flag, iters, qsum, ncol are contiguous (cleared together)
+  s->q = ip;   // q, qnew, flag, iters, qsum, ncol, f32 are contiguous (cleared together)
   ip += al(nn);
   s->qnew = ip;
   ip += al(nn);
@@ -48,6 +48,8 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   s->qsum = ip;
   ip += al(nn);
   s->ncol = ip;
+  ip += al(nn);
+  s->f32 = ip;
   ip += al(nn);
   s->waiting = ip;   // counts .. waiting are written by one upload per run
   ip += al(nn);
@@ -105,6 +107,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   res->q.assign(n, 0);
   res->iters.assign(n, 0);
   res->cols.assign(n, 0);
+  res->f32.assign(n, 0);
   res->iter_bs.clear();
   res->flops_paper_orth.assign(n, 0.0);
   res->flops_slot.assign(n, 0.0);
@@ -140,16 +143,19 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   const size_t sbytes = sizeof(AraSlotDesc) * n;
   const size_t zbytes = sizeof(ZSeg) * spec.zseg.size();
   const size_t pbytes = sizeof(PTile) * ptiles.size();
+  const size_t gbytes = sizeof(GuardDesc) * spec.guard.size();
   const size_t zoff = (sbytes + 255) & ~(size_t)255;
   const size_t poff = zoff + ((zbytes + 255) & ~(size_t)255);
-  TLR_TRY(w.orth.ensure(h->mem, poff + pbytes + 256));
+  const size_t goff = poff + ((pbytes + 255) & ~(size_t)255);
+  TLR_TRY(w.orth.ensure(h->mem, goff + gbytes + 256));
   char* dbase = (char*)w.orth.p;
   {
-    // slot descriptors, Z pieces and P tiles: one copy
-    std::vector<char> blob(poff + pbytes);
+    // slot descriptors, Z pieces, P tiles and precision choices: one copy
+    std::vector<char> blob(goff + gbytes);
     std::memcpy(blob.data(), spec.slots.data(), sbytes);
     if (zbytes) std::memcpy(blob.data() + zoff, spec.zseg.data(), zbytes);
     if (pbytes) std::memcpy(blob.data() + poff, ptiles.data(), pbytes);
+    if (gbytes) std::memcpy(blob.data() + goff, spec.guard.data(), gbytes);
     TLR_TRY(h->stage.upload_to(h, blob.data(), blob.size(), dbase, st));
   }
   const ZSeg* dzseg = (const ZSeg*)(dbase + zoff);
@@ -172,6 +178,8 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     std::copy(waiting.begin(), waiting.end(), blob.begin() + wo);
     TLR_TRY(h->stage.upload_to(h, blob.data(), sizeof(int) * blob.size(), s.counts, st));
   }
+  if (gbytes)
+    TLR_HIP(launch_mixed_guard((AraSlotDesc*)dbase, (const GuardDesc*)(dbase + goff), n, s.f32, st));
   int* ring = nullptr;
   TLR_TRY(h->readback_ring(&ring));
 
@@ -292,18 +300,20 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   // its (empty) sampling launch stays in the timed set, as it runs
   // ---- results: basis widths, iteration counts, summed widths
   const size_t stride = (size_t)(s.qnew - s.q);
-  std::vector<int> back(6 * stride);
+  std::vector<int> back(7 * stride);
   TLR_HIP(hipMemcpyAsync(back.data(), s.q, sizeof(int) * back.size(), hipMemcpyDeviceToHost, st));
   TLR_TRY(h->sync_main());
   const int* bq = back.data();
   const int* bit = back.data() + 3 * stride;
   const int* bqs = back.data() + 4 * stride;
   const int* bnc = back.data() + 5 * stride;
+  const int* bf32 = back.data() + 6 * stride;
   const double b0 = c.bs, b1 = c.bs_tail > 0 ? c.bs_tail : c.bs;
   for (int sl = 0; sl < n; ++sl) {
     res->q[sl] = bq[sl];
     res->iters[sl] = bit[sl];
     res->cols[sl] = bnc[sl];
+    res->f32[sl] = bf32[sl];
     // samples drawn, and the sum of their squares per iteration (every
     // iteration draws b0 or b1 samples)
     const double it = bit[sl], qs = bqs[sl], cols = bnc[sl];
@@ -315,7 +325,8 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     const double orth = 8.0 * m * qs + 6.0 * m * b2;
     res->flops_paper_orth[sl] = orth;
     res->flops_slot[sl] = orth + cols * spec.samp_flops_col[sl];
-    res->samp_bytes_slot[sl] = it * spec.samp_bytes[sl] + cols * spec.samp_bytes_col[sl];
+    const double sb = (bf32[sl] && !spec.samp_bytes32.empty()) ? spec.samp_bytes32[sl] : spec.samp_bytes[sl];
+    res->samp_bytes_slot[sl] = it * sb + cols * spec.samp_bytes_col[sl];
     res->samp_flops_slot[sl] = cols * spec.samp_flops_col[sl];
     res->flops += res->flops_slot[sl];
     res->samp_bytes += res->samp_bytes_slot[sl];

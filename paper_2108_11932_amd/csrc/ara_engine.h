@@ -60,6 +60,7 @@ struct AraSlots {
   int* iters = nullptr;     // n
   int* qsum = nullptr;      // n
   int* ncol = nullptr;      // n: samples drawn per slot
+  int* f32 = nullptr;       // n: precision chosen per slot
   int* piv = nullptr;       // n x (bs + 1)
   int* waiting = nullptr;   // n
   size_t qstride = 0;       // doubles per slot in Q
@@ -93,6 +94,11 @@ struct AraSpec {
   // sampling cost per slot: bytes per iteration = samp_bytes + samp_bytes_col
   // * (samples of the iteration); flops = samp_flops_col * samples
   std::vector<double> samp_bytes, samp_bytes_col, samp_flops_col;
+  // mixed precision: one precision choice per slot, made on the device
+  // before the first iteration; samp_bytes32 replaces samp_bytes for the
+  // slots that take their FP32 panel
+  std::vector<GuardDesc> guard;
+  std::vector<double> samp_bytes32;
   // when set, HIP events are recorded around every sampling launch
   std::vector<std::pair<hipEvent_t, hipEvent_t>>* events = nullptr;
 };
@@ -101,6 +107,7 @@ struct AraResult {
   std::vector<int> q;          // final basis width per slot
   std::vector<int> iters;      // iterations per slot
   std::vector<int> cols;       // samples drawn per slot
+  std::vector<int> f32;        // 1 where the slot sampled with its FP32 panel
   std::vector<int> iter_bs;    // samples per slot of every launched iteration
   std::vector<double> flops_paper_orth;  // per slot: orthogonalisation flops
   long long launches = 0;      // ARA iterations (batches)

@@ -126,7 +126,6 @@ struct Prob {
   Handle* h = nullptr;
   double tau = 0.0, shift = 0.0;
   double* pin_norm = nullptr;
-  int* pin_order = nullptr;
   bool done = false;
   double flops = 0.0, flops_paper = 0.0, bytes_alg = 0.0, samp_bytes = 0.0, samp_flops = 0.0;
   long long ara_iters = 0, tile_iters = 0, fp32_tile_iters = 0;
@@ -147,9 +146,7 @@ struct Prob {
   std::vector<long long> goff_next;
   std::unique_ptr<Plan> dplan, gplan;
   bool side_pending = false;   // the side worker holds this column's launches
-  bool host_order = false;     // this column's order was taken on the host
   std::vector<int> order;
-  std::vector<char> use32;
   const double* gptr(int i, int j) const {
     if (j == jk) {
       const long long go = gkoff[i];
@@ -160,7 +157,6 @@ struct Prob {
   }
 };
 
-constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
 
 // Set-up of one problem: factor storage, streams, thresholds, initial panel
 // capacities.
@@ -197,7 +193,6 @@ tlr_status prob_init(Prob& p, double eps, const tlr_opts& o, bool ldl) {
   if (h->mixed && h->a_fro.empty()) TLR_TRY(input_norms(h));
   h->l_fro.assign((size_t)nb * nb, 0.0);
   if (h->mixed) TLR_TRY(h->pinned_norms((size_t)std::max(nb, 1), &p.pin_norm));
-  TLR_TRY(h->pinned_ints((size_t)std::max(nb, 1), &p.pin_order));
   // initial panel capacities from the input ranks (a large rank in A tends to
   // stay large in L, Section 4.2)
   for (int i = 1; i < nb; ++i) {
@@ -213,10 +208,9 @@ tlr_status prob_init(Prob& p, double eps, const tlr_opts& o, bool ldl) {
   return TLR_OK;
 }
 
-// Column k, before the ARA: G_ij = V_ij^T (D_j) V_kj, the diagonal-tile
-// work queued for the side stream, and the device sortRanks of the column's
-// tiles into `order_out` (read back after the caller's synchronisation).
-tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
+// Column k, before the ARA: G_ij = V_ij^T (D_j) V_kj, the fork of the
+// diagonal-tile stream, and the sortRanks order of the column's tiles.
+tlr_status col_begin(Prob& p, int k, bool ldl) {
   Handle* h = p.h;
   const int m = h->m, nb = h->nb;
   Work& w = h->ws;
@@ -304,32 +298,16 @@ tlr_status col_begin(Prob& p, int k, bool ldl, int* order_out) {
   p.flops += (double)m * m * m / 3.0 + (double)m * m * m / 3.0;
   p.nrow = nb - k - 1;
   // ---------------------------------------------- sortRanks
-  // Without mixed precision nothing else of the previous column is needed
-  // on the host, so the order (descending input rank, ties by row) is taken
-  // here and the device queue is not drained; the mixed form sorts on the
-  // device and reads the order back with the previous column's V norms.
-  p.host_order = !h->mixed;
+  // The order (descending input rank, ties by row) needs only the input
+  // ranks: it is taken on the host and the device queue is not drained
+  // (the mixed form's precision choice is made on the device).
   p.order.clear();
-  if (p.nrow > 0 && p.host_order) {
+  if (p.nrow > 0) {
     p.order.resize(p.nrow);
     for (int s = 0; s < p.nrow; ++s) p.order[s] = s;
     std::stable_sort(p.order.begin(), p.order.end(), [&](int a, int b) {
       return h->ar(k + 1 + a, k) > h->ar(k + 1 + b, k);
     });
-  } else if (p.nrow > 0) {
-    const int nrow = p.nrow;
-    std::vector<int> rk(nrow), rows(nrow);
-    for (int s = 0; s < nrow; ++s) {
-      rk[s] = h->ar(k + 1 + s, k);
-      rows[s] = s;
-    }
-    void* dr = nullptr;
-    void* dw = nullptr;
-    TLR_TRY(h->stage.upload(h, rk.data(), sizeof(int) * nrow, &dr));
-    TLR_TRY(h->stage.upload(h, rows.data(), sizeof(int) * nrow, &dw));
-    TLR_HIP(launch_sort_ranks((const int*)dr, (const int*)dw, nrow, order_out, h->stream));
-    TLR_HIP(hipMemcpyAsync(p.pin_order, order_out, sizeof(int) * nrow, hipMemcpyDeviceToHost,
-                           h->stream));
   }
   return TLR_OK;
 }
@@ -465,23 +443,6 @@ tlr_status side_done(Prob& p) {
   return p.h->worker->wait();
 }
 
-// After the synchronisation that follows col_begin: the sorted order, the V
-// norms of column k - 1 (mixed precision) and the per-tile precision choice.
-void col_order(Prob& p, int k) {
-  Handle* h = p.h;
-  const int nb = h->nb, nrow = p.nrow;
-  if (!p.host_order) p.order.assign(p.pin_order, p.pin_order + nrow);
-  if (h->mixed && k > 0)
-    for (int s = 0; s < nrow + 1; ++s) h->l_fro[(size_t)(k + s) * nb + (k - 1)] = p.pin_norm[s];
-  p.use32.assign(nrow, 0);
-  if (h->mixed)
-    for (int s = 0; s < nrow; ++s) {
-      const int i = k + 1 + s;
-      double nu = h->a_fro[(size_t)i * nb + k];
-      for (int j = 0; j < k; ++j) nu += h->l_fro[(size_t)i * nb + j] * h->l_fro[(size_t)k * nb + j];
-      p.use32[s] = (kU32 * nu <= p.tau / 16.0) ? 1 : 0;
-    }
-}
 
 // The sampling description of problem p's tiles of column k, appended to the
 // pooled spec at slots [p.base, p.base + p.nrow) and P rows [p.roff, ...).
@@ -521,8 +482,8 @@ tlr_status col_spec(Prob& p, int k, int bsm, AraSpec& spec) {
     if (Rk > 0 && Ri > 0) {
       double* zs = Z + zo;
       zo += (long long)Ri * bsm;
-      d.a1 = p.use32[s] ? (const void*)h->UL32[i] : (const void*)h->UL[i];
-      d.a1_f32 = p.use32[s];
+      d.a1 = (const void*)h->UL[i];
+      d.a1_f32 = 0;
       d.k1 = Ri;
       d.b1 = zs;
       d.ldb1 = Ri;
@@ -540,7 +501,19 @@ tlr_status col_spec(Prob& p, int k, int bsm, AraSpec& spec) {
     }
     const double kk = (double)a + d.k1;
     spec.samp_flops_col[p.base + s] = 2.0 * m * kk;
-    spec.samp_bytes[p.base + s] = 8.0 * m * a + (d.a1_f32 ? 4.0 : 8.0) * m * d.k1;
+    spec.samp_bytes[p.base + s] = 8.0 * m * a + 8.0 * m * d.k1;
+    if (h->mixed) {
+      // FP32 panel when its rounding, u32 (||A_ik||_F + sum_j ||L_ij||_F
+      // ||L_kj||_F), stays below tau / 16; the newest column's term is
+      // added on the device, where its norms were formed
+      const int nb = h->nb;
+      double nu = h->a_fro[(size_t)i * nb + k];
+      for (int j = 0; j + 1 < k; ++j)
+        nu += h->l_fro[(size_t)i * nb + j] * h->l_fro[(size_t)k * nb + j];
+      spec.samp_bytes32[p.base + s] = 8.0 * m * a + 4.0 * m * d.k1;
+      spec.guard[p.base + s] = GuardDesc{(const void*)h->UL32[i], h->ws.fro.as<double>(), nu,
+                                         p.tau / 16.0, k >= 1 ? i - k : -1, 0};
+    }
     spec.samp_bytes_col[p.base + s] = 8.0 * (kk + m);
     spec.tau[p.base + s] = p.tau;
   }
@@ -551,6 +524,11 @@ tlr_status col_spec(Prob& p, int k, int bsm, AraSpec& spec) {
 // solve with L_kk, and the append of U_ik = Q_i, V_ik to the row panels.
 tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraSlots& slots,
                       const AraResult& res) {
+  // the norms of column k - 1's factor tiles, read back by the previous
+  // projection (complete since this column's iterations synchronised)
+  if (p.h->mixed && k > 0)
+    for (int s = 0; s < p.h->nb - k; ++s)
+      p.h->l_fro[(size_t)(k + s) * p.h->nb + (k - 1)] = p.pin_norm[s];
   Handle* h = p.h;
   const int m = h->m, nb = h->nb, nrow = p.nrow, Rk = p.Rk;
   Work& w = h->ws;
@@ -570,7 +548,7 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
     for (int j = 0; j < k; ++j) zf += (double)h->lr(i, j) * h->lr(k, j);
     const double cols = res.cols[sl];
     p.flops += cols * 2.0 * ((double)h->ar(i, k) * m + zf);
-    if (p.use32[s]) p.fp32_tile_iters += it[s];
+    if (res.f32[sl]) p.fp32_tile_iters += it[s];
     p.flops += res.flops_slot[sl];
     p.samp_bytes += res.samp_bytes_slot[sl];
     p.samp_flops += res.samp_flops_slot[sl];
@@ -698,8 +676,9 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
     }
   }
   if (h->mixed) {
-    // ||L_ik||_F = ||V_ik||_F (U_ik orthonormal), read back with the next
-    // column's first synchronisation
+    // ||L_ik||_F = ||V_ik||_F (U_ik orthonormal): read on the device by the
+    // next column's precision choice, and back on the host for the later
+    // columns' sums
     TLR_TRY(w.fro.ensure(h->mem, sizeof(double) * (size_t)std::max(nrow, 1)));
     double* fro = w.fro.as<double>();
     std::vector<NormDesc> nd;
@@ -835,15 +814,10 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
     for (int pi : live) {
       Prob& p = ps[pi];
       p.base = base;
-      TLR_TRY(col_begin(p, k, ldl, slots.waiting + base));
+      TLR_TRY(col_begin(p, k, ldl));
       base += p.nrow;
     }
     const int total = base;
-    // one synchronisation for the orders (and norms) read back from the
-    // device, if any problem needs them
-    bool need_sync = false;
-    for (int pi : live) need_sync = need_sync || (!ps[pi].host_order && ps[pi].nrow > 0);
-    if (need_sync) TLR_TRY(lead->sync_main());
     std::vector<int> order;
     {
       // pooled sortRanks: descending input rank; ties by problem, then by
@@ -851,7 +825,6 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
       std::vector<std::pair<int, int>> key;   // (rank, global slot)
       for (int pi : live) {
         Prob& p = ps[pi];
-        col_order(p, k);
         for (int s : p.order) key.push_back({p.h->ar(k + 1 + s, k), p.base + s});
       }
       std::stable_sort(key.begin(), key.end(),
@@ -876,6 +849,10 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
     spec.samp_bytes_col.assign(total, 0.0);
     spec.samp_flops_col.assign(total, 0.0);
     spec.tau.assign(total, 0.0);
+    if (lead->mixed) {
+      spec.guard.assign(total, GuardDesc{nullptr, nullptr, 0.0, 0.0, -1, 0});
+      spec.samp_bytes32.assign(total, 0.0);
+    }
     int prow = 0;
     for (int pi : live) {
       Prob& p = ps[pi];

@@ -185,6 +185,20 @@ struct AraDev {
   int* ncol;    // samples drawn per slot
   int m, bs, qcap, nstrip;
 };
+// Precision choice of one slot under mixed precision: the slot samples with
+// the FP32 copy a1_32 of its panel when u32 (nu + fro[irow] fro[0]) <= thr
+// (no device term when irow < 0); fro holds the Frobenius norms of the
+// previous column's factor tiles (row k - 1 + 1 + s at s) on the device.
+struct GuardDesc {
+  const void* a1_32;
+  const double* fro;
+  double nu, thr;
+  int irow, pad;
+};
+// Applies the choice to the n slot descriptors (panel pointer and FP32
+// flag) and stores it in f32[slot] (1 = FP32 panel).
+hipError_t launch_mixed_guard(AraSlotDesc* slots, const GuardDesc* g, int n, int* f32,
+                              hipStream_t s);
 // Block sizes the orthogonalisation kernels are built for (1, 2, 4, 8, 16,
 // 24, 32).
 bool orth_block_supported(int bs);
