@@ -221,8 +221,6 @@ struct tlr_matrix_s {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gnext = nullptr;
   std::unique_ptr<tlr::SideWorker> worker;   // issues the side-stream launches
   Staging stage;
-  int* pin_back = nullptr;        // pinned read-back area
-  size_t pin_back_n = 0;
 
   // input matrix
   double* Ad = nullptr;           // nb diagonal tiles, m x m each
@@ -277,7 +275,6 @@ struct tlr_matrix_s {
   tlr_status sync();          // both streams; recycles the staging area
   tlr_status sync_main();     // the caller's stream only
   tlr_status init_streams();
-  tlr_status pinned_ints(size_t n, int** p);
   tlr_status pinned_norms(size_t n, double** p);
   tlr_status readback_ring(int** p);
   void release_host();            // pinned buffers and events

@@ -218,13 +218,11 @@ tlr_status tlr_matrix_s::readback_ring(int** p) {
 }
 
 void tlr_matrix_s::release_host() {
-  if (pin_back) (void)hipHostFree(pin_back);
   if (pin_norm) (void)hipHostFree(pin_norm);
   if (pin_ring) (void)hipHostFree(pin_ring);
-  pin_back = nullptr;
   pin_norm = nullptr;
   pin_ring = nullptr;
-  pin_back_n = pin_norm_n = 0;
+  pin_norm_n = 0;
   for (hipEvent_t& e : ev_rb) {
     if (e) (void)hipEventDestroy(e);
     e = nullptr;
@@ -244,22 +242,6 @@ tlr_status tlr_matrix_s::pinned_norms(size_t n, double** p) {
     pin_norm_n = n;
   }
   *p = pin_norm;
-  return TLR_OK;
-}
-
-tlr_status tlr_matrix_s::pinned_ints(size_t n, int** p) {
-  if (n > pin_back_n) {
-    if (pin_back) (void)hipHostFree(pin_back);
-    pin_back = nullptr;
-    pin_back_n = 0;
-    if (hipHostMalloc((void**)&pin_back, sizeof(int) * n, hipHostMallocDefault) != hipSuccess) {
-      pin_back = nullptr;
-      tlr::set_error("pinned host allocation failed");
-      return TLR_ERR_OOM;
-    }
-    pin_back_n = n;
-  }
-  *p = pin_back;
   return TLR_OK;
 }
 
