@@ -455,7 +455,8 @@ __global__ __launch_bounds__(256) void k_compact(int* act, int* counts, const in
 // compact and refill, then record the status word and the largest basis
 // width among the active slots (the host's bound for the next products).
 __global__ __launch_bounds__(256) void k_ara_compact(AraDev D, const int* waiting, int nwaiting,
-                                                     int s_max, const int* info, int* host_out) {
+                                                     int s_max, const int* info, int* host_out,
+                                                     int* host_res, int res_ints) {
   __shared__ int keep_total;
   __shared__ int scan[256];
   const int tid = threadIdx.x;
@@ -485,6 +486,13 @@ __global__ __launch_bounds__(256) void k_ara_compact(AraDev D, const int* waitin
     const int v = tid == 0 ? D.counts[0] : tid == 1 ? D.counts[1] : tid == 2 ? (info ? *info : 0)
                                                                              : scan[0];
     __hip_atomic_store(host_out + tid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  // once no tile is left the per-slot results (basis widths and counters,
+  // res_ints contiguous ints from D.q) are final: they go to the host too,
+  // so the host need not wait for the iteration queued behind this one
+  if (host_res && na == 0) {
+    for (int e = tid; e < res_ints; e += 256)
+      __hip_atomic_store(host_res + e, D.q[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -598,9 +606,10 @@ hipError_t launch_orth_step(const AraDev& D, int pass, int r_min, int count_boun
 }
 
 hipError_t launch_ara_compact(const AraDev& D, const int* waiting, int nwaiting, int s_max,
-                              const int* info, int* host_out, hipStream_t s) {
+                              const int* info, int* host_out, int* host_res, int res_ints,
+                              hipStream_t s) {
   hipLaunchKernelGGL(k_ara_compact, dim3(1), dim3(256), 0, s, D, waiting, nwaiting, s_max, info,
-                     host_out);
+                     host_out, host_res, res_ints);
   return hipGetLastError();
 }
 

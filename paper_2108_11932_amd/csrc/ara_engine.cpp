@@ -182,6 +182,11 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     TLR_HIP(launch_mixed_guard((AraSlotDesc*)dbase, (const GuardDesc*)(dbase + goff), n, s.f32, st));
   int* ring = nullptr;
   TLR_TRY(h->readback_ring(&ring));
+  // per-slot results (q, qnew, flag, iters, qsum, ncol, f32: contiguous)
+  const size_t stride = (size_t)(s.qnew - s.q);
+  const int res_ints = (int)(7 * stride);
+  int* pres = nullptr;
+  TLR_TRY(h->readback_results((size_t)res_ints, &pres));
 
   AraDev D;
   D.slots = (const AraSlotDesc*)dbase;
@@ -260,7 +265,8 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       TLR_HIP(launch_ara_seg(D, 2, cb, st));
     }
     TLR_HIP(launch_orth_step(D, 2, c.r_min, cb, st));
-    TLR_HIP(launch_ara_compact(D, s.waiting, nwait, s_max, info, ring + 8 * (j & 1), st));
+    TLR_HIP(launch_ara_compact(D, s.waiting, nwait, s_max, info, ring + 8 * (j & 1), pres, res_ints,
+                               st));
     TLR_HIP(hipEventRecord(h->ev_rb[j & 1], st));
     return TLR_OK;
   };
@@ -299,10 +305,17 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   // the iteration enqueued past the last active one found nothing to do;
   // its (empty) sampling launch stays in the timed set, as it runs
   // ---- results: basis widths, iteration counts, summed widths
-  const size_t stride = (size_t)(s.qnew - s.q);
+  // the compaction that emptied the active list left the results in pinned
+  // memory (its iteration's event has completed); the iteration queued
+  // behind it finds nothing to do and is not waited for.  After an abort
+  // they are read back from the device.
   std::vector<int> back(7 * stride);
-  TLR_HIP(hipMemcpyAsync(back.data(), s.q, sizeof(int) * back.size(), hipMemcpyDeviceToHost, st));
-  TLR_TRY(h->sync_main());
+  if (known.count == 0) {
+    std::memcpy(back.data(), pres, sizeof(int) * back.size());
+  } else {
+    TLR_HIP(hipMemcpyAsync(back.data(), s.q, sizeof(int) * back.size(), hipMemcpyDeviceToHost, st));
+    TLR_TRY(h->sync_main());
+  }
   const int* bq = back.data();
   const int* bit = back.data() + 3 * stride;
   const int* bqs = back.data() + 4 * stride;

@@ -251,6 +251,8 @@ struct tlr_matrix_s {
   std::vector<double> l_fro;      // ||L_ij||_F per tile (U orthonormal: ||V_ij||_F)
   double* pin_norm = nullptr;     // pinned read-back of a column's V norms
   int* pin_ring = nullptr;        // pinned read-back ring of the ARA iterations (2 x 8)
+  int* pin_res = nullptr;         // pinned read-back of an ARA run's per-slot results
+  size_t pin_res_n = 0;
   hipEvent_t ev_rb[2] = {nullptr, nullptr};
   size_t pin_norm_n = 0;
 
@@ -277,6 +279,7 @@ struct tlr_matrix_s {
   tlr_status init_streams();
   tlr_status pinned_norms(size_t n, double** p);
   tlr_status readback_ring(int** p);
+  tlr_status readback_results(size_t n, int** p);   // pinned, n ints
   void release_host();            // pinned buffers and events
 };
 

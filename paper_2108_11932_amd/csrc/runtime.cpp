@@ -217,9 +217,28 @@ tlr_status tlr_matrix_s::readback_ring(int** p) {
   return TLR_OK;
 }
 
+tlr_status tlr_matrix_s::readback_results(size_t n, int** p) {
+  if (n > pin_res_n) {
+    if (pin_res) (void)hipHostFree(pin_res);
+    pin_res = nullptr;
+    pin_res_n = 0;
+    if (hipHostMalloc((void**)&pin_res, sizeof(int) * n, hipHostMallocDefault) != hipSuccess) {
+      pin_res = nullptr;
+      tlr::set_error("pinned host allocation failed");
+      return TLR_ERR_OOM;
+    }
+    pin_res_n = n;
+  }
+  *p = pin_res;
+  return TLR_OK;
+}
+
 void tlr_matrix_s::release_host() {
   if (pin_norm) (void)hipHostFree(pin_norm);
   if (pin_ring) (void)hipHostFree(pin_ring);
+  if (pin_res) (void)hipHostFree(pin_res);
+  pin_res = nullptr;
+  pin_res_n = 0;
   pin_norm = nullptr;
   pin_ring = nullptr;
   pin_norm_n = 0;

@@ -230,9 +230,12 @@ hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_
 hipError_t launch_orth_step(const AraDev& D, int pass, int r_min, int count_bound, hipStream_t s);
 // Commit the basis widths, compact the active list and refill it (see
 // launch_compact), and record the status word and the largest active width;
-// counts[0..3] are also stored to host_out (pinned host memory) when given.
+// counts[0..3] are also stored to host_out (pinned host memory) when given;
+// when no tile is left active, the res_ints ints from D.q (the per-slot
+// results, laid out contiguously) are stored to host_res as well.
 hipError_t launch_ara_compact(const AraDev& D, const int* waiting, int nwaiting, int s_max,
-                              const int* info, int* host_out, hipStream_t s);
+                              const int* info, int* host_out, int* host_res, int res_ints,
+                              hipStream_t s);
 
 // Dynamic batching: stable compaction of the active list by the convergence
 // flags (flag[slot] != 0 removes the slot), then refill from the waiting
