@@ -525,7 +525,7 @@ tlr_status col_spec(Prob& p, int k, int bsm, AraSpec& spec) {
 tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraSlots& slots,
                       const AraResult& res) {
   // the norms of column k - 1's factor tiles, read back by the previous
-  // projection (complete since this column's iterations synchronised)
+  // projection (complete: this column's iterations ran after it)
   if (p.h->mixed && k > 0)
     for (int s = 0; s < p.h->nb - k; ++s)
       p.h->l_fro[(size_t)(k + s) * p.h->nb + (k - 1)] = p.pin_norm[s];
