@@ -135,6 +135,26 @@ def time_form(mat, w, eps_mode, precision, tlr, torch, steps, warmup, bs_tail=0,
     return (time.perf_counter() - t0) / steps, stats
 
 
+def phase_split(mat, w, tlr, torch):
+    """One factorization with the phase timers on (HIP events at the phase
+    boundaries of every column): GPU milliseconds per phase.  The phases of
+    the caller's stream run one after another and add up to that stream's
+    span; 'diag' (updateDense, chol and the next column's G blocks) runs on
+    the second stream beside them."""
+    o = tlr.opts(bs=w.bs, eps_mode=w.eps_mode, flags=tlr.FLAG_PHASE_TIMING)
+    mat.potrf(w.eps, o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = mat.potrf(w.eps, o)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    ph = dict(zip(tlr.PHASES, st["t_phase"]))
+    main = sum(v for k, v in ph.items() if k != "diag")
+    return {"ms": ph, "main_stream_sum_ms": main, "pass_ms": wall,
+            "note": "phases other than diag run in sequence on the caller's stream; diag runs "
+                    "on the second stream, overlapped"}
+
+
 def batched_form(tlr, torch, wl, count: int, m: int):
     """The batched workload (count independent 2D problems of uneven N,
     relative eps 1e-6): one tlr_factor_batched call over all of them (FP64
@@ -178,6 +198,50 @@ def batched_form(tlr, torch, wl, count: int, m: int):
             "sequential_fp64_s": t_seq, "batched_fp64_s": t_b64, "batched_mixed_fp32_s": t_b32,
             "speedup_fp64": t_seq / t_b64, "speedup_mixed": t_seq / t_b32,
             "batched_fp64_tflops": flops / t_b64 / 1e12}
+
+
+GOLDEN_CFG2 = os.path.join(ROOT, "tests", "golden", "cfg2_ranks.txt")
+
+
+def cov2d_32k_form(tlr, torch, wl, steps: int):
+    """The N = 32768 2D covariance at tile 512, absolute eps 1e-2 and 1e-6:
+    time-to-solution, the random-vector residual against the bound
+    2 sqrt(nb) tau, and the factor's total rank against the oracle's (O4,
+    truncated-SVD recompression, from the committed golden file)."""
+    gold = {}
+    try:
+        with open(GOLDEN_CFG2) as fh:
+            for ln in fh:
+                if ln.strip() and not ln.startswith("#"):
+                    f = ln.split()
+                    gold[float(f[0])] = int(f[2])
+    except OSError:
+        pass
+    out = {}
+    base = wl.standard("cov2d_32k")
+    mat = None
+    for eps in (1e-2, 1e-6):
+        if mat is not None:
+            mat.close()
+        mat = tlr.TLRMatrix.compress_kernel(base.points, base.kernel, base.ell, base.diag_add,
+                                            base.m, eps, tlr.opts(bs=base.bs))
+        o = tlr.opts(bs=base.bs)
+        mat.potrf(eps, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [mat.potrf(eps, o) for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res = residual(mat, torch)
+        bound = 2.0 * math.sqrt(mat.nb) * eps
+        rl = mat.ranks(tlr.FACTOR)[np.tril_indices(mat.nb, -1)]
+        out["eps_%g" % eps] = {
+            "ms_per_step": dt * 1e3, "tflops": float(np.mean([s["flops"] for s in sts])) / dt / 1e12,
+            "residual": res, "bound": bound, "within_bound": bool(res <= bound),
+            "rank_total": int(rl.sum()), "rank_max": int(rl.max()), "rank_mean": float(rl.mean()),
+            "rank_total_oracle": gold.get(eps), "ara_iterations": int(sts[-1]["ara_iters"])}
+    mat.close()
+    return {"workload": _describe(base).replace("eps 1e-06", "eps 1e-2 / 1e-6"), "forms": out}
 
 
 def ldlt_form(tlr, torch, wl, steps: int):
@@ -227,6 +291,10 @@ def main():
     ap.add_argument("--no-kernel-timing", dest="kernel_timing", action="store_false",
                     help="skip the second pass that times the sampling launches with their own "
                          "events (no roofline figures)")
+    ap.add_argument("--no-cfg2", dest="cfg2", action="store_false",
+                    help="skip the N=32768 tile-512 line at eps 1e-2 and 1e-6")
+    ap.add_argument("--no-phases", dest="phases", action="store_false",
+                    help="skip the factorization with phase timers (per-phase GPU time)")
     ap.add_argument("--no-ldlt", dest="ldlt", action="store_false",
                     help="skip the LDL^T line (3D Matern, indefinite) after the main line")
     ap.add_argument("--batched", type=int, default=96,
@@ -274,6 +342,7 @@ def main():
     print("[bench] %d timed steps, %.1f ms each" % (a.steps, dt * 1e3), file=sys.stderr, flush=True)
     dt_ev, stats_ev = (time_form(mat, w, w.eps_mode, tlr.FP64, tlr, torch, a.steps, 0, a.bs_tail, a.tail_active, True)
                        if a.kernel_timing else (0.0, []))
+    phases = phase_split(mat, w, tlr, torch) if a.phases else None
     err_primary = residual(mat, torch)
     flops = float(np.mean([s["flops"] for s in stats]))
     flops_paper = float(np.mean([s["flops_paper"] for s in stats]))
@@ -326,6 +395,7 @@ def main():
         "tau": stats[-1]["tau"],
         "residual": err_primary,
         "forms": forms,
+        "phases": phases,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name),
                      "kernel": "Schur-complement sampling product Y_i -= U_i* Z_i",
@@ -335,6 +405,13 @@ def main():
                      "events_pass_ms_per_step": dt_ev * 1e3},
     }
     mat.close()
+    if a.cfg2:
+        print("[bench] 2D covariance N=32768, tile 512", file=sys.stderr, flush=True)
+        line["cov2d_32k"] = cov2d_32k_form(tlr, torch, wl, max(1, min(a.steps, 5)))
+        for k, v in line["cov2d_32k"]["forms"].items():
+            print("[bench] cov2d_32k %s: %.1f ms, residual %.3g (bound %.3g), rank total %d (oracle %s)"
+                  % (k, v["ms_per_step"], v["residual"], v["bound"], v["rank_total"],
+                     v["rank_total_oracle"]), file=sys.stderr, flush=True)
     if a.ldlt:
         print("[bench] LDL^T workload (3D Matern, N=131072)", file=sys.stderr, flush=True)
         line["ldlt"] = ldlt_form(tlr, torch, wl, max(1, min(a.steps, 2)))

@@ -68,14 +68,22 @@ typedef enum {
 } tlr_status;
 
 enum { TLR_EPS_ABS = 0, TLR_EPS_REL = 1 };
-/* Precision of the factorization.  TLR_MIXED_FP32 keeps an FP32 copy of the
- * factor's block-row U panels and streams it in the Schur-complement
- * sampling of Eq. (2) (products still accumulated in FP64) for every tile
- * whose FP32 rounding cannot reach the threshold:
- *   u_32 * nu_ik <= tau / 16,  nu_ik = ||A_ik||_F + sum_j ||L_ij||_F ||L_kj||_F.
- * Other tiles, the dense diagonal work, the orthogonalisation, the final
- * projection and the triangular solve stay FP64. */
-enum { TLR_FP64 = 0, TLR_MIXED_FP32 = 1 };
+/* Precision of the Schur-complement sampling of Eq. (2).  TLR_FP64: all in
+ * FP64.  The mixed forms keep packed low-precision copies of the factor's
+ * block-row U panels and form a tile's panel term U_i* Z_i on the FP32
+ * (TLR_MIXED_FP32) or BF16 matrix cores with FP32 accumulation, Z_i rounded
+ * to the same precision, whenever that rounding stays below the threshold:
+ *   (2 u_p + sqrt(R_i) u_32) nu_ik <= tau / 16,
+ *   nu_ik = ||A_ik||_F + sum_j ||L_ij||_F ||L_kj||_F,
+ * u_p the unit roundoff of the copy (2^-24 FP32, 2^-8 BF16) and R_i the
+ * panel width; the other tiles sample in FP64.  TLR_MIXED_BF16 tries BF16
+ * first, then FP32.  TLR_MIXED_AUTO is TLR_MIXED_BF16 when tau >= 1e-3
+ * ||A||_2 (the norm estimated by power iteration on the input) and
+ * TLR_MIXED_FP32 otherwise.  In every form the input-tile term of the
+ * sampling, the dense diagonal work, the orthogonalisation (FP64 and
+ * double-double Cholesky QR, two Gram-Schmidt passes), the final projection
+ * and the triangular solve stay FP64; the LDL^T variant samples in FP64. */
+enum { TLR_FP64 = 0, TLR_MIXED_FP32 = 1, TLR_MIXED_BF16 = 2, TLR_MIXED_AUTO = 3 };
 enum { TLR_KERNEL_EXP = 0, TLR_KERNEL_MATERN15 = 1 };
 enum { TLR_INPUT = 0, TLR_FACTOR = 1 };
 
@@ -93,7 +101,8 @@ typedef struct {
                               1, 2, 4, 8, 16, 24, 32; the paper uses 16 in 2D
                               and 32 in 3D (Section 6) */
   int eps_mode;            /* TLR_EPS_ABS (default) or TLR_EPS_REL */
-  int precision;           /* TLR_FP64 (default) or TLR_MIXED_FP32 */
+  int precision;           /* TLR_FP64 (default), TLR_MIXED_FP32, TLR_MIXED_BF16
+                              or TLR_MIXED_AUTO */
   double shift;            /* factor A + shift * I (diagonal shift, Section 5.1);
                               a negative value means shift = tau */
   int max_active;          /* size of the active subset of tiles per column
@@ -112,12 +121,52 @@ typedef struct {
                               still active (as known to the host two iterations
                               earlier); the others draw bs.  0: every iteration
                               after the first draws bs_tail */
+  int auto_shift;          /* nonzero: when a diagonal tile loses definiteness
+                              (TLR_ERR_NOT_SPD) and the shift in use is 0, factor
+                              once more with the diagonal shift s = tau, the
+                              perturbation below the compression threshold of
+                              Section 5.1; stats->shift reports the shift used */
+  int sample_strip;        /* rows of a tile that one workgroup of the
+                              Schur-complement sampling product computes: 0
+                              chooses 64 when enough tiles are active to fill
+                              the GPU and 16 otherwise; 16 or 64 forces one.
+                              Both give the same samples bit for bit */
+  double conv_factor;      /* the ARA accepts new directions and tests
+                              convergence at tau / conv_factor (>= 1; 0 means
+                              the default).  The convergence test reads the
+                              leftover samples of a block, which the pivoted
+                              selection leaves biased towards small norms;
+                              the factor makes the compression error of a
+                              tile stay below tau with high probability */
 } tlr_opts;
 
-/* opts.flags: record HIP events around every launch of the Schur-complement
- * sampling product (the dominant kernel) and report its time and
- * algorithmic bytes in tlr_stats.sample_*. */
-enum { TLR_FLAG_KERNEL_TIMING = 1 };
+/* opts.flags.  TLR_FLAG_KERNEL_TIMING: record HIP events around every launch
+ * of the Schur-complement sampling product and report its time and
+ * algorithmic bytes in tlr_stats.sample_*.  TLR_FLAG_PHASE_TIMING: record
+ * HIP events at the phase boundaries of every column and report the GPU time
+ * per phase in tlr_stats.t_phase. */
+enum { TLR_FLAG_KERNEL_TIMING = 1, TLR_FLAG_PHASE_TIMING = 2 };
+
+/* Phases of a column step (indices of tlr_stats.t_phase).  Phases 0-6 run on
+ * the caller's stream one after another, so their times add up to that
+ * stream's span of the factorization; phase 7 runs on a second stream,
+ * overlapped with them.
+ *   TLR_PHASE_GBLOCKS  the products G_ij = V_ij^T V_kj of the newest column
+ *   TLR_PHASE_SAMPLE   test matrices and the Schur-complement sampling of
+ *                      Eq. (2): batchRandn, sampleLeft
+ *   TLR_PHASE_ORTH     block Gram-Schmidt and Cholesky QR: batchOrthog
+ *   TLR_PHASE_BATCH    getConvergedTiles, updateSubset (dynamic batching)
+ *   TLR_PHASE_PROJECT  the projection B = S^T Q: sampleLeftT
+ *   TLR_PHASE_TRSM     batchTrsm (and batchIDMult), including the wait for
+ *                      the diagonal tile
+ *   TLR_PHASE_APPEND   updateTiles: the new tiles appended to the row panels
+ *   TLR_PHASE_DIAG     second stream: updateDense, chol / ldl of the diagonal
+ *                      tile and its inverse, and the G_ij of the next column */
+enum {
+  TLR_PHASE_GBLOCKS = 0, TLR_PHASE_SAMPLE = 1, TLR_PHASE_ORTH = 2, TLR_PHASE_BATCH = 3,
+  TLR_PHASE_PROJECT = 4, TLR_PHASE_TRSM = 5, TLR_PHASE_APPEND = 6, TLR_PHASE_DIAG = 7,
+  TLR_NPHASE = 8
+};
 
 /* Results of a factorization. */
 typedef struct {
@@ -137,11 +186,17 @@ typedef struct {
   double sample_ms;        /* their summed duration (HIP events), milliseconds */
   double sample_bytes;     /* their algorithmic HBM bytes: U panels, Z, Y read and write */
   double sample_flops;     /* their flops */
-  long long fp32_tile_iters; /* TLR_MIXED_FP32: tile iterations sampled from FP32 panels */
+  long long fp32_tile_iters; /* mixed forms: tile iterations sampled from FP32 panels */
+  double shift;            /* diagonal shift the factor was computed with */
+  int shift_retries;       /* factorizations repeated by opts.auto_shift (0 or 1) */
+  double t_total;          /* host wall time of the call, milliseconds */
+  double t_phase[TLR_NPHASE]; /* TLR_FLAG_PHASE_TIMING: GPU time per phase (TLR_PHASE_*),
+                              milliseconds */
+  long long bf16_tile_iters; /* mixed forms: tile iterations sampled from BF16 panels */
 } tlr_stats;
 
 /* Fill *opts with the defaults: bs 16, absolute eps, FP64, shift 0, all tiles
- * active, r_min 1, seed 0x5eed. */
+ * active, r_min 1, seed 0x5eed, no automatic shift, automatic strip height. */
 void tlr_opts_default(tlr_opts* opts);
 
 /* Create an N x N matrix with tile size m and the given ranks of the strictly
@@ -187,7 +242,8 @@ tlr_status tlr_compress_kernel(const double* points, int dim, long long N, int k
  * tiles of column k sampled through Eq. (1)-(2) with dynamic batching, batched
  * triangular solve with L_kk.  Every off-diagonal tile of L is compressed
  * once, at threshold tau.  stats may be NULL.  Returns TLR_ERR_NOT_SPD when a
- * diagonal tile is not positive definite after its update. */
+ * diagonal tile is not positive definite after its update (with
+ * opts->auto_shift: when it still is with the shift s = tau). */
 tlr_status tlr_potrf(tlr_matrix_t A, double eps, const tlr_opts* opts, tlr_stats* stats,
                      void* stream);
 
@@ -218,6 +274,16 @@ tlr_status tlr_factor_batched(int count, tlr_matrix_t* A, int ldl, double eps,
                               const tlr_opts* opts, double* const* D, tlr_stats* stats,
                               void* stream);
 
+/* tlr_factor_batched with one threshold per matrix: eps (host, count
+ * entries, each > 0) is matrix i's eps, absolute or relative to its own
+ * ||A_i|| as opts->eps_mode says.  tlr_potrf_batched is the Cholesky form,
+ * tlr_ldlt_batched the LDL^T form (D as in tlr_factor_batched).
+ * opts->auto_shift is not supported in the batched forms (TLR_ERR_ARG). */
+tlr_status tlr_potrf_batched(int count, tlr_matrix_t* A, const double* eps, const tlr_opts* opts,
+                             tlr_stats* stats, void* stream);
+tlr_status tlr_ldlt_batched(int count, tlr_matrix_t* A, const double* eps, const tlr_opts* opts,
+                            double* const* D, tlr_stats* stats, void* stream);
+
 /* B <- (L L^T)^{-1} B or (L D L^T)^{-1} B with the factor held by the handle
  * (Algorithm "TLR Triangular Solve" and its transpose).  B is N x nrhs,
  * device memory, leading dimension ldb >= N.  TLR_ERR_STATE if the handle
@@ -243,6 +309,11 @@ tlr_status tlr_get_tile(tlr_matrix_t A, int which, int i, int j, double* U, doub
 tlr_status tlr_get_diag(tlr_matrix_t A, int which, int k, double* D, int ld);
 /* LDL^T pivots (nb * m entries including the padding) to host memory. */
 tlr_status tlr_get_pivots(tlr_matrix_t A, double* d);
+/* The "sortRanks" order (Section 4.2) in which the last factorization
+ * presented the tiles of column k to its ARA: rows (host, nb - k - 1
+ * entries) receives the block rows i > k by input rank a_ik descending, ties
+ * by ascending i.  TLR_ERR_STATE if the handle holds no factor. */
+tlr_status tlr_get_sort_order(tlr_matrix_t A, int k, int* rows);
 
 tlr_status tlr_destroy(tlr_matrix_t A);
 const char* tlr_last_error(void);

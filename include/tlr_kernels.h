@@ -59,6 +59,14 @@ tlr_status tlrk_philox(int n, unsigned long long seed, unsigned c1, unsigned c2,
 tlr_status tlrk_randn(int rows, int cols, unsigned long long seed, unsigned k, unsigned t,
                       unsigned s, double* out, void* stream);
 
+/* The test matrices of nt consecutive ARA iterations t0 .. t0 + nt - 1 of
+ * column k in one launch, as the factorization draws them: matrix t - t0 at
+ * out (device) + (t - t0) rows cols_max, rows x cols0 for iteration 0 and
+ * rows x cols1 after (cols_max = max(cols0, cols1), leading dimension rows),
+ * element for element the matrix tlrk_randn gives for (k, t, s). */
+tlr_status tlrk_randn_iters(int rows, int cols0, int cols1, unsigned long long seed, unsigned k,
+                            unsigned t0, int nt, unsigned s, double* out, void* stream);
+
 /* Batched adaptive randomized approximation of count explicit m x m tiles
  * (device, tile b at tiles + b m^2), Algorithm "Adaptive Randomized
  * Approximation": on return Q (device, count x m x m) holds orthonormal
@@ -69,8 +77,10 @@ tlr_status tlrk_ara(int m, int count, const double* tiles, double tau, int bs, i
                     unsigned long long seed, double* Q, double* B, int* ranks, int* iters,
                     void* stream);
 
-/* "sortRanks": order (host, n) lists rows (host, n) by ranks (host, n),
- * descending, ties by ascending row; computed on the device. */
+/* "sortRanks" (Section 4.2): order (host, n) lists rows (host, n) by ranks
+ * (host, n), descending, ties by ascending row.  The factorization takes its
+ * order of every column's tiles from this same host routine (the input
+ * ranks are known on the host, so the device queue is not drained for it). */
 tlr_status tlrk_sort_ranks(int n, const int* ranks, const int* rows, int* order);
 
 /* One "getConvergedTiles"/"updateSubset" step on the device: the active list

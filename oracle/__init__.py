@@ -19,10 +19,6 @@ Contents (each function cites the passage of the paper it follows):
 * ``bookkeeping``  -- integer bookkeeping of the method: tile offsets, row
                       panel widths, the rank sort of "sortRanks" and the
                       active-set evolution of "updateSubset".
-* ``ara``          -- a single-tile adaptive randomized approximation
-                      (Algorithm "Adaptive Randomized Approximation"), for
-                      debugging only; its random stream differs from the
-                      GPU's, so it is never a parity target.
 * ``philox``       -- Philox4x32-10 (Salmon et al., SC'11) and Box-Muller,
                       written from their published definitions, used only to
                       check the device generator bit for bit.

@@ -243,6 +243,77 @@ def tlr_cholesky(a: TLR, tau: float, shift: float = 0.0, record: Optional[dict] 
     return l
 
 
+def tlr_cholesky_pivoted(a: TLR, tau: float, shift: float = 0.0):
+    """Pivoted left-looking TLR Cholesky with exact recompression (Section 5.2,
+    Algorithm "Pivoted Left Looking TLR Cholesky").
+
+    Symmetric tile pivoting on the diagonal: at step k every remaining
+    diagonal tile is updated with all the low rank products of the columns
+    already factored (the sums D_i of Section 5.2), the pivot is the position
+    p >= k whose updated tile A(i, i) - D_i has the largest Frobenius norm
+    (the norm the paper prefers over the 2-norm; ties go to the first), block
+    rows and columns k and p are swapped, and the column then proceeds as in
+    the unpivoted algorithm: dense Cholesky of the updated diagonal tile,
+    truncated SVD of every Schur-complement tile of Eq. (1), triangular solve.
+
+    Returns (L, perm) with L the factor of P A P^T in the permuted block
+    order: position t of P A P^T is the original block perm[t].  The shift
+    is added to the real rows of every original block, as in tlr_cholesky.
+    """
+    nb, m = a.nb, a.m
+    perm = list(range(nb))
+    nreal = [min(m, a.n - b * m) for b in range(nb)]
+    l = TLR(a.n, a.m)
+
+    def tile(pi, pj):
+        return a.tile(perm[pi], perm[pj])
+
+    for k in range(nb):
+        upd = []
+        for t in range(k, nb):
+            d = tile(t, t).copy()
+            nr = nreal[perm[t]]
+            d[np.arange(nr), np.arange(nr)] += shift
+            for j in range(k):
+                d -= l.u[t, j] @ ((l.v[t, j].T @ l.v[t, j]) @ l.u[t, j].T)
+            upd.append(d)
+        p = k + int(np.argmax([np.linalg.norm(d, "fro") for d in upd]))
+        if p != k:
+            perm[k], perm[p] = perm[p], perm[k]
+            for j in range(k):
+                l.u[k, j], l.u[p, j] = l.u[p, j], l.u[k, j]
+                l.v[k, j], l.v[p, j] = l.v[p, j], l.v[k, j]
+            upd[0], upd[p - k] = upd[p - k], upd[0]
+        try:
+            l.diag[k] = np.linalg.cholesky(upd[0])
+        except np.linalg.LinAlgError:
+            raise NotSPDTile(k)
+        for i in range(k + 1, nb):
+            s = tile(i, k).copy()
+            for j in range(k):
+                s -= l.u[i, j] @ ((l.v[i, j].T @ l.v[k, j]) @ l.u[k, j].T)
+            q, b, _ = truncate_svd(s, tau)
+            l.u[i, k] = q
+            l.v[i, k] = dense.solve_lower(l.diag[k], b)
+    return l, perm
+
+
+def permute(a: TLR, perm) -> TLR:
+    """The TLR matrix P A P^T: position t holds the original block perm[t]
+    (tile (i, j), i > j, of the result is A(perm[i], perm[j]) as a U V^T
+    pair, transposed when perm[i] < perm[j])."""
+    out = TLR(a.n, a.m)
+    for i in range(a.nb):
+        out.diag[i] = a.diag[perm[i]].copy()
+        for j in range(i):
+            bi, bj = perm[i], perm[j]
+            if bi > bj:
+                out.u[i, j], out.v[i, j] = a.u[bi, bj].copy(), a.v[bi, bj].copy()
+            else:
+                out.u[i, j], out.v[i, j] = a.v[bj, bi].copy(), a.u[bj, bi].copy()
+    return out
+
+
 def tlr_ldlt(a: TLR, tau: float, record: Optional[dict] = None):
     """Left-looking TLR LDL^T with exact recompression (oracle O5).
 

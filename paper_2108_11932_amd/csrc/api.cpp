@@ -1,6 +1,7 @@
 // C ABI of the TLR library (include/tlr.h): argument validation, handle life
 // cycle, data transfer in and out of the handle.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 
 #include "host.h"
@@ -42,6 +43,9 @@ const char* tlr_last_error(void) { return tlr::last_error(); }
 
 }  // extern "C"
 
+// Default of opts.conv_factor.
+static constexpr double kConvFactor = 1.0;
+
 static tlr_status check_opts(const tlr_opts* in, tlr_opts* out) {
   if (in)
     *out = *in;
@@ -50,13 +54,18 @@ static tlr_status check_opts(const tlr_opts* in, tlr_opts* out) {
   TLR_ARG(orth_block_supported(out->bs), "opts.bs must be one of 1, 2, 4, 8, 16, 24, 32, got %d",
           out->bs);
   TLR_ARG(out->eps_mode == TLR_EPS_ABS || out->eps_mode == TLR_EPS_REL, "opts.eps_mode invalid");
-  TLR_ARG(out->precision == TLR_FP64 || out->precision == TLR_MIXED_FP32,
-          "opts.precision must be TLR_FP64 or TLR_MIXED_FP32");
+  TLR_ARG(out->precision >= TLR_FP64 && out->precision <= TLR_MIXED_AUTO,
+          "opts.precision must be TLR_FP64, TLR_MIXED_FP32, TLR_MIXED_BF16 or TLR_MIXED_AUTO");
   TLR_ARG(out->r_min >= 1 && out->r_min <= out->bs, "opts.r_min must be in 1..bs");
   TLR_ARG(out->bs_tail == 0 || (orth_block_supported(out->bs_tail) && out->r_min <= out->bs_tail),
           "opts.bs_tail must be 0 or a supported block size >= r_min, got %d", out->bs_tail);
   TLR_ARG(out->tail_active >= 0, "opts.tail_active must be >= 0, got %d", out->tail_active);
   TLR_ARG(std::isfinite(out->shift), "opts.shift must be finite");
+  TLR_ARG(out->sample_strip == 0 || out->sample_strip == 16 || out->sample_strip == 64,
+          "opts.sample_strip must be 0, 16 or 64, got %d", out->sample_strip);
+  TLR_ARG(out->conv_factor == 0.0 || (out->conv_factor >= 1.0 && std::isfinite(out->conv_factor)),
+          "opts.conv_factor must be 0 (default) or >= 1");
+  if (out->conv_factor == 0.0) out->conv_factor = kConvFactor;
   return TLR_OK;
 }
 
@@ -230,19 +239,33 @@ tlr_status tlr_compress_kernel(const double* points, int dim, long long N, int k
   return TLR_OK;
 }
 
+static double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
 static tlr_status factor_entry(tlr_matrix_t A, double eps, const tlr_opts* opts, tlr_stats* stats,
                                bool ldl, double* D) {
+  const auto t0 = std::chrono::steady_clock::now();
   TLR_ARG(A, "NULL handle");
   TLR_ARG(eps > 0.0 && std::isfinite(eps), "eps must be positive");
   tlr_opts o;
   TLR_TRY(check_opts(opts, &o));
   if (stats) std::memset(stats, 0, sizeof *stats);
   tlr_status st = factorize(A, eps, o, stats, ldl);
+  // Section 5.1: a shift s <= eps of the diagonal keeps the perturbation
+  // below the compression threshold; with auto_shift a Cholesky that lost
+  // definiteness without a shift is repeated once with s = tau
+  if (st == TLR_ERR_NOT_SPD && !ldl && o.auto_shift && o.shift == 0.0) {
+    o.shift = -1.0;
+    st = factorize(A, eps, o, stats, ldl);
+    if (stats) stats->shift_retries = 1;
+  }
   if (st == TLR_OK && ldl && D) {
     TLR_HIP(hipMemcpyAsync(D, A->Dv, sizeof(double) * A->N, hipMemcpyDeviceToDevice, A->stream));
     st = A->sync();
   }
   if (st < 0 && st != TLR_ERR_ARG) A->factored = 0;
+  if (stats) stats->t_total = ms_since(t0);
   return st;
 }
 
@@ -258,21 +281,23 @@ tlr_status tlr_ldlt(tlr_matrix_t A, double eps, const tlr_opts* opts, double* D,
   return factor_entry(A, eps, opts, stats, true, D);
 }
 
-tlr_status tlr_factor_batched(int count, tlr_matrix_t* A, int ldl, double eps,
-                              const tlr_opts* opts, double* const* D, tlr_stats* stats,
-                              void* stream) {
-  TLR_ARG(count > 0 && A, "empty batch");
-  TLR_ARG(eps > 0.0 && std::isfinite(eps), "eps must be positive");
+static tlr_status batched_entry(int count, tlr_matrix_t* A, bool ldl, const double* eps,
+                                const tlr_opts* opts, double* const* D, tlr_stats* stats,
+                                void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  TLR_ARG(count > 0 && A && eps, "empty batch");
   for (int i = 0; i < count; ++i) {
     TLR_ARG(A[i], "NULL handle in the batch");
+    TLR_ARG(eps[i] > 0.0 && std::isfinite(eps[i]), "eps of matrix %d must be positive", i);
     for (int j = 0; j < i; ++j) TLR_ARG(A[j] != A[i], "a handle appears twice in the batch");
     TLR_ARG(A[i]->dev == A[0]->dev, "the batch spans several devices");
   }
   tlr_opts o;
   TLR_TRY(check_opts(opts, &o));
+  TLR_ARG(!o.auto_shift, "opts.auto_shift is not supported by the batched factorizations");
   if (stats) std::memset(stats, 0, sizeof(tlr_stats) * count);
   for (int i = 0; i < count; ++i) A[i]->stream = A[i]->mem.stream = (hipStream_t)stream;
-  tlr_status st = factorize_batch(A, count, eps, o, stats, ldl != 0);
+  tlr_status st = factorize_batch(A, count, eps, o, stats, ldl);
   if (ldl && D)
     for (int i = 0; i < count; ++i)
       if (D[i] && A[i]->factored == 2)
@@ -284,7 +309,29 @@ tlr_status tlr_factor_batched(int count, tlr_matrix_t* A, int ldl, double eps,
   }
   if (st < 0 && st != TLR_ERR_NOT_SPD && st != TLR_ERR_ZERO_PIVOT && st != TLR_ERR_ARG)
     for (int i = 0; i < count; ++i) A[i]->factored = 0;
+  if (stats) {
+    const double t = ms_since(t0);
+    for (int i = 0; i < count; ++i) stats[i].t_total = t;
+  }
   return st;
+}
+
+tlr_status tlr_factor_batched(int count, tlr_matrix_t* A, int ldl, double eps,
+                              const tlr_opts* opts, double* const* D, tlr_stats* stats,
+                              void* stream) {
+  TLR_ARG(count > 0 && A, "empty batch");
+  const std::vector<double> e(count, eps);
+  return batched_entry(count, A, ldl != 0, e.data(), opts, D, stats, stream);
+}
+
+tlr_status tlr_potrf_batched(int count, tlr_matrix_t* A, const double* eps, const tlr_opts* opts,
+                             tlr_stats* stats, void* stream) {
+  return batched_entry(count, A, false, eps, opts, nullptr, stats, stream);
+}
+
+tlr_status tlr_ldlt_batched(int count, tlr_matrix_t* A, const double* eps, const tlr_opts* opts,
+                            double* const* D, tlr_stats* stats, void* stream) {
+  return batched_entry(count, A, true, eps, opts, D, stats, stream);
 }
 
 tlr_status tlr_solve(tlr_matrix_t A, int nrhs, double* B, long long ldb, void* stream) {
@@ -388,6 +435,18 @@ tlr_status tlr_get_pivots(tlr_matrix_t A, double* d) {
     return TLR_ERR_STATE;
   }
   TLR_HIP(hipMemcpy(d, A->Dv, sizeof(double) * (size_t)A->nb * A->m, hipMemcpyDeviceToHost));
+  return TLR_OK;
+}
+
+tlr_status tlr_get_sort_order(tlr_matrix_t A, int k, int* rows) {
+  TLR_ARG(A && rows, "NULL argument");
+  TLR_ARG(k >= 0 && k < A->nb, "column %d out of range", k);
+  if (!A->factored || (int)A->sort_log.size() != A->nb) {
+    set_error("the handle holds no factor");
+    return TLR_ERR_STATE;
+  }
+  const std::vector<int>& o = A->sort_log[k];
+  std::copy(o.begin(), o.end(), rows);
   return TLR_OK;
 }
 

@@ -460,7 +460,7 @@ __global__ __launch_bounds__(256) void k_ara_compact(AraDev D, const int* waitin
   __shared__ int keep_total;
   __shared__ int scan[256];
   const int tid = threadIdx.x;
-  const int n = D.counts[0];
+  const int n = D.counts[0];   // active at entry: the iteration that ran
   for (int i = tid; i < n; i += 256) {
     const int slot = D.act[i];
     D.q[slot] = D.qnew[slot];
@@ -487,27 +487,14 @@ __global__ __launch_bounds__(256) void k_ara_compact(AraDev D, const int* waitin
                                                                              : scan[0];
     __hip_atomic_store(host_out + tid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
-  // once no tile is left the per-slot results (basis widths and counters,
-  // res_ints contiguous ints from D.q) are final: they go to the host too,
-  // so the host need not wait for the iteration queued behind this one
-  if (host_res && na == 0) {
+  // the compaction that empties the list (n > 0 tiles ran, none is left)
+  // publishes the per-slot results (basis widths and counters, res_ints
+  // contiguous ints from D.q), so the host need not wait for the iteration
+  // queued behind it; that spare iteration starts empty and writes nothing
+  if (host_res && n > 0 && na == 0) {
     for (int e = tid; e < res_ints; e += 256)
       __hip_atomic_store(host_res + e, D.q[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
-}
-
-// order[p] = rows sorted by (rank descending, row ascending): the position of
-// element i is the number of elements that precede it.
-__global__ void k_sort_ranks(const int* ranks, const int* rows, int n, int* order) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int ri = ranks[i], wi = rows[i];
-  int pos = 0;
-  for (int j = 0; j < n; ++j) {
-    const int rj = ranks[j], wj = rows[j];
-    pos += (rj > ri || (rj == ri && wj < wi)) ? 1 : 0;
-  }
-  order[pos] = wi;
 }
 
 }  // namespace
@@ -543,7 +530,7 @@ hipError_t launch_philox_raw(unsigned* out, int n, unsigned long long seed, unsi
 
 namespace {
 __global__ void k_mixed_guard(AraSlotDesc* slots, const GuardDesc* __restrict__ g, int n,
-                              int* f32) {
+                              int* prec) {
 #pragma clang fp contract(off)
   const int sl = blockIdx.x * blockDim.x + threadIdx.x;
   if (sl >= n) return;
@@ -553,21 +540,25 @@ __global__ void k_mixed_guard(AraSlotDesc* slots, const GuardDesc* __restrict__ 
     const double prod = d.fro[d.irow] * d.fro[0];
     nu = nu + prod;
   }
-  // u32 = 2^-24, the unit roundoff of the FP32 panels
-  const int use = (d.a1_32 != nullptr && 5.9604644775390625e-08 * nu <= d.thr) ? 1 : 0;
+  int use = 0;
+  if (d.a1_16 != nullptr && nu <= d.lim16)
+    use = 2;
+  else if (d.a1_32 != nullptr && nu <= d.lim32)
+    use = 1;
   if (use) {
-    slots[sl].a1 = d.a1_32;
-    slots[sl].a1_f32 = 1;
+    slots[sl].a1 = use == 2 ? d.a1_16 : d.a1_32;
+    slots[sl].lda1 = d.nrb;
+    slots[sl].a1_prec = use;
   }
-  f32[sl] = use;
+  prec[sl] = use;
 }
 }  // namespace
 
-hipError_t launch_mixed_guard(AraSlotDesc* slots, const GuardDesc* g, int n, int* f32,
+hipError_t launch_mixed_guard(AraSlotDesc* slots, const GuardDesc* g, int n, int* prec,
                               hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mixed_guard, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, slots, g, n,
-                     f32);
+                     prec);
   return hipGetLastError();
 }
 
@@ -617,12 +608,6 @@ hipError_t launch_compact(int* act, int* counts, const int* flag, const int* wai
                           int s_max, const int* info, hipStream_t s) {
   hipLaunchKernelGGL(k_compact, dim3(1), dim3(256), 0, s, act, counts, flag, waiting, nwaiting,
                      s_max, info);
-  return hipGetLastError();
-}
-
-hipError_t launch_sort_ranks(const int* ranks, const int* rows, int n, int* order, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sort_ranks, dim3((n + 255) / 256), dim3(256), 0, s, ranks, rows, n, order);
   return hipGetLastError();
 }
 

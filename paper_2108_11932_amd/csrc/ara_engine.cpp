@@ -233,6 +233,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     // descriptors (one buffer, drawn every iteration); the sampling through
     // P and W^A draws the matrices of kOmegaBatch iterations at a time
     const double* om = omega;
+    if (spec.pt) TLR_HIP(spec.pt->mark(TLR_PHASE_SAMPLE, st));
     if (omega_in_slots) {
       TLR_HIP(launch_randn(omega, m, D.bs, m, c.seed, c.stream_id, (unsigned)j, 0, st));
     } else {
@@ -250,11 +251,12 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       TLR_HIP(hipEventCreate(&e0));
       TLR_HIP(hipEventCreate(&e1));
       spec.events->push_back({e0, e1});
-      TLR_HIP(launch_ara_seg(D, 0, cb, st, e0, e1));
+      TLR_HIP(launch_ara_seg(D, 0, cb, st, c.strip, e0, e1));
     } else {
-      TLR_HIP(launch_ara_seg(D, 0, cb, st));
+      TLR_HIP(launch_ara_seg(D, 0, cb, st, c.strip));
     }
     const int bps_q = (qb + 31) / 32;
+    if (spec.pt) TLR_HIP(spec.pt->mark(TLR_PHASE_ORTH, st));
     if (bps_q > 0) {
       TLR_HIP(launch_ara_tn(D, 1, nullptr, nullptr, 0, 0, cb, bps_q, tn_scratch, st));
       TLR_HIP(launch_ara_seg(D, 1, cb, st));
@@ -265,6 +267,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       TLR_HIP(launch_ara_seg(D, 2, cb, st));
     }
     TLR_HIP(launch_orth_step(D, 2, c.r_min, cb, st));
+    if (spec.pt) TLR_HIP(spec.pt->mark(TLR_PHASE_BATCH, st));
     TLR_HIP(launch_ara_compact(D, s.waiting, nwait, s_max, info, ring + 8 * (j & 1), pres, res_ints,
                                st));
     TLR_HIP(hipEventRecord(h->ev_rb[j & 1], st));
@@ -338,7 +341,9 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     const double orth = 8.0 * m * qs + 6.0 * m * b2;
     res->flops_paper_orth[sl] = orth;
     res->flops_slot[sl] = orth + cols * spec.samp_flops_col[sl];
-    const double sb = (bf32[sl] && !spec.samp_bytes32.empty()) ? spec.samp_bytes32[sl] : spec.samp_bytes[sl];
+    const double sb = (bf32[sl] == 1 && !spec.samp_bytes32.empty())   ? spec.samp_bytes32[sl]
+                      : (bf32[sl] == 2 && !spec.samp_bytes16.empty()) ? spec.samp_bytes16[sl]
+                                                                       : spec.samp_bytes[sl];
     res->samp_bytes_slot[sl] = it * sb + cols * spec.samp_bytes_col[sl];
     res->samp_flops_slot[sl] = cols * spec.samp_flops_col[sl];
     res->flops += res->flops_slot[sl];

@@ -35,6 +35,7 @@ struct AraConfig {
   int s_max = 0;      // active subset size (<= 0: all)
   unsigned long long seed = 0;
   unsigned stream_id = 0;   // Philox counter word 2 (column index or batch id)
+  int strip = 0;      // rows per workgroup of the sampling product (0: automatic, 16, 64)
   // samples drawn by iteration `iter`, `active` tiles being active at its start
   int bs_for(int iter, int active) const {
     if (iter == 0 || bs_tail <= 0) return bs;
@@ -98,16 +99,18 @@ struct AraSpec {
   // before the first iteration; samp_bytes32 replaces samp_bytes for the
   // slots that take their FP32 panel
   std::vector<GuardDesc> guard;
-  std::vector<double> samp_bytes32;
+  std::vector<double> samp_bytes32, samp_bytes16;
   // when set, HIP events are recorded around every sampling launch
   std::vector<std::pair<hipEvent_t, hipEvent_t>>* events = nullptr;
+  // when set, the phase boundaries of every iteration are marked on it
+  PhaseTimer* pt = nullptr;
 };
 
 struct AraResult {
   std::vector<int> q;          // final basis width per slot
   std::vector<int> iters;      // iterations per slot
   std::vector<int> cols;       // samples drawn per slot
-  std::vector<int> f32;        // 1 where the slot sampled with its FP32 panel
+  std::vector<int> f32;        // precision of the slot's panel term: 0 FP64, 1 FP32, 2 BF16
   std::vector<int> iter_bs;    // samples per slot of every launched iteration
   std::vector<double> flops_paper_orth;  // per slot: orthogonalisation flops
   long long launches = 0;      // ARA iterations (batches)

@@ -162,11 +162,16 @@ __global__ __launch_bounds__(256) void k_ara_z(AraDev D, const ZSeg* __restrict_
 // of one tile: FM = 4 (64-row strips) reads 512 contiguous bytes of every
 // panel column and each test-matrix row once for four row blocks, where
 // enough tiles are active to keep the CUs busy; FM = 1 spreads few tiles over
-// four times more workgroups.  Both give the same Y bit for bit.
+// four times more workgroups.  Both give the same Y bit for bit.  In mode 0
+// the panel segment U_i* Z_i of a slot runs in the precision its descriptor
+// names (a1_prec: FP64, or the packed FP32 / BF16 panel copy with FP32
+// accumulation).
 template <int NF, int MODE, int FM>
 __global__ __launch_bounds__(256) void k_ara_seg(AraDev D) {
   constexpr int mode = MODE;
+  constexpr int R32 = MODE == 0 ? 4 : 1;
   __shared__ double red[4][FM * NF * 4][64];
+  __shared__ float red32[R32][FM * NF * 4][64];
   __shared__ double ys[16 * FM][16 * NF + 1];
   const int ns = D.nstrip;
   const int nblk = (ns + FM - 1) / FM;
@@ -178,19 +183,23 @@ __global__ __launch_bounds__(256) void k_ara_seg(AraDev D) {
   const int r0 = blk * 16 * FM;
   double* part;
   if (mode == 0) {
-    if (d.a1_f32)
-      seg_strip<NF, true, FM>(d.a0, d.lda0, d.b0, d.ldb0, d.k0, d.a1, d.lda1, d.b1, d.ldb1, d.k1,
-                              d.y, m, m, bs, 0.0, r0, red, ys);
+    float (*r32)[FM * NF * 4][64] = (float (*)[FM * NF * 4][64])red32;
+    if (d.a1_prec == 1)
+      seg_strip<NF, 1, FM>(d.a0, d.lda0, d.b0, d.ldb0, d.k0, d.a1, d.lda1, d.b1, d.ldb1, d.k1,
+                           d.y, m, m, bs, 0.0, r0, red, r32, ys);
+    else if (d.a1_prec == 2)
+      seg_strip<NF, 2, FM>(d.a0, d.lda0, d.b0, d.ldb0, d.k0, d.a1, d.lda1, d.b1, d.ldb1, d.k1,
+                           d.y, m, m, bs, 0.0, r0, red, r32, ys);
     else
-      seg_strip<NF, false, FM>(d.a0, d.lda0, d.b0, d.ldb0, d.k0, d.a1, d.lda1, d.b1, d.ldb1, d.k1,
-                               d.y, m, m, bs, 0.0, r0, red, ys);
+      seg_strip<NF, 0, FM>(d.a0, d.lda0, d.b0, d.ldb0, d.k0, d.a1, d.lda1, d.b1, d.ldb1, d.k1,
+                           d.y, m, m, bs, 0.0, r0, red, r32, ys);
     part = d.part1;
   } else {
     const int q = D.q[slot];
     if (q == 0) return;
     double* dst = mode == 1 ? d.y : d.q + (size_t)q * m;
-    seg_strip<NF, false, FM>(d.q, m, d.c, m, q, nullptr, 1, nullptr, 1, 0, dst, m, m, bs, 1.0, r0,
-                             red, ys);
+    seg_strip<NF, 0, FM>(d.q, m, d.c, m, q, nullptr, 1, nullptr, 1, 0, dst, m, m, bs, 1.0, r0,
+                         red, nullptr, ys);
     part = mode == 1 ? d.part1 : d.part2;
   }
   // Gram partials of each 16-row strip (Dot2 over its rows), pairs a <= b
@@ -273,11 +282,13 @@ hipError_t seg_launch(const AraDev& D, int mode, int count_bound, hipStream_t s,
 }
 }  // namespace
 
-hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_t s,
+hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_t s, int strip,
                           hipEvent_t start, hipEvent_t stop) {
   if (D.bs > 32 || mode < 0 || mode > 2) return hipErrorInvalidValue;
   if ((long long)std::max(count_bound, 0) * D.nstrip <= 0) return hipSuccess;
-  const bool tall = mode == 0 && (long long)count_bound * ((D.nstrip + 3) / 4) >= kTallWgs;
+  const bool tall = mode == 0 && (strip == 64 || (strip == 0 && (long long)count_bound *
+                                                                       ((D.nstrip + 3) / 4) >=
+                                                                   kTallWgs));
   if (D.bs <= 16)
     return tall ? seg_launch<1, 4>(D, mode, count_bound, s, start, stop)
                 : seg_launch<1, 1>(D, mode, count_bound, s, start, stop);

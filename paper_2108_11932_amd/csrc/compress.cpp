@@ -77,8 +77,9 @@ tlr_status compress(Handle* h, const double* A, long long lda, const double* pts
   cfg.bs_tail = o.bs_tail;
   cfg.tail_active = o.tail_active;
   cfg.qcap = m;
-  cfg.tau = eps;
+  cfg.tau = eps / o.conv_factor;
   cfg.r_min = o.r_min;
+  cfg.strip = o.sample_strip;
   cfg.s_max = 0;
   cfg.seed = o.seed ^ 0xC0FFEEULL;
   AraSlots slots;

@@ -36,13 +36,16 @@ void free_factor(Handle* h) {
   for (double* p : h->UL) h->mem.put(p);
   for (double* p : h->VL) h->mem.put(p);
   for (float* p : h->UL32) h->mem.put(p);
+  for (unsigned short* p : h->UL16) h->mem.put(p);
   h->UL.assign(h->nb, nullptr);
   h->VL.assign(h->nb, nullptr);
   h->UL32.assign(h->nb, nullptr);
+  h->UL16.assign(h->nb, nullptr);
   h->R.assign(h->nb, 0);
   h->cap.assign(h->nb, 0);
   h->l_rank.assign((size_t)h->nb * h->nb, 0);
   h->l_off.assign((size_t)h->nb * h->nb, -1);
+  h->sort_log.assign(h->nb, std::vector<int>());
   h->factored = 0;
 }
 
@@ -54,37 +57,43 @@ void free_factor(Handle* h) {
 static tlr_status grow_row(Handle* h, int i, int extra) {
   const int need = h->R[i] + extra;
   if (need <= h->cap[i]) return TLR_OK;
+  // capacities in whole 32-column slices, so that the packed copies (slices
+  // of 16 and 32 columns over all row blocks, one after another) hold a
+  // prefix of whole slices that a larger copy extends
   int nc = std::max(need, h->cap[i] + h->cap[i] / 2 + 16);
-  nc = (nc + 15) & ~15;
+  nc = (nc + 31) & ~31;
+  const size_t prow = (size_t)16 * ((h->m + 15) / 16);   // rows of a packed copy
   void* u = nullptr;
   void* v = nullptr;
-  TLR_TRY(h->mem.get(&u, sizeof(double) * (size_t)h->m * nc));
-  tlr_status st = h->mem.get(&v, sizeof(double) * (size_t)h->m * nc);
-  if (st != TLR_OK) {
-    h->mem.put(u);
-    return st;
-  }
   void* u32 = nullptr;
-  if (h->mixed) {
-    st = h->mem.get(&u32, sizeof(float) * (size_t)h->m * nc);
-    if (st != TLR_OK) {
-      h->mem.put(u);
-      h->mem.put(v);
-      return st;
-    }
+  void* u16 = nullptr;
+  tlr_status st = h->mem.get(&u, sizeof(double) * (size_t)h->m * nc);
+  if (st == TLR_OK) st = h->mem.get(&v, sizeof(double) * (size_t)h->m * nc);
+  if (st == TLR_OK && h->mixed >= 1) st = h->mem.get(&u32, sizeof(float) * prow * nc);
+  if (st == TLR_OK && h->mixed >= 2) st = h->mem.get(&u16, sizeof(unsigned short) * prow * nc);
+  if (st != TLR_OK) {
+    for (void* p : {u, v, u32, u16}) h->mem.put(p);
+    return st;
   }
   if (h->R[i] > 0) {
     const size_t bytes = sizeof(double) * (size_t)h->m * h->R[i];
     TLR_HIP(hipMemcpyAsync(u, h->UL[i], bytes, hipMemcpyDeviceToDevice, h->stream));
     TLR_HIP(hipMemcpyAsync(v, h->VL[i], bytes, hipMemcpyDeviceToDevice, h->stream));
-    if (h->mixed)
-      TLR_HIP(hipMemcpyAsync(u32, h->UL32[i], bytes / 2, hipMemcpyDeviceToDevice, h->stream));
+    // the packed copies: every slice that holds a written column
+    const size_t cols = (size_t)((h->R[i] + 31) & ~31);
+    if (u32)
+      TLR_HIP(hipMemcpyAsync(u32, h->UL32[i], sizeof(float) * prow * cols, hipMemcpyDeviceToDevice,
+                             h->stream));
+    if (u16)
+      TLR_HIP(hipMemcpyAsync(u16, h->UL16[i], sizeof(unsigned short) * prow * cols,
+                             hipMemcpyDeviceToDevice, h->stream));
   }
-  for (void* old : {(void*)h->UL[i], (void*)h->VL[i], (void*)h->UL32[i]})
+  for (void* old : {(void*)h->UL[i], (void*)h->VL[i], (void*)h->UL32[i], (void*)h->UL16[i]})
     if (old) h->retired.push_back(old);
   h->UL[i] = (double*)u;
   h->VL[i] = (double*)v;
   h->UL32[i] = (float*)u32;
+  h->UL16[i] = (unsigned short*)u16;
   h->cap[i] = nc;
   return TLR_OK;
 }
@@ -125,10 +134,11 @@ namespace {
 struct Prob {
   Handle* h = nullptr;
   double tau = 0.0, shift = 0.0;
+  double tau_ara = 0.0;   // threshold of the ARA: tau / conv_factor
   double* pin_norm = nullptr;
   bool done = false;
   double flops = 0.0, flops_paper = 0.0, bytes_alg = 0.0, samp_bytes = 0.0, samp_flops = 0.0;
-  long long ara_iters = 0, tile_iters = 0, fp32_tile_iters = 0;
+  long long ara_iters = 0, tile_iters = 0, fp32_tile_iters = 0, bf16_tile_iters = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   std::vector<long long> goff;
   // column k
@@ -146,6 +156,7 @@ struct Prob {
   std::vector<long long> goff_next;
   std::unique_ptr<Plan> dplan, gplan;
   bool side_pending = false;   // the side worker holds this column's launches
+  PhaseTimer* pt = nullptr;    // phase marks of the (shared) main stream
   std::vector<int> order;
   const double* gptr(int i, int j) const {
     if (j == jk) {
@@ -186,10 +197,19 @@ tlr_status prob_init(Prob& p, double eps, const tlr_opts& o, bool ldl) {
     p.tau = eps * h->norm_a;
   }
   p.shift = o.shift < 0.0 ? p.tau : o.shift;
+  p.tau_ara = p.tau / o.conv_factor;
   TLR_HIP(hipMemsetAsync(h->d_info, 0, sizeof(int), h->stream));
-  // mixed precision: FP32 panels for the tiles whose FP32 rounding stays
-  // below tau / 16 (the LDL^T variant samples in FP64 throughout)
-  h->mixed = o.precision == TLR_MIXED_FP32 && !ldl;
+  // mixed precision: packed FP32 (and BF16) copies of the U panels, used by
+  // the tiles whose rounding in that precision stays below tau / 16 (the
+  // LDL^T variant samples in FP64 throughout).  The automatic form keeps a
+  // BF16 copy when the threshold is at least 1e-3 ||A||_2.
+  h->mixed = 0;
+  if (!ldl && o.precision == TLR_MIXED_FP32) h->mixed = 1;
+  if (!ldl && o.precision == TLR_MIXED_BF16) h->mixed = 2;
+  if (!ldl && o.precision == TLR_MIXED_AUTO) {
+    if (h->norm_a <= 0.0) TLR_TRY(estimate_norm(h, &h->norm_a));
+    h->mixed = p.tau >= 1e-3 * h->norm_a ? 2 : 1;
+  }
   if (h->mixed && h->a_fro.empty()) TLR_TRY(input_norms(h));
   h->l_fro.assign((size_t)nb * nb, 0.0);
   if (h->mixed) TLR_TRY(h->pinned_norms((size_t)std::max(nb, 1), &p.pin_norm));
@@ -214,6 +234,7 @@ tlr_status col_begin(Prob& p, int k, bool ldl) {
   Handle* h = p.h;
   const int m = h->m, nb = h->nb;
   Work& w = h->ws;
+  TLR_HIP(p.pt->mark(TLR_PHASE_GBLOCKS, h->stream));
   p.Rk = h->R[k];
   const int Rk = p.Rk;
   // ---------------------------------------------- G_ij = V_ij^T (D_j) V_kj
@@ -301,14 +322,18 @@ tlr_status col_begin(Prob& p, int k, bool ldl) {
   // The order (descending input rank, ties by row) needs only the input
   // ranks: it is taken on the host and the device queue is not drained
   // (the mixed form's precision choice is made on the device).
-  p.order.clear();
+  p.order.assign(p.nrow, 0);
   if (p.nrow > 0) {
-    p.order.resize(p.nrow);
-    for (int s = 0; s < p.nrow; ++s) p.order[s] = s;
-    std::stable_sort(p.order.begin(), p.order.end(), [&](int a, int b) {
-      return h->ar(k + 1 + a, k) > h->ar(k + 1 + b, k);
-    });
+    std::vector<int> rk(p.nrow), rows(p.nrow);
+    for (int s = 0; s < p.nrow; ++s) {
+      rows[s] = k + 1 + s;
+      rk[s] = h->ar(k + 1 + s, k);
+    }
+    sort_ranks(rk.data(), rows.data(), p.nrow, p.order.data());
   }
+  std::vector<int>& log = h->sort_log[k];
+  log.resize(p.nrow);
+  for (int s = 0; s < p.nrow; ++s) log[s] = k + 1 + p.order[s];
   return TLR_OK;
 }
 
@@ -358,8 +383,11 @@ tlr_status col_diag(Prob& p, int k, bool ldl) {
     if (!h->worker) h->worker.reset(new SideWorker(h->dev));
     std::shared_ptr<Plan> plan(p.dplan.release());
     hipEvent_t ej = h->ev_join;
-    h->worker->submit([plan, ej, ds]() -> tlr_status {
+    PhaseTimer* pts = &h->pt_side;
+    h->worker->submit([plan, ej, ds, pts]() -> tlr_status {
+      TLR_HIP(pts->mark(TLR_PHASE_DIAG, ds));
       TLR_TRY(plan->run());
+      TLR_HIP(pts->mark(-1, ds));
       TLR_HIP(hipEventRecord(ej, ds));
       return TLR_OK;
     });
@@ -428,8 +456,11 @@ tlr_status col_lookahead(Prob& p, int k, bool ldl) {
     p.ahead = kn;
     std::shared_ptr<Plan> gplan(p.gplan.release());
     hipEvent_t eg = h->ev_gnext;
-    h->worker->submit([gplan, eg, ds]() -> tlr_status {
+    PhaseTimer* pts = &h->pt_side;
+    h->worker->submit([gplan, eg, ds, pts]() -> tlr_status {
+      TLR_HIP(pts->mark(TLR_PHASE_DIAG, ds));
       TLR_TRY(gplan->run());
+      TLR_HIP(pts->mark(-1, ds));
       TLR_HIP(hipEventRecord(eg, ds));
       return TLR_OK;
     });
@@ -483,7 +514,7 @@ tlr_status col_spec(Prob& p, int k, int bsm, AraSpec& spec) {
       double* zs = Z + zo;
       zo += (long long)Ri * bsm;
       d.a1 = (const void*)h->UL[i];
-      d.a1_f32 = 0;
+      d.a1_prec = 0;
       d.k1 = Ri;
       d.b1 = zs;
       d.ldb1 = Ri;
@@ -502,20 +533,27 @@ tlr_status col_spec(Prob& p, int k, int bsm, AraSpec& spec) {
     const double kk = (double)a + d.k1;
     spec.samp_flops_col[p.base + s] = 2.0 * m * kk;
     spec.samp_bytes[p.base + s] = 8.0 * m * a + 8.0 * m * d.k1;
-    if (h->mixed) {
-      // FP32 panel when its rounding, u32 (||A_ik||_F + sum_j ||L_ij||_F
-      // ||L_kj||_F), stays below tau / 16; the newest column's term is
-      // added on the device, where its norms were formed
+    if (h->mixed && d.k1 > 0) {
+      // a low-precision panel term when its rounding, (2 u_p + sqrt(R_i)
+      // u32) nu_ik with nu_ik = ||A_ik||_F + sum_j ||L_ij||_F ||L_kj||_F,
+      // stays below tau / 16 (both operands rounded once, FP32 accumulation
+      // over R_i terms); the newest column's term of nu is added on the
+      // device, where its norms were formed
       const int nb = h->nb;
       double nu = h->a_fro[(size_t)i * nb + k];
       for (int j = 0; j + 1 < k; ++j)
         nu += h->l_fro[(size_t)i * nb + j] * h->l_fro[(size_t)k * nb + j];
+      const double u32 = 5.9604644775390625e-08, u16 = 3.90625e-03;
+      const double acc = std::sqrt((double)d.k1) * u32;
       spec.samp_bytes32[p.base + s] = 8.0 * m * a + 4.0 * m * d.k1;
-      spec.guard[p.base + s] = GuardDesc{(const void*)h->UL32[i], h->ws.fro.as<double>(), nu,
-                                         p.tau / 16.0, k >= 1 ? i - k : -1, 0};
+      spec.samp_bytes16[p.base + s] = 8.0 * m * a + 2.0 * m * d.k1;
+      spec.guard[p.base + s] =
+          GuardDesc{(const void*)h->UL32[i], h->mixed >= 2 ? (const void*)h->UL16[i] : nullptr,
+                    h->ws.fro.as<double>(), nu, p.tau_ara / (16.0 * (2.0 * u32 + acc)),
+                    p.tau_ara / (16.0 * (2.0 * u16 + acc)), k >= 1 ? i - k : -1, (m + 15) / 16};
     }
     spec.samp_bytes_col[p.base + s] = 8.0 * (kk + m);
-    spec.tau[p.base + s] = p.tau;
+    spec.tau[p.base + s] = p.tau_ara;
   }
   return TLR_OK;
 }
@@ -548,7 +586,8 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
     for (int j = 0; j < k; ++j) zf += (double)h->lr(i, j) * h->lr(k, j);
     const double cols = res.cols[sl];
     p.flops += cols * 2.0 * ((double)h->ar(i, k) * m + zf);
-    if (res.f32[sl]) p.fp32_tile_iters += it[s];
+    if (res.f32[sl] == 1) p.fp32_tile_iters += it[s];
+    if (res.f32[sl] == 2) p.bf16_tile_iters += it[s];
     p.flops += res.flops_slot[sl];
     p.samp_bytes += res.samp_bytes_slot[sl];
     p.samp_flops += res.samp_flops_slot[sl];
@@ -591,6 +630,7 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
   }
   // The products that need only the bases go out first, so the GPU works on
   // them while the host builds the per-block batch of the update term.
+  TLR_HIP(p.pt->mark(TLR_PHASE_PROJECT, h->stream));
   {
     Plan first(h);
     GemmBatch t1(true, false), t2(true, false), b1(false, false);
@@ -636,9 +676,11 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
   }
   // ---------------------------------------------- batchTrsm (+ batchIDMult)
   // V = L_kk^{-1} B for every tile of the column: one triangular product
+  PhaseTimer* pt = p.pt;
   {
     hipStream_t st = h->stream;
     hipEvent_t ej = h->ev_join;
+    plan.launch([=]() { return pt->mark(TLR_PHASE_TRSM, st); });
     plan.launch([=]() { return hipStreamWaitEvent(st, ej, 0); });
     GemmBatch tb(false, false);
     tb.add(m, (int)sq, m, h->invL(k), m, Ball, m, Bt, m, 1.0, 0.0, GEMM_TRIL_A);
@@ -652,6 +694,8 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
   p.flops += (double)m * m * sq;
   // ---------------------------------------------- updateTiles
   {
+    hipStream_t st = h->stream;
+    plan.launch([=]() { return pt->mark(TLR_PHASE_APPEND, st); });
     std::vector<CopyDesc> cd;
     int maxc = 0;
     for (int s = 0; s < nrow; ++s) {
@@ -659,8 +703,9 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
       if (qs == 0) continue;
       CopyDesc c{slots.qb(p.base + s), h->UL[i] + (size_t)h->R[i] * m, m, qs, m, m};
       if (h->mixed) {
-        c.dst32 = h->UL32[i] + (size_t)h->R[i] * m;
-        c.ldd32 = m;
+        c.dst32 = h->UL32[i];
+        c.dst16 = h->UL16[i];
+        c.pcol = h->R[i];
       }
       cd.push_back(c);
       cd.push_back(CopyDesc{Bt + boff[s] * m, h->VL[i] + (size_t)h->R[i] * m, m, qs, m, m});
@@ -714,7 +759,8 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
 }
 
 // Statistics and status of a finished problem.
-tlr_status prob_finish(Prob& p, const tlr_opts& o, bool ldl, tlr_stats* st) {
+tlr_status prob_finish(Prob& p, const tlr_opts& o, bool ldl, tlr_stats* st,
+                       const double* t_main) {
   Handle* h = p.h;
   const int m = h->m, nb = h->nb;
   double samp_ms = 0.0;
@@ -739,6 +785,7 @@ tlr_status prob_finish(Prob& p, const tlr_opts& o, bool ldl, tlr_stats* st) {
     st->ara_iters = p.ara_iters;
     st->tile_iters = p.tile_iters;
     st->fp32_tile_iters = p.fp32_tile_iters;
+    st->bf16_tile_iters = p.bf16_tile_iters;
     long long cnt = 0, tot = 0, full = 0;
     int mx = 0;
     for (int i = 0; i < nb; ++i)
@@ -757,6 +804,11 @@ tlr_status prob_finish(Prob& p, const tlr_opts& o, bool ldl, tlr_stats* st) {
     st->sample_ms = samp_ms;
     st->sample_bytes = p.samp_bytes;
     st->sample_flops = p.samp_flops;
+    st->shift = p.shift;
+    if (h->pt_side.on) {
+      for (int f = 0; f < TLR_NPHASE; ++f) st->t_phase[f] = t_main[f];
+      TLR_TRY(h->pt_side.collect(st->t_phase));
+    }
   }
   if (info != 0) {
     h->factored = 0;
@@ -774,13 +826,17 @@ tlr_status prob_finish(Prob& p, const tlr_opts& o, bool ldl, tlr_stats* st) {
 // the active tiles of every problem in each launch).  Everything runs on
 // the first problem's (shared) main stream; each problem keeps its own
 // diagonal-tile stream.
-tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o, bool ldl,
-                           tlr_stats* stats, const std::vector<int>& idx) {
+tlr_status factorize_group(std::vector<Prob>& ps, const double* eps, const tlr_opts& o,
+                           bool ldl, tlr_stats* stats, const std::vector<int>& idx) {
   Handle* lead = ps[idx[0]].h;
   const int m = lead->m, bs = o.bs;
   int nbmax = 0, slots_max = 1;
+  const bool phases = (o.flags & TLR_FLAG_PHASE_TIMING) != 0;
+  lead->pt_main.reset(phases);
   for (int pi : idx) {
-    TLR_TRY(prob_init(ps[pi], eps, o, ldl));
+    ps[pi].pt = &lead->pt_main;
+    ps[pi].h->pt_side.reset(phases);
+    TLR_TRY(prob_init(ps[pi], eps[pi], o, ldl));
     nbmax = std::max(nbmax, ps[pi].h->nb);
   }
   for (int k = 0; k < nbmax; ++k) {
@@ -799,6 +855,7 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
   cfg.r_min = o.r_min;
   cfg.s_max = o.max_active;
   cfg.seed = o.seed;
+  cfg.strip = o.sample_strip;
   AraSlots slots;
   TLR_TRY(ara_slots(lead, cfg, slots_max, &slots));
   const bool timing = (o.flags & TLR_FLAG_KERNEL_TIMING) != 0;
@@ -850,8 +907,11 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
     spec.samp_flops_col.assign(total, 0.0);
     spec.tau.assign(total, 0.0);
     if (lead->mixed) {
-      spec.guard.assign(total, GuardDesc{nullptr, nullptr, 0.0, 0.0, -1, 0});
+      GuardDesc none{};
+      none.irow = -1;
+      spec.guard.assign(total, none);
       spec.samp_bytes32.assign(total, 0.0);
+      spec.samp_bytes16.assign(total, 0.0);
     }
     int prow = 0;
     for (int pi : live) {
@@ -865,6 +925,7 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
     spec.p = lw.P.as<double>();
     spec.ldp = std::max(prow, 1);
     spec.events = timing ? &ps[idx[0]].events : nullptr;
+    spec.pt = phases ? &lead->pt_main : nullptr;
     for (int pi : live) {
       Prob& p = ps[pi];
       if (p.nrow > 0) TLR_TRY(col_spec(p, k, bsm, spec));
@@ -902,11 +963,14 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
     TLR_HIP(hipEventRecord(h->ev_join, h->side));
     TLR_HIP(hipStreamWaitEvent(h->stream, h->ev_join, 0));
   }
+  TLR_HIP(lead->pt_main.mark(-1, lead->stream));
   for (int pi : idx) TLR_TRY(ps[pi].h->sync());
   for (int pi : idx) release_retired(ps[pi].h);
+  double t_main[TLR_NPHASE] = {0.0};
+  if (phases) TLR_TRY(lead->pt_main.collect(t_main));
   tlr_status first = TLR_OK;
   for (int pi : idx) {
-    const tlr_status s = prob_finish(ps[pi], o, ldl, stats ? stats + pi : nullptr);
+    const tlr_status s = prob_finish(ps[pi], o, ldl, stats ? stats + pi : nullptr, t_main);
     if (first == TLR_OK && s != TLR_OK) first = s;
   }
   return first;
@@ -914,7 +978,7 @@ tlr_status factorize_group(std::vector<Prob>& ps, double eps, const tlr_opts& o,
 
 }  // namespace
 
-tlr_status factorize_batch(Handle* const* hs, int count, double eps, const tlr_opts& o,
+tlr_status factorize_batch(Handle* const* hs, int count, const double* eps, const tlr_opts& o,
                            tlr_stats* st, bool ldl) {
   std::vector<Prob> ps(count);
   for (int i = 0; i < count; ++i) ps[i].h = hs[i];
@@ -928,14 +992,28 @@ tlr_status factorize_batch(Handle* const* hs, int count, double eps, const tlr_o
     for (int i = 0; i < count; ++i)
       if (hs[i]->m == m) idx.push_back(i);
     const tlr_status s = factorize_group(ps, eps, o, ldl, st, idx);
-    if (s < 0 && s != TLR_ERR_NOT_SPD && s != TLR_ERR_ZERO_PIVOT) return s;
+    if (s < 0) {
+      // a failure part way (allocation, launch): let the queued work of
+      // both streams and of the side worker finish before the handles are
+      // touched again, and leave them without a factor
+      for (int i : idx) {
+        Handle* h = hs[i];
+        if (h->worker) (void)h->worker->wait();
+        (void)hipStreamSynchronize(h->stream);
+        if (h->side) (void)hipStreamSynchronize(h->side);
+        release_retired(h);
+        h->stage.used = 0;
+        h->factored = 0;
+      }
+      return s;
+    }
     if (first == TLR_OK && s != TLR_OK) first = s;
   }
   return first;
 }
 
 tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bool ldl) {
-  return factorize_batch(&h, 1, eps, o, st, ldl);
+  return factorize_batch(&h, 1, &eps, o, st, ldl);
 }
 
 }  // namespace tlr

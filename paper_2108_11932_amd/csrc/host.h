@@ -70,6 +70,9 @@ struct Staging {
   char* host = nullptr;
   char* dev = nullptr;
   size_t cap = 0, used = 0;
+  // when set, an upload larger than the whole ring fails (TLR_ERR_ARG)
+  // instead of growing the ring: callers that must not allocate
+  bool fixed = false;
   tlr_status init(Mem& mem, size_t bytes);
   void release(Mem& mem);
   // Copy `bytes` of host data to device memory on stream s (default: the
@@ -100,41 +103,6 @@ struct GemmBatch {
   tlr_status run(Handle* h, hipStream_t s = nullptr);
 };
 
-// One launch of the narrow two-segment product (sampling, Gram-Schmidt).
-struct SegBatch {
-  std::vector<SegDesc> d;
-  double flops = 0.0, bytes = 0.0;
-  bool a1_f32 = false;   // segment 1's A is float in every problem of the batch
-  void add(int M, int N, const double* A0, int lda0, const double* B0, int ldb0, int K0,
-           const double* A1, int lda1, const double* B1, int ldb1, int K1, double* C, int ldc,
-           double beta) {
-    add_any(M, N, A0, lda0, B0, ldb0, K0, A1, lda1, B1, ldb1, K1, C, ldc, beta, 8.0);
-  }
-  void add_f32(int M, int N, const double* A0, int lda0, const double* B0, int ldb0, int K0,
-               const float* A1, int lda1, const double* B1, int ldb1, int K1, double* C, int ldc,
-               double beta) {
-    a1_f32 = true;
-    add_any(M, N, A0, lda0, B0, ldb0, K0, A1, lda1, B1, ldb1, K1, C, ldc, beta, 4.0);
-  }
-  void add_any(int M, int N, const double* A0, int lda0, const double* B0, int ldb0, int K0,
-               const void* A1, int lda1, const double* B1, int ldb1, int K1, double* C, int ldc,
-               double beta, double a1_bytes) {
-    if (M <= 0 || N <= 0) return;
-    SegDesc s{};
-    s.A[0] = A0; s.B[0] = B0; s.lda[0] = lda0 > 0 ? lda0 : 1; s.ldb[0] = ldb0 > 0 ? ldb0 : 1;
-    s.K[0] = K0 > 0 ? K0 : 0;
-    s.A[1] = A1; s.B[1] = B1; s.lda[1] = lda1 > 0 ? lda1 : 1; s.ldb[1] = ldb1 > 0 ? ldb1 : 1;
-    s.K[1] = K1 > 0 ? K1 : 0;
-    s.C = C; s.ldc = ldc; s.M = M; s.N = N; s.beta = beta;
-    d.push_back(s);
-    const double K = (double)s.K[0] + s.K[1];
-    flops += 2.0 * M * N * K;
-    bytes += 8.0 * ((double)M * s.K[0] + K * N + (beta != 0.0 ? 2.0 : 1.0) * M * N) +
-             a1_bytes * M * s.K[1];
-  }
-  tlr_status run(Handle* h, hipStream_t s = nullptr);
-};
-
 // A sequence of launches whose descriptors are staged with a single copy:
 // add() batches in launch order, then run() uploads everything once and
 // issues the launches on the plan's stream.
@@ -148,7 +116,6 @@ struct Plan {
   // stage raw bytes; returns the offset of the copy inside the device blob
   size_t stage(const void* p, size_t n);
   void gemm(const GemmBatch& b);
-  void seg(const SegBatch& b);
   // a launch that reads staged bytes at `off` (device address passed in)
   void launch(size_t off, std::function<hipError_t(const char*)> f);
   // a launch that needs no staged data
@@ -206,6 +173,26 @@ struct Work {
   }
 };
 
+// Phase timing of one stream (TLR_FLAG_PHASE_TIMING): events recorded at the
+// phase boundaries; the GPU time between a mark and the next one is charged
+// to the phase of the first (phase < 0: not charged, e.g. an idle gap on the
+// second stream).  The events are pooled and reused across calls.
+struct PhaseTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ph;
+  size_t n = 0;
+  void reset(bool enable) {
+    on = enable;
+    n = 0;
+    ph.clear();
+  }
+  hipError_t mark(int phase, hipStream_t s);
+  // after the stream has completed: add the charged times (ms) to t
+  tlr_status collect(double* t);
+  void destroy();
+};
+
 }  // namespace tlr
 
 // The matrix handle behind the opaque tlr_matrix_t.
@@ -221,6 +208,7 @@ struct tlr_matrix_s {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gnext = nullptr;
   std::unique_ptr<tlr::SideWorker> worker;   // issues the side-stream launches
   Staging stage;
+  tlr::PhaseTimer pt_main, pt_side;   // TLR_FLAG_PHASE_TIMING
 
   // input matrix
   double* Ad = nullptr;           // nb diagonal tiles, m x m each
@@ -242,13 +230,20 @@ struct tlr_matrix_s {
   std::vector<long long> l_off;   // column of tile (i, j) inside row i's panel
   std::vector<int> R, cap;        // panel width and capacity per block row
   std::vector<double*> UL, VL;
-  std::vector<float*> UL32;       // FP32 copies of the U panels (mixed precision)
+  // packed FP32 / BF16 copies of the U panels (mixed precision; layout of
+  // pack_index, capacity cap[i] columns)
+  std::vector<float*> UL32;
+  std::vector<unsigned short*> UL16;
   // panels replaced by larger ones during a factorization: queued work may
   // still read them, so they are released once the factorization has
   // synchronised (or with the factor)
   std::vector<void*> retired;
-  bool mixed = false;             // the current factorization keeps UL32
+  // copies the current factorization keeps: 0 none, 1 UL32, 2 UL32 and UL16
+  int mixed = 0;
   std::vector<double> l_fro;      // ||L_ij||_F per tile (U orthonormal: ||V_ij||_F)
+  // sortRanks order of every column's tiles in the last factorization
+  // (global block rows, column k at sort_log[k])
+  std::vector<std::vector<int>> sort_log;
   double* pin_norm = nullptr;     // pinned read-back of a column's V norms
   int* pin_ring = nullptr;        // pinned read-back ring of the ARA iterations (2 x 8)
   int* pin_res = nullptr;         // pinned read-back of an ARA run's per-slot results
@@ -302,23 +297,34 @@ tlr_status dense_factor(Handle* h, struct Plan& plan, bool chol, double* A, int 
 
 // Kernel wrappers not declared in tlr_internal.h.
 hipError_t launch_zero_upper(double* A, int lda, int m, hipStream_t s);
+// p[0 .. n) = v
+hipError_t launch_fill(double* p, long long n, double v, hipStream_t s);
 hipError_t launch_pivot_tol(const double* A, int lda, int m, double* tol, hipStream_t s);
 
 // Batched ARA over a set of explicitly sampled operators: shared by the
 // factorization (Schur-complement tiles) and the compression (explicit tiles).
 struct AraProblem;
 
+// "sortRanks" (Section 4.2): the permutation idx of 0 .. n - 1 that orders
+// the entries by rank descending, ties by row ascending, then by index.
+void sort_ranks(const int* ranks, const int* rows, int n, int* idx);
+
 tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bool ldl);
-// count problems at once (st: count entries or NULL); problems of one tile
-// size step through their columns together with pooled ARA launches.  All
-// handles must use the same main stream.
-tlr_status factorize_batch(Handle* const* hs, int count, double eps, const tlr_opts& o,
+// count problems at once, problem i at threshold eps[i] (st: count entries or
+// NULL); problems of one tile size step through their columns together with
+// pooled ARA launches.  All handles must use the same main stream.
+tlr_status factorize_batch(Handle* const* hs, int count, const double* eps, const tlr_opts& o,
                            tlr_stats* st, bool ldl);
 tlr_status compress(Handle* h, const double* A, long long lda, const double* pts, int dim,
                     int kernel, double ell, double diag_add, double eps, const tlr_opts& o);
 tlr_status estimate_norm(Handle* h, double* out);
 tlr_status matvec(Handle* h, int nrhs, const double* X, long long ldx, double* Y, long long ldy);
 tlr_status solve(Handle* h, int nrhs, double* B, long long ldb);
+// Doubles of workspace the solve of nrhs right-hand sides needs.
+size_t solve_workspace(const Handle* h, int nrhs);
+// The solve with a caller-provided workspace of solve_workspace() doubles
+// (device memory); allocates nothing.
+tlr_status solve_in(Handle* h, int nrhs, double* B, long long ldb, double* work);
 tlr_status alloc_input(Handle* h, const int* ranks);
 void free_factor(Handle* h);
 

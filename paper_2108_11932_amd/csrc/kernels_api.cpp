@@ -118,6 +118,16 @@ tlr_status tlrk_randn(int rows, int cols, unsigned long long seed, unsigned k, u
   return TLR_OK;
 }
 
+tlr_status tlrk_randn_iters(int rows, int cols0, int cols1, unsigned long long seed, unsigned k,
+                            unsigned t0, int nt, unsigned s, double* out, void* stream) {
+  KARG(rows >= 0 && cols0 >= 0 && cols1 >= 0 && nt >= 0 && out, "invalid argument");
+  const size_t stride = (size_t)rows * std::max(cols0, cols1);
+  TLR_HIP(launch_randn_iters(out, rows, stride, cols0, cols1, seed, k, t0, nt, s,
+                             (hipStream_t)stream));
+  TLR_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return TLR_OK;
+}
+
 tlr_status tlrk_ara(int m, int count, const double* tiles, double tau, int bs, int r_min,
                     unsigned long long seed, double* Q, double* B, int* ranks, int* iters,
                     void* stream) {
@@ -163,17 +173,9 @@ tlr_status tlrk_ara(int m, int count, const double* tiles, double tau, int bs, i
 
 tlr_status tlrk_sort_ranks(int n, const int* ranks, const int* rows, int* order) {
   KARG(n >= 0 && (n == 0 || (ranks && rows && order)), "invalid argument");
-  if (n == 0) return TLR_OK;
-  Ctx c;
-  TLR_TRY(c.init(nullptr, 1));
-  void* dr = nullptr;
-  void* dw = nullptr;
-  TLR_TRY(c.h.stage.upload(&c.h, ranks, sizeof(int) * n, &dr));
-  TLR_TRY(c.h.stage.upload(&c.h, rows, sizeof(int) * n, &dw));
-  TLR_TRY(c.h.ws.ints.ensure(c.h.mem, sizeof(int) * n));
-  TLR_HIP(launch_sort_ranks((const int*)dr, (const int*)dw, n, c.h.ws.ints.as<int>(), c.h.stream));
-  TLR_TRY(c.h.sync());
-  TLR_HIP(hipMemcpy(order, c.h.ws.ints.p, sizeof(int) * n, hipMemcpyDeviceToHost));
+  std::vector<int> idx(n);
+  sort_ranks(ranks, rows, n, idx.data());
+  for (int i = 0; i < n; ++i) order[i] = rows[idx[i]];
   return TLR_OK;
 }
 

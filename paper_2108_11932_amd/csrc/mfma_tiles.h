@@ -132,23 +132,76 @@ __device__ inline void tn_tile(const double* __restrict__ A, int lda, const doub
   }
 }
 
+// Packed low-precision copies of a row panel (the FP32 and BF16 mirrors of
+// the factor's U panels, precision P = 1 and 2): the columns are cut into
+// slices of Pack<P>::K columns; a slice holds the panel's row blocks of 16
+// rows one after another, each stored as 64 lanes x Pack<P>::V values, lane
+// i + 16 g holding row i and columns g V .. g V + V - 1 of the slice.  That is
+// the MFMA operand of one wave: one contiguous 16-byte load per lane, 1 KiB
+// per wave.  FP32: K = 16, V = 4 (four v_mfma_f32_16x16x4f32 per slice);
+// BF16: K = 32, V = 8 (one v_mfma_f32_16x16x32_bf16).  A panel of m rows has
+// ceil(m / 16) row blocks.
+template <int P>
+struct Pack;
+template <>
+struct Pack<1> {
+  static constexpr int K = 16, V = 4;
+};
+template <>
+struct Pack<2> {
+  static constexpr int K = 32, V = 8;
+};
+__host__ __device__ inline size_t pack_index(int row, int col, int nrb, int pk, int pv) {
+  return ((size_t)(col / pk) * nrb + (row >> 4)) * (size_t)(64 * pv) +
+         (size_t)(((row & 15) + 16 * ((col % pk) / pv)) * pv + col % pv);
+}
+// BF16 bits of x: rounded to FP32, then to the nearest BF16, ties to even
+// (finite values).
+__device__ inline unsigned short bf16_bits(double x) {
+  unsigned u = __float_as_uint((float)x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(1))) u4v gu4v;
+// Row of the 16 x 16 block held by accumulator register r of lane l of the
+// FP32-accumulating MFMAs (v_mfma_f32_16x16x4f32, v_mfma_f32_16x16x32_bf16;
+// column l % 16), and its inverse: the register and lane group of a row.
+__device__ inline int f32acc_row(int l, int r) { return 4 * (l >> 4) + r; }
+__device__ inline void f32acc_slot(int row, int* r, int* grp) {
+  *r = row & 3;
+  *grp = row >> 2;
+}
+
 // Streaming product of a strip of 16 FM rows (256 threads, 4 waves):
 //   C(r0 : r0 + 16 FM, 0 : N) = beta C + A0 B0 + A1 B1,
-// A_s m x K_s column-major (A1 read as float when A1F32), B_s K_s x N,
-// N <= 16 NF.  The waves take interleaved 16-wide slices of the K range of
-// both segments, U slices per pass with all loads in flight; lane (i, g)
-// reads rows i + 16 f of A for the four columns k0 + 4 g + t (128-byte runs
-// per column over the 16 lanes of a group, FM of them one after another down
-// the column) and rows k0 + 4 g + t of column i of B, which serve all FM row
-// blocks; MFMA t consumes k0 + 4 g + t on both operands.  The four partial
-// strips are added in LDS (red, 4 x FM NF 4 x 64) in a fixed order.  When ys
-// is not NULL the final strip is also left in ys[row - r0][col] (after a
-// barrier).
-template <int NF, bool A1F32, int FM = 1>
+// A_s m x K_s, B_s K_s x N (column-major FP64), N <= 16 NF.  P1 selects how
+// segment 1 is formed: 0, A1 column-major FP64 (ld lda1) on the FP64 matrix
+// cores; 1 or 2, A1 packed FP32 or BF16 (lda1 = its number of row blocks),
+// B1 rounded to the same precision, products accumulated in FP32 on the FP32
+// or BF16 matrix cores, and added to the FP64 result of segment 0 at the end.
+//
+// FP64 segments: the waves take interleaved 16-wide slices of the K range, U
+// slices per pass with all loads in flight; lane (i, g) reads rows i + 16 f of
+// A for the four columns k0 + 4 g + t (128-byte runs per column over the 16
+// lanes of a group, FM of them one after another down the column) and rows
+// k0 + 4 g + t of column i of B, which serve all FM row blocks; MFMA t
+// consumes k0 + 4 g + t on both operands.  Packed segment: the waves take
+// interleaved slices, lane (i, g) loads its 16 bytes of each row block and
+// the V rows of B that match them.  Either way every wave walks the same
+// sequence of slices whatever FM, so the accumulation order of an output does
+// not depend on the strip height.  The four partial strips are added in LDS
+// (red, and red32 for the FP32 accumulators; 4 x FM NF 4 x 64 each) in a
+// fixed order.  When ys is not NULL the final strip is also left in
+// ys[row - r0][col] (after a barrier).
+template <int NF, int P1, int FM = 1>
 __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, int ldb0, int K0,
                                  const void* A1v, int lda1, const double* B1, int ldb1, int K1,
                                  double* C, int ldc, int M, int N, double beta, int r0,
-                                 double (*red)[FM * NF * 4][64], double (*ys)[16 * NF + 1]) {
+                                 double (*red)[FM * NF * 4][64], float (*red32)[FM * NF * 4][64],
+                                 double (*ys)[16 * NF + 1]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
   // rows r0 + 16 f + li (f < FM); rows past M read row 0 and are not stored
@@ -163,17 +216,13 @@ __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, i
   for (int f = 0; f < FM; ++f)
 #pragma unroll
     for (int b = 0; b < NF; ++b) acc[f][b] = d4{0.0, 0.0, 0.0, 0.0};
-  // 64-row K blocks per round of loads: every wave walks the same sequence
-  // of K blocks whatever FM, so the accumulation order of an output does
-  // not depend on the strip height
+  // 64-row K blocks per round of loads
   constexpr int U = FM == 1 ? 4 : 2;
 #pragma unroll
   for (int sg = 0; sg < 2; ++sg) {
     const int K = sg ? K1 : K0;
-    if (K <= 0) continue;
-    const bool f32 = A1F32 && sg == 1;
+    if (K <= 0 || (sg == 1 && P1 != 0)) continue;
     const gdouble* __restrict__ A = gmem(sg ? (const double*)A1v : A0);
-    const gfloat* __restrict__ Af = gmem((const float*)A1v);
     const gdouble* __restrict__ B = gmem(sg ? B1 : B0);
     const size_t lda = sg ? lda1 : lda0, ldb = sg ? ldb1 : ldb0;
     const gdouble* bcol[NF];
@@ -184,7 +233,6 @@ __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, i
     }
     for (int k0 = wave * 16; k0 < K; k0 += 64 * U) {
       double av[U][4][FM], bv[U][NF][4];
-      float af[U][4][FM];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int kr = k0 + 64 * u + 4 * g;
@@ -192,12 +240,7 @@ __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, i
         for (int t = 0; t < 4; ++t) {
           const int kk = min(kr + t, K - 1);
 #pragma unroll
-          for (int f = 0; f < FM; ++f) {
-            if (f32)
-              af[u][t][f] = Af[rowc[f] + (size_t)kk * lda];
-            else
-              av[u][t][f] = A[rowc[f] + (size_t)kk * lda];
-          }
+          for (int f = 0; f < FM; ++f) av[u][t][f] = A[rowc[f] + (size_t)kk * lda];
 #pragma unroll
           for (int b = 0; b < NF; ++b) bv[u][b][t] = bcol[b][kk];
         }
@@ -212,10 +255,8 @@ __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, i
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-          for (int f = 0; f < FM; ++f) {
-            if (f32) av[u][t][f] = (double)af[u][t][f];
+          for (int f = 0; f < FM; ++f)
             if (k0 + 64 * u + 4 * g + t >= K) av[u][t][f] = 0.0;
-          }
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -228,19 +269,113 @@ __device__ inline void seg_strip(const double* A0, int lda0, const double* B0, i
                   __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][t][f], bv[u][b][t], acc[f][b], 0, 0, 0);
     }
   }
+  f4v acc32[FM][NF];
+#pragma unroll
+  for (int f = 0; f < FM; ++f)
+#pragma unroll
+    for (int b = 0; b < NF; ++b) acc32[f][b] = f4v{0.f, 0.f, 0.f, 0.f};
+  if constexpr (P1 != 0) {
+    constexpr int PK = Pack<P1 == 0 ? 1 : P1>::K, PV = Pack<P1 == 0 ? 1 : P1>::V;
+    constexpr int U1 = FM == 1 ? 4 : 2;
+    const int nrb = lda1;
+    const int nsl = (K1 + PK - 1) / PK;
+    // the elements of a packed operand are 4 (FP32) or 2 (BF16) bytes: one
+    // 16-byte run per lane and row block
+    const char* base = (const char*)A1v;
+    constexpr size_t blk_bytes = 64 * 16;   // 64 lanes x 16 bytes
+    int rb[FM];
+#pragma unroll
+    for (int f = 0; f < FM; ++f) rb[f] = min((r0 >> 4) + f, nrb - 1);
+    const gdouble* bcol[NF];
+#pragma unroll
+    for (int b = 0; b < NF; ++b) {
+      const int c = b * 16 + li;
+      bcol[b] = gmem(B1) + (size_t)(c < N ? c : 0) * ldb1;
+    }
+    for (int s0 = wave; s0 < nsl; s0 += 4 * U1) {
+      u4v araw[U1][FM];
+      double bv[U1][NF][PV];
+#pragma unroll
+      for (int u = 0; u < U1; ++u) {
+        const int s = min(s0 + 4 * u, nsl - 1);
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+          araw[u][f] = *(const gu4v*)(base + ((size_t)s * nrb + rb[f]) * blk_bytes + (size_t)lane * 16);
+#pragma unroll
+        for (int v = 0; v < PV; ++v) {
+          const int kk = min(s * PK + g * PV + v, K1 - 1);
+#pragma unroll
+          for (int b = 0; b < NF; ++b) bv[u][b][v] = bcol[b][kk];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U1; ++u) {
+        const int kb = (s0 + 4 * u) * PK + g * PV;   // first column of this lane's run
+        if constexpr (P1 == 1) {
+          // columns past K1 (the tail of the last slice, or a repeated
+          // slice past the end) are zeroed on the A side
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int f = 0; f < FM; ++f) {
+              const float a = kb + t < K1 ? __uint_as_float(araw[u][f][t]) : 0.f;
+#pragma unroll
+              for (int b = 0; b < NF; ++b)
+                acc32[f][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, (float)bv[u][b][t],
+                                                                   acc32[f][b], 0, 0, 0);
+            }
+        } else {
+          u4v bw[NF];
+#pragma unroll
+          for (int b = 0; b < NF; ++b)
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+              bw[b][w] = (unsigned)bf16_bits(bv[u][b][2 * w]) |
+                         ((unsigned)bf16_bits(bv[u][b][2 * w + 1]) << 16);
+#pragma unroll
+          for (int f = 0; f < FM; ++f) {
+            u4v a = araw[u][f];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+              const unsigned lo = kb + 2 * w < K1 ? 0x0000ffffu : 0u;
+              const unsigned hi = kb + 2 * w + 1 < K1 ? 0xffff0000u : 0u;
+              a[w] &= lo | hi;
+            }
+            const bf8v ab = __builtin_bit_cast(bf8v, a);
+#pragma unroll
+            for (int b = 0; b < NF; ++b)
+              acc32[f][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  ab, __builtin_bit_cast(bf8v, bw[b]), acc32[f][b], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
 #pragma unroll
   for (int f = 0; f < FM; ++f)
 #pragma unroll
     for (int b = 0; b < NF; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) red[wave][(f * NF + b) * 4 + r][lane] = acc[f][b][r];
+      for (int r = 0; r < 4; ++r) {
+        red[wave][(f * NF + b) * 4 + r][lane] = acc[f][b][r];
+        if (P1 != 0) red32[wave][(f * NF + b) * 4 + r][lane] = acc32[f][b][r];
+      }
   __syncthreads();
   for (int e = threadIdx.x; e < FM * NF * 4 * 64; e += 256) {
     const int slot = e >> 6, l = e & 63;
     const int f = slot / (NF * 4), b = (slot >> 2) % NF, r = slot & 3;
-    const int rr = 16 * f + (l >> 4) + 4 * r;
+    const int rl = (l >> 4) + 4 * r;   // row inside the 16 x 16 block
+    const int rr = 16 * f + rl;
     const int c = b * 16 + (l & 15);
     double v = ((red[0][slot][l] + red[1][slot][l]) + red[2][slot][l]) + red[3][slot][l];
+    if (P1 != 0) {
+      int r32, grp;
+      f32acc_slot(rl, &r32, &grp);
+      const int s32 = (f * NF + b) * 4 + r32, l32 = 16 * grp + (l & 15);
+      v += (((double)red32[0][s32][l32] + (double)red32[1][s32][l32]) +
+            (double)red32[2][s32][l32]) + (double)red32[3][s32][l32];
+    }
     if (r0 + rr < M && c < N) {
       gdouble* cp = gmem(C) + (r0 + rr) + (size_t)c * ldc;
       if (beta != 0.0) v += beta * *cp;

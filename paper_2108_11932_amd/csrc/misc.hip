@@ -4,6 +4,7 @@
 // (Section 5.1), row scaling by a diagonal (the D factors of LDL^T,
 // Section 5.3), zeroing of a strict triangle, and the covariance tile
 // generator of the Section 6 test matrices.
+#include "mfma_tiles.h"
 #include "tlr_internal.h"
 
 namespace tlr {
@@ -11,16 +12,19 @@ namespace tlr {
 namespace {
 
 // One workgroup per (descriptor, 8-column slab); each thread copies rows.
+// The packed FP32 / BF16 copies take the layout of pack_index.
 __global__ __launch_bounds__(256) void k_copy_batched(const CopyDesc* __restrict__ descs) {
   const CopyDesc d = descs[blockIdx.y];
   const int c0 = blockIdx.x * 8;
   if (c0 >= d.cols) return;
   const int c1 = min(d.cols, c0 + 8);
+  const int nrb = (d.rows + 15) / 16;
   for (int c = c0; c < c1; ++c)
     for (int r = threadIdx.x; r < d.rows; r += blockDim.x) {
       const double v = d.src[r + (size_t)c * d.lds];
       d.dst[r + (size_t)c * d.ldd] = v;
-      if (d.dst32) d.dst32[r + (size_t)c * d.ldd32] = (float)v;
+      if (d.dst32) d.dst32[pack_index(r, d.pcol + c, nrb, Pack<1>::K, Pack<1>::V)] = (float)v;
+      if (d.dst16) d.dst16[pack_index(r, d.pcol + c, nrb, Pack<2>::K, Pack<2>::V)] = bf16_bits(v);
     }
 }
 
@@ -71,6 +75,13 @@ __global__ void k_scale_panel(const double* __restrict__ V, int ldv, double* __r
   if (e >= (long long)m * ncols) return;
   const int r = (int)(e % m), c = (int)(e / m);
   W[r + (size_t)c * ldw] = V[r + (size_t)c * ldv] * Dv[(size_t)colj[c] * m + r];
+}
+
+// p[0 .. n) = v (a fill kernel rather than a memset, so the stream holds
+// only kernel launches)
+__global__ void k_fill(double* p, long long n, double v) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
 }
 
 __global__ void k_zero_upper(double* A, int lda, int m) {
@@ -179,6 +190,12 @@ hipError_t launch_scale_panel(const double* V, int ldv, double* W, int ldw, int 
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scale_panel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, V, ldv, W,
                      ldw, m, ncols, colj, Dv);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, long long n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@ namespace tlr {
 // or back.
 static tlr_status pad_in(Handle* h, const double* X, long long ldx, int nrhs, double* Xp) {
   const long long np = (long long)h->nb * h->m;
-  TLR_HIP(hipMemsetAsync(Xp, 0, sizeof(double) * np * nrhs, h->stream));
+  TLR_HIP(launch_fill(Xp, np * nrhs, 0.0, h->stream));
   CopyDesc cd{X, Xp, (int)h->N, nrhs, (int)ldx, (int)np};
   void* d = nullptr;
   TLR_TRY(h->stage.upload(h, &cd, sizeof cd, &d));
@@ -138,25 +138,37 @@ tlr_status estimate_norm(Handle* h, double* out) {
   return st;
 }
 
-tlr_status solve(Handle* h, int nrhs, double* B, long long ldb) {
-  const int m = h->m, nb = h->nb;
-  const long long np = (long long)nb * m;
-  const bool ldl = h->factored == 2;
-  Work& w = h->ws;
-  long long rmax = 0;
-  for (int k = 0; k < nb; ++k) rmax = std::max<long long>(rmax, h->R[k]);
+// Rows of the per-column products V^T x (forward sweep, the tiles of one
+// column) and U^T x (backward sweep, one block row's panel).
+static long long solve_tcap(const Handle* h) {
+  const int nb = h->nb;
   long long tcap = 0;
   for (int k = 0; k < nb; ++k) {
     long long s = 0;
     for (int i = k + 1; i < nb; ++i) s += h->lr(i, k);
-    tcap = std::max(tcap, s);
+    tcap = std::max(tcap, std::max(s, (long long)h->R[k]));
   }
-  tcap = std::max(tcap, rmax);
-  TLR_TRY(w.omega.ensure(h->mem, sizeof(double) * (np + m) * nrhs));
-  TLR_TRY(w.T.ensure(h->mem, sizeof(double) * (size_t)std::max(tcap, 1LL) * nrhs));
-  double* Xp = w.omega.as<double>();
-  double* tk = Xp + np * nrhs;   // m x nrhs
-  double* T = w.T.as<double>();
+  return std::max(tcap, 1LL);
+}
+
+size_t solve_workspace(const Handle* h, int nrhs) {
+  const long long np = (long long)h->nb * h->m;
+  return (size_t)(np + h->m + solve_tcap(h)) * (size_t)std::max(nrhs, 0);
+}
+
+tlr_status solve(Handle* h, int nrhs, double* B, long long ldb) {
+  TLR_TRY(h->ws.omega.ensure(h->mem, sizeof(double) * std::max<size_t>(solve_workspace(h, nrhs), 1)));
+  return solve_in(h, nrhs, B, ldb, h->ws.omega.as<double>());
+}
+
+tlr_status solve_in(Handle* h, int nrhs, double* B, long long ldb, double* work) {
+  const int m = h->m, nb = h->nb;
+  const long long np = (long long)nb * m;
+  const bool ldl = h->factored == 2;
+  const long long tcap = solve_tcap(h);
+  double* Xp = work;                    // padded N x nrhs
+  double* tk = Xp + np * nrhs;          // m x nrhs
+  double* T = tk + (size_t)m * nrhs;    // tcap x nrhs
   const int ldx = (int)np;
   TLR_TRY(pad_in(h, B, ldb, nrhs, Xp));
   auto apply_inv = [&](int k, bool trans) -> tlr_status {

@@ -97,6 +97,10 @@ tlr_status Staging::upload(Handle* h, const void* data, size_t bytes, void** dpt
   if (used + need > cap) {
     TLR_TRY(h->sync());
     if (need > cap) {
+      if (fixed) {
+        set_error("%zu bytes of launch descriptors exceed the %zu-byte staging ring", need, cap);
+        return TLR_ERR_ARG;
+      }
       Mem& mem = h->mem;
       release(mem);
       TLR_TRY(init(mem, need * 2));
@@ -117,6 +121,10 @@ tlr_status Staging::upload_to(Handle* h, const void* data, size_t bytes, void* d
   if (used + need > cap) {
     TLR_TRY(h->sync());
     if (need > cap) {
+      if (fixed) {
+        set_error("%zu bytes of launch descriptors exceed the %zu-byte staging ring", need, cap);
+        return TLR_ERR_ARG;
+      }
       Mem& mem = h->mem;
       release(mem);
       TLR_TRY(init(mem, need * 2));
@@ -234,6 +242,8 @@ tlr_status tlr_matrix_s::readback_results(size_t n, int** p) {
 }
 
 void tlr_matrix_s::release_host() {
+  pt_main.destroy();
+  pt_side.destroy();
   if (pin_norm) (void)hipHostFree(pin_norm);
   if (pin_ring) (void)hipHostFree(pin_ring);
   if (pin_res) (void)hipHostFree(pin_res);
@@ -266,6 +276,48 @@ tlr_status tlr_matrix_s::pinned_norms(size_t n, double** p) {
 
 namespace tlr {
 
+// ---------------------------------------------------------------- sortRanks
+void sort_ranks(const int* ranks, const int* rows, int n, int* idx) {
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx, idx + n, [&](int a, int b) {
+    if (ranks[a] != ranks[b]) return ranks[a] > ranks[b];
+    if (rows[a] != rows[b]) return rows[a] < rows[b];
+    return a < b;
+  });
+}
+
+// ---------------------------------------------------------------- phase timing
+hipError_t PhaseTimer::mark(int phase, hipStream_t s) {
+  if (!on) return hipSuccess;
+  if (n == ev.size()) {
+    hipEvent_t e = nullptr;
+    const hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    ev.push_back(e);
+  }
+  ph.push_back(phase);
+  return hipEventRecord(ev[n++], s);
+}
+
+tlr_status PhaseTimer::collect(double* t) {
+  for (size_t i = 0; i + 1 < n; ++i) {
+    if (ph[i] < 0 || ph[i] >= TLR_NPHASE) continue;
+    float ms = 0.f;
+    TLR_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+    t[ph[i]] += ms;
+  }
+  n = 0;
+  ph.clear();
+  return TLR_OK;
+}
+
+void PhaseTimer::destroy() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  ev.clear();
+  ph.clear();
+  n = 0;
+}
+
 // ---------------------------------------------------------------- GEMM batch
 tlr_status GemmBatch::run(Handle* h, hipStream_t s) {
   Plan p(h, s);
@@ -273,11 +325,6 @@ tlr_status GemmBatch::run(Handle* h, hipStream_t s) {
   return p.run();
 }
 
-tlr_status SegBatch::run(Handle* h, hipStream_t s) {
-  Plan p(h, s);
-  p.seg(*this);
-  return p.run();
-}
 
 // ---------------------------------------------------------------- plans
 Plan::Plan(Handle* h_, hipStream_t s_) : h(h_), s(s_ ? s_ : h_->stream) {}
@@ -436,26 +483,6 @@ void Plan::gemm(const GemmBatch& b) {
       push(large, TM, bn, false, bn);
     }
   }
-  flops += b.flops;
-}
-
-void Plan::seg(const SegBatch& b) {
-  if (b.d.empty()) return;
-  int maxn = 0;
-  std::vector<BlockMap> map;
-  for (size_t i = 0; i < b.d.size(); ++i) {
-    maxn = b.d[i].N > maxn ? b.d[i].N : maxn;
-    for (int t = 0; t < (b.d[i].M + 15) / 16; ++t) map.push_back(BlockMap{(int)i, t});
-  }
-  const size_t od = stage(b.d.data(), b.d.size() * sizeof(SegDesc));
-  const size_t om = stage(map.data(), map.size() * sizeof(BlockMap));
-  const int nblk = (int)map.size();
-  const bool f32 = b.a1_f32;
-  hipStream_t st = s;
-  steps.push_back([=](const char* base) {
-    return launch_sample_nn((const SegDesc*)(base + od), (const BlockMap*)(base + om), nblk, maxn,
-                            f32, st);
-  });
   flops += b.flops;
 }
 

@@ -66,20 +66,6 @@ hipError_t launch_splitk_sum(double* C, int ldc, int M, int N, const double* par
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, int nblocks,
                                bool trans_a, bool trans_b, int bn, int max_k, hipStream_t s);
 
-// Two-segment product with a narrow right-hand side (N <= 32):
-// C = beta C + A[0] B[0] + A[1] B[1]; a segment with K = 0 is skipped.
-// The block map enumerates 16-row blocks of C (tile = row block).
-struct SegDesc {
-  const void* A[2];   // double, or float for segment 1 of an FP32-panel batch
-  const double* B[2];
-  int lda[2], ldb[2], K[2];
-  double* C;
-  int ldc, M, N;
-  double beta;
-};
-hipError_t launch_sample_nn(const SegDesc* d, const BlockMap* map, int nblocks, int maxn,
-                            bool a1_f32, hipStream_t s);
-
 // ---------------------------------------------------------------------------
 // Dense tile kernels (one m x m tile, m <= 4096)
 // ---------------------------------------------------------------------------
@@ -139,9 +125,12 @@ struct AraSlotDesc {
   // sample Y = A0 B0 + A1 B1 (m x bs)
   const double* a0;       // m x k0 (ld lda0): U^A_ik, or the explicit tile
   const double* b0;       // k0 x bs (ld ldb0): W^A below, or Omega
-  const void* a1;         // m x k1 (ld lda1): the row panel U_i*, double or float
+  const void* a1;         // m x k1: the row panel U_i*, FP64 column-major (ld
+                          // lda1), or its packed FP32 / BF16 copy (lda1 = row
+                          // blocks of the packing), as a1_prec says
   const double* b1;       // k1 x bs (ld ldb1): Z below
-  int lda0, ldb0, k0, lda1, ldb1, k1, a1_f32;
+  int lda0, ldb0, k0, lda1, ldb1, k1;
+  int a1_prec;            // 0 FP64, 1 packed FP32, 2 packed BF16 (FP32 accumulation)
   // W^A = V^A_ik^T Omega (a x bs, ld a), when a > 0
   const double* va;
   double* wa;
@@ -185,19 +174,24 @@ struct AraDev {
   int* ncol;    // samples drawn per slot
   int m, bs, qcap, nstrip;
 };
-// Precision choice of one slot under mixed precision: the slot samples with
-// the FP32 copy a1_32 of its panel when u32 (nu + fro[irow] fro[0]) <= thr
-// (no device term when irow < 0); fro holds the Frobenius norms of the
-// previous column's factor tiles (row k - 1 + 1 + s at s) on the device.
+// Precision choice of one slot under mixed precision.  With
+// nu_tot = nu + fro[irow] fro[0] (no device term when irow < 0; fro holds the
+// Frobenius norms of the previous column's factor tiles, row k - 1 + 1 + s
+// at s, on the device) the slot samples its panel from the packed BF16 copy
+// a1_16 when nu_tot <= lim16, else from the packed FP32 copy a1_32 when
+// nu_tot <= lim32, else in FP64 (a NULL copy is never chosen).  nrb: row
+// blocks of the packing.
 struct GuardDesc {
   const void* a1_32;
+  const void* a1_16;
   const double* fro;
-  double nu, thr;
-  int irow, pad;
+  double nu, lim32, lim16;
+  int irow, nrb;
 };
-// Applies the choice to the n slot descriptors (panel pointer and FP32
-// flag) and stores it in f32[slot] (1 = FP32 panel).
-hipError_t launch_mixed_guard(AraSlotDesc* slots, const GuardDesc* g, int n, int* f32,
+// Applies the choice to the n slot descriptors (panel pointer, leading
+// dimension and precision) and stores it in prec[slot] (0 FP64, 1 FP32,
+// 2 BF16).
+hipError_t launch_mixed_guard(AraSlotDesc* slots, const GuardDesc* g, int n, int* prec,
                               hipStream_t s);
 // Block sizes the orthogonalisation kernels are built for (1, 2, 4, 8, 16,
 // 24, 32).
@@ -218,9 +212,11 @@ hipError_t launch_ara_z(const AraDev& D, const ZSeg* segs, const double* P, int 
                         int count_bound, int bps, hipStream_t s);
 // mode 0: sample Y; mode 1: Y += Q C; mode 2: X += Q C; all write the Gram
 // partials of their output (part1 for modes 0/1, part2 for mode 2).
-// With start/stop events (mode 0 only) the events record the launch's own
-// begin and end.
-hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_t s,
+// Mode 0 computes 64-row strips per workgroup when strip is 64, or when it
+// is 0 and the launch has enough of them to fill the GPU, else 16-row strips
+// (same result bit for bit).  With start/stop events (mode 0 only) the
+// events record the launch's own begin and end.
+hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_t s, int strip = 0,
                           hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // Cholesky QR step of pass 1 (pivoted, thresholded: appends the accepted
 // directions of Y to Q, sets qnew, flag, pivots, iteration counters and the
@@ -244,8 +240,6 @@ hipError_t launch_ara_compact(const AraDev& D, const int* waiting, int nwaiting,
 // read back together with the active list).
 hipError_t launch_compact(int* act, int* counts, const int* flag, const int* waiting, int nwaiting,
                           int s_max, const int* info, hipStream_t s);
-// Rank sort of a column: order rows by rank descending, ties ascending row.
-hipError_t launch_sort_ranks(const int* ranks, const int* rows, int n, int* order, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Misc kernels
@@ -254,8 +248,11 @@ struct CopyDesc {
   const double* src;
   double* dst;
   int rows, cols, lds, ldd;
-  float* dst32 = nullptr;   // optional FP32 copy of the destination
-  int ldd32 = 0;
+  // optional packed FP32 / BF16 copies of the destination (the layout of
+  // pack_index, ceil(rows / 16) row blocks), written at columns pcol ..
+  float* dst32 = nullptr;
+  unsigned short* dst16 = nullptr;
+  int pcol = 0;
 };
 // Frobenius norm of a rows x cols block (ld) into *out.
 struct NormDesc {

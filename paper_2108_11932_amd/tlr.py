@@ -24,8 +24,9 @@ TLR_ERR_STATE = -4
 TLR_ERR_NOT_SPD = 1
 TLR_ERR_ZERO_PIVOT = 2
 EPS_ABS, EPS_REL = 0, 1
-FP64, MIXED_FP32 = 0, 1
-FLAG_KERNEL_TIMING = 1
+FP64, MIXED_FP32, MIXED_BF16, MIXED_AUTO = 0, 1, 2, 3
+FLAG_KERNEL_TIMING, FLAG_PHASE_TIMING = 1, 2
+PHASES = ("gblocks", "sample", "orth", "batch", "project", "trsm", "append", "diag")
 KERNEL_EXP, KERNEL_MATERN15 = 0, 1
 INPUT, FACTOR = 0, 1
 
@@ -43,7 +44,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("bs", ctypes.c_int), ("eps_mode", ctypes.c_int), ("precision", ctypes.c_int),
                 ("shift", ctypes.c_double), ("max_active", ctypes.c_int), ("r_min", ctypes.c_int),
                 ("seed", ctypes.c_ulonglong), ("flags", ctypes.c_int), ("bs_tail", ctypes.c_int),
-                ("tail_active", ctypes.c_int)]
+                ("tail_active", ctypes.c_int), ("auto_shift", ctypes.c_int),
+                ("sample_strip", ctypes.c_int), ("conv_factor", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -54,10 +56,15 @@ class Stats(ctypes.Structure):
                 ("max_rank", ctypes.c_int), ("mean_rank", ctypes.c_double),
                 ("factor_bytes", ctypes.c_double), ("sample_launches", ctypes.c_longlong),
                 ("sample_ms", ctypes.c_double), ("sample_bytes", ctypes.c_double),
-                ("sample_flops", ctypes.c_double), ("fp32_tile_iters", ctypes.c_longlong)]
+                ("sample_flops", ctypes.c_double), ("fp32_tile_iters", ctypes.c_longlong),
+                ("shift", ctypes.c_double), ("shift_retries", ctypes.c_int),
+                ("t_total", ctypes.c_double), ("t_phase", ctypes.c_double * 8),
+                ("bf16_tile_iters", ctypes.c_longlong)]
 
     def as_dict(self) -> Dict[str, float]:
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        out = {f: getattr(self, f) for f, _ in self._fields_}
+        out["t_phase"] = list(self.t_phase)
+        return out
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -101,6 +108,10 @@ SIGNATURES = {
     "tlr_ldlt": (_I, [_P, _D, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P]),
     "tlr_factor_batched": (_I, [_I, ctypes.POINTER(_P), _I, _D, ctypes.POINTER(Opts),
                                 ctypes.POINTER(_P), ctypes.POINTER(Stats), _P]),
+    "tlr_potrf_batched": (_I, [_I, ctypes.POINTER(_P), _DP, ctypes.POINTER(Opts),
+                               ctypes.POINTER(Stats), _P]),
+    "tlr_ldlt_batched": (_I, [_I, ctypes.POINTER(_P), _DP, ctypes.POINTER(Opts),
+                              ctypes.POINTER(_P), ctypes.POINTER(Stats), _P]),
     "tlr_solve": (_I, [_P, _I, _P, _LL, _P]),
     "tlr_matvec": (_I, [_P, _I, _P, _LL, _P, _LL, _P]),
     "tlr_get_info": (_I, [_P, _LLP, _IP, _IP, _IP]),
@@ -109,6 +120,7 @@ SIGNATURES = {
     "tlr_get_tile": (_I, [_P, _I, _I, _I, _DP, _DP, _I]),
     "tlr_get_diag": (_I, [_P, _I, _I, _DP, _I]),
     "tlr_get_pivots": (_I, [_P, _DP]),
+    "tlr_get_sort_order": (_I, [_P, _I, _IP]),
     "tlr_destroy": (_I, [_P]),
     "tlr_last_error": (ctypes.c_char_p, []),
     "tlrk_gemm_batched": (_I, [_I, _I, _I, ctypes.POINTER(GemmProblem), _P]),
@@ -117,6 +129,7 @@ SIGNATURES = {
     "tlrk_trsm": (_I, [_I, _I, _P, _I, _P, _I, _I, _I, _P]),
     "tlrk_philox": (_I, [_I, _ULL, _U, _U, _U, _P, _P]),
     "tlrk_randn": (_I, [_I, _I, _ULL, _U, _U, _U, _P, _P]),
+    "tlrk_randn_iters": (_I, [_I, _I, _I, _ULL, _U, _U, _I, _U, _P, _P]),
     "tlrk_ara": (_I, [_I, _I, _P, _D, _I, _I, _ULL, _P, _P, _IP, _IP, _P]),
     "tlrk_sort_ranks": (_I, [_I, _IP, _IP, _IP]),
     "tlrk_compact": (_I, [_I, _IP, _IP, _IP, _IP, _I, _IP, _I]),
@@ -379,6 +392,13 @@ class TLRMatrix:
         _check(lib().tlr_get_pivots(self.h, d.ctypes.data_as(_DP)))
         return d
 
+    def sort_order(self, k: int) -> list:
+        """Block rows of column k in the sortRanks order of the last factorization."""
+        n = self.nb - k - 1
+        r = np.zeros(max(n, 1), dtype=np.int32)
+        _check(lib().tlr_get_sort_order(self.h, k, r.ctypes.data_as(_IP)))
+        return r[:n].tolist()
+
     def to_host(self, which: int = FACTOR):
         """(diag list, U dict, V dict) of the input or the factor, host numpy."""
         ranks = self.ranks(which)
@@ -416,6 +436,25 @@ def factor_batched(mats, eps: float, o: Optional[Opts] = None, ldl: bool = False
     s = lib().tlr_factor_batched(n, hs, int(ldl), eps, ctypes.byref(o or opts()), darr, sts,
                                  _stream())
     return s, [st.as_dict() for st in sts], dl
+
+
+def factor_batched_eps(mats, eps, o: Optional[Opts] = None, ldl: bool = False):
+    """tlr_potrf_batched / tlr_ldlt_batched with one threshold per matrix:
+    returns (status, list of stats dicts, list of pivot tensors or None)."""
+    torch = _torch()
+    n = len(mats)
+    hs = (_P * n)(*[mt.h for mt in mats])
+    ev = np.ascontiguousarray(eps, dtype=np.float64)
+    sts = (Stats * n)()
+    if ldl:
+        dl = [torch.empty(mt.n, dtype=torch.float64, device="cuda") for mt in mats]
+        darr = (_P * n)(*[ctypes.c_void_p(d.data_ptr()) for d in dl])
+        s = lib().tlr_ldlt_batched(n, hs, ev.ctypes.data_as(_DP), ctypes.byref(o or opts()), darr,
+                                   sts, _stream())
+        return s, [st.as_dict() for st in sts], dl
+    s = lib().tlr_potrf_batched(n, hs, ev.ctypes.data_as(_DP), ctypes.byref(o or opts()), sts,
+                                _stream())
+    return s, [st.as_dict() for st in sts], None
 
 
 def _to_colmajor(b):
@@ -475,6 +514,20 @@ def randn(rows: int, cols: int, seed: int, k: int, t: int, s: int):
     out = torch.empty(rows * cols, dtype=torch.float64, device="cuda")
     _check(lib().tlrk_randn(rows, cols, seed, k, t, s, _ptr(out), _stream()))
     return out.cpu().numpy().reshape(cols, rows).T
+
+
+def randn_iters(rows: int, cols0: int, cols1: int, seed: int, k: int, t0: int, nt: int, s: int):
+    """Test matrices of nt consecutive iterations: list of rows x cols numpy arrays."""
+    torch = _torch()
+    cm = max(cols0, cols1)
+    out = torch.empty(max(1, nt * rows * cm), dtype=torch.float64, device="cuda")
+    _check(lib().tlrk_randn_iters(rows, cols0, cols1, seed, k, t0, nt, s, _ptr(out), _stream()))
+    h = out.cpu().numpy()
+    res = []
+    for i in range(nt):
+        c = cols0 if t0 + i == 0 else cols1
+        res.append(h[i * rows * cm:i * rows * cm + rows * c].reshape(c, rows).T)
+    return res
 
 
 def ara(tiles, tau: float, bs: int = 16, r_min: int = 1, seed: int = 1):

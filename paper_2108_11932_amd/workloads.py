@@ -1,8 +1,10 @@
 """Seeded synthetic inputs shared by the GPU path, the tests and the oracle.
 
-This module only draws points and names workload parameters.  It holds none
-of the factorization arithmetic: no kernel evaluation, compression or
-factorization happens here.
+This module draws points and names workload parameters.  It holds none of
+the factorization arithmetic: no compression or factorization happens here.
+The one kernel evaluation is input-side: matern3d_norm_estimate sums rows
+of the unshifted Matern matrix to size the diagonal shift that makes the 3D
+workload indefinite.
 
 The paper's covariance test matrices (Section 6) come from spatial Gaussian
 processes with an isotropic exponential kernel, correlation length 0.1 in 2D

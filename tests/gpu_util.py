@@ -26,3 +26,39 @@ def oracle_tlr(mat, which):
     t.u = {k: np.array(x) for k, x in u.items()}
     t.v = {k: np.array(x) for k, x in v.items()}
     return t
+
+
+def tile_errors(a, l, d=None):
+    """2-norms of the tiles of A - L L^T (or A - L D L^T) for the TLR input a
+    and the factor l (oracle.tlr.TLR objects), computed tile by tile from the
+    low rank factors (no dense N x N expansion).
+
+    Returns (off, diag): off[(i, k)] for i > k, diag[k] for the diagonal tiles.
+    By the left-looking identity, off[(i, k)] is the compression error of the
+    Schur-complement tile S_ik."""
+    nb, m = a.nb, a.m
+    dv = [np.asarray(x) for x in d] if d is not None else None
+
+    def lfull(i, j):
+        # L_ij as (left, right) with L_ij = left @ right.T
+        if i == j:
+            return np.tril(l.diag[i]), np.eye(m)
+        return l.u[i, j], l.v[i, j]
+
+    off, diag = {}, {}
+    for k in range(nb):
+        for i in range(k, nb):
+            e = a.tile(i, k).copy()
+            for j in range(k + 1):
+                li, ri = lfull(i, j)
+                lk, rk = lfull(k, j)
+                if li.shape[1] == 0 or lk.shape[1] == 0:
+                    continue
+                mid = ri.T @ ((dv[j][:, None] * rk) if dv is not None else rk)
+                e -= li @ (mid @ lk.T)
+            nrm = float(np.linalg.norm(e, 2))
+            if i == k:
+                diag[k] = nrm
+            else:
+                off[i, k] = nrm
+    return off, diag

@@ -292,3 +292,43 @@ def test_mixed_guard_keeps_fp64_below_fp32_rounding():
         for i in range(k + 1, t.nb):
             np.testing.assert_array_equal(out[0][2].u[i, k], out[1][2].u[i, k])
             np.testing.assert_array_equal(out[0][2].v[i, k], out[1][2].v[i, k])
+
+
+def test_mixed_bf16_loose_threshold_with_shift():
+    # relative 1e-2 with the shift s = tau (the loose threshold loses
+    # definiteness without it): the tiles that pass the BF16 guard sample
+    # their panel term on the BF16 matrix cores (FP32 accumulation); the
+    # factor keeps the accuracy of the FP64 form against the unshifted matrix
+    w = wl.standard("cov2d_4k")
+    mat = tlr.TLRMatrix.compress_kernel(w.points, tlr.KERNEL_EXP, w.ell, w.diag_add, w.m, 1e-9)
+    a_t = oracle_tlr(mat, tlr.INPUT)
+    eps = 1e-2
+    res = {}
+    for prec in (tlr.FP64, tlr.MIXED_FP32, tlr.MIXED_BF16, tlr.MIXED_AUTO):
+        st = mat.potrf(eps, tlr.opts(eps_mode=tlr.EPS_REL, precision=prec, shift=-1.0))
+        res[prec] = (st, otlr.factor_error_norm(a_t, oracle_tlr(mat, tlr.FACTOR)))
+    tau = res[tlr.FP64][0]["tau"]
+    s16 = res[tlr.MIXED_BF16][0]
+    assert res[tlr.FP64][0]["bf16_tile_iters"] == 0 and res[tlr.FP64][0]["fp32_tile_iters"] == 0
+    assert res[tlr.MIXED_FP32][0]["bf16_tile_iters"] == 0
+    assert s16["bf16_tile_iters"] > 0
+    # the automatic form keeps BF16 copies at this threshold: the same run
+    sa = res[tlr.MIXED_AUTO][0]
+    assert (sa["bf16_tile_iters"], sa["fp32_tile_iters"], sa["ara_iters"]) == \
+        (s16["bf16_tile_iters"], s16["fp32_tile_iters"], s16["ara_iters"])
+    nb = a_t.nb
+    for prec in (tlr.MIXED_FP32, tlr.MIXED_BF16):
+        err = res[prec][1]
+        assert err <= 2 * math.sqrt(nb) * tau + tau, (prec, err, tau)
+        assert err <= 2 * res[tlr.FP64][1] + tau, (prec, err, res[tlr.FP64][1])
+
+
+def test_mixed_auto_uses_fp32_at_tight_threshold():
+    # relative 1e-6: the automatic form keeps no BF16 copies
+    pts, a = _cov(2048, 23)
+    t = otlr.compress_dense(a, 128, 1e-9)
+    mat = _upload(t)
+    st = mat.potrf(1e-6, tlr.opts(eps_mode=tlr.EPS_REL, precision=tlr.MIXED_AUTO))
+    assert st["bf16_tile_iters"] == 0 and st["fp32_tile_iters"] > 0
+    l = oracle_tlr(mat, tlr.FACTOR)
+    assert np.linalg.norm(_residual_tiles(t, l), 2) <= 2 * math.sqrt(t.nb) * st["tau"]

@@ -333,3 +333,80 @@ def test_active_set_evolution_hand_computed():
     assert sets == [[7, 3, 9, 1], [7, 1, 4, 8], [1, 4, 8], [8], []]
     # without a cap the subset only shrinks
     assert bk.active_sets([2, 5], 99, [[True, False], [True]]) == [[2, 5], [5], []]
+
+
+# ---------------------------------------------------------------- pivoted TLR Cholesky
+
+def test_pivoted_scalar_tiles_match_lapack_dpstrf():
+    # with 1 x 1 tiles the Frobenius-norm tile pivot is the largest remaining
+    # diagonal entry: the pivoted Cholesky of LAPACK's dpstrf
+    from scipy.linalg import lapack
+    rng = np.random.default_rng(17)
+    n = 12
+    g = rng.standard_normal((n, n))
+    a = g @ g.T + np.diag(rng.uniform(0.5, 3.0, n))
+    t = tlr.compress_dense(a, 1, 1e-14)
+    l, perm = tlr.tlr_cholesky_pivoted(t, 1e-14)
+    c, piv, rank, info = lapack.dpstrf(a, lower=1)
+    assert info == 0 and rank == n
+    assert perm == [int(p) - 1 for p in piv]
+    np.testing.assert_allclose(l.dense_lower(), np.tril(c), rtol=0, atol=1e-12 * np.abs(c).max())
+
+
+def _block(m, *rows):
+    """Symmetric block matrix from scalar multiples of the m x m identity."""
+    return np.block([[v * np.eye(m) for v in row] for row in rows])
+
+
+def test_pivoted_order_hand_computed():
+    m = 2
+    # diagonal scales 1, 3, 2 with weak coupling: the order of the scales
+    a = _block(m, (1.0, 0.01, 0.0), (0.01, 3.0, 0.01), (0.0, 0.01, 2.0))
+    _, perm = tlr.tlr_cholesky_pivoted(tlr.compress_dense(a, m, 1e-14), 1e-14)
+    assert perm == [1, 2, 0]
+    # block 2 (scale 2.2) is coupled to block 1 (scale 3) by 2 I: once block 1
+    # is eliminated, its update is 2.2 - 4 / 3 < 2, so block 0 comes next
+    a = _block(m, (2.0, 0.0, 0.0), (0.0, 3.0, 2.0), (0.0, 2.0, 2.2))
+    l, perm = tlr.tlr_cholesky_pivoted(tlr.compress_dense(a, m, 1e-14), 1e-14)
+    assert perm == [1, 0, 2]
+    np.testing.assert_allclose(np.diag(l.diag[2]), math.sqrt(2.2 - 4.0 / 3.0) * np.ones(m), rtol=1e-14)
+
+
+def test_pivoted_backward_error_identity_and_pivot_rule():
+    _, a = _cov(1024, 128, seed=23)
+    tau = 1e-6
+    t = tlr.compress_dense(a, 128, tau)
+    l, perm = tlr.tlr_cholesky_pivoted(t, tau)
+    assert sorted(perm) == list(range(t.nb))
+    tp = tlr.permute(t, perm)
+    e = tp.dense_symmetric() - l.dense_lower() @ l.dense_lower().T
+    for k in range(t.nb):
+        assert np.abs(e[t.blk(k), t.blk(k)]).max() < 1e-12 * np.abs(a).max()
+        for i in range(k + 1, t.nb):
+            # exact SVD truncation: the tile error is below tau
+            assert np.linalg.norm(e[t.blk(i), t.blk(k)], 2) <= tau * (1 + 1e-8)
+        # the pivot of step k has the largest updated diagonal norm
+        norms = []
+        for s in range(k, t.nb):
+            d = tp.diag[s].copy()
+            for j in range(k):
+                d -= l.u[s, j] @ ((l.v[s, j].T @ l.v[s, j]) @ l.u[s, j].T)
+            norms.append(np.linalg.norm(d, "fro"))
+        assert norms[0] >= max(norms) * (1 - 1e-12)
+
+
+def test_pivoted_exact_low_rank_kept():
+    n, m, r = 512, 64, 3
+    rng = np.random.default_rng(29)
+    a = np.zeros((n, n))
+    for k in range(0, n, m):
+        g = rng.standard_normal((m, m))
+        a[k:k + m, k:k + m] = g @ g.T / m + (1.0 + 0.5 * (k // m)) * np.eye(m)
+    w = rng.standard_normal((n, r))
+    a += w @ w.T
+    t = tlr.compress_dense(a, m, 1e-9)
+    l, perm = tlr.tlr_cholesky_pivoted(t, 1e-9)
+    assert perm != list(range(t.nb))
+    assert set(l.ranks()[np.tril_indices(t.nb, -1)].tolist()) == {r}
+    tp = tlr.permute(t, perm)
+    assert np.abs(tp.dense_symmetric() - l.dense_lower() @ l.dense_lower().T).max() < 1e-10 * np.abs(a).max()
