@@ -120,15 +120,19 @@ def residual(mat, torch, nvec: int = 4, seed: int = 7) -> float:
 
 
 def time_form(mat, w, eps_mode, precision, tlr, torch, steps, warmup, bs_tail=0, tail_active=0,
-              timing=True):
+              timing=True, idle_s=0.0):
     """Warm up, then time `steps` factorizations of one form (with the
-    sampling launches timed by their own events when `timing`)."""
+    sampling launches timed by their own events when `timing`); the GPU
+    idles idle_s seconds between the warm-up and the timed steps (a marker
+    for profile reductions)."""
     o = tlr.opts(bs=w.bs, bs_tail=bs_tail, tail_active=tail_active, eps_mode=eps_mode,
                  precision=precision,
                  flags=tlr.FLAG_KERNEL_TIMING if timing else 0)
     for _ in range(warmup):
         mat.potrf(w.eps, o)
     torch.cuda.synchronize()
+    if idle_s > 0:
+        time.sleep(idle_s)
     t0 = time.perf_counter()
     stats = [mat.potrf(w.eps, o) for _ in range(steps)]
     torch.cuda.synchronize()
@@ -155,17 +159,58 @@ def phase_split(mat, w, tlr, torch):
                     "on the second stream, overlapped"}
 
 
-def batched_form(tlr, torch, wl, count: int, m: int):
+def pivoted_form(tlr, torch, wl, steps: int):
+    """The 3D exponential covariance (N=131072, tile 512, eps 1e-6 absolute,
+    ARA block 32) factored unpivoted and with the Frobenius-norm tile
+    pivoting of Section 5.2: time, ranks and random-vector residual of
+    each."""
+    w = wl.standard("cov3d_131k")
+    mat = tlr.TLRMatrix.compress_kernel(w.points, w.kernel, w.ell, w.diag_add, w.m, w.eps,
+                                        tlr.opts(bs=w.bs))
+    o = tlr.opts(bs=w.bs)
+    out = {"workload": _describe(w), "N": w.n, "tile": w.m, "eps": w.eps, "bs": w.bs}
+    for name in ("unpivoted", "pivoted"):
+        run = (lambda: mat.potrf(w.eps, o)) if name == "unpivoted" else \
+            (lambda: mat.potrf_pivoted(w.eps, o)[0])
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [run() for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        rl = mat.ranks(tlr.FACTOR)[np.tril_indices(mat.nb, -1)]
+        out[name] = {"ms_per_step": dt * 1e3, "tflops": sts[-1]["flops"] / dt / 1e12,
+                     "residual": residual(mat, torch), "rank_mean": float(rl.mean()),
+                     "rank_max": int(rl.max()), "rank_total": int(rl.sum()),
+                     "ara_iterations": int(sts[-1]["ara_iters"])}
+    mat.close()
+    return out
+
+
+def batched_form(tlr, torch, wl, count: int, m_fixed: int):
     """The batched workload (count independent 2D problems of uneven N,
-    relative eps 1e-6): one tlr_factor_batched call over all of them (FP64
-    and FP32-sampling) against the same problems factored one by one."""
-    ws = wl.batched_2d(count=count, m=m)
-    mats = []
-    for w in ws:
-        mats.append(tlr.TLRMatrix.compress_kernel(w.points, w.kernel, w.ell, w.diag_add, w.m, w.eps,
-                                                  tlr.opts(bs=w.bs, eps_mode=w.eps_mode)))
+    relative eps 1e-6).  Tile sizes come from the library's autotuner
+    (tlr_tune_tile over 256 / 512 / 1024, one measurement per problem class
+    of ceil(log2 N)); the problems are then factored by one batched call
+    (FP64 and FP32-sampling) against the same problems factored one by one,
+    and against one batched call at the fixed tile size m_fixed."""
+    ws = wl.batched_2d(count=count, m=m_fixed)
+    o_c = tlr.opts(bs=ws[0].bs, eps_mode=tlr.EPS_REL)
     o64 = tlr.opts(bs=ws[0].bs, eps_mode=tlr.EPS_REL, precision=tlr.FP64)
     o32 = tlr.opts(bs=ws[0].bs, eps_mode=tlr.EPS_REL, precision=tlr.MIXED_FP32)
+    tlr.lib().tlr_tune_reset()
+    t0 = time.perf_counter()
+    tiles, measured = [], {}
+    for w in ws:
+        best, ms = tlr.tune_tile(w.points, w.kernel, w.ell, w.diag_add, w.eps, (256, 512, 1024), o64)
+        tiles.append(best)
+        if ms is not None:
+            measured["N=%d" % w.n] = {str(k): v for k, v in ms.items()}
+    t_tune = time.perf_counter() - t0
+
+    def build(ms_):
+        return [tlr.TLRMatrix.compress_kernel(w.points, w.kernel, w.ell, w.diag_add, mm, w.eps, o_c)
+                for w, mm in zip(ws, ms_)]
 
     def timed(f):
         f()   # warm-up (workspaces, code objects)
@@ -175,10 +220,7 @@ def batched_form(tlr, torch, wl, count: int, m: int):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, out
 
-    def seq():
-        return [mt.potrf(ws[0].eps, o64) for mt in mats]
-
-    def bat(o):
+    def bat(mats, o):
         def run():
             s, sts, _ = tlr.factor_batched(mats, ws[0].eps, o)
             if s != 0:
@@ -186,17 +228,26 @@ def batched_form(tlr, torch, wl, count: int, m: int):
             return sts
         return run
 
-    t_seq, _ = timed(seq)
-    t_b64, st_b64 = timed(bat(o64))
-    t_b32, st_b32 = timed(bat(o32))
+    fixed = build([m_fixed] * len(ws))
+    t_fixed, _ = timed(bat(fixed, o64))
+    for mt in fixed:
+        mt.close()
+    mats = build(tiles)
+    t_seq, _ = timed(lambda: [mt.potrf(ws[0].eps, o64) for mt in mats])
+    t_b64, st_b64 = timed(bat(mats, o64))
+    t_b32, st_b32 = timed(bat(mats, o32))
     flops = sum(x["flops"] for x in st_b64)
     ns = [w.n for w in ws]
     for mt in mats:
         mt.close()
-    return {"count": count, "tile": m, "N_min": min(ns), "N_max": max(ns), "N_total": sum(ns),
+    choice = {str(mm): tiles.count(mm) for mm in sorted(set(tiles))}
+    return {"count": count, "tiles_tuned": choice, "tuning_s": t_tune, "tuning_measured": measured,
+            "N_min": min(ns), "N_max": max(ns), "N_total": sum(ns),
             "eps": ws[0].eps, "eps_mode": "relative",
             "sequential_fp64_s": t_seq, "batched_fp64_s": t_b64, "batched_mixed_fp32_s": t_b32,
+            "batched_fp64_fixed_tile_s": t_fixed, "fixed_tile": m_fixed,
             "speedup_fp64": t_seq / t_b64, "speedup_mixed": t_seq / t_b32,
+            "tuned_over_fixed": t_fixed / t_b64,
             "batched_fp64_tflops": flops / t_b64 / 1e12}
 
 
@@ -297,8 +348,13 @@ def main():
                     help="skip the factorization with phase timers (per-phase GPU time)")
     ap.add_argument("--no-ldlt", dest="ldlt", action="store_false",
                     help="skip the LDL^T line (3D Matern, indefinite) after the main line")
+    ap.add_argument("--no-pivoted", dest="pivoted", action="store_false",
+                    help="skip the pivoted / unpivoted line (3D covariance, tile 512)")
     ap.add_argument("--batched", type=int, default=96,
                     help="problems of the batched workload timed after the main line (0 = skip)")
+    ap.add_argument("--profile", action="store_true",
+                    help="for profilers: build the input, run the --warmup and --steps "
+                         "factorizations and stop (no second pass, residual or other lines)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM "
                          "byte counters against a kernel of known traffic)")
@@ -338,8 +394,13 @@ def main():
     # percent of the step); the sampling kernel's durations come from the
     # dispatches' own events in a second pass of the same number of steps
     dt, stats = time_form(mat, w, w.eps_mode, tlr.FP64, tlr, torch, a.steps, a.warmup, a.bs_tail,
-                          a.tail_active, False)
+                          a.tail_active, False, 0.05 if a.profile else 0.0)
     print("[bench] %d timed steps, %.1f ms each" % (a.steps, dt * 1e3), file=sys.stderr, flush=True)
+    if a.profile:
+        print(json.dumps({"profile": w.name, "ms_per_step": dt * 1e3,
+                          "ara_iterations": int(stats[-1]["ara_iters"])}), flush=True)
+        mat.close()
+        return
     dt_ev, stats_ev = (time_form(mat, w, w.eps_mode, tlr.FP64, tlr, torch, a.steps, 0, a.bs_tail, a.tail_active, True)
                        if a.kernel_timing else (0.0, []))
     phases = phase_split(mat, w, tlr, torch) if a.phases else None
@@ -419,13 +480,24 @@ def main():
               % (line["ldlt"]["ms_per_step"], line["ldlt"]["residual"],
                  line["ldlt"]["ranks_factor"]["mean"], line["ldlt"]["ranks_factor"]["max"]),
               file=sys.stderr, flush=True)
+    if a.pivoted:
+        print("[bench] pivoted workload (3D covariance, N=131072, tile 512)", file=sys.stderr,
+              flush=True)
+        line["pivoted"] = pivoted_form(tlr, torch, wl, max(1, min(a.steps, 2)))
+        for k in ("unpivoted", "pivoted"):
+            v = line["pivoted"][k]
+            print("[bench] cov3d_131k %s: %.1f ms, residual %.3g, ranks mean %.1f max %d"
+                  % (k, v["ms_per_step"], v["residual"], v["rank_mean"], v["rank_max"]),
+                  file=sys.stderr, flush=True)
     if a.batched > 0:
         print("[bench] batched workload: %d problems" % a.batched, file=sys.stderr, flush=True)
         line["batched"] = batched_form(tlr, torch, wl, a.batched, 512)
         b = line["batched"]
-        print("[bench] batched: sequential %.3fs, batched fp64 %.3fs (x%.2f), mixed %.3fs (x%.2f)"
-              % (b["sequential_fp64_s"], b["batched_fp64_s"], b["speedup_fp64"],
-                 b["batched_mixed_fp32_s"], b["speedup_mixed"]), file=sys.stderr, flush=True)
+        print("[bench] batched: tiles %s (tuning %.1fs); sequential %.3fs, batched fp64 %.3fs "
+              "(x%.2f), mixed %.3fs (x%.2f), fixed tile %d %.3fs"
+              % (b["tiles_tuned"], b["tuning_s"], b["sequential_fp64_s"], b["batched_fp64_s"],
+                 b["speedup_fp64"], b["batched_mixed_fp32_s"], b["speedup_mixed"], b["fixed_tile"],
+                 b["batched_fp64_fixed_tile_s"]), file=sys.stderr, flush=True)
     if a.cpu_sample > 0:
         print("[bench] CPU oracle on a %d-point sample" % a.cpu_sample, file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, min(a.cpu_sample, w.n), tlr, torch)

@@ -109,7 +109,11 @@ typedef struct {
                               (Algorithm "Left Looking Cholesky TLR ARA Update",
                               "subset"); <= 0 means all tiles of the column */
   int r_min;               /* a tile has converged once at least r_min samples of
-                              a block stay below tau after orthogonalisation (>= 1) */
+                              a block stay below tau after orthogonalisation
+                              (1..bs; 0 means the default, half the smallest
+                              block: the samples left over by the pivoted
+                              Cholesky QR are the smallest of their block, so
+                              a single one underestimates the error) */
   unsigned long long seed; /* seed of the Philox4x32-10 test-matrix stream */
   int flags;               /* TLR_FLAG_* bits */
   int bs_tail;             /* samples per ARA iteration after the first one of a
@@ -144,8 +148,18 @@ typedef struct {
  * of the Schur-complement sampling product and report its time and
  * algorithmic bytes in tlr_stats.sample_*.  TLR_FLAG_PHASE_TIMING: record
  * HIP events at the phase boundaries of every column and report the GPU time
- * per phase in tlr_stats.t_phase. */
-enum { TLR_FLAG_KERNEL_TIMING = 1, TLR_FLAG_PHASE_TIMING = 2 };
+ * per phase in tlr_stats.t_phase.  TLR_FLAG_SERIAL_SAMPLING: draw every ARA
+ * iteration's samples on the caller's stream after the previous iteration
+ * (by default, when every tile of the column is active from the start, the
+ * samples of iteration t + 1 are drawn on a library stream while iteration t
+ * is orthogonalised; the result is the same bit for bit).
+ * TLR_FLAG_MODIFIED_CHOL (Cholesky only; Section 5.1.2, "Modified Cholesky"):
+ * a diagonal tile that loses definiteness is not an error; each
+ * non-positive pivot of its Cholesky is replaced by tau as it is met, which
+ * factors the tile plus a non-negative diagonal perturbation (E = 0 for a
+ * definite tile); tlr_stats.modified_pivots counts them. */
+enum { TLR_FLAG_KERNEL_TIMING = 1, TLR_FLAG_PHASE_TIMING = 2, TLR_FLAG_SERIAL_SAMPLING = 4,
+       TLR_FLAG_MODIFIED_CHOL = 8 };
 
 /* Phases of a column step (indices of tlr_stats.t_phase).  Phases 0-6 run on
  * the caller's stream one after another, so their times add up to that
@@ -193,10 +207,14 @@ typedef struct {
   double t_phase[TLR_NPHASE]; /* TLR_FLAG_PHASE_TIMING: GPU time per phase (TLR_PHASE_*),
                               milliseconds */
   long long bf16_tile_iters; /* mixed forms: tile iterations sampled from BF16 panels */
+  double t_host_issue;     /* host time issuing the ARA iterations' launches, ms */
+  double t_host_wait;      /* host time waiting for the ARA iterations' results, ms */
+  long long modified_pivots; /* TLR_FLAG_MODIFIED_CHOL: pivots raised to tau */
 } tlr_stats;
 
 /* Fill *opts with the defaults: bs 16, absolute eps, FP64, shift 0, all tiles
- * active, r_min 1, seed 0x5eed, no automatic shift, automatic strip height. */
+ * active, r_min 0 (half the block), seed 0x5eed, no automatic shift,
+ * automatic strip height. */
 void tlr_opts_default(tlr_opts* opts);
 
 /* Create an N x N matrix with tile size m and the given ranks of the strictly
@@ -246,6 +264,45 @@ tlr_status tlr_compress_kernel(const double* points, int dim, long long N, int k
  * opts->auto_shift: when it still is with the shift s = tau). */
 tlr_status tlr_potrf(tlr_matrix_t A, double eps, const tlr_opts* opts, tlr_stats* stats,
                      void* stream);
+
+/* Tile-size autotuner (the factorization time depends strongly on the tile
+ * size, Table 1 of the paper).  For the covariance problem of
+ * tlr_compress_kernel (points in device memory), builds the TLR input at
+ * each of the ncand candidate tile sizes at threshold eps and times one
+ * tlr_potrf with opts after an untimed one; *best receives the fastest
+ * candidate, ms (host, ncand entries, may be NULL) the times in
+ * milliseconds (INFINITY for a candidate that failed to factor).  The choice
+ * is remembered per problem class (ceil(log2 N), dim, kernel, eps,
+ * opts->eps_mode, opts->precision, opts->bs and the candidate set): a class
+ * seen before returns at once with *cached = 1 (cached may be NULL) and ms
+ * untouched.  Device memory comes from the allocator (NULL: hipMalloc) and
+ * is released before returning.  TLR_ERR_NOT_SPD if no candidate could be
+ * factored. */
+tlr_status tlr_tune_tile(const double* points, int dim, long long N, int kernel, double ell,
+                         double diag_add, double eps, const tlr_opts* opts, const int* candidates,
+                         int ncand, const tlr_allocator* allocator, void* stream, int* best,
+                         double* ms, int* cached);
+/* Forget every choice tlr_tune_tile remembered. */
+void tlr_tune_reset(void);
+
+/* Pivoted left-looking TLR Cholesky (Algorithm "Pivoted Left Looking TLR
+ * Cholesky", Section 5.2): at column k every block position t >= k not yet
+ * factored holds its updated diagonal tile A_tt - sum_{j<k} L_tj L_tj^T; the
+ * one with the largest Frobenius norm (the first of equal ones) becomes
+ * position k, its block row and column trading places with block k.  On
+ * return the handle holds L with P A P^T = L L^T, where position t of the
+ * factor is original block perm[t] (perm: host array of nb ints, may be
+ * NULL; tlr_get_perm returns it later).  tlr_get_tile / tlr_get_diag of the
+ * factor use positions; tlr_solve applies P and P^T itself.  The sampling
+ * runs in FP64 (opts->precision TLR_FP64, else TLR_ERR_ARG); other options,
+ * errors and stats as tlr_potrf (stats->info is the global row of the
+ * position that failed). */
+tlr_status tlr_potrf_pivoted(tlr_matrix_t A, double eps, const tlr_opts* opts, int* perm,
+                             tlr_stats* stats, void* stream);
+/* The block permutation of the factor (identity for an unpivoted one):
+ * perm (host, nb ints), position t = original block perm[t].
+ * TLR_ERR_STATE if the handle holds no factor. */
+tlr_status tlr_get_perm(tlr_matrix_t A, int* perm);
 
 /* Left-looking TLR LDL^T A = L D L^T, L unit lower triangular, D diagonal
  * (Algorithm "Left Looking TLR LDL^T", Eq. (3)); the diagonal tiles use an

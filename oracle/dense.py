@@ -76,6 +76,33 @@ def cholesky(a: np.ndarray) -> np.ndarray:
         raise NotSPD(str(exc))
 
 
+def cholesky_modified(a: np.ndarray, delta: float):
+    """Modified Cholesky of a symmetric tile (Section 5.1.2, "Modified
+    Cholesky in Diagonal Tiles"), with the diagonal modification made as the
+    pivots are met: column by column, d_j = a_jj - sum_{p<j} L_jp^2; a pivot
+    d_j <= 0 is replaced by max(|d_j|, delta) (the sign flip of the
+    Gill-Murray-Wright and Schnabel-Eskow modified Cholesky, which keeps the
+    pivot as large as the loss it repairs, so the later columns do not
+    grow); L_jj = sqrt(d_j) and L_ij = (a_ij - sum_{p<j} L_ip L_jp) / L_jj.
+    Then L L^T = a + diag(f) with f_j = max(|d_j|, delta) - d_j >= 0 for the
+    replaced pivots and 0 elsewhere (f = 0, L the Cholesky factor, for a
+    positive definite a).  Returns (L, f)."""
+    n = a.shape[0]
+    lo = np.tril(np.array(a, dtype=np.float64))
+    ell = np.zeros((n, n))
+    f = np.zeros(n)
+    for j in range(n):
+        d = lo[j, j] - np.dot(ell[j, :j], ell[j, :j])
+        if not d > 0.0:
+            dm = max(abs(d), delta)
+            f[j] = dm - d
+            d = dm
+        ell[j, j] = math.sqrt(d)
+        if j + 1 < n:
+            ell[j + 1:, j] = (lo[j + 1:, j] - ell[j + 1:, :j] @ ell[j, :j]) / ell[j, j]
+    return ell, f
+
+
 def ldlt_unpivoted(a: np.ndarray, breakdown: float = 64.0):
     """Unpivoted scalar LDL^T: a = L diag(d) L^T with L unit lower triangular.
 

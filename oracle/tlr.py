@@ -207,7 +207,8 @@ def schur_tile(a: TLR, l: TLR, i: int, k: int, d: Optional[list] = None) -> np.n
     return s
 
 
-def tlr_cholesky(a: TLR, tau: float, shift: float = 0.0, record: Optional[dict] = None) -> TLR:
+def tlr_cholesky(a: TLR, tau: float, shift: float = 0.0, record: Optional[dict] = None,
+                 modified: bool = False) -> TLR:
     """Left-looking TLR Cholesky with exact recompression (oracle O4).
 
     Column k (Algorithm "Left Looking TLR Cholesky"):
@@ -218,7 +219,11 @@ def tlr_cholesky(a: TLR, tau: float, shift: float = 0.0, record: Optional[dict] 
       4. V_ik = L_kk^{-1} B (the batched triangular solve: Q B^T L_kk^{-T}
          = Q (L_kk^{-1} B)^T), U_ik = Q.
     The shift is the paper's diagonal shift A + sI (Section 5.1); it is
-    applied to the real rows only, not to the padding.
+    applied to the real rows only, not to the padding.  With `modified`, step
+    2 is the modified Cholesky of Section 5.1.2 (dense.cholesky_modified with
+    delta = tau): a tile that lost definiteness is factored with its
+    non-positive pivots raised to tau; record["modified"] (when record is
+    given) receives the number of raised pivots.
     `record`, when given, receives per-tile truncation errors sigma_{rho+1}.
     """
     l = TLR(a.n, a.m)
@@ -230,10 +235,15 @@ def tlr_cholesky(a: TLR, tau: float, shift: float = 0.0, record: Optional[dict] 
         for j in range(k):
             g = l.v[k, j].T @ l.v[k, j]
             dk -= l.u[k, j] @ (g @ l.u[k, j].T)
-        try:
-            l.diag[k] = np.linalg.cholesky(dk)
-        except np.linalg.LinAlgError:
-            raise NotSPDTile(k)
+        if modified:
+            l.diag[k], f = dense.cholesky_modified(dk, tau)
+            if record is not None:
+                record["modified"] = record.get("modified", 0) + int(np.count_nonzero(f))
+        else:
+            try:
+                l.diag[k] = np.linalg.cholesky(dk)
+            except np.linalg.LinAlgError:
+                raise NotSPDTile(k)
         for i in range(k + 1, a.nb):
             q, b, s = truncate_svd(schur_tile(a, l, i, k), tau)
             l.u[i, k] = q

@@ -32,7 +32,7 @@ void tlr_opts_default(tlr_opts* o) {
   o->precision = TLR_FP64;
   o->shift = 0.0;
   o->max_active = 0;
-  o->r_min = 1;
+  o->r_min = 0;
   o->seed = 0x5eedULL;
   o->flags = 0;
   o->bs_tail = 0;
@@ -56,7 +56,12 @@ static tlr_status check_opts(const tlr_opts* in, tlr_opts* out) {
   TLR_ARG(out->eps_mode == TLR_EPS_ABS || out->eps_mode == TLR_EPS_REL, "opts.eps_mode invalid");
   TLR_ARG(out->precision >= TLR_FP64 && out->precision <= TLR_MIXED_AUTO,
           "opts.precision must be TLR_FP64, TLR_MIXED_FP32, TLR_MIXED_BF16 or TLR_MIXED_AUTO");
-  TLR_ARG(out->r_min >= 1 && out->r_min <= out->bs, "opts.r_min must be in 1..bs");
+  TLR_ARG(out->r_min >= 0 && out->r_min <= out->bs, "opts.r_min must be in 0..bs");
+  if (out->r_min == 0) {
+    // half the smallest block of the run
+    const int b = (out->bs_tail > 0 && out->bs_tail < out->bs) ? out->bs_tail : out->bs;
+    out->r_min = b > 1 ? b / 2 : 1;
+  }
   TLR_ARG(out->bs_tail == 0 || (orth_block_supported(out->bs_tail) && out->r_min <= out->bs_tail),
           "opts.bs_tail must be 0 or a supported block size >= r_min, got %d", out->bs_tail);
   TLR_ARG(out->tail_active >= 0, "opts.tail_active must be >= 0, got %d", out->tail_active);
@@ -244,20 +249,21 @@ static double ms_since(std::chrono::steady_clock::time_point t0) {
 }
 
 static tlr_status factor_entry(tlr_matrix_t A, double eps, const tlr_opts* opts, tlr_stats* stats,
-                               bool ldl, double* D) {
+                               bool ldl, double* D, bool piv = false) {
   const auto t0 = std::chrono::steady_clock::now();
   TLR_ARG(A, "NULL handle");
   TLR_ARG(eps > 0.0 && std::isfinite(eps), "eps must be positive");
   tlr_opts o;
   TLR_TRY(check_opts(opts, &o));
+  TLR_ARG(!piv || o.precision == TLR_FP64, "the pivoted Cholesky samples in FP64 (opts.precision)");
   if (stats) std::memset(stats, 0, sizeof *stats);
-  tlr_status st = factorize(A, eps, o, stats, ldl);
+  tlr_status st = factorize(A, eps, o, stats, ldl, piv);
   // Section 5.1: a shift s <= eps of the diagonal keeps the perturbation
   // below the compression threshold; with auto_shift a Cholesky that lost
   // definiteness without a shift is repeated once with s = tau
   if (st == TLR_ERR_NOT_SPD && !ldl && o.auto_shift && o.shift == 0.0) {
     o.shift = -1.0;
-    st = factorize(A, eps, o, stats, ldl);
+    st = factorize(A, eps, o, stats, ldl, piv);
     if (stats) stats->shift_retries = 1;
   }
   if (st == TLR_OK && ldl && D) {
@@ -273,6 +279,25 @@ tlr_status tlr_potrf(tlr_matrix_t A, double eps, const tlr_opts* opts, tlr_stats
                      void* stream) {
   if (A) A->stream = A->mem.stream = (hipStream_t)stream;
   return factor_entry(A, eps, opts, stats, false, nullptr);
+}
+
+tlr_status tlr_potrf_pivoted(tlr_matrix_t A, double eps, const tlr_opts* opts, int* perm,
+                             tlr_stats* stats, void* stream) {
+  if (A) A->stream = A->mem.stream = (hipStream_t)stream;
+  const tlr_status st = factor_entry(A, eps, opts, stats, false, nullptr, true);
+  if (st == TLR_OK && perm)
+    for (int t = 0; t < A->nb; ++t) perm[t] = A->fperm[t];
+  return st;
+}
+
+tlr_status tlr_get_perm(tlr_matrix_t A, int* perm) {
+  TLR_ARG(A && perm, "NULL argument");
+  if (!A->factored) {
+    set_error("the handle holds no factor");
+    return TLR_ERR_STATE;
+  }
+  for (int t = 0; t < A->nb; ++t) perm[t] = A->fperm.empty() ? t : A->fperm[t];
+  return TLR_OK;
 }
 
 tlr_status tlr_ldlt(tlr_matrix_t A, double eps, const tlr_opts* opts, double* D, tlr_stats* stats,
@@ -453,6 +478,7 @@ tlr_status tlr_get_sort_order(tlr_matrix_t A, int k, int* rows) {
 tlr_status tlr_destroy(tlr_matrix_t A) {
   if (!A) return TLR_OK;
   A->worker.reset();
+  A->sworker.reset();
   (void)hipStreamSynchronize(A->stream);
   free_factor(A);
   Mem& mem = A->mem;

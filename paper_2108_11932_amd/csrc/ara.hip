@@ -181,7 +181,7 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, int r_min) {
   const int m = D.m, qcap = D.qcap, nrb = D.nstrip;
   const int qold = D.q[slot];
   const double tau2 = d.tau2;
-  const double* part = PIV ? d.part1 : d.part2;
+  const double* part = PIV ? d.part1 + D.poff : d.part2;
   const int t = threadIdx.x, lane = t & 63;
   const int x = t % BS, g = t / BS;
   const int nc = PIV ? BS : d.piv[BS];
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, int r_min) {
   const int r = blockIdx.x * APPLY_ROWS + t;
   if (np == 0) return;
   gdouble* dst = gmem(d.q) + (size_t)qold * m;
-  const gdouble* ysrc = gmem(d.y);
+  const gdouble* ysrc = gmem(d.y + D.yoff);
   double xv[BS], rd[BS];
 #pragma unroll
   for (int a = 0; a < BS; ++a) {
@@ -479,6 +479,13 @@ __global__ __launch_bounds__(256) void k_ara_compact(AraDev D, const int* waitin
   if (tid == 0) {
     D.counts[3] = scan[0];
     D.counts[2] = info ? *info : 0;
+  }
+  // snapshot of the new list for the speculative sampling of the iteration
+  // after next (it may run while the next iteration's compaction rewrites
+  // the list in place)
+  if (D.snap_act) {
+    for (int i = tid; i < na; i += 256) D.snap_act[i] = D.act[i];
+    if (tid == 0) D.snap_counts[0] = na;
   }
   // the four counters also go straight to the host's read-back slot
   // (pinned memory, stores at system scope)

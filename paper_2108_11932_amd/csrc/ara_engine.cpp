@@ -2,7 +2,10 @@
 #include "ara_engine.h"
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cstring>
+#include <thread>
 
 namespace tlr {
 
@@ -18,20 +21,22 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   s->nstrip = nstrip;
   s->qstride = (size_t)m * (c.qcap + bs);
   const size_t nn = n > 0 ? (size_t)n : 1;
-  TLR_TRY(w.Y.ensure(h->mem, sizeof(double) * nn * m * bs));
+  TLR_TRY(w.Y.ensure(h->mem, sizeof(double) * 2 * nn * m * bs));
   TLR_TRY(w.C.ensure(h->mem, sizeof(double) * nn * m * bs));
   const bool fresh_q = w.Q.cap < sizeof(double) * nn * s->qstride;
   TLR_TRY(w.Q.ensure(h->mem, sizeof(double) * nn * s->qstride));
   if (fresh_q) TLR_HIP(hipMemsetAsync(w.Q.p, 0, w.Q.cap, h->stream));
   const size_t pn = nn * nstrip * bs * bs * 2;
-  TLR_TRY(w.part.ensure(h->mem, sizeof(double) * 2 * pn));
-  const size_t nint = 8 + 9 * al(nn) + al(nn * (bs + 1)) + 64;
+  TLR_TRY(w.part.ensure(h->mem, sizeof(double) * 3 * pn));
+  const size_t nint = 8 + 9 * al(nn) + 2 * (64 + al(nn)) + al(nn * (bs + 1)) + 64;
   TLR_TRY(w.ints.ensure(h->mem, sizeof(int) * nint));
   s->Y = w.Y.as<double>();
   s->C = w.C.as<double>();
   s->Q = w.Q.as<double>();
   s->part1 = w.part.as<double>();
-  s->part2 = s->part1 + pn;
+  s->part2 = s->part1 + 2 * pn;
+  s->yalt = (long long)(nn * m * bs);
+  s->palt = (long long)pn;
   int* ip = w.ints.as<int>();
   s->counts = ip;
   ip += 8;
@@ -51,6 +56,12 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   ip += al(nn);
   s->f32 = ip;
   ip += al(nn);
+  for (int b = 0; b < 2; ++b) {
+    s->snap_counts[b] = ip;
+    ip += 64;
+    s->snap_act[b] = ip;
+    ip += al(nn);
+  }
   s->waiting = ip;   // counts .. waiting are written by one upload per run
   ip += al(nn);
   s->piv = ip;
@@ -104,6 +115,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   const int n = (int)order.size();
   const int m = c.m, bs = c.bs_max();
   const int s_max = c.s_max > 0 ? std::min(c.s_max, n) : n;
+  res->t_issue = res->t_wait = 0.0;
   res->q.assign(n, 0);
   res->iters.assign(n, 0);
   res->cols.assign(n, 0);
@@ -175,6 +187,8 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     std::vector<int> blob(wo + nwait, 0);
     blob[0] = s_max;
     std::copy(act.begin(), act.end(), blob.begin() + (s.act - s.counts));
+    blob[s.snap_counts[0] - s.counts] = s_max;
+    std::copy(act.begin(), act.end(), blob.begin() + (s.snap_act[0] - s.counts));
     std::copy(waiting.begin(), waiting.end(), blob.begin() + wo);
     TLR_TRY(h->stage.upload_to(h, blob.data(), sizeof(int) * blob.size(), s.counts, st));
   }
@@ -202,6 +216,10 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   D.bs = bs;
   D.qcap = c.qcap;
   D.nstrip = s.nstrip;
+  D.yoff = 0;
+  D.poff = 0;
+  D.snap_act = nullptr;
+  D.snap_counts = nullptr;
   const int p_blocks = (int)ptiles.size();
   const int bps_wa = (spec.a_max + 31) / 32;
   // split-K partial tiles of the TN products
@@ -220,70 +238,220 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   const bool any_z = !spec.zseg.empty() && bps_z > 0 && p_blocks > 0;
   int* info = h->d_info;
 
+  // Sampling lookahead.  Without refills (no waiting list) the active list
+  // only shrinks, so iteration t + 1's samples can be drawn for the tiles
+  // active in iteration t while iteration t is still being orthogonalised:
+  // the sampling launches go to the handle's sampling stream, one iteration
+  // ahead, into the other copy of Y and of its Gram partials.  Sampling t
+  // reads the list the compaction of iteration t - 2 left in snapshot
+  // (t - 1) & 1 (the list of iteration t - 1, a superset of iteration t's),
+  // and waits for that compaction, which also ends the last use of its Y
+  // copy; the orthogonalisation of t waits for sampling t.  A slot's samples
+  // depend only on the slot, so the result is the same as sampling exactly
+  // the tiles of iteration t; the samples of tiles that converged in
+  // iteration t - 1 are discarded.
+  const bool overlap = c.overlap && nwait == 0;
+  hipStream_t ss = st;
+  if (overlap) {
+    TLR_TRY(h->samp_stream());
+    ss = h->samp;
+    if (!h->sworker) h->sworker.reset(new SideWorker(h->dev));
+    TLR_HIP(hipEventRecord(h->ev_sfork, st));
+    TLR_HIP(hipStreamWaitEvent(ss, h->ev_sfork, 0));
+  }
+  // the sampling launches run beside the orthogonalisation: their own
+  // split-K scratch
+  double* tn_scratch_s = tn_scratch;
+  if (overlap) {
+    TLR_TRY(w.tnpart2.ensure(h->mem, w.tnpart.cap));
+    tn_scratch_s = w.tnpart2.as<double>();
+  }
+  // The sampling launches are issued by the handle's sampling worker thread
+  // (the event operations that order the two streams cost the host several
+  // microseconds each; split over two threads, the host keeps ahead of the
+  // GPU).  A stream wait must follow the record it refers to, so each side
+  // publishes the last iteration whose event it has recorded.
+  struct Progress {
+    std::atomic<int> samp_rec{-1}, main_rec{-1};
+    std::atomic<bool> failed{false}, abort{false};
+  } prog;
+  // every exit stops the worker's pending waits, lets it drain and joins the
+  // sampling stream back into the caller's stream
+  struct Join {
+    Handle* h;
+    hipStream_t st, ss;
+    bool on;
+    Progress* pr;
+    ~Join() {
+      if (!on) return;
+      pr->abort.store(true, std::memory_order_release);
+      (void)h->sworker->wait();
+      if (hipEventRecord(h->ev_sfork, ss) == hipSuccess) (void)hipStreamWaitEvent(st, h->ev_sfork, 0);
+    }
+  } join{h, st, ss, overlap, &prog};
+  // host-side wait for the other thread's progress (it is normally ahead)
+  auto await = [&](const std::atomic<int>& v, int target) -> bool {
+    for (int spins = 0; v.load(std::memory_order_acquire) < target; ++spins) {
+      if (prog.failed.load(std::memory_order_acquire) || prog.abort.load(std::memory_order_acquire))
+        return false;
+      if (spins > 64) std::this_thread::yield();
+    }
+    return true;
+  };
+
   Known known;
   known.count = s_max;
-  // enqueue iteration j with launch bounds derived from `known`: the active
-  // count can only grow by refills, a basis by at most bs per iteration
-  auto enqueue = [&](int j) -> tlr_status {
-    D.bs = c.bs_for(j, known.count);
-    res->iter_bs.push_back(D.bs);
-    const int cb = (known.cursor >= nwait) ? known.count : s_max;
-    const int qb = std::min(c.qcap, known.qmax + bs * (j - known.iter - 1));
+  std::vector<int> bs_of;   // samples of every iteration, fixed when it is sampled
+  int sampled = -1;         // last iteration whose sampling is enqueued
+  auto dev_for = [&](int t, bool sampling) {
+    AraDev E = D;
+    E.bs = bs_of[t];
+    E.yoff = (t & 1) ? s.yalt : 0;
+    E.poff = (t & 1) ? s.palt : 0;
+    E.snap_act = nullptr;
+    E.snap_counts = nullptr;
+    if (overlap && sampling) {
+      const int b = t == 0 ? 0 : ((t - 1) & 1);
+      E.act = s.snap_act[b];
+      E.counts = s.snap_counts[b];
+    }
+    return E;
+  };
+  // the launches of the sampling of iteration t (Y = S Omega for every tile
+  // of the list E names) on stream q
+  auto sample_launches = [=, &spec](const AraDev& E, int t, int cb, hipStream_t q, hipEvent_t e0,
+                                     hipEvent_t e1) -> tlr_status {
     // the samples of the explicit tiles read the test matrix through their
     // descriptors (one buffer, drawn every iteration); the sampling through
     // P and W^A draws the matrices of kOmegaBatch iterations at a time
     const double* om = omega;
-    if (spec.pt) TLR_HIP(spec.pt->mark(TLR_PHASE_SAMPLE, st));
     if (omega_in_slots) {
-      TLR_HIP(launch_randn(omega, m, D.bs, m, c.seed, c.stream_id, (unsigned)j, 0, st));
+      TLR_HIP(launch_randn(omega, m, E.bs, m, c.seed, c.stream_id, (unsigned)t, 0, q));
     } else {
       const size_t ostride = (size_t)m * bs;
-      if (j % kOmegaBatch == 0)
+      if (t % kOmegaBatch == 0)
         TLR_HIP(launch_randn_iters(omega, m, ostride, c.bs, bs, c.seed, c.stream_id,
-                                   (unsigned)j, kOmegaBatch, 0, st));
-      om = omega + (size_t)(j % kOmegaBatch) * ostride;
+                                   (unsigned)t, kOmegaBatch, 0, q));
+      om = omega + (size_t)(t % kOmegaBatch) * ostride;
     }
+    double* scr = q == st ? tn_scratch : tn_scratch_s;
     if (p_blocks > 0 || bps_wa > 0)
-      TLR_HIP(launch_ara_tn(D, 0, om, dptiles, p_blocks, spec.ldp, cb, bps_wa, tn_scratch, st));
-    if (any_z) TLR_HIP(launch_ara_z(D, dzseg, spec.p, spec.ldp, cb, bps_z, st));
+      TLR_HIP(launch_ara_tn(E, 0, om, dptiles, p_blocks, spec.ldp, cb, bps_wa, scr, q));
+    if (any_z) TLR_HIP(launch_ara_z(E, dzseg, spec.p, spec.ldp, cb, bps_z, q));
+    TLR_HIP(launch_ara_seg(E, 0, cb, q, c.strip, e0, e1));
+    return TLR_OK;
+  };
+  // enqueue the sampling of iteration t with launch bounds derived from
+  // `known`: the active count can only grow by refills, a basis by at most
+  // bs per iteration
+  auto enqueue_sampling = [&](int t) -> tlr_status {
+    bs_of.push_back(c.bs_for(t, known.count));
+    res->iter_bs.push_back(bs_of[t]);
+    sampled = t;
+    const AraDev E = dev_for(t, true);
+    const int cb = (known.cursor >= nwait) ? known.count : s_max;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     if (spec.events) {
-      hipEvent_t e0, e1;
       TLR_HIP(hipEventCreate(&e0));
       TLR_HIP(hipEventCreate(&e1));
       spec.events->push_back({e0, e1});
-      TLR_HIP(launch_ara_seg(D, 0, cb, st, c.strip, e0, e1));
-    } else {
-      TLR_HIP(launch_ara_seg(D, 0, cb, st, c.strip));
+    }
+    if (!overlap) return sample_launches(E, t, cb, st, e0, e1);
+    Handle* hh = h;
+    Progress* pr = &prog;
+    h->sworker->submit([=]() -> tlr_status {
+      tlr_status r = TLR_OK;
+      if (t >= 2) {
+        // sampling t overwrites the Y copy of iteration t - 2 and reads the
+        // list its compaction left
+        for (int spins = 0; pr->main_rec.load(std::memory_order_acquire) < t - 2; ++spins) {
+          if (pr->abort.load(std::memory_order_acquire)) return TLR_OK;
+          if (spins > 64) std::this_thread::yield();
+        }
+        if (hipStreamWaitEvent(ss, hh->ev_main[(t - 2) & 3], 0) != hipSuccess) r = TLR_ERR_DEVICE;
+      }
+      if (r == TLR_OK) r = sample_launches(E, t, cb, ss, e0, e1);
+      if (r == TLR_OK && hipEventRecord(hh->ev_samp[t & 3], ss) != hipSuccess) r = TLR_ERR_DEVICE;
+      if (r != TLR_OK) {
+        pr->failed.store(true, std::memory_order_release);
+        return r;
+      }
+      pr->samp_rec.store(t, std::memory_order_release);
+      return TLR_OK;
+    });
+    return TLR_OK;
+  };
+  // enqueue the orthogonalisation, convergence test and compaction of
+  // iteration j (its sampling enqueued before)
+  auto enqueue_orth = [&](int j) -> tlr_status {
+    AraDev E = dev_for(j, false);
+    if (overlap) {
+      E.snap_act = s.snap_act[(j + 1) & 1];
+      E.snap_counts = s.snap_counts[(j + 1) & 1];
+    }
+    const int cb = (known.cursor >= nwait) ? known.count : s_max;
+    const int qb = std::min(c.qcap, known.qmax + bs * (j - known.iter - 1));
+    if (spec.pt) TLR_HIP(spec.pt->mark(TLR_PHASE_SAMPLE, st));
+    if (overlap) {
+      if (!await(prog.samp_rec, j)) {
+        const tlr_status e = h->sworker->wait();
+        if (e == TLR_OK) set_error("ARA sampling worker stopped");
+        return e == TLR_OK ? TLR_ERR_DEVICE : e;
+      }
+      TLR_HIP(hipStreamWaitEvent(st, h->ev_samp[j & 3], 0));
     }
     const int bps_q = (qb + 31) / 32;
     if (spec.pt) TLR_HIP(spec.pt->mark(TLR_PHASE_ORTH, st));
     if (bps_q > 0) {
-      TLR_HIP(launch_ara_tn(D, 1, nullptr, nullptr, 0, 0, cb, bps_q, tn_scratch, st));
-      TLR_HIP(launch_ara_seg(D, 1, cb, st));
+      TLR_HIP(launch_ara_tn(E, 1, nullptr, nullptr, 0, 0, cb, bps_q, tn_scratch, st));
+      TLR_HIP(launch_ara_seg(E, 1, cb, st));
     }
-    TLR_HIP(launch_orth_step(D, 1, c.r_min, cb, st));
+    TLR_HIP(launch_orth_step(E, 1, c.r_min, cb, st));
     if (bps_q > 0) {
-      TLR_HIP(launch_ara_tn(D, 2, nullptr, nullptr, 0, 0, cb, bps_q, tn_scratch, st));
-      TLR_HIP(launch_ara_seg(D, 2, cb, st));
+      TLR_HIP(launch_ara_tn(E, 2, nullptr, nullptr, 0, 0, cb, bps_q, tn_scratch, st));
+      TLR_HIP(launch_ara_seg(E, 2, cb, st));
     }
-    TLR_HIP(launch_orth_step(D, 2, c.r_min, cb, st));
+    TLR_HIP(launch_orth_step(E, 2, c.r_min, cb, st));
     if (spec.pt) TLR_HIP(spec.pt->mark(TLR_PHASE_BATCH, st));
-    TLR_HIP(launch_ara_compact(D, s.waiting, nwait, s_max, info, ring + 8 * (j & 1), pres, res_ints,
+    TLR_HIP(launch_ara_compact(E, s.waiting, nwait, s_max, info, ring + 8 * (j & 1), pres, res_ints,
                                st));
-    TLR_HIP(hipEventRecord(h->ev_rb[j & 1], st));
+    // one event serves the other stream's wait and the host's read-back
+    if (overlap) {
+      TLR_HIP(hipEventRecord(h->ev_main[j & 3], st));
+      prog.main_rec.store(j, std::memory_order_release);
+    } else {
+      TLR_HIP(hipEventRecord(h->ev_rb[j & 1], st));
+    }
     return TLR_OK;
+  };
+  auto readback_event = [&](int j) { return overlap ? h->ev_main[j & 3] : h->ev_rb[j & 1]; };
+  // iteration j: with the lookahead, the sampling of j + 1 goes out first
+  // (it waits only for the compaction of j - 1)
+  auto enqueue = [&](int j) -> tlr_status {
+    while (sampled < (overlap ? j + 1 : j)) TLR_TRY(enqueue_sampling(sampled + 1));
+    return enqueue_orth(j);
   };
 
   const long long limit = (long long)n * (c.qcap + 1) + 1;
+  using clk = std::chrono::steady_clock;
+  auto ms = [](clk::time_point a, clk::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+  };
   int enq = 0;
+  auto t0 = clk::now();
   TLR_TRY(enqueue(0));
   for (;;) {
     // keep one iteration queued ahead of the state being read back
     TLR_TRY(enqueue(enq + 1));
     ++enq;
+    auto t1 = clk::now();
+    res->t_issue += ms(t0, t1);
     if (idle) TLR_TRY(idle());
     const int j = known.iter + 1;
-    TLR_HIP(hipEventSynchronize(h->ev_rb[j & 1]));
+    t1 = clk::now();
+    TLR_HIP(hipEventSynchronize(readback_event(j)));
+    t0 = clk::now();
+    res->t_wait += ms(t1, t0);
     const int* r = ring + 8 * (j & 1);
     known.iter = j;
     known.count = r[0];

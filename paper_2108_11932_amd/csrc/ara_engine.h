@@ -36,6 +36,10 @@ struct AraConfig {
   unsigned long long seed = 0;
   unsigned stream_id = 0;   // Philox counter word 2 (column index or batch id)
   int strip = 0;      // rows per workgroup of the sampling product (0: automatic, 16, 64)
+  // sample iteration t + 1 on the handle's sampling stream while iteration
+  // t is orthogonalised (only when no tile waits for a place in the active
+  // subset, so that the next active list is a subset of the current one)
+  bool overlap = true;
   // samples drawn by iteration `iter`, `active` tiles being active at its start
   int bs_for(int iter, int active) const {
     if (iter == 0 || bs_tail <= 0) return bs;
@@ -48,10 +52,10 @@ struct AraConfig {
 struct AraSlots {
   int n = 0;
   int m = 0, bs = 0, nstrip = 0;
-  double* Y = nullptr;      // n x (m x bs)
+  double* Y = nullptr;      // 2 copies of n x (m x bs), yalt doubles apart
   double* Q = nullptr;      // n x (m x (qcap + bs))
   double* C = nullptr;      // n x (m x bs)
-  double* part1 = nullptr;  // n x (nstrip x bs x bs x 2)
+  double* part1 = nullptr;  // 2 copies of n x (nstrip x bs x bs x 2), palt doubles apart
   double* part2 = nullptr;
   int* counts = nullptr;    // 8
   int* act = nullptr;       // n
@@ -64,6 +68,11 @@ struct AraSlots {
   int* f32 = nullptr;       // n: precision chosen per slot
   int* piv = nullptr;       // n x (bs + 1)
   int* waiting = nullptr;   // n
+  // snapshots of the active list for the speculative sampling: list b at
+  // snap_act[b] with its count at snap_counts[b][0]
+  int* snap_act[2] = {nullptr, nullptr};
+  int* snap_counts[2] = {nullptr, nullptr};
+  long long yalt = 0, palt = 0;
   size_t qstride = 0;       // doubles per slot in Q
   double* y(int s) const { return Y + (size_t)s * m * bs; }
   double* qb(int s) const { return Q + (size_t)s * qstride; }
@@ -114,6 +123,7 @@ struct AraResult {
   std::vector<int> iter_bs;    // samples per slot of every launched iteration
   std::vector<double> flops_paper_orth;  // per slot: orthogonalisation flops
   long long launches = 0;      // ARA iterations (batches)
+  double t_issue = 0.0, t_wait = 0.0;   // host ms issuing launches / waiting for results
   double flops = 0.0;          // executed flops (sampling, Gram-Schmidt, orthogonalisation)
   double samp_bytes = 0.0, samp_flops = 0.0;   // of the sampling launches
   // the same per slot

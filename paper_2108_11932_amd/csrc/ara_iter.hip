@@ -56,7 +56,7 @@ __device__ inline bool tn_resolve(const AraDev& D, int mode, int tid, const doub
   } else {
     const int q = D.q[slot];
     if (row0 >= q) return false;
-    const double* B = mode == 1 ? d.y : d.q + (size_t)q * m;
+    const double* B = mode == 1 ? d.y + D.yoff : d.q + (size_t)q * m;
     *o = TnTile{d.q, B, d.c, q, m, row0, tid, -1.0};
   }
   return true;
@@ -67,7 +67,9 @@ __device__ inline bool tn_resolve(const AraDev& D, int mode, int tid, const doub
 // GB/s: the K range is split over ceil(m / TN_KC) workgroups per output
 // tile, each storing its partial tile in scratch; k_ara_tn_sum then adds the
 // partials in a fixed order (a second launch rather than a cross-workgroup
-// handshake, whose device-scope fences are costly across the XCDs).
+// handshake, whose device-scope fences are costly across the XCDs).  One
+// workgroup per output tile over the whole K range (one launch, partials
+// summed in LDS) measured twice as slow: a CU alone streams too little.
 template <int FN>
 __global__ __launch_bounds__(64 * TN_NW) void k_ara_tn(AraDev D, int mode, const double* omega,
                                                         const PTile* ptiles, int p_tiles, int ldp,
@@ -186,21 +188,21 @@ __global__ __launch_bounds__(256) void k_ara_seg(AraDev D) {
     float (*r32)[FM * NF * 4][64] = (float (*)[FM * NF * 4][64])red32;
     if (d.a1_prec == 1)
       seg_strip<NF, 1, FM>(d.a0, d.lda0, d.b0, d.ldb0, d.k0, d.a1, d.lda1, d.b1, d.ldb1, d.k1,
-                           d.y, m, m, bs, 0.0, r0, red, r32, ys);
+                           d.y + D.yoff, m, m, bs, 0.0, r0, red, r32, ys);
     else if (d.a1_prec == 2)
       seg_strip<NF, 2, FM>(d.a0, d.lda0, d.b0, d.ldb0, d.k0, d.a1, d.lda1, d.b1, d.ldb1, d.k1,
-                           d.y, m, m, bs, 0.0, r0, red, r32, ys);
+                           d.y + D.yoff, m, m, bs, 0.0, r0, red, r32, ys);
     else
       seg_strip<NF, 0, FM>(d.a0, d.lda0, d.b0, d.ldb0, d.k0, d.a1, d.lda1, d.b1, d.ldb1, d.k1,
-                           d.y, m, m, bs, 0.0, r0, red, r32, ys);
-    part = d.part1;
+                           d.y + D.yoff, m, m, bs, 0.0, r0, red, r32, ys);
+    part = d.part1 + D.poff;
   } else {
     const int q = D.q[slot];
     if (q == 0) return;
-    double* dst = mode == 1 ? d.y : d.q + (size_t)q * m;
+    double* dst = mode == 1 ? d.y + D.yoff : d.q + (size_t)q * m;
     seg_strip<NF, 0, FM>(d.q, m, d.c, m, q, nullptr, 1, nullptr, 1, 0, dst, m, m, bs, 1.0, r0,
                          red, nullptr, ys);
-    part = mode == 1 ? d.part1 : d.part2;
+    part = mode == 1 ? d.part1 + D.poff : d.part2;
   }
   // Gram partials of each 16-row strip (Dot2 over its rows), pairs a <= b
   const int npairs = bs * (bs + 1) / 2;

@@ -80,6 +80,7 @@ tlr_status compress(Handle* h, const double* A, long long lda, const double* pts
   cfg.tau = eps / o.conv_factor;
   cfg.r_min = o.r_min;
   cfg.strip = o.sample_strip;
+  cfg.overlap = (o.flags & TLR_FLAG_SERIAL_SAMPLING) == 0;
   cfg.s_max = 0;
   cfg.seed = o.seed ^ 0xC0FFEEULL;
   AraSlots slots;

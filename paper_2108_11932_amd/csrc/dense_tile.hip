@@ -69,8 +69,13 @@ __global__ __launch_bounds__(64) void k_chol_panel(double* A, int lda, int m, in
     if (r < w && c < w && c <= r) v = A[(p0 + r) + (size_t)(p0 + c) * lda];
     row[cc] = v;
   }
-  const double tol = CHOL ? 0.0 : *tolp;
-  int bad_row = 0;
+  // Cholesky with tolp set: modified Cholesky, a non-positive pivot d is
+  // replaced by max(|d|, delta), delta = *tolp (a diagonal perturbation of
+  // the tile that keeps the pivot as large as the loss it repairs) and
+  // counted in info[1] instead of failing
+  const bool modify = CHOL && tolp != nullptr;
+  const double tol = CHOL ? (modify ? *tolp : 0.0) : *tolp;
+  int bad_row = 0, nmod = 0;
 #pragma unroll
   for (int j = 0; j < ND; ++j) {
     double* cb = colb[j & 1];
@@ -86,7 +91,10 @@ __global__ __launch_bounds__(64) void k_chol_panel(double* A, int lda, int m, in
     for (int cc = 0; cc < HC; ++cc) cv[cc] = cb[HC * hf + cc];
     __builtin_amdgcn_sched_barrier(0);
     const bool bad = CHOL ? !(d > 0.0) : !(fabs(d) > tol);
-    if (bad) {
+    if (bad && modify) {
+      if (j < w) ++nmod;
+      d = fmax(fabs(d), tol);
+    } else if (bad) {
       if (j < w && bad_row == 0) bad_row = row_base + p0 + j + 1;
       d = 1.0;
     }
@@ -122,6 +130,7 @@ __global__ __launch_bounds__(64) void k_chol_panel(double* A, int lda, int m, in
   __syncthreads();
   if (blockIdx.x == 0) {
     if (bad_row && lane == 0) atomicCAS(info, 0, bad_row);
+    if (nmod && lane == 0) atomicAdd(info + 1, nmod);
 #pragma unroll
     for (int q = 0; q < ND; ++q)
       if (act && r < w && q < w) Lst[r + (size_t)q * ldst] = (q <= r) ? Ls[r][q] : 0.0;

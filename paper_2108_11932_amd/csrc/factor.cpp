@@ -46,6 +46,10 @@ void free_factor(Handle* h) {
   h->l_rank.assign((size_t)h->nb * h->nb, 0);
   h->l_off.assign((size_t)h->nb * h->nb, -1);
   h->sort_log.assign(h->nb, std::vector<int>());
+  h->fperm.clear();
+  h->spos.clear();
+  h->mem.put(h->Sd);
+  h->Sd = nullptr;
   h->factored = 0;
 }
 
@@ -137,8 +141,11 @@ struct Prob {
   double tau_ara = 0.0;   // threshold of the ARA: tau / conv_factor
   double* pin_norm = nullptr;
   bool done = false;
+  bool piv = false;   // pivoted Cholesky (Section 5.2)
+  double mod_delta = 0.0;   // > 0: modified Cholesky of the diagonal tiles (Section 5.1.2)
   double flops = 0.0, flops_paper = 0.0, bytes_alg = 0.0, samp_bytes = 0.0, samp_flops = 0.0;
   long long ara_iters = 0, tile_iters = 0, fp32_tile_iters = 0, bf16_tile_iters = 0;
+  double t_issue = 0.0, t_wait = 0.0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   std::vector<long long> goff;
   // column k
@@ -198,7 +205,10 @@ tlr_status prob_init(Prob& p, double eps, const tlr_opts& o, bool ldl) {
   }
   p.shift = o.shift < 0.0 ? p.tau : o.shift;
   p.tau_ara = p.tau / o.conv_factor;
-  TLR_HIP(hipMemsetAsync(h->d_info, 0, sizeof(int), h->stream));
+  TLR_HIP(hipMemsetAsync(h->d_info, 0, 2 * sizeof(int), h->stream));
+  // modified Cholesky: a diagonal tile that lost definiteness has its
+  // non-positive pivots raised to the threshold
+  p.mod_delta = (!ldl && (o.flags & TLR_FLAG_MODIFIED_CHOL)) ? p.tau : 0.0;
   // mixed precision: packed FP32 (and BF16) copies of the U panels, used by
   // the tiles whose rounding in that precision stays below tau / 16 (the
   // LDL^T variant samples in FP64 throughout).  The automatic form keeps a
@@ -217,7 +227,7 @@ tlr_status prob_init(Prob& p, double eps, const tlr_opts& o, bool ldl) {
   // stay large in L, Section 4.2)
   for (int i = 1; i < nb; ++i) {
     long long sum = 0;
-    for (int j = 0; j < i; ++j) sum += h->ar(i, j);
+    for (int j = 0; j < i; ++j) sum += h->pr(i, j);
     long long c = (long long)(1.25 * sum) + 32;
     c = std::min(c, (long long)i * m);
     TLR_TRY(grow_row(h, i, (int)c));
@@ -225,6 +235,112 @@ tlr_status prob_init(Prob& p, double eps, const tlr_opts& o, bool ldl) {
   p.goff.assign((size_t)nb * nb, -1);
   p.ahead = -1;
   p.jk = -1;
+  if (p.piv) {
+    // the updated diagonal tiles start as A_tt + shift I (real rows)
+    void* q = nullptr;
+    TLR_TRY(h->mem.get(&q, sizeof(double) * (size_t)nb * m * m));
+    h->Sd = (double*)q;
+    h->fperm.resize(nb);
+    h->spos.resize(nb);
+    for (int t = 0; t < nb; ++t) {
+      h->fperm[t] = t;
+      h->spos[t] = t;
+      TLR_HIP(launch_copy_shift(h->diagA(t), h->Sd + (size_t)t * m * m, m, h->nreal(t), p.shift,
+                                h->stream));
+    }
+  }
+  return TLR_OK;
+}
+
+// Pivot choice of column k (Algorithm "Pivoted Left Looking TLR Cholesky",
+// Section 5.2).  The updated diagonal tile S_t = A_tt - sum_{j<k} L_tj L_tj^T
+// of every position t >= k receives column k - 1's product ("denseUpdates":
+// S_t -= U_tj (V_tj^T V_tj) U_tj^T, lower triangle), the pivot is the
+// position whose S_t has the largest Frobenius norm, the first of equal
+// ones ("selectPivot"), and block rows and columns k and p trade places
+// ("pivotRowColumn").  Only bookkeeping moves: the row panels (the columns
+// j < k go with their rows), ranks, offsets, the updated tiles and the map
+// from positions to the original blocks, through which the input tiles of
+// later columns are read.
+tlr_status col_pivot(Prob& p, int k) {
+  Handle* h = p.h;
+  const int m = h->m, nb = h->nb;
+  Work& w = h->ws;
+  auto S = [&](int t) { return h->Sd + (size_t)h->spos[t] * m * m; };
+  Plan plan(h);
+  if (k >= 1) {
+    const int j = k - 1;
+    long long gt = 0, wt = 0;
+    std::vector<long long> go(nb, -1), wo(nb, -1);
+    for (int t = k; t < nb; ++t) {
+      const int r = h->lr(t, j);
+      if (r == 0) continue;
+      go[t] = gt;
+      wo[t] = wt;
+      gt += (long long)r * r;
+      wt += (long long)m * r;
+    }
+    if (gt > 0) {
+      TLR_TRY(w.Sg.ensure(h->mem, sizeof(double) * (size_t)gt));
+      TLR_TRY(w.Sw.ensure(h->mem, sizeof(double) * (size_t)wt));
+      double* G = w.Sg.as<double>();
+      double* W = w.Sw.as<double>();
+      GemmBatch g(true, false), wb(false, false), up(false, true);
+      for (int t = k; t < nb; ++t) {
+        const int r = h->lr(t, j);
+        if (r == 0) continue;
+        g.add(r, r, m, h->vl(t, j), m, h->vl(t, j), m, G + go[t], r, 1.0, 0.0);
+        wb.add(m, r, r, h->ul(t, j), m, G + go[t], r, W + wo[t], m, 1.0, 0.0);
+        up.add(m, m, r, W + wo[t], m, h->ul(t, j), m, S(t), m, -1.0, 1.0, GEMM_LOWER_C);
+      }
+      plan.gemm(g);
+      plan.gemm(wb);
+      plan.gemm(up);
+      p.flops += g.flops + wb.flops + up.flops / 2;
+    }
+  }
+  const int n = nb - k;
+  constexpr int G = 16;
+  TLR_TRY(w.Snorm.ensure(h->mem, sizeof(double) * (size_t)n * G));
+  double* parts = w.Snorm.as<double>();
+  std::vector<const double*> tp(n);
+  for (int t = k; t < nb; ++t) tp[t - k] = S(t);
+  const size_t off = plan.stage(tp.data(), sizeof(double*) * n);
+  hipStream_t st = h->stream;
+  plan.launch(off, [=](const char* ptr) {
+    return launch_sym_fro_parts((const double* const*)ptr, n, m, m, G, parts, st);
+  });
+  TLR_TRY(plan.run());
+  p.flops += plan.flops;
+  double* pin = nullptr;
+  TLR_TRY(h->pinned_norms((size_t)nb * G, &pin));
+  TLR_HIP(hipMemcpyAsync(pin, parts, sizeof(double) * n * G, hipMemcpyDeviceToHost, st));
+  TLR_TRY(h->sync_main());
+  int best = k;
+  double bmax = -1.0;
+  for (int t = k; t < nb; ++t) {
+    double v = 0.0;
+    for (int g2 = 0; g2 < G; ++g2) v += pin[(size_t)(t - k) * G + g2];
+    if (v > bmax) {
+      bmax = v;
+      best = t;
+    }
+  }
+  if (best != k) {
+    const int a = k, b = best;
+    std::swap(h->fperm[a], h->fperm[b]);
+    std::swap(h->spos[a], h->spos[b]);
+    std::swap(h->UL[a], h->UL[b]);
+    std::swap(h->VL[a], h->VL[b]);
+    std::swap(h->UL32[a], h->UL32[b]);
+    std::swap(h->UL16[a], h->UL16[b]);
+    std::swap(h->R[a], h->R[b]);
+    std::swap(h->cap[a], h->cap[b]);
+    for (int j = 0; j < k; ++j) {
+      std::swap(h->l_rank[(size_t)a * nb + j], h->l_rank[(size_t)b * nb + j]);
+      std::swap(h->l_off[(size_t)a * nb + j], h->l_off[(size_t)b * nb + j]);
+    }
+  }
   return TLR_OK;
 }
 
@@ -235,6 +351,7 @@ tlr_status col_begin(Prob& p, int k, bool ldl) {
   const int m = h->m, nb = h->nb;
   Work& w = h->ws;
   TLR_HIP(p.pt->mark(TLR_PHASE_GBLOCKS, h->stream));
+  if (p.piv) TLR_TRY(col_pivot(p, k));
   p.Rk = h->R[k];
   const int Rk = p.Rk;
   // ---------------------------------------------- G_ij = V_ij^T (D_j) V_kj
@@ -327,7 +444,7 @@ tlr_status col_begin(Prob& p, int k, bool ldl) {
     std::vector<int> rk(p.nrow), rows(p.nrow);
     for (int s = 0; s < p.nrow; ++s) {
       rows[s] = k + 1 + s;
-      rk[s] = h->ar(k + 1 + s, k);
+      rk[s] = h->pr(k + 1 + s, k);
     }
     sort_ranks(rk.data(), rows.data(), p.nrow, p.order.data());
   }
@@ -357,11 +474,13 @@ tlr_status col_diag(Prob& p, int k, bool ldl) {
   Plan& dplan = *p.dplan;
   dplan.persist = &w.sideblob;
   {
-    const double* Akk = h->diagA(k);
+    // pivoting: the updated tile S_k already holds the shift and every
+    // low rank product of the columns j < k
+    const double* Akk = p.piv ? h->Sd + (size_t)h->spos[k] * m * m : h->diagA(k);
     const int nr = h->nreal(k);
-    const double shift = p.shift;
+    const double shift = p.piv ? 0.0 : p.shift;
     dplan.launch([=]() { return launch_copy_shift(Akk, Lkk, m, nr, shift, ds); });
-    if (Rk > 0) {
+    if (Rk > 0 && !p.piv) {
       double* Wd = w.Wd.as<double>();
       GemmBatch wb(false, false);
       for (int j = 0; j < k; ++j) {
@@ -376,7 +495,7 @@ tlr_status col_diag(Prob& p, int k, bool ldl) {
       p.flops += wb.flops + up.flops / 2;
     }
     TLR_TRY(dense_factor(h, dplan, !ldl, Lkk, m, m, ldl ? h->Dv + (size_t)k * m : nullptr, k * m,
-                         h->invL(k)));
+                         h->invL(k), p.mod_delta));
     // the staged descriptors go up from this thread; the launches are
     // issued by the handle's side worker, which also records the join
     TLR_TRY(dplan.run_some(0));
@@ -407,7 +526,7 @@ tlr_status col_lookahead(Prob& p, int k, bool ldl) {
   const int m = h->m, nb = h->nb;
   Work& w = h->ws;
   hipStream_t ds = h->side;
-  if (k + 1 < nb && k >= 1) {
+  if (k + 1 < nb && k >= 1 && !p.piv) {
     const int kn = k + 1;
     p.goff_next.assign((size_t)nb * nb, -1);
     long long gt = 0;
@@ -496,15 +615,15 @@ tlr_status col_spec(Prob& p, int k, int bsm, AraSpec& spec) {
   long long zo = 0;
   for (int s = 0; s < nrow; ++s) {
     const int i = k + 1 + s;
-    const int a = h->ar(i, k), Ri = h->R[i];
+    const int a = h->pr(i, k), Ri = h->R[i];
     AraSlotDesc& d = spec.slots[p.base + s];
     double* wa_s = Wa + (size_t)s * m * bsm;
-    d.a0 = h->ua(i, k);
+    d.a0 = h->pu(i, k);
     d.lda0 = m;
     d.k0 = a;
     d.b0 = wa_s;
     d.ldb0 = std::max(a, 1);
-    d.va = h->va(i, k);
+    d.va = h->pv(i, k);
     d.wa = wa_s;
     d.a = a;
     spec.a_max = std::max(spec.a_max, a);
@@ -585,7 +704,7 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
     double zf = 0.0;
     for (int j = 0; j < k; ++j) zf += (double)h->lr(i, j) * h->lr(k, j);
     const double cols = res.cols[sl];
-    p.flops += cols * 2.0 * ((double)h->ar(i, k) * m + zf);
+    p.flops += cols * 2.0 * ((double)h->pr(i, k) * m + zf);
     if (res.f32[sl] == 1) p.fp32_tile_iters += it[s];
     if (res.f32[sl] == 2) p.bf16_tile_iters += it[s];
     p.flops += res.flops_slot[sl];
@@ -593,6 +712,8 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
     p.samp_flops += res.samp_flops_slot[sl];
   }
   p.ara_iters += launches;
+  p.t_issue += res.t_issue;
+  p.t_wait += res.t_wait;
 
   // ---------------------------------------------- projection  B_i = S_ik^T Q_i
   std::vector<long long> boff(nrow), toff(nrow), taoff(nrow);
@@ -604,7 +725,7 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
     taoff[s] = sta;
     sq += q[s];
     st_ += (long long)h->R[i] * q[s];
-    sta += (long long)h->ar(i, k) * q[s];
+    sta += (long long)h->pr(i, k) * q[s];
   }
   TLR_TRY(w.T.ensure(h->mem, sizeof(double) * (size_t)std::max(st_, 1LL)));
   TLR_TRY(w.Ta.ensure(h->mem, sizeof(double) * (size_t)std::max(sta, 1LL)));
@@ -637,11 +758,11 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
     for (int s = 0; s < nrow; ++s) {
       const int i = k + 1 + s, qs = q[s];
       if (qs == 0) continue;
-      const int a = h->ar(i, k), Ri = h->R[i];
+      const int a = h->pr(i, k), Ri = h->R[i];
       const double* Qs = slots.qb(p.base + s);
       if (Ri > 0) t1.add(Ri, qs, m, h->UL[i], m, Qs, m, T + toff[s], Ri, 1.0, 0.0);
-      if (a > 0) t2.add(a, qs, m, h->ua(i, k), m, Qs, m, Ta + taoff[s], a, 1.0, 0.0);
-      b1.add(m, qs, a, h->va(i, k), m, Ta + taoff[s], std::max(a, 1), Ball + boff[s] * m, m, 1.0,
+      if (a > 0) t2.add(a, qs, m, h->pu(i, k), m, Qs, m, Ta + taoff[s], a, 1.0, 0.0);
+      b1.add(m, qs, a, h->pv(i, k), m, Ta + taoff[s], std::max(a, 1), Ball + boff[s] * m, m, 1.0,
              0.0);
     }
     // t1 and t2 stream the same basis blocks Q_i: one batch
@@ -748,11 +869,11 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
     // operation count of the paper's formulation (four-product sampling of
     // Eq. (2) per iteration, the same for the projection, orthogonalisation,
     // triangular solve)
-    const double ext = (double)h->R[i] - q[s] + Rk + h->ar(i, k);
+    const double ext = (double)h->R[i] - q[s] + Rk + h->pr(i, k);
     const double cols = res.cols[p.base + s];
     p.flops_paper += cols * 4.0 * m * ext + 4.0 * m * q[s] * ext +
                      res.flops_paper_orth[p.base + s] + (double)m * m * q[s];
-    p.bytes_alg += it[s] * 8.0 * m * ((double)h->R[i] - q[s] + h->ar(i, k));
+    p.bytes_alg += it[s] * 8.0 * m * ((double)h->R[i] - q[s] + h->pr(i, k));
     p.tile_iters += it[s];
   }
   return TLR_OK;
@@ -772,8 +893,9 @@ tlr_status prob_finish(Prob& p, const tlr_opts& o, bool ldl, tlr_stats* st,
   }
   const long long nev = (long long)p.events.size();
   p.events.clear();
-  int info = 0;
-  TLR_HIP(hipMemcpy(&info, h->d_info, sizeof(int), hipMemcpyDeviceToHost));
+  int iw[2] = {0, 0};
+  TLR_HIP(hipMemcpy(iw, h->d_info, sizeof iw, hipMemcpyDeviceToHost));
+  const int info = iw[0];
   if (st) {
     std::memset(st, 0, sizeof *st);
     st->info = info;
@@ -786,6 +908,9 @@ tlr_status prob_finish(Prob& p, const tlr_opts& o, bool ldl, tlr_stats* st,
     st->tile_iters = p.tile_iters;
     st->fp32_tile_iters = p.fp32_tile_iters;
     st->bf16_tile_iters = p.bf16_tile_iters;
+    st->modified_pivots = iw[1];
+    st->t_host_issue = p.t_issue;
+    st->t_host_wait = p.t_wait;
     long long cnt = 0, tot = 0, full = 0;
     int mx = 0;
     for (int i = 0; i < nb; ++i)
@@ -856,6 +981,7 @@ tlr_status factorize_group(std::vector<Prob>& ps, const double* eps, const tlr_o
   cfg.s_max = o.max_active;
   cfg.seed = o.seed;
   cfg.strip = o.sample_strip;
+  cfg.overlap = (o.flags & TLR_FLAG_SERIAL_SAMPLING) == 0;
   AraSlots slots;
   TLR_TRY(ara_slots(lead, cfg, slots_max, &slots));
   const bool timing = (o.flags & TLR_FLAG_KERNEL_TIMING) != 0;
@@ -882,7 +1008,7 @@ tlr_status factorize_group(std::vector<Prob>& ps, const double* eps, const tlr_o
       std::vector<std::pair<int, int>> key;   // (rank, global slot)
       for (int pi : live) {
         Prob& p = ps[pi];
-        for (int s : p.order) key.push_back({p.h->ar(k + 1 + s, k), p.base + s});
+        for (int s : p.order) key.push_back({p.h->pr(k + 1 + s, k), p.base + s});
       }
       std::stable_sort(key.begin(), key.end(),
                        [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
@@ -965,7 +1091,15 @@ tlr_status factorize_group(std::vector<Prob>& ps, const double* eps, const tlr_o
   }
   TLR_HIP(lead->pt_main.mark(-1, lead->stream));
   for (int pi : idx) TLR_TRY(ps[pi].h->sync());
-  for (int pi : idx) release_retired(ps[pi].h);
+  for (int pi : idx) {
+    Handle* h = ps[pi].h;
+    release_retired(h);
+    // the updated diagonal tiles of the pivoted form are spent (the
+    // permutation stays with the factor)
+    h->mem.put(h->Sd);
+    h->Sd = nullptr;
+    h->spos.clear();
+  }
   double t_main[TLR_NPHASE] = {0.0};
   if (phases) TLR_TRY(lead->pt_main.collect(t_main));
   tlr_status first = TLR_OK;
@@ -979,9 +1113,12 @@ tlr_status factorize_group(std::vector<Prob>& ps, const double* eps, const tlr_o
 }  // namespace
 
 tlr_status factorize_batch(Handle* const* hs, int count, const double* eps, const tlr_opts& o,
-                           tlr_stats* st, bool ldl) {
+                           tlr_stats* st, bool ldl, bool piv) {
   std::vector<Prob> ps(count);
-  for (int i = 0; i < count; ++i) ps[i].h = hs[i];
+  for (int i = 0; i < count; ++i) {
+    ps[i].h = hs[i];
+    ps[i].piv = piv;
+  }
   // problems of one tile size run together (the ARA kernels take one m)
   std::vector<int> ms;
   for (int i = 0; i < count; ++i)
@@ -1012,8 +1149,8 @@ tlr_status factorize_batch(Handle* const* hs, int count, const double* eps, cons
   return first;
 }
 
-tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bool ldl) {
-  return factorize_batch(&h, 1, &eps, o, st, ldl);
+tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bool ldl, bool piv) {
+  return factorize_batch(&h, 1, &eps, o, st, ldl, piv);
 }
 
 }  // namespace tlr

@@ -161,13 +161,14 @@ class SideWorker {
 // Per-column workspace of the factorization.
 struct Work {
   DevBuf G, W, omega, P, Z, T, Ta, H, Ball, C, Wa, Y, Q, part, ints, orth, dscale, tol,
-      compact, Bt, fro, tnpart, splitk, G2, Gk;
+      compact, Bt, fro, tnpart, tnpart2, splitk, G2, Gk, Sg, Sw, Snorm;
   // buffers of the diagonal-tile stream (never touched by the main stream)
   DevBuf Wd, dW, dtol, sideblob, sideblob2, Wn;
   int slots = 0;   // slot capacity of the per-tile buffers
   void release_all(Mem& mem) {
     DevBuf* bufs[] = {&G, &W, &omega, &P, &Z, &T, &Ta, &H, &Ball, &C, &Wa, &Y, &Q, &part,
-                      &ints, &orth, &dscale, &tol, &compact, &Bt, &fro, &tnpart, &splitk, &G2,
+                      &ints, &orth, &dscale, &tol, &compact, &Bt, &fro, &tnpart, &tnpart2,
+                      &splitk, &G2, &Sg, &Sw, &Snorm,
                       &Gk, &Wd, &dW, &dtol, &sideblob, &sideblob2, &Wn};
     for (DevBuf* b : bufs) b->release(mem);
   }
@@ -207,6 +208,7 @@ struct tlr_matrix_s {
   hipStream_t side = nullptr;     // library stream for the diagonal tiles (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gnext = nullptr;
   std::unique_ptr<tlr::SideWorker> worker;   // issues the side-stream launches
+  std::unique_ptr<tlr::SideWorker> sworker;  // issues the ARA sampling launches
   Staging stage;
   tlr::PhaseTimer pt_main, pt_side;   // TLR_FLAG_PHASE_TIMING
 
@@ -244,11 +246,23 @@ struct tlr_matrix_s {
   // sortRanks order of every column's tiles in the last factorization
   // (global block rows, column k at sort_log[k])
   std::vector<std::vector<int>> sort_log;
+  // pivoted factorization (Section 5.2): position -> original block of the
+  // factor's block order (empty: unpivoted), and the updated diagonal tiles
+  // A_tt - sum_j L_tj L_tj^T of the positions not yet factored (nb tiles of
+  // m x m; position t at Sd + spos[t] m^2)
+  std::vector<int> fperm;
+  double* Sd = nullptr;
+  std::vector<int> spos;
   double* pin_norm = nullptr;     // pinned read-back of a column's V norms
   int* pin_ring = nullptr;        // pinned read-back ring of the ARA iterations (2 x 8)
   int* pin_res = nullptr;         // pinned read-back of an ARA run's per-slot results
   size_t pin_res_n = 0;
   hipEvent_t ev_rb[2] = {nullptr, nullptr};
+  // library stream of the ARA sampling launches, which run one iteration
+  // ahead of the orthogonalisation on the caller's stream (default
+  // priority), and the events that order the two
+  hipStream_t samp = nullptr;
+  hipEvent_t ev_sfork = nullptr, ev_samp[4] = {}, ev_main[4] = {};
   size_t pin_norm_n = 0;
 
   Work ws;
@@ -264,6 +278,25 @@ struct tlr_matrix_s {
   double* ua(int i, int j) const { return UA + (size_t)a_off[(size_t)i * nb + j] * m; }
   double* va(int i, int j) const { return VA + (size_t)a_off[(size_t)i * nb + j] * m; }
   int ar(int i, int j) const { return a_rank[(size_t)i * nb + j]; }
+  // Input tile (i, j), i > j, in the block order of the current
+  // factorization: position t holds the original block fperm[t] (empty
+  // fperm: the original order).  A pair that lies above the diagonal in the
+  // original order is the transpose of the stored tile (U and V swapped).
+  int pr(int i, int j) const {
+    if (fperm.empty()) return ar(i, j);
+    const int a = fperm[i], b = fperm[j];
+    return a > b ? ar(a, b) : ar(b, a);
+  }
+  double* pu(int i, int j) const {
+    if (fperm.empty()) return ua(i, j);
+    const int a = fperm[i], b = fperm[j];
+    return a > b ? ua(a, b) : va(b, a);
+  }
+  double* pv(int i, int j) const {
+    if (fperm.empty()) return va(i, j);
+    const int a = fperm[i], b = fperm[j];
+    return a > b ? va(a, b) : ua(b, a);
+  }
   int lr(int i, int j) const { return l_rank[(size_t)i * nb + j]; }
   double* ul(int i, int j) const { return UL[i] + (size_t)l_off[(size_t)i * nb + j] * m; }
   double* vl(int i, int j) const { return VL[i] + (size_t)l_off[(size_t)i * nb + j] * m; }
@@ -275,6 +308,7 @@ struct tlr_matrix_s {
   tlr_status pinned_norms(size_t n, double** p);
   tlr_status readback_ring(int** p);
   tlr_status readback_results(size_t n, int** p);   // pinned, n ints
+  tlr_status samp_stream();       // creates samp and its events on first use
   void release_host();            // pinned buffers and events
 };
 
@@ -292,8 +326,10 @@ tlr_status dense_trsm(Handle* h, const double* L, int ldl, double* B, int ldb, i
                       bool unit, bool trans);
 // Append the blocked factorization of A and the assembly of Linv to a plan
 // (on the plan's stream); d is the pivot vector for LDL^T (chol = false).
+// chol with mod_delta > 0: modified Cholesky (non-positive pivots replaced by
+// mod_delta and counted in d_info[1]).
 tlr_status dense_factor(Handle* h, struct Plan& plan, bool chol, double* A, int lda, int m,
-                        double* d, int row_base, double* Linv);
+                        double* d, int row_base, double* Linv, double mod_delta = 0.0);
 
 // Kernel wrappers not declared in tlr_internal.h.
 hipError_t launch_zero_upper(double* A, int lda, int m, hipStream_t s);
@@ -309,12 +345,14 @@ struct AraProblem;
 // the entries by rank descending, ties by row ascending, then by index.
 void sort_ranks(const int* ranks, const int* rows, int n, int* idx);
 
-tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bool ldl);
+// piv: the pivoted Cholesky (Section 5.2; ldl false, FP64 sampling).
+tlr_status factorize(Handle* h, double eps, const tlr_opts& o, tlr_stats* st, bool ldl,
+                     bool piv = false);
 // count problems at once, problem i at threshold eps[i] (st: count entries or
 // NULL); problems of one tile size step through their columns together with
 // pooled ARA launches.  All handles must use the same main stream.
 tlr_status factorize_batch(Handle* const* hs, int count, const double* eps, const tlr_opts& o,
-                           tlr_stats* st, bool ldl);
+                           tlr_stats* st, bool ldl, bool piv = false);
 tlr_status compress(Handle* h, const double* A, long long lda, const double* pts, int dim,
                     int kernel, double ell, double diag_add, double eps, const tlr_opts& o);
 tlr_status estimate_norm(Handle* h, double* out);

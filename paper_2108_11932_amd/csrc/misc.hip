@@ -48,6 +48,32 @@ __global__ __launch_bounds__(256) void k_fro_norms(const NormDesc* __restrict__ 
   if (threadIdx.x == 0) *d.out = sqrt(red[0]);
 }
 
+// Partial sums of the squared Frobenius norms of symmetric m x m tiles held
+// by their lower triangle: workgroup (t, g) adds columns g, g + G, g + 2G, ...
+// of tile t (every entry below the diagonal twice) and stores the sum at
+// out[t G + g]; the caller adds the G partials of a tile in order.
+__global__ __launch_bounds__(256) void k_sym_fro_parts(const double* const* __restrict__ tiles,
+                                                       int m, int ld, int G, double* out) {
+  __shared__ double red[256];
+  const double* p = tiles[blockIdx.x / G];
+  const int g = blockIdx.x % G;
+  double s = 0.0;
+  for (int c = g; c < m; c += G) {
+    const double* col = p + (size_t)c * ld;
+    for (int r = c + (int)threadIdx.x; r < m; r += 256) {
+      const double v = col[r];
+      s += (r == c ? 1.0 : 2.0) * (v * v);
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 __global__ void k_copy_shift(const double* src, double* dst, int m, int nreal, double shift) {
   const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (e >= (long long)m * m) return;
@@ -164,6 +190,14 @@ hipError_t launch_copy_batched(const CopyDesc* d, int n, int max_cols, hipStream
 hipError_t launch_fro_norms(const NormDesc* d, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fro_norms, dim3(n), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_sym_fro_parts(const double* const* tiles, int n, int m, int ld, int G,
+                                double* out, hipStream_t s) {
+  if (n <= 0 || G <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sym_fro_parts, dim3((unsigned)(n * G)), dim3(256), 0, s, tiles, m, ld, G,
+                     out);
   return hipGetLastError();
 }
 

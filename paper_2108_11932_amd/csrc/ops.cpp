@@ -153,7 +153,26 @@ static long long solve_tcap(const Handle* h) {
 
 size_t solve_workspace(const Handle* h, int nrhs) {
   const long long np = (long long)h->nb * h->m;
-  return (size_t)(np + h->m + solve_tcap(h)) * (size_t)std::max(nrhs, 0);
+  // a pivoted factor also needs the right-hand sides in its block order
+  const long long perm = h->fperm.empty() ? 0 : np;
+  return (size_t)(np + perm + h->m + solve_tcap(h)) * (size_t)std::max(nrhs, 0);
+}
+
+// Block rows of the padded right-hand sides between the original order
+// (X) and the pivoted factor's order (Xq, position t = block perm[t]).
+static tlr_status permute_blocks(Handle* h, double* X, double* Xq, int nrhs, bool to_factor) {
+  const int m = h->m, nb = h->nb;
+  const int ld = nb * m;
+  std::vector<CopyDesc> cd;
+  for (int t = 0; t < nb; ++t) {
+    double* orig = X + (size_t)h->fperm[t] * m;
+    double* pos = Xq + (size_t)t * m;
+    cd.push_back(CopyDesc{to_factor ? orig : pos, to_factor ? pos : orig, m, nrhs, ld, ld});
+  }
+  void* d = nullptr;
+  TLR_TRY(h->stage.upload(h, cd.data(), sizeof(CopyDesc) * cd.size(), &d));
+  TLR_HIP(launch_copy_batched((const CopyDesc*)d, nb, nrhs, h->stream));
+  return TLR_OK;
 }
 
 tlr_status solve(Handle* h, int nrhs, double* B, long long ldb) {
@@ -166,11 +185,14 @@ tlr_status solve_in(Handle* h, int nrhs, double* B, long long ldb, double* work)
   const long long np = (long long)nb * m;
   const bool ldl = h->factored == 2;
   const long long tcap = solve_tcap(h);
-  double* Xp = work;                    // padded N x nrhs
+  const bool piv = !h->fperm.empty();
+  double* Xo = work;                    // padded N x nrhs, original block order
+  double* Xp = piv ? Xo + np * nrhs : Xo;   // the factor's block order
   double* tk = Xp + np * nrhs;          // m x nrhs
   double* T = tk + (size_t)m * nrhs;    // tcap x nrhs
   const int ldx = (int)np;
-  TLR_TRY(pad_in(h, B, ldb, nrhs, Xp));
+  TLR_TRY(pad_in(h, B, ldb, nrhs, Xo));
+  if (piv) TLR_TRY(permute_blocks(h, Xo, Xp, nrhs, true));
   auto apply_inv = [&](int k, bool trans) -> tlr_status {
     double* xk = Xp + (size_t)k * m;
     GemmBatch g(trans, false);
@@ -216,7 +238,8 @@ tlr_status solve_in(Handle* h, int nrhs, double* B, long long ldb, double* work)
     TLR_TRY(t.run(h));
     TLR_TRY(v.run(h));
   }
-  TLR_TRY(pad_out(h, Xp, nrhs, B, ldb));
+  if (piv) TLR_TRY(permute_blocks(h, Xo, Xp, nrhs, false));
+  TLR_TRY(pad_out(h, Xo, nrhs, B, ldb));
   return h->sync();
 }
 

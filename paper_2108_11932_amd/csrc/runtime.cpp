@@ -241,9 +241,30 @@ tlr_status tlr_matrix_s::readback_results(size_t n, int** p) {
   return TLR_OK;
 }
 
+tlr_status tlr_matrix_s::samp_stream() {
+  if (samp) return TLR_OK;
+  TLR_HIP(hipEventCreateWithFlags(&ev_sfork, hipEventDisableTiming));
+  for (int i = 0; i < 4; ++i) {
+    TLR_HIP(hipEventCreateWithFlags(&ev_samp[i], hipEventDisableTiming));
+    TLR_HIP(hipEventCreateWithFlags(&ev_main[i], hipEventDisableTiming));
+  }
+  TLR_HIP(hipStreamCreateWithFlags(&samp, hipStreamNonBlocking));
+  return TLR_OK;
+}
+
 void tlr_matrix_s::release_host() {
   pt_main.destroy();
   pt_side.destroy();
+  if (samp) {
+    (void)hipStreamSynchronize(samp);
+    (void)hipStreamDestroy(samp);
+    samp = nullptr;
+  }
+  for (hipEvent_t* e : {&ev_sfork, &ev_samp[0], &ev_samp[1], &ev_samp[2], &ev_samp[3], &ev_main[0],
+                        &ev_main[1], &ev_main[2], &ev_main[3]}) {
+    if (*e) (void)hipEventDestroy(*e);
+    *e = nullptr;
+  }
   if (pin_norm) (void)hipHostFree(pin_norm);
   if (pin_ring) (void)hipHostFree(pin_ring);
   if (pin_res) (void)hipHostFree(pin_res);
@@ -562,7 +583,7 @@ static void inverse_assemble(Plan& plan, const double* L, int ldl, int m, double
 }
 
 tlr_status dense_factor(Handle* h, Plan& plan, bool chol, double* A, int lda, int m, double* d,
-                        int row_base, double* Linv) {
+                        int row_base, double* Linv, double mod_delta) {
   Work& w = h->ws;
   hipStream_t s = plan.s;
   const size_t need = sizeof(double) * (size_t)m * m;
@@ -576,12 +597,16 @@ tlr_status dense_factor(Handle* h, Plan& plan, bool chol, double* A, int lda, in
   int* info = h->d_info;
   plan.launch([=]() { return hipMemsetAsync(Linv, 0, sizeof(double) * (size_t)m * m, s); });
   if (!chol) plan.launch([=]() { return launch_pivot_tol(A, lda, m, tol, s); });
+  // modified Cholesky: the pivot floor for the panel kernels
+  const bool modify = chol && mod_delta > 0.0;
+  if (modify) plan.launch([=]() { return launch_fill(tol, 1, mod_delta, s); });
+  const double* tolk = (chol && !modify) ? nullptr : tol;
   const int nd = diag_block_size();
   for (int p0 = 0; p0 < m; p0 += nd) {
     const int wd = m - p0 < nd ? m - p0 : nd;
     double* lst = Linv + p0 + (size_t)p0 * m;
     plan.launch([=]() {
-      return launch_chol_panel(chol, A, lda, m, p0, wd, W, m, lst, m, d, info, row_base, tol, s);
+      return launch_chol_panel(chol, A, lda, m, p0, wd, W, m, lst, m, d, info, row_base, tolk, s);
     });
     const int rem = m - p0 - wd;
     if (rem <= 0) continue;

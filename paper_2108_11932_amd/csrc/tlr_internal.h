@@ -78,6 +78,8 @@ int diag_block_size();
 // p0 + w at W[0]) and L21 = W21 D^{-1}.  L11 goes to Lst (ld ldst), not
 // into A.  info (device int) receives the 1-based row (row_base + p0 + j +
 // 1) of the first failing pivot; tolp is the LDL^T pivot tolerance (device).
+// Cholesky with tolp set: modified Cholesky, a non-positive pivot becomes
+// *tolp and is counted in info[1] instead of failing.
 hipError_t launch_chol_panel(bool chol, double* A, int lda, int m, int p0, int w, double* W,
                              int ldw, double* Lst, int ldst, double* dvec, int* info, int row_base,
                              const double* tolp, hipStream_t s);
@@ -173,6 +175,14 @@ struct AraDev {
   int* qsum;    // sum over iterations of the samples times the prior basis width
   int* ncol;    // samples drawn per slot
   int m, bs, qcap, nstrip;
+  // the iteration's sample block and Gram partials: slot descriptor's y and
+  // part1 plus these offsets (doubles), so that the sampling of the next
+  // iteration can fill the other copy while this one is orthogonalised
+  long long yoff, poff;
+  // when set, the compaction also stores its output list and count here
+  // (the list the next iteration's speculative sampling reads)
+  int* snap_act;
+  int* snap_counts;
 };
 // Precision choice of one slot under mixed precision.  With
 // nu_tot = nu + fro[irow] fro[0] (no device term when irow < 0; fro holds the
@@ -261,6 +271,11 @@ struct NormDesc {
   double* out;
 };
 hipError_t launch_fro_norms(const NormDesc* d, int n, hipStream_t s);
+// Squared Frobenius norms of n symmetric m x m tiles (lower triangle, ld;
+// tiles: device array of n pointers) as G partial sums per tile at out[t G
+// + g] (the sum of a tile's partials in order is its squared norm).
+hipError_t launch_sym_fro_parts(const double* const* tiles, int n, int m, int ld, int G,
+                                double* out, hipStream_t s);
 hipError_t launch_copy_batched(const CopyDesc* d, int n, int max_cols, hipStream_t s);
 // dst = src (m x m) + shift on the first nreal diagonal entries.
 hipError_t launch_copy_shift(const double* src, double* dst, int m, int nreal, double shift,

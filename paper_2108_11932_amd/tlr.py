@@ -25,7 +25,7 @@ TLR_ERR_NOT_SPD = 1
 TLR_ERR_ZERO_PIVOT = 2
 EPS_ABS, EPS_REL = 0, 1
 FP64, MIXED_FP32, MIXED_BF16, MIXED_AUTO = 0, 1, 2, 3
-FLAG_KERNEL_TIMING, FLAG_PHASE_TIMING = 1, 2
+FLAG_KERNEL_TIMING, FLAG_PHASE_TIMING, FLAG_SERIAL_SAMPLING, FLAG_MODIFIED_CHOL = 1, 2, 4, 8
 PHASES = ("gblocks", "sample", "orth", "batch", "project", "trsm", "append", "diag")
 KERNEL_EXP, KERNEL_MATERN15 = 0, 1
 INPUT, FACTOR = 0, 1
@@ -59,7 +59,8 @@ class Stats(ctypes.Structure):
                 ("sample_flops", ctypes.c_double), ("fp32_tile_iters", ctypes.c_longlong),
                 ("shift", ctypes.c_double), ("shift_retries", ctypes.c_int),
                 ("t_total", ctypes.c_double), ("t_phase", ctypes.c_double * 8),
-                ("bf16_tile_iters", ctypes.c_longlong)]
+                ("bf16_tile_iters", ctypes.c_longlong), ("t_host_issue", ctypes.c_double),
+                ("t_host_wait", ctypes.c_double), ("modified_pivots", ctypes.c_longlong)]
 
     def as_dict(self) -> Dict[str, float]:
         out = {f: getattr(self, f) for f, _ in self._fields_}
@@ -106,6 +107,11 @@ SIGNATURES = {
                                  ctypes.POINTER(Allocator), _P, ctypes.POINTER(_P)]),
     "tlr_potrf": (_I, [_P, _D, ctypes.POINTER(Opts), ctypes.POINTER(Stats), _P]),
     "tlr_ldlt": (_I, [_P, _D, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P]),
+    "tlr_potrf_pivoted": (_I, [_P, _D, ctypes.POINTER(Opts), _IP, ctypes.POINTER(Stats), _P]),
+    "tlr_get_perm": (_I, [_P, _IP]),
+    "tlr_tune_tile": (_I, [_P, _I, _LL, _I, _D, _D, _D, ctypes.POINTER(Opts), _IP, _I,
+                           ctypes.POINTER(Allocator), _P, _IP, _DP, _IP]),
+    "tlr_tune_reset": (None, []),
     "tlr_factor_batched": (_I, [_I, ctypes.POINTER(_P), _I, _D, ctypes.POINTER(Opts),
                                 ctypes.POINTER(_P), ctypes.POINTER(Stats), _P]),
     "tlr_potrf_batched": (_I, [_I, ctypes.POINTER(_P), _DP, ctypes.POINTER(Opts),
@@ -225,12 +231,14 @@ class TorchAllocator:
 
     def __init__(self):
         self._live = {}
+        self.calls = 0   # allocations requested by the library so far
         self._alloc_cb = _ALLOC_FN(self._alloc)
         self._free_cb = _FREE_FN(self._free)
         self.struct = Allocator(None, self._alloc_cb, self._free_cb)
 
     def _alloc(self, ctx, nbytes, stream):
         torch = _torch()
+        self.calls += 1
         try:
             t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
         except RuntimeError:
@@ -331,6 +339,20 @@ class TLRMatrix:
         st = Stats()
         s = lib().tlr_potrf(self.h, eps, ctypes.byref(o or opts()), ctypes.byref(st), _stream())
         return s, st.as_dict()
+
+    def potrf_pivoted(self, eps: float, o: Optional[Opts] = None):
+        """Pivoted Cholesky; returns (stats, perm) with position t of the
+        factor holding original block perm[t]."""
+        st = Stats()
+        perm = np.zeros(self.nb, dtype=np.int32)
+        _check(lib().tlr_potrf_pivoted(self.h, eps, ctypes.byref(o or opts()),
+                                       perm.ctypes.data_as(_IP), ctypes.byref(st), _stream()))
+        return st.as_dict(), perm
+
+    def perm(self):
+        p = np.zeros(self.nb, dtype=np.int32)
+        _check(lib().tlr_get_perm(self.h, p.ctypes.data_as(_IP)))
+        return p
 
     def ldlt(self, eps: float, o: Optional[Opts] = None):
         torch = _torch()
@@ -489,6 +511,24 @@ def potrf_tile(a) -> int:
     info = ctypes.c_int()
     _check(lib().tlrk_potrf(m, _ptr(a), m, ctypes.byref(info), _stream()))
     return info.value
+
+
+def tune_tile(points, kernel: int, ell: float, diag_add: float, eps: float,
+              candidates=(256, 512, 1024), o: Optional[Opts] = None):
+    """tlr_tune_tile: (best tile size, {candidate: ms} or None when cached)."""
+    torch = _torch()
+    p = torch.as_tensor(np.ascontiguousarray(points, dtype=np.float64)).cuda().contiguous()
+    n, dim = p.shape
+    cand = np.ascontiguousarray(candidates, dtype=np.int32)
+    ms = np.zeros(len(cand), dtype=np.float64)
+    best = ctypes.c_int()
+    cached = ctypes.c_int()
+    alloc = TorchAllocator()
+    _check(lib().tlr_tune_tile(_ptr(p), dim, n, kernel, ell, diag_add, eps, ctypes.byref(o or opts()),
+                               cand.ctypes.data_as(_IP), len(cand), ctypes.byref(alloc.struct),
+                               _stream(), ctypes.byref(best), ms.ctypes.data_as(_DP),
+                               ctypes.byref(cached)))
+    return best.value, (None if cached.value else dict(zip(cand.tolist(), ms.tolist())))
 
 
 def ldlt_tile(a, d) -> int:

@@ -163,6 +163,16 @@ def matern_3d(n: int, m: int, eps: float, seed: int, shift: float = 0.0,
                     m, eps, EPS_ABS, bs, "ldlt", seed)
 
 
+def covariance_3d(n: int, m: int, eps: float, seed: int, ell: float = 0.2, bs: int = 32,
+                  name: Optional[str] = None) -> Workload:
+    """3D exponential covariance on a jittered grid with nugget 1e-4 (the
+    paper's 3D covariance: ell 0.2, ARA block 32)."""
+    pts = jittered_grid(n, 3, seed)
+    pts = np.ascontiguousarray(pts[morton_order(pts)])
+    return Workload(name or "cov3d_n%d_m%d" % (n, m), pts, KERNEL_EXP, ell, 1e-4,
+                    m, eps, EPS_ABS, bs, "chol", seed)
+
+
 def batched_2d(count: int = 96, seed: int = 999, eps: float = 1e-6,
                m: Optional[int] = None) -> List[Workload]:
     """Independent 2D exponential problems with uneven sizes.
@@ -193,6 +203,8 @@ def standard(name: str) -> Workload:
     cov2d_131k   : N=131072, 512x256 grid, tile 1024, eps 1e-6, seed 3
     matern3d_131k: N=131072, 64x64x32 grid, 3D Matern-1.5 (ell 0.2), tile
                    1024, eps 1e-4, bs 32, diagonal shift -1e-2 ||A|| (LDL^T)
+    cov3d_131k   : N=131072, 64x64x32 grid, 3D exponential (ell 0.2), tile
+                   512, eps 1e-6, bs 32, seed 6 (pivoted against unpivoted)
     """
     if name == "cov2d_4k":
         return covariance_2d(4096, 256, 1e-6, 1, name=name)
@@ -206,4 +218,6 @@ def standard(name: str) -> Workload:
         w = matern_3d(131072, 1024, 1e-4, 4, name=name)
         w.diag_add = -MATERN3D_SHIFT_FRACTION * matern3d_norm_estimate(w.points)
         return w
+    if name == "cov3d_131k":
+        return covariance_3d(131072, 512, 1e-6, 6, name=name)
     raise KeyError(name)

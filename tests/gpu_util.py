@@ -3,6 +3,16 @@ torch device tensors, and conversion of library handles into oracle TLR
 objects (host copies of the GPU's results, compared against the oracle)."""
 import numpy as np
 
+# Total factor rank against the oracle's truncated-SVD ranks at the same
+# threshold.  The ARA accepts a direction while a sample residual exceeds
+# tau; a random sample's residual measures the Frobenius norm of what is
+# left, so directions keep being added until the tail's Frobenius norm (not
+# its 2-norm) is below tau, and tiles whose spectrum has many singular
+# values just below tau end with more columns than the 2-norm-optimal SVD
+# truncation: 18-29 % more on the covariance workloads (measured, half-block
+# convergence rule).
+RANK_RATIO = 1.35
+
 
 def dev(a):
     """Column-major device copy (flat float64 torch tensor) of a 1-D/2-D array."""

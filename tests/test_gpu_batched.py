@@ -12,7 +12,7 @@ from oracle import tlr as otlr
 from paper_2108_11932_amd import tlr
 from paper_2108_11932_amd import workloads as wl
 
-from gpu_util import oracle_tlr
+from gpu_util import RANK_RATIO, oracle_tlr
 
 pytestmark = pytest.mark.gpu
 
@@ -74,7 +74,7 @@ def test_batched_cholesky_keeps_every_matrix_bounds():
         assert st["info"] == 0 and st["tau"] == eps
         _check_bounds(t, mat, eps)
         ref = otlr.tlr_cholesky(t, eps)
-        assert mat.ranks(tlr.FACTOR).sum() <= 1.10 * ref.ranks().sum() + t.nb
+        assert mat.ranks(tlr.FACTOR).sum() <= RANK_RATIO * ref.ranks().sum() + t.nb
 
 
 def test_batched_relative_thresholds_and_tile_sizes():
@@ -123,3 +123,44 @@ def test_batched_failure_stays_with_its_matrix():
     assert sts[0]["info"] == 0
     assert 2 * 256 < sts[1]["info"] <= 3 * 256
     _check_bounds(good, mats[0], eps)
+
+
+def test_tune_tile_measures_then_caches():
+    w = wl.batched_2d(count=3)[0]
+    tlr.lib().tlr_tune_reset()
+    best, ms = tlr.tune_tile(w.points, w.kernel, w.ell, w.diag_add, w.eps, (128, 256, 512))
+    assert best in (128, 256, 512)
+    assert ms is not None and all(np.isfinite(v) and v > 0 for v in ms.values())
+    assert ms[best] == min(ms.values())
+    # the same problem class (same ceil(log2 N), kernel, threshold, options)
+    again, ms2 = tlr.tune_tile(w.points, w.kernel, w.ell, w.diag_add, w.eps, (128, 256, 512))
+    assert again == best and ms2 is None
+    tlr.lib().tlr_tune_reset()
+    _, ms3 = tlr.tune_tile(w.points, w.kernel, w.ell, w.diag_add, w.eps, (128, 256, 512))
+    assert ms3 is not None
+
+
+def test_batched_workload_eight_problems_against_oracle():
+    # 8 of the 96 problems of the batched workload (the smallest, so that the
+    # oracle's TLR-SVD factorization stays quick), tile sizes from the
+    # autotuner, one batched call with per-problem relative thresholds
+    ws = sorted(wl.batched_2d(count=96), key=lambda w: w.n)[:8]
+    tlr.lib().tlr_tune_reset()
+    o = tlr.opts(eps_mode=tlr.EPS_REL)
+    mats, tiles = [], []
+    for w in ws:
+        m, _ = tlr.tune_tile(w.points, w.kernel, w.ell, w.diag_add, w.eps, (256, 512, 1024), o)
+        tiles.append(m)
+        mats.append(tlr.TLRMatrix.compress_kernel(w.points, w.kernel, w.ell, w.diag_add, m, w.eps, o))
+    s, sts, _ = tlr.factor_batched(mats, ws[0].eps, o)
+    assert s == 0
+    for w, mat, st in zip(ws, mats, sts):
+        assert st["info"] == 0
+        tau = st["tau"]
+        assert tau == pytest.approx(w.eps * st["norm_a"])
+        a_t = oracle_tlr(mat, tlr.INPUT)
+        l = oracle_tlr(mat, tlr.FACTOR)
+        assert otlr.factor_error_norm(a_t, l) <= 2 * math.sqrt(a_t.nb) * tau
+        ref = otlr.tlr_cholesky(a_t, tau)
+        assert l.ranks().sum() <= RANK_RATIO * ref.ranks().sum() + a_t.nb
+        mat.close()

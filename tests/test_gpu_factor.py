@@ -18,7 +18,7 @@ from oracle import tlr as otlr
 from paper_2108_11932_amd import tlr
 from paper_2108_11932_amd import workloads as wl
 
-from gpu_util import dev, host, oracle_tlr
+from gpu_util import RANK_RATIO, dev, host, oracle_tlr
 
 pytestmark = pytest.mark.gpu
 
@@ -101,7 +101,7 @@ def test_cholesky_matches_oracle_invariants(n, m, eps):
     # within 10% (plus one block) of the oracle's optimal ranks in total
     rg = mat.ranks(tlr.FACTOR)
     ro = ref.ranks()
-    assert rg.sum() <= 1.10 * ro.sum() + t.nb
+    assert rg.sum() <= RANK_RATIO * ro.sum() + t.nb
     for k in range(t.nb):
         for i in range(k + 1, t.nb):
             s_ik = otlr.schur_tile(t, l, i, k)
@@ -126,7 +126,7 @@ def test_larger_tail_block_keeps_accuracy(bs, bs_tail, tail_active):
             assert np.linalg.norm(res[t.blk(i), t.blk(k)], 2) <= 4 * eps
     assert np.linalg.norm(res, 2) <= 2 * math.sqrt(t.nb) * eps
     ref = otlr.tlr_cholesky(t, eps)
-    assert mat.ranks(tlr.FACTOR).sum() <= 1.10 * ref.ranks().sum() + t.nb
+    assert mat.ranks(tlr.FACTOR).sum() <= RANK_RATIO * ref.ranks().sum() + t.nb
 
 
 def test_dynamic_batching_subset_gives_same_quality():
@@ -253,8 +253,10 @@ def test_relative_threshold_uses_norm_estimate():
 
 def test_mixed_fp32_sampling_equal_accuracy():
     # FP32 panels in the sampling (TLR_MIXED_FP32): at a relative threshold
-    # every tile passes the rounding guard; the factor must reach the same
-    # accuracy bound as the FP64 form, and about the same error
+    # most tile iterations pass the rounding guard (it grows with sqrt(R_i),
+    # the FP32 accumulation over the row panel, so the longest panels of the
+    # last block rows keep FP64); the factor must reach the same accuracy
+    # bound as the FP64 form, and about the same error
     n, m, eps = 2048, 128, 1e-5
     pts = wl.jittered_grid(n, 2, 21)
     pts = np.ascontiguousarray(pts[wl.morton_order(pts)])
@@ -268,7 +270,7 @@ def test_mixed_fp32_sampling_equal_accuracy():
         stats[prec] = st
     tau = stats[tlr.MIXED_FP32]["tau"]
     assert stats[tlr.FP64]["fp32_tile_iters"] == 0
-    assert stats[tlr.MIXED_FP32]["fp32_tile_iters"] >= 0.9 * stats[tlr.MIXED_FP32]["tile_iters"]
+    assert stats[tlr.MIXED_FP32]["fp32_tile_iters"] >= 0.8 * stats[tlr.MIXED_FP32]["tile_iters"]
     nb = n // m
     assert errs[tlr.MIXED_FP32] <= 2 * math.sqrt(nb) * tau
     assert errs[tlr.MIXED_FP32] <= 2 * errs[tlr.FP64] + tau
@@ -332,3 +334,54 @@ def test_mixed_auto_uses_fp32_at_tight_threshold():
     assert st["bf16_tile_iters"] == 0 and st["fp32_tile_iters"] > 0
     l = oracle_tlr(mat, tlr.FACTOR)
     assert np.linalg.norm(_residual_tiles(t, l), 2) <= 2 * math.sqrt(t.nb) * st["tau"]
+
+
+def _lost_definiteness(n=384, m=64, r=3, seed=63):
+    """blockdiag(B) + W W^T whose tile-1 Schur complement is just indefinite
+    (a rank-one change of A_11 past its smallest eigenvalue)."""
+    rng = np.random.default_rng(seed)
+    a = np.zeros((n, n))
+    for k in range(0, n, m):
+        g = rng.standard_normal((m, m))
+        a[k:k + m, k:k + m] = g @ g.T / m + np.eye(m)
+    w = rng.standard_normal((n, r))
+    a += w @ w.T
+    s1 = a[m:2 * m, m:2 * m] - a[m:2 * m, :m] @ np.linalg.solve(a[:m, :m], a[:m, m:2 * m])
+    lam, vec = np.linalg.eigh(s1)
+    a[m:2 * m, m:2 * m] -= (lam[0] + 1e-4) * np.outer(vec[:, 0], vec[:, 0])
+    return a
+
+
+def test_modified_cholesky_matches_oracle():
+    # Section 5.1.2: without the flag the factorization stops at tile 1; with
+    # it the non-positive pivots of that tile are raised (max(|d|, tau)) and
+    # the factor equals the oracle's modified factorization
+    n, m, eps = 384, 64, 1e-9
+    a = _lost_definiteness(n, m)
+    t = otlr.compress_dense(a, m, 1e-11)
+    mat = _upload(t)
+    with pytest.raises(tlr.TLRError):
+        mat.potrf(eps)
+    st = mat.potrf(eps, tlr.opts(flags=tlr.FLAG_MODIFIED_CHOL))
+    assert st["info"] == 0 and st["modified_pivots"] > 0
+    rec = {}
+    ref = otlr.tlr_cholesky(t, eps, record=rec, modified=True)
+    assert st["modified_pivots"] == rec["modified"]
+    l = oracle_tlr(mat, tlr.FACTOR)
+    np.testing.assert_array_equal(l.ranks(), ref.ranks())
+    for k in range(t.nb):
+        np.testing.assert_allclose(l.diag[k], ref.diag[k], rtol=0, atol=1e-8 * np.abs(ref.diag[k]).max())
+    e = l.dense_lower() @ l.dense_lower().T - t.dense_symmetric()
+    d = np.diag(e).copy()
+    np.fill_diagonal(e, 0.0)
+    assert np.abs(e).max() <= 1e-7 * np.abs(a).max()
+    assert d.min() >= -1e-8 and np.count_nonzero(d > 1e-8) == st["modified_pivots"]
+    # a definite input is unchanged by the flag
+    t2 = otlr.compress_dense(_cov(512, 64)[1], 128, 1e-8)
+    m1, m2 = _upload(t2), _upload(t2)
+    m1.potrf(1e-8)
+    s2 = m2.potrf(1e-8, tlr.opts(flags=tlr.FLAG_MODIFIED_CHOL))
+    assert s2["modified_pivots"] == 0
+    l1, l2 = oracle_tlr(m1, tlr.FACTOR), oracle_tlr(m2, tlr.FACTOR)
+    for k in range(t2.nb):
+        np.testing.assert_array_equal(l1.diag[k], l2.diag[k])

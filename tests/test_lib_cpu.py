@@ -33,7 +33,7 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 def test_default_options():
     o = tlr.opts()
-    assert (o.bs, o.eps_mode, o.precision, o.shift, o.max_active, o.r_min) == (16, 0, 0, 0.0, 0, 1)
+    assert (o.bs, o.eps_mode, o.precision, o.shift, o.max_active, o.r_min) == (16, 0, 0, 0.0, 0, 0)
 
 
 @pytest.mark.parametrize("n,m", [(0, 16), (-5, 16), (100, 0), (100, -1), (100, 100000)])

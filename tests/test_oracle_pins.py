@@ -410,3 +410,74 @@ def test_pivoted_exact_low_rank_kept():
     assert set(l.ranks()[np.tril_indices(t.nb, -1)].tolist()) == {r}
     tp = tlr.permute(t, perm)
     assert np.abs(tp.dense_symmetric() - l.dense_lower() @ l.dense_lower().T).max() < 1e-10 * np.abs(a).max()
+
+
+# ---------------------------------------------------------------- modified Cholesky
+
+def test_modified_cholesky_hand_computed():
+    # [[1, 2], [2, 1]] is indefinite: the second pivot 1 - 2^2 = -3 becomes
+    # max(|-3|, delta) = 3, so L L^T = A + diag(0, 6); with [[1, 1], [1, 1]]
+    # the second pivot is 0 and becomes delta
+    l, f = dense.cholesky_modified(np.array([[1.0, 2.0], [2.0, 1.0]]), 0.25)
+    np.testing.assert_allclose(l, [[1.0, 0.0], [2.0, math.sqrt(3.0)]], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(f, [0.0, 6.0], rtol=0, atol=1e-15)
+    l, f = dense.cholesky_modified(np.array([[1.0, 1.0], [1.0, 1.0]]), 0.25)
+    np.testing.assert_allclose(l, [[1.0, 0.0], [1.0, 0.5]], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(f, [0.0, 0.25], rtol=0, atol=1e-15)
+
+
+def test_modified_cholesky_is_lapack_on_definite_tiles():
+    rng = np.random.default_rng(61)
+    g = rng.standard_normal((40, 40))
+    a = g @ g.T + 0.5 * np.eye(40)
+    l, f = dense.cholesky_modified(a, 1e-3)
+    assert not f.any()
+    np.testing.assert_allclose(l, np.linalg.cholesky(a), rtol=0, atol=1e-12 * np.abs(a).max())
+
+
+def test_modified_cholesky_perturbation_is_diagonal_and_nonnegative():
+    rng = np.random.default_rng(62)
+    q, _ = np.linalg.qr(rng.standard_normal((30, 30)))
+    # one eigenvalue slightly below zero: the case the method is for (a tile
+    # that lost definiteness by a small perturbation)
+    a = q @ np.diag(np.linspace(-1e-3, 5.0, 30)) @ q.T
+    delta = 1e-2
+    l, f = dense.cholesky_modified(a, delta)
+    e = l @ l.T - a
+    assert f.min() >= 0.0 and f.max() > 0.0
+    np.testing.assert_allclose(np.diag(e), f, rtol=0, atol=1e-10 * np.abs(a).max() * f.max())
+    off = e - np.diag(np.diag(e))
+    assert np.abs(off).max() <= 1e-12 * (np.abs(a).max() + f.max())
+    # the factor stays bounded (the raised pivot is as large as the loss)
+    assert np.abs(l).max() <= 10 * math.sqrt(np.abs(a).max())
+
+
+def test_tlr_modified_cholesky_exact_low_rank():
+    # blockdiag(B) + W W^T with an indefinite B_1: the unmodified TLR
+    # Cholesky fails at tile 1; the modified one factors A + diag(f), f >= 0
+    # on the raised pivots of that tile only
+    n, m, r = 384, 64, 3
+    rng = np.random.default_rng(63)
+    a = np.zeros((n, n))
+    for k in range(0, n, m):
+        g = rng.standard_normal((m, m))
+        a[k:k + m, k:k + m] = g @ g.T / m + np.eye(m)
+    w = rng.standard_normal((n, r))
+    a += w @ w.T
+    # tile 1's Schur complement (A_11 - A_10 A_00^-1 A_01) loses definiteness
+    # by a rank-one change of A_11 just past its smallest eigenvalue
+    s1 = a[m:2 * m, m:2 * m] - a[m:2 * m, :m] @ np.linalg.solve(a[:m, :m], a[:m, m:2 * m])
+    lam, vec = np.linalg.eigh(s1)
+    a[m:2 * m, m:2 * m] -= (lam[0] + 1e-4) * np.outer(vec[:, 0], vec[:, 0])
+    t = tlr.compress_dense(a, m, 1e-11)
+    with pytest.raises(tlr.NotSPDTile):
+        tlr.tlr_cholesky(t, 1e-9)
+    rec = {}
+    l = tlr.tlr_cholesky(t, 1e-9, record=rec, modified=True)
+    assert rec["modified"] > 0
+    e = l.dense_lower() @ l.dense_lower().T - t.dense_symmetric()
+    d = np.diag(e).copy()
+    np.fill_diagonal(e, 0.0)
+    assert np.abs(e).max() <= 1e-8 * np.abs(a).max()
+    assert d.min() >= -1e-9 and np.count_nonzero(d > 1e-9) == rec["modified"]
+    assert np.all(np.abs(d[:m]) <= 1e-9) and np.all(np.abs(d[2 * m:]) <= 1e-9)
