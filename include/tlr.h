@@ -347,6 +347,20 @@ tlr_status tlr_ldlt_batched(int count, tlr_matrix_t* A, const double* eps, const
  * holds no factor. */
 tlr_status tlr_solve(tlr_matrix_t A, int nrhs, double* B, long long ldb, void* stream);
 
+/* tlr_solve without any allocation, for callers that cannot allocate device
+ * or host memory during the call (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, result and
+ * errors as tlr_solve; the workspace, (nb m + m + T) nrhs doubles with T the
+ * largest number of factor columns of one block column or block row (plus
+ * nb m nrhs for a pivoted factor), lives
+ * in a fixed device array of tlr_solve_noalloc_max_bytes() bytes (32 MiB)
+ * that each GPU keeps until the process ends.  A larger need, or launch
+ * descriptors that do not fit the handle's staging ring, is TLR_ERR_ARG.
+ * All calls on one GPU share that array: calls that overlap on one GPU (two
+ * streams, two threads) race and must be serialised by the caller. */
+tlr_status tlr_solve_noalloc(tlr_matrix_t A, int nrhs, double* B, long long ldb, void* stream);
+size_t tlr_solve_noalloc_max_bytes(void);
+
 /* Y <- A X for the TLR input matrix (which = TLR_INPUT), X and Y N x nrhs in
  * device memory. */
 tlr_status tlr_matvec(tlr_matrix_t A, int nrhs, const double* X, long long ldx, double* Y,

@@ -119,6 +119,8 @@ SIGNATURES = {
     "tlr_ldlt_batched": (_I, [_I, ctypes.POINTER(_P), _DP, ctypes.POINTER(Opts),
                               ctypes.POINTER(_P), ctypes.POINTER(Stats), _P]),
     "tlr_solve": (_I, [_P, _I, _P, _LL, _P]),
+    "tlr_solve_noalloc": (_I, [_P, _I, _P, _LL, _P]),
+    "tlr_solve_noalloc_max_bytes": (ctypes.c_size_t, []),
     "tlr_matvec": (_I, [_P, _I, _P, _LL, _P, _LL, _P]),
     "tlr_get_info": (_I, [_P, _LLP, _IP, _IP, _IP]),
     "tlr_get_ranks": (_I, [_P, _I, _IP]),
@@ -374,6 +376,14 @@ class TLRMatrix:
         x = _to_colmajor(b)
         nrhs = 1 if b.dim() == 1 else b.shape[1]
         _check(lib().tlr_solve(self.h, nrhs, _ptr(x), self.n, _stream()))
+        return _from_colmajor(x, b.shape)
+
+    def solve_noalloc(self, b):
+        """As solve(), through tlr_solve_noalloc (workspace in the library's
+        fixed per-GPU scratch array, no allocation inside the call)."""
+        x = _to_colmajor(b)
+        nrhs = 1 if b.dim() == 1 else b.shape[1]
+        _check(lib().tlr_solve_noalloc(self.h, nrhs, _ptr(x), self.n, _stream()))
         return _from_colmajor(x, b.shape)
 
     def matvec(self, x):
