@@ -187,6 +187,45 @@ def pivoted_form(tlr, torch, wl, steps: int):
     return out
 
 
+def pcg_form(tlr, torch, wl):
+    """TLR factorizations as preconditioners (Section 6): the N=32768 2D
+    exponential covariance with nugget 1e-6 as the operator (compressed at
+    1e-9), preconditioned CG to a relative residual of 1e-8 with the TLR
+    Cholesky at eps 1e-2, 1e-4 and 1e-6 (shift tau where definiteness is
+    lost), and without a preconditioner."""
+    base = wl.standard("cov2d_32k")
+    pts = base.points
+    op = tlr.TLRMatrix.compress_kernel(pts, base.kernel, base.ell, 1e-6, base.m, 1e-9,
+                                       tlr.opts(bs=base.bs))
+    g = torch.Generator(device="cpu").manual_seed(9)
+    b = torch.randn(op.n, generator=g, dtype=torch.float64).cuda()
+    out = {"workload": "2D exponential covariance (ell 0.1, diagonal +1e-6), N=%d, tile %d; "
+                       "operator eps 1e-9" % (op.n, base.m), "rtol": 1e-8}
+    for eps in (1e-2, 1e-4, 1e-6):
+        f = tlr.TLRMatrix.compress_kernel(pts, base.kernel, base.ell, 1e-6, base.m, eps,
+                                          tlr.opts(bs=base.bs))
+        o = tlr.opts(bs=base.bs, auto_shift=1)
+        f.potrf(eps, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = f.potrf(eps, o)
+        torch.cuda.synchronize()
+        t_f = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, it, rel = op.pcg(b, f, rtol=1e-8, maxit=2000)
+        torch.cuda.synchronize()
+        t_s = time.perf_counter() - t0
+        out["eps_%g" % eps] = {"factor_ms": t_f * 1e3, "pcg_ms": t_s * 1e3, "iterations": it,
+                               "relres": rel, "shift": st["shift"], "rank_mean": st["mean_rank"]}
+        f.close()
+    t0 = time.perf_counter()
+    _, it, rel = op.pcg(b, None, rtol=1e-8, maxit=2000)
+    torch.cuda.synchronize()
+    out["none"] = {"pcg_ms": (time.perf_counter() - t0) * 1e3, "iterations": it, "relres": rel}
+    op.close()
+    return out
+
+
 def batched_form(tlr, torch, wl, count: int, m_fixed: int):
     """The batched workload (count independent 2D problems of uneven N,
     relative eps 1e-6).  Tile sizes come from the library's autotuner
@@ -350,8 +389,15 @@ def main():
                     help="skip the LDL^T line (3D Matern, indefinite) after the main line")
     ap.add_argument("--no-pivoted", dest="pivoted", action="store_false",
                     help="skip the pivoted / unpivoted line (3D covariance, tile 512)")
+    ap.add_argument("--no-pcg", dest="pcg", action="store_false",
+                    help="skip the preconditioned CG line (N=32768)")
     ap.add_argument("--batched", type=int, default=96,
                     help="problems of the batched workload timed after the main line (0 = skip)")
+    ap.add_argument("--form", default="fp64",
+                    choices=["fp64", "mixed_fp32_rel", "mixed_bf16_rel"],
+                    help="with --profile: the form to factor (fp64: the headline; mixed_fp32_rel: "
+                         "relative 1e-6 with FP32 panels; mixed_bf16_rel: relative 1e-2 with BF16 "
+                         "panels and the shift tau)")
     ap.add_argument("--profile", action="store_true",
                     help="for profilers: build the input, run the --warmup and --steps "
                          "factorizations and stop (no second pass, residual or other lines)")
@@ -393,6 +439,24 @@ def main():
     # the headline steps run without per-launch events (they cost a few
     # percent of the step); the sampling kernel's durations come from the
     # dispatches' own events in a second pass of the same number of steps
+    if a.profile and a.form != "fp64":
+        prec, eps, shift = ((tlr.MIXED_FP32, 1e-6, 0.0) if a.form == "mixed_fp32_rel"
+                            else (tlr.MIXED_BF16, 1e-2, -1.0))
+        o = tlr.opts(bs=w.bs, eps_mode=tlr.EPS_REL, precision=prec, shift=shift)
+        for _ in range(a.warmup):
+            mat.potrf(eps, o)
+        torch.cuda.synchronize()
+        time.sleep(0.05)
+        t0 = time.perf_counter()
+        sts = [mat.potrf(eps, o) for _ in range(a.steps)]
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": w.name, "form": a.form,
+                          "ms_per_step": (time.perf_counter() - t0) / a.steps * 1e3,
+                          "fp32_tile_iters": sts[-1]["fp32_tile_iters"],
+                          "bf16_tile_iters": sts[-1]["bf16_tile_iters"],
+                          "tile_iters": sts[-1]["tile_iters"]}), flush=True)
+        mat.close()
+        return
     dt, stats = time_form(mat, w, w.eps_mode, tlr.FP64, tlr, torch, a.steps, a.warmup, a.bs_tail,
                           a.tail_active, False, 0.05 if a.profile else 0.0)
     print("[bench] %d timed steps, %.1f ms each" % (a.steps, dt * 1e3), file=sys.stderr, flush=True)
@@ -489,6 +553,13 @@ def main():
             print("[bench] cov3d_131k %s: %.1f ms, residual %.3g, ranks mean %.1f max %d"
                   % (k, v["ms_per_step"], v["residual"], v["rank_mean"], v["rank_max"]),
                   file=sys.stderr, flush=True)
+    if a.pcg:
+        print("[bench] preconditioned CG (N=32768)", file=sys.stderr, flush=True)
+        line["pcg"] = pcg_form(tlr, torch, wl)
+        for k, v in line["pcg"].items():
+            if isinstance(v, dict):
+                print("[bench] pcg %s: %d iterations, %.1f ms" % (k, v["iterations"], v["pcg_ms"]),
+                      file=sys.stderr, flush=True)
     if a.batched > 0:
         print("[bench] batched workload: %d problems" % a.batched, file=sys.stderr, flush=True)
         line["batched"] = batched_form(tlr, torch, wl, a.batched, 512)

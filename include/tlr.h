@@ -361,6 +361,20 @@ tlr_status tlr_solve(tlr_matrix_t A, int nrhs, double* B, long long ldb, void* s
 tlr_status tlr_solve_noalloc(tlr_matrix_t A, int nrhs, double* B, long long ldb, void* stream);
 size_t tlr_solve_noalloc_max_bytes(void);
 
+/* Preconditioned conjugate gradients for A x = b, the use of the
+ * factorization as a preconditioner in Section 6: A is applied by
+ * tlr_matvec of the input matrix of handle A, the preconditioner by
+ * tlr_solve of the factor held by handle F (typically a looser threshold;
+ * NULL: no preconditioner).  b and x are N-vectors in device memory; x holds
+ * the initial guess on entry and the solution on return.  Stops when
+ * ||b - A x||_2 <= rtol ||b||_2 or after maxit iterations; *iters receives
+ * the iterations taken and *relres the final relative residual (the
+ * recurrence's).  The two inner products of an iteration are reduced in a
+ * fixed order and read back to the host.  TLR_ERR_NOT_SPD if a search
+ * direction has p^T A p <= 0; TLR_ERR_STATE if F holds no factor. */
+tlr_status tlr_pcg(tlr_matrix_t A, tlr_matrix_t F, const double* b, double* x, double rtol,
+                   int maxit, int* iters, double* relres, void* stream);
+
 /* Y <- A X for the TLR input matrix (which = TLR_INPUT), X and Y N x nrhs in
  * device memory. */
 tlr_status tlr_matvec(tlr_matrix_t A, int nrhs, const double* X, long long ldx, double* Y,

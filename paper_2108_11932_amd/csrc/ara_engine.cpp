@@ -220,6 +220,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   D.poff = 0;
   D.snap_act = nullptr;
   D.snap_counts = nullptr;
+  D.skip = nullptr;
   const int p_blocks = (int)ptiles.size();
   const int bps_wa = (spec.a_max + 31) / 32;
   // split-K partial tiles of the TN products
@@ -239,17 +240,16 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   int* info = h->d_info;
 
   // Sampling lookahead.  Without refills (no waiting list) the active list
-  // only shrinks, so iteration t + 1's samples can be drawn for the tiles
-  // active in iteration t while iteration t is still being orthogonalised:
-  // the sampling launches go to the handle's sampling stream, one iteration
-  // ahead, into the other copy of Y and of its Gram partials.  Sampling t
-  // reads the list the compaction of iteration t - 2 left in snapshot
-  // (t - 1) & 1 (the list of iteration t - 1, a superset of iteration t's),
-  // and waits for that compaction, which also ends the last use of its Y
-  // copy; the orthogonalisation of t waits for sampling t.  A slot's samples
-  // depend only on the slot, so the result is the same as sampling exactly
-  // the tiles of iteration t; the samples of tiles that converged in
-  // iteration t - 1 are discarded.
+  // only shrinks, so iteration t + 1's samples can be drawn while iteration
+  // t is still being orthogonalised: the sampling launches go to the
+  // handle's sampling stream, one iteration ahead, into the other copy of Y
+  // and of its Gram partials.  Sampling t starts after the pass-1 Cholesky
+  // QR step of iteration t - 1 and takes the list of iteration t - 1 (the
+  // snapshot the compaction of t - 2 left in (t - 1) & 1) less the tiles that
+  // pass 1 flagged as converged: exactly the tiles of iteration t.  It then
+  // runs beside pass 2 and the compaction of t - 1; the orthogonalisation of
+  // t waits for it.  A slot's samples depend only on the slot, so the result
+  // is the same as sampling after the compaction.
   const bool overlap = c.overlap && nwait == 0;
   hipStream_t ss = st;
   if (overlap) {
@@ -310,10 +310,12 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     E.poff = (t & 1) ? s.palt : 0;
     E.snap_act = nullptr;
     E.snap_counts = nullptr;
+    E.skip = nullptr;
     if (overlap && sampling) {
       const int b = t == 0 ? 0 : ((t - 1) & 1);
       E.act = s.snap_act[b];
       E.counts = s.snap_counts[b];
+      if (t >= 1) E.skip = s.flag;
     }
     return E;
   };
@@ -361,14 +363,15 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     Progress* pr = &prog;
     h->sworker->submit([=]() -> tlr_status {
       tlr_status r = TLR_OK;
-      if (t >= 2) {
-        // sampling t overwrites the Y copy of iteration t - 2 and reads the
-        // list its compaction left
-        for (int spins = 0; pr->main_rec.load(std::memory_order_acquire) < t - 2; ++spins) {
+      if (t >= 1) {
+        // sampling t waits for the pass-1 Cholesky QR step of iteration
+        // t - 1: it flags the tiles that converge there (skipped), and the Y
+        // copy sampling t overwrites was last read by pass 1 of t - 2
+        for (int spins = 0; pr->main_rec.load(std::memory_order_acquire) < t - 1; ++spins) {
           if (pr->abort.load(std::memory_order_acquire)) return TLR_OK;
           if (spins > 64) std::this_thread::yield();
         }
-        if (hipStreamWaitEvent(ss, hh->ev_main[(t - 2) & 3], 0) != hipSuccess) r = TLR_ERR_DEVICE;
+        if (hipStreamWaitEvent(ss, hh->ev_main[(t - 1) & 3], 0) != hipSuccess) r = TLR_ERR_DEVICE;
       }
       if (r == TLR_OK) r = sample_launches(E, t, cb, ss, e0, e1);
       if (r == TLR_OK && hipEventRecord(hh->ev_samp[t & 3], ss) != hipSuccess) r = TLR_ERR_DEVICE;
@@ -407,6 +410,12 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       TLR_HIP(launch_ara_seg(E, 1, cb, st));
     }
     TLR_HIP(launch_orth_step(E, 1, c.r_min, cb, st));
+    // the next iteration's sampling may start: this iteration's
+    // convergence flags are set
+    if (overlap) {
+      TLR_HIP(hipEventRecord(h->ev_main[j & 3], st));
+      prog.main_rec.store(j, std::memory_order_release);
+    }
     if (bps_q > 0) {
       TLR_HIP(launch_ara_tn(E, 2, nullptr, nullptr, 0, 0, cb, bps_q, tn_scratch, st));
       TLR_HIP(launch_ara_seg(E, 2, cb, st));
@@ -415,18 +424,12 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     if (spec.pt) TLR_HIP(spec.pt->mark(TLR_PHASE_BATCH, st));
     TLR_HIP(launch_ara_compact(E, s.waiting, nwait, s_max, info, ring + 8 * (j & 1), pres, res_ints,
                                st));
-    // one event serves the other stream's wait and the host's read-back
-    if (overlap) {
-      TLR_HIP(hipEventRecord(h->ev_main[j & 3], st));
-      prog.main_rec.store(j, std::memory_order_release);
-    } else {
-      TLR_HIP(hipEventRecord(h->ev_rb[j & 1], st));
-    }
+    TLR_HIP(hipEventRecord(h->ev_rb[j & 1], st));
     return TLR_OK;
   };
-  auto readback_event = [&](int j) { return overlap ? h->ev_main[j & 3] : h->ev_rb[j & 1]; };
-  // iteration j: with the lookahead, the sampling of j + 1 goes out first
-  // (it waits only for the compaction of j - 1)
+  auto readback_event = [&](int j) { return h->ev_rb[j & 1]; };
+  // iteration j: with the lookahead, the sampling of j + 1 is handed to the
+  // worker first (it starts after pass 1 of iteration j)
   auto enqueue = [&](int j) -> tlr_status {
     while (sampled < (overlap ? j + 1 : j)) TLR_TRY(enqueue_sampling(sampled + 1));
     return enqueue_orth(j);

@@ -48,6 +48,7 @@ __device__ inline bool tn_resolve(const AraDev& D, int mode, int tid, const doub
   const int ai = t / tps, tile = t % tps;
   if (ai >= D.counts[0]) return false;
   const int slot = D.act[ai];
+  if (D.skip && D.skip[slot]) return false;
   const AraSlotDesc& d = D.slots[slot];
   const int row0 = tile * TN_TM;
   if (mode == 0) {
@@ -124,6 +125,7 @@ __global__ __launch_bounds__(256) void k_ara_z(AraDev D, const ZSeg* __restrict_
   const int ai = blockIdx.x / bps, tb = blockIdx.x % bps;
   if (ai >= D.counts[0]) return;
   const int slot = D.act[ai];
+  if (D.skip && D.skip[slot]) return;
   const AraSlotDesc& d = D.slots[slot];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int pi = tb * 4 + wave;
@@ -180,6 +182,7 @@ __global__ __launch_bounds__(256) void k_ara_seg(AraDev D) {
   const int ai = blockIdx.x / nblk, blk = blockIdx.x % nblk;
   if (ai >= D.counts[0]) return;
   const int slot = D.act[ai];
+  if (D.skip && D.skip[slot]) return;
   const AraSlotDesc& d = D.slots[slot];
   const int m = D.m, bs = D.bs;
   const int r0 = blk * 16 * FM;

@@ -33,11 +33,13 @@ __global__ __launch_bounds__(256) void k_fro_norms(const NormDesc* __restrict__ 
   __shared__ double red[256];
   const NormDesc d = descs[blockIdx.x];
   double s = 0.0;
-  const long long n = (long long)d.rows * d.cols;
-  for (long long e = threadIdx.x; e < n; e += 256) {
-    const int r = (int)(e % d.rows), c = (int)(e / d.rows);
-    const double v = d.p[r + (size_t)c * d.ld];
-    s += v * v;
+  // column by column (no 64-bit index division on the way; coalesced rows)
+  for (int c = 0; c < d.cols; ++c) {
+    const double* col = d.p + (size_t)c * d.ld;
+    for (int r = threadIdx.x; r < d.rows; r += 256) {
+      const double v = col[r];
+      s += v * v;
+    }
   }
   red[threadIdx.x] = s;
   __syncthreads();

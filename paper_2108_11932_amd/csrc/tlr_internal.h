@@ -183,6 +183,9 @@ struct AraDev {
   // (the list the next iteration's speculative sampling reads)
   int* snap_act;
   int* snap_counts;
+  // when set, the sampling launches skip the slots with skip[slot] != 0
+  // (the convergence flags of the iteration before)
+  const int* skip;
 };
 // Precision choice of one slot under mixed precision.  With
 // nu_tot = nu + fro[irow] fro[0] (no device term when irow < 0; fro holds the

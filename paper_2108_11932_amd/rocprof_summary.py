@@ -3,7 +3,9 @@ kept under profiles/.
 
     python -m paper_2108_11932_amd.rocprof_summary kernels  <kernel_trace.csv>
     python -m paper_2108_11932_amd.rocprof_summary counters <counter_collection.csv> \
-        [--trace <kernel_trace.csv>] [--copy-mib N]
+        [--trace <kernel_trace.csv>] [--copy-mib N] [--durations <kernel_trace.csv>]
+    python -m paper_2108_11932_amd.rocprof_summary table <mfma summary> \
+        --fetch <FETCH_SIZE summary> --write <WRITE_SIZE summary>
 
 Both select the dispatches of the last factorization of a bench.py --profile
 run: those after the last input-generation kernel (k_gen_tiles) and after
@@ -109,7 +111,19 @@ def kernels(path: str) -> str:
     return "\n".join(out)
 
 
-def counters(path: str, trace: str = None, copy_mib: int = 0) -> str:
+def _avg_durations(path: str):
+    """Per-kernel average duration (us) and calls of the last factorization
+    of a plain --kernel-trace run."""
+    tot = defaultdict(float)
+    calls = defaultdict(int)
+    for r in _window(_rows(path)):
+        k = _short(_col(r, "Kernel_Name"))
+        tot[k] += (int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))) / 1e3
+        calls[k] += 1
+    return {k: (tot[k] / calls[k], calls[k]) for k in tot}
+
+
+def counters(path: str, trace: str = None, copy_mib: int = 0, durations: str = None) -> str:
     rows = _rows(path)
     by_disp = OrderedDict()
     for r in rows:
@@ -148,8 +162,17 @@ def counters(path: str, trace: str = None, copy_mib: int = 0) -> str:
             agg[k][cn] += v * cal.get(cn, 1.0)
         if d in dur:
             agg[k]["_us"] += dur[d]
+    plain = _avg_durations(durations) if durations else {}
+    if plain:
+        # kernel time from the run without counters (counter collection
+        # serialises and slows the dispatches): calls x plain average
+        for k in agg:
+            if k in plain:
+                agg[k]["_us"] = plain[k][0] * calls[k]
     names = sorted({cn for k in agg for cn in agg[k] if cn != "_us"})
-    out = ["dispatches after the last k_gen_tiles: %d; counters: %s" % (len(win), ", ".join(names))]
+    out = ["dispatches of the last factorization: %d; counters: %s" % (len(win), ", ".join(names))]
+    if plain:
+        out.append("time_us: calls x the kernel's average duration in the run without counters")
     if cal:
         out.append("byte counters scaled by the copy calibration: %s" %
                    ", ".join("%s x%.4f" % kv for kv in sorted(cal.items())))
@@ -176,17 +199,64 @@ def counters(path: str, trace: str = None, copy_mib: int = 0) -> str:
     return "\n".join(out)
 
 
+def _parse_table(path: str):
+    """Rows of a `counters` summary: {kernel: {column: value}}."""
+    rows, hdr = {}, None
+    with open(path) as fh:
+        for ln in fh:
+            if ln.startswith("kernel "):
+                hdr = ln.split()
+                continue
+            if hdr is None or not ln.strip():
+                continue
+            name, rest = ln[:60].strip(), ln[60:].split()
+            rows[name] = dict(zip(hdr[1:], [float(x) for x in rest]))
+    return rows
+
+
+HBM_PEAK = 8.0e12
+
+
+def table(mfma: str, fetch: str, write: str) -> str:
+    """Per-kernel roofline table of one factorization from the `counters`
+    summaries of an MFMA-op run and of the FETCH_SIZE and WRITE_SIZE runs
+    (calibrated KiB): time, achieved FP64 matrix-core rate and HBM rate, and
+    their fractions of the MI355X peaks; `bound` names the larger one."""
+    mf, fe, wr = _parse_table(mfma), _parse_table(fetch), _parse_table(write)
+    tot = sum(v.get("time_us", 0.0) for v in mf.values())
+    out = ["kernel | calls | time_us | share | mfma_f64_tflops | frac_mfma_f64 | hbm_gbs | "
+           "frac_hbm | bound"]
+    for k in sorted(mf, key=lambda x: -mf[x].get("time_us", 0.0)):
+        v = mf[k]
+        t = v.get("time_us", 0.0) * 1e-6
+        if t <= 0:
+            continue
+        fl = v.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * MOPS_UNIT
+        by = (fe.get(k, {}).get("FETCH_SIZE", 0.0) + wr.get(k, {}).get("WRITE_SIZE", 0.0)) * 1024.0
+        fm, fh = fl / t / PEAK["F64"], by / t / HBM_PEAK
+        out.append("%s | %d | %.1f | %.3f | %.3f | %.4f | %.1f | %.4f | %s" %
+                   (k, int(v.get("calls", 0)), v["time_us"], v["time_us"] / tot, fl / t / 1e12, fm,
+                    by / t / 1e9, fh, "mfma" if fm >= fh else "hbm"))
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
-    ap.add_argument("what", choices=["kernels", "counters"])
+    ap.add_argument("what", choices=["kernels", "counters", "table"])
+    ap.add_argument("--fetch", default=None)
+    ap.add_argument("--write", default=None)
     ap.add_argument("csv")
     ap.add_argument("--trace", default=None)
     ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--durations", default=None,
+                    help="kernel_trace.csv of a run without counters (kernel times)")
     a = ap.parse_args(argv)
     if a.what == "kernels":
         print(kernels(a.csv))
+    elif a.what == "table":
+        print(table(a.csv, a.fetch, a.write))
     else:
-        print(counters(a.csv, a.trace, a.copy_mib))
+        print(counters(a.csv, a.trace, a.copy_mib, a.durations))
 
 
 if __name__ == "__main__":

@@ -122,6 +122,7 @@ SIGNATURES = {
     "tlr_solve_noalloc": (_I, [_P, _I, _P, _LL, _P]),
     "tlr_solve_noalloc_max_bytes": (ctypes.c_size_t, []),
     "tlr_matvec": (_I, [_P, _I, _P, _LL, _P, _LL, _P]),
+    "tlr_pcg": (_I, [_P, _P, _P, _P, _D, _I, _IP, _DP, _P]),
     "tlr_get_info": (_I, [_P, _LLP, _IP, _IP, _IP]),
     "tlr_get_ranks": (_I, [_P, _I, _IP]),
     "tlr_get_offsets": (_I, [_P, _I, _LLP]),
@@ -385,6 +386,19 @@ class TLRMatrix:
         nrhs = 1 if b.dim() == 1 else b.shape[1]
         _check(lib().tlr_solve_noalloc(self.h, nrhs, _ptr(x), self.n, _stream()))
         return _from_colmajor(x, b.shape)
+
+    def pcg(self, b, precond: Optional["TLRMatrix"] = None, rtol: float = 1e-10,
+            maxit: int = 1000, x0=None):
+        """tlr_pcg with this handle's input matrix as the operator and the
+        factor of `precond` as the preconditioner: (x, iterations, relres)."""
+        torch = _torch()
+        bd = b.to(dtype=torch.float64).contiguous()
+        x = torch.zeros_like(bd) if x0 is None else x0.to(dtype=torch.float64).clone().contiguous()
+        it = ctypes.c_int()
+        rr = ctypes.c_double()
+        _check(lib().tlr_pcg(self.h, precond.h if precond is not None else None, _ptr(bd), _ptr(x),
+                             rtol, maxit, ctypes.byref(it), ctypes.byref(rr), _stream()))
+        return x, it.value, rr.value
 
     def matvec(self, x):
         torch = _torch()
