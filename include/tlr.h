@@ -149,10 +149,11 @@ typedef struct {
  * algorithmic bytes in tlr_stats.sample_*.  TLR_FLAG_PHASE_TIMING: record
  * HIP events at the phase boundaries of every column and report the GPU time
  * per phase in tlr_stats.t_phase.  TLR_FLAG_SERIAL_SAMPLING: draw every ARA
- * iteration's samples on the caller's stream after the previous iteration
- * (by default, when every tile of the column is active from the start, the
- * samples of iteration t + 1 are drawn on a library stream while iteration t
- * is orthogonalised; the result is the same bit for bit).
+ * iteration's samples in launches of their own after the previous iteration
+ * (by default, when every tile of the column is active from the start and
+ * the block size is 16 or 32, the samples of iteration t + 1 are drawn in
+ * the launches of iteration t's second Gram-Schmidt pass; the result is the
+ * same bit for bit).
  * TLR_FLAG_MODIFIED_CHOL (Cholesky only; Section 5.1.2, "Modified Cholesky"):
  * a diagonal tile that loses definiteness is not an error; each
  * non-positive pivot of its Cholesky is replaced by tau as it is met, which

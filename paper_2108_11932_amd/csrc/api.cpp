@@ -478,7 +478,6 @@ tlr_status tlr_get_sort_order(tlr_matrix_t A, int k, int* rows) {
 tlr_status tlr_destroy(tlr_matrix_t A) {
   if (!A) return TLR_OK;
   A->worker.reset();
-  A->sworker.reset();
   (void)hipStreamSynchronize(A->stream);
   free_factor(A);
   Mem& mem = A->mem;

@@ -2,10 +2,8 @@
 #include "ara_engine.h"
 
 #include <algorithm>
-#include <atomic>
 #include <chrono>
 #include <cstring>
-#include <thread>
 
 namespace tlr {
 
@@ -28,7 +26,7 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   if (fresh_q) TLR_HIP(hipMemsetAsync(w.Q.p, 0, w.Q.cap, h->stream));
   const size_t pn = nn * nstrip * bs * bs * 2;
   TLR_TRY(w.part.ensure(h->mem, sizeof(double) * 3 * pn));
-  const size_t nint = 8 + 9 * al(nn) + 2 * (64 + al(nn)) + al(nn * (bs + 1)) + 64;
+  const size_t nint = 8 + 9 * al(nn) + al(nn * (bs + 1)) + 64;
   TLR_TRY(w.ints.ensure(h->mem, sizeof(int) * nint));
   s->Y = w.Y.as<double>();
   s->C = w.C.as<double>();
@@ -56,12 +54,6 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   ip += al(nn);
   s->f32 = ip;
   ip += al(nn);
-  for (int b = 0; b < 2; ++b) {
-    s->snap_counts[b] = ip;
-    ip += 64;
-    s->snap_act[b] = ip;
-    ip += al(nn);
-  }
   s->waiting = ip;   // counts .. waiting are written by one upload per run
   ip += al(nn);
   s->piv = ip;
@@ -187,8 +179,6 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     std::vector<int> blob(wo + nwait, 0);
     blob[0] = s_max;
     std::copy(act.begin(), act.end(), blob.begin() + (s.act - s.counts));
-    blob[s.snap_counts[0] - s.counts] = s_max;
-    std::copy(act.begin(), act.end(), blob.begin() + (s.snap_act[0] - s.counts));
     std::copy(waiting.begin(), waiting.end(), blob.begin() + wo);
     TLR_TRY(h->stage.upload_to(h, blob.data(), sizeof(int) * blob.size(), s.counts, st));
   }
@@ -218,8 +208,6 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   D.nstrip = s.nstrip;
   D.yoff = 0;
   D.poff = 0;
-  D.snap_act = nullptr;
-  D.snap_counts = nullptr;
   D.skip = nullptr;
   const int p_blocks = (int)ptiles.size();
   const int bps_wa = (spec.a_max + 31) / 32;
@@ -240,64 +228,23 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   int* info = h->d_info;
 
   // Sampling lookahead.  Without refills (no waiting list) the active list
-  // only shrinks, so iteration t + 1's samples can be drawn while iteration
-  // t is still being orthogonalised: the sampling launches go to the
-  // handle's sampling stream, one iteration ahead, into the other copy of Y
-  // and of its Gram partials.  Sampling t starts after the pass-1 Cholesky
-  // QR step of iteration t - 1 and takes the list of iteration t - 1 (the
-  // snapshot the compaction of t - 2 left in (t - 1) & 1) less the tiles that
-  // pass 1 flagged as converged: exactly the tiles of iteration t.  It then
-  // runs beside pass 2 and the compaction of t - 1; the orthogonalisation of
-  // t waits for it.  A slot's samples depend only on the slot, so the result
-  // is the same as sampling after the compaction.
-  const bool overlap = c.overlap && nwait == 0;
-  hipStream_t ss = st;
-  if (overlap) {
-    TLR_TRY(h->samp_stream());
-    ss = h->samp;
-    if (!h->sworker) h->sworker.reset(new SideWorker(h->dev));
-    TLR_HIP(hipEventRecord(h->ev_sfork, st));
-    TLR_HIP(hipStreamWaitEvent(ss, h->ev_sfork, 0));
-  }
-  // the sampling launches run beside the orthogonalisation: their own
-  // split-K scratch
+  // only shrinks: iteration t + 1 samples the tiles of iteration t less the
+  // ones that the pass-1 Cholesky QR step of iteration t flagged as
+  // converged.  So, once that step has run, the sampling of t + 1 needs
+  // nothing more from iteration t, and it shares the launches of t's second
+  // Gram-Schmidt pass (the first blocks of each launch sample, the others
+  // orthogonalise): both run at once on one stream, and the host issues one
+  // launch for two.  The samples go to the other copy of Y and of its Gram
+  // partials.  A slot's samples depend only on the slot, so the result is
+  // the same bit for bit as sampling at the start of each iteration.
+  const bool fuse = c.overlap && nwait == 0 && !spec.events && fused_block_supported(c.bs) &&
+                    (c.bs_tail <= 0 || c.bs_tail == c.bs);
+  // the sampling half writes its split-K partials beside the other half's
   double* tn_scratch_s = tn_scratch;
-  if (overlap) {
+  if (fuse) {
     TLR_TRY(w.tnpart2.ensure(h->mem, w.tnpart.cap));
     tn_scratch_s = w.tnpart2.as<double>();
   }
-  // The sampling launches are issued by the handle's sampling worker thread
-  // (the event operations that order the two streams cost the host several
-  // microseconds each; split over two threads, the host keeps ahead of the
-  // GPU).  A stream wait must follow the record it refers to, so each side
-  // publishes the last iteration whose event it has recorded.
-  struct Progress {
-    std::atomic<int> samp_rec{-1}, main_rec{-1};
-    std::atomic<bool> failed{false}, abort{false};
-  } prog;
-  // every exit stops the worker's pending waits, lets it drain and joins the
-  // sampling stream back into the caller's stream
-  struct Join {
-    Handle* h;
-    hipStream_t st, ss;
-    bool on;
-    Progress* pr;
-    ~Join() {
-      if (!on) return;
-      pr->abort.store(true, std::memory_order_release);
-      (void)h->sworker->wait();
-      if (hipEventRecord(h->ev_sfork, ss) == hipSuccess) (void)hipStreamWaitEvent(st, h->ev_sfork, 0);
-    }
-  } join{h, st, ss, overlap, &prog};
-  // host-side wait for the other thread's progress (it is normally ahead)
-  auto await = [&](const std::atomic<int>& v, int target) -> bool {
-    for (int spins = 0; v.load(std::memory_order_acquire) < target; ++spins) {
-      if (prog.failed.load(std::memory_order_acquire) || prog.abort.load(std::memory_order_acquire))
-        return false;
-      if (spins > 64) std::this_thread::yield();
-    }
-    return true;
-  };
 
   Known known;
   known.count = s_max;
@@ -308,42 +255,25 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     E.bs = bs_of[t];
     E.yoff = (t & 1) ? s.yalt : 0;
     E.poff = (t & 1) ? s.palt : 0;
-    E.snap_act = nullptr;
-    E.snap_counts = nullptr;
-    E.skip = nullptr;
-    if (overlap && sampling) {
-      const int b = t == 0 ? 0 : ((t - 1) & 1);
-      E.act = s.snap_act[b];
-      E.counts = s.snap_counts[b];
-      if (t >= 1) E.skip = s.flag;
-    }
+    E.skip = (sampling && fuse && t >= 1) ? s.flag : nullptr;
     return E;
   };
-  // the launches of the sampling of iteration t (Y = S Omega for every tile
-  // of the list E names) on stream q
-  auto sample_launches = [=, &spec](const AraDev& E, int t, int cb, hipStream_t q, hipEvent_t e0,
-                                     hipEvent_t e1) -> tlr_status {
-    // the samples of the explicit tiles read the test matrix through their
-    // descriptors (one buffer, drawn every iteration); the sampling through
-    // P and W^A draws the matrices of kOmegaBatch iterations at a time
-    const double* om = omega;
-    if (omega_in_slots) {
-      TLR_HIP(launch_randn(omega, m, E.bs, m, c.seed, c.stream_id, (unsigned)t, 0, q));
-    } else {
-      const size_t ostride = (size_t)m * bs;
-      if (t % kOmegaBatch == 0)
-        TLR_HIP(launch_randn_iters(omega, m, ostride, c.bs, bs, c.seed, c.stream_id,
-                                   (unsigned)t, kOmegaBatch, 0, q));
-      om = omega + (size_t)(t % kOmegaBatch) * ostride;
-    }
-    double* scr = q == st ? tn_scratch : tn_scratch_s;
-    if (p_blocks > 0 || bps_wa > 0)
-      TLR_HIP(launch_ara_tn(E, 0, om, dptiles, p_blocks, spec.ldp, cb, bps_wa, scr, q));
-    if (any_z) TLR_HIP(launch_ara_z(E, dzseg, spec.p, spec.ldp, cb, bps_z, q));
-    TLR_HIP(launch_ara_seg(E, 0, cb, q, c.strip, e0, e1));
+  const size_t ostride = (size_t)m * bs;
+  // the test matrix of iteration t: explicit tiles read one buffer through
+  // their descriptors (drawn every iteration); the sampling through P and
+  // W^A draws the matrices of kOmegaBatch iterations at a time
+  auto draw = [&](int t, int bst) -> tlr_status {
+    if (omega_in_slots)
+      TLR_HIP(launch_randn(omega, m, bst, m, c.seed, c.stream_id, (unsigned)t, 0, st));
+    else if (t % kOmegaBatch == 0)
+      TLR_HIP(launch_randn_iters(omega, m, ostride, c.bs, bs, c.seed, c.stream_id, (unsigned)t,
+                                 kOmegaBatch, 0, st));
     return TLR_OK;
   };
-  // enqueue the sampling of iteration t with launch bounds derived from
+  auto omega_of = [&](int t) {
+    return omega_in_slots ? omega : omega + (size_t)(t % kOmegaBatch) * ostride;
+  };
+  // the sampling of iteration t alone, with launch bounds derived from
   // `known`: the active count can only grow by refills, a basis by at most
   // bs per iteration
   auto enqueue_sampling = [&](int t) -> tlr_status {
@@ -358,51 +288,23 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       TLR_HIP(hipEventCreate(&e1));
       spec.events->push_back({e0, e1});
     }
-    if (!overlap) return sample_launches(E, t, cb, st, e0, e1);
-    Handle* hh = h;
-    Progress* pr = &prog;
-    h->sworker->submit([=]() -> tlr_status {
-      tlr_status r = TLR_OK;
-      if (t >= 1) {
-        // sampling t waits for the pass-1 Cholesky QR step of iteration
-        // t - 1: it flags the tiles that converge there (skipped), and the Y
-        // copy sampling t overwrites was last read by pass 1 of t - 2
-        for (int spins = 0; pr->main_rec.load(std::memory_order_acquire) < t - 1; ++spins) {
-          if (pr->abort.load(std::memory_order_acquire)) return TLR_OK;
-          if (spins > 64) std::this_thread::yield();
-        }
-        if (hipStreamWaitEvent(ss, hh->ev_main[(t - 1) & 3], 0) != hipSuccess) r = TLR_ERR_DEVICE;
-      }
-      if (r == TLR_OK) r = sample_launches(E, t, cb, ss, e0, e1);
-      if (r == TLR_OK && hipEventRecord(hh->ev_samp[t & 3], ss) != hipSuccess) r = TLR_ERR_DEVICE;
-      if (r != TLR_OK) {
-        pr->failed.store(true, std::memory_order_release);
-        return r;
-      }
-      pr->samp_rec.store(t, std::memory_order_release);
-      return TLR_OK;
-    });
+    TLR_TRY(draw(t, E.bs));
+    if (p_blocks > 0 || bps_wa > 0)
+      TLR_HIP(launch_ara_tn(E, 0, omega_of(t), dptiles, p_blocks, spec.ldp, cb, bps_wa, tn_scratch,
+                            st));
+    if (any_z) TLR_HIP(launch_ara_z(E, dzseg, spec.p, spec.ldp, cb, bps_z, st));
+    TLR_HIP(launch_ara_seg(E, 0, cb, st, c.strip, e0, e1));
     return TLR_OK;
   };
-  // enqueue the orthogonalisation, convergence test and compaction of
-  // iteration j (its sampling enqueued before)
-  auto enqueue_orth = [&](int j) -> tlr_status {
-    AraDev E = dev_for(j, false);
-    if (overlap) {
-      E.snap_act = s.snap_act[(j + 1) & 1];
-      E.snap_counts = s.snap_counts[(j + 1) & 1];
-    }
+  // iteration j: its samples (unless drawn with the previous iteration),
+  // both Gram-Schmidt passes with the Cholesky QR steps, the compaction;
+  // with `fuse`, the sampling of j + 1 inside the second pass
+  auto enqueue = [&](int j) -> tlr_status {
+    if (spec.pt) TLR_HIP(spec.pt->mark(TLR_PHASE_SAMPLE, st));
+    if (sampled < j) TLR_TRY(enqueue_sampling(j));
+    const AraDev E = dev_for(j, false);
     const int cb = (known.cursor >= nwait) ? known.count : s_max;
     const int qb = std::min(c.qcap, known.qmax + bs * (j - known.iter - 1));
-    if (spec.pt) TLR_HIP(spec.pt->mark(TLR_PHASE_SAMPLE, st));
-    if (overlap) {
-      if (!await(prog.samp_rec, j)) {
-        const tlr_status e = h->sworker->wait();
-        if (e == TLR_OK) set_error("ARA sampling worker stopped");
-        return e == TLR_OK ? TLR_ERR_DEVICE : e;
-      }
-      TLR_HIP(hipStreamWaitEvent(st, h->ev_samp[j & 3], 0));
-    }
     const int bps_q = (qb + 31) / 32;
     if (spec.pt) TLR_HIP(spec.pt->mark(TLR_PHASE_ORTH, st));
     if (bps_q > 0) {
@@ -410,29 +312,31 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       TLR_HIP(launch_ara_seg(E, 1, cb, st));
     }
     TLR_HIP(launch_orth_step(E, 1, c.r_min, cb, st));
-    // the next iteration's sampling may start: this iteration's
-    // convergence flags are set
-    if (overlap) {
-      TLR_HIP(hipEventRecord(h->ev_main[j & 3], st));
-      prog.main_rec.store(j, std::memory_order_release);
+    const int bn = c.bs_for(j + 1, known.count);
+    if (fuse && bn == E.bs) {
+      bs_of.push_back(bn);
+      res->iter_bs.push_back(bn);
+      sampled = j + 1;
+      const AraDev S = dev_for(j + 1, true);
+      TLR_TRY(draw(j + 1, bn));
+      TLR_HIP(launch_fused_tn(S, omega_of(j + 1), dptiles, p_blocks, spec.ldp,
+                              (p_blocks > 0 || bps_wa > 0) ? cb : 0, bps_wa, tn_scratch_s, E,
+                              bps_q > 0 ? cb : 0, bps_q, tn_scratch, st));
+      TLR_HIP(launch_fused_z_seg(S, dzseg, spec.p, spec.ldp, any_z ? cb : 0, bps_z, E,
+                                 bps_q > 0 ? cb : 0, st));
+      TLR_HIP(launch_fused_seg_orth(S, cb, c.strip, E, cb, c.r_min, st));
+    } else {
+      if (bps_q > 0) {
+        TLR_HIP(launch_ara_tn(E, 2, nullptr, nullptr, 0, 0, cb, bps_q, tn_scratch, st));
+        TLR_HIP(launch_ara_seg(E, 2, cb, st));
+      }
+      TLR_HIP(launch_orth_step(E, 2, c.r_min, cb, st));
     }
-    if (bps_q > 0) {
-      TLR_HIP(launch_ara_tn(E, 2, nullptr, nullptr, 0, 0, cb, bps_q, tn_scratch, st));
-      TLR_HIP(launch_ara_seg(E, 2, cb, st));
-    }
-    TLR_HIP(launch_orth_step(E, 2, c.r_min, cb, st));
     if (spec.pt) TLR_HIP(spec.pt->mark(TLR_PHASE_BATCH, st));
     TLR_HIP(launch_ara_compact(E, s.waiting, nwait, s_max, info, ring + 8 * (j & 1), pres, res_ints,
                                st));
     TLR_HIP(hipEventRecord(h->ev_rb[j & 1], st));
     return TLR_OK;
-  };
-  auto readback_event = [&](int j) { return h->ev_rb[j & 1]; };
-  // iteration j: with the lookahead, the sampling of j + 1 is handed to the
-  // worker first (it starts after pass 1 of iteration j)
-  auto enqueue = [&](int j) -> tlr_status {
-    while (sampled < (overlap ? j + 1 : j)) TLR_TRY(enqueue_sampling(sampled + 1));
-    return enqueue_orth(j);
   };
 
   const long long limit = (long long)n * (c.qcap + 1) + 1;
@@ -452,7 +356,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     if (idle) TLR_TRY(idle());
     const int j = known.iter + 1;
     t1 = clk::now();
-    TLR_HIP(hipEventSynchronize(readback_event(j)));
+    TLR_HIP(hipEventSynchronize(h->ev_rb[j & 1]));
     t0 = clk::now();
     res->t_wait += ms(t1, t0);
     const int* r = ring + 8 * (j & 1);

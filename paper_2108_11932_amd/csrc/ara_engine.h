@@ -36,9 +36,10 @@ struct AraConfig {
   unsigned long long seed = 0;
   unsigned stream_id = 0;   // Philox counter word 2 (column index or batch id)
   int strip = 0;      // rows per workgroup of the sampling product (0: automatic, 16, 64)
-  // sample iteration t + 1 on the handle's sampling stream while iteration
-  // t is orthogonalised (only when no tile waits for a place in the active
-  // subset, so that the next active list is a subset of the current one)
+  // sample iteration t + 1 in the launches of iteration t's second
+  // Gram-Schmidt pass (only when no tile waits for a place in the active
+  // subset, so that the next active list is the current one less the tiles
+  // that converge, and for block sizes 16 and 32)
   bool overlap = true;
   // samples drawn by iteration `iter`, `active` tiles being active at its start
   int bs_for(int iter, int active) const {
@@ -68,10 +69,6 @@ struct AraSlots {
   int* f32 = nullptr;       // n: precision chosen per slot
   int* piv = nullptr;       // n x (bs + 1)
   int* waiting = nullptr;   // n
-  // snapshots of the active list for the speculative sampling: list b at
-  // snap_act[b] with its count at snap_counts[b][0]
-  int* snap_act[2] = {nullptr, nullptr};
-  int* snap_counts[2] = {nullptr, nullptr};
   long long yalt = 0, palt = 0;
   size_t qstride = 0;       // doubles per slot in Q
   double* y(int s) const { return Y + (size_t)s * m * bs; }

@@ -20,6 +20,8 @@
 // the Gram partials use error-free transformations
 #pragma clang fp contract(off)
 
+#include "ara_orth.h"
+
 namespace tlr {
 
 namespace {
@@ -72,14 +74,13 @@ __device__ inline bool tn_resolve(const AraDev& D, int mode, int tid, const doub
 // workgroup per output tile over the whole K range (one launch, partials
 // summed in LDS) measured twice as slow: a CU alone streams too little.
 template <int FN>
-__global__ __launch_bounds__(64 * TN_NW) void k_ara_tn(AraDev D, int mode, const double* omega,
-                                                        const PTile* ptiles, int p_tiles, int ldp,
-                                                        int tps, double* scratch) {
+__device__ inline void tn_body(const AraDev& D, int mode, const double* omega, const PTile* ptiles,
+                               int p_tiles, int ldp, int tps, double* scratch, int bid) {
   constexpr int FM = 2, TSZ = TN_TM * 16 * FN;
   __shared__ double red[TN_NW][FM * FN * 4][64];
   const int m = D.m, bs = D.bs;
   const int ks_n = (m + TN_KC - 1) / TN_KC;
-  const int ks = blockIdx.x % ks_n, tid = blockIdx.x / ks_n;
+  const int ks = bid % ks_n, tid = bid / ks_n;
   TnTile o;
   if (!tn_resolve(D, mode, tid, omega, ptiles, p_tiles, ldp, tps, &o)) return;
   const int k0 = ks * TN_KC, k1 = min(m, k0 + TN_KC);
@@ -88,15 +89,22 @@ __global__ __launch_bounds__(64 * TN_NW) void k_ara_tn(AraDev D, int mode, const
 }
 
 template <int FN>
-__global__ __launch_bounds__(256) void k_ara_tn_sum(AraDev D, int mode, const double* omega,
-                                                    const PTile* ptiles, int p_tiles, int ldp,
-                                                    int tps, const double* scratch) {
+__global__ __launch_bounds__(64 * TN_NW) void k_ara_tn(AraDev D, int mode, const double* omega,
+                                                        const PTile* ptiles, int p_tiles, int ldp,
+                                                        int tps, double* scratch) {
+  tn_body<FN>(D, mode, omega, ptiles, p_tiles, ldp, tps, scratch, blockIdx.x);
+}
+
+template <int FN>
+__device__ inline void tn_sum_body(const AraDev& D, int mode, const double* omega,
+                                   const PTile* ptiles, int p_tiles, int ldp, int tps,
+                                   const double* scratch, int bid) {
   constexpr int TSZ = TN_TM * 16 * FN;
   const int m = D.m, bs = D.bs;
   const int ks_n = (m + TN_KC - 1) / TN_KC;
   TnTile o;
-  if (!tn_resolve(D, mode, blockIdx.x, omega, ptiles, p_tiles, ldp, tps, &o)) return;
-  const double* part = scratch + (size_t)blockIdx.x * ks_n * TSZ;
+  if (!tn_resolve(D, mode, bid, omega, ptiles, p_tiles, ldp, tps, &o)) return;
+  const double* part = scratch + (size_t)bid * ks_n * TSZ;
   for (int e = threadIdx.x; e < TSZ; e += 256) {
     const int lr = e % TN_TM, lc = e / TN_TM;
     if (o.row0 + lr >= o.M || lc >= bs) continue;
@@ -115,14 +123,21 @@ __global__ __launch_bounds__(256) void k_ara_tn_sum(AraDev D, int mode, const do
   }
 }
 
+template <int FN>
+__global__ __launch_bounds__(256) void k_ara_tn_sum(AraDev D, int mode, const double* omega,
+                                                    const PTile* ptiles, int p_tiles, int ldp,
+                                                    int tps, const double* scratch) {
+  tn_sum_body<FN>(D, mode, omega, ptiles, p_tiles, ldp, tps, scratch, blockIdx.x);
+}
+
 // Z on the matrix cores: one wave per piece (16 rows of one block G_ij P_j),
 // four pieces per workgroup.  Lane l supplies G(l % 16, t) and P(t, l % 16)
 // for t = t0 + l / 16; the k loop loads ZCH MFMA steps ahead.
 constexpr int ZCH = 4;
 
-__global__ __launch_bounds__(256) void k_ara_z(AraDev D, const ZSeg* __restrict__ segs,
-                                               const double* __restrict__ P, int ldp, int bps) {
-  const int ai = blockIdx.x / bps, tb = blockIdx.x % bps;
+__device__ inline void z_body(const AraDev& D, const ZSeg* __restrict__ segs,
+                              const double* __restrict__ P, int ldp, int bps, int bid) {
+  const int ai = bid / bps, tb = bid % bps;
   if (ai >= D.counts[0]) return;
   const int slot = D.act[ai];
   if (D.skip && D.skip[slot]) return;
@@ -161,6 +176,11 @@ __global__ __launch_bounds__(256) void k_ara_z(AraDev D, const ZSeg* __restrict_
   }
 }
 
+__global__ __launch_bounds__(256) void k_ara_z(AraDev D, const ZSeg* __restrict__ segs,
+                                               const double* __restrict__ P, int ldp, int bps) {
+  z_body(D, segs, P, ldp, bps, blockIdx.x);
+}
+
 // MODE 0 (the sampling product) and modes 1, 2 are separate instantiations
 // so that profiles tell them apart.  A workgroup computes FM 16-row strips
 // of one tile: FM = 4 (64-row strips) reads 512 contiguous bytes of every
@@ -171,7 +191,7 @@ __global__ __launch_bounds__(256) void k_ara_z(AraDev D, const ZSeg* __restrict_
 // names (a1_prec: FP64, or the packed FP32 / BF16 panel copy with FP32
 // accumulation).
 template <int NF, int MODE, int FM>
-__global__ __launch_bounds__(256) void k_ara_seg(AraDev D) {
+__device__ inline void seg_body(const AraDev& D, int bid) {
   constexpr int mode = MODE;
   constexpr int R32 = MODE == 0 ? 4 : 1;
   __shared__ double red[4][FM * NF * 4][64];
@@ -179,7 +199,7 @@ __global__ __launch_bounds__(256) void k_ara_seg(AraDev D) {
   __shared__ double ys[16 * FM][16 * NF + 1];
   const int ns = D.nstrip;
   const int nblk = (ns + FM - 1) / FM;
-  const int ai = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+  const int ai = bid / nblk, blk = bid % nblk;
   if (ai >= D.counts[0]) return;
   const int slot = D.act[ai];
   if (D.skip && D.skip[slot]) return;
@@ -223,6 +243,66 @@ __global__ __launch_bounds__(256) void k_ara_seg(AraDev D) {
     gdouble* out = gmem(part) + (size_t)(s0 + sub) * bs * bs * 2;
     out[(a + b * bs) * 2 + 0] = v.hi;
     out[(a + b * bs) * 2 + 1] = v.lo;
+  }
+}
+
+template <int NF, int MODE, int FM>
+__global__ __launch_bounds__(256) void k_ara_seg(AraDev D) {
+  seg_body<NF, MODE, FM>(D, blockIdx.x);
+}
+
+
+// ---------------------------------------------------- fused launches
+// The sampling of ARA iteration t + 1 needs only the convergence flags of
+// iteration t (it skips the tiles they name), so it is computed in the same
+// launches as the second Gram-Schmidt pass of iteration t: the first blocks
+// of each launch do the one, the others the other.  Both halves run
+// concurrently without a second stream, and the host issues one launch for
+// two.
+//   tn     : P, W^A of t + 1 (mode 0)   |  C = -Q^T X of t (mode 2), split K
+//   tn_sum : their partial sums
+//   z_seg  : Z of t + 1                 |  X += Q C of t (mode 2)
+//   seg_orth: Y of t + 1 (mode 0)       |  pass-2 Cholesky QR of t
+template <int FN>
+__global__ __launch_bounds__(64 * TN_NW) void k_fuse_tn(AraDev Da, const double* omega,
+                                                         const PTile* ptiles, int p_tiles, int ldp,
+                                                         int tpsa, double* scra, int na, AraDev Db,
+                                                         int tpsb, double* scrb) {
+  if ((int)blockIdx.x < na)
+    tn_body<FN>(Da, 0, omega, ptiles, p_tiles, ldp, tpsa, scra, blockIdx.x);
+  else
+    tn_body<FN>(Db, 2, nullptr, nullptr, 0, 0, tpsb, scrb, blockIdx.x - na);
+}
+
+template <int FN>
+__global__ __launch_bounds__(256) void k_fuse_tn_sum(AraDev Da, const double* omega,
+                                                     const PTile* ptiles, int p_tiles, int ldp,
+                                                     int tpsa, const double* scra, int na,
+                                                     AraDev Db, int tpsb, const double* scrb) {
+  if ((int)blockIdx.x < na)
+    tn_sum_body<FN>(Da, 0, omega, ptiles, p_tiles, ldp, tpsa, scra, blockIdx.x);
+  else
+    tn_sum_body<FN>(Db, 2, nullptr, nullptr, 0, 0, tpsb, scrb, blockIdx.x - na);
+}
+
+template <int NF>
+__global__ __launch_bounds__(256) void k_fuse_z_seg(AraDev Dz, const ZSeg* __restrict__ segs,
+                                                    const double* __restrict__ P, int ldp, int bps,
+                                                    int nz, AraDev Ds) {
+  if ((int)blockIdx.x < nz)
+    z_body(Dz, segs, P, ldp, bps, blockIdx.x);
+  else
+    seg_body<NF, 2, 1>(Ds, blockIdx.x - nz);
+}
+
+template <int NF, int FM, int BS>
+__global__ __launch_bounds__(256) void k_fuse_seg_orth(AraDev D0, int n0, AraDev D2, int r_min,
+                                                       int gx) {
+  if ((int)blockIdx.x < n0) {
+    seg_body<NF, 0, FM>(D0, blockIdx.x);
+  } else {
+    const int b = blockIdx.x - n0;
+    orth_body<BS, false>(D2, r_min, b % gx, b / gx);
   }
 }
 
@@ -299,6 +379,75 @@ hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_
                 : seg_launch<1, 1>(D, mode, count_bound, s, start, stop);
   return tall ? seg_launch<2, 4>(D, mode, count_bound, s, start, stop)
               : seg_launch<2, 1>(D, mode, count_bound, s, start, stop);
+}
+
+bool fused_block_supported(int bs) { return bs == 16 || bs == 32; }
+
+hipError_t launch_fused_tn(const AraDev& Da, const double* omega, const PTile* ptiles, int p_tiles,
+                           int ldp, int cba, int tpsa, double* scra, const AraDev& Db, int cbb,
+                           int tpsb, double* scrb, hipStream_t s) {
+  if (Da.bs != Db.bs || !fused_block_supported(Da.bs)) return hipErrorInvalidValue;
+  const int ks_n = (Da.m + TN_KC - 1) / TN_KC;
+  const long long ta = p_tiles + (long long)std::max(cba, 0) * std::max(tpsa, 0);
+  const long long tb = (long long)std::max(cbb, 0) * std::max(tpsb, 0);
+  if (ta + tb <= 0) return hipSuccess;
+  const int pa = std::max(tpsa, 1), pb = std::max(tpsb, 1);
+  const unsigned na = (unsigned)(ta * ks_n), ns = (unsigned)((ta + tb) * ks_n);
+  const unsigned ma = (unsigned)ta, ms = (unsigned)(ta + tb);
+  if (Da.bs <= 16) {
+    hipLaunchKernelGGL((k_fuse_tn<1>), dim3(ns), dim3(64 * TN_NW), 0, s, Da, omega, ptiles, p_tiles,
+                       ldp, pa, scra, (int)na, Db, pb, scrb);
+    hipLaunchKernelGGL((k_fuse_tn_sum<1>), dim3(ms), dim3(256), 0, s, Da, omega, ptiles, p_tiles,
+                       ldp, pa, scra, (int)ma, Db, pb, scrb);
+  } else {
+    hipLaunchKernelGGL((k_fuse_tn<2>), dim3(ns), dim3(64 * TN_NW), 0, s, Da, omega, ptiles, p_tiles,
+                       ldp, pa, scra, (int)na, Db, pb, scrb);
+    hipLaunchKernelGGL((k_fuse_tn_sum<2>), dim3(ms), dim3(256), 0, s, Da, omega, ptiles, p_tiles,
+                       ldp, pa, scra, (int)ma, Db, pb, scrb);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_z_seg(const AraDev& Dz, const ZSeg* segs, const double* P, int ldp, int cbz,
+                              int bps, const AraDev& Ds, int cbs, hipStream_t s) {
+  if (Dz.bs != Ds.bs || !fused_block_supported(Ds.bs)) return hipErrorInvalidValue;
+  const long long nz = (long long)std::max(cbz, 0) * std::max(bps, 0);
+  const long long ns = (long long)std::max(cbs, 0) * Ds.nstrip;
+  if (nz + ns <= 0) return hipSuccess;
+  const dim3 g((unsigned)(nz + ns)), b(256);
+  if (Ds.bs <= 16)
+    hipLaunchKernelGGL((k_fuse_z_seg<1>), g, b, 0, s, Dz, segs, P, ldp, std::max(bps, 1), (int)nz,
+                       Ds);
+  else
+    hipLaunchKernelGGL((k_fuse_z_seg<2>), g, b, 0, s, Dz, segs, P, ldp, std::max(bps, 1), (int)nz,
+                       Ds);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_seg_orth(const AraDev& D0, int cb0, int strip, const AraDev& D2, int cb2,
+                                 int r_min, hipStream_t s) {
+  if (D0.bs != D2.bs || !fused_block_supported(D2.bs)) return hipErrorInvalidValue;
+  const bool tall = strip == 64 || (strip == 0 && (long long)std::max(cb0, 0) *
+                                                         ((D0.nstrip + 3) / 4) >= kTallWgs);
+  const int fm = tall ? 4 : 1;
+  const long long n0 = (long long)std::max(cb0, 0) * ((D0.nstrip + fm - 1) / fm);
+  const int gx = (D2.m + APPLY_ROWS - 1) / APPLY_ROWS;
+  const long long n2 = (long long)gx * std::max(cb2, 0);
+  if (n0 + n2 <= 0) return hipSuccess;
+  const dim3 g((unsigned)(n0 + n2)), b(256);
+  static_assert(APPLY_ROWS == 256, "the fused launch runs 256 threads per block");
+  if (D2.bs == 16) {
+    if (tall)
+      hipLaunchKernelGGL((k_fuse_seg_orth<1, 4, 16>), g, b, 0, s, D0, (int)n0, D2, r_min, gx);
+    else
+      hipLaunchKernelGGL((k_fuse_seg_orth<1, 1, 16>), g, b, 0, s, D0, (int)n0, D2, r_min, gx);
+  } else {
+    if (tall)
+      hipLaunchKernelGGL((k_fuse_seg_orth<2, 4, 32>), g, b, 0, s, D0, (int)n0, D2, r_min, gx);
+    else
+      hipLaunchKernelGGL((k_fuse_seg_orth<2, 1, 32>), g, b, 0, s, D0, (int)n0, D2, r_min, gx);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace tlr

@@ -208,7 +208,6 @@ struct tlr_matrix_s {
   hipStream_t side = nullptr;     // library stream for the diagonal tiles (default priority)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gnext = nullptr;
   std::unique_ptr<tlr::SideWorker> worker;   // issues the side-stream launches
-  std::unique_ptr<tlr::SideWorker> sworker;  // issues the ARA sampling launches
   Staging stage;
   tlr::PhaseTimer pt_main, pt_side;   // TLR_FLAG_PHASE_TIMING
 
@@ -258,11 +257,6 @@ struct tlr_matrix_s {
   int* pin_res = nullptr;         // pinned read-back of an ARA run's per-slot results
   size_t pin_res_n = 0;
   hipEvent_t ev_rb[2] = {nullptr, nullptr};
-  // library stream of the ARA sampling launches, which run one iteration
-  // ahead of the orthogonalisation on the caller's stream (default
-  // priority), and the events that order the two
-  hipStream_t samp = nullptr;
-  hipEvent_t ev_sfork = nullptr, ev_samp[4] = {}, ev_main[4] = {};
   size_t pin_norm_n = 0;
 
   Work ws;
@@ -308,7 +302,6 @@ struct tlr_matrix_s {
   tlr_status pinned_norms(size_t n, double** p);
   tlr_status readback_ring(int** p);
   tlr_status readback_results(size_t n, int** p);   // pinned, n ints
-  tlr_status samp_stream();       // creates samp and its events on first use
   void release_host();            // pinned buffers and events
 };
 

@@ -241,30 +241,9 @@ tlr_status tlr_matrix_s::readback_results(size_t n, int** p) {
   return TLR_OK;
 }
 
-tlr_status tlr_matrix_s::samp_stream() {
-  if (samp) return TLR_OK;
-  TLR_HIP(hipEventCreateWithFlags(&ev_sfork, hipEventDisableTiming));
-  for (int i = 0; i < 4; ++i) {
-    TLR_HIP(hipEventCreateWithFlags(&ev_samp[i], hipEventDisableTiming));
-    TLR_HIP(hipEventCreateWithFlags(&ev_main[i], hipEventDisableTiming));
-  }
-  TLR_HIP(hipStreamCreateWithFlags(&samp, hipStreamNonBlocking));
-  return TLR_OK;
-}
-
 void tlr_matrix_s::release_host() {
   pt_main.destroy();
   pt_side.destroy();
-  if (samp) {
-    (void)hipStreamSynchronize(samp);
-    (void)hipStreamDestroy(samp);
-    samp = nullptr;
-  }
-  for (hipEvent_t* e : {&ev_sfork, &ev_samp[0], &ev_samp[1], &ev_samp[2], &ev_samp[3], &ev_main[0],
-                        &ev_main[1], &ev_main[2], &ev_main[3]}) {
-    if (*e) (void)hipEventDestroy(*e);
-    *e = nullptr;
-  }
   if (pin_norm) (void)hipHostFree(pin_norm);
   if (pin_ring) (void)hipHostFree(pin_ring);
   if (pin_res) (void)hipHostFree(pin_res);

@@ -179,10 +179,6 @@ struct AraDev {
   // part1 plus these offsets (doubles), so that the sampling of the next
   // iteration can fill the other copy while this one is orthogonalised
   long long yoff, poff;
-  // when set, the compaction also stores its output list and count here
-  // (the list the next iteration's speculative sampling reads)
-  int* snap_act;
-  int* snap_counts;
   // when set, the sampling launches skip the slots with skip[slot] != 0
   // (the convergence flags of the iteration before)
   const int* skip;
@@ -231,6 +227,18 @@ hipError_t launch_ara_z(const AraDev& D, const ZSeg* segs, const double* P, int 
 // events record the launch's own begin and end.
 hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_t s, int strip = 0,
                           hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+// Fused launches of one ARA iteration step: the sampling of iteration t + 1
+// (Da / Dz / D0: mode 0, its tiles less the ones the flags of t name)
+// together with the second Gram-Schmidt pass of iteration t (Db / Ds / D2).
+// Block sizes 16 and 32 only (fused_block_supported), the same in both.
+bool fused_block_supported(int bs);
+hipError_t launch_fused_tn(const AraDev& Da, const double* omega, const PTile* ptiles, int p_tiles,
+                           int ldp, int cba, int tpsa, double* scra, const AraDev& Db, int cbb,
+                           int tpsb, double* scrb, hipStream_t s);
+hipError_t launch_fused_z_seg(const AraDev& Dz, const ZSeg* segs, const double* P, int ldp, int cbz,
+                              int bps, const AraDev& Ds, int cbs, hipStream_t s);
+hipError_t launch_fused_seg_orth(const AraDev& D0, int cb0, int strip, const AraDev& D2, int cb2,
+                                 int r_min, hipStream_t s);
 // Cholesky QR step of pass 1 (pivoted, thresholded: appends the accepted
 // directions of Y to Q, sets qnew, flag, pivots, iteration counters and the
 // Gram partials of the new columns) or pass 2 (re-orthonormalises the new
