@@ -28,20 +28,45 @@ import numpy as np
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 # measured HBM traffic of the sampling kernel (rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, calibrated on a plain copy); valid only for the kernel sources
-# it was measured on
+# WRITE_SIZE, calibrated on a plain copy); valid only for the sources it was
+# measured on: the sampling kernels and the engine that schedules them
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sampling_traffic_cov2d_131k.txt")
-KERNEL_SOURCES = ["paper_2108_11932_amd/csrc/ara_iter.hip", "paper_2108_11932_amd/csrc/mfma_tiles.h",
-                  "paper_2108_11932_amd/csrc/tlr_internal.h"]
+KERNEL_SOURCES = ["paper_2108_11932_amd/csrc/ara_iter.hip", "paper_2108_11932_amd/csrc/ara_orth.h",
+                  "paper_2108_11932_amd/csrc/dd.h", "paper_2108_11932_amd/csrc/mfma_tiles.h",
+                  "paper_2108_11932_amd/csrc/tlr_internal.h",
+                  "paper_2108_11932_amd/csrc/ara_engine.cpp"]
+# per-kernel roofline table of the headline factorization (time share, FP64
+# matrix-core and HBM fractions from rocprofv3 counters); valid for the
+# library sources it was measured on
+TABLE_FILE = os.path.join(ROOT, "profiles", "roofline_table_cov2d_131k.txt")
+CSRC = os.path.join(ROOT, "paper_2108_11932_amd", "csrc")
+
+
+def _sha256(paths) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in paths:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def kernel_source_hash() -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    return _sha256(os.path.join(ROOT, f) for f in KERNEL_SOURCES)
+
+
+def library_source_hash() -> str:
+    return _sha256(os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)))
+
+
+def _key_values(path):
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#") and "|" not in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    return kv
 
 
 def measured_traffic(workload: str):
@@ -49,17 +74,45 @@ def measured_traffic(workload: str):
     summary, or None when it is absent, for another workload, or taken on
     other kernel sources."""
     try:
-        kv = {}
-        with open(TRAFFIC_FILE) as fh:
-            for line in fh:
-                if ":" in line and not line.startswith("#"):
-                    k, v = line.split(":", 1)
-                    kv[k.strip()] = v.strip()
+        kv = _key_values(TRAFFIC_FILE)
         if kv.get("workload") != workload or kv.get("source_sha256") != kernel_source_hash():
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def kernel_table(workload: str, top: int = 14):
+    """The leading rows of the committed per-kernel roofline table (share of
+    GPU time, FP64 matrix-core and HBM fractions, bound), and whether it was
+    measured on the library sources of this tree."""
+    try:
+        kv = _key_values(TABLE_FILE)
+        if kv.get("workload") != workload:
+            return None
+        rows, head = [], None
+        with open(TABLE_FILE) as fh:
+            for line in fh:
+                if "|" not in line or line.startswith("#"):
+                    continue
+                cells = [c.strip() for c in line.split("|")]
+                if head is None:
+                    head = cells
+                    continue
+                r = dict(zip(head, cells))
+                rows.append({"kernel": r["kernel"], "calls": int(r["calls"]),
+                             "share": float(r["share"]), "avg_us": float(r["time_us"]) / int(r["calls"]),
+                             "mfma_f64_tflops": float(r["mfma_f64_tflops"]),
+                             "frac_mfma_f64": float(r["frac_mfma_f64"]),
+                             "hbm_gbs": float(r["hbm_gbs"]), "frac_hbm": float(r["frac_hbm"]),
+                             "bound": r["bound"]})
+        return {"source": os.path.relpath(TABLE_FILE, ROOT),
+                "measured_on_these_sources": kv.get("source_sha256") == library_source_hash(),
+                "rows": rows[:top]}
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 METRIC = "TLR Cholesky time-to-solution + TFLOP/s, N=131072 eps=1e-6; FP64 vs mixed"
 
 
@@ -81,9 +134,12 @@ def cpu_baseline(w, n_sample: int, tlr, torch):
     from oracle import tlr as otlr
     try:
         from threadpoolctl import threadpool_info
-        cores = max((d.get("num_threads", 1) for d in threadpool_info()), default=os.cpu_count())
+        blas = [d for d in threadpool_info() if d.get("user_api") == "blas"]
+        cores = max((d.get("num_threads", 1) for d in blas), default=os.cpu_count())
+        vendor = ", ".join("%s %s (%s)" % (d.get("internal_api"), d.get("version"),
+                                           d.get("threading_layer")) for d in blas) or "unknown"
     except Exception:  # pragma: no cover
-        cores = os.cpu_count()
+        cores, vendor = os.cpu_count(), "unknown"
     pts = np.ascontiguousarray(w.points[:n_sample])
     a_s = otlr.compress_kernel(pts, w.m, w.kernel, w.ell, w.diag_add, w.eps)
     t0 = time.perf_counter()
@@ -104,7 +160,7 @@ def cpu_baseline(w, n_sample: int, tlr, torch):
                       "left-looking TLR Cholesky with truncated-SVD recompression (numpy/LAPACK "
                       "FP64); work = the GPU algorithm's executed flops on that block (%.3g)"
                       % (n_sample, n_sample, a_s.nb, w.m, st["flops"]),
-            "oracle_seconds": t_cpu, "gpu_seconds_same_sample": t_gpu}
+            "blas": vendor, "oracle_seconds": t_cpu, "gpu_seconds_same_sample": t_gpu}
 
 
 def residual(mat, torch, nvec: int = 4, seed: int = 7) -> float:
@@ -120,14 +176,17 @@ def residual(mat, torch, nvec: int = 4, seed: int = 7) -> float:
 
 
 def time_form(mat, w, eps_mode, precision, tlr, torch, steps, warmup, bs_tail=0, tail_active=0,
-              timing=True, idle_s=0.0):
+              timing=True, idle_s=0.0, serial=False):
     """Warm up, then time `steps` factorizations of one form (with the
-    sampling launches timed by their own events when `timing`); the GPU
-    idles idle_s seconds between the warm-up and the timed steps (a marker
-    for profile reductions)."""
+    sampling launches timed by their own events when `timing`, which runs
+    every sampling product in a launch of its own); the GPU idles idle_s
+    seconds between the warm-up and the timed steps (a marker for profile
+    reductions).  `serial` asks for that same launch schedule without the
+    events (for counter runs that match the timed launches)."""
     o = tlr.opts(bs=w.bs, bs_tail=bs_tail, tail_active=tail_active, eps_mode=eps_mode,
                  precision=precision,
-                 flags=tlr.FLAG_KERNEL_TIMING if timing else 0)
+                 flags=(tlr.FLAG_KERNEL_TIMING if timing else 0) |
+                       (tlr.FLAG_SERIAL_SAMPLING if serial else 0))
     for _ in range(warmup):
         mat.potrf(w.eps, o)
     torch.cuda.synchronize()
@@ -401,6 +460,10 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="for profilers: build the input, run the --warmup and --steps "
                          "factorizations and stop (no second pass, residual or other lines)")
+    ap.add_argument("--serial", action="store_true",
+                    help="with --profile: run each sampling product in a launch of its own (the "
+                         "schedule of the pass that times them with events), for the HBM counters "
+                         "of the roofline")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM "
                          "byte counters against a kernel of known traffic)")
@@ -458,11 +521,13 @@ def main():
         mat.close()
         return
     dt, stats = time_form(mat, w, w.eps_mode, tlr.FP64, tlr, torch, a.steps, a.warmup, a.bs_tail,
-                          a.tail_active, False, 0.05 if a.profile else 0.0)
+                          a.tail_active, False, 0.05 if a.profile else 0.0,
+                          a.profile and a.serial)
     print("[bench] %d timed steps, %.1f ms each" % (a.steps, dt * 1e3), file=sys.stderr, flush=True)
     if a.profile:
-        print(json.dumps({"profile": w.name, "ms_per_step": dt * 1e3,
-                          "ara_iterations": int(stats[-1]["ara_iters"])}), flush=True)
+        print(json.dumps({"profile": w.name, "ms_per_step": dt * 1e3, "serial": a.serial,
+                          "ara_iterations": int(stats[-1]["ara_iters"]),
+                          "sample_bytes": stats[-1]["sample_bytes"]}), flush=True)
         mat.close()
         return
     dt_ev, stats_ev = (time_form(mat, w, w.eps_mode, tlr.FP64, tlr, torch, a.steps, 0, a.bs_tail, a.tail_active, True)
@@ -521,6 +586,7 @@ def main():
         "residual": err_primary,
         "forms": forms,
         "phases": phases,
+        "kernels": kernel_table(w.name),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name),
                      "kernel": "Schur-complement sampling product Y_i -= U_i* Z_i",

@@ -215,13 +215,16 @@ def _parse_table(path: str):
 
 
 HBM_PEAK = 8.0e12
+LATENCY_FRAC = 0.10
 
 
 def table(mfma: str, fetch: str, write: str) -> str:
     """Per-kernel roofline table of one factorization from the `counters`
     summaries of an MFMA-op run and of the FETCH_SIZE and WRITE_SIZE runs
     (calibrated KiB): time, achieved FP64 matrix-core rate and HBM rate, and
-    their fractions of the MI355X peaks; `bound` names the larger one."""
+    their fractions of the MI355X peaks; `bound` names the larger one, or
+    `latency` when neither reaches LATENCY_FRAC of its peak (a chain of
+    dependent steps or a launch too small to fill the chip)."""
     mf, fe, wr = _parse_table(mfma), _parse_table(fetch), _parse_table(write)
     tot = sum(v.get("time_us", 0.0) for v in mf.values())
     out = ["kernel | calls | time_us | share | mfma_f64_tflops | frac_mfma_f64 | hbm_gbs | "
@@ -236,7 +239,8 @@ def table(mfma: str, fetch: str, write: str) -> str:
         fm, fh = fl / t / PEAK["F64"], by / t / HBM_PEAK
         out.append("%s | %d | %.1f | %.3f | %.3f | %.4f | %.1f | %.4f | %s" %
                    (k, int(v.get("calls", 0)), v["time_us"], v["time_us"] / tot, fl / t / 1e12, fm,
-                    by / t / 1e9, fh, "mfma" if fm >= fh else "hbm"))
+                    by / t / 1e9, fh,
+                    "latency" if max(fm, fh) < LATENCY_FRAC else ("mfma" if fm >= fh else "hbm")))
     return "\n".join(out)
 
 
