@@ -1,16 +1,19 @@
-// Dense tile kernels: the latency-bound pieces of the blocked Cholesky and
-// unpivoted LDL^T of the diagonal tiles, and the diagonal-block step of the
-// blocked triangular solve.
+// Dense tile kernels: the blocked Cholesky and unpivoted LDL^T of the
+// diagonal tiles, and the diagonal-block step of the blocked triangular solve.
 //
 // The diagonal tile factorization is the "chol" (Algorithm "Left Looking TLR
 // Cholesky") and "ldl" (Algorithm "Left Looking TLR LDL^T", unpivoted with
-// scalar pivots) step of the paper.  The tile is factored by blocks of 32
-// columns: one launch per block factors the 32 x 32 diagonal block and
-// solves the panel below it (L21 = A21 L11^{-T}), the trailing update runs
-// as an MFMA GEMM.  The diagonal-block inverses, taken afterwards for all
-// blocks in one launch, seed the assembly of L_kk^{-1}, so the batched
-// triangular solve of a column ("batchTrsm", one triangle shared by every
-// tile) becomes one product.
+// scalar pivots) step of the paper.  The tile is factored right-looking by
+// panels of 32 columns with one launch per panel: the launch for panel p
+// solves the panel below its diagonal block with the block's explicit
+// inverse (L21 = A21 L11^{-T}, one MFMA product), applies the rank-32
+// trailing update on MFMA, and the workgroup that owns the next diagonal
+// block then factors that block and inverts it in the same pass (Gauss-
+// Jordan elimination beside the factorization), so that the next launch
+// finds L11 and L11^{-1} ready.  The diagonal-block inverses also seed the
+// assembly of L_kk^{-1}, by which the batched triangular solve of a column
+// ("batchTrsm", one triangle shared by every tile) becomes one product.
+#include "mfma_tiles.h"
 #include "tlr_internal.h"
 
 namespace tlr {
@@ -19,195 +22,286 @@ namespace {
 
 constexpr int NB = 64;   // block size of the blocked triangular solve
 constexpr int ND = 32;   // diagonal block of the blocked factorizations
+constexpr int TT = 64;   // trailing-update tile
 
-// Broadcast lane `lane` (a compile-time constant) of a double to the wave.
-__device__ __forceinline__ double lane_bcast(double v, int lane) {
-  const unsigned long long b = __double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, lane);
-  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), lane);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// Panel step of the blocked right-looking factorization.  Every workgroup
-// (one wave) factors the w x w (w <= 32) diagonal block at (p0, p0) of A on
-// its own -- Cholesky, or unit LDL^T with scalar pivots -- and then solves
-// for its 64 rows of the panel below: Cholesky L21 = A21 L11^{-T} in place;
-// LDL^T W21 = A21 L11^{-T} into W (row p0 + w + i at W[i], ld ldw) and
-// L21 = W21 D^{-1} in place.  The factorization is deterministic, so every
-// workgroup reaches the same L11; workgroup 0 stores the pivots, the
-// failure record and L11 itself -- not into A, whose diagonal block the
-// other workgroups may still be reading, but into Lst (ld ldst, zeros above
-// the diagonal), from where the diagonal-block inversion moves it into A.
+// One wave factors the w x w (w <= 32) symmetric block S (LDS, lower
+// triangle read, ld ND + 1) whose top-left entry sits at (b0, b0) of the
+// tile A: Cholesky S = L L^T, or unit LDL^T S = L D L^T with scalar
+// pivots.  L goes to A (zeros above its diagonal); L^{-1} (the unit
+// inverse for LDL^T) to Inv at (b0, b0) (zeros above); the pivots to
+// dvec[b0..] (LDL^T).
 //
-// Factor: lanes r and r + 32 hold the two halves of row r of the block in
-// registers (rows and columns beyond w are the identity, which leaves the
-// real part unchanged).  Right-looking: at step j the lanes holding column
-// j put it into LDS, and by symmetry that column is also row j, so each
-// lane reads d = S(j, j), its own S(r, j) and the S(c, j) of its half as
-// LDS broadcasts and subtracts S(r, j) S(c, j) / d from S(r, c); column j
-// of the factor goes to LDS at once.  Two column buffers alternate.  Solve: thread i takes row p0 + w + 64 b
-// + i of A21 and runs the forward substitution against L11 (LDS) along it.
+// Lanes r and r + 32 hold the two halves of row r of S, and of row r of
+// X, in registers (rows and columns beyond w are the identity, which leaves
+// the real part unchanged).  At step j the lanes holding column j put it
+// into LDS, and by symmetry that column is also row j, so each lane reads
+// d = S(j, j), its own S(r, j) and the S(c, j) of its half as LDS
+// broadcasts and subtracts l_rj S(j, c) from S(r, c), l_rj = S(r, j) / d.
+// The same row operation applied to X, which starts as the identity,
+// leaves X = L_unit^{-1} after the last step (Gauss-Jordan elimination:
+// the product of the elimination matrices), with row j of X read from the
+// two lanes that hold it; L^{-1} = D^{-1/2} X for Cholesky.
+//
+// info receives the 1-based row (row_base + b0 + j + 1) of the first
+// failing pivot (the pivot is then taken as 1 so that the factor stays
+// finite).  LDL^T: a pivot fails when |d| <= *tolp.  Cholesky: when d <= 0,
+// or, with tolp set (modified Cholesky), d becomes max(|d|, *tolp) and is
+// counted in info[1] instead.
 template <bool CHOL>
-__global__ __launch_bounds__(64) void k_chol_panel(double* A, int lda, int m, int p0, int w,
-                                                   double* W, int ldw, double* Lst, int ldst,
-                                                   double* dvec, int* info, int row_base,
-                                                   const double* tolp) {
+__device__ __forceinline__ void factor_block(const double (*S)[ND + 1], int w, double* A, int lda, int b0,
+                                    double* Inv, int ldi, double* dvec, int* info, int row_base,
+                                    const double* tolp) {
   __shared__ double colb[2][ND];
-  __shared__ double Ls[ND][ND + 1];   // Ls[r][q] = L(r, q), q <= r
-  __shared__ double Rd[ND];           // 1 / L(c, c) (Cholesky)
-  __shared__ double Ds[ND];           // LDL^T pivots
-  const int lane = threadIdx.x;
+  __shared__ double xrow[2][ND];
+  __shared__ double Ls[ND][ND + 1];   // Ls[r][j] = L(r, j)
+  const int lane = threadIdx.x & 63;
   const int r = lane & (ND - 1);
-  const int hf = lane >> 5;         // this lane holds columns [16 hf, 16 hf + 16) of row r
-  const bool act = lane < ND;
+  const int hf = lane >> 5;   // this lane holds columns [16 hf, 16 hf + 16) of row r
   constexpr int HC = ND / 2;
-  double row[HC];
+  double row[HC], xr[HC];
 #pragma unroll
   for (int cc = 0; cc < HC; ++cc) {
     const int c = HC * hf + cc;
     double v = (r == c) ? 1.0 : 0.0;
-    if (r < w && c < w && c <= r) v = A[(p0 + r) + (size_t)(p0 + c) * lda];
+    if (r < w && c < w && c <= r) v = S[r][c];
     row[cc] = v;
+    xr[cc] = (r == c) ? 1.0 : 0.0;
   }
-  // Cholesky with tolp set: modified Cholesky, a non-positive pivot d is
-  // replaced by max(|d|, delta), delta = *tolp (a diagonal perturbation of
-  // the tile that keeps the pivot as large as the loss it repairs) and
-  // counted in info[1] instead of failing
   const bool modify = CHOL && tolp != nullptr;
   const double tol = CHOL ? (modify ? *tolp : 0.0) : *tolp;
   int bad_row = 0, nmod = 0;
+  double my_rs = 1.0, my_d = 1.0;
+  // the steps in two halves of 16 (a fully unrolled loop of 32 lets the
+  // compiler hoist across steps until the registers run out)
+#pragma unroll 1
+  for (int hb = 0; hb < 2; ++hb) {
 #pragma unroll
-  for (int j = 0; j < ND; ++j) {
-    double* cb = colb[j & 1];
-    if (hf == j / HC) cb[r] = row[j % HC];
-    // the workgroup is one wave, whose LDS operations complete in issue
-    // order: the reads below see the write above without a wait for it
-    __builtin_amdgcn_wave_barrier();
-    // all reads of the step in flight at once
-    double d = cb[j];
-    const double a = cb[r];              // S(r, j)
-    double cv[HC];
+    for (int jj = 0; jj < HC; ++jj) {
+      const int j = HC * hb + jj;
+      double* cb = colb[jj & 1];
+      double* xb = xrow[jj & 1];
+      if (hf == hb) cb[r] = row[jj];
+      if (r == j) {
 #pragma unroll
-    for (int cc = 0; cc < HC; ++cc) cv[cc] = cb[HC * hf + cc];
-    __builtin_amdgcn_sched_barrier(0);
-    const bool bad = CHOL ? !(d > 0.0) : !(fabs(d) > tol);
-    if (bad && modify) {
-      if (j < w) ++nmod;
-      d = fmax(fabs(d), tol);
-    } else if (bad) {
-      if (j < w && bad_row == 0) bad_row = row_base + p0 + j + 1;
-      d = 1.0;
-    }
-    // 1/sqrt(d) (Cholesky) or 1/d from the hardware estimate and two Newton
-    // steps: a handful of FMAs instead of the division and square-root
-    // sequences on the step's dependency chain
-    double rs = 0.0, rd;
-    if (CHOL) {
-      rs = __builtin_amdgcn_rsq(d);
-#pragma unroll
-      for (int it = 0; it < 2; ++it) rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
-      rd = rs * rs;
-    } else {
-      rd = __builtin_amdgcn_rcp(d);
-#pragma unroll
-      for (int it = 0; it < 2; ++it) rd = fma(rd, fma(-d, rd, 1.0), rd);
-    }
-    const double mr = a * rd;            // l_rj of the unit factor
-    // every column of the half (finished columns and the upper triangle
-    // only collect values that are never read again)
-#pragma unroll
-    for (int cc = 0; cc < HC; ++cc) row[cc] = fma(-mr, cv[cc], row[cc]);
-    double lv;
-    if (CHOL) {
-      lv = (r == j) ? d * rs : (r > j ? a * rs : 0.0);
-      if (lane == j) Rd[j] = rs;
-    } else {
-      lv = (r == j) ? 1.0 : (r > j ? mr : 0.0);
-      if (lane == j) Ds[j] = d;
-    }
-    if (act) Ls[r][j] = lv;
-  }
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    if (bad_row && lane == 0) atomicCAS(info, 0, bad_row);
-    if (nmod && lane == 0) atomicAdd(info + 1, nmod);
-#pragma unroll
-    for (int q = 0; q < ND; ++q)
-      if (act && r < w && q < w) Lst[r + (size_t)q * ldst] = (q <= r) ? Ls[r][q] : 0.0;
-    if (!CHOL && act && r < w) dvec[p0 + r] = Ds[r];
-  }
-  __syncthreads();
-  const int i = blockIdx.x * 64 + lane;
-  const int gr = p0 + w + i;
-  if (gr >= m) return;
-  double x[ND];
-#pragma unroll
-  for (int c = 0; c < ND; ++c) x[c] = (c < w) ? A[gr + (size_t)(p0 + c) * lda] : 0.0;
-#pragma unroll
-  for (int c = 0; c < ND; ++c) {
-    double v = x[c];
-#pragma unroll
-    for (int q = 0; q < c; ++q) v = fma(-x[q], Ls[c][q], v);
-    x[c] = CHOL ? v * Rd[c] : v;
-    // x[c] is finished here and row c + 1 of L11 is read only afterwards
-    // (the compiler would otherwise read every row first and sink the
-    // arithmetic to the stores, holding ~500 values in registers)
-    asm volatile("" : "+v"(x[c])::"memory");
-  }
-#pragma unroll
-  for (int c = 0; c < ND; ++c) {
-    if (c < w) {
-      if (CHOL) {
-        A[gr + (size_t)(p0 + c) * lda] = x[c];
-      } else {
-        W[i + (size_t)c * ldw] = x[c];
-        A[gr + (size_t)(p0 + c) * lda] = x[c] / Ds[c];
+        for (int cc = 0; cc < HC; ++cc) xb[HC * hf + cc] = xr[cc];
       }
+      // the caller runs this on one wave, whose LDS operations complete in
+      // issue order: the reads below see the writes above without a wait
+      __builtin_amdgcn_wave_barrier();
+      double d = cb[j];
+      const double a = cb[r];   // S(r, j)
+      double cv[HC], xv[HC];
+#pragma unroll
+      for (int cc = 0; cc < HC; ++cc) {
+        cv[cc] = cb[HC * hf + cc];
+        xv[cc] = xb[HC * hf + cc];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      const bool bad = CHOL ? !(d > 0.0) : !(fabs(d) > tol);
+      if (bad && modify) {
+        if (j < w) ++nmod;
+        d = fmax(fabs(d), tol);
+      } else if (bad) {
+        if (j < w && bad_row == 0) bad_row = row_base + b0 + j + 1;
+        d = 1.0;
+      }
+      // 1/sqrt(d) (Cholesky) or 1/d from the hardware estimate and two
+      // Newton steps: a handful of FMAs instead of the division and
+      // square-root sequences on the step's dependency chain
+      double rs = 0.0, rd;
+      if (CHOL) {
+        rs = __builtin_amdgcn_rsq(d);
+#pragma unroll
+        for (int it = 0; it < 2; ++it) rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+        rd = rs * rs;
+      } else {
+        rd = __builtin_amdgcn_rcp(d);
+#pragma unroll
+        for (int it = 0; it < 2; ++it) rd = fma(rd, fma(-d, rd, 1.0), rd);
+      }
+      const double mr = a * rd;   // l_rj of the unit factor (r > j)
+      // every column of the half of S (finished columns and the upper
+      // triangle only collect values that are never read again); X only on
+      // the rows below j
+      const double xm = (r > j) ? mr : 0.0;
+#pragma unroll
+      for (int cc = 0; cc < HC; ++cc) {
+        row[cc] = fma(-mr, cv[cc], row[cc]);
+        xr[cc] = fma(-xm, xv[cc], xr[cc]);
+      }
+      if (r == j) {
+        my_rs = rs;
+        my_d = d;
+      }
+      double lv;
+      if (CHOL)
+        lv = (r == j) ? d * rs : (r > j ? a * rs : 0.0);
+      else
+        lv = (r == j) ? 1.0 : (r > j ? mr : 0.0);
+      if (hf == 0) Ls[r][j] = lv;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (bad_row && lane == 0) atomicCAS(info, 0, bad_row);
+  if (nmod && lane == 0) atomicAdd(info + 1, nmod);
+  if (!CHOL && hf == 0 && r < w) gmem(dvec)[b0 + r] = my_d;
+  gdouble* Ag = gmem(A);
+  gdouble* Ig = gmem(Inv);
+#pragma unroll
+  for (int cc = 0; cc < HC; ++cc) {
+    const int c = HC * hf + cc;
+    if (r < w && c < w) {
+      Ag[(b0 + r) + (size_t)(b0 + c) * lda] = Ls[r][c];
+      Ig[(b0 + r) + (size_t)(b0 + c) * ldi] = (c <= r) ? (CHOL ? my_rs * xr[cc] : xr[cc]) : 0.0;
     }
   }
 }
 
-// Diagonal blocks of a factored m x m tile, one wave per block (block b at
-// (32 b, 32 b)): the panel steps left each lower factor L_bb in Inv; it is
-// moved into A (zeros above its diagonal) and replaced in Inv by its
-// inverse (unit diagonal when UNIT).  Lane r holds row r of the block and
-// row r of X = L^{-1}: at step p lane p scales its row of X by 1 / L(p, p),
-// then rows i > p lose L(i, p) X(p, :), with X(p, :) read from lane p.
-template <bool UNIT>
-__global__ __launch_bounds__(64) void k_diag_finish(double* A, int lda, int m, double* Inv,
-                                                    int ldi) {
-  const int p0 = blockIdx.x * ND;
-  const int w = min(ND, m - p0);
-  const int r = threadIdx.x & (ND - 1);
-  const bool act = threadIdx.x < ND;
-  double row[ND], x[ND];
+// The first diagonal block of the tile: factor and invert (one wave).
+template <bool CHOL>
+__global__ __launch_bounds__(64) void k_potrf_first(double* A, int lda, int m, double* Inv, int ldi,
+                                                    double* dvec, int* info, int row_base,
+                                                    const double* tolp) {
+  __shared__ double S[ND][ND + 1];
+  const int w = min(ND, m);
+  for (int e = threadIdx.x; e < ND * ND; e += 64) {
+    const int r = e % ND, c = e / ND;
+    S[r][c] = (r < w && c < w && c <= r) ? gmem(A)[r + (size_t)c * lda] : 0.0;
+  }
+  __syncthreads();
+  factor_block<CHOL>(S, w, A, lda, 0, Inv, ldi, dvec, info, row_base, tolp);
+}
+
+// Panel p (columns [p0, p0 + 32), its diagonal block already factored with
+// L11^{-1} at (p0, p0) of Inv) of the blocked factorization.  The trailing
+// matrix T = rows and columns [p0 + 32, m) is cut into 64 x 64 tiles; one
+// workgroup (four waves) per tile (I, J), I >= J, of its lower triangle:
+//   W(I) = A21(I) L11^{-T}           (Cholesky: L21(I) = W(I))
+//   L21(J) = W(J) D^{-1}             (LDL^T; Cholesky: L21(J) = W(J))
+//   T(I, J) -= W(I) L21(J)^T         (diagonal tiles: lower triangle stored)
+// on the FP64 matrix cores (a 16-row slice of the tile per wave).  The
+// workgroups with J = 0 write L21(I) into Lp (ld ldp, at the rows and
+// columns it has in A: A's panel columns are still being read by the other
+// workgroups); the workgroup of tile (0, 0), which holds the next diagonal
+// block updated, then factors and inverts it (factor_block on its first
+// wave).
+template <bool CHOL>
+__global__ __launch_bounds__(256) void k_potrf_step(double* A, int lda, int m, int p0, double* Lp,
+                                                    int ldp, double* Inv, int ldi, double* dvec,
+                                                    int* info, int row_base, const double* tolp) {
+  __shared__ double Lv[ND][ND + 1];   // L11^{-1}(c, q)
+  __shared__ double Ai[TT][ND + 1];   // A21 rows of tile row I, then W(I)
+  __shared__ double Aj[TT][ND + 1];   // A21 rows of tile column J, then L21(J)
+  __shared__ double Sb[ND][ND + 1];   // the next diagonal block, updated (tile (0, 0))
+  __shared__ double Dp[ND];
+  const int t0 = p0 + ND;
+  // tile (I, J) of the lower triangle from the workgroup index
+  const int t = blockIdx.x;
+  int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while (bi * (bi + 1) / 2 > t) --bi;
+  while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+  const int bj = t - bi * (bi + 1) / 2;
+  const int r0 = t0 + TT * bi, c0 = t0 + TT * bj;
+  const int nr = min(TT, m - r0), nc = min(TT, m - c0);
+  const bool diag = bi == bj;
+  const int tid = threadIdx.x;
+  const gdouble* Ag = gmem((const double*)A);
+  for (int e = tid; e < ND * ND; e += 256) {
+    const int r = e % ND, c = e / ND;
+    Lv[r][c] = gmem((const double*)Inv)[(p0 + r) + (size_t)(p0 + c) * ldi];
+  }
+  for (int e = tid; e < TT * ND; e += 256) {
+    const int r = e % TT, q = e / TT;
+    Ai[r][q] = (r < nr) ? Ag[(r0 + r) + (size_t)(p0 + q) * lda] : 0.0;
+    if (!diag) Aj[r][q] = (r < nc) ? Ag[(c0 + r) + (size_t)(p0 + q) * lda] : 0.0;
+  }
+  if (!CHOL && tid < ND) Dp[tid] = gmem((const double*)dvec)[p0 + tid];
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  // W = A21 L11^{-T} for the 16-row slice wv of tile row I (and of tile
+  // column J): D(i, n) = sum_q A21(i, q) L11^{-1}(n, q)
+  d4 wi[2], wj[2];
 #pragma unroll
-  for (int c = 0; c < ND; ++c) {
-    double v = (r == c) ? 1.0 : 0.0;
-    if (r < w && c < w && c <= r) v = Inv[(p0 + r) + (size_t)(p0 + c) * ldi];
-    row[c] = (UNIT && r == c) ? 1.0 : v;
-    x[c] = (r == c) ? 1.0 : 0.0;
+  for (int ct = 0; ct < 2; ++ct) {
+    wi[ct] = d4{0.0, 0.0, 0.0, 0.0};
+    wj[ct] = d4{0.0, 0.0, 0.0, 0.0};
   }
 #pragma unroll
-  for (int c = 0; c < ND; ++c)
-    if (act && r < w && c < w) A[(p0 + r) + (size_t)(p0 + c) * lda] = (c <= r) ? row[c] : 0.0;
+  for (int k0 = 0; k0 < ND; k0 += 4) {
+    const double ai = Ai[16 * wv + li][k0 + g];
+    const double aj = diag ? 0.0 : Aj[16 * wv + li][k0 + g];
 #pragma unroll
-  for (int p = 0; p < ND; ++p) {
-    if (!UNIT) {
-      const double inv = 1.0 / row[p];
-      if (r == p) {
-#pragma unroll
-        for (int c = 0; c <= p; ++c) x[c] *= inv;
-      }
+    for (int ct = 0; ct < 2; ++ct) {
+      const double b = Lv[16 * ct + li][k0 + g];
+      wi[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b, wi[ct], 0, 0, 0);
+      if (!diag) wj[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj, b, wj[ct], 0, 0, 0);
     }
-    const double lip = (r > p) ? row[p] : 0.0;
-#pragma unroll
-    for (int c = 0; c <= p; ++c) x[c] -= lip * lane_bcast(x[c], p);
-    __builtin_amdgcn_sched_barrier(0);
   }
+  __syncthreads();   // every read of A21 done
 #pragma unroll
-  for (int c = 0; c < ND; ++c)
-    if (act && r < w && c < w) Inv[(p0 + r) + (size_t)(p0 + c) * ldi] = (r >= c) ? x[c] : 0.0;
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int lr = 16 * wv + g + 4 * rr, lc = 16 * ct + li;
+      const double vi = wi[ct][rr];
+      Ai[lr][lc] = vi;
+      if (diag) {
+        if (!CHOL) Aj[lr][lc] = vi / Dp[lc];
+      } else {
+        Aj[lr][lc] = CHOL ? wj[ct][rr] : wj[ct][rr] / Dp[lc];
+      }
+      if (bj == 0 && lr < nr) gmem(Lp)[(r0 + lr) + (size_t)(p0 + lc) * ldp] = CHOL ? vi : vi / Dp[lc];
+    }
+  __syncthreads();
+  const double (*Lj)[ND + 1] = (CHOL && diag) ? Ai : Aj;
+  // T(I, J) -= W(I) L21(J)^T: rows 16 wv .. 16 wv + 15 of the tile, all 64
+  // columns
+  d4 acc[4];
+  gdouble* Tg = gmem(A);
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int lr = 16 * wv + g + 4 * rr, lc = 16 * ct + li;
+      acc[ct][rr] = (lr < nr && lc < nc) ? Tg[(r0 + lr) + (size_t)(c0 + lc) * lda] : 0.0;
+    }
+#pragma unroll
+  for (int k0 = 0; k0 < ND; k0 += 4) {
+    const double a = -Ai[16 * wv + li][k0 + g];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Lj[16 * ct + li][k0 + g], acc[ct], 0, 0, 0);
+  }
+  const bool first = bi == 0 && bj == 0;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int lr = 16 * wv + g + 4 * rr, lc = 16 * ct + li;
+      // the next diagonal block goes to A factored (below), not updated
+      if (first && lr < ND && lc < ND)
+        Sb[lr][lc] = acc[ct][rr];
+      else if (lr < nr && lc < nc && (!diag || lr >= lc))
+        Tg[(r0 + lr) + (size_t)(c0 + lc) * lda] = acc[ct][rr];
+    }
+  if (!first) return;
+  __syncthreads();
+  if (wv == 0)
+    factor_block<CHOL>(Sb, min(ND, m - t0), A, lda, t0, Inv, ldi, dvec, info, row_base, tolp);
+}
+
+// A's final form after the panel steps: the panels below the diagonal
+// blocks from Lp, the diagonal blocks as factored, zeros above the
+// diagonal.
+__global__ void k_tri_finish(double* A, int lda, const double* Lp, int ldp, int m) {
+  const long long e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= (long long)m * m) return;
+  const int r = (int)(e % m), c = (int)(e / m);
+  if (c > r)
+    gmem(A)[r + (size_t)c * lda] = 0.0;
+  else if (r / ND != c / ND)
+    gmem(A)[r + (size_t)c * lda] = gmem(Lp)[r + (size_t)c * ldp];
 }
 
 // out(r, c) = in(r, c) * s[c] or / s[c] (column scaling, LDL^T panels).
@@ -265,29 +359,39 @@ __global__ __launch_bounds__(64) void k_trsm_diag(const double* L, int ldl, doub
 
 int diag_block_size() { return ND; }
 
-hipError_t launch_chol_panel(bool chol, double* A, int lda, int m, int p0, int w, double* W,
-                             int ldw, double* Lst, int ldst, double* dvec, int* info, int row_base,
-                             const double* tolp, hipStream_t s) {
-  if (w <= 0 || w > ND || p0 < 0 || p0 + w > m || ldst < w) return hipErrorInvalidValue;
-  const int rem = m - p0 - w;
-  const unsigned nwg = (unsigned)(rem > 0 ? (rem + 63) / 64 : 1);
+hipError_t launch_potrf_first(bool chol, double* A, int lda, int m, double* Inv, int ldi,
+                              double* dvec, int* info, int row_base, const double* tolp,
+                              hipStream_t s) {
+  if (m <= 0) return hipErrorInvalidValue;
   if (chol)
-    hipLaunchKernelGGL(k_chol_panel<true>, dim3(nwg), dim3(64), 0, s, A, lda, m, p0, w, W, ldw,
-                       Lst, ldst, dvec, info, row_base, tolp);
+    hipLaunchKernelGGL(k_potrf_first<true>, dim3(1), dim3(64), 0, s, A, lda, m, Inv, ldi, dvec,
+                       info, row_base, tolp);
   else
-    hipLaunchKernelGGL(k_chol_panel<false>, dim3(nwg), dim3(64), 0, s, A, lda, m, p0, w, W, ldw,
-                       Lst, ldst, dvec, info, row_base, tolp);
+    hipLaunchKernelGGL(k_potrf_first<false>, dim3(1), dim3(64), 0, s, A, lda, m, Inv, ldi, dvec,
+                       info, row_base, tolp);
   return hipGetLastError();
 }
 
-hipError_t launch_diag_finish(bool unit, double* A, int lda, int m, double* Inv, int ldi,
-                              hipStream_t s) {
-  if (m <= 0) return hipSuccess;
-  const unsigned nblk = (unsigned)((m + ND - 1) / ND);
-  if (unit)
-    hipLaunchKernelGGL(k_diag_finish<true>, dim3(nblk), dim3(64), 0, s, A, lda, m, Inv, ldi);
+hipError_t launch_potrf_step(bool chol, double* A, int lda, int m, int p0, double* Lp, int ldp,
+                             double* Inv, int ldi, double* dvec, int* info, int row_base,
+                             const double* tolp, hipStream_t s) {
+  if (p0 < 0 || p0 % ND != 0 || p0 + ND >= m) return hipErrorInvalidValue;
+  const int nt = (m - p0 - ND + TT - 1) / TT;
+  const unsigned nwg = (unsigned)(nt * (nt + 1) / 2);
+  if (chol)
+    hipLaunchKernelGGL(k_potrf_step<true>, dim3(nwg), dim3(256), 0, s, A, lda, m, p0, Lp, ldp, Inv,
+                       ldi, dvec, info, row_base, tolp);
   else
-    hipLaunchKernelGGL(k_diag_finish<false>, dim3(nblk), dim3(64), 0, s, A, lda, m, Inv, ldi);
+    hipLaunchKernelGGL(k_potrf_step<false>, dim3(nwg), dim3(256), 0, s, A, lda, m, p0, Lp, ldp,
+                       Inv, ldi, dvec, info, row_base, tolp);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_finish(double* A, int lda, const double* Lp, int ldp, int m, hipStream_t s) {
+  const long long n = (long long)m * m;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tri_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, lda, Lp,
+                     ldp, m);
   return hipGetLastError();
 }
 

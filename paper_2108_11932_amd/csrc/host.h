@@ -325,7 +325,6 @@ tlr_status dense_factor(Handle* h, struct Plan& plan, bool chol, double* A, int 
                         double* d, int row_base, double* Linv, double mod_delta = 0.0);
 
 // Kernel wrappers not declared in tlr_internal.h.
-hipError_t launch_zero_upper(double* A, int lda, int m, hipStream_t s);
 // p[0 .. n) = v
 hipError_t launch_fill(double* p, long long n, double v, hipStream_t s);
 hipError_t launch_pivot_tol(const double* A, int lda, int m, double* tol, hipStream_t s);

@@ -112,13 +112,6 @@ __global__ void k_fill(double* p, long long n, double v) {
   if (e < n) p[e] = v;
 }
 
-__global__ void k_zero_upper(double* A, int lda, int m) {
-  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (e >= (long long)m * m) return;
-  const int r = (int)(e % m), c = (int)(e / m);
-  if (c > r) A[r + (size_t)c * lda] = 0.0;
-}
-
 // 64 * u * ||A||_F (the LDL^T zero-pivot tolerance) for an m x m tile.
 __global__ __launch_bounds__(256) void k_pivot_tol(const double* A, int lda, int m, double* tol) {
   __shared__ double red[256];
@@ -232,12 +225,6 @@ hipError_t launch_scale_panel(const double* V, int ldv, double* W, int ldw, int 
 hipError_t launch_fill(double* p, long long n, double v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_zero_upper(double* A, int lda, int m, hipStream_t s) {
-  const long long n = (long long)m * m;
-  hipLaunchKernelGGL(k_zero_upper, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, lda, m);
   return hipGetLastError();
 }
 

@@ -581,26 +581,14 @@ tlr_status dense_factor(Handle* h, Plan& plan, bool chol, double* A, int lda, in
   if (modify) plan.launch([=]() { return launch_fill(tol, 1, mod_delta, s); });
   const double* tolk = (chol && !modify) ? nullptr : tol;
   const int nd = diag_block_size();
-  for (int p0 = 0; p0 < m; p0 += nd) {
-    const int wd = m - p0 < nd ? m - p0 : nd;
-    double* lst = Linv + p0 + (size_t)p0 * m;
+  // W holds the panels below the diagonal blocks until the last step (A's
+  // panel columns are read while they are formed)
+  plan.launch([=]() { return launch_potrf_first(chol, A, lda, m, Linv, m, d, info, row_base, tolk, s); });
+  for (int p0 = 0; p0 + nd < m; p0 += nd)
     plan.launch([=]() {
-      return launch_chol_panel(chol, A, lda, m, p0, wd, W, m, lst, m, d, info, row_base, tolk, s);
+      return launch_potrf_step(chol, A, lda, m, p0, W, m, Linv, m, d, info, row_base, tolk, s);
     });
-    const int rem = m - p0 - wd;
-    if (rem <= 0) continue;
-    double* a21 = A + (p0 + wd) + (size_t)p0 * lda;
-    double* a22 = A + (p0 + wd) + (size_t)(p0 + wd) * lda;
-    // trailing update: A22 -= L21 L21^T, or A22 -= W21 L21^T (LDL^T)
-    GemmBatch t(false, true);
-    if (chol)
-      t.add(rem, rem, wd, a21, lda, a21, lda, a22, lda, -1.0, 1.0, GEMM_LOWER_C);
-    else
-      t.add(rem, rem, wd, W, m, a21, lda, a22, lda, -1.0, 1.0, GEMM_LOWER_C);
-    plan.gemm(t);
-  }
-  plan.launch([=]() { return launch_diag_finish(!chol, A, lda, m, Linv, m, s); });
-  plan.launch([=]() { return launch_zero_upper(A, lda, m, s); });
+  plan.launch([=]() { return launch_tri_finish(A, lda, W, m, m, s); });
   inverse_assemble(plan, A, lda, m, Linv, W);
   return TLR_OK;
 }

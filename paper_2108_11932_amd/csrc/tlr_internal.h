@@ -71,23 +71,27 @@ hipError_t launch_gemm_batched(const GemmDesc* d_descs, const BlockMap* d_map, i
 // ---------------------------------------------------------------------------
 // Width of the diagonal blocks the factorization kernel handles (32).
 int diag_block_size();
-// Panel step of the blocked factorization of the m x m tile A: factor the
-// w x w (w <= diag_block_size()) diagonal block at (p0, p0) (Cholesky, or
-// unit LDL^T with pivots into dvec[p0..]) and solve the panel below it:
-// Cholesky L21 = A21 L11^{-T}; LDL^T W21 = A21 L11^{-T} into W (ld ldw, row
-// p0 + w at W[0]) and L21 = W21 D^{-1}.  L11 goes to Lst (ld ldst), not
-// into A.  info (device int) receives the 1-based row (row_base + p0 + j +
-// 1) of the first failing pivot; tolp is the LDL^T pivot tolerance (device).
-// Cholesky with tolp set: modified Cholesky, a non-positive pivot becomes
-// *tolp and is counted in info[1] instead of failing.
-hipError_t launch_chol_panel(bool chol, double* A, int lda, int m, int p0, int w, double* W,
-                             int ldw, double* Lst, int ldst, double* dvec, int* info, int row_base,
-                             const double* tolp, hipStream_t s);
-// After the panel steps, with every diagonal-block factor L_bb left in Inv
-// at (32 b, 32 b): move each into A (zeros above its diagonal) and replace
-// it in Inv by its inverse (unit diagonal when unit).
-hipError_t launch_diag_finish(bool unit, double* A, int lda, int m, double* Inv, int ldi,
+// Blocked factorization of the m x m tile A by panels of diag_block_size()
+// columns: Cholesky A = L L^T, or unit LDL^T A = L D L^T with scalar pivots
+// into dvec (device, m).  Inv (ld ldi) receives the inverse of every
+// diagonal block of L (unit for LDL^T) at (32 b, 32 b), zeros above its
+// diagonal.  info (device, two ints) receives the 1-based row (row_base +
+// row + 1) of the first failing pivot in info[0]; tolp (device) is the
+// LDL^T pivot tolerance, or, for Cholesky, the floor of modified Cholesky
+// (a non-positive pivot becomes max(|d|, *tolp) and is counted in info[1]
+// instead of failing); nullptr for plain Cholesky.
+//   launch_potrf_first: the first diagonal block (one wave);
+//   launch_potrf_step: panel p0 (p0 a multiple of 32, p0 + 32 < m): the
+//     panel below its block into Lp (ld ldp, same positions as in A), the
+//     trailing update of A, and the next diagonal block factored into A;
+//   launch_tri_finish: the panels from Lp into A, zeros above the diagonal.
+hipError_t launch_potrf_first(bool chol, double* A, int lda, int m, double* Inv, int ldi,
+                              double* dvec, int* info, int row_base, const double* tolp,
                               hipStream_t s);
+hipError_t launch_potrf_step(bool chol, double* A, int lda, int m, int p0, double* Lp, int ldp,
+                             double* Inv, int ldi, double* dvec, int* info, int row_base,
+                             const double* tolp, hipStream_t s);
+hipError_t launch_tri_finish(double* A, int lda, const double* Lp, int ldp, int m, hipStream_t s);
 // out(r, c) = in(r, c) * s[c] (or / s[c]).
 hipError_t launch_scale_cols(const double* in, int ldi, double* out, int ldo, const double* sc,
                              int rows, int cols, bool inverse, hipStream_t s);

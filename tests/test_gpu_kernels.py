@@ -83,7 +83,7 @@ def test_gemm_tn_streamed_ragged():
         np.testing.assert_allclose(got, ref, rtol=0, atol=tol)
 
 
-@pytest.mark.parametrize("m", [1, 7, 64, 65, 200, 256, 513])
+@pytest.mark.parametrize("m", [1, 7, 32, 33, 64, 65, 97, 200, 256, 513, 1024])
 def test_potrf_tile_matches_lapack(m):
     g = _rand((m, m), m)
     a = g @ g.T / m + np.eye(m)
@@ -104,7 +104,7 @@ def test_potrf_tile_reports_first_bad_pivot():
     assert tlr.potrf_tile(d) == 71
 
 
-@pytest.mark.parametrize("m", [3, 64, 150])
+@pytest.mark.parametrize("m", [3, 64, 150, 320])
 def test_ldlt_tile_matches_oracle(m):
     rng = np.random.default_rng(m)
     sgn = np.where(rng.random(m) < 0.4, -1.0, 1.0)
