@@ -48,8 +48,10 @@ __device__ inline bool tn_resolve(const AraDev& D, int mode, int tid, const doub
   }
   const int t = mode == 0 ? tid - p_tiles : tid;
   const int ai = t / tps, tile = t % tps;
-  if (ai >= D.counts[0]) return false;
+  // the slot and the active count are read together: act has an entry for
+  // every block of the launch
   const int slot = D.act[ai];
+  if (ai >= D.counts[0]) return false;
   if (D.skip && D.skip[slot]) return false;
   const AraSlotDesc& d = D.slots[slot];
   const int row0 = tile * TN_TM;
@@ -138,8 +140,8 @@ constexpr int ZCH = 4;
 __device__ inline void z_body(const AraDev& D, const ZSeg* __restrict__ segs,
                               const double* __restrict__ P, int ldp, int bps, int bid) {
   const int ai = bid / bps, tb = bid % bps;
+  const int slot = D.act[ai];   // read with the active count, as in tn_resolve
   if (ai >= D.counts[0]) return;
-  const int slot = D.act[ai];
   if (D.skip && D.skip[slot]) return;
   const AraSlotDesc& d = D.slots[slot];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -200,8 +202,8 @@ __device__ inline void seg_body(const AraDev& D, int bid) {
   const int ns = D.nstrip;
   const int nblk = (ns + FM - 1) / FM;
   const int ai = bid / nblk, blk = bid % nblk;
+  const int slot = D.act[ai];   // read with the active count, as in tn_resolve
   if (ai >= D.counts[0]) return;
-  const int slot = D.act[ai];
   if (D.skip && D.skip[slot]) return;
   const AraSlotDesc& d = D.slots[slot];
   const int m = D.m, bs = D.bs;

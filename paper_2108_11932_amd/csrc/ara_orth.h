@@ -94,53 +94,67 @@ __device__ inline void orth_body(const AraDev& D, int r_min, int bx, int by) {
   __shared__ int perm[BS];
   // copy s of the Gram: (dd (*)[BS + 1])(smem + 2 * GSZ * s)
   double (*Xs)[XR + 1] = (double (*)[XR + 1])smem;
-  if ((int)by >= D.counts[0]) return;
+  // the slot and the active count are read together (act has an entry
+  // for every block row of the launch), and then every per-slot value, so
+  // that two memory latencies precede the Gram partials; pass 2 takes the
+  // accepted count from the basis widths (qnew = q + accepted) rather than
+  // from the pivot record, one dependent load fewer
   const int slot = D.act[by];
+  if ((int)by >= D.counts[0]) return;
   const AraSlotDesc& d = D.slots[slot];
   const int m = D.m, qcap = D.qcap, nrb = D.nstrip;
   const int qold = D.q[slot];
+  const int qnew = PIV ? 0 : D.qnew[slot];
   const double tau2 = d.tau2;
   const double* part = PIV ? d.part1 + D.poff : d.part2;
   const int t = threadIdx.x, lane = t & 63;
   const int x = t % BS, g = t / BS;
-  const int nc = PIV ? BS : d.piv[BS];
+  const int nc = PIV ? BS : qnew - qold;
   if (nc == 0) return;
-  // ---- sum of the partial Gram matrices (stored for a <= b)
-  // (loads in chunks of PCH partials, all in flight before the sums)
-  constexpr int PCH = 32;
-  dd gv[CPG];
-#pragma unroll
-  for (int i = 0; i < CPG; ++i) {
-    const int b = g * CPG + i;
+  // ---- sum of the partial Gram matrices (stored for a <= b).  Thread t
+  // sums entries e = t, t + APPLY_ROWS, ... (a = e % BS, b = e / BS) over
+  // the strips with one 16-byte (hi, lo) load per strip, consecutive
+  // threads reading consecutive entries of a strip, in chunks of PCH
+  // strips all in flight before the sums (one round for m <= 1024 in pass
+  // 1; pass 2 runs inside the fused sampling launch, whose occupancy the
+  // registers of a larger chunk would halve); the sums go to copy 0 of the
+  // Gram in LDS, both triangles (entries beyond nc are zero).
+  constexpr int PCH = PIV ? 64 : 32;
+  dd (*G0)[BS + 1] = (dd (*)[BS + 1])smem;
+  for (int e = t; e < BS * BS; e += APPLY_ROWS) {
+    const int a = e % BS, b = e / BS;
+    if (a > b) continue;
     dd acc{0.0, 0.0};
-    if (g < NG && b < nc && x < nc) {
-      const int lo = min(x, b), hi = max(x, b);
-      const gdouble* pp = gmem(part) + (size_t)(lo + hi * BS) * 2;
+    if (b < nc) {
       // compensated summation (Sum2 of Ogita, Rump and Oishi): the running
       // sum is the only dependency chain, the rounding errors and the low
       // parts are gathered beside it
+      const gdv2* pp = (const gdv2*)(gmem(part) + (size_t)e * 2);
       double sh = 0.0, sc = 0.0;
       for (int rb0 = 0; rb0 < nrb; rb0 += PCH) {
-        double ph[PCH], pl[PCH];
+        dv2 pv[PCH];
 #pragma unroll
-        for (int u = 0; u < PCH; ++u) {
-          const gdouble* q2 = pp + (size_t)min(rb0 + u, nrb - 1) * BS * BS * 2;
-          ph[u] = q2[0];
-          pl[u] = q2[1];
-        }
+        for (int u = 0; u < PCH; ++u) pv[u] = pp[(size_t)min(rb0 + u, nrb - 1) * BS * BS];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < PCH; ++u)
           if (rb0 + u < nrb) {
-            const dd t = two_sum(sh, ph[u]);
-            sh = t.hi;
-            sc += t.lo + pl[u];
+            const dd t2 = two_sum(sh, pv[u].x);
+            sh = t2.hi;
+            sc += t2.lo + pv[u].y;
           }
       }
       acc = fast_two_sum(sh, sc);
     }
-    gv[i] = acc;
-    if (g < NG && b < BS) ((dd (*)[BS + 1])smem)[x][b] = acc;
+    G0[a][b] = acc;
+    G0[b][a] = acc;
+  }
+  __syncthreads();
+  dd gv[CPG];
+#pragma unroll
+  for (int i = 0; i < CPG; ++i) {
+    const int b = g * CPG + i;
+    gv[i] = (g < NG && b < BS) ? G0[x][b] : dd{0.0, 0.0};
   }
   for (int e = t; e < BS * (BS + 1); e += APPLY_ROWS) {
     (&Lm[0][0])[e] = 0.0;
