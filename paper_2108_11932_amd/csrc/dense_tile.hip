@@ -24,147 +24,142 @@ constexpr int NB = 64;   // block size of the blocked triangular solve
 constexpr int ND = 32;   // diagonal block of the blocked factorizations
 constexpr int TT = 64;   // trailing-update tile
 
-// One wave factors the w x w (w <= 32) symmetric block S (LDS, lower
-// triangle read, ld ND + 1) whose top-left entry sits at (b0, b0) of the
-// tile A: Cholesky S = L L^T, or unit LDL^T S = L D L^T with scalar
-// pivots.  L goes to A (zeros above its diagonal); L^{-1} (the unit
+// A workgroup of FT = 256 threads factors the w x w (w <= 32) symmetric
+// block S (LDS, lower triangle read, ld ND + 1) whose top-left entry sits at
+// (b0, b0) of the tile A: Cholesky S = L L^T, or unit LDL^T S = L D L^T with
+// scalar pivots.  L goes to A (zeros above its diagonal); L^{-1} (the unit
 // inverse for LDL^T) to Inv at (b0, b0) (zeros above); the pivots to
 // dvec[b0..] (LDL^T).
 //
-// Lanes r and r + 32 hold the two halves of row r of S, and of row r of
-// X, in registers (rows and columns beyond w are the identity, which leaves
-// the real part unchanged).  At step j the lanes holding column j put it
-// into LDS, and by symmetry that column is also row j, so each lane reads
-// d = S(j, j), its own S(r, j) and the S(c, j) of its half as LDS
-// broadcasts and subtracts l_rj S(j, c) from S(r, c), l_rj = S(r, j) / d.
-// The same row operation applied to X, which starts as the identity,
-// leaves X = L_unit^{-1} after the last step (Gauss-Jordan elimination:
-// the product of the elimination matrices), with row j of X read from the
-// two lanes that hold it; L^{-1} = D^{-1/2} X for Cholesky.
+// Thread t holds row r = t % 32, columns 4 g .. 4 g + 3 (g = t / 32), of S
+// and of X in registers (rows and columns beyond w are the identity, which
+// leaves the real part unchanged).  At step j the threads holding column j
+// put it into LDS, and by symmetry that column is also row j, so each
+// thread reads d = S(j, j), its own S(r, j) and the S(c, j) of its columns
+// as LDS broadcasts and subtracts l_rj S(j, c) from S(r, c), l_rj =
+// S(r, j) / d.  The same row operation applied to X, which starts as the
+// identity, leaves X = L_unit^{-1} after the last step (Gauss-Jordan
+// elimination: the product of the elimination matrices), with row j of X
+// read from the threads that hold it; L^{-1} = D^{-1/2} X for Cholesky.
+// Two LDS buffers alternate, so one barrier per step suffices.
 //
 // info receives the 1-based row (row_base + b0 + j + 1) of the first
 // failing pivot (the pivot is then taken as 1 so that the factor stays
 // finite).  LDL^T: a pivot fails when |d| <= *tolp.  Cholesky: when d <= 0,
 // or, with tolp set (modified Cholesky), d becomes max(|d|, *tolp) and is
-// counted in info[1] instead.
+// counted in info[1] instead.  Every thread of the workgroup calls it.
+constexpr int FT = 256;
 template <bool CHOL>
-__device__ __forceinline__ void factor_block(const double (*S)[ND + 1], int w, double* A, int lda, int b0,
-                                    double* Inv, int ldi, double* dvec, int* info, int row_base,
-                                    const double* tolp) {
+__device__ __forceinline__ void factor_block(const double (*S)[ND + 1], int w, double* A, int lda,
+                                             int b0, double* Inv, int ldi, double* dvec, int* info,
+                                             int row_base, const double* tolp) {
+  constexpr int CW = ND * ND / FT;   // columns per thread (4)
   __shared__ double colb[2][ND];
   __shared__ double xrow[2][ND];
   __shared__ double Ls[ND][ND + 1];   // Ls[r][j] = L(r, j)
-  const int lane = threadIdx.x & 63;
-  const int r = lane & (ND - 1);
-  const int hf = lane >> 5;   // this lane holds columns [16 hf, 16 hf + 16) of row r
-  constexpr int HC = ND / 2;
-  double row[HC], xr[HC];
+  const int t = threadIdx.x;
+  const int r = t % ND, g = t / ND, c0 = CW * g;
+  double sv[CW], xr[CW];
 #pragma unroll
-  for (int cc = 0; cc < HC; ++cc) {
-    const int c = HC * hf + cc;
+  for (int i = 0; i < CW; ++i) {
+    const int c = c0 + i;
     double v = (r == c) ? 1.0 : 0.0;
     if (r < w && c < w && c <= r) v = S[r][c];
-    row[cc] = v;
-    xr[cc] = (r == c) ? 1.0 : 0.0;
+    sv[i] = v;
+    xr[i] = (r == c) ? 1.0 : 0.0;
   }
   const bool modify = CHOL && tolp != nullptr;
   const double tol = CHOL ? (modify ? *tolp : 0.0) : *tolp;
   int bad_row = 0, nmod = 0;
   double my_rs = 1.0, my_d = 1.0;
-  // the steps in two halves of 16 (a fully unrolled loop of 32 lets the
-  // compiler hoist across steps until the registers run out)
-#pragma unroll 1
-  for (int hb = 0; hb < 2; ++hb) {
 #pragma unroll
-    for (int jj = 0; jj < HC; ++jj) {
-      const int j = HC * hb + jj;
-      double* cb = colb[jj & 1];
-      double* xb = xrow[jj & 1];
-      if (hf == hb) cb[r] = row[jj];
-      if (r == j) {
+  for (int j = 0; j < ND; ++j) {
+    double* cb = colb[j & 1];
+    double* xb = xrow[j & 1];
+    if (g == j / CW) cb[r] = sv[j % CW];
+    if (r == j) {
 #pragma unroll
-        for (int cc = 0; cc < HC; ++cc) xb[HC * hf + cc] = xr[cc];
-      }
-      // the caller runs this on one wave, whose LDS operations complete in
-      // issue order: the reads below see the writes above without a wait
-      __builtin_amdgcn_wave_barrier();
-      double d = cb[j];
-      const double a = cb[r];   // S(r, j)
-      double cv[HC], xv[HC];
+      for (int i = 0; i < CW; ++i) xb[c0 + i] = xr[i];
+    }
+    __syncthreads();
+    double d = cb[j];
+    const double a = cb[r];   // S(r, j)
+    double cv[CW], xv[CW];
 #pragma unroll
-      for (int cc = 0; cc < HC; ++cc) {
-        cv[cc] = cb[HC * hf + cc];
-        xv[cc] = xb[HC * hf + cc];
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      const bool bad = CHOL ? !(d > 0.0) : !(fabs(d) > tol);
-      if (bad && modify) {
-        if (j < w) ++nmod;
-        d = fmax(fabs(d), tol);
-      } else if (bad) {
-        if (j < w && bad_row == 0) bad_row = row_base + b0 + j + 1;
-        d = 1.0;
-      }
-      // 1/sqrt(d) (Cholesky) or 1/d from the hardware estimate and two
-      // Newton steps: a handful of FMAs instead of the division and
-      // square-root sequences on the step's dependency chain
-      double rs = 0.0, rd;
-      if (CHOL) {
-        rs = __builtin_amdgcn_rsq(d);
+    for (int i = 0; i < CW; ++i) {
+      cv[i] = cb[c0 + i];
+      xv[i] = xb[c0 + i];
+    }
+    const bool bad = CHOL ? !(d > 0.0) : !(fabs(d) > tol);
+    if (bad && modify) {
+      if (j < w) ++nmod;
+      d = fmax(fabs(d), tol);
+    } else if (bad) {
+      if (j < w && bad_row == 0) bad_row = row_base + b0 + j + 1;
+      d = 1.0;
+    }
+    // 1/sqrt(d) (Cholesky) or 1/d from the hardware estimate and two Newton
+    // steps: a handful of FMAs instead of the division and square-root
+    // sequences on the step's dependency chain
+    double rs = 0.0, rd;
+    if (CHOL) {
+      rs = __builtin_amdgcn_rsq(d);
 #pragma unroll
-        for (int it = 0; it < 2; ++it) rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
-        rd = rs * rs;
-      } else {
-        rd = __builtin_amdgcn_rcp(d);
+      for (int it = 0; it < 2; ++it) rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+      rd = rs * rs;
+    } else {
+      rd = __builtin_amdgcn_rcp(d);
 #pragma unroll
-        for (int it = 0; it < 2; ++it) rd = fma(rd, fma(-d, rd, 1.0), rd);
-      }
-      const double mr = a * rd;   // l_rj of the unit factor (r > j)
-      // every column of the half of S (finished columns and the upper
-      // triangle only collect values that are never read again); X only on
-      // the rows below j
-      const double xm = (r > j) ? mr : 0.0;
+      for (int it = 0; it < 2; ++it) rd = fma(rd, fma(-d, rd, 1.0), rd);
+    }
+    const double mr = a * rd;   // l_rj of the unit factor (r > j)
+    // every column of S (finished columns and the upper triangle only
+    // collect values that are never read again); X only on the rows below j
+    const double xm = (r > j) ? mr : 0.0;
 #pragma unroll
-      for (int cc = 0; cc < HC; ++cc) {
-        row[cc] = fma(-mr, cv[cc], row[cc]);
-        xr[cc] = fma(-xm, xv[cc], xr[cc]);
-      }
-      if (r == j) {
-        my_rs = rs;
-        my_d = d;
-      }
+    for (int i = 0; i < CW; ++i) {
+      sv[i] = fma(-mr, cv[i], sv[i]);
+      xr[i] = fma(-xm, xv[i], xr[i]);
+    }
+    if (r == j) {
+      my_rs = rs;
+      my_d = d;
+    }
+    if (g == 0) {
       double lv;
       if (CHOL)
         lv = (r == j) ? d * rs : (r > j ? a * rs : 0.0);
       else
         lv = (r == j) ? 1.0 : (r > j ? mr : 0.0);
-      if (hf == 0) Ls[r][j] = lv;
+      Ls[r][j] = lv;
     }
   }
-  __builtin_amdgcn_wave_barrier();
-  if (bad_row && lane == 0) atomicCAS(info, 0, bad_row);
-  if (nmod && lane == 0) atomicAdd(info + 1, nmod);
-  if (!CHOL && hf == 0 && r < w) gmem(dvec)[b0 + r] = my_d;
+  __syncthreads();
+  if (bad_row && t == 0) atomicCAS(info, 0, bad_row);
+  if (nmod && t == 0) atomicAdd(info + 1, nmod);
+  if (!CHOL && g == 0 && r < w) gmem(dvec)[b0 + r] = my_d;
   gdouble* Ag = gmem(A);
   gdouble* Ig = gmem(Inv);
 #pragma unroll
-  for (int cc = 0; cc < HC; ++cc) {
-    const int c = HC * hf + cc;
+  for (int i = 0; i < CW; ++i) {
+    const int c = c0 + i;
     if (r < w && c < w) {
       Ag[(b0 + r) + (size_t)(b0 + c) * lda] = Ls[r][c];
-      Ig[(b0 + r) + (size_t)(b0 + c) * ldi] = (c <= r) ? (CHOL ? my_rs * xr[cc] : xr[cc]) : 0.0;
+      Ig[(b0 + r) + (size_t)(b0 + c) * ldi] = (c <= r) ? (CHOL ? my_rs * xr[i] : xr[i]) : 0.0;
     }
   }
 }
 
-// The first diagonal block of the tile: factor and invert (one wave).
+// The first diagonal block of the tile: factor and invert.
 template <bool CHOL>
-__global__ __launch_bounds__(64) void k_potrf_first(double* A, int lda, int m, double* Inv, int ldi,
+__global__ __launch_bounds__(FT) void k_potrf_first(double* A, int lda, int m, double* Inv, int ldi,
                                                     double* dvec, int* info, int row_base,
                                                     const double* tolp) {
   __shared__ double S[ND][ND + 1];
   const int w = min(ND, m);
-  for (int e = threadIdx.x; e < ND * ND; e += 64) {
+#pragma unroll
+  for (int u = 0; u < ND * ND / FT; ++u) {
+    const int e = threadIdx.x + FT * u;
     const int r = e % ND, c = e / ND;
     S[r][c] = (r < w && c < w && c <= r) ? gmem(A)[r + (size_t)c * lda] : 0.0;
   }
@@ -183,8 +178,7 @@ __global__ __launch_bounds__(64) void k_potrf_first(double* A, int lda, int m, d
 // workgroups with J = 0 write L21(I) into Lp (ld ldp, at the rows and
 // columns it has in A: A's panel columns are still being read by the other
 // workgroups); the workgroup of tile (0, 0), which holds the next diagonal
-// block updated, then factors and inverts it (factor_block on its first
-// wave).
+// block updated, then factors and inverts it (factor_block).
 template <bool CHOL>
 __global__ __launch_bounds__(256) void k_potrf_step(double* A, int lda, int m, int p0, double* Lp,
                                                     int ldp, double* Inv, int ldi, double* dvec,
@@ -205,20 +199,48 @@ __global__ __launch_bounds__(256) void k_potrf_step(double* A, int lda, int m, i
   const int nr = min(TT, m - r0), nc = min(TT, m - c0);
   const bool diag = bi == bj;
   const int tid = threadIdx.x;
-  const gdouble* Ag = gmem((const double*)A);
-  for (int e = tid; e < ND * ND; e += 256) {
-    const int r = e % ND, c = e / ND;
-    Lv[r][c] = gmem((const double*)Inv)[(p0 + r) + (size_t)(p0 + c) * ldi];
-  }
-  for (int e = tid; e < TT * ND; e += 256) {
-    const int r = e % TT, q = e / TT;
-    Ai[r][q] = (r < nr) ? Ag[(r0 + r) + (size_t)(p0 + q) * lda] : 0.0;
-    if (!diag) Aj[r][q] = (r < nc) ? Ag[(c0 + r) + (size_t)(p0 + q) * lda] : 0.0;
-  }
-  if (!CHOL && tid < ND) Dp[tid] = gmem((const double*)dvec)[p0 + tid];
-  __syncthreads();
   const int lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
+  const gdouble* Ag = gmem((const double*)A);
+  // every load of the launch in flight at once: L11^{-1}, the panel rows
+  // of tile row I and column J, the pivots, and this wave's slice of the
+  // trailing tile in the accumulator layout (register r of lane l: row
+  // l / 16 + 4 r, column l % 16 of a 16 x 16 block)
+  constexpr int NL = ND * ND / 256, NA = TT * ND / 256;
+  double lvv[NL], aiv[NA], ajv[NA];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int e = tid + 256 * u, r = e % ND, c = e / ND;
+    lvv[u] = gmem((const double*)Inv)[(p0 + r) + (size_t)(p0 + c) * ldi];
+  }
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int e = tid + 256 * u, r = e % TT, q = e / TT;
+    aiv[u] = Ag[(r0 + min(r, nr - 1)) + (size_t)(p0 + q) * lda];
+    ajv[u] = diag ? 0.0 : Ag[(c0 + min(r, nc - 1)) + (size_t)(p0 + q) * lda];
+  }
+  const double dp = (!CHOL && tid < ND) ? gmem((const double*)dvec)[p0 + tid] : 1.0;
+  d4 acc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int lr = 16 * wv + g + 4 * rr, lc = 16 * ct + li;
+      acc[ct][rr] = Ag[(r0 + min(lr, nr - 1)) + (size_t)(c0 + min(lc, nc - 1)) * lda];
+    }
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int e = tid + 256 * u;
+    Lv[e % ND][e / ND] = lvv[u];
+  }
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int e = tid + 256 * u, r = e % TT, q = e / TT;
+    Ai[r][q] = (r < nr) ? aiv[u] : 0.0;
+    if (!diag) Aj[r][q] = (r < nc) ? ajv[u] : 0.0;
+  }
+  if (!CHOL && tid < ND) Dp[tid] = dp;
+  __syncthreads();
   // W = A21 L11^{-T} for the 16-row slice wv of tile row I (and of tile
   // column J): D(i, n) = sum_q A21(i, q) L11^{-1}(n, q)
   d4 wi[2], wj[2];
@@ -257,15 +279,7 @@ __global__ __launch_bounds__(256) void k_potrf_step(double* A, int lda, int m, i
   const double (*Lj)[ND + 1] = (CHOL && diag) ? Ai : Aj;
   // T(I, J) -= W(I) L21(J)^T: rows 16 wv .. 16 wv + 15 of the tile, all 64
   // columns
-  d4 acc[4];
   gdouble* Tg = gmem(A);
-#pragma unroll
-  for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int lr = 16 * wv + g + 4 * rr, lc = 16 * ct + li;
-      acc[ct][rr] = (lr < nr && lc < nc) ? Tg[(r0 + lr) + (size_t)(c0 + lc) * lda] : 0.0;
-    }
 #pragma unroll
   for (int k0 = 0; k0 < ND; k0 += 4) {
     const double a = -Ai[16 * wv + li][k0 + g];
@@ -287,8 +301,7 @@ __global__ __launch_bounds__(256) void k_potrf_step(double* A, int lda, int m, i
     }
   if (!first) return;
   __syncthreads();
-  if (wv == 0)
-    factor_block<CHOL>(Sb, min(ND, m - t0), A, lda, t0, Inv, ldi, dvec, info, row_base, tolp);
+  factor_block<CHOL>(Sb, min(ND, m - t0), A, lda, t0, Inv, ldi, dvec, info, row_base, tolp);
 }
 
 // A's final form after the panel steps: the panels below the diagonal
@@ -364,10 +377,10 @@ hipError_t launch_potrf_first(bool chol, double* A, int lda, int m, double* Inv,
                               hipStream_t s) {
   if (m <= 0) return hipErrorInvalidValue;
   if (chol)
-    hipLaunchKernelGGL(k_potrf_first<true>, dim3(1), dim3(64), 0, s, A, lda, m, Inv, ldi, dvec,
+    hipLaunchKernelGGL(k_potrf_first<true>, dim3(1), dim3(FT), 0, s, A, lda, m, Inv, ldi, dvec,
                        info, row_base, tolp);
   else
-    hipLaunchKernelGGL(k_potrf_first<false>, dim3(1), dim3(64), 0, s, A, lda, m, Inv, ldi, dvec,
+    hipLaunchKernelGGL(k_potrf_first<false>, dim3(1), dim3(FT), 0, s, A, lda, m, Inv, ldi, dvec,
                        info, row_base, tolp);
   return hipGetLastError();
 }
