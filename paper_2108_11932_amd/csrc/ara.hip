@@ -19,6 +19,7 @@
 // a*b + c into fused multiply-adds in this file (explicit fma() calls stay).
 #pragma clang fp contract(off)
 
+#include "ara_compact.h"
 #include "ara_orth.h"
 
 namespace tlr {
@@ -100,106 +101,18 @@ __global__ __launch_bounds__(APPLY_ROWS) void k_orth_step(AraDev D, int r_min) {
   orth_body<BS, PIV>(D, r_min, blockIdx.x, blockIdx.y);
 }
 
-// ------------------------------------------------------- dynamic batching
-// Stable compaction of the active list (slots whose flag is set leave) and
-// refill from the waiting list, keeping at most s_max tiles.  Run by one
-// whole workgroup of 256 threads.
-__device__ inline void compact_active(int* act, int* counts, const int* flag, const int* waiting,
-                                      int nwaiting, int s_max, int* keep_total, int* scan) {
-  const int tid = threadIdx.x;
-  const int n = counts[0];
-  if (tid == 0) *keep_total = 0;
-  __syncthreads();
-  // in-place stable compaction, processed in chunks of 256 entries; writes
-  // never overtake reads because pos <= index
-  for (int base = 0; base < n; base += 256) {
-    const int i = base + tid;
-    int slot = -1, keep = 0;
-    if (i < n) {
-      slot = act[i];
-      keep = flag[slot] ? 0 : 1;
-    }
-    scan[tid] = keep;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      const int v = (tid >= off) ? scan[tid - off] : 0;
-      __syncthreads();
-      scan[tid] += v;
-      __syncthreads();
-    }
-    const int pos = *keep_total + scan[tid] - keep;
-    const int chunk_keep = scan[255];
-    __syncthreads();
-    if (keep) act[pos] = slot;
-    __syncthreads();
-    if (tid == 0) *keep_total += chunk_keep;
-    __syncthreads();
-  }
-  const int kept = *keep_total;
-  const int cursor = counts[1];
-  const int take = max(0, min(min(n - kept, s_max - kept), nwaiting - cursor));
-  for (int j = tid; j < take; j += blockDim.x) act[kept + j] = waiting[cursor + j];
-  __syncthreads();
-  if (tid == 0) {
-    counts[0] = kept + take;
-    counts[1] = cursor + take;
-  }
-  __syncthreads();
-}
-
 __global__ __launch_bounds__(256) void k_compact(int* act, int* counts, const int* flag,
                                                  const int* waiting, int nwaiting, int s_max,
                                                  const int* info) {
-  __shared__ int keep_total;
-  __shared__ int scan[256];
-  compact_active(act, counts, flag, waiting, nwaiting, s_max, &keep_total, scan);
+  __shared__ int wsum[8];
+  compact_active(act, act, counts, counts, flag, waiting, nwaiting, s_max, nullptr, nullptr, wsum);
   if (threadIdx.x == 0 && info) counts[2] = *info;
 }
 
-// End of an ARA iteration: commit the basis widths of the slots that ran,
-// compact and refill, then record the status word and the largest basis
-// width among the active slots (the host's bound for the next products).
 __global__ __launch_bounds__(256) void k_ara_compact(AraDev D, const int* waiting, int nwaiting,
                                                      int s_max, const int* info, int* host_out,
                                                      int* host_res, int res_ints) {
-  __shared__ int keep_total;
-  __shared__ int scan[256];
-  const int tid = threadIdx.x;
-  const int n = D.counts[0];   // active at entry: the iteration that ran
-  for (int i = tid; i < n; i += 256) {
-    const int slot = D.act[i];
-    D.q[slot] = D.qnew[slot];
-  }
-  __syncthreads();
-  compact_active(D.act, D.counts, D.flag, waiting, nwaiting, s_max, &keep_total, scan);
-  const int na = D.counts[0];
-  int qm = 0;
-  for (int i = tid; i < na; i += 256) qm = max(qm, D.q[D.act[i]]);
-  scan[tid] = qm;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) scan[tid] = max(scan[tid], scan[tid + w]);
-    __syncthreads();
-  }
-  if (tid == 0) {
-    D.counts[3] = scan[0];
-    D.counts[2] = info ? *info : 0;
-  }
-  // the four counters also go straight to the host's read-back slot
-  // (pinned memory, stores at system scope)
-  if (host_out && tid < 4) {
-    const int v = tid == 0 ? D.counts[0] : tid == 1 ? D.counts[1] : tid == 2 ? (info ? *info : 0)
-                                                                             : scan[0];
-    __hip_atomic_store(host_out + tid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  }
-  // the compaction that empties the list (n > 0 tiles ran, none is left)
-  // publishes the per-slot results (basis widths and counters, res_ints
-  // contiguous ints from D.q), so the host need not wait for the iteration
-  // queued behind it; that spare iteration starts empty and writes nothing
-  if (host_res && n > 0 && na == 0) {
-    for (int e = tid; e < res_ints; e += 256)
-      __hip_atomic_store(host_res + e, D.q[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  }
+  ara_compact_body(D, waiting, nwaiting, s_max, info, host_out, host_res, res_ints);
 }
 
 }  // namespace

@@ -26,7 +26,7 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   if (fresh_q) TLR_HIP(hipMemsetAsync(w.Q.p, 0, w.Q.cap, h->stream));
   const size_t pn = nn * nstrip * bs * bs * 2;
   TLR_TRY(w.part.ensure(h->mem, sizeof(double) * 3 * pn));
-  const size_t nint = 8 + 9 * al(nn) + al(nn * (bs + 1)) + 64;
+  const size_t nint = 8 + 13 * al(nn) + al(nn * (bs + 1)) + 64;
   TLR_TRY(w.ints.ensure(h->mem, sizeof(int) * nint));
   s->Y = w.Y.as<double>();
   s->C = w.C.as<double>();
@@ -53,6 +53,14 @@ tlr_status ara_slots(Handle* h, const AraConfig& c, int n, AraSlots* s) {
   s->ncol = ip;
   ip += al(nn);
   s->f32 = ip;
+  ip += al(nn);
+  s->qpa = ip;
+  ip += al(nn);
+  s->qpb = ip;
+  ip += al(nn);
+  s->counts2 = ip;
+  ip += al(nn);
+  s->act2 = ip;
   ip += al(nn);
   s->waiting = ip;   // counts .. waiting are written by one upload per run
   ip += al(nn);
@@ -196,6 +204,10 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   D.slots = (const AraSlotDesc*)dbase;
   D.act = s.act;
   D.counts = s.counts;
+  D.act_next = s.act2;
+  D.counts_next = s.counts2;
+  D.qin = s.qpa;
+  D.qout = s.qpb;
   D.q = s.q;
   D.qnew = s.qnew;
   D.flag = s.flag;
@@ -250,12 +262,22 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
   known.count = s_max;
   std::vector<int> bs_of;   // samples of every iteration, fixed when it is sampled
   int sampled = -1;         // last iteration whose sampling is enqueued
+  // the list a launch of iteration t reads: its own, except for a sampling
+  // fused into iteration t - 1, which reads t - 1's (less the flagged tiles)
   auto dev_for = [&](int t, bool sampling) {
     AraDev E = D;
     E.bs = bs_of[t];
     E.yoff = (t & 1) ? s.yalt : 0;
     E.poff = (t & 1) ? s.palt : 0;
-    E.skip = (sampling && fuse && t >= 1) ? s.flag : nullptr;
+    const bool ahead = sampling && fuse && t >= 1;
+    E.skip = ahead ? s.flag : nullptr;
+    const int lp = (ahead ? t - 1 : t) & 1;
+    E.act = lp ? s.act2 : s.act;
+    E.counts = lp ? s.counts2 : s.counts;
+    E.act_next = lp ? s.act : s.act2;
+    E.counts_next = lp ? s.counts : s.counts2;
+    E.qin = (t & 1) ? s.qpb : s.qpa;
+    E.qout = (t & 1) ? s.qpa : s.qpb;
     return E;
   };
   const size_t ostride = (size_t)m * bs;
@@ -313,6 +335,7 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
     }
     TLR_HIP(launch_orth_step(E, 1, c.r_min, cb, st));
     const int bn = c.bs_for(j + 1, known.count);
+    bool compacted = false;
     if (fuse && bn == E.bs) {
       bs_of.push_back(bn);
       res->iter_bs.push_back(bn);
@@ -321,7 +344,9 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       TLR_TRY(draw(j + 1, bn));
       TLR_HIP(launch_fused_tn(S, omega_of(j + 1), dptiles, p_blocks, spec.ldp,
                               (p_blocks > 0 || bps_wa > 0) ? cb : 0, bps_wa, tn_scratch_s, E,
-                              bps_q > 0 ? cb : 0, bps_q, tn_scratch, st));
+                              bps_q > 0 ? cb : 0, bps_q, tn_scratch, s.waiting, nwait, s_max,
+                              info, ring + 8 * (j & 1), pres, res_ints, st));
+      compacted = true;
       TLR_HIP(launch_fused_z_seg(S, dzseg, spec.p, spec.ldp, any_z ? cb : 0, bps_z, E,
                                  bps_q > 0 ? cb : 0, st));
       TLR_HIP(launch_fused_seg_orth(S, cb, c.strip, E, cb, c.r_min, st));
@@ -333,8 +358,9 @@ tlr_status ara_run(Handle* h, const AraConfig& c, const AraSlots& s, const std::
       TLR_HIP(launch_orth_step(E, 2, c.r_min, cb, st));
     }
     if (spec.pt) TLR_HIP(spec.pt->mark(TLR_PHASE_BATCH, st));
-    TLR_HIP(launch_ara_compact(E, s.waiting, nwait, s_max, info, ring + 8 * (j & 1), pres, res_ints,
-                               st));
+    if (!compacted)
+      TLR_HIP(launch_ara_compact(E, s.waiting, nwait, s_max, info, ring + 8 * (j & 1), pres,
+                                 res_ints, st));
     TLR_HIP(hipEventRecord(h->ev_rb[j & 1], st));
     return TLR_OK;
   };

@@ -67,6 +67,10 @@ struct AraSlots {
   int* qsum = nullptr;      // n
   int* ncol = nullptr;      // n: samples drawn per slot
   int* f32 = nullptr;       // n: precision chosen per slot
+  int* qpa = nullptr;       // n: basis widths at the start of even iterations
+  int* qpb = nullptr;       // n: ... of odd iterations
+  int* counts2 = nullptr;   // 8: the counters of odd iterations
+  int* act2 = nullptr;      // n: the active list of odd iterations
   int* piv = nullptr;       // n x (bs + 1)
   int* waiting = nullptr;   // n
   long long yalt = 0, palt = 0;

@@ -20,6 +20,7 @@
 // the Gram partials use error-free transformations
 #pragma clang fp contract(off)
 
+#include "ara_compact.h"
 #include "ara_orth.h"
 
 namespace tlr {
@@ -59,7 +60,7 @@ __device__ inline bool tn_resolve(const AraDev& D, int mode, int tid, const doub
     if (row0 >= d.a) return false;
     *o = TnTile{d.va, omega, d.wa, d.a, d.a, row0, tid, 1.0};
   } else {
-    const int q = D.q[slot];
+    const int q = D.qin[slot];
     if (row0 >= q) return false;
     const double* B = mode == 1 ? d.y + D.yoff : d.q + (size_t)q * m;
     *o = TnTile{d.q, B, d.c, q, m, row0, tid, -1.0};
@@ -222,7 +223,7 @@ __device__ inline void seg_body(const AraDev& D, int bid) {
                            d.y + D.yoff, m, m, bs, 0.0, r0, red, r32, ys);
     part = d.part1 + D.poff;
   } else {
-    const int q = D.q[slot];
+    const int q = D.qin[slot];
     if (q == 0) return;
     double* dst = mode == 1 ? d.y + D.yoff : d.q + (size_t)q * m;
     seg_strip<NF, 0, FM>(d.q, m, d.c, m, q, nullptr, 1, nullptr, 1, 0, dst, m, m, bs, 1.0, r0,
@@ -262,18 +263,35 @@ __global__ __launch_bounds__(256) void k_ara_seg(AraDev D) {
 // concurrently without a second stream, and the host issues one launch for
 // two.
 //   tn     : P, W^A of t + 1 (mode 0)   |  C = -Q^T X of t (mode 2), split K
+//            and, in one more workgroup, the compaction of t's active list
+//            into t + 1's (the flags are set by pass 1; the list t + 1 reads
+//            is a second copy, and the widths need no commit)
 //   tn_sum : their partial sums
 //   z_seg  : Z of t + 1                 |  X += Q C of t (mode 2)
 //   seg_orth: Y of t + 1 (mode 0)       |  pass-2 Cholesky QR of t
+struct CompactArgs {
+  const int* waiting;
+  int nwaiting, s_max;
+  const int* info;
+  int* host_out;
+  int* host_res;
+  int res_ints;
+};
+
 template <int FN>
 __global__ __launch_bounds__(64 * TN_NW) void k_fuse_tn(AraDev Da, const double* omega,
                                                          const PTile* ptiles, int p_tiles, int ldp,
                                                          int tpsa, double* scra, int na, AraDev Db,
-                                                         int tpsb, double* scrb) {
+                                                         int tpsb, double* scrb, int nab,
+                                                         CompactArgs ca) {
+  static_assert(64 * TN_NW == 256, "the compaction runs on 256 threads");
   if ((int)blockIdx.x < na)
     tn_body<FN>(Da, 0, omega, ptiles, p_tiles, ldp, tpsa, scra, blockIdx.x);
-  else
+  else if ((int)blockIdx.x < nab)
     tn_body<FN>(Db, 2, nullptr, nullptr, 0, 0, tpsb, scrb, blockIdx.x - na);
+  else
+    ara_compact_body(Db, ca.waiting, ca.nwaiting, ca.s_max, ca.info, ca.host_out, ca.host_res,
+                     ca.res_ints);
 }
 
 template <int FN>
@@ -387,25 +405,31 @@ bool fused_block_supported(int bs) { return bs == 16 || bs == 32; }
 
 hipError_t launch_fused_tn(const AraDev& Da, const double* omega, const PTile* ptiles, int p_tiles,
                            int ldp, int cba, int tpsa, double* scra, const AraDev& Db, int cbb,
-                           int tpsb, double* scrb, hipStream_t s) {
+                           int tpsb, double* scrb, const int* waiting, int nwaiting, int s_max,
+                           const int* info, int* host_out, int* host_res, int res_ints,
+                           hipStream_t s) {
   if (Da.bs != Db.bs || !fused_block_supported(Da.bs)) return hipErrorInvalidValue;
   const int ks_n = (Da.m + TN_KC - 1) / TN_KC;
   const long long ta = p_tiles + (long long)std::max(cba, 0) * std::max(tpsa, 0);
   const long long tb = (long long)std::max(cbb, 0) * std::max(tpsb, 0);
-  if (ta + tb <= 0) return hipSuccess;
   const int pa = std::max(tpsa, 1), pb = std::max(tpsb, 1);
-  const unsigned na = (unsigned)(ta * ks_n), ns = (unsigned)((ta + tb) * ks_n);
+  // the products' blocks, then the compaction's
+  const unsigned na = (unsigned)(ta * ks_n), nab = (unsigned)((ta + tb) * ks_n);
   const unsigned ma = (unsigned)ta, ms = (unsigned)(ta + tb);
-  if (Da.bs <= 16) {
-    hipLaunchKernelGGL((k_fuse_tn<1>), dim3(ns), dim3(64 * TN_NW), 0, s, Da, omega, ptiles, p_tiles,
-                       ldp, pa, scra, (int)na, Db, pb, scrb);
-    hipLaunchKernelGGL((k_fuse_tn_sum<1>), dim3(ms), dim3(256), 0, s, Da, omega, ptiles, p_tiles,
-                       ldp, pa, scra, (int)ma, Db, pb, scrb);
-  } else {
-    hipLaunchKernelGGL((k_fuse_tn<2>), dim3(ns), dim3(64 * TN_NW), 0, s, Da, omega, ptiles, p_tiles,
-                       ldp, pa, scra, (int)na, Db, pb, scrb);
-    hipLaunchKernelGGL((k_fuse_tn_sum<2>), dim3(ms), dim3(256), 0, s, Da, omega, ptiles, p_tiles,
-                       ldp, pa, scra, (int)ma, Db, pb, scrb);
+  const CompactArgs ca{waiting, nwaiting, s_max, info, host_out, host_res, res_ints};
+  if (Da.bs <= 16)
+    hipLaunchKernelGGL((k_fuse_tn<1>), dim3(nab + 1), dim3(64 * TN_NW), 0, s, Da, omega, ptiles,
+                       p_tiles, ldp, pa, scra, (int)na, Db, pb, scrb, (int)nab, ca);
+  else
+    hipLaunchKernelGGL((k_fuse_tn<2>), dim3(nab + 1), dim3(64 * TN_NW), 0, s, Da, omega, ptiles,
+                       p_tiles, ldp, pa, scra, (int)na, Db, pb, scrb, (int)nab, ca);
+  if (ms > 0) {
+    if (Da.bs <= 16)
+      hipLaunchKernelGGL((k_fuse_tn_sum<1>), dim3(ms), dim3(256), 0, s, Da, omega, ptiles, p_tiles,
+                         ldp, pa, scra, (int)ma, Db, pb, scrb);
+    else
+      hipLaunchKernelGGL((k_fuse_tn_sum<2>), dim3(ms), dim3(256), 0, s, Da, omega, ptiles, p_tiles,
+                         ldp, pa, scra, (int)ma, Db, pb, scrb);
   }
   return hipGetLastError();
 }

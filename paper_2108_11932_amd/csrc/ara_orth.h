@@ -103,7 +103,7 @@ __device__ inline void orth_body(const AraDev& D, int r_min, int bx, int by) {
   if ((int)by >= D.counts[0]) return;
   const AraSlotDesc& d = D.slots[slot];
   const int m = D.m, qcap = D.qcap, nrb = D.nstrip;
-  const int qold = D.q[slot];
+  const int qold = D.qin[slot];
   const int qnew = PIV ? 0 : D.qnew[slot];
   const double tau2 = d.tau2;
   const double* part = PIV ? d.part1 + D.poff : d.part2;
@@ -235,6 +235,8 @@ __device__ inline void orth_body(const AraDev& D, int r_min, int bx, int by) {
       if (t == 0) {
         d.piv[BS] = np;
         D.qnew[slot] = qold + np;
+        D.qout[slot] = qold + np;
+        D.q[slot] = qold + np;
         D.flag[slot] = ((np <= BS - r_min) || (qold + np >= qcap)) ? 1 : 0;
         D.iters[slot] += 1;
         D.qsum[slot] += qold * BS;

@@ -170,9 +170,18 @@ struct ZSeg {
 // Device state of one ARA run (passed by value).
 struct AraDev {
   const AraSlotDesc* slots;
-  int* act;     // active slots, counts[0] of them
+  int* act;     // active slots of this iteration, counts[0] of them
   int* counts;  // [0] active, [1] waiting cursor, [2] status word copy, [3] max basis width of the active slots
-  int* q;       // basis width per slot (committed by the compaction)
+  // the next iteration's list and counters, formed by the compaction (two
+  // copies alternate by iteration, so that the compaction can run while
+  // this iteration's launches still read its list)
+  int* act_next;
+  int* counts_next;
+  // basis width per slot at the start of this iteration (qin) and after it
+  // (qout, set by pass 1); two copies alternate by iteration
+  const int* qin;
+  int* qout;
+  int* q;       // latest basis width per slot (the run's result)
   int* qnew;    // basis width after this iteration's pass 1
   int* flag;    // converged
   int* iters;   // iterations per slot
@@ -235,10 +244,14 @@ hipError_t launch_ara_seg(const AraDev& D, int mode, int count_bound, hipStream_
 // (Da / Dz / D0: mode 0, its tiles less the ones the flags of t name)
 // together with the second Gram-Schmidt pass of iteration t (Db / Ds / D2).
 // Block sizes 16 and 32 only (fused_block_supported), the same in both.
+// launch_fused_tn also runs the compaction of iteration t (the work of
+// launch_ara_compact for Db, with the same arguments) in one more block.
 bool fused_block_supported(int bs);
 hipError_t launch_fused_tn(const AraDev& Da, const double* omega, const PTile* ptiles, int p_tiles,
                            int ldp, int cba, int tpsa, double* scra, const AraDev& Db, int cbb,
-                           int tpsb, double* scrb, hipStream_t s);
+                           int tpsb, double* scrb, const int* waiting, int nwaiting, int s_max,
+                           const int* info, int* host_out, int* host_res, int res_ints,
+                           hipStream_t s);
 hipError_t launch_fused_z_seg(const AraDev& Dz, const ZSeg* segs, const double* P, int ldp, int cbz,
                               int bps, const AraDev& Ds, int cbs, hipStream_t s);
 hipError_t launch_fused_seg_orth(const AraDev& D0, int cb0, int strip, const AraDev& D2, int cb2,
@@ -249,9 +262,10 @@ hipError_t launch_fused_seg_orth(const AraDev& D0, int cb0, int strip, const Ara
 // columns in place).
 // The threshold of each tile is its slot's tau2.
 hipError_t launch_orth_step(const AraDev& D, int pass, int r_min, int count_bound, hipStream_t s);
-// Commit the basis widths, compact the active list and refill it (see
-// launch_compact), and record the status word and the largest active width;
-// counts[0..3] are also stored to host_out (pinned host memory) when given;
+// Compact the active list D.act into D.act_next and refill it (see
+// launch_compact; D.counts to D.counts_next), and record the status word and
+// the largest basis width (D.qout) on the new list; counts_next[0..3] are
+// also stored to host_out (pinned host memory) when given;
 // when no tile is left active, the res_ints ints from D.q (the per-slot
 // results, laid out contiguously) are stored to host_res as well.
 hipError_t launch_ara_compact(const AraDev& D, const int* waiting, int nwaiting, int s_max,
