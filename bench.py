@@ -163,37 +163,41 @@ def cpu_baseline(w, n_sample: int, tlr, torch):
             "blas": vendor, "oracle_seconds": t_cpu, "gpu_seconds_same_sample": t_gpu}
 
 
-def residual(mat, torch, nvec: int = 4, seed: int = 7) -> float:
+def residual(mat, torch, nvec: int = 4, seed: int = 7, shift: float = 0.0) -> float:
     """Random-vector residual of the factor against the FP64 TLR input:
-    max over Gaussian b of ||A x - b|| / ||x|| with x = (L L^T)^{-1} b, i.e.
-    ||(A - L L^T) x|| / ||x||; A is applied by tlr_matvec (FP64), x by
-    tlr_solve with the factor."""
+    max over Gaussian b of ||(A + shift I) x - b|| / ||x|| with
+    x = (L L^T)^{-1} b, i.e. ||(A + shift I - L L^T) x|| / ||x|| (shift: the
+    diagonal shift the factorization applied); A is applied by tlr_matvec
+    (FP64), x by tlr_solve with the factor."""
     g = torch.Generator(device="cpu").manual_seed(seed)
     b = torch.randn(mat.n, nvec, generator=g, dtype=torch.float64).cuda()
     x = mat.solve(b)
-    r = mat.matvec(x) - b
+    r = mat.matvec(x) + shift * x - b
     return float((r.norm(dim=0) / x.norm(dim=0)).max())
 
 
 def time_form(mat, w, eps_mode, precision, tlr, torch, steps, warmup, bs_tail=0, tail_active=0,
-              timing=True, idle_s=0.0, serial=False):
+              timing=True, idle_s=0.0, serial=False, eps=None, shift=0.0):
     """Warm up, then time `steps` factorizations of one form (with the
     sampling launches timed by their own events when `timing`, which runs
     every sampling product in a launch of its own); the GPU idles idle_s
     seconds between the warm-up and the timed steps (a marker for profile
     reductions).  `serial` asks for that same launch schedule without the
-    events (for counter runs that match the timed launches)."""
+    events (for counter runs that match the timed launches).  eps (default:
+    the workload's) and shift (< 0: the shift tau of Section 5.1) select
+    the form's threshold."""
+    eps = w.eps if eps is None else eps
     o = tlr.opts(bs=w.bs, bs_tail=bs_tail, tail_active=tail_active, eps_mode=eps_mode,
-                 precision=precision,
+                 precision=precision, shift=shift,
                  flags=(tlr.FLAG_KERNEL_TIMING if timing else 0) |
                        (tlr.FLAG_SERIAL_SAMPLING if serial else 0))
     for _ in range(warmup):
-        mat.potrf(w.eps, o)
+        mat.potrf(eps, o)
     torch.cuda.synchronize()
     if idle_s > 0:
         time.sleep(idle_s)
     t0 = time.perf_counter()
-    stats = [mat.potrf(w.eps, o) for _ in range(steps)]
+    stats = [mat.potrf(eps, o) for _ in range(steps)]
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps, stats
 
@@ -453,10 +457,11 @@ def main():
     ap.add_argument("--batched", type=int, default=96,
                     help="problems of the batched workload timed after the main line (0 = skip)")
     ap.add_argument("--form", default="fp64",
-                    choices=["fp64", "mixed_fp32_rel", "mixed_bf16_rel"],
-                    help="with --profile: the form to factor (fp64: the headline; mixed_fp32_rel: "
-                         "relative 1e-6 with FP32 panels; mixed_bf16_rel: relative 1e-2 with BF16 "
-                         "panels and the shift tau)")
+                    choices=["fp64", "fp64_rel", "mixed_fp32_rel", "mixed_bf16_rel", "fp64_rel2"],
+                    help="with --profile: the form to factor (fp64: the headline; fp64_rel: "
+                         "relative 1e-6 in FP64; mixed_fp32_rel: relative 1e-6 with FP32 panels; "
+                         "mixed_bf16_rel: relative 1e-2 with BF16 panels and the shift tau; "
+                         "fp64_rel2: relative 1e-2 in FP64 with the shift tau)")
     ap.add_argument("--profile", action="store_true",
                     help="for profilers: build the input, run the --warmup and --steps "
                          "factorizations and stop (no second pass, residual or other lines)")
@@ -503,8 +508,10 @@ def main():
     # percent of the step); the sampling kernel's durations come from the
     # dispatches' own events in a second pass of the same number of steps
     if a.profile and a.form != "fp64":
-        prec, eps, shift = ((tlr.MIXED_FP32, 1e-6, 0.0) if a.form == "mixed_fp32_rel"
-                            else (tlr.MIXED_BF16, 1e-2, -1.0))
+        prec, eps, shift = {"fp64_rel": (tlr.FP64, 1e-6, 0.0),
+                            "mixed_fp32_rel": (tlr.MIXED_FP32, 1e-6, 0.0),
+                            "mixed_bf16_rel": (tlr.MIXED_BF16, 1e-2, -1.0),
+                            "fp64_rel2": (tlr.FP64, 1e-2, -1.0)}[a.form]
         o = tlr.opts(bs=w.bs, eps_mode=tlr.EPS_REL, precision=prec, shift=shift)
         for _ in range(a.warmup):
             mat.potrf(eps, o)
@@ -543,20 +550,27 @@ def main():
     rl = mat.ranks(tlr.FACTOR)[np.tril_indices(mat.nb, -1)]
     # FP64 against mixed precision at the relative threshold, where the FP32
     # rounding guard admits the tiles (at an absolute 1e-6 it admits almost
-    # none, and the mixed form is the FP64 one)
+    # none, and the mixed form is the FP64 one), and BF16 against FP64 at a
+    # relative 1e-2 with the shift tau
     forms = {}
     if a.forms:
-        for name, mode, prec in (("fp64_rel", 1, tlr.FP64), ("mixed_fp32_rel", 1, tlr.MIXED_FP32),
-                                 ("mixed_fp32_abs", 0, tlr.MIXED_FP32)):
+        for name, mode, prec, feps, fshift in (
+                ("fp64_rel", 1, tlr.FP64, 1e-6, 0.0), ("mixed_fp32_rel", 1, tlr.MIXED_FP32, 1e-6, 0.0),
+                ("mixed_fp32_abs", 0, tlr.MIXED_FP32, 1e-6, 0.0),
+                ("fp64_rel_1e-2", 1, tlr.FP64, 1e-2, -1.0),
+                ("mixed_bf16_rel_1e-2", 1, tlr.MIXED_BF16, 1e-2, -1.0)):
             fdt, fst = time_form(mat, w, mode, prec, tlr, torch, a.steps, a.warmup, a.bs_tail,
-                                 a.tail_active, False)
+                                 a.tail_active, False, eps=feps, shift=fshift)
             s0 = fst[-1]
             forms[name] = {"ms_per_step": fdt * 1e3,
                            "tflops": float(np.mean([x["flops"] for x in fst])) / fdt / 1e12,
+                           "eps": feps, "shift": s0["shift"],
                            "eps_mode": "relative" if mode else "absolute", "tau": s0["tau"],
-                           "residual": residual(mat, torch),
+                           "residual": residual(mat, torch, shift=s0["shift"]),
                            "fp32_share": s0["fp32_tile_iters"] / max(1, s0["tile_iters"]),
+                           "bf16_share": s0["bf16_tile_iters"] / max(1, s0["tile_iters"]),
                            "ara_iterations": int(s0["ara_iters"]),
+                           "tile_iterations": int(s0["tile_iters"]),
                            "mean_rank": s0["mean_rank"], "max_rank": int(s0["max_rank"])}
             print("[bench] form %s: %.1f ms, residual %.3g" % (name, fdt * 1e3,
                                                                forms[name]["residual"]),

@@ -843,21 +843,17 @@ tlr_status col_finish(Prob& p, int k, bool ldl, const AraConfig& cfg, const AraS
   }
   if (h->mixed) {
     // ||L_ik||_F = ||V_ik||_F (U_ik orthonormal): read on the device by the
-    // next column's precision choice, and back on the host for the later
-    // columns' sums
+    // next column's precision choice, and stored by the same kernel to the
+    // host's pinned copy for the later columns' sums
     TLR_TRY(w.fro.ensure(h->mem, sizeof(double) * (size_t)std::max(nrow, 1)));
     double* fro = w.fro.as<double>();
     std::vector<NormDesc> nd;
     for (int s = 0; s < nrow; ++s)
-      nd.push_back(NormDesc{Bt + boff[s] * m, m, q[s], m, fro + s});
+      nd.push_back(NormDesc{Bt + boff[s] * m, m, q[s], m, fro + s, p.pin_norm + s});
     const size_t off = plan.stage(nd.data(), sizeof(NormDesc) * nd.size());
     const int n = nrow;
     hipStream_t st = h->stream;
-    double* pn = p.pin_norm;
     plan.launch(off, [=](const char* ptr) { return launch_fro_norms((const NormDesc*)ptr, n, st); });
-    plan.launch([=]() {
-      return hipMemcpyAsync(pn, fro, sizeof(double) * n, hipMemcpyDeviceToHost, st);
-    });
   }
   TLR_TRY(plan.run());
   p.flops += plan.flops;

@@ -29,17 +29,25 @@ __global__ __launch_bounds__(256) void k_copy_batched(const CopyDesc* __restrict
 }
 
 // Frobenius norms: one workgroup per block, a fixed-order tree reduction.
+// Thread t takes the entries t, t + 256, ... of the block in column-major
+// order (32-bit indices: a block has at most 2^31 entries), eight loads in
+// flight before their squares are added; the norm also goes to pinned host
+// memory when the descriptor names it (stores at system scope).
 __global__ __launch_bounds__(256) void k_fro_norms(const NormDesc* __restrict__ descs) {
   __shared__ double red[256];
   const NormDesc d = descs[blockIdx.x];
+  const int n = d.rows * d.cols;
+  constexpr int U = 8;
   double s = 0.0;
-  // column by column (no 64-bit index division on the way; coalesced rows)
-  for (int c = 0; c < d.cols; ++c) {
-    const double* col = d.p + (size_t)c * d.ld;
-    for (int r = threadIdx.x; r < d.rows; r += 256) {
-      const double v = col[r];
-      s += v * v;
+  for (int e0 = threadIdx.x; e0 < n; e0 += 256 * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + 256 * u;
+      v[u] = (e < n) ? d.p[(e % d.rows) + (size_t)(e / d.rows) * d.ld] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) s = fma(v[u], v[u], s);
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -47,7 +55,13 @@ __global__ __launch_bounds__(256) void k_fro_norms(const NormDesc* __restrict__ 
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *d.out = sqrt(red[0]);
+  if (threadIdx.x == 0) {
+    const double f = sqrt(red[0]);
+    *d.out = f;
+    if (d.host)
+      __hip_atomic_store((unsigned long long*)d.host, (unsigned long long)__double_as_longlong(f),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // Partial sums of the squared Frobenius norms of symmetric m x m tiles held

@@ -298,6 +298,7 @@ struct NormDesc {
   const double* p;
   int rows, cols, ld;
   double* out;
+  double* host;   // when set, the norm is also stored here (pinned host memory)
 };
 hipError_t launch_fro_norms(const NormDesc* d, int n, hipStream_t s);
 // Squared Frobenius norms of n symmetric m x m tiles (lower triangle, ld;
