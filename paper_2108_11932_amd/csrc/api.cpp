@@ -490,6 +490,7 @@ tlr_status tlr_destroy(tlr_matrix_t A) {
   mem.put(A->d_info);
   if (A->side) (void)hipStreamSynchronize(A->side);
   A->ws.release_all(mem);
+  A->dg.destroy(mem);
   A->stage.release(mem);
   A->release_host();
   if (A->ev_fork) (void)hipEventDestroy(A->ev_fork);

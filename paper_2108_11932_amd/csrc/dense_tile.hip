@@ -317,6 +317,28 @@ __global__ void k_tri_finish(double* A, int lda, const double* Lp, int ldp, int 
     gmem(A)[r + (size_t)c * lda] = gmem(Lp)[r + (size_t)c * ldp];
 }
 
+// After a replay of the captured factorization: copy the results out of
+// its fixed buffers and merge its status word (see launch_diag_out).
+__global__ void k_diag_out(const double* __restrict__ A, double* __restrict__ Adst,
+                           const double* __restrict__ Linv, double* __restrict__ Ldst,
+                           const double* __restrict__ D, double* __restrict__ Ddst, int m,
+                           int* ginfo, int* info, int row_base) {
+  const long long e = blockIdx.x * 256LL + threadIdx.x;
+  const long long n = (long long)m * m;
+  if (e < n) {
+    gmem(Adst)[e] = gmem((const double*)A)[e];
+    gmem(Ldst)[e] = gmem((const double*)Linv)[e];
+  }
+  if (D && e < m) gmem(Ddst)[e] = gmem((const double*)D)[e];
+  if (e == 0) {
+    const int bad = ginfo[0], nmod = ginfo[1];
+    if (bad) atomicCAS(info, 0, row_base + bad);
+    if (nmod) atomicAdd(info + 1, nmod);
+    ginfo[0] = 0;
+    ginfo[1] = 0;
+  }
+}
+
 // out(r, c) = in(r, c) * s[c] or / s[c] (column scaling, LDL^T panels).
 __global__ void k_scale_cols(const double* in, int ldi, double* out, int ldo, const double* s,
                              int rows, int cols, int inverse) {
@@ -397,6 +419,16 @@ hipError_t launch_potrf_step(bool chol, double* A, int lda, int m, int p0, doubl
   else
     hipLaunchKernelGGL(k_potrf_step<false>, dim3(nwg), dim3(256), 0, s, A, lda, m, p0, Lp, ldp,
                        Inv, ldi, dvec, info, row_base, tolp);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_out(const double* A, double* Adst, const double* Linv, double* Ldst,
+                           const double* D, double* Ddst, int m, int* ginfo, int* info,
+                           int row_base, hipStream_t s) {
+  const long long n = (long long)m * m;
+  if (n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_diag_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, Adst, Linv,
+                     Ldst, D, Ddst, m, ginfo, info, row_base);
   return hipGetLastError();
 }
 

@@ -142,6 +142,9 @@ struct Prob {
   double* pin_norm = nullptr;
   bool done = false;
   bool piv = false;   // pivoted Cholesky (Section 5.2)
+  // the diagonal tiles' factorization replayed from the handle's captured
+  // graph (else launched kernel by kernel)
+  DiagGraph* dg = nullptr;
   double mod_delta = 0.0;   // > 0: modified Cholesky of the diagonal tiles (Section 5.1.2)
   double flops = 0.0, flops_paper = 0.0, bytes_alg = 0.0, samp_bytes = 0.0, samp_flops = 0.0;
   long long ara_iters = 0, tile_iters = 0, fp32_tile_iters = 0, bf16_tile_iters = 0;
@@ -209,6 +212,9 @@ tlr_status prob_init(Prob& p, double eps, const tlr_opts& o, bool ldl) {
   // modified Cholesky: a diagonal tile that lost definiteness has its
   // non-positive pivots raised to the threshold
   p.mod_delta = (!ldl && (o.flags & TLR_FLAG_MODIFIED_CHOL)) ? p.tau : 0.0;
+  p.dg = nullptr;
+  if (o.flags & TLR_FLAG_DIAG_GRAPH)
+    TLR_TRY(diag_graph(h, m, ldl ? 2 : (p.mod_delta > 0.0 ? 1 : 0), &p.dg));
   // mixed precision: packed FP32 (and BF16) copies of the U panels, used by
   // the tiles whose rounding in that precision stays below tau / 16 (the
   // LDL^T variant samples in FP64 throughout).  The automatic form keeps a
@@ -475,11 +481,13 @@ tlr_status col_diag(Prob& p, int k, bool ldl) {
   dplan.persist = &w.sideblob;
   {
     // pivoting: the updated tile S_k already holds the shift and every
-    // low rank product of the columns j < k
+    // low rank product of the columns j < k.  The updated tile is formed in
+    // place of the factor, or in the captured factorization's buffer.
     const double* Akk = p.piv ? h->Sd + (size_t)h->spos[k] * m * m : h->diagA(k);
     const int nr = h->nreal(k);
     const double shift = p.piv ? 0.0 : p.shift;
-    dplan.launch([=]() { return launch_copy_shift(Akk, Lkk, m, nr, shift, ds); });
+    double* Tk = p.dg ? p.dg->A.as<double>() : Lkk;
+    dplan.launch([=]() { return launch_copy_shift(Akk, Tk, m, nr, shift, ds); });
     if (Rk > 0 && !p.piv) {
       double* Wd = w.Wd.as<double>();
       GemmBatch wb(false, false);
@@ -490,12 +498,33 @@ tlr_status col_diag(Prob& p, int k, bool ldl) {
       }
       dplan.gemm(wb);
       GemmBatch up(false, true);
-      up.add(m, m, Rk, Wd, m, h->UL[k], m, Lkk, m, -1.0, 1.0, GEMM_LOWER_C);
+      up.add(m, m, Rk, Wd, m, h->UL[k], m, Tk, m, -1.0, 1.0, GEMM_LOWER_C);
       dplan.gemm(up);
       p.flops += wb.flops + up.flops / 2;
     }
-    TLR_TRY(dense_factor(h, dplan, !ldl, Lkk, m, m, ldl ? h->Dv + (size_t)k * m : nullptr, k * m,
-                         h->invL(k), p.mod_delta));
+    if (DiagGraph* g = p.dg) {
+      // the updated tile went to the graph's buffer (above); one replay,
+      // then the results to their places
+      double* tol = g->tol.as<double>();
+      const double md = p.mod_delta;
+      if (md > 0.0) dplan.launch([=]() { return launch_fill(tol, 1, md, ds); });
+      hipGraphExec_t ex = g->exec;
+      dplan.launch([=]() { return hipGraphLaunch(ex, ds); });
+      const double* gA = g->A.as<double>();
+      const double* gL = g->Linv.as<double>();
+      const double* gD = ldl ? g->D.as<double>() : nullptr;
+      double* dv = ldl ? h->Dv + (size_t)k * m : nullptr;
+      double* Li = h->invL(k);
+      int* gi = g->info.as<int>();
+      int* info = h->d_info;
+      const int rb = k * m;
+      dplan.launch([=]() {
+        return launch_diag_out(gA, Lkk, gL, Li, gD, dv, m, gi, info, rb, ds);
+      });
+    } else {
+      TLR_TRY(dense_factor(h, dplan, !ldl, Lkk, m, m, ldl ? h->Dv + (size_t)k * m : nullptr,
+                           k * m, h->invL(k), p.mod_delta));
+    }
     // the staged descriptors go up from this thread; the launches are
     // issued by the handle's side worker, which also records the join
     TLR_TRY(dplan.run_some(0));

@@ -174,6 +174,22 @@ struct Work {
   }
 };
 
+// The blocked factorization of a diagonal tile (the launches of
+// dense_factor) captured once as a HIP graph on fixed buffers, and replayed
+// for every column: one graph launch on the diagonal-tile stream instead of
+// one launch per panel.  mode: 0 Cholesky, 1 modified Cholesky (pivot floor
+// read from tol, filled before each replay), 2 LDL^T.  The graph writes its
+// status word (rows local to the tile) to info; the caller merges and
+// clears it after each replay (launch_diag_out).
+struct DiagGraph {
+  int m = 0, mode = -1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;   // capture stream: records, never executes
+  DevBuf A, Linv, W, D, info, tol, desc;
+  void destroy(Mem& mem);
+};
+
 // Phase timing of one stream (TLR_FLAG_PHASE_TIMING): events recorded at the
 // phase boundaries; the GPU time between a mark and the next one is charged
 // to the phase of the first (phase < 0: not charged, e.g. an idle gap on the
@@ -261,6 +277,7 @@ struct tlr_matrix_s {
 
   Work ws;
   int* d_info = nullptr;          // device status word
+  tlr::DiagGraph dg;              // captured diagonal-tile factorization
 
   int nreal(int k) const {
     const long long r = N - (long long)k * m;
@@ -323,6 +340,10 @@ tlr_status dense_trsm(Handle* h, const double* L, int ldl, double* B, int ldb, i
 // mod_delta and counted in d_info[1]).
 tlr_status dense_factor(Handle* h, struct Plan& plan, bool chol, double* A, int lda, int m,
                         double* d, int row_base, double* Linv, double mod_delta = 0.0);
+// The handle's captured diagonal-tile factorization for tile size m and
+// mode (DiagGraph), built on first use (or when m or mode change: then both
+// streams are drained first).
+tlr_status diag_graph(Handle* h, int m, int mode, DiagGraph** out);
 
 // Kernel wrappers not declared in tlr_internal.h.
 // p[0 .. n) = v

@@ -561,24 +561,16 @@ static void inverse_assemble(Plan& plan, const double* L, int ldl, int m, double
   }
 }
 
-tlr_status dense_factor(Handle* h, Plan& plan, bool chol, double* A, int lda, int m, double* d,
-                        int row_base, double* Linv, double mod_delta) {
-  Work& w = h->ws;
+// The launches of the blocked factorization of the m x m tile A (ld lda)
+// and of the assembly of Linv, on the workspace W (m x m), the device word
+// tol and the status word info.  modify: modified Cholesky, its pivot floor
+// already in tol (Cholesky only); LDL^T forms its pivot tolerance in tol.
+static void factor_launches(Plan& plan, bool chol, double* A, int lda, int m, double* d,
+                            int row_base, double* Linv, double* W, double* tol, int* info,
+                            bool modify) {
   hipStream_t s = plan.s;
-  const size_t need = sizeof(double) * (size_t)m * m;
-  if (w.dW.cap < need || w.dtol.cap < 256) {
-    TLR_HIP(hipStreamSynchronize(s));
-    TLR_TRY(w.dW.ensure(h->mem, need));
-    TLR_TRY(w.dtol.ensure(h->mem, 256));
-  }
-  double* W = w.dW.as<double>();
-  double* tol = w.dtol.as<double>();
-  int* info = h->d_info;
-  plan.launch([=]() { return hipMemsetAsync(Linv, 0, sizeof(double) * (size_t)m * m, s); });
+  plan.launch([=]() { return launch_fill(Linv, (long long)m * m, 0.0, s); });
   if (!chol) plan.launch([=]() { return launch_pivot_tol(A, lda, m, tol, s); });
-  // modified Cholesky: the pivot floor for the panel kernels
-  const bool modify = chol && mod_delta > 0.0;
-  if (modify) plan.launch([=]() { return launch_fill(tol, 1, mod_delta, s); });
   const double* tolk = (chol && !modify) ? nullptr : tol;
   const int nd = diag_block_size();
   // W holds the panels below the diagonal blocks until the last step (A's
@@ -590,6 +582,79 @@ tlr_status dense_factor(Handle* h, Plan& plan, bool chol, double* A, int lda, in
     });
   plan.launch([=]() { return launch_tri_finish(A, lda, W, m, m, s); });
   inverse_assemble(plan, A, lda, m, Linv, W);
+}
+
+tlr_status dense_factor(Handle* h, Plan& plan, bool chol, double* A, int lda, int m, double* d,
+                        int row_base, double* Linv, double mod_delta) {
+  Work& w = h->ws;
+  hipStream_t s = plan.s;
+  const size_t need = sizeof(double) * (size_t)m * m;
+  if (w.dW.cap < need || w.dtol.cap < 256) {
+    TLR_HIP(hipStreamSynchronize(s));
+    TLR_TRY(w.dW.ensure(h->mem, need));
+    TLR_TRY(w.dtol.ensure(h->mem, 256));
+  }
+  double* tol = w.dtol.as<double>();
+  // modified Cholesky: the pivot floor for the panel kernels
+  const bool modify = chol && mod_delta > 0.0;
+  if (modify) plan.launch([=]() { return launch_fill(tol, 1, mod_delta, s); });
+  factor_launches(plan, chol, A, lda, m, d, row_base, Linv, w.dW.as<double>(), tol, h->d_info,
+                  modify);
+  return TLR_OK;
+}
+
+void DiagGraph::destroy(Mem& mem) {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  exec = nullptr;
+  graph = nullptr;
+  if (cap) (void)hipStreamDestroy(cap);
+  cap = nullptr;
+  DevBuf* bufs[] = {&A, &Linv, &W, &D, &info, &tol, &desc};
+  for (DevBuf* b : bufs) b->release(mem);
+  m = 0;
+  mode = -1;
+}
+
+tlr_status diag_graph(Handle* h, int m, int mode, DiagGraph** out) {
+  DiagGraph& g = h->dg;
+  *out = &g;
+  if (g.exec && g.m == m && g.mode == mode) return TLR_OK;
+  // the buffers of a previous graph may still be read by queued work
+  TLR_TRY(h->sync());
+  g.destroy(h->mem);
+  const size_t mm = sizeof(double) * (size_t)m * m;
+  TLR_TRY(g.A.ensure(h->mem, mm));
+  TLR_TRY(g.Linv.ensure(h->mem, mm));
+  TLR_TRY(g.W.ensure(h->mem, mm));
+  TLR_TRY(g.D.ensure(h->mem, sizeof(double) * (size_t)m));
+  TLR_TRY(g.info.ensure(h->mem, 256));
+  TLR_TRY(g.tol.ensure(h->mem, 256));
+  TLR_HIP(hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking));
+  TLR_HIP(hipMemsetAsync(g.info.p, 0, 256, g.cap));
+  const bool chol = mode != 2;
+  Plan plan(h, g.cap);
+  plan.persist = &g.desc;
+  factor_launches(plan, chol, g.A.as<double>(), m, m, chol ? nullptr : g.D.as<double>(), 0,
+                  g.Linv.as<double>(), g.W.as<double>(), g.tol.as<double>(), g.info.as<int>(),
+                  mode == 1);
+  // the GEMM descriptors go up before the capture (the graph reads them
+  // where they stay); then every launch is recorded, none executed
+  TLR_TRY(plan.run_some(0));
+  TLR_HIP(hipStreamSynchronize(g.cap));
+  TLR_HIP(hipStreamBeginCapture(g.cap, hipStreamCaptureModeRelaxed));
+  const tlr_status st = plan.run();
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(g.cap, &graph);
+  if (st != TLR_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != TLR_OK) return st;
+    TLR_HIP(e);
+  }
+  g.graph = graph;
+  TLR_HIP(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+  g.m = m;
+  g.mode = mode;
   return TLR_OK;
 }
 

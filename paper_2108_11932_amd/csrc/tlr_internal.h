@@ -92,6 +92,14 @@ hipError_t launch_potrf_step(bool chol, double* A, int lda, int m, int p0, doubl
                              double* Inv, int ldi, double* dvec, int* info, int row_base,
                              const double* tolp, hipStream_t s);
 hipError_t launch_tri_finish(double* A, int lda, const double* Lp, int ldp, int m, hipStream_t s);
+// After a replay of the captured diagonal-tile factorization: the factor A
+// and the inverse Linv (m x m, ld m) to Adst and Ldst (ld m), the pivots D
+// to Ddst (both NULL for Cholesky), and the graph's status word ginfo (two
+// ints, rows local to the tile) into info (first failing row row_base +
+// ginfo[0], modified pivots added), ginfo then cleared.
+hipError_t launch_diag_out(const double* A, double* Adst, const double* Linv, double* Ldst,
+                           const double* D, double* Ddst, int m, int* ginfo, int* info,
+                           int row_base, hipStream_t s);
 // out(r, c) = in(r, c) * s[c] (or / s[c]).
 hipError_t launch_scale_cols(const double* in, int ldi, double* out, int ldo, const double* sc,
                              int rows, int cols, bool inverse, hipStream_t s);

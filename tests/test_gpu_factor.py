@@ -385,3 +385,65 @@ def test_modified_cholesky_matches_oracle():
     l1, l2 = oracle_tlr(m1, tlr.FACTOR), oracle_tlr(m2, tlr.FACTOR)
     for k in range(t2.nb):
         np.testing.assert_array_equal(l1.diag[k], l2.diag[k])
+
+
+def _factor_arrays(mat):
+    diag, u, v, ranks = mat.to_host(tlr.FACTOR)
+    return diag, u, v, ranks
+
+
+@pytest.mark.parametrize("form", ["chol", "ldlt", "modified"])
+def test_diag_graph_replay_matches_launches(form):
+    # With TLR_FLAG_DIAG_GRAPH the diagonal tiles' factorization is captured
+    # once as a HIP graph and replayed for every column, with the column's
+    # other work between the replays; its factor must equal the
+    # kernel-by-kernel launches' bit for bit, on every column (each column is
+    # one replay), over two calls in a row, the second with the graph
+    # already built.
+    if form == "modified":
+        n, m, eps = 384, 64, 1e-9
+        t = otlr.compress_dense(_lost_definiteness(n, m), m, 1e-11)
+        base = tlr.FLAG_MODIFIED_CHOL
+    else:
+        n, m, eps = 2048, 256, 1e-6
+        t = otlr.compress_dense(_cov(n, 11)[1], m, eps)
+        base = 0
+    ref, got = _upload(t), _upload(t)
+
+    def run(mat, flags):
+        o = tlr.opts(flags=flags)
+        if form == "ldlt":
+            st, d = mat.ldlt(eps, o)
+            return st, d.cpu().numpy()
+        return mat.potrf(eps, o), None
+
+    st_r, d_r = run(ref, base)
+    for call in range(2):
+        st_g, d_g = run(got, base | tlr.FLAG_DIAG_GRAPH)
+        assert st_g["info"] == st_r["info"] == 0
+        assert st_g["modified_pivots"] == st_r["modified_pivots"]
+        if form == "modified":
+            assert st_g["modified_pivots"] > 0
+        a, b = _factor_arrays(ref), _factor_arrays(got)
+        np.testing.assert_array_equal(a[3], b[3])
+        for k in range(t.nb):
+            np.testing.assert_array_equal(a[0][k], b[0][k])
+        for key in a[1]:
+            np.testing.assert_array_equal(a[1][key], b[1][key])
+            np.testing.assert_array_equal(a[2][key], b[2][key])
+        if d_r is not None:
+            np.testing.assert_array_equal(d_r, d_g)
+    # a failing tile is reported at its global row through the replay too
+    if form == "chol":
+        bad = t.dense_symmetric().copy()
+        bad[700, 700] = -1.0
+        tb = otlr.compress_dense(bad, m, eps)
+        m1, m2 = _upload(tb), _upload(tb)
+        s1, i1 = m1.potrf_status(eps)
+        s2, i2 = m2.potrf_status(eps, tlr.opts(flags=tlr.FLAG_DIAG_GRAPH))
+        assert s1 == s2 != 0
+        assert i1["info"] == i2["info"] > 512
+        m1.close()
+        m2.close()
+    ref.close()
+    got.close()
