@@ -348,6 +348,9 @@ tlr_status diag_graph(Handle* h, int m, int mode, DiagGraph** out);
 // Kernel wrappers not declared in tlr_internal.h.
 // p[0 .. n) = v
 hipError_t launch_fill(double* p, long long n, double v, hipStream_t s);
+// tol[0] = 64 u ||A||_F for the m x m tile A (lower triangle); tol must hold
+// kPivotTolDoubles doubles (partial sums beside the result).
+constexpr int kPivotTolDoubles = 32 + 256;
 hipError_t launch_pivot_tol(const double* A, int lda, int m, double* tol, hipStream_t s);
 
 // Batched ARA over a set of explicitly sampled operators: shared by the

@@ -126,21 +126,40 @@ __global__ void k_fill(double* p, long long n, double v) {
   if (e < n) p[e] = v;
 }
 
-// 64 * u * ||A||_F (the LDL^T zero-pivot tolerance) for an m x m tile.
-__global__ __launch_bounds__(256) void k_pivot_tol(const double* A, int lda, int m, double* tol) {
+// 64 * u * ||A||_F (the LDL^T zero-pivot tolerance) for an m x m tile held
+// by its lower triangle (the strict upper part may be stale), in two
+// launches: workgroup g of kPivotParts adds columns g, g + kPivotParts, ...
+// (entries below the diagonal twice) into parts[g]; one workgroup then adds
+// the partials in a fixed tree order.
+constexpr int kPivotParts = 256;
+
+__global__ __launch_bounds__(256) void k_pivot_tol_parts(const double* A, int lda, int m,
+                                                         double* parts) {
   __shared__ double red[256];
   double s = 0.0;
-  // the lower triangle holds the tile (the strict upper part may be stale)
-  for (long long e = threadIdx.x; e < (long long)m * m; e += blockDim.x) {
-    const int r = (int)(e % m), c = (int)(e / m);
-    if (r < c) continue;
-    const double v = A[r + (size_t)c * lda];
-    s += (r == c ? 1.0 : 2.0) * v * v;
+  for (int c = blockIdx.x; c < m; c += kPivotParts) {
+    const double* col = A + (size_t)c * lda;
+    for (int r = c + (int)threadIdx.x; r < m; r += 256) {
+      const double v = col[r];
+      s += (r == c ? 1.0 : 2.0) * (v * v);
+    }
   }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) parts[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kPivotParts) void k_pivot_tol_final(const double* parts,
+                                                                 double* tol) {
+  __shared__ double red[kPivotParts];
+  red[threadIdx.x] = parts[threadIdx.x];
+  __syncthreads();
+  for (int o = kPivotParts / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
   if (threadIdx.x == 0) *tol = 64.0 * 1.1102230246251565e-16 * sqrt(red[0]);
@@ -243,7 +262,9 @@ hipError_t launch_fill(double* p, long long n, double v, hipStream_t s) {
 }
 
 hipError_t launch_pivot_tol(const double* A, int lda, int m, double* tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_pivot_tol, dim3(1), dim3(256), 0, s, A, lda, m, tol);
+  double* parts = tol + 32;
+  hipLaunchKernelGGL(k_pivot_tol_parts, dim3(kPivotParts), dim3(256), 0, s, A, lda, m, parts);
+  hipLaunchKernelGGL(k_pivot_tol_final, dim3(1), dim3(kPivotParts), 0, s, parts, tol);
   return hipGetLastError();
 }
 

@@ -589,10 +589,11 @@ tlr_status dense_factor(Handle* h, Plan& plan, bool chol, double* A, int lda, in
   Work& w = h->ws;
   hipStream_t s = plan.s;
   const size_t need = sizeof(double) * (size_t)m * m;
-  if (w.dW.cap < need || w.dtol.cap < 256) {
+  const size_t ntol = sizeof(double) * kPivotTolDoubles;
+  if (w.dW.cap < need || w.dtol.cap < ntol) {
     TLR_HIP(hipStreamSynchronize(s));
     TLR_TRY(w.dW.ensure(h->mem, need));
-    TLR_TRY(w.dtol.ensure(h->mem, 256));
+    TLR_TRY(w.dtol.ensure(h->mem, ntol));
   }
   double* tol = w.dtol.as<double>();
   // modified Cholesky: the pivot floor for the panel kernels
@@ -629,7 +630,7 @@ tlr_status diag_graph(Handle* h, int m, int mode, DiagGraph** out) {
   TLR_TRY(g.W.ensure(h->mem, mm));
   TLR_TRY(g.D.ensure(h->mem, sizeof(double) * (size_t)m));
   TLR_TRY(g.info.ensure(h->mem, 256));
-  TLR_TRY(g.tol.ensure(h->mem, 256));
+  TLR_TRY(g.tol.ensure(h->mem, sizeof(double) * kPivotTolDoubles));
   TLR_HIP(hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking));
   TLR_HIP(hipMemsetAsync(g.info.p, 0, 256, g.cap));
   const bool chol = mode != 2;
