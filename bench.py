@@ -594,10 +594,18 @@ def main():
                    "precision": "fp64"},
         "time_to_solution_s": dt,
         "tflops_paper_count": flops_paper / dt / 1e12,
-        "ranks_factor": {"min": int(rl.min()), "mean": float(rl.mean()), "max": int(rl.max())},
+        "ranks_factor": {"min": int(rl.min()), "median": float(np.median(rl)),
+                         "mean": float(rl.mean()), "max": int(rl.max())},
         "ara_iterations": int(stats[-1]["ara_iters"]),
         "tau": stats[-1]["tau"],
         "residual": err_primary,
+        # the error bound the parity tests hold the factor to:
+        # ||(A - L L^T) x|| / ||x|| <= ||A - L L^T||_2, each off-diagonal tile
+        # of the error at most tau (the ARA threshold, both triangles), and
+        # errors of independent tiles adding up like sqrt(nb) (the rigorous
+        # worst case, (nb - 1) tau, is far looser)
+        "residual_bound": 2.0 * math.sqrt(mat.nb) * stats[-1]["tau"],
+        "residual_within_bound": bool(err_primary <= 2.0 * math.sqrt(mat.nb) * stats[-1]["tau"]),
         "forms": forms,
         "phases": phases,
         "kernels": kernel_table(w.name),

@@ -112,18 +112,23 @@ __device__ inline void orth_body(const AraDev& D, int r_min, int bx, int by) {
   const int nc = PIV ? BS : qnew - qold;
   if (nc == 0) return;
   // ---- sum of the partial Gram matrices (stored for a <= b).  Thread t
-  // sums entries e = t, t + APPLY_ROWS, ... (a = e % BS, b = e / BS) over
-  // the strips with one 16-byte (hi, lo) load per strip, consecutive
-  // threads reading consecutive entries of a strip, in chunks of PCH
+  // sums the pairs p = t, t + APPLY_ROWS, ... of the upper triangle (b
+  // major: entry e = a + b BS, a <= b; at most three per thread when
+  // BS = 32) over the strips with one 16-byte (hi, lo) load per strip,
+  // nearby threads reading nearby entries of a strip, in chunks of PCH
   // strips all in flight before the sums (one round for m <= 1024 in pass
   // 1; pass 2 runs inside the fused sampling launch, whose occupancy the
   // registers of a larger chunk would halve); the sums go to copy 0 of the
   // Gram in LDS, both triangles (entries beyond nc are zero).
   constexpr int PCH = PIV ? 64 : 32;
   dd (*G0)[BS + 1] = (dd (*)[BS + 1])smem;
-  for (int e = t; e < BS * BS; e += APPLY_ROWS) {
-    const int a = e % BS, b = e / BS;
-    if (a > b) continue;
+  constexpr int NPAIR = BS * (BS + 1) / 2;
+  for (int p = t; p < NPAIR; p += APPLY_ROWS) {
+    int b = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+    while (b * (b + 1) / 2 > p) --b;
+    while ((b + 1) * (b + 2) / 2 <= p) ++b;
+    const int a = p - b * (b + 1) / 2;
+    const int e = a + b * BS;
     dd acc{0.0, 0.0};
     if (b < nc) {
       // compensated summation (Sum2 of Ogita, Rump and Oishi): the running

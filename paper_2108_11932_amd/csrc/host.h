@@ -352,6 +352,11 @@ hipError_t launch_fill(double* p, long long n, double v, hipStream_t s);
 // kPivotTolDoubles doubles (partial sums beside the result).
 constexpr int kPivotTolDoubles = 32 + 256;
 hipError_t launch_pivot_tol(const double* A, int lda, int m, double* tol, hipStream_t s);
+// *out = ||x||_2 (device; parts: kPivotTolDoubles - 32 doubles of device
+// scratch), summed in a fixed order; x = y / *sc (y where *sc is zero).
+hipError_t launch_norm2(const double* x, long long n, double* out, double* parts, hipStream_t s);
+hipError_t launch_scale_by(const double* y, long long n, const double* sc, double* x,
+                           hipStream_t s);
 
 // Batched ARA over a set of explicitly sampled operators: shared by the
 // factorization (Schur-complement tiles) and the compression (explicit tiles).

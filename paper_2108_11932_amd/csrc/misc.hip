@@ -261,6 +261,57 @@ hipError_t launch_fill(double* p, long long n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ||x||_2 of a vector: kPivotParts grid-stride partial sums of squares,
+// then one workgroup adds them in a fixed tree order (*out on the device).
+__global__ __launch_bounds__(256) void k_sumsq_parts(const double* __restrict__ x, long long n,
+                                                     double* parts) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * kPivotParts)
+    s = fma(x[i], x[i], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) parts[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kPivotParts) void k_norm_final(const double* parts, double* out) {
+  __shared__ double red[kPivotParts];
+  red[threadIdx.x] = parts[threadIdx.x];
+  __syncthreads();
+  for (int o = kPivotParts / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sqrt(red[0]);
+}
+
+// x = y / *s (x = y when *s is zero)
+__global__ void k_scale_by(const double* __restrict__ y, long long n, const double* s,
+                           double* __restrict__ x) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  const double d = *s;
+  x[i] = d > 0.0 ? y[i] / d : y[i];
+}
+
+hipError_t launch_norm2(const double* x, long long n, double* out, double* parts, hipStream_t s) {
+  if (n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sumsq_parts, dim3(kPivotParts), dim3(256), 0, s, x, n, parts);
+  hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kPivotParts), 0, s, parts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_by(const double* y, long long n, const double* sc, double* x,
+                           hipStream_t s) {
+  if (n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scale_by, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, n, sc, x);
+  return hipGetLastError();
+}
+
 hipError_t launch_pivot_tol(const double* A, int lda, int m, double* tol, hipStream_t s) {
   double* parts = tol + 32;
   hipLaunchKernelGGL(k_pivot_tol_parts, dim3(kPivotParts), dim3(256), 0, s, A, lda, m, parts);

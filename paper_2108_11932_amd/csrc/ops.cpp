@@ -89,52 +89,34 @@ tlr_status matvec(Handle* h, int nrhs, const double* X, long long ldx, double* Y
 }
 
 tlr_status estimate_norm(Handle* h, double* out) {
+  // power iteration on the TLR input (20 steps from a Gaussian start), the
+  // norms and the normalisation on the device; one read-back at the end
   const long long n = h->N;
   void* xv = nullptr;
-  TLR_TRY(h->mem.get(&xv, sizeof(double) * n * 2));
+  TLR_TRY(h->mem.get(&xv, sizeof(double) * (n * 2 + 2 + 256)));
   double* x = (double*)xv;
   double* y = x + n;
-  std::vector<double> hv(n);
+  double* nrm = y + n;          // [0] ||x_0||, [1] ||A x|| of the last step
+  double* parts = nrm + 2;
   tlr_status st = TLR_OK;
-  double lam = 0.0;
-  if (launch_randn(x, (int)n, 1, (int)n, 0x4e6f726dULL, 0, 0, 0, h->stream) != hipSuccess) {
-    set_error("norm estimate: randn launch failed");
-    st = TLR_ERR_DEVICE;
-  }
-  for (int it = 0; it < 20 && st == TLR_OK; ++it) {
-    st = matvec(h, 1, x, n, y, n);
-    if (st != TLR_OK) break;
-    if (hipMemcpyAsync(hv.data(), y, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream) !=
-        hipSuccess) {
-      st = TLR_ERR_DEVICE;
-      break;
+  double host[2] = {0.0, 0.0};
+  const int steps = 20;
+  auto body = [&]() -> tlr_status {
+    TLR_HIP(launch_randn(x, (int)n, 1, (int)n, 0x4e6f726dULL, 0, 0, 0, h->stream));
+    TLR_HIP(launch_norm2(x, n, nrm, parts, h->stream));
+    for (int it = 0; it < steps; ++it) {
+      TLR_TRY(matvec(h, 1, x, n, y, n));
+      TLR_HIP(launch_norm2(y, n, nrm + 1, parts, h->stream));
+      TLR_HIP(launch_scale_by(y, n, nrm + 1, x, h->stream));
     }
-    st = h->sync();
-    if (st != TLR_OK) break;
-    double s = 0.0;
-    for (double v : hv) s += v * v;
-    s = std::sqrt(s);
-    if (it == 0) {
-      // first pass normalises the random start vector's image
-      double xs = 0.0;
-      std::vector<double> hx(n);
-      (void)hipMemcpy(hx.data(), x, sizeof(double) * n, hipMemcpyDeviceToHost);
-      for (double v : hx) xs += v * v;
-      lam = s / std::sqrt(xs);
-    } else {
-      lam = s;
-    }
-    if (s == 0.0) break;
-    for (double& v : hv) v /= s;
-    if (hipMemcpyAsync(x, hv.data(), sizeof(double) * n, hipMemcpyHostToDevice, h->stream) !=
-        hipSuccess) {
-      st = TLR_ERR_DEVICE;
-      break;
-    }
-    st = h->sync();
-  }
+    TLR_HIP(hipMemcpyAsync(host, nrm, sizeof(double) * 2, hipMemcpyDeviceToHost, h->stream));
+    return h->sync();
+  };
+  st = body();
   h->mem.put(xv);
-  *out = lam;
+  // after the first step x is normalised, so the last ||A x|| is the estimate
+  // (the start vector's norm enters only when a single step ran)
+  *out = steps > 1 ? host[1] : (host[0] > 0.0 ? host[1] / host[0] : 0.0);
   return st;
 }
 
