@@ -15,7 +15,9 @@ Contents (each function cites the passage of the paper it follows):
                       Looking TLR LDL^T", Eq. (1)-(3)) with the ARA step
                       replaced by exact SVD truncation of the assembled
                       Schur-complement tile, the TLR triangular solve
-                      (Algorithm "TLR Triangular Solve") and the TLR matvec.
+                      (Algorithm "TLR Triangular Solve"), the TLR matvec and
+                      the SVD post-recompression of the low rank tiles
+                      (Section 6.2).
 * ``bookkeeping``  -- integer bookkeeping of the method: tile offsets, row
                       panel widths, the rank sort of "sortRanks" and the
                       active-set evolution of "updateSubset".

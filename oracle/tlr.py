@@ -448,3 +448,26 @@ def factor_error_norm(a: TLR, l: TLR, d: Optional[list] = None, seed: int = 7,
 def norm2(a: TLR, seed: int = 11, iters: int = 20) -> float:
     """||A||_2 of a symmetric TLR matrix by power iteration."""
     return dense.norm2_power(lambda x: matvec(a, x), a.n, seed=seed, iters=iters, rtol=0.0)
+
+
+# ---------------------------------------------------------------------------
+# SVD post-recompression of the low rank tiles (Section 6.2)
+# ---------------------------------------------------------------------------
+
+def recompress(t: TLR, tau: float) -> TLR:
+    """Minimal-rank form of every strictly lower tile at threshold tau.
+
+    Section 6.2 observes that the ranks the ARA finds sit a few percent above
+    the smallest ones the threshold allows, and that a post-processing pass
+    applying the SVD to each low rank tile reduces them to that minimum.
+    Each tile U V^T is expanded and replaced by its truncated SVD
+    (truncate_svd: the singular values above tau are kept, U orthonormal,
+    V = right vectors times singular values); the diagonal tiles are copied.
+    Returns a new TLR of the same kind (matrix or factor).
+    """
+    out = TLR(t.n, t.m)
+    out.diag = [d.copy() for d in t.diag]
+    for (i, j), u in t.u.items():
+        q, b, _ = truncate_svd(u @ t.v[i, j].T, tau)
+        out.u[i, j], out.v[i, j] = q, b
+    return out

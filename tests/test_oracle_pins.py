@@ -481,3 +481,75 @@ def test_tlr_modified_cholesky_exact_low_rank():
     assert np.abs(e).max() <= 1e-8 * np.abs(a).max()
     assert d.min() >= -1e-9 and np.count_nonzero(d > 1e-9) == rec["modified"]
     assert np.all(np.abs(d[:m]) <= 1e-9) and np.all(np.abs(d[2 * m:]) <= 1e-9)
+
+
+# ---------------------------------------------------------------- SVD post-recompression
+
+def _tile_with_spectrum(m, s, seed):
+    """U V^T with orthonormal U and singular values s (in a scrambled order),
+    V = Y diag(s) for an orthonormal Y: the exact spectrum is s."""
+    rng = np.random.default_rng(seed)
+    q = len(s)
+    x, _ = np.linalg.qr(rng.standard_normal((m, q)))
+    y, _ = np.linalg.qr(rng.standard_normal((m, q)))
+    order = rng.permutation(q)
+    return x, y[:, order] * np.asarray(s)[order]
+
+
+def test_recompress_keeps_exactly_the_values_above_tau():
+    """Eckart-Young: the kept count is #{sigma > tau}, the error is the first
+    dropped singular value, U stays orthonormal and the columns of V carry
+    the kept singular values (a dropped scaling or swapped factor fails)."""
+    m, tau = 64, 1e-3
+    s = tau * np.array([40.0, 9.0, 3.0, 1.0 + 1e-8, 1.0 - 1e-8, 0.5, 0.1, 1e-3])
+    a = tlr.TLR(3 * m, m)
+    a.u[1, 0], a.v[1, 0] = _tile_with_spectrum(m, s, 3)
+    a.u[2, 0], a.v[2, 0] = _tile_with_spectrum(m, s[:3] * 1e-3, 4)   # all below tau
+    a.u[2, 1], a.v[2, 1] = np.zeros((m, 0)), np.zeros((m, 0))
+    a.diag = [np.eye(m) * (k + 2.0) for k in range(3)]
+    r = tlr.recompress(a, tau)
+    assert r.ranks()[1, 0] == 4 and r.ranks()[2, 0] == 0 and r.ranks()[2, 1] == 0
+    u, v = r.u[1, 0], r.v[1, 0]
+    np.testing.assert_allclose(u.T @ u, np.eye(4), atol=1e-13)
+    np.testing.assert_allclose(np.linalg.norm(v, axis=0), s[:4], rtol=1e-12)
+    err = np.linalg.norm(a.tile(1, 0) - u @ v.T, 2)
+    assert abs(err - s[4]) <= 1e-12 * s[0]
+    # the upper tile is the transpose: the stored factors keep the lower orientation
+    np.testing.assert_allclose(r.tile(0, 1), (u @ v.T).T, atol=1e-15)
+    for k in range(3):
+        np.testing.assert_array_equal(r.diag[k], a.diag[k])
+    assert r.memory_doubles() == 3 * m * m + 2 * m * 4
+
+
+def test_recompress_is_idempotent_and_never_raises_an_svd_rank():
+    """A tile already at its minimal rank keeps it; on a truncated-SVD
+    compression (the minimal ranks) nothing changes but rounding."""
+    _, a = _cov(512, 128)
+    tau = 1e-6
+    t = tlr.compress_dense(a, 128, tau)
+    r = tlr.recompress(t, tau)
+    np.testing.assert_array_equal(r.ranks(), t.ranks())
+    for (i, j) in t.u:
+        np.testing.assert_allclose(r.tile(i, j), t.tile(i, j), atol=1e-13)
+    r2 = tlr.recompress(r, tau)
+    np.testing.assert_array_equal(r2.ranks(), r.ranks())
+
+
+def test_recompress_of_a_padded_rank_surplus():
+    """Extra directions of a tile (rank surplus, as the ARA leaves) are
+    removed: U = [X | X2], V = [Y S | 0-weighted] collapses to the rank of
+    the spectrum above tau; the result matches the dense truncated SVD."""
+    rng = np.random.default_rng(9)
+    m, tau = 48, 1e-4
+    s = np.array([3.0, 1.0, 1e-2, 5e-4, 5e-5, 1e-6])
+    x, v = _tile_with_spectrum(m, s, 11)
+    extra, _ = np.linalg.qr(np.hstack([x, rng.standard_normal((m, 5))]))
+    u_big = extra                                   # 11 orthonormal columns
+    v_big = np.hstack([v, 1e-7 * rng.standard_normal((m, 5))])
+    a = tlr.TLR(2 * m, m)
+    a.u[1, 0], a.v[1, 0] = u_big, v_big
+    r = tlr.recompress(a, tau)
+    dense_s = np.linalg.svd(u_big @ v_big.T, compute_uv=False)
+    assert r.rank(1, 0) == int(np.sum(dense_s > tau)) == 4
+    err = np.linalg.norm(a.tile(1, 0) - r.tile(1, 0), 2)
+    assert abs(err - dense_s[4]) <= 1e-12 * dense_s[0]
