@@ -384,6 +384,30 @@ size_t tlr_solve_noalloc_max_bytes(void);
 tlr_status tlr_pcg(tlr_matrix_t A, tlr_matrix_t F, const double* b, double* x, double rtol,
                    int maxit, int* iters, double* relres, void* stream);
 
+/* SVD post-recompression (Section 6.2: the ARA's ranks exceed the smallest
+ * ones its threshold allows by a few percent, which a pass applying the SVD
+ * to every low rank tile removes).  Every strictly lower tile U V^T of the
+ * input (which = TLR_INPUT) or of the factor (TLR_FACTOR) is replaced by its
+ * truncated SVD at the absolute 2-norm threshold tau: the singular values
+ * sigma_j > tau are kept, so each tile takes the smallest rank whose error
+ * is at most tau and changes by sigma_{r+1} <= tau in the 2-norm (the
+ * factorization's own threshold is stats->tau).  The new U has orthonormal
+ * columns, the new V = right singular vectors times sigma.  The tile's
+ * singular values are taken as the square roots of the eigenvalues of
+ * V^T V, which assumes orthonormal U: true of the factor and of input built
+ * by tlr_compress or tlr_compress_kernel; input with tiles from
+ * tlr_set_tile returns TLR_ERR_STATE.  The Gram matrix squares the spread of
+ * the singular values, so thresholds below about 1e-7 times a tile's norm
+ * are not resolved.  Tiles of rank above 2048 are kept as they are.  The
+ * panels shrink to the new ranks (offsets as tlr_get_offsets reports them);
+ * the factor stays usable by tlr_solve and tlr_pcg.
+ * Errors: TLR_ERR_ARG (tau negative or not finite, bad which; nothing
+ * changes), TLR_ERR_STATE (no factor, or input of unknown U), TLR_ERR_OOM
+ * when the work buffers cannot be allocated (nothing changes); a device
+ * error after tiles have moved leaves the factor invalid (the input
+ * undefined). */
+tlr_status tlr_recompress(tlr_matrix_t A, int which, double tau, void* stream);
+
 /* Y <- A X for the TLR input matrix (which = TLR_INPUT), X and Y N x nrhs in
  * device memory. */
 tlr_status tlr_matvec(tlr_matrix_t A, int nrhs, const double* X, long long ldx, double* Y,

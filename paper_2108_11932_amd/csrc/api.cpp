@@ -383,6 +383,22 @@ tlr_status tlr_matvec(tlr_matrix_t A, int nrhs, const double* X, long long ldx, 
   return A->sync();
 }
 
+tlr_status tlr_recompress(tlr_matrix_t A, int which, double tau, void* stream) {
+  TLR_ARG(A, "NULL handle");
+  TLR_ARG(which == TLR_INPUT || which == TLR_FACTOR, "which must be TLR_INPUT or TLR_FACTOR");
+  TLR_ARG(std::isfinite(tau) && tau >= 0.0, "tau must be finite and non-negative");
+  if (which == TLR_FACTOR && !A->factored) {
+    set_error("the handle holds no factor");
+    return TLR_ERR_STATE;
+  }
+  if (which == TLR_INPUT && !A->a_orth) {
+    set_error("the input tiles were set with tlr_set_tile: their U need not be orthonormal");
+    return TLR_ERR_STATE;
+  }
+  A->stream = A->mem.stream = (hipStream_t)stream;
+  return recompress(A, which, tau);
+}
+
 tlr_status tlr_get_info(tlr_matrix_t A, long long* N, int* m, int* nb, int* factored) {
   TLR_ARG(A, "NULL handle");
   if (N) *N = A->N;

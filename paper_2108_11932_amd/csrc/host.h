@@ -377,6 +377,7 @@ tlr_status factorize_batch(Handle* const* hs, int count, const double* eps, cons
 tlr_status compress(Handle* h, const double* A, long long lda, const double* pts, int dim,
                     int kernel, double ell, double diag_add, double eps, const tlr_opts& o);
 tlr_status estimate_norm(Handle* h, double* out);
+tlr_status recompress(Handle* h, int which, double tau);
 tlr_status matvec(Handle* h, int nrhs, const double* X, long long ldx, double* Y, long long ldy);
 tlr_status solve(Handle* h, int nrhs, double* B, long long ldb);
 // Doubles of workspace the solve of nrhs right-hand sides needs.

@@ -315,6 +315,24 @@ hipError_t launch_fro_norms(const NormDesc* d, int n, hipStream_t s);
 hipError_t launch_sym_fro_parts(const double* const* tiles, int n, int m, int ld, int G,
                                 double* out, hipStream_t s);
 hipError_t launch_copy_batched(const CopyDesc* d, int n, int max_cols, hipStream_t s);
+
+// SVD post-recompression (Section 6.2): symmetric eigensolver of the Gram
+// matrices V^T V of low rank tiles.  G (q x q, ld q) is overwritten with the
+// eigenvectors in descending order of the eigenvalues; res[0] receives the
+// number r of eigenvalues with sqrt(lambda) > tau, res[1] their sum.  W is a
+// q x q workspace for class 2.  Classes: 0 for q <= kEigLdsSmall, 1 for
+// q <= kEigLdsLarge (LDS-resident), 2 for q <= kEigMaxRank (global memory).
+// abs_scale > 0 adds the absolute rotation threshold abs_scale max_j g_jj
+// to the relative one (the first of the two passes).
+constexpr int kEigLdsSmall = 32, kEigLdsLarge = 64, kEigMaxRank = 2048;
+struct EigDesc {
+  double* G;
+  double* W;
+  double* res;
+  int q;
+};
+hipError_t launch_sym_eig(const EigDesc* d, int n, int cls, double tau, double abs_scale,
+                          hipStream_t s);
 // dst = src (m x m) + shift on the first nreal diagonal entries.
 hipError_t launch_copy_shift(const double* src, double* dst, int m, int nreal, double shift,
                              hipStream_t s);

@@ -123,6 +123,7 @@ SIGNATURES = {
     "tlr_solve_noalloc": (_I, [_P, _I, _P, _LL, _P]),
     "tlr_solve_noalloc_max_bytes": (ctypes.c_size_t, []),
     "tlr_matvec": (_I, [_P, _I, _P, _LL, _P, _LL, _P]),
+    "tlr_recompress": (_I, [_P, _I, _D, _P]),
     "tlr_pcg": (_I, [_P, _P, _P, _P, _D, _I, _IP, _DP, _P]),
     "tlr_get_info": (_I, [_P, _LLP, _IP, _IP, _IP]),
     "tlr_get_ranks": (_I, [_P, _I, _IP]),
@@ -408,6 +409,11 @@ class TLRMatrix:
         y = torch.empty_like(xc)
         _check(lib().tlr_matvec(self.h, nrhs, _ptr(xc), self.n, _ptr(y), self.n, _stream()))
         return _from_colmajor(y, x.shape)
+
+    def recompress(self, tau: float, which: int = FACTOR):
+        """SVD post-recompression of every low rank tile of the factor (or
+        input) at the absolute threshold tau (tlr_recompress)."""
+        _check(lib().tlr_recompress(self.h, which, float(tau), _stream()))
 
     # -- inspection
     def ranks(self, which: int = INPUT) -> np.ndarray:

@@ -1,0 +1,212 @@
+"""SVD post-recompression of the low rank tiles (Section 6.2) on the GPU
+against the oracle's definition: every tile of the GPU's own factor (or
+input), downloaded before the call, is truncated by a dense SVD on the host
+(oracle.tlr.recompress) and compared with what the library left.
+
+What is unique about a truncated SVD is compared directly: the kept rank
+(except where a singular value lies within a hair of tau, where either
+choice is right), the kept singular values, the error sigma_{r+1}, the
+orthonormality of U and the product U V^T.  The bookkeeping (offsets of the
+compacted panels) is compared bit for bit with the oracle's, and the solve
+with the recompressed factor against the oracle's solve with the same
+factor."""
+import numpy as np
+import pytest
+
+from oracle import bookkeeping as bk
+from oracle import dense
+from oracle import tlr as otlr
+from paper_2108_11932_amd import tlr
+from paper_2108_11932_amd import workloads as wl
+
+from gpu_util import oracle_tlr
+
+pytestmark = pytest.mark.gpu
+
+# A singular value within this relative distance of tau may fall on either
+# side (the two-pass Gram solver resolves singular values to a relative
+# error near m u; the band leaves three orders of magnitude of margin).
+BAND = 1e-9
+
+
+def _check_tiles(before, after, tau, ranks_or):
+    """Per tile: rank, spectrum, error and orthonormality against the dense
+    truncated SVD of the tile before the call."""
+    n_band = 0
+    for (i, j), u0 in before.u.items():
+        t = u0 @ before.v[i, j].T
+        s = np.linalg.svd(t, compute_uv=False)
+        u1, v1 = after.u[i, j], after.v[i, j]
+        r = u1.shape[1]
+        r_or = int(ranks_or[i, j])
+        near = np.abs(s / tau - 1.0) <= BAND if tau > 0 else np.zeros_like(s, bool)
+        if r != r_or:
+            # only values inside the band may change sides
+            lo, hi = sorted((r, r_or))
+            assert np.all(near[lo:hi]), (i, j, r, r_or, s[lo:hi] / tau)
+            n_band += 1
+        assert np.all(s[:r] > tau * (1 - BAND)), (i, j)
+        if r < len(s):
+            assert s[r] <= tau * (1 + BAND), (i, j, s[r] / tau)
+        if r == 0:
+            continue
+        np.testing.assert_allclose(u1.T @ u1, np.eye(r), atol=1e-12, err_msg=str((i, j)))
+        sv = np.linalg.norm(v1, axis=0)
+        np.testing.assert_allclose(sv, s[:r], rtol=1e-9, atol=1e-13 * s[0], err_msg=str((i, j)))
+        err = np.linalg.norm(t - u1 @ v1.T, 2)
+        tail = s[r] if r < len(s) else 0.0
+        assert abs(err - tail) <= 1e-11 * s[0] + 1e-9 * tail, (i, j, err, tail)
+    return n_band
+
+
+def _cov_factor(n, m, eps, ldl=False, pivoted=False, seed=21):
+    pts = wl.jittered_grid(n, 2, seed)
+    pts = np.ascontiguousarray(pts[wl.morton_order(pts)])
+    mat = tlr.TLRMatrix.compress_kernel(pts, tlr.KERNEL_EXP, 0.1, 1e-4, m, eps)
+    o = tlr.opts(bs=16)
+    if ldl:
+        st = mat.ldlt(eps, o)[0]
+    elif pivoted:
+        st = mat.potrf_pivoted(eps, o)[0]
+    else:
+        st = mat.potrf(eps, o)
+    return pts, mat, st
+
+
+@pytest.mark.parametrize("kind", ["chol", "ldlt", "pivoted"])
+def test_factor_recompression_matches_truncated_svd(kind):
+    n, m, eps = 4096, 256, 1e-6
+    _, mat, st = _cov_factor(n, m, eps, ldl=kind == "ldlt", pivoted=kind == "pivoted")
+    tau = st["tau"]
+    before = oracle_tlr(mat, tlr.FACTOR)
+    r0 = mat.ranks(tlr.FACTOR)
+    ref = otlr.recompress(before, tau)
+    mat.recompress(tau)
+    after = oracle_tlr(mat, tlr.FACTOR)
+    r1 = mat.ranks(tlr.FACTOR)
+    n_band = _check_tiles(before, after, tau, ref.ranks())
+    assert n_band <= 1
+    assert np.all(r1 <= r0) and r1.sum() < r0.sum()
+    # the compacted panels: offsets as the oracle's bookkeeping lays them out
+    np.testing.assert_array_equal(mat.offsets(tlr.FACTOR), bk.row_panel_offsets(r1))
+    # diagonal tiles untouched
+    for k in range(before.nb):
+        np.testing.assert_array_equal(after.diag[k], before.diag[k])
+    # the solve with the recompressed factor is the oracle's solve with it
+    import torch
+    b = np.random.default_rng(3).standard_normal((n, 2))
+    x = mat.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    d = None
+    if kind == "ldlt":
+        piv = mat.pivots()
+        d = [piv[k * m:(k + 1) * m] for k in range(before.nb)]
+    if kind == "pivoted":
+        # P A P^T = L L^T, position t holding original block perm[t] (n = nb m)
+        idx = np.concatenate([np.arange(p * m, (p + 1) * m) for p in mat.perm()])
+        want = np.zeros_like(b)
+        want[idx] = otlr.solve(after, b[idx], d)
+    else:
+        want = otlr.solve(after, b, d)
+    np.testing.assert_allclose(x, want, rtol=1e-9, atol=1e-9 * np.abs(want).max())
+    # a second pass at the same threshold keeps every rank
+    mat.recompress(tau)
+    np.testing.assert_array_equal(mat.ranks(tlr.FACTOR), r1)
+    mat.close()
+
+
+def test_input_recompression_and_matvec():
+    n, m, eps = 4096, 256, 1e-6
+    pts = wl.jittered_grid(n, 2, 5)
+    pts = np.ascontiguousarray(pts[wl.morton_order(pts)])
+    mat = tlr.TLRMatrix.compress_kernel(pts, tlr.KERNEL_EXP, 0.1, 1e-4, m, eps)
+    before = oracle_tlr(mat, tlr.INPUT)
+    r0 = mat.ranks(tlr.INPUT)
+    ref = otlr.recompress(before, eps)
+    mat.recompress(eps, tlr.INPUT)
+    after = oracle_tlr(mat, tlr.INPUT)
+    r1 = mat.ranks(tlr.INPUT)
+    assert _check_tiles(before, after, eps, ref.ranks()) <= 1
+    assert r1.sum() < r0.sum()
+    np.testing.assert_array_equal(mat.offsets(tlr.INPUT), bk.lower_offsets(r1)[0])
+    import torch
+    x = np.random.default_rng(4).standard_normal(n)
+    y = mat.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    want = otlr.matvec(after, x)
+    np.testing.assert_allclose(y, want, rtol=1e-11, atol=1e-11 * np.abs(want).max())
+    # the recompressed input still factors, with the factor's usual bound
+    st = mat.potrf(eps, tlr.opts(bs=16))
+    l = oracle_tlr(mat, tlr.FACTOR)
+    a = oracle_tlr(mat, tlr.INPUT)
+    err = otlr.factor_error_norm(a, l)
+    assert err <= 2.0 * np.sqrt(a.nb) * st["tau"]
+    mat.close()
+
+
+def _spectrum_tile(rng, m, q, decades):
+    x, _ = np.linalg.qr(rng.standard_normal((m, q)))
+    y, _ = np.linalg.qr(rng.standard_normal((m, q)))
+    s = np.logspace(0, -decades, q)
+    return (x * s) @ y.T
+
+
+def test_all_solver_classes_and_full_rank_tiles():
+    """Tiles of rank <= 32, <= 64 (LDS solvers), 100 and 128 = m (the
+    global-memory solver, a full-rank tile) with spectra spread over ten
+    decades, cut at a threshold inside each spectrum."""
+    m, nb = 128, 4
+    n = m * nb
+    rng = np.random.default_rng(17)
+    a = np.eye(n) * 4.0
+    qs = {(1, 0): 20, (2, 0): 50, (2, 1): 100, (3, 0): 128, (3, 1): 7, (3, 2): 64}
+    for (i, j), q in qs.items():
+        t = _spectrum_tile(rng, m, q, 10)
+        a[i * m:(i + 1) * m, j * m:(j + 1) * m] = t
+        a[j * m:(j + 1) * m, i * m:(i + 1) * m] = t.T
+    import torch
+    mat = tlr.TLRMatrix.compress(torch.from_numpy(a).cuda(), m, 1e-13)
+    r0 = mat.ranks(tlr.INPUT)
+    for (i, j), q in qs.items():
+        assert r0[i, j] >= min(q, m) - 2, (i, j, r0[i, j], q)
+    before = oracle_tlr(mat, tlr.INPUT)
+    tau = 3.3e-6
+    ref = otlr.recompress(before, tau)
+    mat.recompress(tau, tlr.INPUT)
+    after = oracle_tlr(mat, tlr.INPUT)
+    assert _check_tiles(before, after, tau, ref.ranks()) == 0
+    r1 = mat.ranks(tlr.INPUT)
+    for (i, j), q in qs.items():
+        s = np.logspace(0, -10, q)
+        assert r1[i, j] == int(np.sum(s > tau)), (i, j, r1[i, j])
+    # tau = 0 keeps every direction of the exact spectra (the smallest is 1e-10)
+    mat2 = tlr.TLRMatrix.compress(torch.from_numpy(a).cuda(), m, 1e-13)
+    mat2.recompress(0.0, tlr.INPUT)
+    r2 = mat2.ranks(tlr.INPUT)
+    for (i, j), q in qs.items():
+        assert min(q, m) <= r2[i, j] <= r0[i, j], (i, j, r2[i, j], r0[i, j])
+    mat.close()
+    mat2.close()
+
+
+def test_recompress_errors():
+    n, m = 512, 128
+    pts, mat, st = _cov_factor(n, m, 1e-6)
+    with pytest.raises(tlr.TLRError) as e:
+        mat.recompress(-1.0)
+    assert e.value.status == -1
+    with pytest.raises(tlr.TLRError) as e:
+        mat.recompress(float("nan"))
+    assert e.value.status == -1
+    r = mat.ranks(tlr.FACTOR)
+    mat.close()
+    # input whose tiles were set from the host: U of unknown orthonormality
+    t = otlr.compress_dense(dense.covariance_matrix(pts, dense.KERNEL_EXP, 0.1, 1e-4), m, 1e-6)
+    h = tlr.TLRMatrix.from_tlr(n, m, t.diag, t.u, t.v)
+    with pytest.raises(tlr.TLRError) as e:
+        h.recompress(1e-6, tlr.INPUT)
+    assert e.value.status == -4
+    # no factor yet
+    with pytest.raises(tlr.TLRError) as e:
+        h.recompress(1e-6, tlr.FACTOR)
+    assert e.value.status == -4
+    h.close()
+    assert r.sum() > 0
