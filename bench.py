@@ -289,6 +289,59 @@ def pcg_form(tlr, torch, wl):
     return out
 
 
+def recompress_form(mat, w, tlr, torch, o, reps: int = 2):
+    """SVD post-recompression of the headline factor (Section 6.2): the
+    factor's low rank tiles cut to their minimal ranks at the
+    factorization's own threshold.  Per repetition: factor (untimed), time
+    the solve with one right-hand side (median of 5), time tlr_recompress,
+    time the solve again.  Reports the factor's memory (diagonal tiles plus
+    U and V panels) before and after, the times, and the random-vector
+    residual of the recompressed factor against its bound."""
+    def solve_ms():
+        g = torch.Generator(device="cpu").manual_seed(5)
+        b = torch.randn(mat.n, generator=g, dtype=torch.float64).cuda()
+        mat.solve(b)
+        ts = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mat.solve(b)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(ts))
+
+    def mem(r):
+        return 8.0 * (mat.nb * mat.m * mat.m + 2 * mat.m * int(r.sum()))
+
+    runs = []
+    for _ in range(reps):
+        st = mat.potrf(w.eps, o)
+        r0 = mat.ranks(tlr.FACTOR)
+        s0 = solve_ms()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mat.recompress(st["tau"])
+        torch.cuda.synchronize()
+        t_rc = (time.perf_counter() - t0) * 1e3
+        r1 = mat.ranks(tlr.FACTOR)
+        runs.append({"recompress_ms": t_rc, "solve_ms_before": s0, "solve_ms_after": solve_ms(),
+                     "rank_sum_before": int(r0.sum()), "rank_sum_after": int(r1.sum()),
+                     "tau": st["tau"]})
+    last = runs[-1]
+    err = residual(mat, torch)
+    bound = 2.0 * math.sqrt(mat.nb) * last["tau"]
+    return {"workload": _describe(w) + ", the FP64 factor at the factorization's tau",
+            "recompress_ms": min(x["recompress_ms"] for x in runs),
+            "recompress_ms_runs": [x["recompress_ms"] for x in runs],
+            "rank_sum_before": last["rank_sum_before"], "rank_sum_after": last["rank_sum_after"],
+            "lowrank_rank_reduction": 1.0 - last["rank_sum_after"] / max(1, last["rank_sum_before"]),
+            "factor_bytes_before": mem(np.array([last["rank_sum_before"]])),
+            "factor_bytes_after": mem(np.array([last["rank_sum_after"]])),
+            "solve_ms_before": last["solve_ms_before"], "solve_ms_after": last["solve_ms_after"],
+            "residual_after": err, "residual_bound": bound,
+            "residual_within_bound": bool(err <= bound)}
+
+
 def batched_form(tlr, torch, wl, count: int, m_fixed: int):
     """The batched workload (count independent 2D problems of uneven N,
     relative eps 1e-6).  Tile sizes come from the library's autotuner
@@ -454,6 +507,10 @@ def main():
                     help="skip the pivoted / unpivoted line (3D covariance, tile 512)")
     ap.add_argument("--no-pcg", dest="pcg", action="store_false",
                     help="skip the preconditioned CG line (N=32768)")
+    ap.add_argument("--no-recompress", dest="recompress", action="store_false",
+                    help="skip the SVD post-recompression line (the headline factor)")
+    ap.add_argument("--profile-recompress", action="store_true",
+                    help="with --profile: recompress the last factor after the timed steps")
     ap.add_argument("--batched", type=int, default=96,
                     help="problems of the batched workload timed after the main line (0 = skip)")
     ap.add_argument("--form", default="fp64",
@@ -532,9 +589,19 @@ def main():
                           a.profile and a.serial)
     print("[bench] %d timed steps, %.1f ms each" % (a.steps, dt * 1e3), file=sys.stderr, flush=True)
     if a.profile:
-        print(json.dumps({"profile": w.name, "ms_per_step": dt * 1e3, "serial": a.serial,
-                          "ara_iterations": int(stats[-1]["ara_iters"]),
-                          "sample_bytes": stats[-1]["sample_bytes"]}), flush=True)
+        out = {"profile": w.name, "ms_per_step": dt * 1e3, "serial": a.serial,
+               "ara_iterations": int(stats[-1]["ara_iters"]),
+               "sample_bytes": stats[-1]["sample_bytes"]}
+        if a.profile_recompress:
+            # the last factor's SVD post-recompression, after a marker gap
+            time.sleep(0.05)
+            r0 = int(mat.ranks(tlr.FACTOR).sum())
+            t0 = time.perf_counter()
+            mat.recompress(stats[-1]["tau"])
+            torch.cuda.synchronize()
+            out.update({"recompress_ms": (time.perf_counter() - t0) * 1e3, "rank_sum_before": r0,
+                        "rank_sum_after": int(mat.ranks(tlr.FACTOR).sum())})
+        print(json.dumps(out), flush=True)
         mat.close()
         return
     dt_ev, stats_ev = (time_form(mat, w, w.eps_mode, tlr.FP64, tlr, torch, a.steps, 0, a.bs_tail, a.tail_active, True)
@@ -617,6 +684,18 @@ def main():
                      "avg_launch_us": smp_ms * 1e3 / max(1, smp_n),
                      "events_pass_ms_per_step": dt_ev * 1e3},
     }
+    if a.recompress:
+        print("[bench] SVD post-recompression of the factor", file=sys.stderr, flush=True)
+        line["recompress"] = recompress_form(
+            mat, w, tlr, torch, tlr.opts(bs=w.bs, bs_tail=a.bs_tail, tail_active=a.tail_active,
+                                        eps_mode=w.eps_mode))
+        rc = line["recompress"]
+        print("[bench] recompress: %.1f ms, ranks %d -> %d (-%.1f%%), factor %.2f -> %.2f GB, "
+              "solve %.1f -> %.1f ms, residual %.3g (bound %.3g)"
+              % (rc["recompress_ms"], rc["rank_sum_before"], rc["rank_sum_after"],
+                 100 * rc["lowrank_rank_reduction"], rc["factor_bytes_before"] / 1e9,
+                 rc["factor_bytes_after"] / 1e9, rc["solve_ms_before"], rc["solve_ms_after"],
+                 rc["residual_after"], rc["residual_bound"]), file=sys.stderr, flush=True)
     mat.close()
     if a.cfg2:
         print("[bench] 2D covariance N=32768, tile 512", file=sys.stderr, flush=True)

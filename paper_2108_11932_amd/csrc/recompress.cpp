@@ -45,7 +45,8 @@ constexpr double kPass1Abs = 1e-14;
 int eig_class(int q) {
   if (q <= kEigLdsSmall) return 0;
   if (q <= kEigLdsLarge) return 1;
-  if (q <= kEigMaxRank) return 2;
+  if (q <= kEigPacked) return 2;
+  if (q <= kEigMaxRank) return 3;
   return -1;   // kept as it is
 }
 
@@ -71,8 +72,10 @@ tlr_status recompress(Handle* h, int which, double tau) {
     return a.j < b.j;
   });
 
-  // chunks of tiles whose buffers fit the budget (at least one tile each)
-  const size_t budget = (size_t)1 << 30;
+  // chunks of tiles whose buffers fit the budget (at least one tile each):
+  // every chunk costs two solver launches as long as its slowest tile, so
+  // the budget is generous (N = 131072 with ranks near 14 fits one chunk)
+  const size_t budget = (size_t)4 << 30;
   std::vector<size_t> cuts{0};
   size_t acc = 0, chunk_max = 0;
   for (size_t t = 0; t < tiles.size(); ++t) {
@@ -124,7 +127,7 @@ tlr_status recompress(Handle* h, int which, double tau) {
       p += (size_t)m * q;
     }
     GemmBatch gram(true, false), rot(false, false), gram2(true, false);
-    std::vector<EigDesc> ed[3], ed2[3];
+    std::vector<EigDesc> ed[4], ed2[4];
     std::vector<CopyDesc> keep;   // tiles above the solver's rank limit
     for (size_t t = 0; t < nt; ++t) {
       const RTile& r = tiles[t0 + t];
@@ -142,7 +145,7 @@ tlr_status recompress(Handle* h, int which, double tau) {
       ed2[cls].push_back(EigDesc{G2[t], W[t], res + 2 * t, r.q});
     }
     auto eig = [&](std::vector<EigDesc>* sets, double abs_scale) -> tlr_status {
-      for (int cls = 0; cls < 3; ++cls) {
+      for (int cls = 0; cls < 4; ++cls) {
         if (sets[cls].empty()) continue;
         void* d = nullptr;
         TLR_TRY(h->stage.upload(h, sets[cls].data(), sizeof(EigDesc) * sets[cls].size(), &d));

@@ -65,12 +65,27 @@ struct JacShared {
 // and |g_ab| > abs_scale max_j g_jj, with the rotation of Golub and Van
 // Loan's symmetric Schur decomposition of the 2 x 2 block
 // (t = sign(theta) / (|theta| + sqrt(1 + theta^2)),
-// theta = (g_bb - g_aa) / (2 g_ab)), which zeroes g_ab.  The rounds' pairs
-// are disjoint, so the row updates of all of them and then the column
-// updates run in parallel.  The run ends after a sweep without rotations
-// or after kSweeps sweeps; the decision is the workgroup's, so every wave
+// theta = (g_bb - g_aa) / (2 g_ab)), which zeroes g_ab.  The pairs of a
+// round are disjoint, so the round's transformation J^T G J acts on the
+// 2 x 2 blocks (pair k1's rows, pair k2's columns) independently:
+// block <- R_k1^T block R_k2, one block per work item, together with the
+// column pairs of W.  The run ends after a sweep without rotations or
+// after kSweeps sweeps; the decision is the workgroup's, so every wave
 // leaves the loop together.
-template <int NT>
+// Element (i, j) of G: column-major with leading dimension lg, or (PACKED)
+// the upper triangle stored by columns, (i, j) and (j, i) at one place.
+template <bool PACKED>
+__device__ __forceinline__ size_t gidx(int i, int j, int lg) {
+  if (!PACKED) return i + (size_t)j * lg;
+  if (i > j) {
+    const int x = i;
+    i = j;
+    j = x;
+  }
+  return (size_t)j * (j + 1) / 2 + i;
+}
+
+template <int NT, bool PACKED = false>
 __device__ void jacobi(double* G, int lg, double* W, int lw, int q, double abs_scale,
                        const JacShared& sh) {
   const int tid = threadIdx.x;
@@ -81,11 +96,13 @@ __device__ void jacobi(double* G, int lg, double* W, int lw, int q, double abs_s
   }
   if (tid == 0) {
     double g = 0.0;
-    for (int j = 0; j < q; ++j) g = fmax(g, fabs(G[j + (size_t)j * lg]));
+    for (int j = 0; j < q; ++j) g = fmax(g, fabs(G[gidx<PACKED>(j, j, lg)]));
     *sh.atol = abs_scale * g;
   }
   __syncthreads();
   const double atol = *sh.atol;
+  // packed storage holds each block pair once: the blocks k1 <= k2
+  const int nblk = PACKED ? half * (half + 1) / 2 : half * half;
   for (int sweep = 0; sweep < kSweeps; ++sweep) {
     if (tid == 0) *sh.flag = 0;
     __syncthreads();
@@ -95,8 +112,8 @@ __device__ void jacobi(double* G, int lg, double* W, int lw, int q, double abs_s
         jac_pair(n, t, k, a, b);
         double c = 1.0, s = 0.0;
         if (b < q) {
-          const double gaa = G[a + (size_t)a * lg], gbb = G[b + (size_t)b * lg];
-          const double gab = G[a + (size_t)b * lg];
+          const double gaa = G[gidx<PACKED>(a, a, lg)], gbb = G[gidx<PACKED>(b, b, lg)];
+          const double gab = G[gidx<PACKED>(a, b, lg)];
           if (fabs(gab) > fmax(kJacTol * sqrt(fabs(gaa)) * sqrt(fabs(gbb)), atol)) {
             const double th = (gbb - gaa) / (2.0 * gab);
             const double at = fabs(th);
@@ -114,30 +131,62 @@ __device__ void jacobi(double* G, int lg, double* W, int lw, int q, double abs_s
         sh.pb[k] = b;
       }
       __syncthreads();
-      // rows a and b of G: G <- J^T G
-      for (int e = tid; e < half * q; e += NT) {
-        const int k = e / q, j = e - k * q;
-        const double s = sh.sn[k];
-        if (s == 0.0) continue;
-        const double c = sh.cs[k];
-        double* ra = G + sh.pa[k] + (size_t)j * lg;
-        double* rb = G + sh.pb[k] + (size_t)j * lg;
-        const double x = *ra, y = *rb;
-        *ra = c * x - s * y;
-        *rb = s * x + c * y;
+      // blocks of G (k2 fastest: consecutive items share pair k1's rows)
+      for (int e = tid; e < nblk; e += NT) {
+        int k1, k2;
+        if (PACKED) {
+          // e = k2 (k2 + 1) / 2 + k1, k1 <= k2
+          k2 = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+          while ((k2 + 1) * (k2 + 2) / 2 <= e) ++k2;
+          while (k2 * (k2 + 1) / 2 > e) --k2;
+          k1 = e - k2 * (k2 + 1) / 2;
+        } else {
+          k1 = e / half;
+          k2 = e - k1 * half;
+        }
+        const double s1 = sh.sn[k1], s2 = sh.sn[k2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const double c1 = sh.cs[k1], c2 = sh.cs[k2];
+        const int a1 = sh.pa[k1], b1 = sh.pb[k1], a2 = sh.pa[k2], b2 = sh.pb[k2];
+        // a pair holding the padding index (b = q) has s = 0 and no row b
+        const bool hb1 = b1 < q, hb2 = b2 < q;
+        if (PACKED && k1 == k2) {
+          // diagonal block of a symmetric matrix: R^T X R with X = [xaa xab; xab xbb]
+          if (!hb1) continue;
+          double* paa = G + gidx<true>(a1, a1, lg);
+          double* pab = G + gidx<true>(a1, b1, lg);
+          double* pbb = G + gidx<true>(b1, b1, lg);
+          const double xaa = *paa, xab = *pab, xbb = *pbb;
+          const double yaa = c1 * xaa - s1 * xab, yab = c1 * xab - s1 * xbb;
+          const double yba = s1 * xaa + c1 * xab, ybb = s1 * xab + c1 * xbb;
+          *paa = c1 * yaa - s1 * yab;
+          *pab = s1 * yaa + c1 * yab;
+          *pbb = s1 * yba + c1 * ybb;
+          continue;
+        }
+        double* paa = G + gidx<PACKED>(a1, a2, lg);
+        double* pab = G + gidx<PACKED>(a1, b2, lg);
+        double* pba = G + gidx<PACKED>(b1, a2, lg);
+        double* pbb = G + gidx<PACKED>(b1, b2, lg);
+        const double xaa = *paa;
+        const double xab = hb2 ? *pab : 0.0;
+        const double xba = hb1 ? *pba : 0.0;
+        const double xbb = hb1 && hb2 ? *pbb : 0.0;
+        // rows: R1^T X
+        const double yaa = c1 * xaa - s1 * xba, yab = c1 * xab - s1 * xbb;
+        const double yba = s1 * xaa + c1 * xba, ybb = s1 * xab + c1 * xbb;
+        // columns: Y R2
+        *paa = c2 * yaa - s2 * yab;
+        if (hb2) *pab = s2 * yaa + c2 * yab;
+        if (hb1) *pba = c2 * yba - s2 * ybb;
+        if (hb1 && hb2) *pbb = s2 * yba + c2 * ybb;
       }
-      __syncthreads();
-      // columns a and b of G and W: G <- G J, W <- W J
+      // column pairs of W
       for (int e = tid; e < half * q; e += NT) {
         const int k = e / q, i = e - k * q;
         const double s = sh.sn[k];
         if (s == 0.0) continue;
         const double c = sh.cs[k];
-        double* ca = G + i + (size_t)sh.pa[k] * lg;
-        double* cb = G + i + (size_t)sh.pb[k] * lg;
-        const double x = *ca, y = *cb;
-        *ca = c * x - s * y;
-        *cb = s * x + c * y;
         double* wa = W + i + (size_t)sh.pa[k] * lw;
         double* wb = W + i + (size_t)sh.pb[k] * lw;
         const double u = *wa, v = *wb;
@@ -157,15 +206,15 @@ __device__ void jacobi(double* G, int lg, double* W, int lw, int q, double abs_s
 // = r, the number of leading eigenvalues with sqrt(max(lambda, 0)) > tau,
 // res[1] = their sum (the squared Frobenius norm of the kept part).  `out`
 // may be G's own storage: G is only read before the barrier.
-template <int NT>
+template <int NT, bool PACKED = false>
 __device__ void finish(const double* G, int lg, const double* W, int lw, int q, double tau,
                        double* out, double* res, double* lam, int* pos) {
   const int tid = threadIdx.x;
   for (int j = tid; j < q; j += NT) {
-    const double lj = G[j + (size_t)j * lg];
+    const double lj = G[gidx<PACKED>(j, j, lg)];
     int p = 0;
     for (int i = 0; i < q; ++i) {
-      const double li = G[i + (size_t)i * lg];
+      const double li = G[gidx<PACKED>(i, i, lg)];
       p += (li > lj) || (li == lj && i < j);
     }
     pos[j] = p;
@@ -212,9 +261,35 @@ __global__ __launch_bounds__(NT) void k_sym_eig_lds(const EigDesc* __restrict__ 
   finish<NT>(sG, LG, sW, q, q, tau, d.G, d.res, lam, pos);
 }
 
+// Tiles of rank q <= QMAX: G packed (upper triangle) in LDS, W in the
+// descriptor's workspace in global memory (column pairs: coalesced).
+template <int QMAX, int NT>
+__global__ __launch_bounds__(NT) void k_sym_eig_packed(const EigDesc* __restrict__ descs,
+                                                      double tau, double abs_scale) {
+  __shared__ double sG[QMAX * (QMAX + 1) / 2];
+  __shared__ double cs[QMAX / 2], sn[QMAX / 2], lam[QMAX];
+  __shared__ int pa[QMAX / 2], pb[QMAX / 2], pos[QMAX], flag;
+  __shared__ double atol;
+  const EigDesc d = descs[blockIdx.x];
+  const int q = d.q;
+  if (q <= 0 || q > QMAX) return;
+  const int np = q * (q + 1) / 2;
+  for (int e = threadIdx.x; e < np; e += NT) {
+    int j = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while ((j + 1) * (j + 2) / 2 <= e) ++j;
+    while (j * (j + 1) / 2 > e) --j;
+    const int i = e - j * (j + 1) / 2;
+    sG[e] = d.G[i + (size_t)j * q];
+  }
+  __syncthreads();
+  jacobi<NT, true>(sG, 0, d.W, q, q, abs_scale, JacShared{cs, sn, pa, pb, &flag, &atol});
+  finish<NT, true>(sG, 0, d.W, q, q, tau, d.G, d.res, lam, pos);
+}
+
 // Tiles of rank up to kEigMaxRank: G in place and W in the descriptor's
-// workspace, both q x q in global memory (L2-resident for the ranks met).
-__global__ __launch_bounds__(256) void k_sym_eig_glb(const EigDesc* __restrict__ descs, double tau,
+// workspace, both q x q in global memory (L2-resident for the ranks met),
+// 1024 threads to keep many accesses in flight.
+__global__ __launch_bounds__(1024) void k_sym_eig_glb(const EigDesc* __restrict__ descs, double tau,
                                                      double abs_scale) {
   __shared__ double cs[kEigMaxRank / 2], sn[kEigMaxRank / 2], lam[kEigMaxRank];
   __shared__ int pa[kEigMaxRank / 2], pb[kEigMaxRank / 2], pos[kEigMaxRank], flag;
@@ -222,8 +297,8 @@ __global__ __launch_bounds__(256) void k_sym_eig_glb(const EigDesc* __restrict__
   const EigDesc d = descs[blockIdx.x];
   const int q = d.q;
   if (q <= 0 || q > kEigMaxRank) return;
-  jacobi<256>(d.G, q, d.W, q, q, abs_scale, JacShared{cs, sn, pa, pb, &flag, &atol});
-  finish<256>(d.G, q, d.W, q, q, tau, d.G, d.res, lam, pos);
+  jacobi<1024>(d.G, q, d.W, q, q, abs_scale, JacShared{cs, sn, pa, pb, &flag, &atol});
+  finish<1024>(d.G, q, d.W, q, q, tau, d.G, d.res, lam, pos);
 }
 
 }  // namespace
@@ -237,11 +312,15 @@ hipError_t launch_sym_eig(const EigDesc* d, int n, int cls, double tau, double a
                          abs_scale);
       break;
     case 1:
-      hipLaunchKernelGGL((k_sym_eig_lds<kEigLdsLarge, 256>), dim3(n), dim3(256), 0, s, d, tau,
+      hipLaunchKernelGGL((k_sym_eig_lds<kEigLdsLarge, 512>), dim3(n), dim3(512), 0, s, d, tau,
                          abs_scale);
       break;
     case 2:
-      hipLaunchKernelGGL(k_sym_eig_glb, dim3(n), dim3(256), 0, s, d, tau, abs_scale);
+      hipLaunchKernelGGL((k_sym_eig_packed<kEigPacked, 1024>), dim3(n), dim3(1024), 0, s, d, tau,
+                         abs_scale);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_sym_eig_glb, dim3(n), dim3(1024), 0, s, d, tau, abs_scale);
       break;
     default:
       return hipErrorInvalidValue;

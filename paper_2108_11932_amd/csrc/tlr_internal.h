@@ -320,11 +320,12 @@ hipError_t launch_copy_batched(const CopyDesc* d, int n, int max_cols, hipStream
 // matrices V^T V of low rank tiles.  G (q x q, ld q) is overwritten with the
 // eigenvectors in descending order of the eigenvalues; res[0] receives the
 // number r of eigenvalues with sqrt(lambda) > tau, res[1] their sum.  W is a
-// q x q workspace for class 2.  Classes: 0 for q <= kEigLdsSmall, 1 for
-// q <= kEigLdsLarge (LDS-resident), 2 for q <= kEigMaxRank (global memory).
+// q x q workspace for classes 2 and 3.  Classes: 0 for q <= kEigLdsSmall,
+// 1 for q <= kEigLdsLarge (G and W in LDS), 2 for q <= kEigPacked (G packed
+// in LDS, W in global memory), 3 for q <= kEigMaxRank (global memory).
 // abs_scale > 0 adds the absolute rotation threshold abs_scale max_j g_jj
 // to the relative one (the first of the two passes).
-constexpr int kEigLdsSmall = 32, kEigLdsLarge = 64, kEigMaxRank = 2048;
+constexpr int kEigLdsSmall = 32, kEigLdsLarge = 96, kEigPacked = 180, kEigMaxRank = 2048;
 struct EigDesc {
   double* G;
   double* W;

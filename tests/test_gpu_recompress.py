@@ -149,15 +149,20 @@ def _spectrum_tile(rng, m, q, decades):
     return (x * s) @ y.T
 
 
-def test_all_solver_classes_and_full_rank_tiles():
-    """Tiles of rank <= 32, <= 64 (LDS solvers), 100 and 128 = m (the
-    global-memory solver, a full-rank tile) with spectra spread over ten
-    decades, cut at a threshold inside each spectrum."""
-    m, nb = 128, 4
+@pytest.mark.parametrize("m,qs", [
+    # ranks <= 32 and <= 96 (G and W in LDS), 100 and 128 = m (G packed in
+    # LDS; a full-rank tile)
+    (128, {(1, 0): 20, (2, 0): 50, (2, 1): 100, (3, 0): 128, (3, 1): 7, (3, 2): 96}),
+    # ranks above 180 (the global-memory solver; a full-rank tile) and 150
+    (256, {(1, 0): 200, (2, 0): 150, (2, 1): 256}),
+])
+def test_all_solver_classes_and_full_rank_tiles(m, qs):
+    """Tiles of every solver class with spectra spread over ten decades, cut
+    at a threshold inside each spectrum."""
+    nb = max(i for i, _ in qs) + 1
     n = m * nb
     rng = np.random.default_rng(17)
     a = np.eye(n) * 4.0
-    qs = {(1, 0): 20, (2, 0): 50, (2, 1): 100, (3, 0): 128, (3, 1): 7, (3, 2): 64}
     for (i, j), q in qs.items():
         t = _spectrum_tile(rng, m, q, 10)
         a[i * m:(i + 1) * m, j * m:(j + 1) * m] = t
