@@ -103,6 +103,23 @@ def cholesky_modified(a: np.ndarray, delta: float):
     return ell, f
 
 
+def schur_compensation(d: np.ndarray, tau: float) -> np.ndarray:
+    """Diagonal Schur compensation of an accumulated update (Section 5.1.1).
+
+    d is the symmetric positive semidefinite update D_k = sum_j L_kj L_kj^T
+    of a diagonal tile.  D_k compressed to the threshold tau is its
+    truncated eigen-decomposition Dbar = sum_{lambda_j > tau} lambda_j v_j
+    v_j^T (the optimal 2-norm approximation, error max dropped lambda <=
+    tau); the difference D_k - Dbar (positive semidefinite) is added to the
+    diagonal as its absolute row sums.  Returns the vector c with
+    c_i = sum_j |(D_k - Dbar)_ij|; the compensated tile is
+    A_kk - D_k + diag(c)."""
+    lam, v = np.linalg.eigh(np.asarray(d, dtype=np.float64))
+    drop = lam <= tau
+    e = (v[:, drop] * lam[drop]) @ v[:, drop].T
+    return np.abs(e).sum(axis=1)
+
+
 def ldlt_unpivoted(a: np.ndarray, breakdown: float = 64.0):
     """Unpivoted scalar LDL^T: a = L diag(d) L^T with L unit lower triangular.
 

@@ -208,7 +208,7 @@ def schur_tile(a: TLR, l: TLR, i: int, k: int, d: Optional[list] = None) -> np.n
 
 
 def tlr_cholesky(a: TLR, tau: float, shift: float = 0.0, record: Optional[dict] = None,
-                 modified: bool = False) -> TLR:
+                 modified: bool = False, schur_comp: bool = False) -> TLR:
     """Left-looking TLR Cholesky with exact recompression (oracle O4).
 
     Column k (Algorithm "Left Looking TLR Cholesky"):
@@ -223,7 +223,12 @@ def tlr_cholesky(a: TLR, tau: float, shift: float = 0.0, record: Optional[dict] 
     2 is the modified Cholesky of Section 5.1.2 (dense.cholesky_modified with
     delta = tau): a tile that lost definiteness is factored with its
     non-positive pivots raised to tau; record["modified"] (when record is
-    given) receives the number of raised pivots.
+    given) receives the number of raised pivots.  With `schur_comp`, step 1
+    adds the Schur compensation of Section 5.1.1: the accumulated update
+    D_k = sum_j L_kj L_kj^T is compressed to tau and the absolute row sums of
+    what the compression drops go to the diagonal,
+    A_kk - D_k + diag(dense.schur_compensation(D_k, tau)); record["comp"][k]
+    receives that vector.
     `record`, when given, receives per-tile truncation errors sigma_{rho+1}.
     """
     l = TLR(a.n, a.m)
@@ -232,9 +237,16 @@ def tlr_cholesky(a: TLR, tau: float, shift: float = 0.0, record: Optional[dict] 
     for k in range(a.nb):
         dk = a.diag[k].copy()
         dk[np.arange(nreal[k]), np.arange(nreal[k])] += shift
+        upd = np.zeros((m, m))
         for j in range(k):
             g = l.v[k, j].T @ l.v[k, j]
-            dk -= l.u[k, j] @ (g @ l.u[k, j].T)
+            upd += l.u[k, j] @ (g @ l.u[k, j].T)
+        dk -= upd
+        if schur_comp and k > 0:
+            c = dense.schur_compensation(upd, tau)
+            dk[np.arange(m), np.arange(m)] += c
+            if record is not None:
+                record.setdefault("comp", {})[k] = c
         if modified:
             l.diag[k], f = dense.cholesky_modified(dk, tau)
             if record is not None:

@@ -553,3 +553,56 @@ def test_recompress_of_a_padded_rank_surplus():
     assert r.rank(1, 0) == int(np.sum(dense_s > tau)) == 4
     err = np.linalg.norm(a.tile(1, 0) - r.tile(1, 0), 2)
     assert abs(err - dense_s[4]) <= 1e-12 * dense_s[0]
+
+
+# ---------------------------------------------------------------- Schur compensation
+
+def test_schur_compensation_hand_computed():
+    """D = [[2, 1], [1, 2]] has eigenvalues 3 and 1 (vectors (1, 1)/sqrt2 and
+    (1, -1)/sqrt2).  At tau = 2 the compression keeps 3: D - Dbar =
+    [[.5, -.5], [-.5, .5]], absolute row sums (1, 1).  At tau = 0.5 nothing
+    is dropped; at tau = 3.5 everything is, and c is the row sums of |D|."""
+    d = np.array([[2.0, 1.0], [1.0, 2.0]])
+    np.testing.assert_allclose(dense.schur_compensation(d, 2.0), [1.0, 1.0], atol=1e-15)
+    np.testing.assert_allclose(dense.schur_compensation(d, 0.5), [0.0, 0.0], atol=1e-15)
+    np.testing.assert_allclose(dense.schur_compensation(d, 3.5), [3.0, 3.0], atol=1e-14)
+    # a diagonal update: the dropped entries stay on the diagonal
+    np.testing.assert_allclose(dense.schur_compensation(np.diag([5.0, 1e-3, 2e-3]), 1e-2),
+                               [0.0, 1e-3, 2e-3], atol=1e-18)
+
+
+def test_schur_compensation_dominates_the_dropped_part():
+    """diag(c) - (D - Dbar) is diagonally dominant, so the compensated tile
+    is at least A - Dbar in the Loewner order, and c <= sqrt(m) tau per row
+    (the row of a PSD matrix of 2-norm <= tau)."""
+    rng = np.random.default_rng(2)
+    m, tau = 40, 1e-3
+    x = rng.standard_normal((m, m))
+    q, _ = np.linalg.qr(x)
+    lam = np.concatenate([np.logspace(1, -1, 10), np.logspace(-3.5, -8, 30)])
+    d = (q * lam) @ q.T
+    c = dense.schur_compensation(d, tau)
+    keep = lam > tau
+    dbar = (q[:, keep] * lam[keep]) @ q[:, keep].T
+    e = d - dbar
+    assert np.all(c >= 0) and np.all(c <= np.sqrt(m) * tau)
+    assert np.linalg.eigvalsh(np.diag(c) - e).min() >= -1e-14
+    np.testing.assert_allclose(c, np.abs(e).sum(axis=1), atol=1e-15)
+
+
+def test_tlr_cholesky_schur_compensation_is_the_paper_update():
+    """The column step with compensation factors A_kk - D_k + diag(c): the
+    factor's diagonal tiles satisfy L_kk L_kk^T = that tile, with D_k from
+    the factor's own tiles; the first column has no update and matches the
+    plain factor; every c is within the sqrt(m) tau row bound."""
+    _, a = _cov(512, 128)
+    t = tlr.compress_dense(a, 128, 1e-6)
+    rec = {}
+    l = tlr.tlr_cholesky(t, 1e-4, schur_comp=True, record=rec)
+    for k in range(1, t.nb):
+        upd = sum(l.u[k, j] @ l.v[k, j].T @ l.v[k, j] @ l.u[k, j].T for j in range(k))
+        want = t.diag[k] - upd + np.diag(dense.schur_compensation(upd, 1e-4))
+        np.testing.assert_allclose(l.diag[k] @ l.diag[k].T, want, atol=1e-12)
+        assert 0 < rec["comp"][k].max() <= np.sqrt(128) * 1e-4
+    plain = tlr.tlr_cholesky(t, 1e-4)
+    np.testing.assert_array_equal(l.diag[0], plain.diag[0])
