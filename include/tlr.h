@@ -166,9 +166,19 @@ typedef struct {
  * instead of launching it kernel by kernel; the result is the same bit for
  * bit.  Off by default: that stream is not on the critical path, and the
  * replay measured 1.6 % slower on the 2D covariance workload (N = 131072,
- * tile 1024). */
+ * tile 1024).
+ * TLR_FLAG_SCHUR_COMP (unpivoted Cholesky, tile size m <= 2048; Section
+ * 5.1.1, "Schur Compensation"): the accumulated update D_k of each diagonal
+ * tile is compressed to tau by its truncated eigen-decomposition (the
+ * eigenvalues above tau kept), and the absolute row sums of the dropped
+ * part D_k - Dbar_k (positive semidefinite, 2-norm <= tau) are added to the
+ * diagonal: the tile factored is A_kk - D_k + diag(rowsum |D_k - Dbar_k|).
+ * Costs one symmetric m x m eigen-decomposition (batched Jacobi, one
+ * workgroup) and two m x m x m products per column on the diagonal-tile
+ * stream.  Rejected with TLR_ERR_ARG by tlr_ldlt, tlr_potrf_pivoted and the
+ * batched factorizations. */
 enum { TLR_FLAG_KERNEL_TIMING = 1, TLR_FLAG_PHASE_TIMING = 2, TLR_FLAG_SERIAL_SAMPLING = 4,
-       TLR_FLAG_MODIFIED_CHOL = 8, TLR_FLAG_DIAG_GRAPH = 16 };
+       TLR_FLAG_MODIFIED_CHOL = 8, TLR_FLAG_DIAG_GRAPH = 16, TLR_FLAG_SCHUR_COMP = 32 };
 
 /* Phases of a column step (indices of tlr_stats.t_phase).  Phases 0-6 run on
  * the caller's stream one after another, so their times add up to that

@@ -256,6 +256,10 @@ static tlr_status factor_entry(tlr_matrix_t A, double eps, const tlr_opts* opts,
   tlr_opts o;
   TLR_TRY(check_opts(opts, &o));
   TLR_ARG(!piv || o.precision == TLR_FP64, "the pivoted Cholesky samples in FP64 (opts.precision)");
+  TLR_ARG(!(o.flags & TLR_FLAG_SCHUR_COMP) || (!ldl && !piv),
+          "Schur compensation (TLR_FLAG_SCHUR_COMP) applies to the unpivoted Cholesky");
+  TLR_ARG(!(o.flags & TLR_FLAG_SCHUR_COMP) || eig_class(A->m) >= 0,
+          "Schur compensation needs tile size m <= %d", kEigMaxRank);
   if (stats) std::memset(stats, 0, sizeof *stats);
   tlr_status st = factorize(A, eps, o, stats, ldl, piv);
   // Section 5.1: a shift s <= eps of the diagonal keeps the perturbation
@@ -320,6 +324,8 @@ static tlr_status batched_entry(int count, tlr_matrix_t* A, bool ldl, const doub
   tlr_opts o;
   TLR_TRY(check_opts(opts, &o));
   TLR_ARG(!o.auto_shift, "opts.auto_shift is not supported by the batched factorizations");
+  TLR_ARG(!(o.flags & TLR_FLAG_SCHUR_COMP),
+          "Schur compensation is not supported by the batched factorizations");
   if (stats) std::memset(stats, 0, sizeof(tlr_stats) * count);
   for (int i = 0; i < count; ++i) A[i]->stream = A[i]->mem.stream = (hipStream_t)stream;
   tlr_status st = factorize_batch(A, count, eps, o, stats, ldl);

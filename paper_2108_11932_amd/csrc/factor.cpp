@@ -146,6 +146,9 @@ struct Prob {
   // graph (else launched kernel by kernel)
   DiagGraph* dg = nullptr;
   double mod_delta = 0.0;   // > 0: modified Cholesky of the diagonal tiles (Section 5.1.2)
+  bool schur = false;       // Schur compensation of the diagonal updates (Section 5.1.1)
+  double* sch = nullptr;    // its buffers (Work::schur), device descriptor at sch_desc
+  EigDesc* sch_desc = nullptr;
   double flops = 0.0, flops_paper = 0.0, bytes_alg = 0.0, samp_bytes = 0.0, samp_flops = 0.0;
   long long ara_iters = 0, tile_iters = 0, fp32_tile_iters = 0, bf16_tile_iters = 0;
   double t_issue = 0.0, t_wait = 0.0;
@@ -212,6 +215,21 @@ tlr_status prob_init(Prob& p, double eps, const tlr_opts& o, bool ldl) {
   // modified Cholesky: a diagonal tile that lost definiteness has its
   // non-positive pivots raised to the threshold
   p.mod_delta = (!ldl && (o.flags & TLR_FLAG_MODIFIED_CHOL)) ? p.tau : 0.0;
+  // Schur compensation: buffers of one column, reused column after column on
+  // the diagonal-tile stream, and the eigensolver's descriptor (fixed)
+  p.schur = !ldl && !p.piv && (o.flags & TLR_FLAG_SCHUR_COMP);
+  if (p.schur) {
+    Work& w = h->ws;
+    const size_t mm = (size_t)m * m;
+    const size_t doubles = 4 * mm + m + 2;
+    const size_t bytes = sizeof(double) * doubles + sizeof(EigDesc) + 64;
+    TLR_TRY(w.schur.ensure(h->mem, bytes));
+    p.sch = w.schur.as<double>();
+    const size_t doff = ((sizeof(double) * doubles + 63) / 64) * 64;
+    p.sch_desc = reinterpret_cast<EigDesc*>(reinterpret_cast<char*>(w.schur.p) + doff);
+    EigDesc ed{p.sch, p.sch + mm, p.sch + 4 * mm + m, m, p.sch + 4 * mm};
+    TLR_HIP(hipMemcpy(p.sch_desc, &ed, sizeof ed, hipMemcpyHostToDevice));
+  }
   p.dg = nullptr;
   if (o.flags & TLR_FLAG_DIAG_GRAPH)
     TLR_TRY(diag_graph(h, m, ldl ? 2 : (p.mod_delta > 0.0 ? 1 : 0), &p.dg));
@@ -501,6 +519,31 @@ tlr_status col_diag(Prob& p, int k, bool ldl) {
       up.add(m, m, Rk, Wd, m, h->UL[k], m, Tk, m, -1.0, 1.0, GEMM_LOWER_C);
       dplan.gemm(up);
       p.flops += wb.flops + up.flops / 2;
+      if (p.schur) {
+        // Schur compensation (Section 5.1.1): the update D_k = W U_k*^T in
+        // full, D_k = V diag(lambda) V^T, the part the compression to tau
+        // drops, E = V diag(lambda_j <= tau ? lambda_j : 0) V^T, and the
+        // absolute row sums of E onto the diagonal of the updated tile
+        const size_t mm = (size_t)m * m;
+        double* D = p.sch;            // D_k, then its eigenvectors
+        double* Vs = p.sch + 2 * mm;
+        double* E = p.sch + 3 * mm;
+        const double* lam = p.sch + 4 * mm;
+        const EigDesc* ed = p.sch_desc;
+        const int cls = eig_class(m);
+        const double tau = p.tau;
+        GemmBatch db(false, true);
+        db.add(m, m, Rk, Wd, m, h->UL[k], m, D, m, 1.0, 0.0);
+        dplan.gemm(db);
+        // the solver compares sqrt(lambda) with its threshold
+        dplan.launch([=]() { return launch_sym_eig(ed, 1, cls, std::sqrt(tau), 1e-15, ds); });
+        dplan.launch([=]() { return launch_schur_scale(D, lam, m, tau, Vs, ds); });
+        GemmBatch eb(false, true);
+        eb.add(m, m, m, Vs, m, D, m, E, m, 1.0, 0.0);
+        dplan.gemm(eb);
+        dplan.launch([=]() { return launch_schur_diag(E, m, Tk, m, nr, ds); });
+        p.flops += db.flops + eb.flops;
+      }
     }
     if (DiagGraph* g = p.dg) {
       // the updated tile went to the graph's buffer (above); one replay,

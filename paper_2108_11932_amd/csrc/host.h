@@ -164,12 +164,16 @@ struct Work {
       compact, Bt, fro, tnpart, tnpart2, splitk, G2, Gk, Sg, Sw, Snorm;
   // buffers of the diagonal-tile stream (never touched by the main stream)
   DevBuf Wd, dW, dtol, sideblob, sideblob2, Wn;
+  // Schur compensation: D_k (then its eigenvectors), the solver's
+  // workspace, V diag(f), E (m x m each), the eigenvalues, two result
+  // words and the solver's descriptor
+  DevBuf schur;
   int slots = 0;   // slot capacity of the per-tile buffers
   void release_all(Mem& mem) {
     DevBuf* bufs[] = {&G, &W, &omega, &P, &Z, &T, &Ta, &H, &Ball, &C, &Wa, &Y, &Q, &part,
                       &ints, &orth, &dscale, &tol, &compact, &Bt, &fro, &tnpart, &tnpart2,
                       &splitk, &G2, &Sg, &Sw, &Snorm,
-                      &Gk, &Wd, &dW, &dtol, &sideblob, &sideblob2, &Wn};
+                      &Gk, &Wd, &dW, &dtol, &sideblob, &sideblob2, &Wn, &schur};
     for (DevBuf* b : bufs) b->release(mem);
   }
 };

@@ -42,14 +42,6 @@ size_t tile_bytes(int m, int q) {
 // diagonal entry: the Gram matrix's own rounding level.
 constexpr double kPass1Abs = 1e-14;
 
-int eig_class(int q) {
-  if (q <= kEigLdsSmall) return 0;
-  if (q <= kEigLdsLarge) return 1;
-  if (q <= kEigPacked) return 2;
-  if (q <= kEigMaxRank) return 3;
-  return -1;   // kept as it is
-}
-
 }  // namespace
 
 tlr_status recompress(Handle* h, int which, double tau) {

@@ -208,7 +208,7 @@ __device__ void jacobi(double* G, int lg, double* W, int lw, int q, double abs_s
 // may be G's own storage: G is only read before the barrier.
 template <int NT, bool PACKED = false>
 __device__ void finish(const double* G, int lg, const double* W, int lw, int q, double tau,
-                       double* out, double* res, double* lam, int* pos) {
+                       double* out, double* res, double* lam, int* pos, double* lam_out) {
   const int tid = threadIdx.x;
   for (int j = tid; j < q; j += NT) {
     const double lj = G[gidx<PACKED>(j, j, lg)];
@@ -225,6 +225,8 @@ __device__ void finish(const double* G, int lg, const double* W, int lw, int q, 
     const int i = e % q, j = e / q;
     out[i + (size_t)pos[j] * q] = W[i + (size_t)j * lw];
   }
+  if (lam_out)
+    for (int j = tid; j < q; j += NT) lam_out[j] = lam[j];
   if (tid == 0) {
     int r = 0;
     double sum = 0.0;
@@ -258,7 +260,7 @@ __global__ __launch_bounds__(NT) void k_sym_eig_lds(const EigDesc* __restrict__ 
   }
   __syncthreads();
   jacobi<NT>(sG, LG, sW, q, q, abs_scale, JacShared{cs, sn, pa, pb, &flag, &atol});
-  finish<NT>(sG, LG, sW, q, q, tau, d.G, d.res, lam, pos);
+  finish<NT>(sG, LG, sW, q, q, tau, d.G, d.res, lam, pos, d.lam);
 }
 
 // Tiles of rank q <= QMAX: G packed (upper triangle) in LDS, W in the
@@ -283,7 +285,7 @@ __global__ __launch_bounds__(NT) void k_sym_eig_packed(const EigDesc* __restrict
   }
   __syncthreads();
   jacobi<NT, true>(sG, 0, d.W, q, q, abs_scale, JacShared{cs, sn, pa, pb, &flag, &atol});
-  finish<NT, true>(sG, 0, d.W, q, q, tau, d.G, d.res, lam, pos);
+  finish<NT, true>(sG, 0, d.W, q, q, tau, d.G, d.res, lam, pos, d.lam);
 }
 
 // Tiles of rank up to kEigMaxRank: G in place and W in the descriptor's
@@ -298,10 +300,49 @@ __global__ __launch_bounds__(1024) void k_sym_eig_glb(const EigDesc* __restrict_
   const int q = d.q;
   if (q <= 0 || q > kEigMaxRank) return;
   jacobi<1024>(d.G, q, d.W, q, q, abs_scale, JacShared{cs, sn, pa, pb, &flag, &atol});
-  finish<1024>(d.G, q, d.W, q, q, tau, d.G, d.res, lam, pos);
+  finish<1024>(d.G, q, d.W, q, q, tau, d.G, d.res, lam, pos, d.lam);
+}
+
+__global__ __launch_bounds__(256) void k_schur_scale(const double* __restrict__ V,
+                                                    const double* __restrict__ lam, int m,
+                                                    double tau, double* __restrict__ Vs) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (size_t)m * m) return;
+  const double l = lam[e / m];
+  Vs[e] = l <= tau ? V[e] * l : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_schur_diag(const double* __restrict__ E, int m,
+                                                   double* __restrict__ T, int ldt, int nreal) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) acc += fabs(E[i + (size_t)j * m]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && j < nreal) T[j + (size_t)j * ldt] += red[0];
 }
 
 }  // namespace
+
+hipError_t launch_schur_scale(const double* V, const double* lam, int m, double tau, double* Vs,
+                              hipStream_t s) {
+  const size_t n = (size_t)m * m;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_schur_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, V, lam, m,
+                     tau, Vs);
+  return hipGetLastError();
+}
+
+hipError_t launch_schur_diag(const double* E, int m, double* T, int ldt, int nreal, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_schur_diag, dim3(m), dim3(256), 0, s, E, m, T, ldt, nreal);
+  return hipGetLastError();
+}
 
 hipError_t launch_sym_eig(const EigDesc* d, int n, int cls, double tau, double abs_scale,
                           hipStream_t s) {

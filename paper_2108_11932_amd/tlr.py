@@ -26,7 +26,7 @@ TLR_ERR_ZERO_PIVOT = 2
 EPS_ABS, EPS_REL = 0, 1
 FP64, MIXED_FP32, MIXED_BF16, MIXED_AUTO = 0, 1, 2, 3
 FLAG_KERNEL_TIMING, FLAG_PHASE_TIMING, FLAG_SERIAL_SAMPLING, FLAG_MODIFIED_CHOL = 1, 2, 4, 8
-FLAG_DIAG_GRAPH = 16
+FLAG_DIAG_GRAPH, FLAG_SCHUR_COMP = 16, 32
 PHASES = ("gblocks", "sample", "orth", "batch", "project", "trsm", "append", "diag")
 KERNEL_EXP, KERNEL_MATERN15 = 0, 1
 INPUT, FACTOR = 0, 1
