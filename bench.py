@@ -342,6 +342,32 @@ def recompress_form(mat, w, tlr, torch, o, reps: int = 2):
             "residual_within_bound": bool(err <= bound)}
 
 
+def schur_form(tlr, torch, wl):
+    """Schur compensation (Section 5.1.1) on the N=32768 tile-512 2D
+    covariance: the factorization at eps 1e-6 absolute with and without
+    TLR_FLAG_SCHUR_COMP (time, residual against the unshifted input), and
+    at a relative 1e-2 without a shift, where the plain factorization loses
+    definiteness: the first failing row with and without the compensation."""
+    w = wl.standard("cov2d_32k")
+    mat = tlr.TLRMatrix.compress_kernel(w.points, w.kernel, w.ell, w.diag_add, w.m, w.eps,
+                                        tlr.opts(bs=w.bs))
+    out = {"workload": _describe(w)}
+    for name, fl in (("plain", 0), ("schur", tlr.FLAG_SCHUR_COMP)):
+        o = tlr.opts(bs=w.bs, flags=fl)
+        mat.potrf(w.eps, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = mat.potrf(w.eps, o)
+        torch.cuda.synchronize()
+        out[name] = {"ms": (time.perf_counter() - t0) * 1e3, "residual": residual(mat, torch),
+                     "bound": 2.0 * math.sqrt(mat.nb) * st["tau"]}
+        s_rel, st_rel = mat.potrf_status(1e-2, tlr.opts(bs=w.bs, eps_mode=tlr.EPS_REL, flags=fl))
+        out[name]["rel_1e-2_status"] = int(s_rel)
+        out[name]["rel_1e-2_failing_row"] = int(st_rel["info"])
+    mat.close()
+    return out
+
+
 def batched_form(tlr, torch, wl, count: int, m_fixed: int):
     """The batched workload (count independent 2D problems of uneven N,
     relative eps 1e-6).  Tile sizes come from the library's autotuner
@@ -509,6 +535,8 @@ def main():
                     help="skip the preconditioned CG line (N=32768)")
     ap.add_argument("--no-recompress", dest="recompress", action="store_false",
                     help="skip the SVD post-recompression line (the headline factor)")
+    ap.add_argument("--no-schur", dest="schur", action="store_false",
+                    help="skip the Schur compensation line (N=32768)")
     ap.add_argument("--profile-recompress", action="store_true",
                     help="with --profile: recompress the last factor after the timed steps")
     ap.add_argument("--batched", type=int, default=96,
@@ -727,6 +755,14 @@ def main():
             if isinstance(v, dict):
                 print("[bench] pcg %s: %d iterations, %.1f ms" % (k, v["iterations"], v["pcg_ms"]),
                       file=sys.stderr, flush=True)
+    if a.schur:
+        print("[bench] Schur compensation (N=32768, tile 512)", file=sys.stderr, flush=True)
+        line["schur"] = schur_form(tlr, torch, wl)
+        for k in ("plain", "schur"):
+            v = line["schur"][k]
+            print("[bench] schur %s: %.1f ms, residual %.3g (bound %.3g); relative 1e-2: status %d, "
+                  "row %d" % (k, v["ms"], v["residual"], v["bound"], v["rel_1e-2_status"],
+                              v["rel_1e-2_failing_row"]), file=sys.stderr, flush=True)
     if a.batched > 0:
         print("[bench] batched workload: %d problems" % a.batched, file=sys.stderr, flush=True)
         line["batched"] = batched_form(tlr, torch, wl, a.batched, 512)

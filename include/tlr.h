@@ -167,15 +167,15 @@ typedef struct {
  * bit.  Off by default: that stream is not on the critical path, and the
  * replay measured 1.6 % slower on the 2D covariance workload (N = 131072,
  * tile 1024).
- * TLR_FLAG_SCHUR_COMP (unpivoted Cholesky, tile size m <= 2048; Section
+ * TLR_FLAG_SCHUR_COMP (unpivoted Cholesky; Section
  * 5.1.1, "Schur Compensation"): the accumulated update D_k of each diagonal
  * tile is compressed to tau by its truncated eigen-decomposition (the
  * eigenvalues above tau kept), and the absolute row sums of the dropped
  * part D_k - Dbar_k (positive semidefinite, 2-norm <= tau) are added to the
  * diagonal: the tile factored is A_kk - D_k + diag(rowsum |D_k - Dbar_k|).
- * Costs one symmetric m x m eigen-decomposition (batched Jacobi, one
- * workgroup) and two m x m x m products per column on the diagonal-tile
- * stream.  Rejected with TLR_ERR_ARG by tlr_ldlt, tlr_potrf_pivoted and the
+ * The dropped part is formed as D_k P with P = (I - sign(D_k - tau I)) / 2,
+ * the sign function by 100 Newton-Schulz steps (two m x m x m products
+ * each, on the matrix cores) per column on the diagonal-tile stream.  Rejected with TLR_ERR_ARG by tlr_ldlt, tlr_potrf_pivoted and the
  * batched factorizations. */
 enum { TLR_FLAG_KERNEL_TIMING = 1, TLR_FLAG_PHASE_TIMING = 2, TLR_FLAG_SERIAL_SAMPLING = 4,
        TLR_FLAG_MODIFIED_CHOL = 8, TLR_FLAG_DIAG_GRAPH = 16, TLR_FLAG_SCHUR_COMP = 32 };

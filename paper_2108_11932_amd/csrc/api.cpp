@@ -258,8 +258,7 @@ static tlr_status factor_entry(tlr_matrix_t A, double eps, const tlr_opts* opts,
   TLR_ARG(!piv || o.precision == TLR_FP64, "the pivoted Cholesky samples in FP64 (opts.precision)");
   TLR_ARG(!(o.flags & TLR_FLAG_SCHUR_COMP) || (!ldl && !piv),
           "Schur compensation (TLR_FLAG_SCHUR_COMP) applies to the unpivoted Cholesky");
-  TLR_ARG(!(o.flags & TLR_FLAG_SCHUR_COMP) || eig_class(A->m) >= 0,
-          "Schur compensation needs tile size m <= %d", kEigMaxRank);
+
   if (stats) std::memset(stats, 0, sizeof *stats);
   tlr_status st = factorize(A, eps, o, stats, ldl, piv);
   // Section 5.1: a shift s <= eps of the diagonal keeps the perturbation

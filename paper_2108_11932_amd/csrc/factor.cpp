@@ -147,8 +147,7 @@ struct Prob {
   DiagGraph* dg = nullptr;
   double mod_delta = 0.0;   // > 0: modified Cholesky of the diagonal tiles (Section 5.1.2)
   bool schur = false;       // Schur compensation of the diagonal updates (Section 5.1.1)
-  double* sch = nullptr;    // its buffers (Work::schur), device descriptor at sch_desc
-  EigDesc* sch_desc = nullptr;
+  double* sch = nullptr;    // its buffers (Work::schur)
   double flops = 0.0, flops_paper = 0.0, bytes_alg = 0.0, samp_bytes = 0.0, samp_flops = 0.0;
   long long ara_iters = 0, tile_iters = 0, fp32_tile_iters = 0, bf16_tile_iters = 0;
   double t_issue = 0.0, t_wait = 0.0;
@@ -184,6 +183,12 @@ struct Prob {
 
 // Set-up of one problem: factor storage, streams, thresholds, initial panel
 // capacities.
+// Newton-Schulz steps of the Schur compensation's sign function: an
+// eigenvalue at relative distance delta from the threshold grows by 3/2 per
+// step until it converges quadratically, so 100 steps resolve every one
+// farther than ~1e-16 (relative to ||D_k - tau I||_F) from it.
+constexpr int kSchurSignIters = 100;
+
 tlr_status prob_init(Prob& p, double eps, const tlr_opts& o, bool ldl) {
   Handle* h = p.h;
   const int m = h->m, nb = h->nb;
@@ -216,19 +221,12 @@ tlr_status prob_init(Prob& p, double eps, const tlr_opts& o, bool ldl) {
   // non-positive pivots raised to the threshold
   p.mod_delta = (!ldl && (o.flags & TLR_FLAG_MODIFIED_CHOL)) ? p.tau : 0.0;
   // Schur compensation: buffers of one column, reused column after column on
-  // the diagonal-tile stream, and the eigensolver's descriptor (fixed)
+  // the diagonal-tile stream
   p.schur = !ldl && !p.piv && (o.flags & TLR_FLAG_SCHUR_COMP);
   if (p.schur) {
     Work& w = h->ws;
-    const size_t mm = (size_t)m * m;
-    const size_t doubles = 4 * mm + m + 2;
-    const size_t bytes = sizeof(double) * doubles + sizeof(EigDesc) + 64;
-    TLR_TRY(w.schur.ensure(h->mem, bytes));
+    TLR_TRY(w.schur.ensure(h->mem, sizeof(double) * (5 * (size_t)m * m + kPivotTolDoubles)));
     p.sch = w.schur.as<double>();
-    const size_t doff = ((sizeof(double) * doubles + 63) / 64) * 64;
-    p.sch_desc = reinterpret_cast<EigDesc*>(reinterpret_cast<char*>(w.schur.p) + doff);
-    EigDesc ed{p.sch, p.sch + mm, p.sch + 4 * mm + m, m, p.sch + 4 * mm};
-    TLR_HIP(hipMemcpy(p.sch_desc, &ed, sizeof ed, hipMemcpyHostToDevice));
   }
   p.dg = nullptr;
   if (o.flags & TLR_FLAG_DIAG_GRAPH)
@@ -521,28 +519,53 @@ tlr_status col_diag(Prob& p, int k, bool ldl) {
       p.flops += wb.flops + up.flops / 2;
       if (p.schur) {
         // Schur compensation (Section 5.1.1): the update D_k = W U_k*^T in
-        // full, D_k = V diag(lambda) V^T, the part the compression to tau
-        // drops, E = V diag(lambda_j <= tau ? lambda_j : 0) V^T, and the
-        // absolute row sums of E onto the diagonal of the updated tile
+        // full; the part its compression to tau drops is D_k P, P the
+        // spectral projector on the eigenvalues <= tau,
+        // P = (I - sign(D_k - tau I)) / 2; the sign function by the
+        // Newton-Schulz iteration X <- (3 X - X^3) / 2 from
+        // X_0 = (D_k - tau I) / ||D_k - tau I||_F (eigenvalues in [-1, 1]),
+        // matrix products only; then the absolute row sums of
+        // E = (D_k - D_k X) / 2 onto the diagonal of the updated tile
         const size_t mm = (size_t)m * m;
-        double* D = p.sch;            // D_k, then its eigenvectors
-        double* Vs = p.sch + 2 * mm;
-        double* E = p.sch + 3 * mm;
-        const double* lam = p.sch + 4 * mm;
-        const EigDesc* ed = p.sch_desc;
-        const int cls = eig_class(m);
+        double* D = p.sch;
+        double* X = p.sch + mm;
+        double* Xn = p.sch + 2 * mm;
+        double* Y = p.sch + 3 * mm;
+        double* E = p.sch + 4 * mm;
+        double* parts = p.sch + 5 * mm;
+        double* nrm = parts + (kPivotTolDoubles - 32);
         const double tau = p.tau;
         GemmBatch db(false, true);
         db.add(m, m, Rk, Wd, m, h->UL[k], m, D, m, 1.0, 0.0);
         dplan.gemm(db);
-        // the solver compares sqrt(lambda) with its threshold
-        dplan.launch([=]() { return launch_sym_eig(ed, 1, cls, std::sqrt(tau), 1e-15, ds); });
-        dplan.launch([=]() { return launch_schur_scale(D, lam, m, tau, Vs, ds); });
-        GemmBatch eb(false, true);
-        eb.add(m, m, m, Vs, m, D, m, E, m, 1.0, 0.0);
+        p.flops += db.flops;
+        dplan.launch([=]() { return launch_schur_shift(D, m, tau, X, ds); });
+        dplan.launch([=]() { return launch_norm2(X, (long long)mm, nrm, parts, ds); });
+        dplan.launch([=]() { return launch_scale_by(X, (long long)mm, nrm, X, ds); });
+        for (int it = 0; it < kSchurSignIters; ++it) {
+          GemmBatch sq(false, false), st(false, false);
+          sq.add(m, m, m, X, m, X, m, Y, m, 1.0, 0.0);
+          dplan.gemm(sq);
+          const double* xs = X;
+          double* xd = Xn;
+          dplan.launch([=]() {
+            return hipMemcpyAsync(xd, xs, sizeof(double) * mm, hipMemcpyDeviceToDevice, ds);
+          });
+          st.add(m, m, m, X, m, Y, m, Xn, m, -0.5, 1.5);
+          dplan.gemm(st);
+          p.flops += sq.flops + st.flops;
+          std::swap(X, Xn);
+        }
+        const double* dsrc = D;
+        double* edst = E;
+        dplan.launch([=]() {
+          return hipMemcpyAsync(edst, dsrc, sizeof(double) * mm, hipMemcpyDeviceToDevice, ds);
+        });
+        GemmBatch eb(false, false);
+        eb.add(m, m, m, D, m, X, m, E, m, -0.5, 0.5);
         dplan.gemm(eb);
         dplan.launch([=]() { return launch_schur_diag(E, m, Tk, m, nr, ds); });
-        p.flops += db.flops + eb.flops;
+        p.flops += eb.flops;
       }
     }
     if (DiagGraph* g = p.dg) {

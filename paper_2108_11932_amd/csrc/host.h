@@ -164,9 +164,8 @@ struct Work {
       compact, Bt, fro, tnpart, tnpart2, splitk, G2, Gk, Sg, Sw, Snorm;
   // buffers of the diagonal-tile stream (never touched by the main stream)
   DevBuf Wd, dW, dtol, sideblob, sideblob2, Wn;
-  // Schur compensation: D_k (then its eigenvectors), the solver's
-  // workspace, V diag(f), E (m x m each), the eigenvalues, two result
-  // words and the solver's descriptor
+  // Schur compensation: D_k, the sign iterates X and X', X^2, E (m x m
+  // each), the norm's partial sums and the norm
   DevBuf schur;
   int slots = 0;   // slot capacity of the per-tile buffers
   void release_all(Mem& mem) {

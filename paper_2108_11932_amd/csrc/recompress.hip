@@ -208,7 +208,7 @@ __device__ void jacobi(double* G, int lg, double* W, int lw, int q, double abs_s
 // may be G's own storage: G is only read before the barrier.
 template <int NT, bool PACKED = false>
 __device__ void finish(const double* G, int lg, const double* W, int lw, int q, double tau,
-                       double* out, double* res, double* lam, int* pos, double* lam_out) {
+                       double* out, double* res, double* lam, int* pos) {
   const int tid = threadIdx.x;
   for (int j = tid; j < q; j += NT) {
     const double lj = G[gidx<PACKED>(j, j, lg)];
@@ -225,8 +225,6 @@ __device__ void finish(const double* G, int lg, const double* W, int lw, int q, 
     const int i = e % q, j = e / q;
     out[i + (size_t)pos[j] * q] = W[i + (size_t)j * lw];
   }
-  if (lam_out)
-    for (int j = tid; j < q; j += NT) lam_out[j] = lam[j];
   if (tid == 0) {
     int r = 0;
     double sum = 0.0;
@@ -260,7 +258,7 @@ __global__ __launch_bounds__(NT) void k_sym_eig_lds(const EigDesc* __restrict__ 
   }
   __syncthreads();
   jacobi<NT>(sG, LG, sW, q, q, abs_scale, JacShared{cs, sn, pa, pb, &flag, &atol});
-  finish<NT>(sG, LG, sW, q, q, tau, d.G, d.res, lam, pos, d.lam);
+  finish<NT>(sG, LG, sW, q, q, tau, d.G, d.res, lam, pos);
 }
 
 // Tiles of rank q <= QMAX: G packed (upper triangle) in LDS, W in the
@@ -285,7 +283,7 @@ __global__ __launch_bounds__(NT) void k_sym_eig_packed(const EigDesc* __restrict
   }
   __syncthreads();
   jacobi<NT, true>(sG, 0, d.W, q, q, abs_scale, JacShared{cs, sn, pa, pb, &flag, &atol});
-  finish<NT, true>(sG, 0, d.W, q, q, tau, d.G, d.res, lam, pos, d.lam);
+  finish<NT, true>(sG, 0, d.W, q, q, tau, d.G, d.res, lam, pos);
 }
 
 // Tiles of rank up to kEigMaxRank: G in place and W in the descriptor's
@@ -300,16 +298,14 @@ __global__ __launch_bounds__(1024) void k_sym_eig_glb(const EigDesc* __restrict_
   const int q = d.q;
   if (q <= 0 || q > kEigMaxRank) return;
   jacobi<1024>(d.G, q, d.W, q, q, abs_scale, JacShared{cs, sn, pa, pb, &flag, &atol});
-  finish<1024>(d.G, q, d.W, q, q, tau, d.G, d.res, lam, pos, d.lam);
+  finish<1024>(d.G, q, d.W, q, q, tau, d.G, d.res, lam, pos);
 }
 
-__global__ __launch_bounds__(256) void k_schur_scale(const double* __restrict__ V,
-                                                    const double* __restrict__ lam, int m,
-                                                    double tau, double* __restrict__ Vs) {
+__global__ __launch_bounds__(256) void k_schur_shift(const double* __restrict__ D, int m,
+                                                    double tau, double* __restrict__ X) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (size_t)m * m) return;
-  const double l = lam[e / m];
-  Vs[e] = l <= tau ? V[e] * l : 0.0;
+  X[e] = D[e] - (e % m == e / m ? tau : 0.0);
 }
 
 __global__ __launch_bounds__(256) void k_schur_diag(const double* __restrict__ E, int m,
@@ -329,12 +325,11 @@ __global__ __launch_bounds__(256) void k_schur_diag(const double* __restrict__ E
 
 }  // namespace
 
-hipError_t launch_schur_scale(const double* V, const double* lam, int m, double tau, double* Vs,
-                              hipStream_t s) {
+hipError_t launch_schur_shift(const double* D, int m, double tau, double* X, hipStream_t s) {
   const size_t n = (size_t)m * m;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_schur_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, V, lam, m,
-                     tau, Vs);
+  hipLaunchKernelGGL(k_schur_shift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, D, m, tau,
+                     X);
   return hipGetLastError();
 }
 

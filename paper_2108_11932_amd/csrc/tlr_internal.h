@@ -331,7 +331,6 @@ struct EigDesc {
   double* W;
   double* res;
   int q;
-  double* lam = nullptr;   // when set: the q eigenvalues, descending
 };
 // The solver class of a q x q problem (-1: above kEigMaxRank).
 inline int eig_class(int q) {
@@ -343,13 +342,10 @@ inline int eig_class(int q) {
 }
 hipError_t launch_sym_eig(const EigDesc* d, int n, int cls, double tau, double abs_scale,
                           hipStream_t s);
-// Schur compensation (Section 5.1.1) from the eigen-decomposition D = V
-// diag(lam) V^T (m x m, V column-major): Vs = V diag(f), f_j = lam_j when
-// lam_j <= tau, else 0 (the part the compression to tau drops); then, for
-// E = Vs V^T, T(j, j) += sum_i |E(i, j)| for j < nreal (E is symmetric: the
-// column sums are the row sums; one workgroup per column, fixed order).
-hipError_t launch_schur_scale(const double* V, const double* lam, int m, double tau, double* Vs,
-                              hipStream_t s);
+// Schur compensation (Section 5.1.1).  X = D - tau I (m x m, full).
+hipError_t launch_schur_shift(const double* D, int m, double tau, double* X, hipStream_t s);
+// T(j, j) += sum_i |E(i, j)| for j < nreal (E symmetric: the column sums are
+// the row sums; one workgroup per column, a fixed-order sum).
 hipError_t launch_schur_diag(const double* E, int m, double* T, int ldt, int nreal, hipStream_t s);
 // dst = src (m x m) + shift on the first nreal diagonal entries.
 hipError_t launch_copy_shift(const double* src, double* dst, int m, int nreal, double shift,
