@@ -215,3 +215,42 @@ def test_recompress_errors():
     assert e.value.status == -4
     h.close()
     assert r.sum() > 0
+
+
+def test_headline_factor_sampled_tiles():
+    """The benchmark's configuration: the N = 131072 2D covariance at tile
+    1024, eps 1e-6 absolute, ARA block 16, the whole factor recompressed in
+    one call (every solver class, one chunk); sampled tiles (the highest
+    ranks, which take the packed-LDS solver, and a spread of others) against
+    the dense truncated SVD of the same tiles before the call, the offsets
+    of every row, and the random-vector residual of the result."""
+    w = wl.standard("cov2d_131k")
+    mat = tlr.TLRMatrix.compress_kernel(w.points, w.kernel, w.ell, w.diag_add, w.m, w.eps,
+                                        tlr.opts(bs=w.bs))
+    st = mat.potrf(w.eps, tlr.opts(bs=w.bs, eps_mode=w.eps_mode))
+    tau = st["tau"]
+    r0 = mat.ranks(tlr.FACTOR)
+    low = np.tril_indices(mat.nb, -1)
+    order = np.argsort(-r0[low], kind="stable")
+    pick = list(order[:6]) + list(order[len(order) // 8::len(order) // 6][:6])
+    tiles = [(int(low[0][p]), int(low[1][p])) for p in pick]
+    assert max(r0[t] for t in tiles) > 96
+    before = otlr.TLR(mat.n, mat.m)
+    for t in tiles:
+        before.u[t], before.v[t] = mat.tile(tlr.FACTOR, *t)
+    mat.recompress(tau)
+    after = otlr.TLR(mat.n, mat.m)
+    for t in tiles:
+        after.u[t], after.v[t] = mat.tile(tlr.FACTOR, *t)
+    ref = otlr.recompress(before, tau)
+    assert _check_tiles(before, after, tau, ref.ranks()) <= 1
+    r1 = mat.ranks(tlr.FACTOR)
+    assert r1.sum() < 0.9 * r0.sum()
+    np.testing.assert_array_equal(mat.offsets(tlr.FACTOR), bk.row_panel_offsets(r1))
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(7)
+    b = torch.randn(mat.n, 4, generator=g, dtype=torch.float64).cuda()
+    x = mat.solve(b)
+    res = float(((mat.matvec(x) - b).norm(dim=0) / x.norm(dim=0)).max())
+    assert res <= 2.0 * np.sqrt(mat.nb) * tau
+    mat.close()
