@@ -254,3 +254,35 @@ def test_headline_factor_sampled_tiles():
     res = float(((mat.matvec(x) - b).norm(dim=0) / x.norm(dim=0)).max())
     assert res <= 2.0 * np.sqrt(mat.nb) * tau
     mat.close()
+
+
+def test_recompress_mixed_precision_factor_then_refactor():
+    """A factor made with the FP32 panel copies: the recompression releases
+    the copies (they serve the sampling only), the solve uses the new
+    panels, and the next mixed-precision factorization builds them again
+    and gives the factor of a fresh handle."""
+    n, m = 4096, 256
+    pts = wl.jittered_grid(n, 2, 13)
+    pts = np.ascontiguousarray(pts[wl.morton_order(pts)])
+    mat = tlr.TLRMatrix.compress_kernel(pts, tlr.KERNEL_EXP, 0.1, 1e-4, m, 1e-8)
+    o = tlr.opts(bs=16, eps_mode=tlr.EPS_REL, precision=tlr.MIXED_FP32)
+    st = mat.potrf(1e-6, o)
+    r0 = mat.ranks(tlr.FACTOR)
+    mat.recompress(st["tau"])
+    assert mat.ranks(tlr.FACTOR).sum() <= r0.sum()
+    import torch
+    b = torch.randn(n, 2, dtype=torch.float64, generator=torch.Generator().manual_seed(1)).cuda()
+    x = mat.solve(b)
+    res = float(((mat.matvec(x) - b).norm(dim=0) / x.norm(dim=0)).max())
+    assert res <= 2.0 * np.sqrt(mat.nb) * st["tau"]
+    st2 = mat.potrf(1e-6, o)
+    l2 = oracle_tlr(mat, tlr.FACTOR)
+    fresh = tlr.TLRMatrix.compress_kernel(pts, tlr.KERNEL_EXP, 0.1, 1e-4, m, 1e-8)
+    fresh.potrf(1e-6, o)
+    lf = oracle_tlr(fresh, tlr.FACTOR)
+    np.testing.assert_array_equal(l2.ranks(), lf.ranks())
+    for key in lf.u:
+        np.testing.assert_array_equal(l2.v[key], lf.v[key])
+    assert st2["fp32_tile_iters"] > 0
+    fresh.close()
+    mat.close()

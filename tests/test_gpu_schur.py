@@ -66,3 +66,29 @@ def test_schur_compensation_rejected_outside_unpivoted_cholesky():
     # the handle is untouched: the plain factorization still runs
     mat.potrf(1e-6, tlr.opts(bs=16))
     mat.close()
+
+
+def test_schur_compensation_with_graph_replay_and_modified_cholesky():
+    """The compensation is added to the updated tile before the diagonal
+    factorization, so the captured-graph replay of that factorization gives
+    the factor of the launches bit for bit, and modified Cholesky combines
+    with it (a definite run raises no pivot and matches the plain one)."""
+    pts = wl.jittered_grid(2048, 2, 9)
+    pts = np.ascontiguousarray(pts[wl.morton_order(pts)])
+    mat = tlr.TLRMatrix.compress_kernel(pts, tlr.KERNEL_EXP, 0.1, 1e-4, 128, 1e-8)
+    base = tlr.FLAG_SCHUR_COMP
+    ref = None
+    for fl in (base, base | tlr.FLAG_DIAG_GRAPH, base | tlr.FLAG_MODIFIED_CHOL,
+               base | tlr.FLAG_DIAG_GRAPH | tlr.FLAG_MODIFIED_CHOL):
+        st = mat.potrf(1e-5, tlr.opts(bs=16, flags=fl))
+        l = oracle_tlr(mat, tlr.FACTOR)
+        if ref is None:
+            ref = l
+            continue
+        assert st["modified_pivots"] == 0
+        for k in range(l.nb):
+            np.testing.assert_array_equal(l.diag[k], ref.diag[k])
+        for key in ref.u:
+            np.testing.assert_array_equal(l.u[key], ref.u[key])
+            np.testing.assert_array_equal(l.v[key], ref.v[key])
+    mat.close()
