@@ -286,3 +286,38 @@ def test_recompress_mixed_precision_factor_then_refactor():
     assert st2["fp32_tile_iters"] > 0
     fresh.close()
     mat.close()
+
+
+def test_recompress_degenerate_shapes():
+    """One block (no low rank tile), N below the tile size, and an input
+    whose off-diagonal tiles are all of rank 0 (a block-diagonal matrix):
+    nothing to cut, the call succeeds and the handle stays usable."""
+    import torch
+    # N < m: a single padded block
+    pts = wl.uniform_points(100, 2, 3)
+    mat = tlr.TLRMatrix.compress_kernel(pts, tlr.KERNEL_EXP, 0.1, 1e-4, 128, 1e-8)
+    st = mat.potrf(1e-8, tlr.opts(bs=16))
+    mat.recompress(st["tau"])
+    mat.recompress(1e-8, tlr.INPUT)
+    b = np.random.default_rng(0).standard_normal(100)
+    x = mat.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    d = dense.covariance_matrix(pts, dense.KERNEL_EXP, 0.1, 1e-4)
+    np.testing.assert_allclose(d @ x, b, atol=1e-8 * np.abs(b).max())
+    mat.close()
+    # block diagonal: every off-diagonal tile of rank 0
+    m, nb = 64, 3
+    a = np.zeros((m * nb, m * nb))
+    rng = np.random.default_rng(1)
+    for k in range(nb):
+        g = rng.standard_normal((m, m))
+        a[k * m:(k + 1) * m, k * m:(k + 1) * m] = g @ g.T + m * np.eye(m)
+    mat = tlr.TLRMatrix.compress(torch.from_numpy(a).cuda(), m, 1e-10)
+    assert mat.ranks(tlr.INPUT).sum() == 0
+    mat.recompress(1e-10, tlr.INPUT)
+    mat.potrf(1e-10, tlr.opts(bs=16))
+    mat.recompress(1e-10)
+    assert mat.ranks(tlr.FACTOR).sum() == 0
+    b = rng.standard_normal(m * nb)
+    x = mat.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    np.testing.assert_allclose(a @ x, b, atol=1e-9 * np.abs(b).max())
+    mat.close()
