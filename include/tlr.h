@@ -174,8 +174,9 @@ typedef struct {
  * part D_k - Dbar_k (positive semidefinite, 2-norm <= tau) are added to the
  * diagonal: the tile factored is A_kk - D_k + diag(rowsum |D_k - Dbar_k|).
  * The dropped part is formed as D_k P with P = (I - sign(D_k - tau I)) / 2,
- * the sign function by 100 Newton-Schulz steps (two m x m x m products
- * each, on the matrix cores) per column on the diagonal-tile stream.  Rejected with TLR_ERR_ARG by tlr_ldlt, tlr_potrf_pivoted and the
+ * the sign function by 30 steps of an odd quintic and 12 Newton-Schulz
+ * steps (114 m x m x m products, on the matrix cores) per column on the
+ * diagonal-tile stream.  Rejected with TLR_ERR_ARG by tlr_ldlt, tlr_potrf_pivoted and the
  * batched factorizations. */
 enum { TLR_FLAG_KERNEL_TIMING = 1, TLR_FLAG_PHASE_TIMING = 2, TLR_FLAG_SERIAL_SAMPLING = 4,
        TLR_FLAG_MODIFIED_CHOL = 8, TLR_FLAG_DIAG_GRAPH = 16, TLR_FLAG_SCHUR_COMP = 32 };
