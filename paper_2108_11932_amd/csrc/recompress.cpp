@@ -82,6 +82,7 @@ tlr_status recompress(Handle* h, int which, double tau) {
   chunk_max = std::max(chunk_max, acc);
   cuts.push_back(tiles.size());
 
+  TLR_TRY(h->init_streams());
   // every buffer is allocated before the first tile changes
   void* work = nullptr;
   TLR_TRY(h->mem.get(&work, std::max<size_t>(chunk_max, 64)));
@@ -136,17 +137,30 @@ tlr_status recompress(Handle* h, int which, double tau) {
       gram2.add(r.q, r.q, m, PV[t], m, PV[t], m, G2[t], r.q, 1.0, 0.0);   // G_2 = V_1^T V_1
       ed2[cls].push_back(EigDesc{G2[t], W[t], res + 2 * t, r.q});
     }
+    // the solver classes of a pass: the large ones (a few hundred tiles next
+    // to the diagonal, one workgroup per CU) on the second stream, beside
+    // the small ones on the caller's stream, then joined
     auto eig = [&](std::vector<EigDesc>* sets, double abs_scale) -> tlr_status {
-      for (int cls = 0; cls < 4; ++cls) {
+      const bool fork = !sets[2].empty() || !sets[3].empty();
+      if (fork) {
+        TLR_HIP(hipEventRecord(h->ev_fork, h->stream));
+        TLR_HIP(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+      }
+      for (int cls = 3; cls >= 0; --cls) {
         if (sets[cls].empty()) continue;
+        hipStream_t s = cls >= 2 ? h->side : h->stream;
         void* d = nullptr;
-        TLR_TRY(h->stage.upload(h, sets[cls].data(), sizeof(EigDesc) * sets[cls].size(), &d));
+        TLR_TRY(h->stage.upload(h, sets[cls].data(), sizeof(EigDesc) * sets[cls].size(), &d, s));
         const hipError_t e = launch_sym_eig((const EigDesc*)d, (int)sets[cls].size(), cls, tau,
-                                            abs_scale, h->stream);
+                                            abs_scale, s);
         if (e != hipSuccess) {
           set_error("launch_sym_eig: %s", hipGetErrorString(e));
           return TLR_ERR_DEVICE;
         }
+      }
+      if (fork) {
+        TLR_HIP(hipEventRecord(h->ev_join, h->side));
+        TLR_HIP(hipStreamWaitEvent(h->stream, h->ev_join, 0));
       }
       return TLR_OK;
     };
